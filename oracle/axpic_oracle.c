@@ -1,0 +1,830 @@
+/* axpic_oracle.c -- FP64 CPU oracle of the axion Monte-Carlo operators.
+ *
+ * TEST INFRASTRUCTURE ONLY (see axpic_oracle.h).  Every function is the plain
+ * definition of what the method computes, written from the paper:
+ *   "An axion framework for Particle-in-Cell codes with Monte-Carlo sampling"
+ *   (Radford et al., arXiv:2604.24627).
+ * Section / equation labels below refer to that paper.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC.
+ * Contraction is off so that the Poisson inversion and the FP32 push follow
+ * exactly the operation order written here.
+ */
+#include "axpic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Constants (CODATA 2018).  The paper rounds m_e c^2 to 511 keV and 1 keV to
+ * 1.602e-9 erg; the exact values are used here.                             */
+/* ------------------------------------------------------------------------ */
+#define OR_PI 3.14159265358979323846
+#define OR_ALPHA (1.0 / 137.035999084)
+#define OR_HBARC_GEVCM 1.973269804e-14
+#define OR_HBARC_KEVCM 1.973269804e-8
+#define OR_C_CMS 2.99792458e10
+#define OR_ME_KEV 510.99895000
+#define OR_KEV_ERG 1.602176634e-9
+#define OR_KEV_T7 1.160451812 /* T_7 = T / 10^7 K per keV */
+#define OR_MU_G 1.66053906660e-24
+#define OR_ZETA3 1.2020569031595942854
+#define OR_ZETA5 1.0369277551433699263
+#define OR_ZETA6 1.0173430619844491397
+#define OR_LAMBDA_HARD_CAP 64.0
+#define OR_KMAX 255
+
+double or_const(int which) {
+    switch (which) {
+    case 0: return OR_ALPHA;
+    case 1: return OR_HBARC_GEVCM;
+    case 2: return OR_HBARC_KEVCM;
+    case 3: return OR_C_CMS;
+    case 4: return OR_ME_KEV;
+    case 5: return OR_KEV_ERG;
+    case 6: return OR_KEV_T7;
+    case 7: return OR_MU_G;
+    case 8: return OR_ZETA3;
+    case 9: return OR_ZETA5;
+    case 10: return OR_ZETA6;
+    case 11: return OR_LAMBDA_HARD_CAP;
+    case 12: return (double)OR_KMAX;
+    default: return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).     */
+/* ------------------------------------------------------------------------ */
+static void or_mulhilo(uint32_t a, uint32_t b, uint32_t* hi, uint32_t* lo) {
+    uint64_t prod = (uint64_t)a * (uint64_t)b;
+    *hi = (uint32_t)(prod >> 32);
+    *lo = (uint32_t)prod;
+}
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { /* key schedule: Weyl sequence bump between rounds */
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0, lo0, hi1, lo1;
+        or_mulhilo(0xD2511F53u, c0, &hi0, &lo0);
+        or_mulhilo(0xCD9E8D57u, c2, &hi1, &lo1);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Draw contract: key = (seed lo, seed hi); counter = (id lo, id hi, step,
+ * stream << 24 | block).  Streams: 0 Primakoff count, 1 thermal counts
+ * (words 0-1 Compton, 2-3 brems), 2 Compton event k, 3 brems event k,
+ * 4 absorption (words 0-1 thermal absorption, 2-3 a->gamma count).        */
+void or_draw(uint64_t seed, uint64_t id, uint32_t step, uint32_t stream, uint32_t block,
+             uint32_t out[4]) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(id >> 32), step, (stream << 24) | (block & 0xFFFFFFu)};
+    or_philox4x32_10(ctr, key, out);
+}
+
+/* Uniform in [0,1) with 53 random bits: (a>>5)*2^26 + (b>>6), times 2^-53. */
+double or_u53(uint32_t a, uint32_t b) {
+    double hi = (double)(a >> 5);
+    double lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+/* Uniform in (0,1) on the odd multiples of 2^-24 (exact in FP32). */
+double or_u24(uint32_t a) {
+    return (double)(2u * (a >> 9) + 1u) * (1.0 / 16777216.0);
+}
+
+/* Poisson(lam) by sequential inversion of the CDF (eq. poisson_macro): the
+ * smallest k with u < sum_{j<=k} lam^j e^-lam / j!.  Fixed operation order. */
+int32_t or_poisson(double lam, double u) {
+    if (!(lam > 0.0)) return 0;
+    int32_t k = 0;
+    double p = exp(-lam);
+    double F = p;
+    while (u >= F && k < OR_KMAX) {
+        k += 1;
+        p = p * lam;
+        p = p / (double)k;
+        F = F + p;
+    }
+    return k;
+}
+
+void or_poisson_batch(const double* lam, const double* u, int32_t* k, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) k[i] = or_poisson(lam[i], u[i]);
+}
+
+/* Poisson-mean capping with weight rescale (eq. lambda_eff, eq. wa_rescaled).
+ * The user cap is bounded by the sampler's own limit; the rescale keeps the
+ * expected physical yield unchanged either way.                             */
+static double or_cap(double lam_macro, const or_params* prm, double* wscale, int* capped) {
+    double cap = prm->lambda_cap;
+    if (!(cap <= OR_LAMBDA_HARD_CAP)) cap = OR_LAMBDA_HARD_CAP;
+    double le = lam_macro < cap ? lam_macro : cap;
+    *capped = lam_macro > cap;
+    *wscale = (lam_macro > cap) ? lam_macro / le : 1.0;
+    return le;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Screened Primakoff kernel (eq. prim_F).                                    */
+/* ------------------------------------------------------------------------ */
+double or_F(double s) {
+    if (!(s > 0.0)) return 0.0;
+    return (1.0 + 1.0 / s) * log1p(s) - 1.0;
+}
+
+double or_dt_phys(const or_grid* g) { return g->dt / g->omega0; }   /* eq. dt_phys */
+
+double or_V_cell(const or_grid* g) {
+    double L = g->dx * OR_C_CMS / g->omega0;
+    return L * L * L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local plasma state (Sec. II.E) and channel rates (Secs. II.F-II.H).       */
+/* ------------------------------------------------------------------------ */
+void or_cell_state(const or_grid* g, const or_params* prm, int64_t ncell, const double* T,
+                   const double* dens_e, int32_t nion, const double* dens_ion,
+                   const double* Zion, const double* Aion, or_cell* out) {
+    (void)g;
+    const double alpha_ae = prm->g_ae * prm->g_ae / (4.0 * OR_PI);
+    const double aratio = alpha_ae / 1.60e-23;
+    const double meanC_over_T = 5.0 * OR_ZETA6 / OR_ZETA5;
+    const double meanB_over_T = prm->brems_k * prm->brems_theta;
+    for (int64_t c = 0; c < ncell; ++c) {
+        or_cell* o = &out[c];
+        memset(o, 0, sizeof(*o));
+        double nZ = 0.0, nZ2 = 0.0, rho = 0.0, rhoH = 0.0;
+        for (int32_t s = 0; s < nion; ++s) {
+            double ni = dens_ion[(int64_t)s * ncell + c];
+            nZ += Zion[s] * ni;
+            nZ2 += Zion[s] * Zion[s] * ni;                 /* effective charge-weighted targets */
+            rho += ni * Aion[s] * OR_MU_G;                 /* eq. rho_def */
+            if (Zion[s] == 1.0 && Aion[s] < 1.5) rhoH += ni * Aion[s] * OR_MU_G;
+        }
+        double ne_dep = dens_e ? dens_e[c] : 0.0;
+        double ne = prm->quasi_neutral ? nZ : ne_dep;      /* eq. qn_def */
+        double Tk = T[c];
+        o->T = Tk; o->n_e = ne; o->n_e_dep = ne_dep; o->nZ = nZ; o->nZ2 = nZ2; o->rho = rho;
+        o->XH = rho > 0.0 ? rhoH / rho : 0.0;
+        /* Debye screening, eq. kappa_debye, in keV^2: 4 pi alpha n_eff (hbar c)^3 / T */
+        if (prm->kappa_mode == 1) {
+            o->kappa2 = prm->kappa_fixed_keV * prm->kappa_fixed_keV;
+        } else {
+            double neff = ne + nZ2;
+            double hc3 = OR_HBARC_KEVCM * OR_HBARC_KEVCM * OR_HBARC_KEVCM;
+            o->kappa2 = 4.0 * OR_PI * OR_ALPHA * neff * hc3 / Tk;
+        }
+        /* Primakoff: Gamma = n_t sigma c with sigma = alpha g^2 Z^2 F(s) (hbar c)^2 / 8
+         * and n_t Z^2 -> sum_i Z_i^2 n_i (eqs. prim_xs, prim_rate).               */
+        double targets = prm->prim_targets ? (ne + nZ2) : nZ2;
+        double hc2 = OR_HBARC_GEVCM * OR_HBARC_GEVCM;
+        o->G_P0 = prm->boost * (OR_ALPHA * prm->g_agg_GeV * prm->g_agg_GeV / 8.0) * hc2 *
+                  OR_C_CMS * targets;
+        /* Compton-like: eqs. epsC, QC, GammaC */
+        double T7 = Tk * OR_KEV_T7;
+        double XH = o->XH;
+        double epsC = 2.67e-2 * (1.0 + XH) * pow(T7, 6.0) * aratio;
+        o->Q_C = rho * epsC;
+        o->meanE_C = meanC_over_T * Tk;
+        /* Bremsstrahlung: eqs. eps_eZ, eps_ee; screening fit factors kept >= 0 */
+        double rho2 = rho / 100.0;
+        double eta = (3.0 + XH) * rho2 / (T7 * T7);
+        double base = 0.150 * pow(T7, 2.5) * rho2 * (1.0 + XH) * aratio;
+        double sZ = 1.0 - 6.98e-2 * eta; if (sZ < 0.0) sZ = 0.0;
+        double se = 1.0 - 0.140 * eta; if (se < 0.0) se = 0.0;
+        double epsZ = base * sZ;
+        double epsE = base * (1.0 + XH) / (2.0 * sqrt(2.0)) * se;
+        double epsB = epsZ + (prm->brems_ee ? epsE : 0.0);
+        o->Q_B = rho * epsB;
+        o->meanE_B = meanB_over_T * Tk;
+        if (ne > 0.0) {
+            o->G_C = prm->boost * o->Q_C / (ne * o->meanE_C * OR_KEV_ERG);
+            o->G_B = prm->boost * o->Q_B / (ne * o->meanE_B * OR_KEV_ERG);
+        }
+    }
+}
+
+double or_gamma_prim(const or_cell* c, const or_params* prm, double omega_keV) {
+    (void)prm;
+    double s = 4.0 * omega_keV * omega_keV / c->kappa2;   /* eq. prim_xs */
+    return c->G_P0 * or_F(s);
+}
+
+/* Normalised number spectra that the thermal samplers draw from.           */
+static double or_pdf_compton(double E, double T) {          /* x^4/(e^x-1)/(24 zeta5) / T */
+    double x = E / T;
+    return x * x * x * x / expm1(x) / (24.0 * OR_ZETA5 * T);
+}
+static double or_pdf_brems(double E, double T, double k, double th) {
+    double y = E / (th * T);
+    return exp((k - 1.0) * log(y) - y - lgamma(k)) / (th * T);
+}
+/* Equilibrium spectra dn_eq/dE (BE or MB), Sec. II.I. */
+static double or_dneq(double E, double T, int mb) {
+    double hc3 = OR_HBARC_KEVCM * OR_HBARC_KEVCM * OR_HBARC_KEVCM;
+    double occ = mb ? exp(-E / T) : 1.0 / expm1(E / T);
+    return E * E / (2.0 * OR_PI * OR_PI * hc3) * occ;
+}
+
+/* Detailed-balance absorption rate, eq. gamma_abs: (dn_dot/dE)/(dn_eq/dE),
+ * with dn_dot/dE = n_e Gamma_c p_c(E) for each active thermal channel.     */
+double or_gamma_abs(const or_cell* c, const or_params* prm, double E_keV, double* parts) {
+    double gC = 0.0, gB = 0.0;
+    double neq = or_dneq(E_keV, c->T, prm->eq_stats);
+    if (neq > 0.0) {
+        if (prm->channels & OR_CH_C)
+            gC = c->n_e_dep * c->G_C * or_pdf_compton(E_keV, c->T) / neq;
+        if (prm->channels & OR_CH_B)
+            gB = c->n_e_dep * c->G_B * or_pdf_brems(E_keV, c->T, prm->brems_k, prm->brems_theta) / neq;
+    }
+    if (parts) { parts[0] = gC; parts[1] = gB; }
+    return gC + gB;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact inverse-CDF samplers.                                               */
+/* ------------------------------------------------------------------------ */
+static double or_gl_x[10], or_gl_w[10];
+static int or_gl_ready = 0;
+
+static void or_gl_init(void) {       /* 10-point Gauss-Legendre on [-1,1] */
+    if (or_gl_ready) return;
+    const int n = 10;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(OR_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2; p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabs(z - z1) < 1e-16) break;
+        }
+        or_gl_x[i] = z;
+        or_gl_w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+    or_gl_ready = 1;
+}
+
+static double or_compton_integrand(double x) {
+    if (x <= 0.0) return 0.0;
+    return x * x * x * x / expm1(x);
+}
+
+static double or_gl_panel(double a, double b) {
+    double h = 0.5 * (b - a), m = 0.5 * (b + a), s = 0.0;
+    for (int i = 0; i < 10; ++i) s += or_gl_w[i] * or_compton_integrand(m + h * or_gl_x[i]);
+    return s * h;
+}
+
+/* Integral of x^4/(e^x-1) over [a,b] by composite Gauss-Legendre, unit panels. */
+static double or_compton_integral(double a, double b) {
+    or_gl_init();
+    double s = 0.0;
+    double lo = a;
+    while (lo < b) {
+        double hi = floor(lo) + 1.0;
+        if (hi > b) hi = b;
+        s += or_gl_panel(lo, hi);
+        lo = hi;
+    }
+    return s;
+}
+
+double or_compton_cdf(double X) {
+    if (!(X > 0.0)) return 0.0;
+    return or_compton_integral(0.0, X) / (24.0 * OR_ZETA5);
+}
+
+/* Upper tail.  For X >= 2 by the mixture identity 1/(e^x-1) = sum_j e^{-jx}:
+ * Q(X) = sum_j j^-5 Gamma(5, jX)/(24 zeta5), Gamma(5,y) = 24 e^-y sum_{m<5} y^m/m!
+ * (positive terms, e^{-jX} convergence); below, by quadrature.            */
+double or_compton_ccdf(double X) {
+    if (!(X > 0.0)) return 1.0;
+    if (X < 2.0) return or_compton_integral(X, X + 60.0) / (24.0 * OR_ZETA5);
+    double s = 0.0;
+    for (int j = 1; j < 200; ++j) {
+        double y = (double)j * X;
+        double poly = 1.0 + y + y * y / 2.0 + y * y * y / 6.0 + y * y * y * y / 24.0;
+        double t = exp(-y) * poly / pow((double)j, 5.0);
+        s += t;
+        if (t < 1e-18 * s) break;
+    }
+    return s / OR_ZETA5;
+}
+
+/* Safeguarded Newton on a monotone CDF: f(x) = F(x) - target, f' = pdf. */
+static double or_invert(double (*cdf)(double, const double*), double (*pdf)(double, const double*),
+                        const double* par, double target, int upper, double lo, double hi) {
+    double x = (5.0 > lo && 5.0 < hi) ? 5.0 : 0.5 * (lo + hi);
+    for (int it = 0; it < 400; ++it) {
+        double F = cdf(x, par);
+        double f = upper ? (target - F) : (F - target);   /* increasing in x */
+        if (f > 0.0) hi = x; else lo = x;
+        double d = pdf(x, par);
+        double xn = (d > 0.0) ? x - f / d : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (fabs(xn - x) <= 1e-14 * fabs(x) || hi - lo <= 1e-14 * fabs(x)) { x = xn; break; }
+        x = xn;
+    }
+    return x;
+}
+
+static double cdf_c(double x, const double* par) { (void)par; return or_compton_cdf(x); }
+static double ccdf_c(double x, const double* par) { (void)par; return or_compton_ccdf(x); }
+static double pdf_c(double x, const double* par) {
+    (void)par;
+    return or_compton_integrand(x) / (24.0 * OR_ZETA5);
+}
+
+/* x = E/T of a Compton-like event: number density x^4/(e^x-1)/(24 zeta(5)).
+ * (The power spectrum of eq. compton_kernel is x times this density.)       */
+double or_compton_x(double u) {
+    if (u <= 0.5) return or_invert(cdf_c, pdf_c, NULL, u, 0, 0.0, 200.0);
+    return or_invert(ccdf_c, pdf_c, NULL, 1.0 - u, 1, 0.0, 200.0);
+}
+
+/* Regularised lower incomplete gamma P(a, y) by its power series. */
+double or_gammainc_P(double a, double y) {
+    if (!(y > 0.0)) return 0.0;
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 100000; ++n) {
+        term *= y / (a + n);
+        sum += term;
+        if (term < sum * 1e-18) break;
+    }
+    return sum * exp(-y + a * log(y) - lgamma(a));
+}
+
+/* Regularised upper incomplete gamma Q(a, y): Legendre continued fraction
+ * (modified Lentz) for y >= a + 1, otherwise 1 - P.                       */
+double or_gammainc_Q(double a, double y) {
+    if (!(y > 0.0)) return 1.0;
+    if (y < a + 1.0) return 1.0 - or_gammainc_P(a, y);
+    const double tiny = 1e-300;
+    double b = y + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 100000; ++i) {
+        double an = -(double)i * ((double)i - a);
+        b += 2.0;
+        d = an * d + b; if (fabs(d) < tiny) d = tiny;
+        c = b + an / c; if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-17) break;
+    }
+    return exp(-y + a * log(y) - lgamma(a)) * h;
+}
+
+static double cdf_g(double y, const double* par) { return or_gammainc_P(par[0], y); }
+static double ccdf_g(double y, const double* par) { return or_gammainc_Q(par[0], y); }
+static double pdf_g(double y, const double* par) {
+    if (!(y > 0.0)) return 0.0;
+    return exp((par[0] - 1.0) * log(y) - y - lgamma(par[0]));
+}
+
+/* y such that P(k, y) = u (the Gamma(k,1) quantile). */
+double or_gamma_x(double k, double u) {
+    double par[1] = {k};
+    if (u <= 0.5) return or_invert(cdf_g, pdf_g, par, u, 0, 0.0, 200.0);
+    return or_invert(ccdf_g, pdf_g, par, 1.0 - u, 1, 0.0, 200.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: energy histogram bin (App. B).                              */
+/* ------------------------------------------------------------------------ */
+int32_t or_hist_bin(const or_params* prm, double E) {
+    int32_t nb = prm->hist_nbins;
+    double t;
+    if (prm->hist_log) t = log(E / prm->hist_lo_keV) / log(prm->hist_hi_keV / prm->hist_lo_keV);
+    else t = (E - prm->hist_lo_keV) / (prm->hist_hi_keV - prm->hist_lo_keV);
+    double b = floor(t * (double)nb);
+    if (!(b >= 0.0)) return nb;          /* underflow (and NaN) */
+    if (b >= (double)nb) return nb + 1;  /* overflow */
+    return (int32_t)b;
+}
+
+static void or_hist_add(double* hist, const or_params* prm, int ch, double E_keV, double wphys) {
+    if (!hist) return;
+    int32_t b = or_hist_bin(prm, E_keV);
+    hist[(int64_t)ch * (prm->hist_nbins + 2) + b] += wphys * E_keV;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Deposit (NGP): density = sum of physical weights in the cell / volume.    */
+/* ------------------------------------------------------------------------ */
+void or_deposit(const or_species* s, int64_t ncell, double V, double* dens) {
+    double* acc = (double*)calloc((size_t)ncell, sizeof(double));
+    for (int64_t i = 0; i < s->n; ++i) acc[s->cell[i]] += s->w[i];
+    for (int64_t c = 0; c < ncell; ++c) dens[c] = acc[c] / V;
+    free(acc);
+}
+
+static uint64_t or_product_id(uint64_t next_id, int64_t rank) {
+    return (next_id + (uint64_t)rank) | (1ull << 63);
+}
+
+static void or_put(or_products* out, int64_t slot, const or_species* par, int64_t i,
+                   const double p[3], double w, uint64_t id, int ch) {
+    for (int d = 0; d < 3; ++d) {
+        out->x[d][slot] = par->x[d] ? par->x[d][i] : 0.0;
+        out->p[d][slot] = p[d];
+    }
+    out->w[slot] = w;
+    out->id[slot] = id;
+    out->cell[slot] = par->cell[i];
+    if (out->parent) out->parent[slot] = i;
+    if (out->chan) out->chan[slot] = ch;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward Primakoff conversion on photon macroparticles (Sec. II.F.1).      */
+/* Returns the number of products, or -(required) when out->cap is too small
+ * (then nothing is modified).                                              */
+/* ------------------------------------------------------------------------ */
+int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell* cells,
+                          or_species* ph, const double* lam_in, int64_t step,
+                          uint64_t next_id, or_products* out, double* hist, double* stats,
+                          double* lam_out, int32_t* K_out) {
+    const int64_t n = ph->n;
+    const double dtp = or_dt_phys(g);
+    const double wprod = prm->w_a * prm->wa_mul[0];
+    double* lam = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t total = 0;
+#pragma omp parallel for reduction(+ : total) if (n > 8192)
+    for (int64_t i = 0; i < n; ++i) {
+        double l;
+        if (lam_in) {
+            l = lam_in[i];
+        } else {
+            double px = ph->p[0][i], py = ph->p[1][i], pz = ph->p[2][i];
+            double om = OR_ME_KEV * sqrt(px * px + py * py + pz * pz);
+            double G = or_gamma_prim(&cells[ph->cell[i]], prm, om);    /* eq. prim_rate */
+            double P = -expm1(-G * dtp);                                /* eq. prim_prob */
+            l = ph->w[i] * P / wprod;                                   /* lambda_P */
+        }
+        if (!(ph->w[i] > 0.0)) l = 0.0;
+        lam[i] = l;
+        double ws; int capped;
+        double le = or_cap(l, prm, &ws, &capped);
+        uint32_t r[4];
+        or_draw(prm->seed, ph->id[i], (uint32_t)step, 0, 0, r);
+        K[i] = or_poisson(le, or_u53(r[0], r[1]));
+        total += K[i];
+    }
+    if (lam_out) memcpy(lam_out, lam, sizeof(double) * (size_t)n);
+    if (K_out) memcpy(K_out, K, sizeof(int32_t) * (size_t)n);
+    if (!out || total > out->cap) { free(lam); free(K); return -total; }
+    int64_t rank = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (K[i] == 0) continue;
+        double ws; int capped;
+        (void)or_cap(lam[i], prm, &ws, &capped);
+        double wp = wprod * ws;                        /* eq. wa_rescaled */
+        double dep = (double)K[i] * wp;
+        if (dep > ph->w[i]) {                          /* convert the whole parent */
+            wp = ph->w[i] / (double)K[i];
+            dep = ph->w[i];
+            if (stats) stats[OR_ST_OVERDEPLETED] += 1.0;
+        }
+        if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
+        double p[3] = {ph->p[0][i], ph->p[1][i], ph->p[2][i]};     /* product inherits p */
+        double E = OR_ME_KEV * sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        for (int32_t k = 0; k < K[i]; ++k) {
+            or_put(out, rank, ph, i, p, wp, or_product_id(next_id, rank), 0);
+            ++rank;
+            or_hist_add(hist, prm, 0, E, wp);
+            if (stats) {
+                stats[OR_ST_EVENTS_P] += 1.0;
+                stats[OR_ST_NUM_P] += wp;
+                stats[OR_ST_EN_P] += wp * E;
+            }
+        }
+        ph->w[i] = (dep >= ph->w[i]) ? 0.0 : ph->w[i] - dep;   /* number-conserving depletion */
+    }
+    free(lam); free(K);
+    return total;
+}
+
+/* Isotropic unit vector from two uniforms (cos theta = 2u-1, phi = 2 pi u). */
+static void or_isotropic(double u1, double u2, double n[3]) {
+    double mu = 2.0 * u1 - 1.0;
+    double phi = 2.0 * OR_PI * u2;
+    double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+    n[0] = s * cos(phi); n[1] = s * sin(phi); n[2] = mu;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermal-bath emission on electrons: Compton-like (Sec. II.G) and          */
+/* bremsstrahlung (Sec. II.H).  lam_in (optional) is [2][n]: Compton, brems. */
+/* fb is [ncell][4]: dE (m_e c^2 * count), dPx, dPy, dPz (m_e c * count).    */
+/* ------------------------------------------------------------------------ */
+int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* cells,
+                        const or_species* el, const double* lam_in, int64_t step,
+                        uint64_t next_id, or_products* out, double* fb, double* hist,
+                        double* stats, double* lam_out, int32_t* K_out) {
+    const int64_t n = el->n;
+    const double dtp = or_dt_phys(g);
+    const double wC = prm->w_a * prm->wa_mul[1], wB = prm->w_a * prm->wa_mul[2];
+    const int onC = (prm->channels & OR_CH_C) != 0, onB = (prm->channels & OR_CH_B) != 0;
+    double* lam = (double*)malloc(sizeof(double) * (size_t)(2 * n + 1));
+    int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * n + 1));
+    int64_t total = 0;
+#pragma omp parallel for reduction(+ : total) if (n > 8192)
+    for (int64_t i = 0; i < n; ++i) {
+        const or_cell* c = &cells[el->cell[i]];
+        double lC, lB;
+        if (lam_in) { lC = lam_in[i]; lB = lam_in[n + i]; }
+        else {
+            lC = el->w[i] * c->G_C * dtp / wC;      /* eq. lambda_macro */
+            lB = el->w[i] * c->G_B * dtp / wB;
+        }
+        if (!onC) lC = 0.0;
+        if (!onB) lB = 0.0;
+        lam[i] = lC; lam[n + i] = lB;
+        uint32_t r[4];
+        or_draw(prm->seed, el->id[i], (uint32_t)step, 1, 0, r);
+        double ws; int capped;
+        K[i] = or_poisson(or_cap(lC, prm, &ws, &capped), or_u53(r[0], r[1]));
+        K[n + i] = or_poisson(or_cap(lB, prm, &ws, &capped), or_u53(r[2], r[3]));
+        total += K[i] + K[n + i];
+    }
+    if (lam_out) memcpy(lam_out, lam, sizeof(double) * (size_t)(2 * n));
+    if (K_out) memcpy(K_out, K, sizeof(int32_t) * (size_t)(2 * n));
+    if (!out || total > out->cap) { free(lam); free(K); return -total; }
+    int64_t rank = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int ch = 1; ch <= 2; ++ch) {
+            int32_t Kc = K[(ch - 1) * n + i];
+            if (Kc == 0) continue;
+            const or_cell* c = &cells[el->cell[i]];
+            double ws; int capped;
+            (void)or_cap(lam[(ch - 1) * n + i], prm, &ws, &capped);
+            if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
+            double wp = (ch == 1 ? wC : wB) * ws;
+            for (int32_t k = 0; k < Kc; ++k) {
+                uint32_t r[4];
+                or_draw(prm->seed, el->id[i], (uint32_t)step, (uint32_t)(ch + 1), (uint32_t)k, r);
+                double u = or_u24(r[0]);
+                double x = (ch == 1) ? or_compton_x(u)
+                                     : prm->brems_theta * or_gamma_x(prm->brems_k, u);
+                double E = c->T * x;                     /* keV */
+                double nh[3];
+                or_isotropic(or_u24(r[1]), or_u24(r[2]), nh);
+                double pm = E / OR_ME_KEV;
+                double p[3] = {pm * nh[0], pm * nh[1], pm * nh[2]};
+                or_put(out, rank, el, i, p, wp, or_product_id(next_id, rank), ch);
+                ++rank;
+                or_hist_add(hist, prm, ch, E, wp);
+                if (fb) {                               /* energy/momentum leave the plasma */
+                    double* f = &fb[(int64_t)el->cell[i] * 4];
+                    f[0] -= wp * pm;
+                    f[1] -= wp * p[0]; f[2] -= wp * p[1]; f[3] -= wp * p[2];
+                }
+                if (stats) {
+                    stats[OR_ST_EVENTS_P + ch] += 1.0;
+                    stats[OR_ST_NUM_P + ch] += wp;
+                    stats[OR_ST_EN_P + ch] += wp * E;
+                }
+            }
+        }
+    }
+    free(lam); free(K);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inverse operators on axions (Sec. II.I and Sec. II.F.1): detailed-balance */
+/* absorption for the thermal channels, then a->gamma conversion of what     */
+/* survives.  pabs_in / lam_in optionally replace the computed probability / */
+/* mean.  Products (photons) are written to out.                              */
+/* ------------------------------------------------------------------------ */
+int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
+                  or_species* ax, const double* pabs_in, const double* lam_in, int64_t step,
+                  uint64_t next_id, or_products* out, double* fb, double* stats,
+                  double* pabs_out, double* lam_out, int32_t* K_out, int32_t* absorbed_out) {
+    const int64_t n = ax->n;
+    const double dtp = or_dt_phys(g);
+    const int thermal = prm->inverse && (prm->channels & (OR_CH_C | OR_CH_B));
+    const int a2g = prm->inverse && (prm->channels & OR_CH_P);
+    const double wg = prm->w_gamma_prod;
+    double* pab = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    double* lam = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    int32_t* K = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t* dead = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int64_t total = 0;
+#pragma omp parallel for reduction(+ : total) if (n > 8192)
+    for (int64_t i = 0; i < n; ++i) {
+        pab[i] = 0.0; lam[i] = 0.0; K[i] = 0; dead[i] = 0;
+        double w = ax->w[i];
+        if (!(w > 0.0)) continue;
+        const or_cell* c = &cells[ax->cell[i]];
+        double px = ax->p[0][i], py = ax->p[1][i], pz = ax->p[2][i];
+        double E = OR_ME_KEV * sqrt(px * px + py * py + pz * pz);
+        uint32_t r[4];
+        or_draw(prm->seed, ax->id[i], (uint32_t)step, 4, 0, r);
+        if (thermal) {
+            double P = pabs_in ? pabs_in[i] : -expm1(-or_gamma_abs(c, prm, E, NULL) * dtp);
+            pab[i] = P;
+            if (prm->absorb_mode == 0) {
+                if (or_u53(r[0], r[1]) < P) { dead[i] = 1; w = 0.0; }
+            } else {
+                w = w - w * P;
+            }
+        }
+        if (a2g && w > 0.0) {
+            double l;
+            if (lam_in) l = lam_in[i];
+            else {
+                double G = prm->prim_inv_ratio * or_gamma_prim(c, prm, E);
+                l = w * (-expm1(-G * dtp)) / wg;
+            }
+            lam[i] = l;
+            double ws; int capped;
+            K[i] = or_poisson(or_cap(l, prm, &ws, &capped), or_u53(r[2], r[3]));
+        }
+        total += K[i];
+    }
+    if (pabs_out) memcpy(pabs_out, pab, sizeof(double) * (size_t)n);
+    if (lam_out) memcpy(lam_out, lam, sizeof(double) * (size_t)n);
+    if (K_out) memcpy(K_out, K, sizeof(int32_t) * (size_t)n);
+    if (absorbed_out) memcpy(absorbed_out, dead, sizeof(int32_t) * (size_t)n);
+    if (!out || total > out->cap) { free(pab); free(lam); free(K); free(dead); return -total; }
+    int64_t rank = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double w = ax->w[i];
+        if (!(w > 0.0)) continue;
+        double p[3] = {ax->p[0][i], ax->p[1][i], ax->p[2][i]};
+        double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        double E = OR_ME_KEV * pm;
+        double* f = fb ? &fb[(int64_t)ax->cell[i] * 4] : NULL;
+        if (thermal) {
+            double dw = dead[i] ? w : (prm->absorb_mode == 1 ? w * pab[i] : 0.0);
+            if (dw > 0.0) {
+                if (f) { f[0] += dw * pm; f[1] += dw * p[0]; f[2] += dw * p[1]; f[3] += dw * p[2]; }
+                if (stats) {
+                    stats[OR_ST_ABS_NUM] += dw; stats[OR_ST_ABS_EN] += dw * E;
+                    if (dead[i]) stats[OR_ST_ABS_EVENTS] += 1.0;
+                }
+            }
+            w = dead[i] ? 0.0 : w - dw;
+            ax->w[i] = w;
+        }
+        if (K[i] > 0) {
+            double ws; int capped;
+            (void)or_cap(lam[i], prm, &ws, &capped);
+            if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
+            double wp = wg * ws;
+            double dep = (double)K[i] * wp;
+            if (dep > w) { wp = w / (double)K[i]; dep = w; if (stats) stats[OR_ST_OVERDEPLETED] += 1.0; }
+            for (int32_t k = 0; k < K[i]; ++k) {
+                or_put(out, rank, ax, i, p, wp, or_product_id(next_id, rank), 3);
+                ++rank;
+                if (stats) { stats[OR_ST_AG_EVENTS] += 1.0; stats[OR_ST_AG_NUM] += wp; stats[OR_ST_AG_EN] += wp * E; }
+            }
+            ax->w[i] = (dep >= w) ? 0.0 : w - dep;
+        }
+    }
+    free(pab); free(lam); free(K); free(dead);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conservative feedback: affine momentum remap (Sec. II.J.1, eqs.           */
+/* cell_moments to b_def) and temperature estimate/relaxation (Sec. II.J.2,  */
+/* eqs. Te_est, Te_relax).  Electrons are grouped by cell (off[ncell+1]).    */
+/* moments_out (optional) is [ncell][5]: W, Px, Py, Pz, U2 before the remap. */
+/* ------------------------------------------------------------------------ */
+void or_feedback(const or_grid* g, const or_params* prm, int64_t ncell, const int64_t* off,
+                 or_species* el, const double* fb, double* T, double* stats,
+                 double* moments_out) {
+    (void)g;
+    const double mu = 1.0;   /* electrons: mass in units of m_e */
+    for (int64_t c = 0; c < ncell; ++c) {
+        double W = 0.0, P[3] = {0.0, 0.0, 0.0}, U2 = 0.0;
+        for (int64_t i = off[c]; i < off[c + 1]; ++i) {
+            double w = el->w[i];
+            double px = el->p[0][i], py = el->p[1][i], pz = el->p[2][i];
+            W += w;
+            P[0] += w * px; P[1] += w * py; P[2] += w * pz;
+            U2 += w * (px * px + py * py + pz * pz);
+        }
+        if (moments_out) {
+            double* m = &moments_out[c * 5];
+            m[0] = W; m[1] = P[0]; m[2] = P[1]; m[3] = P[2]; m[4] = U2;
+        }
+        if (!(W > 0.0)) continue;
+        const double* f = fb ? &fb[c * 4] : NULL;
+        double dE = f ? f[0] : 0.0;
+        double dP[3] = {f ? f[1] : 0.0, f ? f[2] : 0.0, f ? f[3] : 0.0};
+        double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+        double var = U2 - P2 / W;                                       /* eq. var_unnormalized */
+        double pbar[3] = {P[0] / W, P[1] / W, P[2] / W};
+        double delta[3] = {dP[0] / W, dP[1] / W, dP[2] / W};            /* eq. delta_def */
+        double dP2 = delta[0] * delta[0] + delta[1] * delta[1] + delta[2] * delta[2];
+        double dotdP = delta[0] * P[0] + delta[1] * P[1] + delta[2] * P[2];
+        double dEbulk = (2.0 * dotdP + W * dP2) / (2.0 * mu);          /* eq. dE_bulk */
+        double dEth = dE - dEbulk;                                      /* eq. dE_th */
+        double var_new = var + 2.0 * mu * dEth;                         /* eq. var_new */
+        int cold = !(var > 1e-14 * (U2 + 1e-300));
+        double S = 1.0;
+        if (cold) {
+            var_new = var;
+            if (stats) { stats[OR_ST_COLD_CELLS] += 1.0; stats[OR_ST_UNAPPLIED_E] += dEth; }
+        } else {
+            if (var_new < 0.0) {
+                if (stats) { stats[OR_ST_CLAMPED_CELLS] += 1.0; stats[OR_ST_UNAPPLIED_E] += -var_new / (2.0 * mu); }
+                var_new = 0.0;
+            }
+            S = sqrt(var_new / var);                                    /* eq. s_def */
+        }
+        if (prm->feedback) {
+            double b[3];
+            for (int d = 0; d < 3; ++d) b[d] = (1.0 - S) * pbar[d] + delta[d];   /* eq. b_def */
+            for (int64_t i = off[c]; i < off[c + 1]; ++i)
+                for (int d = 0; d < 3; ++d) el->p[d][i] = S * el->p[d][i] + b[d];  /* eq. affine_map */
+        }
+        if (prm->T_mode == 2) {
+            double Test = OR_ME_KEV / 3.0 * var_new / W;                /* eq. Te_est */
+            double Tn = (1.0 - prm->r_relax) * T[c] + prm->r_relax * Test;   /* eq. Te_relax */
+            if (Tn < prm->T_floor_keV) Tn = prm->T_floor_keV;
+            if (Tn > prm->T_ceil_keV) Tn = prm->T_ceil_keV;
+            T[c] = Tn;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ballistic push of massless particles, v = p/|p| (Sec. II.B), periodic,    */
+/* then the NGP cell index.  The positions are advanced in the precision of  */
+/* the particle storage (prec32 = 1: binary32) with correctly rounded       */
+/* operations only, so that the cell index is decided identically by any    */
+/* IEEE implementation of the same steps.                                    */
+/* ------------------------------------------------------------------------ */
+void or_push(const or_grid* g, or_species* ax, int32_t prec32) {
+    const double dtdx64 = g->dt / g->dx;
+    const float dtdx32 = (float)dtdx64;
+    for (int64_t i = 0; i < ax->n; ++i) {
+        int64_t cell = 0, stride = 1;
+        if (prec32) {
+            float px = (float)ax->p[0][i], py = (float)ax->p[1][i], pz = (float)ax->p[2][i];
+            float s = fmaf(pz, pz, fmaf(py, py, px * px));
+            float inv = s > 0.0f ? 1.0f / sqrtf(s) : 0.0f;
+            float pv[3] = {px, py, pz};
+            for (int d = 0; d < 3; ++d) {
+                int32_t nd = g->n[d];
+                float x = (float)ax->x[d][i];
+                if (d < g->ndim) {
+                    float v = pv[d] * inv;
+                    x = fmaf(v, dtdx32, x);
+                    if (x < 0.0f) x = x + (float)nd;
+                    if (x >= (float)nd) x = x - (float)nd;
+                    ax->x[d][i] = (double)x;
+                }
+                int64_t ix = (int64_t)floorf(x);
+                if (ix < 0) ix = 0;
+                if (ix > nd - 1) ix = nd - 1;
+                cell += ix * stride;
+                stride *= nd;
+            }
+        } else {
+            double px = ax->p[0][i], py = ax->p[1][i], pz = ax->p[2][i];
+            double s = fma(pz, pz, fma(py, py, px * px));
+            double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+            double pv[3] = {px, py, pz};
+            for (int d = 0; d < 3; ++d) {
+                int32_t nd = g->n[d];
+                double x = ax->x[d][i];
+                if (d < g->ndim) {
+                    double v = pv[d] * inv;
+                    x = fma(v, dtdx64, x);
+                    if (x < 0.0) x = x + (double)nd;
+                    if (x >= (double)nd) x = x - (double)nd;
+                    ax->x[d][i] = x;
+                }
+                int64_t ix = (int64_t)floor(x);
+                if (ix < 0) ix = 0;
+                if (ix > nd - 1) ix = nd - 1;
+                cell += ix * stride;
+                stride *= nd;
+            }
+        }
+        ax->cell[i] = (int32_t)cell;
+    }
+}

@@ -1,0 +1,200 @@
+"""Statistical pins of the oracle's Monte-Carlo operators.
+
+Each test runs the oracle's operators and compares with an expectation fixed
+by the paper's construction: the unbiased macro-event yield (Sec. II.D),
+the expected per-bin relaxation towards the detailed-balance fixed point
+(Sec. II.I), the exact invariants of the bidirectional Primakoff conversion
+(Sec. II.F.1) and of the conservative feedback (Sec. II.J), and invariance
+under the axion macro-weight (App. A).  Tolerances are a few standard errors.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle as O
+from oracle import analytic as A
+from paper_2604_24627_amd import inputs as I
+
+ME = 510.99895
+HBARC = 1.973269804e-8
+ZETA3 = 1.2020569031595942854
+
+
+def small_plasma(T=3.0, ne=6e25, ncell=4, ppc=2048, dtype="f64", seed=0, **pkw):
+    p = I.Params(**pkw)
+    wl = I.Workload("t", ndim=1, n=(ncell,), ppc=ppc, dtype=dtype, T_keV=T, n_e=ne, params=p)
+    return wl, I.make_plasma(wl, seed)
+
+
+def test_thermal_emission_yield_is_unbiased():
+    """E[sum of product weights * E] over one step = Q V dt for each thermal channel,
+    with and without Poisson-mean capping."""
+    for cap, wa in ((math.inf, 4e-38), (0.1, 1e-39)):
+        wl, pl = small_plasma(channels=6, g_ae=1e-13, w_a=wa, lambda_cap=cap, boost=1.0)
+        sim = O.OracleSim(pl, wl.params)
+        cells = sim.cells()
+        st = np.zeros(O.ST_COUNT)
+        tot = {1: [], 2: []}
+        for s in range(10):
+            prod, lam, K = O.emit_thermal(sim.grid, sim.params, cells, sim.el, s, 10 ** 9, stats=st)
+            E = ME * np.sqrt((prod["p"] ** 2).sum(axis=0))
+            for ch in (1, 2):
+                m = prod["chan"] == ch
+                tot[ch].append((prod["w"][m] * E[m], lam[ch - 1]))
+        V = O.V_cell(sim.grid) * wl.ncell
+        dt = O.dt_phys(sim.grid)
+        c = cells[0]
+        for ch, Q in ((1, c["Q_C"]), (2, c["Q_B"])):
+            est = np.mean([t[0].sum() for t in tot[ch]]) * 1.602176634e-9 / (V * dt)
+            # relative standard error from the number of events and the spread of E
+            nev = sum(t[0].size for t in tot[ch])
+            assert nev > 2000
+            rel = 5 * 1.3 / math.sqrt(nev)
+            assert est == pytest.approx(Q, rel=rel), (ch, cap, est / Q)
+        if cap < math.inf:
+            assert st[O.ST["capped"]] > 0
+
+
+def test_primakoff_yield_matches_conditional_expectation():
+    """E[sum w_a' E] = sum_photons w_gamma P(omega) omega, and the photon weight lost equals
+    the axion weight made (number conservation, Sec. II.F.1)."""
+    wl, pl = small_plasma(T=1.3, channels=1, g_agg_GeV=1e-10, w_a=1e-38, boost=1e3)
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    dt = O.dt_phys(sim.grid)
+    om = ME * np.sqrt((sim.ph.p ** 2).sum(axis=0))
+    G = np.array([O.gamma_prim(cells[c], sim.params, o) for c, o in zip(sim.ph.cell, om)])
+    expect = (sim.ph.w * -np.expm1(-G * dt) * om).sum()
+    got = []
+    for s in range(5):
+        ph = sim.ph.copy()
+        w0 = ph.w.sum()
+        prod, lam, K = O.emit_primakoff(sim.grid, sim.params, cells, ph, s, 10 ** 9)
+        E = ME * np.sqrt((prod["p"] ** 2).sum(axis=0))
+        got.append((prod["w"] * E).sum())
+        assert w0 - ph.w.sum() == pytest.approx(prod["w"].sum(), rel=1e-9)
+    nev = prod["w"].size
+    assert nev > 500
+    assert np.mean(got) == pytest.approx(expect, rel=5 * 1.5 / math.sqrt(5 * nev))
+
+
+def _bin_number(ax, edges):
+    E = ME * np.sqrt((ax.p ** 2).sum(axis=0))
+    return np.histogram(E, bins=edges, weights=ax.w)[0], np.histogram(E, bins=edges,
+                                                                     weights=ax.w ** 2)[0]
+
+
+@pytest.mark.parametrize("chan,mb", [(2, 0), (4, 1)])
+def test_relaxation_follows_detailed_balance_recursion(chan, mb):
+    """Forward + inverse thermal operators in one cell: the expected axion number per
+    energy bin after t steps is n_eq(E) * g/(1 - e^-g) * (1 - e^-g t), g = Gamma_abs dt,
+    which tends to the equilibrium spectrum n_eq as g -> 0 (Sec. II.I)."""
+    T, ne = 3.0, 6e25
+    wl, pl = small_plasma(T=T, ne=ne, ncell=1, ppc=4096, channels=chan, inverse=1, g_ae=1e-13,
+                          boost=2e34, w_a=5e-5, lambda_cap=1.0, eq_stats=mb)
+    sim = O.OracleSim(pl, wl.params)
+    steps = 160
+    for _ in range(steps):
+        sim.step()
+    c = sim.cells()[0]
+    dt = O.dt_phys(sim.grid)
+    V = O.V_cell(sim.grid)
+    edges = np.array([1.0, 2.0, 3.0, 4.5, 6.0, 8.0, 11.0, 15.0, 22.0])
+
+    def dneq(E):
+        occ = math.exp(-E / T) if mb else 1.0 / math.expm1(E / T)
+        return E * E / (2 * math.pi ** 2 * HBARC ** 3) * occ
+
+    def expected(E):
+        g = O.gamma_abs(c, sim.params, E)[0] * dt
+        return V * dneq(E) * g / -math.expm1(-g) * -math.expm1(-g * steps)
+
+    exp_bins = np.array([integrate.quad(expected, edges[k], edges[k + 1], epsrel=1e-9)[0]
+                         for k in range(edges.size - 1)])
+    got, w2 = _bin_number(sim.ax, edges)
+    # axions are born one step before being eligible for absorption: the oracle's
+    # operators absorb the start-of-step population only (Jacobi order), as the recursion.
+    z = (got - exp_bins) / np.sqrt(np.maximum(w2, 1e-300) * 3.0)
+    assert np.all(np.abs(z) < 5.0), (got / exp_bins, z)
+    # equilibrium number density of a massless boson: zeta3 T^3 / (pi^2 (hbar c)^3)
+    if mb == 0:
+        Neq = ZETA3 * T ** 3 / (math.pi ** 2 * HBARC ** 3) * V
+        full = integrate.quad(lambda E: V * dneq(E), 1e-9, 200)[0]
+        assert full == pytest.approx(Neq, rel=1e-8)
+
+
+def test_primakoff_pair_conserves_number_energy_momentum():
+    """Forward and inverse Primakoff conversion conserve sum w, sum w E and sum w p exactly
+    (up to rounding) every step, and drive the axion share towards the two-state fixed point."""
+    wl, pl = small_plasma(T=1.3, ncell=2, ppc=512, channels=1, inverse=1, g_agg_GeV=1e-10,
+                          boost=3e31, w_a=2e-5, lambda_cap=4.0)
+    ph_wref = pl["species"]["photons"]["w_ref"]
+    wl.params.w_gamma_prod = 2e-5
+    sim = O.OracleSim(pl, wl.params)
+    assert sim.pdict["w_gamma_prod"] == 2e-5 and ph_wref > 1e-5
+
+    def tot():
+        out = []
+        for sp in (sim.ph, sim.ax):
+            E = ME * np.sqrt((sp.p ** 2).sum(axis=0))
+            out.append(np.array([sp.w.sum(), (sp.w * E).sum(), *(sp.w * sp.p).sum(axis=1)]))
+        return out
+    t0 = sum(tot())
+    shares = []
+    for s in range(30):
+        sim.step()
+        t = tot()
+        np.testing.assert_allclose(t[0] + t[1], t0, rtol=1e-11, atol=1e-14 * abs(t0[1]))
+        shares.append(t[1][0] / (t[0][0] + t[1][0]))
+    assert shares[-1] > shares[0] > 0.0
+    assert sim.stats[O.ST["ag_events"]] > 0
+
+
+def test_full_step_conserves_plasma_plus_axion_energy():
+    """With feedback on, the electrons' kinetic energy plus the axions' energy is constant
+    every step (thermal channels only; Sec. II.J)."""
+    wl, pl = small_plasma(T=3.0, ncell=8, ppc=256, channels=6, inverse=1, g_ae=1e-13,
+                          boost=3e34, w_a=2e-4, lambda_cap=1.0, feedback=1, T_mode=2)
+    sim = O.OracleSim(pl, wl.params)
+
+    def energy():
+        Ee = 0.5 * (sim.el.w * (sim.el.p ** 2).sum(axis=0)).sum()
+        Ea = (sim.ax.w * np.sqrt((sim.ax.p ** 2).sum(axis=0))).sum()
+        return Ee + Ea, Ea
+    e0, _ = energy()
+    for s in range(25):
+        sim.step()
+        e, ea = energy()
+        assert e == pytest.approx(e0, rel=1e-12)
+    assert ea > 1e-6 * e0
+    assert sim.stats[O.ST["clamped_cells"]] == 0 and sim.stats[O.ST["cold_cells"]] == 0
+    assert np.all(sim.T != 3.0)
+
+
+def test_spectrum_invariant_under_axion_macro_weight():
+    """App. A: the reconstructed brems spectrum does not depend on w_a (per-bin power agrees
+    with the analytic expectation within Monte-Carlo noise for w_a and 100 w_a)."""
+    edges = np.array([0.5, 1.5, 3.0, 5.0, 8.0, 12.0, 20.0])
+    res = {}
+    for wa in (2e-39, 2e-37):
+        wl, pl = small_plasma(T=1.3, ncell=4, ppc=4096, channels=4, g_ae=1e-13, w_a=wa,
+                              boost=3e3, lambda_cap=math.inf)
+        sim = O.OracleSim(pl, wl.params)
+        cells = sim.cells()
+        H = np.zeros(edges.size - 1); H2 = np.zeros_like(H)
+        for s in range(4):
+            prod, lam, K = O.emit_thermal(sim.grid, sim.params, cells, sim.el, s, 10 ** 9)
+            E = ME * np.sqrt((prod["p"] ** 2).sum(axis=0))
+            H += np.histogram(E, bins=edges, weights=prod["w"] * E)[0]
+            H2 += np.histogram(E, bins=edges, weights=(prod["w"] * E) ** 2)[0]
+        V = O.V_cell(sim.grid) * wl.ncell
+        scale = 1.602176634e-9 / (V * 4 * O.dt_phys(sim.grid) * 3e3)
+        res[wa] = (H * scale, np.sqrt(H2) * scale)
+        ref = np.array([integrate.quad(
+            lambda e: float(A.dQdE_brems(np.array([e]), cells[0], sim.params)[0]),
+            edges[k], edges[k + 1])[0] for k in range(edges.size - 1)])
+        z = (res[wa][0] - ref) / res[wa][1]
+        assert np.all(np.abs(z) < 5.0), (wa, z)
+    assert res[2e-39][1].mean() < res[2e-37][1].mean()

@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks a printed value,
+a closed form derived independently, a textbook special case, a library
+routine computing the same quantity by another method, or an invariant the
+paper states.  All run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+import oracle as O
+from oracle import analytic as A
+from paper_2604_24627_amd import inputs as I
+from conftest import read_golden
+
+ME = 510.99895
+HBARC = 1.973269804e-8
+MU = 1.66053906660e-24
+ZETA3, ZETA5, ZETA6, ZETA7 = 1.2020569031595942854, 1.0369277551433699263, \
+    1.0173430619844491397, 1.0083492773819228268
+GRID1 = dict(ndim=1, n=(1, 1, 1), dx=0.2, dt=0.1, omega0=4.3697e17)
+
+
+def one_cell(params, T, ne, Z=1, A_=1.0, n_e_dep=None):
+    ni = ne / Z
+    return O.cell_state(GRID1, params, np.array([T]), np.array([ne if n_e_dep is None else n_e_dep]),
+                        [np.array([ni])], [float(Z)], [A_])[0]
+
+
+# --------------------------------------------------------------------------- RNG
+def test_philox_known_answers():
+    rows = read_golden("philox_kat.txt")
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = O.philox(v[0:4], v[4:6])
+        assert out.tolist() == v[6:10]
+
+
+def test_uniform_constructions_exact():
+    assert O.u53(0, 0) == 0.0
+    assert O.u53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    assert O.u24(0) == 2.0 ** -24
+    assert O.u24(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    rng = np.random.default_rng(1)
+    for a in rng.integers(0, 2 ** 32, 1000, dtype=np.uint64):
+        u = O.u24(int(a))
+        assert float(np.float32(u)) == u and 0.0 < u < 1.0
+
+
+def test_poisson_inversion_matches_library_quantile():
+    """K is the smallest k with u < CDF(k): scipy's Poisson quantile."""
+    rng = np.random.default_rng(2)
+    for lam in (1e-3, 0.3, 1.0, 4.5, 16.0, 60.0):
+        u = rng.random(20000)
+        k = O.poisson_batch(np.full(u.size, lam), u)
+        ref = stats.poisson.ppf(u, lam).astype(np.int64)
+        assert np.count_nonzero(k != ref) == 0, lam
+
+
+def test_poisson_pmf_chi2():
+    rng = np.random.default_rng(3)
+    for lam in (0.7, 3.0, 12.0):
+        n = 200000
+        k = O.poisson_batch(np.full(n, lam), rng.random(n))
+        kmax = int(stats.poisson.ppf(1 - 1e-4, lam))
+        obs = np.bincount(np.minimum(k, kmax), minlength=kmax + 1)
+        pmf = stats.poisson.pmf(np.arange(kmax + 1), lam)
+        pmf[-1] = stats.poisson.sf(kmax - 1, lam)
+        chi2 = ((obs - n * pmf) ** 2 / (n * pmf)).sum()
+        assert stats.chi2.sf(chi2, kmax) > 1e-4
+        assert abs(k.mean() - lam) < 5 * math.sqrt(lam / n)
+        assert abs(k.var() - lam) < 8 * lam * math.sqrt(2.0 / n) + 1e-9
+
+
+# --------------------------------------------------------------------------- Primakoff
+def _F_angular(s):
+    """(1/pi) Integral dOmega omega^4 sin^2 / (q^2 (q^2 + kappa^2)), q^2 = 2 omega^2 (1 - cos),
+    with omega = 1 and kappa^2 = 4/s: the angular integral behind the screened cross section."""
+    k2 = 4.0 / s
+
+    def f(mu):
+        q2 = 2.0 * (1.0 - mu)
+        return (1.0 - mu * mu) / (q2 * (q2 + k2)) if q2 > 0 else 1.0 / (2.0 * k2) * 2.0
+    pts = [1.0 - 10.0 ** (-j) for j in range(1, 8)]
+    val = integrate.quad(f, -1.0, 1.0, points=pts, limit=500, epsabs=0, epsrel=1e-13)[0]
+    return 2.0 * math.pi * val / math.pi
+
+
+@pytest.mark.parametrize("s", [1e-3, 1e-2, 0.1, 0.5, 1.0, 3.0, 10.0, 100.0, 1e3])
+def test_screening_function_equals_angular_quadrature(s):
+    assert O.F(s) == pytest.approx(_F_angular(s), rel=2e-10)
+
+
+def test_screening_function_special_values():
+    assert O.F(1.0) == pytest.approx(2 * math.log(2) - 1, rel=1e-15)
+    for s in (1e-4, 1e-3):   # series s/2 - s^2/6 + s^3/12
+        assert O.F(s) == pytest.approx(s / 2 - s * s / 6 + s ** 3 / 12, rel=1e-8)
+    assert O.F(1e8) == pytest.approx(math.log(1e8) - 1, rel=1e-6)
+
+
+def test_primakoff_rate_equals_textbook_thermal_rate():
+    """With every charged species as a target, Gamma = g^2 T kappa^2 F(s) / (32 pi) in natural
+    units (the classic screened thermal Primakoff rate); converted with hbar, not hbar c and c."""
+    HBAR_KEV_S = 6.582119569e-19
+    p = I.Params(g_agg_GeV=1e-10, channels=1, prim_targets=1)
+    for T, ne in ((1.3, 6e25), (3.0, 1e25), (5.0, 6e25)):
+        c = one_cell(p, T, ne)
+        for om in (0.5, 3.0, 10.0, 40.0):
+            s = 4 * om * om / c["kappa2"]
+            g_keV = 1e-10 * 1e-6          # GeV^-1 -> keV^-1
+            G_nat = g_keV ** 2 * T * c["kappa2"] * O.F(s) / (32 * math.pi)   # keV
+            assert O.gamma_prim(c, p, om) == pytest.approx(G_nat / HBAR_KEV_S, rel=1e-8)
+
+
+def test_primakoff_coupling_and_charge_scaling():
+    p1 = I.Params(g_agg_GeV=1e-10, channels=1)
+    p2 = I.Params(g_agg_GeV=3e-10, channels=1)
+    c = one_cell(p1, 3.0, 6e25)
+    assert O.gamma_prim(c, p2, 5.0) == pytest.approx(9 * O.gamma_prim(c, p1, 5.0), rel=1e-14)
+    # same electron density in Z=2 ions: n_i halves, sum Z^2 n_i doubles
+    cH = one_cell(p1, 3.0, 6e25, Z=1)
+    cHe = one_cell(p1, 3.0, 6e25, Z=2, A_=4.0)
+    assert cHe["nZ2"] == pytest.approx(2 * cH["nZ2"], rel=1e-14)
+
+
+# --------------------------------------------------------------------------- Compton
+def test_compton_reproduces_table2():
+    """Table II Compton rows: Q_C = rho eps_C at rho = 100 g cm^-3, X_H = 1, g_ae = 1e-13,
+    integrated over [0, 80] keV, and the peak of dQ/dE."""
+    rows = [r for r in read_golden("table2.txt") if r[0] == "compton"]
+    p = I.Params(g_ae=1e-13, channels=2)
+    ne = 100.0 / MU
+    for r in rows:
+        T, pkR, QR = float(r[1]), float(r[5]), float(r[7])
+        c = one_cell(p, T, ne)
+        assert c["XH"] == 1.0
+        Q = A.integrate_Q(A.dQdE_compton, 1e-6, 80.0, c)
+        assert Q == pytest.approx(QR, rel=0.025)
+        _, h = A.peak(A.dQdE_compton, 0.5, 80.0, c)
+        assert h == pytest.approx(pkR, rel=0.035)
+
+
+def test_compton_temperature_and_coupling_scaling():
+    p = I.Params(g_ae=1e-13, channels=2)
+    p2 = I.Params(g_ae=2e-13, channels=2)
+    c3, c5 = one_cell(p, 3.0, 6e25), one_cell(p, 5.0, 6e25)
+    assert c5["Q_C"] / c3["Q_C"] == pytest.approx((5 / 3) ** 6, rel=1e-13)
+    assert one_cell(p2, 3.0, 6e25)["Q_C"] == pytest.approx(4 * c3["Q_C"], rel=1e-13)
+
+
+def test_compton_sampler_cdf_against_series():
+    """CDF of x^4/(e^x-1)/(24 zeta5) = sum_j j^-5 P(5, j X) / zeta5 (mixture of Gamma(5))."""
+    j = np.arange(1, 200001, dtype=np.float64)
+    for X in (0.05, 0.5, 2.0, 4.9, 10.0, 30.0):
+        ser = float(np.sum(j ** -5 * special.gammainc(5, j * X)) / ZETA5)
+        assert O.compton_cdf(X) == pytest.approx(ser, rel=1e-9, abs=1e-15)
+        assert O.compton_cdf(X) + O.compton_ccdf(X) == pytest.approx(1.0, abs=1e-13)
+    assert O.compton_cdf(150.0) == pytest.approx(1.0, abs=1e-14)
+
+
+def test_compton_sampler_moments():
+    """Number mean 5 zeta6/zeta5 and second moment 30 zeta7/zeta5 (in units of T)."""
+    m1 = integrate.quad(O.compton_x, 0, 1, limit=200, epsrel=1e-9)[0]
+    m2 = integrate.quad(lambda u: O.compton_x(u) ** 2, 0, 1, limit=200, epsrel=1e-9)[0]
+    assert m1 == pytest.approx(5 * ZETA6 / ZETA5, rel=1e-7)
+    assert m2 == pytest.approx(30 * ZETA7 / ZETA5, rel=1e-6)
+    rng = np.random.default_rng(4)
+    for u in rng.random(50):
+        x = O.compton_x(u)
+        F = O.compton_cdf(x) if u <= 0.5 else 1 - O.compton_ccdf(x)
+        assert F == pytest.approx(u, abs=1e-13)
+
+
+def test_compton_power_peak():
+    """x^5/(e^x-1) peaks where x = 5(1 - e^-x)."""
+    xs = float(scipy_brentq(lambda x: x - 5 * (1 - math.exp(-x)), 1, 10))
+    c = one_cell(I.Params(g_ae=1e-13, channels=2), 3.0, 6e25)
+    Epk, _ = A.peak(A.dQdE_compton, 1.0, 80.0, c)
+    assert Epk / 3.0 == pytest.approx(xs, rel=1e-6)
+    assert xs == pytest.approx(4.965114, rel=1e-6)
+
+
+def scipy_brentq(f, a, b):
+    from scipy.optimize import brentq
+    return brentq(f, a, b, xtol=1e-14)
+
+
+# --------------------------------------------------------------------------- brems
+def test_gamma_sampler_against_library():
+    for a in (1.2, 1.7, 2.5):
+        for y in (1e-3, 0.1, 1.0, 3.0, 10.0, 30.0):
+            assert O.gammainc_P(a, y) == pytest.approx(special.gammainc(a, y), rel=1e-12, abs=1e-300)
+            assert O.gammainc_Q(a, y) == pytest.approx(special.gammaincc(a, y), rel=1e-11, abs=1e-300)
+        for u in (2 ** -24, 1e-3, 0.3, 0.5, 0.9, 1 - 2 ** -24):
+            assert O.gamma_x(a, u) == pytest.approx(special.gammaincinv(a, u), rel=1e-9)
+
+
+def test_brems_structure():
+    """eps_ee/eps_eZ -> (1+X_H)/(2 sqrt2) as eta -> 0; T^2.5 and rho scaling; screening lowers."""
+    pe = I.Params(g_ae=1e-13, channels=4, brems_ee=1)
+    pz = I.Params(g_ae=1e-13, channels=4, brems_ee=0)
+    for Z, A_, XH in ((1, 1.0, 1.0), (2, 4.0, 0.0)):
+        ne = 1e18        # eta ~ 1e-8
+        cE, cZ = one_cell(pe, 3.0, ne, Z, A_), one_cell(pz, 3.0, ne, Z, A_)
+        assert cE["XH"] == XH
+        assert cE["Q_B"] / cZ["Q_B"] - 1 == pytest.approx((1 + XH) / (2 * math.sqrt(2)), rel=1e-6)
+        # Q = rho eps, eps ~ T^2.5 rho -> Q ~ T^2.5 rho^2 at vanishing screening
+        c2 = one_cell(pz, 6.0, 2 * ne, Z, A_)
+        assert c2["Q_B"] / cZ["Q_B"] == pytest.approx(2 ** 2.5 * 4, rel=1e-6)
+    lo, hi = one_cell(pz, 3.0, 1e18), one_cell(pz, 3.0, 6e25)
+    assert hi["Q_B"] / hi["rho"] ** 2 < lo["Q_B"] / lo["rho"] ** 2
+
+
+def test_brems_sampler_peak_matches_table2():
+    """The brems sampler reading (Gamma, shape 1.7, scale T) puts the power-spectrum peak at
+    1.7 T; Table II prints analytic brems peaks at 1.68-1.73 T."""
+    p = I.Params(g_ae=1e-13, channels=4)
+    for r in [r for r in read_golden("table2.txt") if r[0] == "brems"]:
+        T, EpkR = float(r[1]), float(r[4])
+        c = one_cell(p, T, 6e25)
+        Epk, _ = A.peak(A.dQdE_brems, 0.1 * T, 20 * T, c, p)
+        assert Epk / T == pytest.approx(1.7, rel=1e-6)
+        assert Epk == pytest.approx(EpkR, rel=0.03)
+
+
+def test_thermal_emission_integrates_to_emissivity():
+    p = I.Params(g_ae=1e-13, channels=6)
+    c = one_cell(p, 3.0, 6e25)
+    assert A.integrate_Q(A.dQdE_compton, 1e-8, 400.0, c) == pytest.approx(c["Q_C"], rel=1e-7)
+    assert A.integrate_Q(A.dQdE_brems, 1e-8, 400.0, c, p) == pytest.approx(c["Q_B"], rel=1e-7)
+
+
+# --------------------------------------------------------------------------- absorption
+@pytest.mark.parametrize("mb", [0, 1])
+def test_detailed_balance_net_source_vanishes(mb):
+    """At n_a = n_eq the net source n_e Gamma p(E) - Gamma_abs(E) dn_eq/dE is zero bin by bin."""
+    p = I.Params(g_ae=1e-13, channels=6, inverse=1, eq_stats=mb)
+    c = one_cell(p, 3.0, 6e25)
+    for E in (0.05, 0.5, 2.0, 8.0, 25.0, 60.0):
+        tot, (gC, gB) = O.gamma_abs(c, p, E)
+        x = E / 3.0
+        dneq = E * E / (2 * math.pi ** 2 * HBARC ** 3) * (math.exp(-x) if mb else 1 / math.expm1(x))
+        src_C = c["n_e"] * c["G_C"] * float(A.pdf_compton(E, 3.0))
+        src_B = c["n_e"] * c["G_B"] * float(A.pdf_brems(E, 3.0, 1.7, 1.0))
+        assert gC * dneq == pytest.approx(src_C, rel=1e-12)
+        assert gB * dneq == pytest.approx(src_B, rel=1e-12)
+
+
+def test_compton_absorption_closed_form():
+    """Compton + BE: Gamma_abs = n_e Gamma_C 2 pi^2 (hbar c)^3 E^2 / (24 zeta5 T^5)."""
+    p = I.Params(g_ae=1e-13, channels=2, inverse=1)
+    c = one_cell(p, 3.0, 6e25)
+    for E in (0.3, 3.0, 30.0):
+        ref = c["n_e"] * c["G_C"] * 2 * math.pi ** 2 * HBARC ** 3 * E * E / (24 * ZETA5 * 3.0 ** 5)
+        assert O.gamma_abs(c, p, E)[0] == pytest.approx(ref, rel=1e-12)
+
+
+# --------------------------------------------------------------------------- feedback
+def _cells_of_electrons(ncell, ppc, rng, T=3.0):
+    n = ncell * ppc
+    sig = math.sqrt(T / ME)
+    x = np.zeros((3, n)); x[0] = np.repeat(np.arange(ncell), ppc) + 0.5
+    p = rng.standard_normal((3, n)) * sig + rng.standard_normal((3, 1)) * 0.01
+    w = rng.lognormal(0.0, 0.5, n) * 2.4
+    el = O.OSpecies(x, p, w, np.arange(n, dtype=np.uint64), np.repeat(np.arange(ncell), ppc))
+    off = np.arange(ncell + 1) * ppc
+    return el, off
+
+
+def test_feedback_conserves_momentum_and_energy_exactly():
+    rng = np.random.default_rng(5)
+    ncell, ppc = 50, 32
+    el, off = _cells_of_electrons(ncell, ppc, rng)
+    p0 = el.p.copy()
+    grid = dict(ndim=1, n=(ncell, 1, 1), dx=0.2, dt=0.1, omega0=4.3697e17)
+    prm = I.Params(feedback=1, T_mode=0).as_dict()
+    fb = np.zeros(ncell * 4)
+    fb[0::4] = rng.normal(0, 1e-3, ncell) * 50        # dE (m_e c^2 * count)
+    fb[1::4] = rng.normal(0, 1e-3, ncell); fb[2::4] = rng.normal(0, 1e-3, ncell)
+    fb[3::4] = rng.normal(0, 1e-3, ncell)
+    T = np.full(ncell, 3.0)
+    st = np.zeros(O.ST_COUNT); mom = np.zeros(ncell * 5)
+    O.feedback(grid, prm, off, el, fb, T, st, mom)
+    assert st[O.ST["clamped_cells"]] == 0 and st[O.ST["cold_cells"]] == 0
+    for c in range(ncell):
+        sl = slice(off[c], off[c + 1])
+        w = el.w[sl]
+        P0 = (w * p0[:, sl]).sum(axis=1); P1 = (w * el.p[:, sl]).sum(axis=1)
+        np.testing.assert_allclose(P1 - P0, fb[4 * c + 1: 4 * c + 4], rtol=1e-9, atol=1e-15)
+        E0 = 0.5 * (w * (p0[:, sl] ** 2).sum(axis=0)).sum()
+        E1 = 0.5 * (w * (el.p[:, sl] ** 2).sum(axis=0)).sum()
+        assert E1 - E0 == pytest.approx(fb[4 * c], rel=1e-8, abs=1e-14)
+        assert mom[5 * c] == pytest.approx(w.sum(), rel=1e-14)
+
+
+def test_feedback_cold_cell_and_clamp():
+    grid = dict(ndim=1, n=(2, 1, 1), dx=0.2, dt=0.1, omega0=4.3697e17)
+    n = 4
+    x = np.zeros((3, 2 * n)); x[0] = [0.5] * n + [1.5] * n
+    p = np.zeros((3, 2 * n)); p[0, :n] = 0.01                        # cell 0 cold (all equal)
+    p[:, n:] = np.random.default_rng(6).normal(0, 0.05, (3, n))
+    el = O.OSpecies(x, p, np.ones(2 * n), np.arange(2 * n, dtype=np.uint64), [0] * n + [1] * n)
+    fb = np.array([1.0, 0.0, 0.0, 0.0, -1e6, 0.0, 0.0, 0.0])            # huge loss in cell 1
+    prm = I.Params(feedback=1).as_dict()
+    st = np.zeros(O.ST_COUNT)
+    O.feedback(grid, prm, [0, n, 2 * n], el, fb, np.full(2, 3.0), st)
+    assert st[O.ST["cold_cells"]] == 1 and st[O.ST["clamped_cells"]] == 1
+    np.testing.assert_array_equal(el.p[:, :n], p[:, :n])                  # S = 1, delta = 0
+    mean1 = p[:, n:].mean(axis=1)
+    np.testing.assert_allclose(el.p[:, n:], np.repeat(mean1[:, None], n, 1), atol=1e-15)
+
+
+def test_temperature_estimate_and_relaxation():
+    """T_est of a non-relativistic Maxwellian at T is T; relaxation is geometric; clamp."""
+    rng = np.random.default_rng(7)
+    ncell, ppc = 4, 200000
+    el, off = _cells_of_electrons(ncell, ppc, rng, T=3.0)
+    grid = dict(ndim=1, n=(ncell, 1, 1), dx=0.2, dt=0.1, omega0=4.3697e17)
+    T = np.array([1.0, 3.0, 6.0, 1000.0])
+    prm = I.Params(feedback=0, T_mode=2, r_relax=0.25, T_floor_keV=0.05, T_ceil_keV=100.0).as_dict()
+    O.feedback(grid, prm, off, el, np.zeros(ncell * 4), T)
+    Test = (T[:3] - 0.75 * np.array([1.0, 3.0, 6.0])) / 0.25
+    np.testing.assert_allclose(Test, 3.0, rtol=0.01)
+    assert T[3] == 100.0
+
+
+# --------------------------------------------------------------------------- push / hist
+def test_push_matches_closed_form():
+    grid = dict(ndim=2, n=(16, 8, 1), dx=0.2, dt=0.1, omega0=1.0)
+    rng = np.random.default_rng(8)
+    n = 1000
+    x0 = np.zeros((3, n)); x0[0] = rng.random(n) * 16; x0[1] = rng.random(n) * 8
+    p = rng.normal(0, 1, (3, n))
+    ax = O.OSpecies(x0, p, np.ones(n), np.arange(n, dtype=np.uint64), np.zeros(n, np.int32))
+    steps = 37
+    for _ in range(steps):
+        O.push(grid, ax, False)
+    v = p / np.sqrt((p ** 2).sum(axis=0))
+    ref0 = np.mod(x0[0] + steps * 0.5 * v[0], 16); ref1 = np.mod(x0[1] + steps * 0.5 * v[1], 8)
+    d0 = np.abs(ax.x[0] - ref0); d0 = np.minimum(d0, 16 - d0)
+    d1 = np.abs(ax.x[1] - ref1); d1 = np.minimum(d1, 8 - d1)
+    assert d0.max() < 1e-12 and d1.max() < 1e-12
+    assert np.all(ax.cell == np.floor(ax.x[0]).astype(int) + 16 * np.floor(ax.x[1]).astype(int))
+
+
+def test_histogram_bins():
+    prm = I.Params(hist_lo_keV=0.1, hist_hi_keV=20.0, hist_nbins=128, hist_log=1)
+    e = A.hist_edges(prm)
+    for k in (0, 1, 63, 127):
+        mid = math.sqrt(e[k] * e[k + 1])
+        assert O.hist_bin(prm, mid) == k
+    assert O.hist_bin(prm, 0.05) == 128 and O.hist_bin(prm, 25.0) == 129
+    prl = I.Params(hist_lo_keV=0.0, hist_hi_keV=80.0, hist_nbins=80, hist_log=0)
+    assert O.hist_bin(prl, 10.5) == 10
+
+
+# --------------------------------------------------------------------------- inputs
+def test_input_blackbody_photons():
+    wl = I.config1()
+    pl = I.make_plasma(wl)
+    ph = pl["species"]["photons"]
+    x = ME * np.sqrt((ph["p"] ** 2).sum(axis=0)) / 1.3
+    assert x.mean() == pytest.approx(math.pi ** 4 / 30 / ZETA3 * 3 / math.pi ** 4 * 30 * 1.0823232337111381,
+                                     rel=0.03)
+    dens = ph["w_ref"] * ph["w"].sum() / (wl.ncell * wl.V_cell_cm3)
+    assert dens == pytest.approx(2 * ZETA3 * 1.3 ** 3 / (math.pi ** 2 * HBARC ** 3), rel=1e-12)

@@ -15,6 +15,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Constants (CODATA 2018).  The paper rounds m_e c^2 to 511 keV and 1 keV to
@@ -34,6 +37,14 @@
 #define OR_ZETA6 1.0173430619844491397
 #define OR_LAMBDA_HARD_CAP 64.0
 #define OR_KMAX 255
+
+int32_t or_num_threads(void) {
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 double or_const(int which) {
     switch (which) {
@@ -139,9 +150,13 @@ static double or_cap(double lam_macro, const or_params* prm, double* wscale, int
 /* ------------------------------------------------------------------------ */
 /* Screened Primakoff kernel (eq. prim_F).                                    */
 /* ------------------------------------------------------------------------ */
+/* Evaluated in extended precision; below s = 1e-4, where the closed form
+ * cancels even there, by its Taylor series sum_n (-1)^{n+1} s^n/(n(n+1)). */
 double or_F(double s) {
     if (!(s > 0.0)) return 0.0;
-    return (1.0 + 1.0 / s) * log1p(s) - 1.0;
+    if (s < 1e-4) return s / 2.0 - s * s / 6.0 + s * s * s / 12.0 - s * s * s * s / 20.0;
+    long double S = (long double)s;
+    return (double)((1.0L + 1.0L / S) * log1pl(S) - 1.0L);
 }
 
 double or_dt_phys(const or_grid* g) { return g->dt / g->omega0; }   /* eq. dt_phys */

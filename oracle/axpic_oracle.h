@@ -85,6 +85,7 @@ enum {
 
 /* ---- constants ---- */
 double or_const(int which);
+int32_t or_num_threads(void);
 
 /* ---- RNG ---- */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -1,0 +1,279 @@
+/* axpic.h -- C ABI of the MI355X (gfx950) axion Monte-Carlo operators.
+ *
+ * Implements the per-macroparticle Monte-Carlo operators of
+ *   Radford et al., "An axion framework for Particle-in-Cell codes with
+ *   Monte-Carlo sampling: emission, absorption, and detailed balance in
+ *   plasmas", arXiv:2604.24627,
+ * for one GPU's share of a uniform Cartesian grid.  Section and equation
+ * labels in the comments refer to that paper.
+ *
+ * Conventions
+ *  - Every pointer inside the structs and every array argument is a DEVICE
+ *    pointer unless marked [host].  The structs themselves live in host memory.
+ *  - All calls are asynchronous on `stream` (a hipStream_t passed as void*).
+ *    No call allocates or frees memory or synchronises the device; all
+ *    scratch space is the caller's `ws` workspace.
+ *  - The caller owns every buffer.  Appending calls never write at or beyond
+ *    `capacity`: when the products do not fit they write the required length
+ *    to status[0], set AXPIC_FLAG_CAPACITY in status[1], modify nothing else,
+ *    and the caller may grow the buffer and repeat the call with the same
+ *    arguments, which gives bit-identical results (the random numbers are
+ *    keyed by (seed, particle id, step), see below).
+ *  - Host-side argument errors return AXPIC_E_INVAL before any launch; a
+ *    failed launch returns AXPIC_E_DEVICE.  No C++ exception crosses the ABI.
+ *
+ * Units: positions in cell units (x/dx); momenta in m_e c; the energy of a
+ * massless particle is m_e c^2 |p| (Sec. II.B); time step and cell size in
+ * the PIC normalisation (1/omega0, c/omega0); weights are RELATIVE: the
+ * physical weight is w_ref * w.  Temperatures in keV, densities in cm^-3.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ * (seed lo, seed hi) and counter (id lo, id hi, step, stream<<24 | block).
+ * Streams: 0 Primakoff count; 1 thermal counts (words 0-1 Compton, 2-3
+ * brems); 2 Compton event k (block k); 3 brems event k; 4 absorption
+ * (words 0-1 thermal absorption, 2-3 a->gamma count).  u53 = ((a>>5)*2^26 +
+ * (b>>6)) 2^-53; u24 = (2(a>>9)+1) 2^-24.  Counts are drawn by FP64 inversion
+ * of the Poisson CDF (eq. poisson_macro); absorption is u53 < P_abs.
+ */
+#ifndef AXPIC_H
+#define AXPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AXPIC_MAX_IONS 4
+#define AXPIC_PREF_N 8      /* per-cell prefactors (see axpic_cell_state) */
+#define AXPIC_STATE_N 16    /* per-cell FP64 local state */
+#define AXPIC_STATUS_N 4    /* int64 status words */
+
+typedef enum {
+    AXPIC_OK = 0,
+    AXPIC_E_INVAL = -1,
+    AXPIC_E_CAPACITY = -2,
+    AXPIC_E_DOMAIN = -3,
+    AXPIC_E_DEVICE = -4,
+    AXPIC_E_UNSUPPORTED = -5
+} axpic_status;
+
+/* status[1] flag bits */
+#define AXPIC_FLAG_CAPACITY 1
+#define AXPIC_FLAG_DOMAIN 2
+
+typedef enum { AXPIC_PRIMAKOFF = 1, AXPIC_COMPTON = 2, AXPIC_BREMS = 4 } axpic_channel;
+typedef enum { AXPIC_F32 = 0, AXPIC_F64 = 1 } axpic_dtype;
+typedef enum { AXPIC_ELECTRON = 0, AXPIC_ION = 1, AXPIC_PHOTON = 2, AXPIC_AXION = 3 } axpic_kind;
+
+/* Periodic grid of n[0] x n[1] x n[2] cells (unused dimensions have n = 1);
+ * cell index = ix + n0 (iy + n1 iz).  Every cell has volume (dx c/omega0)^3. */
+typedef struct {
+    int32_t ndim;
+    int32_t n[3];
+    double dx;       /* cell size [c/omega0] */
+    double dt;       /* time step [1/omega0]; dt_phys = dt/omega0 (eq. dt_phys) */
+    double omega0;   /* normalising frequency [s^-1] */
+} axpic_grid;
+
+/* Structure-of-arrays macroparticle buffer.  x[d], p[d], w are `dtype`
+ * arrays of length >= capacity; id is uint64, cell int32.  Photon and
+ * electron buffers of the plasma are grouped by cell in cell order. */
+typedef struct {
+    void* x[3];
+    void* p[3];
+    void* w;
+    uint64_t* id;
+    int32_t* cell;
+    int64_t n;          /* [host] live length */
+    int64_t capacity;   /* [host] allocated length */
+    int32_t dtype;      /* axpic_dtype */
+    int32_t kind;       /* axpic_kind */
+    double w_ref;       /* [host] physical weight of w = 1 */
+    double Z, A;        /* [host] ion charge state and mass number */
+} axpic_species;
+
+/* Per-cell tables.  dens: [1+AXPIC_MAX_IONS][ncell] FP64 deposited physical
+ * densities (slot 0 electrons, slot 1+s ion species s).  state: [ncell]
+ * records of AXPIC_STATE_N doubles: T, n_e, n_e_dep, nZ, nZ2, rho, X_H,
+ * kappa^2 [keV^2], G_P0, G_C, G_B [s^-1], Q_C, Q_B [erg cm^-3 s^-1],
+ * <E>_C, <E>_B [keV], 0.  pref32 / pref64: [ncell] records of AXPIC_PREF_N
+ * prefactors in FP32 / FP64 (filled by axpic_cell_state). */
+typedef struct {
+    int64_t ncell;
+    double* T_keV;
+    double* dens;
+    double* state;
+    float* pref32;
+    double* pref64;
+    int32_t nion;                 /* [host] */
+    double Zion[AXPIC_MAX_IONS];  /* [host] */
+    double Aion[AXPIC_MAX_IONS];  /* [host] */
+    double w_ref_e, w_ref_g;      /* [host] reference weights baked into the prefactors;
+                                     written by axpic_cell_state */
+} axpic_cells;
+
+/* Method parameters [host]; the fields mirror the options the paper names. */
+typedef struct {
+    double g_agg_GeV;       /* axion-photon coupling [GeV^-1] (Sec. II.C) */
+    double g_ae;            /* axion-electron coupling */
+    int32_t channels;       /* axpic_channel mask */
+    int32_t inverse;        /* 1: inverse operators active (Sec. II.I) */
+    double w_a;             /* axion macro-weight (Sec. II.D.1) */
+    double wa_mul[3];       /* product base weights / w_a for Primakoff, Compton, brems */
+    double w_gamma_prod;    /* physical weight of an a->gamma photon (0: photon w_ref) */
+    double lambda_cap;      /* Poisson-mean cap (eq. lambda_eff); bounded by 64 */
+    double boost;           /* common multiplier of every rate */
+    int32_t eq_stats;       /* 0 Bose-Einstein, 1 Maxwell-Boltzmann equilibrium */
+    int32_t kappa_mode;     /* 0 Debye (eq. kappa_debye), 1 fixed */
+    double kappa_fixed_keV;
+    int32_t prim_targets;   /* 0: sum_i Z_i^2 n_i (ions); 1: plus electrons */
+    double prim_inv_ratio;  /* Gamma(a->gamma)/Gamma(gamma->a) */
+    int32_t brems_ee;       /* include the e-e term (eq. eps_ee) */
+    double brems_k;         /* brems energy sampler: x = E/T ~ Gamma(k, theta) */
+    double brems_theta;
+    int32_t absorb_mode;    /* 0 Bernoulli deletion, 1 weight reduction */
+    int32_t quasi_neutral;  /* n_e from sum Z_i n_i (eq. qn_def) */
+    int32_t T_mode;         /* 0 fixed, 1 prescribed field, 2 evolved (Sec. II.J.2) */
+    int32_t feedback;       /* apply the affine remap (Sec. II.J.1) */
+    double r_relax;         /* eq. Te_relax */
+    double T_floor_keV, T_ceil_keV;
+    uint64_t seed;
+    double hist_lo_keV, hist_hi_keV;
+    int32_t hist_nbins;     /* histogram bins (+2 under/overflow slots) per channel */
+    int32_t hist_log;       /* 1: logarithmic bins */
+} axpic_params;
+
+/* Statistics slots (FP64, accumulated by the calls that own them). */
+enum {
+    AXPIC_ST_EVENTS_P = 0, AXPIC_ST_EVENTS_C, AXPIC_ST_EVENTS_B,
+    AXPIC_ST_NUM_P, AXPIC_ST_NUM_C, AXPIC_ST_NUM_B,
+    AXPIC_ST_EN_P, AXPIC_ST_EN_C, AXPIC_ST_EN_B,
+    AXPIC_ST_ABS_NUM, AXPIC_ST_ABS_EN, AXPIC_ST_AG_EVENTS, AXPIC_ST_AG_NUM, AXPIC_ST_AG_EN,
+    AXPIC_ST_CAPPED, AXPIC_ST_OVERDEPLETED, AXPIC_ST_COLD_CELLS, AXPIC_ST_CLAMPED_CELLS,
+    AXPIC_ST_UNAPPLIED_E, AXPIC_ST_ABS_EVENTS,
+    AXPIC_ST_COUNT
+};
+
+const char* axpic_status_string(int32_t status);
+int32_t axpic_version(void);
+
+/* Bytes of workspace the calls below need for parents / axions of up to
+ * n_max particles. */
+size_t axpic_workspace_bytes(int64_t n_max);
+
+/* axpic_bin_cells -- Sec. II.B, II.E.  For a massless species (axions):
+ * if `push` != 0 advance x by v dt/dx with v = p/|p| (periodic), then
+ * recompute `cell` by nearest-grid-point binning of x (always).  Position
+ * arithmetic uses only correctly rounded IEEE operations (fma, sqrt, div) in
+ * the storage precision.  Returns AXPIC_E_INVAL for a NULL array or a
+ * species whose dims exceed the grid. */
+axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, void* stream);
+
+/* axpic_deposit -- Sec. II.E (NGP deposit).  dens[slot][c] = w_ref * sum of
+ * w over the particles of cell c / V_cell, for a species grouped by cell
+ * with offsets off[ncell+1] (int64).  Deterministic (sequential per cell). */
+axpic_status axpic_deposit(const axpic_grid* g, const axpic_species* sp, const int64_t* off,
+                           axpic_cells* cells, int32_t slot, void* stream);
+
+/* axpic_cell_state -- Sec. II.E-II.I.  From dens and T_keV computes the FP64
+ * local state (eqs. rho_def, qn_def, kappa_debye, prim_xs, prim_rate, epsC,
+ * QC, GammaC, eps_eZ, eps_ee) and the per-cell prefactors, in pref32 and
+ * pref64: [0] T, [1] 4 (m_e c^2)^2/kappa^2, [2] G_P0 dt_phys,
+ * [3] G_P0 dt_phys w_ref_g/(w_a wa_mul[0]), [4] w_ref_e G_C dt_phys/(w_a wa_mul[1]),
+ * [5] w_ref_e G_B dt_phys/(w_a wa_mul[2]), [6] Compton absorption coefficient,
+ * [7] brems absorption coefficient (eq. gamma_abs times dt_phys).
+ * w_ref_e / w_ref_g: reference weights of the emitting electrons / photons. */
+axpic_status axpic_cell_state(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
+                              double w_ref_e, double w_ref_g, void* stream);
+
+/* axpic_rates -- per-particle rate materialisation (FP32 for f32 species,
+ * FP64 for f64), written to out[n] of the species' dtype:
+ *   photons,   AXPIC_PRIMAKOFF: lambda_P = w P_{gamma->a}/w_a (Sec. II.F.1, eq. prim_prob)
+ *   electrons, AXPIC_COMPTON / AXPIC_BREMS: lambda_macro (eq. lambda_macro)
+ *   axions,    AXPIC_COMPTON|AXPIC_BREMS: P_abs = 1 - exp(-Gamma_abs dt_phys) (eq. gamma_abs)
+ *   axions,    AXPIC_PRIMAKOFF: a->gamma mean lambda (before the thermal absorption)
+ * These are exactly the values the fused sampling calls compute internally. */
+axpic_status axpic_rates(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                         const axpic_species* sp, int32_t channel, void* out, void* stream);
+
+/* axpic_sample_emit -- Secs. II.D, II.F.1, II.G, II.H.  Forward operators on
+ * the first parent->n particles of `parent`:
+ *   photons (AXPIC_PRIMAKOFF): K ~ Poisson(min(lambda_P, cap)) conversions,
+ *     each product inherits x and p, parent weight depleted by K w_a';
+ *   electrons (AXPIC_COMPTON and/or AXPIC_BREMS): K per channel, each event
+ *     an axion at the emitter's position with E = T x, x from the channel's
+ *     number spectrum (Compton x^4/(e^x-1); brems Gamma(k, theta)) and an
+ *     isotropic direction; fb[cell] -= (w E, w p).
+ * Products are appended to `axions` at axions->n .. in the canonical order
+ * (parent index, channel, event k) with ids (next_id + rank) | 2^63.
+ * lam_in: NULL (fused rates) or the per-parent means (photons: [n];
+ * electrons: [2][n] Compton then brems) in the parent's dtype.
+ * hist: [3][nbins+2] FP64 power histogram (w_phys E [keV]) or NULL;
+ * fb: [ncell][4] FP64 (dE [m_e c^2], dP [m_e c]) or NULL; stats:
+ * [AXPIC_ST_COUNT] or NULL; status: int64[AXPIC_STATUS_N] (status[2] =
+ * products written).  On return axions->n is NOT updated (the count is on
+ * the device); the caller reads status[2]. */
+axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
+                               const axpic_params* prm, axpic_species* parent, int32_t channels,
+                               const void* lam_in, int64_t step, uint64_t next_id,
+                               axpic_species* axions, double* fb, double* hist, double* stats,
+                               int64_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* axpic_absorb -- Sec. II.I and the inverse of Sec. II.F.1.  On the first
+ * axions->n axions: thermal absorption (delete with probability P_abs or
+ * reduce the weight by it; fb[cell] += (w E, w p)), then a->gamma conversion
+ * of what survives (products appended to `photons` with ids as above).
+ * pabs_in / lam_in optionally replace the computed P_abs / a->gamma means. */
+axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                          axpic_species* axions, const void* pabs_in, const void* lam_in,
+                          int64_t step, uint64_t next_id, axpic_species* photons, double* fb,
+                          double* stats, int64_t* status, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* axpic_feedback -- Sec. II.J.  Per cell over the electrons (grouped by cell,
+ * offsets off[ncell+1]): FP64 moments W, P, U2 (eq. cell_moments), the
+ * affine remap p' = S p + b (eqs. delta_def .. b_def, applied when
+ * prm->feedback) and the temperature update (eqs. Te_est, Te_relax, clamp)
+ * when prm->T_mode == 2.  moments: [ncell][5] FP64 output (before the remap)
+ * or NULL. */
+axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
+                            axpic_species* electrons, const int64_t* off, const double* fb,
+                            double* moments, double* stats, void* stream);
+
+/* axpic_compact -- stable removal of particles with w <= 0 from `in` into
+ * `out` (distinct buffers, same dtype, out->capacity >= in->n).  status[2]
+ * receives the surviving count. */
+axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t* status,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* axpic_diag -- Sec. III.E: out[0] = N_a = sum w_ref w, out[1] = U_a =
+ * sum w_ref w E [keV] over the species (FP64, deterministic order). */
+axpic_status axpic_diag(const axpic_species* sp, double* out, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* axpic_sampler_table -- host-only access to the thermal energy samplers'
+ * quantile tables (no device work).  which = 0: Compton-like number spectrum
+ * x^4/(e^x-1) (Sec. II.G); which = 1: Gamma(k, 1) (Sec. II.H).  out receives
+ * 2*(2048+1) doubles: y = ln x at z_j = -18 + 36 j/2048 (z = ln(u/(1-u))),
+ * then dy/dz at the same nodes. */
+axpic_status axpic_sampler_table(int32_t which, double k, double* out);
+
+/* axpic_stream_copy -- plain device copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned): the calibration kernel for achievable HBM
+ * bandwidth and for scaling the profiler's byte counters. */
+axpic_status axpic_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* axpic_timing_enable / axpic_timing_read -- instrumentation.  While enabled,
+ * every kernel the library launches is bracketed by HIP events recorded on
+ * its own stream.  axpic_timing_read waits for those events and writes one
+ * line "kernel_name launches total_ms" per kernel into buf (NUL-terminated),
+ * then resets the counters; AXPIC_E_CAPACITY if buf was too short. */
+void axpic_timing_enable(int32_t on);
+axpic_status axpic_timing_read(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1479 @@
+// axpic.hip -- HIP (gfx950) implementation of the axion Monte-Carlo operators
+// behind the C ABI in include/axpic.h.
+//
+// Layout of the work: every per-particle operator that creates products runs
+// as three launches over the parent stream
+//   count : rates + Philox + Poisson per parent, 16-bit event code per parent,
+//           per-block totals;
+//   scan  : one workgroup turns the block totals into exclusive offsets and
+//           checks the capacity;
+//   apply : blocks with activity recompute their parents' rates (bitwise the
+//           same values), scan the codes in parent order and write products,
+//           depletion, histogram and feedback.
+// Products therefore land in the canonical order (parent, channel, event) and
+// their ids come from the offset, never from an atomic slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/axpic.h"
+#include "axpic_device.hpp"
+#include "axpic_tables.h"
+
+using namespace axpic;
+
+namespace {
+
+constexpr int kThreads = 256;          // threads per workgroup
+constexpr int kPer = 4;                // parents per thread in the count/apply kernels
+constexpr int kBlockParents = kThreads * kPer;
+constexpr int kStatSlots = 12;         // per-block partial statistics
+constexpr int kScanThreads = 1024;
+
+__device__ double g_tab_compton[2 * (kTabN + 1)];
+__device__ double g_tab_gamma[2 * (kTabN + 1)];
+
+// ------------------------------------------------------------------ workspace
+struct Workspace {
+    uint16_t* code;      // [n_max]
+    uint32_t* bsum;      // [nb] products per block
+    uint32_t* bact;      // [nb] active parents per block
+    uint64_t* boff;      // [nb] exclusive product offsets
+    double* bstat;       // [nb][kStatSlots]
+    int64_t* ctrl;       // [8]: 0 skip flag, 1 total
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+inline int64_t nblocks_for(int64_t n) { return (n + kBlockParents - 1) / kBlockParents; }
+
+size_t ws_bytes_for(int64_t n) {
+    int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
+    return align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1)) + align256(4 * (size_t)nb) +
+           align256(4 * (size_t)nb) + align256(8 * (size_t)nb) +
+           align256(sizeof(double) * kStatSlots * (size_t)nb) + 256;
+}
+
+bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
+    if (!ws || bytes < ws_bytes_for(n)) return false;
+    int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
+    char* p = (char*)ws;
+    w->code = (uint16_t*)p; p += align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1));
+    w->bsum = (uint32_t*)p; p += align256(4 * (size_t)nb);
+    w->bact = (uint32_t*)p; p += align256(4 * (size_t)nb);
+    w->boff = (uint64_t*)p; p += align256(8 * (size_t)nb);
+    w->bstat = (double*)p; p += align256(sizeof(double) * kStatSlots * (size_t)nb);
+    w->ctrl = (int64_t*)p;
+    return true;
+}
+
+// ------------------------------------------------------------------ host params
+KParams make_kparams(const axpic_grid* g, const axpic_params* prm, double w_ref_g) {
+    KParams k;
+    std::memset(&k, 0, sizeof(k));
+    k.dt_phys = g->dt / g->omega0;
+    k.w_a = prm->w_a;
+    for (int i = 0; i < 3; ++i) k.wa_mul[i] = prm->wa_mul[i];
+    k.w_gamma_prod = prm->w_gamma_prod > 0.0 ? prm->w_gamma_prod : w_ref_g;
+    k.cap = (prm->lambda_cap <= kLambdaHardCap) ? prm->lambda_cap : kLambdaHardCap;
+    k.inv_ratio = prm->prim_inv_ratio;
+    k.ag_unit = (w_ref_g > 0.0 && k.w_gamma_prod > 0.0)
+                    ? prm->prim_inv_ratio * prm->w_a * prm->w_a * prm->wa_mul[0] /
+                          (w_ref_g * k.w_gamma_prod)
+                    : 0.0;
+    k.brems_k = prm->brems_k;
+    k.brems_theta = prm->brems_theta;
+    k.nbins = prm->hist_nbins;
+    k.hist_log = prm->hist_log;
+    k.hist_lo = prm->hist_lo_keV;
+    k.hist_scale = prm->hist_log ? prm->hist_nbins / std::log(prm->hist_hi_keV / prm->hist_lo_keV)
+                                 : prm->hist_nbins / (prm->hist_hi_keV - prm->hist_lo_keV);
+    k.r_relax = prm->r_relax;
+    k.T_floor = prm->T_floor_keV;
+    k.T_ceil = prm->T_ceil_keV;
+    k.dtdx = g->dt / g->dx;
+    k.seed_lo = (uint32_t)prm->seed;
+    k.seed_hi = (uint32_t)(prm->seed >> 32);
+    k.channels = prm->channels;
+    k.inverse = prm->inverse;
+    k.absorb_mode = prm->absorb_mode;
+    k.eq_stats = prm->eq_stats;
+    k.T_mode = prm->T_mode;
+    k.feedback = prm->feedback;
+    k.ndim = g->ndim;
+    for (int d = 0; d < 3; ++d) k.n[d] = g->n[d];
+    return k;
+}
+
+bool grid_ok(const axpic_grid* g) {
+    if (!g || g->ndim < 1 || g->ndim > 3) return false;
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 1) return false;
+        if (d >= g->ndim && g->n[d] != 1) return false;
+    }
+    if (!(g->dx > 0.0) || !(g->dt > 0.0) || !(g->omega0 > 0.0)) return false;
+    if ((int64_t)g->n[0] * g->n[1] * g->n[2] > INT32_MAX) return false;
+    return true;
+}
+
+bool params_ok(const axpic_params* p) {
+    if (!p) return false;
+    if (!(p->lambda_cap > 0.0) || !(p->w_a > 0.0)) return false;
+    if (!(p->r_relax >= 0.0 && p->r_relax <= 1.0)) return false;
+    if (p->hist_nbins < 1 || !(p->hist_hi_keV > p->hist_lo_keV)) return false;
+    if (p->hist_log && !(p->hist_lo_keV > 0.0)) return false;
+    if (!(p->brems_k > 0.0) || !(p->brems_theta >= 1.0)) return false;
+    for (int i = 0; i < 3; ++i)
+        if (!(p->wa_mul[i] > 0.0)) return false;
+    return true;
+}
+
+int64_t ncell_of(const axpic_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
+
+bool species_ok(const axpic_species* s, bool need_p) {
+    if (!s || s->n < 0 || s->capacity < s->n) return false;
+    if (s->dtype != AXPIC_F32 && s->dtype != AXPIC_F64) return false;
+    if (s->n == 0) return true;
+    if (!s->w || !s->id || !s->cell) return false;
+    if (need_p && (!s->p[0] || !s->p[1] || !s->p[2])) return false;
+    return true;
+}
+
+// Sampler tables: per device, uploaded on first use and when brems_k changes.
+std::mutex g_tab_mutex;
+struct TabState { bool compton = false; double k = -1.0; };
+std::vector<TabState> g_tab_state;
+
+axpic_status ensure_tables(double k) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return AXPIC_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_tab_mutex);
+    if ((int)g_tab_state.size() <= dev) g_tab_state.resize(dev + 1);
+    TabState& st = g_tab_state[dev];
+    static std::vector<double> buf(2 * (kTabN + 1));
+    if (!st.compton) {
+        axpic_host::build_compton_table(buf.data());
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_tab_compton), buf.data(), sizeof(double) * buf.size()) !=
+            hipSuccess)
+            return AXPIC_E_DEVICE;
+        st.compton = true;
+    }
+    if (st.k != k) {
+        axpic_host::build_gamma_table(buf.data(), k);
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_tab_gamma), buf.data(), sizeof(double) * buf.size()) !=
+            hipSuccess)
+            return AXPIC_E_DEVICE;
+        st.k = k;
+    }
+    return AXPIC_OK;
+}
+
+inline axpic_status launched() {
+    return hipGetLastError() == hipSuccess ? AXPIC_OK : AXPIC_E_DEVICE;
+}
+
+
+// ------------------------------------------------------------------ kernel timing
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// every kernel, read back and accumulated by axpic_timing_read.
+struct PendingTime { const char* name; hipEvent_t a, b; };
+struct TimingState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<PendingTime> pending;
+    std::vector<std::pair<std::string, std::pair<long long, double>>> acc;
+};
+TimingState& timing() { static TimingState t; return t; }
+
+hipEvent_t pool_get(TimingState& t) {
+    if (!t.pool.empty()) { hipEvent_t e = t.pool.back(); t.pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct KTimer {
+    const char* name; hipStream_t s; hipEvent_t a = nullptr, b = nullptr;
+    KTimer(const char* n, hipStream_t st) : name(n), s(st) {
+        TimingState& t = timing();
+        if (!t.on) return;
+        std::lock_guard<std::mutex> lock(t.mu);
+        a = pool_get(t); b = pool_get(t);
+        if (a && b) hipEventRecord(a, s);
+    }
+    ~KTimer() {
+        if (!a || !b) return;
+        TimingState& t = timing();
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lock(t.mu);
+        t.pending.push_back({name, a, b});
+    }
+};
+
+#define LAUNCH(NAME, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                       \
+    do {                                                                                           \
+        KTimer kt_(NAME, STREAM);                                                                  \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                         \
+    } while (0)
+
+// ------------------------------------------------------------------ device helpers
+__device__ __forceinline__ int hist_bin(const KParams& kp, double E) {
+    double t = kp.hist_log ? log(E / kp.hist_lo) * kp.hist_scale : (E - kp.hist_lo) * kp.hist_scale;
+    double b = floor(t);
+    if (!(b >= 0.0)) return kp.nbins;
+    if (b >= (double)kp.nbins) return kp.nbins + 1;
+    return (int)b;
+}
+
+template <typename T>
+__device__ __forceinline__ T psq(const T* __restrict__ px, const T* __restrict__ py,
+                                 const T* __restrict__ pz, int64_t i) {
+    const T a = px[i], b = py[i], c = pz[i];
+    return a * a + b * b + c * c;
+}
+
+template <typename T> struct PrefOf;
+template <> struct PrefOf<float> { static __device__ const float* get(const float* p32, const double*) { return p32; } };
+template <> struct PrefOf<double> { static __device__ const double* get(const float*, const double* p64) { return p64; } };
+
+// lambda_P = w P_{gamma->a} / w_prod with P = 1 - exp(-c_P F(s)) (eqs. prim_xs, prim_prob)
+template <typename T>
+__device__ __forceinline__ T lambda_primakoff(const T* __restrict__ pc, T w, T p2) {
+    const T s = pc[1] * p2;
+    const T F = screenF(s);
+    const T x = pc[2] * F;
+    return w * pc[3] * F * one_minus_exp_over(x);
+}
+
+// Thermal absorption probability, eq. gamma_abs: Gamma_abs dt = aC E^2 g_C + aB g_B
+template <typename T>
+__device__ __forceinline__ T pabs_thermal(const KParams& kp, const T* __restrict__ pc, T E) {
+    const T Tk = pc[0];
+    const T x = E / Tk;
+    T g = (T)0;
+    if (pc[6] != (T)0) {
+        T occ = kp.eq_stats ? -dev_expm1<T>(-x) : (T)1;
+        g += pc[6] * E * E / occ;
+    }
+    if (pc[7] != (T)0) {
+        const T th = (T)kp.brems_theta, k = (T)kp.brems_k;
+        const T pw = dev_exp<T>((k - (T)3) * dev_log<T>(x));
+        // MB: e^{x(1-1/theta)}; BE: e^{-x/theta} (e^x - 1), with expm1 for small x
+        T shape;
+        if (kp.eq_stats || x > (T)60) shape = dev_exp<T>(x * ((T)1 - (T)1 / th));
+        else shape = dev_exp<T>(-x / th) * dev_expm1<T>(x);
+        g += pc[7] * pw * shape;
+    }
+    return -dev_expm1<T>(-g);
+}
+
+// a->gamma mean: w_a-weight * (w_a/w_gamma_prod) * (1 - exp(-ratio c_P F))
+template <typename T>
+__device__ __forceinline__ T lambda_ag(const KParams& kp, const T* __restrict__ pc, T w, T p2) {
+    const T s = pc[1] * p2;
+    const T F = screenF(s);
+    const T x = (T)kp.inv_ratio * pc[2] * F;
+    const T unit = (T)((double)pc[3] * kp.ag_unit);
+    return w * unit * F * one_minus_exp_over(x);
+}
+
+// ------------------------------------------------------------------ block scan
+// Exclusive scan of one value per thread across the workgroup (kThreads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds_w, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) lds_w[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        uint32_t s = lds_w[w];
+        if (w < wave) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* lds_w) {
+    uint32_t tot;
+    (void)block_excl_scan(v, lds_w, &tot);
+    return tot;
+}
+
+__device__ void block_stats_store(double* st, double* bstat_block, double* lds) {
+    // reduce kStatSlots doubles over the workgroup; lds has kStatSlots * 4 doubles
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int s = 0; s < kStatSlots; ++s) {
+        double v = wave_sum(st[s]);
+        if (lane == 0) lds[s * 4 + wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kStatSlots) {
+        const int s = threadIdx.x;
+        bstat_block[s] = lds[s * 4 + 0] + lds[s * 4 + 1] + lds[s * 4 + 2] + lds[s * 4 + 3];
+    }
+}
+
+// ------------------------------------------------------------------ scan kernel
+// One workgroup: exclusive offsets of the block product counts, capacity check.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t nb,
+       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status) {
+    __shared__ uint64_t lds[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t b0 = std::min<int64_t>(nb, (int64_t)t * chunk), b1 = std::min<int64_t>(nb, b0 + chunk);
+    uint64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+    uint64_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wave) base += lds[w];
+        tot += lds[w];
+    }
+    uint64_t run = base + inc - s;
+    for (int64_t b = b0; b < b1; ++b) {
+        boff[b] = run;
+        run += bsum[b];
+    }
+    if (t == 0) {
+        const bool over = n_out + (int64_t)tot > capacity;
+        ctrl[0] = over ? 1 : 0;
+        ctrl[1] = (int64_t)tot;
+        if (status) {
+            status[0] = n_out + (int64_t)tot;
+            status[1] = over ? AXPIC_FLAG_CAPACITY : 0;
+            status[2] = over ? 0 : (int64_t)tot;
+            status[3] = 0;
+        }
+    }
+}
+
+// Deterministic final reduction of the per-block statistics into stats[].
+struct StatMap { int m[kStatSlots]; };
+
+__global__ void __launch_bounds__(kThreads)
+k_stats_reduce(const double* __restrict__ bstat, const uint32_t* __restrict__ bact, int64_t nb,
+               const int64_t* __restrict__ ctrl, StatMap map, double* __restrict__ stats) {
+    if (ctrl[0]) return;
+    const int s = threadIdx.x;
+    if (s >= kStatSlots || map.m[s] < 0) return;
+    double acc = 0.0;
+    for (int64_t b = 0; b < nb; ++b)
+        if (bact[b]) acc += bstat[b * kStatSlots + s];
+    stats[map.m[s]] += acc;
+}
+
+// ------------------------------------------------------------------ cell state
+__global__ void __launch_bounds__(kThreads)
+k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restrict__ dens,
+             int32_t nion, double Z0, double Z1, double Z2, double Z3, double A0, double A1,
+             double A2, double A3, axpic_params prm, double dt_phys, double w_ref_e,
+             double w_ref_g, double* __restrict__ state, float* __restrict__ p32,
+             double* __restrict__ p64) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const double Zs[4] = {Z0, Z1, Z2, Z3}, As[4] = {A0, A1, A2, A3};
+    double nZ = 0.0, nZ2 = 0.0, rho = 0.0, rhoH = 0.0;
+    for (int s = 0; s < nion; ++s) {
+        const double ni = dens[(int64_t)(1 + s) * ncell + c];
+        nZ += Zs[s] * ni;
+        nZ2 += Zs[s] * Zs[s] * ni;
+        const double m = ni * As[s] * kMu;
+        rho += m;
+        if (Zs[s] == 1.0 && As[s] < 1.5) rhoH += m;
+    }
+    const double ne_dep = dens[c];
+    const double ne = prm.quasi_neutral ? nZ : ne_dep;
+    const double T = Tk[c];
+    const double XH = rho > 0.0 ? rhoH / rho : 0.0;
+    const double hc3 = kHbarcKeVcm * kHbarcKeVcm * kHbarcKeVcm;
+    const double kappa2 = prm.kappa_mode == 1 ? prm.kappa_fixed_keV * prm.kappa_fixed_keV
+                                              : 4.0 * kPi * kAlpha * (ne + nZ2) * hc3 / T;
+    const double targets = prm.prim_targets ? (ne + nZ2) : nZ2;
+    const double G_P0 = prm.boost * kAlpha * prm.g_agg_GeV * prm.g_agg_GeV * 0.125 *
+                        (kHbarcGeVcm * kHbarcGeVcm) * kC * targets;
+    const double a_ae = prm.g_ae * prm.g_ae / (4.0 * kPi) / 1.60e-23;
+    const double T7 = T * kKeVT7;
+    const double T7sq = T7 * T7;
+    const double Q_C = rho * 2.67e-2 * (1.0 + XH) * (T7sq * T7sq * T7sq) * a_ae;
+    const double rho2 = rho * 0.01;
+    const double eta = (3.0 + XH) * rho2 / T7sq;
+    const double base = 0.150 * T7sq * sqrt(T7) * rho2 * (1.0 + XH) * a_ae;
+    const double fZ = fmax(0.0, 1.0 - 6.98e-2 * eta), fE = fmax(0.0, 1.0 - 0.140 * eta);
+    const double epsB = base * fZ + (prm.brems_ee ? base * (1.0 + XH) * (0.25 * sqrt(2.0)) * fE : 0.0);
+    const double Q_B = rho * epsB;
+    const double meanC = 5.0 * kZeta6 / kZeta5 * T, meanB = prm.brems_k * prm.brems_theta * T;
+    const double G_C = ne > 0.0 ? prm.boost * Q_C / (ne * meanC * kKeVerg) : 0.0;
+    const double G_B = ne > 0.0 ? prm.boost * Q_B / (ne * meanB * kKeVerg) : 0.0;
+    double* st = state + c * AXPIC_STATE_N;
+    st[0] = T; st[1] = ne; st[2] = ne_dep; st[3] = nZ; st[4] = nZ2; st[5] = rho; st[6] = XH;
+    st[7] = kappa2; st[8] = G_P0; st[9] = G_C; st[10] = G_B; st[11] = Q_C; st[12] = Q_B;
+    st[13] = meanC; st[14] = meanB; st[15] = 0.0;
+    const bool onP = prm.channels & AXPIC_PRIMAKOFF, onC = prm.channels & AXPIC_COMPTON,
+               onB = prm.channels & AXPIC_BREMS;
+    double pr[AXPIC_PREF_N];
+    pr[0] = T;
+    pr[1] = 4.0 * kMe * kMe / kappa2;
+    pr[2] = G_P0 * dt_phys;
+    pr[3] = onP ? G_P0 * dt_phys * w_ref_g / (prm.w_a * prm.wa_mul[0]) : 0.0;
+    pr[4] = onC ? w_ref_e * G_C * dt_phys / (prm.w_a * prm.wa_mul[1]) : 0.0;
+    pr[5] = onB ? w_ref_e * G_B * dt_phys / (prm.w_a * prm.wa_mul[2]) : 0.0;
+    // detailed-balance absorption coefficients (eq. gamma_abs) times dt_phys
+    const double twopi2hc3 = 2.0 * kPi * kPi * hc3;
+    pr[6] = (prm.inverse && onC && T > 0.0)
+                ? ne_dep * G_C * twopi2hc3 * dt_phys / (24.0 * kZeta5 * T * T * T * T * T) : 0.0;
+    const double k = prm.brems_k, th = prm.brems_theta;
+    pr[7] = (prm.inverse && onB && T > 0.0)
+                ? ne_dep * G_B * twopi2hc3 * dt_phys / (exp(lgamma(k)) * pow(th, k) * T * T * T) : 0.0;
+    for (int i = 0; i < AXPIC_PREF_N; ++i) {
+        p64[c * AXPIC_PREF_N + i] = pr[i];
+        p32[c * AXPIC_PREF_N + i] = (float)pr[i];
+    }
+}
+
+// ------------------------------------------------------------------ deposit
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_deposit(int64_t ncell, const T* __restrict__ w, const int64_t* __restrict__ off, double scale,
+          double* __restrict__ dens_slot) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    double s = 0.0;
+    for (int64_t i = off[c]; i < off[c + 1]; ++i) s += (double)w[i];
+    dens_slot[c] = s * scale;
+}
+
+// ------------------------------------------------------------------ bin_cells
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_bin(int64_t n, KParams kp, int push, T* __restrict__ x0, T* __restrict__ x1, T* __restrict__ x2,
+      const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
+      int32_t* __restrict__ cell) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T* xs[3] = {x0, x1, x2};
+    T pv[3] = {px[i], py[i], pz[i]};
+    T inv = (T)0;
+    if (push) {
+        const T s = dev_fma<T>(pv[2], pv[2], dev_fma<T>(pv[1], pv[1], pv[0] * pv[0]));
+        inv = s > (T)0 ? (T)1 / dev_sqrt<T>(s) : (T)0;
+    }
+    const T dtdx = (T)kp.dtdx;
+    int64_t c = 0, stride = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int nd = kp.n[d];
+        T x = (d < kp.ndim) ? xs[d][i] : (T)0;
+        if (d < kp.ndim && push) {
+            const T v = pv[d] * inv;
+            x = dev_fma<T>(v, dtdx, x);
+            if (x < (T)0) x = x + (T)nd;
+            if (x >= (T)nd) x = x - (T)nd;
+            xs[d][i] = x;
+        }
+        int64_t ix = (int64_t)dev_floor<T>(x);
+        ix = ix < 0 ? 0 : (ix > nd - 1 ? nd - 1 : ix);
+        c += ix * stride;
+        stride *= nd;
+    }
+    cell[i] = (int32_t)c;
+}
+
+// ------------------------------------------------------------------ rates
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const double* __restrict__ p64,
+        const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
+        const T* __restrict__ pz, const int32_t* __restrict__ cell, T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T* pc = PrefOf<T>::get(p32, p64) + (int64_t)cell[i] * AXPIC_PREF_N;
+    const T wt = w[i];
+    T r = (T)0;
+    if (mode == 0) {                       // photons, Primakoff
+        r = wt > (T)0 ? lambda_primakoff<T>(pc, wt, psq<T>(px, py, pz, i)) : (T)0;
+    } else if (mode == 1) {                // electrons, Compton
+        r = wt * pc[4];
+    } else if (mode == 2) {                // electrons, brems
+        r = wt * pc[5];
+    } else if (mode == 3) {                // axions, thermal absorption probability
+        r = wt > (T)0 ? pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(psq<T>(px, py, pz, i))) : (T)0;
+    } else {                               // axions, a->gamma mean
+        r = wt > (T)0 ? lambda_ag<T>(kp, pc, wt, psq<T>(px, py, pz, i)) : (T)0;
+    }
+    out[i] = r;
+}
+
+// ------------------------------------------------------------------ Primakoff emission
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
+             const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
+             const T* __restrict__ py, const T* __restrict__ pz, const uint64_t* __restrict__ id,
+             const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+             uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
+    __shared__ uint32_t lds[kThreads / 64];
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint32_t tot = 0, act = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        if (i >= n) break;
+        const T wt = w[i];
+        T l = (T)0;
+        if (wt > (T)0)
+            l = lam_in ? lam_in[i]
+                       : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
+                                             psq<T>(px, py, pz, i));
+        int K = 0;
+        if (l > (T)0) {
+            double ws; int cp;
+            const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
+            const uint4 r = draw(kp, id[i], step, 0, 0);
+            K = poisson_inv(le, u53(r.x, r.y));
+        }
+        code[i] = (uint16_t)K;
+        tot += K;
+        act += K > 0;
+    }
+    const uint32_t bt = block_sum_u32(tot, lds);
+    const uint32_t ba = block_sum_u32(act, lds);
+    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_prim_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_g,
+             const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
+             const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
+             const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
+             const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+             const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
+             const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
+             int64_t out_cap, T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2,
+             T* __restrict__ apx, T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
+             uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ hist,
+             double* __restrict__ bstat) {
+    __shared__ uint32_t lds[kThreads / 64];
+    __shared__ double lds_st[kStatSlots * 4];
+    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    double st[kStatSlots];
+    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    uint64_t run = boff[blockIdx.x];
+    const int nbh = kp.nbins + 2;
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const uint32_t K = (i < n) ? code[i] : 0u;
+        uint32_t segtot;
+        const uint32_t pre = block_excl_scan(K, lds, &segtot);
+        if (K > 0) {
+            const T wt = w[i];
+            const T l = lam_in ? lam_in[i]
+                               : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
+                                                     psq<T>(px, py, pz, i));
+            double ws; int cp;
+            (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+            double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
+            const double wpar = w_ref_g * (double)wt;
+            double dep = (double)K * wp;
+            if (dep > wpar) { wp = wpar / (double)K; dep = wpar; st[10] += 1.0; }
+            st[9] += cp ? 1.0 : 0.0;
+            const T pxv = px[i], pyv = py[i], pzv = pz[i];
+            const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
+            const T wrel = (T)(wp / kp.w_a);
+            const int bin = hist ? hist_bin(kp, E) : 0;
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint64_t rank = run + pre + k;
+                const int64_t slot = out_n + (int64_t)rank;
+                if (slot < out_cap) {
+                    ax0[slot] = x0 ? x0[i] : (T)0;
+                    if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
+                    if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
+                    apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
+                    aw[slot] = wrel;
+                    aid[slot] = (next_id + rank) | (1ull << 63);
+                    acell[slot] = cell[i];
+                }
+                if (hist) atomicAdd(&hist[0 * nbh + bin], wp * E);
+            }
+            st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
+            w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
+        }
+        run += segtot;
+    }
+    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+}
+
+// ------------------------------------------------------------------ thermal emission
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
+              const double* __restrict__ p64, const T* __restrict__ w,
+              const uint64_t* __restrict__ id, const int32_t* __restrict__ cell,
+              const T* __restrict__ lam_in, uint16_t* __restrict__ code,
+              uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
+    __shared__ uint32_t lds[kThreads / 64];
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint32_t tot = 0, act = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        if (i >= n) break;
+        T lC, lB;
+        if (lam_in) { lC = lam_in[i]; lB = lam_in[n + i]; }
+        else {
+            const T* pc = pref + (int64_t)cell[i] * AXPIC_PREF_N;
+            const T wt = w[i];
+            lC = wt * pc[4];
+            lB = wt * pc[5];
+        }
+        if (!onC) lC = (T)0;
+        if (!onB) lB = (T)0;
+        int KC = 0, KB = 0;
+        if (lC > (T)0 || lB > (T)0) {
+            const uint4 r = draw(kp, id[i], step, 1, 0);
+            double ws; int cp;
+            KC = poisson_inv(cap_lambda((double)lC, kp.cap, &ws, &cp), u53(r.x, r.y));
+            KB = poisson_inv(cap_lambda((double)lB, kp.cap, &ws, &cp), u53(r.z, r.w));
+        }
+        code[i] = (uint16_t)(KC | (KB << 8));
+        tot += KC + KB;
+        act += (KC + KB) > 0;
+    }
+    const uint32_t bt = block_sum_u32(tot, lds);
+    const uint32_t ba = block_sum_u32(act, lds);
+    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_therm_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_e,
+              const float* __restrict__ p32, const double* __restrict__ p64,
+              const double* __restrict__ state, const T* __restrict__ w, const T* __restrict__ x0,
+              const T* __restrict__ x1, const T* __restrict__ x2, const uint64_t* __restrict__ id,
+              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+              const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
+              const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
+              int64_t out_cap, T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2,
+              T* __restrict__ apx, T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
+              uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ fb,
+              double* __restrict__ hist, double* __restrict__ bstat) {
+    __shared__ uint32_t lds[kThreads / 64];
+    __shared__ double lds_st[kStatSlots * 4];
+    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    double st[kStatSlots];
+    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    uint64_t run = boff[blockIdx.x];
+    const int nbh = kp.nbins + 2;
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const uint32_t cd = (i < n) ? code[i] : 0u;
+        const uint32_t Ktot = (cd & 0xFFu) + (cd >> 8);
+        uint32_t segtot;
+        const uint32_t pre = block_excl_scan(Ktot, lds, &segtot);
+        if (Ktot > 0) {
+            const int32_t c = cell[i];
+            const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
+            const double Tc = state[(int64_t)c * AXPIC_STATE_N + 0];
+            const T wt = w[i];
+            uint32_t rank = pre;
+            for (int ch = 1; ch <= 2; ++ch) {
+                const uint32_t K = ch == 1 ? (cd & 0xFFu) : (cd >> 8);
+                if (K == 0) continue;
+                T l;
+                if (lam_in) l = lam_in[(int64_t)(ch - 1) * n + i];
+                else l = wt * pc[3 + ch];
+                double ws; int cp;
+                (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+                st[9] += cp ? 1.0 : 0.0;
+                const double wp = kp.w_a * kp.wa_mul[ch] * ws;
+                const T wrel = (T)(kp.wa_mul[ch] * ws);
+                const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
+                const double xs = ch == 1 ? 1.0 : kp.brems_theta;
+                for (uint32_t k = 0; k < K; ++k) {
+                    const uint4 r = draw(kp, id[i], step, 1 + ch, k);
+                    const double E = Tc * xs * quantile(tab, u24(r.x));
+                    const double mu = 2.0 * u24(r.y) - 1.0;
+                    const double phi = 2.0 * kPi * u24(r.z);
+                    const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+                    double sphi, cphi;
+                    sincos(phi, &sphi, &cphi);
+                    const double pm = E / kMe;
+                    const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
+                    const uint64_t grank = run + rank;
+                    const int64_t slot = out_n + (int64_t)grank;
+                    if (slot < out_cap) {
+                        ax0[slot] = x0 ? x0[i] : (T)0;
+                        if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
+                        if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
+                        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
+                        aw[slot] = wrel;
+                        aid[slot] = (next_id + grank) | (1ull << 63);
+                        acell[slot] = c;
+                    }
+                    ++rank;
+                    if (hist) atomicAdd(&hist[ch * nbh + hist_bin(kp, E)], wp * E);
+                    if (fb) {
+                        double* f = fb + (int64_t)c * 4;
+                        atomicAdd(&f[0], -wp * pm);
+                        atomicAdd(&f[1], -wp * pa[0]);
+                        atomicAdd(&f[2], -wp * pa[1]);
+                        atomicAdd(&f[3], -wp * pa[2]);
+                    }
+                    st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
+                }
+            }
+        }
+        run += segtot;
+    }
+    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+}
+
+// ------------------------------------------------------------------ absorption
+// code: bits 0-7 a->gamma count, bit 8 absorbed (deletion mode)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
+            const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
+            const T* __restrict__ py, const T* __restrict__ pz, const uint64_t* __restrict__ id,
+            const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
+            const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
+            uint32_t* __restrict__ bact) {
+    __shared__ uint32_t lds[kThreads / 64];
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
+    const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint32_t tot = 0, act = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        if (i >= n) break;
+        T wt = w[i];
+        uint32_t cd = 0;
+        if (wt > (T)0) {
+            const T* pc = pref + (int64_t)cell[i] * AXPIC_PREF_N;
+            const T p2 = psq<T>(px, py, pz, i);
+            const uint4 r = draw(kp, id[i], step, 4, 0);
+            if (thermal) {
+                const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
+                if (kp.absorb_mode == 0) {
+                    if (u53(r.x, r.y) < (double)P) { cd |= 256u; wt = (T)0; }
+                } else {
+                    wt = (T)((double)wt - (double)wt * (double)P);
+                }
+            }
+            if (a2g && wt > (T)0) {
+                const T l = lam_in ? lam_in[i] : lambda_ag<T>(kp, pc, wt, p2);
+                double ws; int cp;
+                cd |= (uint32_t)poisson_inv(cap_lambda((double)l, kp.cap, &ws, &cp), u53(r.z, r.w));
+            }
+        }
+        code[i] = (uint16_t)cd;
+        tot += cd & 0xFFu;
+        act += cd != 0;
+    }
+    const uint32_t bt = block_sum_u32(tot, lds);
+    const uint32_t ba = block_sum_u32(act, lds);
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = bt;
+        // in weight-reduction mode every block with live axions must be applied
+        bact[blockIdx.x] = (kp.absorb_mode == 1 && thermal) ? 1u + ba : ba;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_a,
+            const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
+            const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
+            const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
+            const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
+            const T* __restrict__ lam_in, const uint16_t* __restrict__ code,
+            const uint32_t* __restrict__ bact, const uint64_t* __restrict__ boff,
+            const int64_t* __restrict__ ctrl, int64_t out_n, int64_t out_cap, T* __restrict__ gx0,
+            T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gpx, T* __restrict__ gpy,
+            T* __restrict__ gpz, T* __restrict__ gw, uint64_t* __restrict__ gid,
+            int32_t* __restrict__ gcell, double w_ref_g, double* __restrict__ fb,
+            double* __restrict__ bstat) {
+    __shared__ uint32_t lds[kThreads / 64];
+    __shared__ double lds_st[kStatSlots * 4];
+    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    double st[kStatSlots];
+    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    uint64_t run = boff[blockIdx.x];
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const uint32_t cd = (i < n) ? code[i] : 0u;
+        const uint32_t K = cd & 0xFFu;
+        uint32_t segtot;
+        const uint32_t pre = block_excl_scan(K, lds, &segtot);
+        const bool live = i < n && w[i] > (T)0;
+        if (live && (cd != 0 || (thermal && kp.absorb_mode == 1))) {
+            T wt = w[i];
+            const int32_t c = cell[i];
+            const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
+            const T pxv = px[i], pyv = py[i], pzv = pz[i];
+            const T p2 = pxv * pxv + pyv * pyv + pzv * pzv;
+            const double pm = sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
+            const double E = kMe * pm;
+            double wphys = w_ref_a * (double)wt;
+            if (thermal) {
+                double dw = 0.0;
+                if (cd & 256u) dw = wphys;
+                else if (kp.absorb_mode == 1) {
+                    const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
+                    wt = (T)((double)wt - (double)wt * (double)P);
+                    dw = wphys - w_ref_a * (double)wt;
+                }
+                if (dw > 0.0) {
+                    if (fb) {
+                        double* f = fb + (int64_t)c * 4;
+                        atomicAdd(&f[0], dw * pm);
+                        atomicAdd(&f[1], dw * (double)pxv);
+                        atomicAdd(&f[2], dw * (double)pyv);
+                        atomicAdd(&f[3], dw * (double)pzv);
+                    }
+                    st[0] += dw; st[1] += dw * E;
+                    if (cd & 256u) st[7] += 1.0;
+                }
+                if (cd & 256u) wt = (T)0;
+                wphys = w_ref_a * (double)wt;
+            }
+            if (K > 0) {
+                const T l = lam_in ? lam_in[i] : lambda_ag<T>(kp, pc, wt, p2);
+                double ws; int cp;
+                (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+                st[5] += cp ? 1.0 : 0.0;
+                double wp = kp.w_gamma_prod * ws;
+                double dep = (double)K * wp;
+                if (dep > wphys) { wp = wphys / (double)K; dep = wphys; st[6] += 1.0; }
+                const T wrel = (T)(wp / w_ref_g);
+                for (uint32_t k = 0; k < K; ++k) {
+                    const uint64_t rank = run + pre + k;
+                    const int64_t slot = out_n + (int64_t)rank;
+                    if (slot < out_cap) {
+                        gx0[slot] = x0 ? x0[i] : (T)0;
+                        if (gx1) gx1[slot] = x1 ? x1[i] : (T)0;
+                        if (gx2) gx2[slot] = x2 ? x2[i] : (T)0;
+                        gpx[slot] = pxv; gpy[slot] = pyv; gpz[slot] = pzv;
+                        gw[slot] = wrel;
+                        gid[slot] = (next_id + rank) | (1ull << 63);
+                        gcell[slot] = c;
+                    }
+                }
+                st[2] += (double)K; st[3] += (double)K * wp; st[4] += (double)K * wp * E;
+                wt = (dep >= wphys) ? (T)0 : (T)((wphys - dep) / w_ref_a);
+            }
+            w[i] = wt;
+        }
+        run += segtot;
+    }
+    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+}
+
+// ------------------------------------------------------------------ feedback
+// One wavefront per cell: FP64 moments, affine remap, temperature update.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ off,
+           const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
+           const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
+           double* __restrict__ stats) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (c >= ncell) return;
+    const int64_t lo = off[c], hi = off[c + 1];
+    double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
+    for (int64_t i = lo + lane; i < hi; i += 64) {
+        const double wi = w_ref * (double)w[i];
+        const double a = px[i], b = py[i], d = pz[i];
+        W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
+        U2 += wi * (a * a + b * b + d * d);
+    }
+    W = wave_sum(W); P0 = wave_sum(P0); P1 = wave_sum(P1); P2 = wave_sum(P2); U2 = wave_sum(U2);
+    if (moments && lane == 0) {
+        double* m = moments + c * 5;
+        m[0] = W; m[1] = P0; m[2] = P1; m[3] = P2; m[4] = U2;
+    }
+    if (!(W > 0.0)) return;
+    const double* f = fb ? fb + c * 4 : nullptr;
+    const double dE = f ? f[0] : 0.0;
+    const double d0 = f ? f[1] / W : 0.0, d1 = f ? f[2] / W : 0.0, d2 = f ? f[3] / W : 0.0;
+    const double var = U2 - (P0 * P0 + P1 * P1 + P2 * P2) / W;
+    const double dEbulk = (2.0 * (d0 * P0 + d1 * P1 + d2 * P2) + W * (d0 * d0 + d1 * d1 + d2 * d2)) * 0.5;
+    const double dEth = dE - dEbulk;
+    double var_new = var + 2.0 * dEth;
+    const bool cold = !(var > 1e-14 * (U2 + 1e-300));
+    double S = 1.0;
+    if (cold) {
+        var_new = var;
+        if (lane == 0 && stats) {
+            atomicAdd(&stats[AXPIC_ST_COLD_CELLS], 1.0);
+            atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], dEth);
+        }
+    } else {
+        if (var_new < 0.0) {
+            if (lane == 0 && stats) {
+                atomicAdd(&stats[AXPIC_ST_CLAMPED_CELLS], 1.0);
+                atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], -var_new * 0.5);
+            }
+            var_new = 0.0;
+        }
+        S = sqrt(var_new / var);
+    }
+    if (kp.feedback && (dE != 0.0 || d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
+        const double b0 = (1.0 - S) * (P0 / W) + d0, b1 = (1.0 - S) * (P1 / W) + d1,
+                     b2 = (1.0 - S) * (P2 / W) + d2;
+        for (int64_t i = lo + lane; i < hi; i += 64) {
+            px[i] = (T)(S * (double)px[i] + b0);
+            py[i] = (T)(S * (double)py[i] + b1);
+            pz[i] = (T)(S * (double)pz[i] + b2);
+        }
+    }
+    if (kp.T_mode == 2 && lane == 0) {
+        const double Test = kMe / 3.0 * var_new / W;
+        double Tn = (1.0 - kp.r_relax) * Tk[c] + kp.r_relax * Test;
+        Tn = Tn < kp.T_floor ? kp.T_floor : (Tn > kp.T_ceil ? kp.T_ceil : Tn);
+        Tk[c] = Tn;
+    }
+}
+
+// ------------------------------------------------------------------ compaction
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_live_count(int64_t n, const T* __restrict__ w, uint16_t* __restrict__ code,
+             uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
+    __shared__ uint32_t lds[kThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint32_t tot = 0;
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        if (i >= n) break;
+        const uint32_t a = w[i] > (T)0 ? 1u : 0u;
+        code[i] = (uint16_t)a;
+        tot += a;
+    }
+    const uint32_t bt = block_sum_u32(tot, lds);
+    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = bt; }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __restrict__ boff,
+                const int64_t* __restrict__ ctrl, int64_t out_cap, int ndim,
+                const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
+                const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
+                const T* __restrict__ w, const uint64_t* __restrict__ id,
+                const int32_t* __restrict__ cell, T* __restrict__ ox0, T* __restrict__ ox1,
+                T* __restrict__ ox2, T* __restrict__ opx, T* __restrict__ opy, T* __restrict__ opz,
+                T* __restrict__ ow, uint64_t* __restrict__ oid, int32_t* __restrict__ ocell) {
+    __shared__ uint32_t lds[kThreads / 64];
+    if (ctrl[0]) return;
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint64_t run = boff[blockIdx.x];
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const uint32_t a = (i < n) ? code[i] : 0u;
+        uint32_t segtot;
+        const uint32_t pre = block_excl_scan(a, lds, &segtot);
+        if (a) {
+            const int64_t s = (int64_t)(run + pre);
+            if (s < out_cap) {
+                ox0[s] = x0[i];
+                if (ndim > 1) ox1[s] = x1[i];
+                if (ndim > 2) ox2[s] = x2[i];
+                opx[s] = px[i]; opy[s] = py[i]; opz[s] = pz[i];
+                ow[s] = w[i]; oid[s] = id[i]; ocell[s] = cell[i];
+            }
+        }
+        run += segtot;
+    }
+}
+
+// ------------------------------------------------------------------ diagnostics
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_diag_partial(int64_t n, double w_ref, const T* __restrict__ w, const T* __restrict__ px,
+               const T* __restrict__ py, const T* __restrict__ pz, double* __restrict__ part) {
+    __shared__ double lds[2 * (kThreads / 64)];
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    double N = 0.0, U = 0.0;
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        if (i >= n) break;
+        const double wi = w_ref * (double)w[i];
+        if (wi > 0.0) {
+            const double a = px[i], b = py[i], c = pz[i];
+            N += wi;
+            U += wi * kMe * sqrt(a * a + b * b + c * c);
+        }
+    }
+    N = wave_sum(N); U = wave_sum(U);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { lds[2 * wave] = N; lds[2 * wave + 1] = U; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k) { a += lds[2 * k]; b += lds[2 * k + 1]; }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_diag_final(int64_t nb, const double* __restrict__ part, double* __restrict__ out) {
+    const int lane = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t k = lane; k < nb; k += 64) { a += part[2 * k]; b += part[2 * k + 1]; }
+    a = wave_sum(a); b = wave_sum(b);
+    if (lane == 0) { out[0] = a; out[1] = b; }
+}
+
+
+// ------------------------------------------------------------------ copy calibration
+__global__ void __launch_bounds__(kThreads)
+k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ host launch helpers
+inline dim3 grid1(int64_t n, int t = kThreads) { return dim3((unsigned)((n + t - 1) / t)); }
+
+const StatMap kEmitMap = {{AXPIC_ST_EVENTS_P, AXPIC_ST_EVENTS_C, AXPIC_ST_EVENTS_B, AXPIC_ST_NUM_P,
+                           AXPIC_ST_NUM_C, AXPIC_ST_NUM_B, AXPIC_ST_EN_P, AXPIC_ST_EN_C,
+                           AXPIC_ST_EN_B, AXPIC_ST_CAPPED, AXPIC_ST_OVERDEPLETED, -1}};
+const StatMap kAbsMap = {{AXPIC_ST_ABS_NUM, AXPIC_ST_ABS_EN, AXPIC_ST_AG_EVENTS, AXPIC_ST_AG_NUM,
+                          AXPIC_ST_AG_EN, AXPIC_ST_CAPPED, AXPIC_ST_OVERDEPLETED,
+                          AXPIC_ST_ABS_EVENTS, -1, -1, -1, -1}};
+
+template <typename T> inline T* TP(void* p) { return (T*)p; }
+template <typename T> inline const T* TCP(const void* p) { return (const T*)p; }
+
+struct SpT {   // typed view of a species
+    void* x[3]; void* p[3]; void* w; uint64_t* id; int32_t* cell;
+};
+
+template <typename T>
+axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_species* ph,
+                            const void* lam_in, int64_t step, uint64_t next_id,
+                            axpic_species* ax, double* hist, double* stats, int64_t* status,
+                            const Workspace& W, hipStream_t s) {
+    const int64_t n = ph->n, nb = nblocks_for(std::max<int64_t>(n, 1));
+    LAUNCH("k_prim_count", k_prim_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
+                       cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
+                       TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), ph->id, ph->cell, TCP<T>(lam_in),
+                       W.code, W.bsum, W.bact);
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
+                       ax->capacity, W.ctrl, status);
+    LAUNCH("k_prim_apply", k_prim_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
+                       kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
+                       TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
+                       TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.bact, W.boff, W.ctrl,
+                       ax->n, ax->capacity, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]),
+                       TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
+                       ax->cell, hist, W.bstat);
+    if (stats)
+        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
+                           W.ctrl, kEmitMap, stats);
+    return launched();
+}
+
+template <typename T>
+axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_species* el,
+                          const void* lam_in, int64_t step, uint64_t next_id, axpic_species* ax,
+                          double* fb, double* hist, double* stats, int64_t* status,
+                          const Workspace& W, hipStream_t s) {
+    const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
+    LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
+                       cells->pref32, cells->pref64, TCP<T>(el->w), el->id, el->cell,
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact);
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
+                       ax->capacity, W.ctrl, status);
+    LAUNCH("k_therm_apply", k_therm_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step,
+                       next_id, kp, el->w_ref, cells->pref32, cells->pref64, cells->state,
+                       TCP<T>(el->w), TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), el->id,
+                       el->cell, TCP<T>(lam_in), W.code, W.bact, W.boff, W.ctrl, ax->n,
+                       ax->capacity, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]),
+                       TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
+                       ax->cell, fb, hist, W.bstat);
+    if (stats)
+        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
+                           W.ctrl, kEmitMap, stats);
+    return launched();
+}
+
+template <typename T>
+axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_species* ax,
+                         const void* pabs_in, const void* lam_in, int64_t step, uint64_t next_id,
+                         axpic_species* ph, double* fb, double* stats, int64_t* status,
+                         const Workspace& W, hipStream_t s) {
+    const int64_t n = ax->n, nb = nblocks_for(std::max<int64_t>(n, 1));
+    LAUNCH("k_abs_count", k_abs_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
+                       cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
+                       TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), ax->id, ax->cell, TCP<T>(pabs_in),
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact);
+    const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
+                       out_cap, W.ctrl, status);
+    LAUNCH("k_abs_apply", k_abs_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
+                       kp, ax->w_ref, cells->pref32, cells->pref64, TP<T>(ax->w), TCP<T>(ax->x[0]),
+                       TCP<T>(ax->x[1]), TCP<T>(ax->x[2]), TCP<T>(ax->p[0]), TCP<T>(ax->p[1]),
+                       TCP<T>(ax->p[2]), ax->cell, TCP<T>(pabs_in), TCP<T>(lam_in), W.code, W.bact,
+                       W.boff, W.ctrl, out_n, out_cap, ph ? TP<T>(ph->x[0]) : nullptr,
+                       ph ? TP<T>(ph->x[1]) : nullptr, ph ? TP<T>(ph->x[2]) : nullptr,
+                       ph ? TP<T>(ph->p[0]) : nullptr, ph ? TP<T>(ph->p[1]) : nullptr,
+                       ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
+                       ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
+                       W.bstat);
+    if (stats)
+        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
+                           W.ctrl, kAbsMap, stats);
+    return launched();
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char* axpic_status_string(int32_t s) {
+    switch (s) {
+    case AXPIC_OK: return "ok";
+    case AXPIC_E_INVAL: return "invalid argument";
+    case AXPIC_E_CAPACITY: return "output capacity exceeded";
+    case AXPIC_E_DOMAIN: return "value outside the model's domain";
+    case AXPIC_E_DEVICE: return "HIP launch or runtime failure";
+    case AXPIC_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+int32_t axpic_version(void) { return 1; }
+
+size_t axpic_workspace_bytes(int64_t n_max) { return ws_bytes_for(n_max) + 64 * sizeof(int); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ ABI entry points
+namespace {
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+}
+
+extern "C" {
+
+axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, void* stream) {
+    if (!grid_ok(g) || !species_ok(sp, push != 0)) return AXPIC_E_INVAL;
+    if (sp->n == 0) return AXPIC_OK;
+    for (int d = 0; d < g->ndim; ++d)
+        if (!sp->x[d]) return AXPIC_E_INVAL;
+    if (push && (!sp->p[0] || !sp->p[1] || !sp->p[2])) return AXPIC_E_INVAL;
+    axpic_params dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    KParams kp = make_kparams(g, &dummy, 1.0);
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_bin", k_bin<float>, grid1(sp->n), dim3(kThreads), 0, S(stream), sp->n, kp,
+                           push, (float*)sp->x[0], (float*)sp->x[1], (float*)sp->x[2],
+                           (const float*)sp->p[0], (const float*)sp->p[1], (const float*)sp->p[2],
+                           sp->cell);
+    else
+        LAUNCH("k_bin", k_bin<double>, grid1(sp->n), dim3(kThreads), 0, S(stream), sp->n, kp,
+                           push, (double*)sp->x[0], (double*)sp->x[1], (double*)sp->x[2],
+                           (const double*)sp->p[0], (const double*)sp->p[1],
+                           (const double*)sp->p[2], sp->cell);
+    return launched();
+}
+
+axpic_status axpic_deposit(const axpic_grid* g, const axpic_species* sp, const int64_t* off,
+                           axpic_cells* cells, int32_t slot, void* stream) {
+    if (!grid_ok(g) || !sp || !off || !cells || !cells->dens) return AXPIC_E_INVAL;
+    if (slot < 0 || slot > AXPIC_MAX_IONS || cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
+    if (sp->n > 0 && !sp->w) return AXPIC_E_INVAL;
+    const double L = g->dx * kC / g->omega0;
+    const double scale = sp->w_ref / (L * L * L);
+    double* dst = cells->dens + (int64_t)slot * cells->ncell;
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_deposit", k_deposit<float>, grid1(cells->ncell), dim3(kThreads), 0, S(stream),
+                           cells->ncell, (const float*)sp->w, off, scale, dst);
+    else
+        LAUNCH("k_deposit", k_deposit<double>, grid1(cells->ncell), dim3(kThreads), 0, S(stream),
+                           cells->ncell, (const double*)sp->w, off, scale, dst);
+    return launched();
+}
+
+axpic_status axpic_cell_state(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
+                              double w_ref_e, double w_ref_g, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
+    if (!cells->T_keV || !cells->dens || !cells->state || !cells->pref32 || !cells->pref64)
+        return AXPIC_E_INVAL;
+    if (cells->nion < 0 || cells->nion > AXPIC_MAX_IONS) return AXPIC_E_INVAL;
+    axpic_status st = ensure_tables(prm->brems_k);
+    if (st != AXPIC_OK) return st;
+    const double dtp = g->dt / g->omega0;
+    cells->w_ref_e = w_ref_e;
+    cells->w_ref_g = w_ref_g;
+    const double* Z = cells->Zion; const double* A = cells->Aion;
+    LAUNCH("k_cell_state", k_cell_state, grid1(cells->ncell), dim3(kThreads), 0, S(stream),
+                       cells->ncell, cells->T_keV, cells->dens, cells->nion, Z[0], Z[1], Z[2], Z[3],
+                       A[0], A[1], A[2], A[3], *prm, dtp, w_ref_e, w_ref_g, cells->state,
+                       cells->pref32, cells->pref64);
+    return launched();
+}
+
+axpic_status axpic_rates(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                         const axpic_species* sp, int32_t channel, void* out, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !species_ok(sp, true) || (!out && sp->n))
+        return AXPIC_E_INVAL;
+    int mode;
+    if (sp->kind == AXPIC_PHOTON && channel == AXPIC_PRIMAKOFF) mode = 0;
+    else if (sp->kind == AXPIC_ELECTRON && channel == AXPIC_COMPTON) mode = 1;
+    else if (sp->kind == AXPIC_ELECTRON && channel == AXPIC_BREMS) mode = 2;
+    else if (sp->kind == AXPIC_AXION && channel != 0 && (channel & ~(AXPIC_COMPTON | AXPIC_BREMS)) == 0) mode = 3;
+    else if (sp->kind == AXPIC_AXION && channel == AXPIC_PRIMAKOFF) mode = 4;
+    else return AXPIC_E_INVAL;
+    if (sp->n == 0) return AXPIC_OK;
+    axpic_params p2 = *prm;
+    if (mode == 3) p2.channels = prm->channels & channel;
+    KParams kp = make_kparams(g, &p2, cells->w_ref_g);
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_rates", k_rates<float>, grid1(sp->n), dim3(kThreads), 0, S(stream), sp->n, kp,
+                           mode, cells->pref32, cells->pref64, (const float*)sp->w,
+                           (const float*)sp->p[0], (const float*)sp->p[1], (const float*)sp->p[2],
+                           sp->cell, (float*)out);
+    else
+        LAUNCH("k_rates", k_rates<double>, grid1(sp->n), dim3(kThreads), 0, S(stream), sp->n, kp,
+                           mode, cells->pref32, cells->pref64, (const double*)sp->w,
+                           (const double*)sp->p[0], (const double*)sp->p[1],
+                           (const double*)sp->p[2], sp->cell, (double*)out);
+    return launched();
+}
+
+axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
+                               const axpic_params* prm, axpic_species* parent, int32_t channels,
+                               const void* lam_in, int64_t step, uint64_t next_id,
+                               axpic_species* axions, double* fb, double* hist, double* stats,
+                               int64_t* status, void* ws, size_t ws_bytes, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !status) return AXPIC_E_INVAL;
+    if (!species_ok(parent, parent && parent->kind == AXPIC_PHOTON) || !species_ok(axions, false))
+        return AXPIC_E_INVAL;
+    if (axions->dtype != parent->dtype || axions->kind != AXPIC_AXION) return AXPIC_E_INVAL;
+    if (!axions->x[0] || !axions->p[0] || !axions->p[1] || !axions->p[2] || !axions->w ||
+        !axions->id || !axions->cell || !parent->x[0])
+        return AXPIC_E_INVAL;
+    for (int d = 1; d < g->ndim; ++d)
+        if (!axions->x[d] || !parent->x[d]) return AXPIC_E_INVAL;
+    Workspace W;
+    if (!carve(ws, ws_bytes, parent->n, &W)) return AXPIC_E_INVAL;
+    if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
+    axpic_status st = ensure_tables(prm->brems_k);
+    if (st != AXPIC_OK) return st;
+    axpic_params p2 = *prm;
+    p2.channels = prm->channels & channels;
+    if (parent->kind == AXPIC_PHOTON && std::fabs(parent->w_ref - cells->w_ref_g) > 1e-12 * parent->w_ref)
+        return AXPIC_E_INVAL;
+    if (parent->kind == AXPIC_ELECTRON && std::fabs(parent->w_ref - cells->w_ref_e) > 1e-12 * parent->w_ref)
+        return AXPIC_E_INVAL;
+    KParams kp = make_kparams(g, &p2, cells->w_ref_g);
+    const bool f64 = parent->dtype == AXPIC_F64;
+    if (parent->kind == AXPIC_PHOTON) {
+        if (!(p2.channels & AXPIC_PRIMAKOFF)) return AXPIC_E_INVAL;
+        return f64 ? emit_primakoff<double>(kp, cells, parent, lam_in, step, next_id, axions, hist,
+                                            stats, status, W, S(stream))
+                   : emit_primakoff<float>(kp, cells, parent, lam_in, step, next_id, axions, hist,
+                                           stats, status, W, S(stream));
+    }
+    if (parent->kind == AXPIC_ELECTRON) {
+        if (!(p2.channels & (AXPIC_COMPTON | AXPIC_BREMS))) return AXPIC_E_INVAL;
+        return f64 ? emit_thermal<double>(kp, cells, parent, lam_in, step, next_id, axions, fb,
+                                          hist, stats, status, W, S(stream))
+                   : emit_thermal<float>(kp, cells, parent, lam_in, step, next_id, axions, fb, hist,
+                                         stats, status, W, S(stream));
+    }
+    return AXPIC_E_INVAL;
+}
+
+axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                          axpic_species* axions, const void* pabs_in, const void* lam_in,
+                          int64_t step, uint64_t next_id, axpic_species* photons, double* fb,
+                          double* stats, int64_t* status, void* ws, size_t ws_bytes,
+                          void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !status) return AXPIC_E_INVAL;
+    if (!species_ok(axions, true) || axions->kind != AXPIC_AXION) return AXPIC_E_INVAL;
+    const bool a2g = prm->inverse && (prm->channels & AXPIC_PRIMAKOFF);
+    if (a2g) {
+        if (!species_ok(photons, true) || photons->kind != AXPIC_PHOTON ||
+            photons->dtype != axions->dtype || !photons->x[0] || !photons->w || !photons->id ||
+            !photons->cell || !photons->p[0] || !photons->p[1] || !photons->p[2])
+            return AXPIC_E_INVAL;
+        for (int d = 1; d < g->ndim; ++d)
+            if (!photons->x[d]) return AXPIC_E_INVAL;
+    }
+    for (int d = 0; d < g->ndim; ++d)
+        if (axions->n && !axions->x[d]) return AXPIC_E_INVAL;
+    Workspace W;
+    if (!carve(ws, ws_bytes, axions->n, &W)) return AXPIC_E_INVAL;
+    if (a2g && std::fabs(photons->w_ref - cells->w_ref_g) > 1e-12 * photons->w_ref)
+        return AXPIC_E_INVAL;
+    if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
+    KParams kp = make_kparams(g, prm, cells->w_ref_g);
+    axpic_species* ph = a2g ? photons : nullptr;
+    if (axions->dtype == AXPIC_F64)
+        return absorb_impl<double>(kp, cells, axions, pabs_in, lam_in, step, next_id, ph, fb, stats,
+                                   status, W, S(stream));
+    return absorb_impl<float>(kp, cells, axions, pabs_in, lam_in, step, next_id, ph, fb, stats,
+                              status, W, S(stream));
+}
+
+axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
+                            axpic_species* el, const int64_t* off, const double* fb,
+                            double* moments, double* stats, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !off || !cells->T_keV) return AXPIC_E_INVAL;
+    if (!species_ok(el, true) || el->kind != AXPIC_ELECTRON) return AXPIC_E_INVAL;
+    if (cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
+    KParams kp = make_kparams(g, prm, 0.0);
+    const int64_t threads = cells->ncell * 64;
+    if (el->dtype == AXPIC_F32)
+        LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, S(stream),
+                           cells->ncell, kp, el->w_ref, off, (const float*)el->w, (float*)el->p[0],
+                           (float*)el->p[1], (float*)el->p[2], fb, cells->T_keV, moments, stats);
+    else
+        LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, S(stream),
+                           cells->ncell, kp, el->w_ref, off, (const double*)el->w,
+                           (double*)el->p[0], (double*)el->p[1], (double*)el->p[2], fb,
+                           cells->T_keV, moments, stats);
+    return launched();
+}
+
+axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t* status, void* ws,
+                           size_t ws_bytes, void* stream) {
+    if (!species_ok(in, true) || !out || !status || out->dtype != in->dtype) return AXPIC_E_INVAL;
+    if (out->capacity < in->n || !out->x[0] || !out->w || !out->id || !out->cell || !out->p[0] ||
+        !out->p[1] || !out->p[2] || !in->x[0])
+        return AXPIC_E_INVAL;
+    int ndim = 1;
+    if (in->x[1]) { ndim = 2; if (!out->x[1]) return AXPIC_E_INVAL; }
+    if (in->x[2]) { ndim = 3; if (!in->x[1] || !out->x[2]) return AXPIC_E_INVAL; }
+    Workspace W;
+    if (!carve(ws, ws_bytes, in->n, &W)) return AXPIC_E_INVAL;
+    const int64_t n = in->n, nb = nblocks_for(std::max<int64_t>(n, 1));
+    hipStream_t s = S(stream);
+#define AXPIC_COMPACT(T)                                                                           \
+    LAUNCH("k_live_count", k_live_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n,              \
+                       (const T*)in->w, W.code, W.bsum, W.bact);                                   \
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, (int64_t)0, \
+                       out->capacity, W.ctrl, status);                                             \
+    LAUNCH("k_compact_apply", k_compact_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, W.code,   \
+                       W.boff, W.ctrl, out->capacity, ndim, (const T*)in->x[0],                   \
+                       (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],                \
+                       (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, in->id, in->cell, \
+                       (T*)out->x[0], (T*)out->x[1], (T*)out->x[2], (T*)out->p[0], (T*)out->p[1], \
+                       (T*)out->p[2], (T*)out->w, out->id, out->cell)
+    if (in->dtype == AXPIC_F32) { AXPIC_COMPACT(float); }
+    else { AXPIC_COMPACT(double); }
+#undef AXPIC_COMPACT
+    return launched();
+}
+
+axpic_status axpic_diag(const axpic_species* sp, double* out, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!species_ok(sp, true) || !out) return AXPIC_E_INVAL;
+    const int64_t nb = nblocks_for(std::max<int64_t>(sp->n, 1));
+    if (!ws || ws_bytes < sizeof(double) * 2 * (size_t)nb) return AXPIC_E_INVAL;
+    double* part = (double*)ws;
+    hipStream_t s = S(stream);
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_diag_partial", k_diag_partial<float>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
+                           sp->w_ref, (const float*)sp->w, (const float*)sp->p[0],
+                           (const float*)sp->p[1], (const float*)sp->p[2], part);
+    else
+        LAUNCH("k_diag_partial", k_diag_partial<double>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
+                           sp->w_ref, (const double*)sp->w, (const double*)sp->p[0],
+                           (const double*)sp->p[1], (const double*)sp->p[2], part);
+    LAUNCH("k_diag_final", k_diag_final, dim3(1), dim3(64), 0, s, nb, part, out);
+    return launched();
+}
+
+axpic_status axpic_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+        return AXPIC_E_INVAL;
+    const int64_t n4 = (int64_t)(bytes / 16);
+    if (n4 == 0) return AXPIC_OK;
+    const int64_t blocks = std::min<int64_t>((n4 + kThreads - 1) / kThreads, 256 * 64);
+    LAUNCH("k_stream_copy", k_stream_copy, dim3((unsigned)blocks), dim3(kThreads), 0, S(stream),
+           (const float4*)src, (float4*)dst, n4);
+    return launched();
+}
+
+/* Host-side access to the sampler tables (no device work): which = 0 Compton,
+ * 1 Gamma(k).  out has 2 (2048 + 1) doubles: y = ln x on the z grid, then dy/dz. */
+axpic_status axpic_sampler_table(int32_t which, double k, double* out) {
+    if (!out || (which != 0 && which != 1) || (which == 1 && !(k > 0.0))) return AXPIC_E_INVAL;
+    if (which == 0) axpic_host::build_compton_table(out);
+    else axpic_host::build_gamma_table(out, k);
+    return AXPIC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+void axpic_timing_enable(int32_t on) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    t.on = on != 0;
+}
+
+axpic_status axpic_timing_read(char* buf, size_t len) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    for (auto& p : t.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+            return AXPIC_E_DEVICE;
+        bool found = false;
+        for (auto& e : t.acc)
+            if (e.first == p.name) { e.second.first += 1; e.second.second += ms; found = true; break; }
+        if (!found) t.acc.push_back({p.name, {1, (double)ms}});
+        t.pool.push_back(p.a); t.pool.push_back(p.b);
+    }
+    t.pending.clear();
+    if (!buf || len == 0) return AXPIC_E_INVAL;
+    std::string out;
+    char line[256];
+    for (auto& e : t.acc) {
+        std::snprintf(line, sizeof(line), "%s %lld %.6f\n", e.first.c_str(), e.second.first, e.second.second);
+        out += line;
+    }
+    t.acc.clear();
+    std::snprintf(buf, len, "%s", out.c_str());
+    return out.size() < len ? AXPIC_OK : AXPIC_E_CAPACITY;
+}
+
+}  // extern "C"

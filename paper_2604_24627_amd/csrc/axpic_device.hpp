@@ -1,0 +1,196 @@
+// axpic_device.hpp -- device building blocks of the axion Monte-Carlo operators
+// (gfx950).  Counter-based random numbers, Poisson inversion, the screened
+// Primakoff kernel, quantile-table energy samplers and small reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace axpic {
+
+// Physical constants (CODATA 2018; cgs / keV).
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kAlpha = 1.0 / 137.035999084;
+constexpr double kHbarcGeVcm = 1.973269804e-14;
+constexpr double kHbarcKeVcm = 1.973269804e-8;
+constexpr double kC = 2.99792458e10;
+constexpr double kMe = 510.99895000;          // m_e c^2 [keV]
+constexpr double kKeVerg = 1.602176634e-9;
+constexpr double kKeVT7 = 1.160451812;        // T_7 per keV
+constexpr double kMu = 1.66053906660e-24;     // atomic mass unit [g]
+constexpr double kZeta5 = 1.0369277551433699263;
+constexpr double kZeta6 = 1.0173430619844491397;
+constexpr double kLambdaHardCap = 64.0;       // bound of the inversion sampler
+constexpr int kKmax = 255;
+
+constexpr int kTabN = 2048;                   // quantile-table intervals
+constexpr double kTabZ0 = -18.0, kTabZ1 = 18.0;
+
+// Kernel-side parameter block (derived on the host from axpic_params).
+struct KParams {
+    double dt_phys;
+    double w_a;
+    double wa_mul[3];
+    double w_gamma_prod;        // physical
+    double cap;                 // min(lambda_cap, 64)
+    double ag_unit;             // inv_ratio * w_a^2 * wa_mul0 / (w_ref_g * w_gamma_prod)
+    double inv_ratio;
+    double brems_k, brems_theta;
+    double hist_lo, hist_scale; // bin = floor(scale * log(E/lo)) or floor(scale * (E - lo))
+    double r_relax, T_floor, T_ceil;
+    double dtdx;
+    uint32_t seed_lo, seed_hi;
+    int32_t channels, inverse, absorb_mode, eq_stats, T_mode, feedback;
+    int32_t nbins, hist_log;
+    int32_t ndim;
+    int32_t n[3];
+};
+
+// ---------------------------------------------------------------- Philox4x32-10
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 draw(const KParams& kp, uint64_t id, int64_t step,
+                                      uint32_t stream, uint32_t block) {
+    uint4 c = make_uint4((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step,
+                         (stream << 24) | (block & 0xFFFFFFu));
+    return philox4x32_10(c, kp.seed_lo, kp.seed_hi);
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+__device__ __forceinline__ double u24(uint32_t a) {
+    return (double)(2u * (a >> 9) + 1u) * (1.0 / 16777216.0);
+}
+
+// Poisson(lam) by sequential CDF inversion in FP64 (fixed operation order).
+// The leading test is an exact shortcut: exp(-lam) >= 1 - lam, and the FP64
+// exponential is within one ulp, so u < fl(1 - lam) - 2^-50 implies K = 0.
+__device__ __forceinline__ int poisson_inv(double lam, double u) {
+#pragma clang fp contract(off)
+    if (!(lam > 0.0)) return 0;
+    if (u < (1.0 - lam) - 8.881784197001252e-16) return 0;
+    int k = 0;
+    double p = exp(-lam);
+    double F = p;
+    while (u >= F && k < kKmax) {
+        k += 1;
+        p = p * lam;
+        p = p / (double)k;
+        F = F + p;
+    }
+    return k;
+}
+
+// Cap and rescale (eqs. lambda_eff, wa_rescaled): returns lambda_eff, *ws = w'/w.
+__device__ __forceinline__ double cap_lambda(double lam, double cap, double* ws, int* capped) {
+    const bool c = lam > cap;
+    *capped = c;
+    const double le = c ? cap : lam;
+    *ws = c ? lam / le : 1.0;
+    return le;
+}
+
+// ---------------------------------------------------------------- screening F(s)
+// F(s) = (1 + 1/s) ln(1 + s) - 1 (eq. prim_F).  Below s = 1/2 (single) or
+// 1/100 (double) the closed form cancels; its series
+// sum_{n>=1} (-1)^{n+1} s^n / (n (n+1)) is used instead.
+__device__ __forceinline__ float screenF(float s) {
+    if (!(s > 0.0f)) return 0.0f;
+    if (s < 0.5f) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int n = 22; n >= 1; --n) {
+            const float c = ((n & 1) ? 1.0f : -1.0f) / (float)(n * (n + 1));
+            acc = acc * s + c;
+        }
+        return acc * s;
+    }
+    return (1.0f + 1.0f / s) * log1pf(s) - 1.0f;
+}
+__device__ __forceinline__ double screenF(double s) {
+    if (!(s > 0.0)) return 0.0;
+    if (s < 0.01) {
+        double acc = 0.0;
+#pragma unroll
+        for (int n = 12; n >= 1; --n) {
+            const double c = ((n & 1) ? 1.0 : -1.0) / (double)(n * (n + 1));
+            acc = acc * s + c;
+        }
+        return acc * s;
+    }
+    return (1.0 + 1.0 / s) * log1p(s) - 1.0;
+}
+
+// (1 - e^-x)/x, accurate for tiny (or underflowed) x.
+__device__ __forceinline__ float one_minus_exp_over(float x) {
+    if (x < 1e-3f) return 1.0f - 0.5f * x + x * x * (1.0f / 6.0f);
+    return -expm1f(-x) / x;
+}
+__device__ __forceinline__ double one_minus_exp_over(double x) {
+    if (x < 1e-5) return 1.0 - 0.5 * x + x * x * (1.0 / 6.0);
+    return -expm1(-x) / x;
+}
+
+template <typename T> __device__ __forceinline__ T dev_expm1(T x);
+template <> __device__ __forceinline__ float dev_expm1(float x) { return expm1f(x); }
+template <> __device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
+template <typename T> __device__ __forceinline__ T dev_exp(T x);
+template <> __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+template <typename T> __device__ __forceinline__ T dev_log(T x);
+template <> __device__ __forceinline__ float dev_log(float x) { return logf(x); }
+template <> __device__ __forceinline__ double dev_log(double x) { return log(x); }
+template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
+template <> __device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T dev_fma(T a, T b, T c);
+template <> __device__ __forceinline__ float dev_fma(float a, float b, float c) { return fmaf(a, b, c); }
+template <> __device__ __forceinline__ double dev_fma(double a, double b, double c) { return fma(a, b, c); }
+template <typename T> __device__ __forceinline__ T dev_floor(T x);
+template <> __device__ __forceinline__ float dev_floor(float x) { return floorf(x); }
+template <> __device__ __forceinline__ double dev_floor(double x) { return floor(x); }
+
+// ---------------------------------------------------------------- samplers
+// Quantile tables: y = ln x on a uniform grid of z = ln(u/(1-u)) with slopes
+// dy/dz, evaluated by cubic Hermite interpolation (FP64).  tab[0..N] = y,
+// tab[N+1..2N+1] = dy/dz.
+__device__ __forceinline__ double quantile(const double* __restrict__ tab, double u) {
+    const double z = log(u) - log1p(-u);
+    const double h = (kTabZ1 - kTabZ0) / kTabN;
+    double t = (z - kTabZ0) / h;
+    int j = (int)floor(t);
+    j = j < 0 ? 0 : (j > kTabN - 1 ? kTabN - 1 : j);
+    const double f = t - (double)j;
+    const double y0 = tab[j], y1 = tab[j + 1];
+    const double m0 = tab[kTabN + 1 + j] * h, m1 = tab[kTabN + 2 + j] * h;
+    const double f2 = f * f, f3 = f2 * f;
+    const double y = (2 * f3 - 3 * f2 + 1) * y0 + (f3 - 2 * f2 + f) * m0 +
+                     (-2 * f3 + 3 * f2) * y1 + (f3 - f2) * m1;
+    return exp(y);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+}  // namespace axpic

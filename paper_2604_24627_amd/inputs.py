@@ -268,11 +268,11 @@ def config1(**kw) -> Workload:
 def config2(T_keV=3.0, n_e=6e25, Z=1, n=(512, 512), ppc=64, seed=0, **kw) -> Workload:
     """2D 512x512, 64 per cell per species, fp32, all three channels forward,
     g_ae = 1e-13, g_agg = 1e-10, 500 steps.  Product weights put the mean
-    macro-event count near 1e-3 per particle and channel at T = 3 keV,
+    macro-event count near 2e-3 per particle and channel at T = 3 keV,
     n_e = 6e25 cm^-3."""
     A = 1.0 if Z == 1 else 4.0
     p = Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=CH_PRIMAKOFF | CH_COMPTON | CH_BREMS,
-               w_a=1.8e-34, wa_mul=(44.0, 1.0, 1.0), lambda_cap=16.0, seed=seed,
+               w_a=1e-34, wa_mul=(400.0, 1.0, 0.3), lambda_cap=16.0, seed=seed,
                hist_lo_keV=0.1, hist_hi_keV=80.0, hist_nbins=128, hist_log=1)
     wl = Workload("cfg2", ndim=2, n=tuple(n), ppc=ppc, dtype="f32", T_keV=T_keV, n_e=n_e,
                   Z=Z, A=A, steps=500, n_ref=6e25, params=p)

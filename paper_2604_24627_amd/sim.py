@@ -1,0 +1,309 @@
+"""Host driver of one time step of the axion Monte-Carlo operators on one GPU.
+
+Buffers are torch tensors on the device (memory and streams only); every
+operator is a call into libaxpic.so.  The step order is the one the operators
+are defined with: every operator acts on the population present at the start
+of the step, and the feedback is applied last:
+
+  1. push the axions present at the start of the step and re-bin them;
+  2. local state of every cell (deposits, temperature field -> prefactors);
+  3. forward Primakoff on the photons; thermal emission on the electrons;
+  4. absorption and a->gamma on the axions present before step 3;
+  5. feedback remap of the electrons and temperature update.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import axpic as B
+
+
+def _tdtype(dt: int):
+    return torch.float32 if dt == B.F32 else torch.float64
+
+
+class DeviceSpecies:
+    """SoA macroparticle buffer on the GPU with host-side length/capacity."""
+
+    def __init__(self, kind: int, dtype: int, ndim: int, capacity: int, w_ref: float,
+                 device, Z: float = 0.0, A: float = 0.0, with_p: bool = True):
+        self.kind, self.dtype, self.ndim = kind, dtype, ndim
+        self.w_ref, self.Z, self.A = float(w_ref), float(Z), float(A)
+        self.device = device
+        self.with_p = with_p
+        self.n = 0
+        self.capacity = 0
+        self.x = [None, None, None]
+        self.p = [None, None, None]
+        self.w = self.id = self.cell = None
+        self.off = None
+        self._alloc(max(int(capacity), 1))
+
+    def _alloc(self, cap: int):
+        td = _tdtype(self.dtype)
+        dev = self.device
+
+        def grow(t, dt_):
+            new = torch.zeros(cap, dtype=dt_, device=dev)
+            if t is not None and self.n:
+                new[: self.n].copy_(t[: self.n])
+            return new
+        for d in range(3):
+            self.x[d] = grow(self.x[d], td) if d < self.ndim else None
+            self.p[d] = grow(self.p[d], td) if self.with_p else None
+        self.w = grow(self.w, td)
+        self.id = grow(self.id, torch.int64)
+        self.cell = grow(self.cell, torch.int32)
+        self.capacity = cap
+
+    def ensure(self, cap: int):
+        if cap > self.capacity:
+            self._alloc(int(cap * 1.25) + 1024)
+
+    @staticmethod
+    def from_input(sp: Dict, kind: int, ndim: int, device, extra: int = 0) -> "DeviceSpecies":
+        dt = B.F64 if sp["w"].dtype == np.float64 else B.F32
+        n = int(sp["n"])
+        s = DeviceSpecies(kind, dt, ndim, n + extra, sp["w_ref"], device, sp["Z"], sp["A"],
+                          with_p=sp["p"] is not None)
+        s.n = n
+        for d in range(ndim):
+            s.x[d][:n].copy_(torch.from_numpy(np.ascontiguousarray(sp["x"][d])))
+        if sp["p"] is not None:
+            for d in range(3):
+                s.p[d][:n].copy_(torch.from_numpy(np.ascontiguousarray(sp["p"][d])))
+        s.w[:n].copy_(torch.from_numpy(sp["w"]))
+        s.id[:n].copy_(torch.from_numpy(sp["id"].view(np.int64)))
+        s.cell[:n].copy_(torch.from_numpy(sp["cell"]))
+        s.off = torch.from_numpy(sp["off"]).to(device)
+        return s
+
+    def struct(self) -> B.SpeciesC:
+        S = B.SpeciesC()
+        for d in range(3):
+            S.x[d] = B.ptr(self.x[d])
+            S.p[d] = B.ptr(self.p[d])
+        S.w, S.id, S.cell = B.ptr(self.w), B.ptr(self.id), B.ptr(self.cell)
+        S.n, S.capacity = self.n, self.capacity
+        S.dtype, S.kind = self.dtype, self.kind
+        S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
+        return S
+
+    def to_numpy(self) -> Dict:
+        n = self.n
+        out = dict(w=self.w[:n].cpu().numpy(), id=self.id[:n].cpu().numpy().view(np.uint64),
+                   cell=self.cell[:n].cpu().numpy())
+        out["x"] = np.stack([self.x[d][:n].cpu().numpy() if self.x[d] is not None
+                             else np.zeros(n, dtype=out["w"].dtype) for d in range(3)])
+        out["p"] = (np.stack([self.p[d][:n].cpu().numpy() for d in range(3)])
+                    if self.with_p else None)
+        return out
+
+
+class AxpicSim:
+    """One uniform-grid run on the current GPU."""
+
+    def __init__(self, plasma: Dict, params, device: str = "cuda", axion_capacity: int = 0,
+                 photon_extra: int = 0, compact_every: int = 0, stream=None):
+        self.lib = B.load()
+        self.device = torch.device(device)
+        self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
+        self.params = B.make_params(self.pdict)
+        self.grid_d = plasma["grid"]
+        self.grid = B.make_grid(self.grid_d)
+        self.ndim = self.grid_d["ndim"]
+        sp = plasma["species"]
+        self.el = DeviceSpecies.from_input(sp["electrons"], B.ELECTRON, self.ndim, self.device)
+        self.ion = DeviceSpecies.from_input(sp["ions"], B.ION, self.ndim, self.device)
+        self.ph = DeviceSpecies.from_input(sp["photons"], B.PHOTON, self.ndim, self.device,
+                                           extra=photon_extra)
+        self.dtype = self.el.dtype
+        cap = axion_capacity or max(4096, self.ph.n // 8)
+        self.ax = DeviceSpecies(B.AXION, self.dtype, self.ndim, cap, self.pdict["w_a"], self.device)
+        self.ncell = int(np.prod(self.grid_d["n"]))
+        self.next_id = int(plasma["next_id"])
+        self.compact_every = compact_every
+        self.step_index = 0
+        dev = self.device
+        f64 = torch.float64
+        self.T = torch.from_numpy(plasma["T_cell"]).to(dev, f64).clone()
+        self.dens = torch.zeros((1 + B.MAX_IONS) * self.ncell, dtype=f64, device=dev)
+        self.state = torch.zeros(self.ncell * B.STATE_N, dtype=f64, device=dev)
+        self.pref32 = torch.zeros(self.ncell * B.PREF_N, dtype=torch.float32, device=dev)
+        self.pref64 = torch.zeros(self.ncell * B.PREF_N, dtype=f64, device=dev)
+        self.cells = B.CellsC()
+        self.cells.ncell = self.ncell
+        self.cells.T_keV, self.cells.dens = B.ptr(self.T), B.ptr(self.dens)
+        self.cells.state, self.cells.pref32, self.cells.pref64 = (B.ptr(self.state),
+                                                                  B.ptr(self.pref32),
+                                                                  B.ptr(self.pref64))
+        self.cells.nion = 1
+        self.cells.Zion[0], self.cells.Aion[0] = self.ion.Z, self.ion.A
+        nb = self.pdict["hist_nbins"] + 2
+        self.hist = torch.zeros(3 * nb, dtype=f64, device=dev)
+        self.stats = torch.zeros(B.ST_COUNT, dtype=f64, device=dev)
+        self.fb = torch.zeros(self.ncell * 4, dtype=f64, device=dev)
+        self.status = torch.zeros(B.STATUS_N, dtype=torch.int64, device=dev)
+        self.diag_out = torch.zeros(2, dtype=f64, device=dev)
+        self.ws = None
+        self.ws_bytes = 0
+        self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity))
+        self.stream = stream
+        s = self.sh
+        B.check(self.lib.axpic_deposit(B.ref(self.grid), B.ref(self.el.struct()), B.ptr(self.el.off),
+                                       B.ref(self.cells), 0, s), "deposit electrons")
+        B.check(self.lib.axpic_deposit(B.ref(self.grid), B.ref(self.ion.struct()),
+                                       B.ptr(self.ion.off), B.ref(self.cells), 1, s),
+                "deposit ions")
+        self.cell_state()
+        self.need_feedback = bool(self.pdict["feedback"] or self.pdict["T_mode"] == 2)
+
+    @property
+    def sh(self):
+        return B.stream_handle(self.stream)
+
+    def _ensure_ws(self, n: int):
+        need = self.lib.axpic_workspace_bytes(int(n))
+        if need > self.ws_bytes:
+            need = int(need * 1.25) + 4096
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self.ws_bytes = need
+
+    def cell_state(self):
+        B.check(self.lib.axpic_cell_state(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
+                                          self.el.w_ref, self.ph.w_ref, self.sh), "cell_state")
+
+    # -------------------------------------------------------------- operators
+    def _append_call(self, fn, out_species: DeviceSpecies, what: str):
+        """Run an appending call; grow the output and repeat on capacity overflow."""
+        for _ in range(8):
+            rc = fn()
+            B.check(rc, what)
+            st = self.status.cpu()
+            if int(st[1]) & B.FLAG_CAPACITY:
+                out_species.ensure(int(st[0]))
+                continue
+            return int(st[2])
+        raise B.AxpicError(f"{what}: capacity growth did not converge")
+
+    def emit_primakoff(self, lam_in=None):
+        s = self.sh
+        self._ensure_ws(self.ph.n)
+
+        def call():
+            return self.lib.axpic_sample_emit(
+                B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.ph_struct),
+                B.PRIMAKOFF, B.ptr(lam_in), self.step_index, self.next_id,
+                B.ref(self.ax.struct()), None, B.ptr(self.hist), B.ptr(self.stats),
+                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+        self.ph_struct = self.ph.struct()
+        k = self._append_call(call, self.ax, "sample_emit(primakoff)")
+        self.ax.n += k
+        self.next_id += k
+        return k
+
+    def emit_thermal(self, lam_in=None):
+        s = self.sh
+        self._ensure_ws(self.el.n)
+
+        def call():
+            return self.lib.axpic_sample_emit(
+                B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.el_struct),
+                B.COMPTON | B.BREMS, B.ptr(lam_in), self.step_index, self.next_id,
+                B.ref(self.ax.struct()), B.ptr(self.fb), B.ptr(self.hist), B.ptr(self.stats),
+                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+        self.el_struct = self.el.struct()
+        k = self._append_call(call, self.ax, "sample_emit(thermal)")
+        self.ax.n += k
+        self.next_id += k
+        return k
+
+    def absorb(self, n_old: int, pabs_in=None, lam_in=None):
+        s = self.sh
+        self._ensure_ws(n_old)
+        ax_n = self.ax.n
+        self.ax.n = n_old
+        try:
+            def call():
+                return self.lib.axpic_absorb(
+                    B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.ax_struct),
+                    B.ptr(pabs_in), B.ptr(lam_in), self.step_index, self.next_id,
+                    B.ref(self.ph.struct()), B.ptr(self.fb), B.ptr(self.stats), B.ptr(self.status),
+                    B.ptr(self.ws), self.ws_bytes, s)
+            self.ax_struct = self.ax.struct()
+            k = self._append_call(call, self.ph, "absorb")
+        finally:
+            self.ax.n = ax_n
+        self.ph.n += k
+        self.next_id += k
+        return k
+
+    def feedback(self, moments=None):
+        B.check(self.lib.axpic_feedback(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
+                                        B.ref(self.el.struct()), B.ptr(self.el.off),
+                                        B.ptr(self.fb), B.ptr(moments), B.ptr(self.stats), self.sh),
+                "feedback")
+
+    def bin_axions(self, push: bool = True):
+        if self.ax.n:
+            B.check(self.lib.axpic_bin_cells(B.ref(self.grid), B.ref(self.ax.struct()),
+                                             1 if push else 0, self.sh), "bin_cells")
+
+    def rates(self, sp: DeviceSpecies, channel: int):
+        out = torch.zeros(max(sp.n, 1), dtype=_tdtype(sp.dtype), device=self.device)
+        B.check(self.lib.axpic_rates(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
+                                     B.ref(sp.struct()), channel, B.ptr(out), self.sh), "rates")
+        return out[: sp.n]
+
+    def compact_axions(self):
+        if self.ax.n == 0:
+            return
+        out = DeviceSpecies(B.AXION, self.dtype, self.ndim, self.ax.capacity, self.ax.w_ref,
+                            self.device)
+        self._ensure_ws(self.ax.n)
+        B.check(self.lib.axpic_compact(B.ref(self.ax.struct()), B.ref(out.struct()),
+                                       B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, self.sh),
+                "compact")
+        out.n = int(self.status.cpu()[2])
+        self.ax = out
+
+    def diag(self):
+        self._ensure_ws(self.ax.n)
+        B.check(self.lib.axpic_diag(B.ref(self.ax.struct()), B.ptr(self.diag_out), B.ptr(self.ws),
+                                    self.ws_bytes, self.sh), "diag")
+        v = self.diag_out.cpu().tolist()
+        return dict(N_a=v[0], U_a=v[1])
+
+    # -------------------------------------------------------------- one step
+    def step(self):
+        p = self.pdict
+        self.bin_axions(push=True)
+        if p["T_mode"] == 2:
+            self.cell_state()
+        if self.need_feedback:
+            self.fb.zero_()
+        n_ax0 = self.ax.n
+        self._ensure_ws(max(self.el.n, self.ph.n, n_ax0))
+        if p["channels"] & B.PRIMAKOFF:
+            self.emit_primakoff()
+        if p["channels"] & (B.COMPTON | B.BREMS):
+            self.emit_thermal()
+        if p["inverse"] and n_ax0 > 0:
+            self.absorb(n_ax0)
+        if self.need_feedback:
+            self.feedback()
+        self.step_index += 1
+        if self.compact_every and self.step_index % self.compact_every == 0:
+            self.compact_axions()
+
+    def hist_np(self):
+        nb = self.pdict["hist_nbins"] + 2
+        return self.hist.cpu().numpy().reshape(3, nb)
+
+    def stats_dict(self):
+        v = self.stats.cpu().numpy()
+        return {n: float(v[i]) for i, n in enumerate(B.ST_NAMES)}

@@ -1,0 +1,330 @@
+"""Parity of the HIP operators with the FP64 oracle (needs an MI355X).
+
+Inputs are the seeded synthetic plasmas of paper_2604_24627_amd.inputs, at
+sizes the oracle finishes in seconds that still span several 1024-particle
+tiles and a ragged tail.  Bars:
+  * integer work (event counts, product ids, absorption decisions, cell
+    indices, push in binary32) is bit-exact, with the oracle fed the GPU's
+    own FP32 means where the decision depends on them;
+  * FP32 rates within 1e-5 relative of the FP64 oracle; FP64 paths 1e-11;
+  * sampled energies within 1e-6 relative (quantile-table accuracy 2e-8
+    plus binary32 storage);
+  * FP64 reductions (histograms, exchange buffers, moments) within 1e-9
+    relative (summation order only).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+from paper_2604_24627_amd import inputs as I  # noqa: E402
+from paper_2604_24627_amd import axpic as B  # noqa: E402
+from paper_2604_24627_amd.sim import AxpicSim  # noqa: E402
+
+ME = 510.99895
+
+
+def small_workload(dtype="f32", n=(24, 20), ppc=37, T=3.0, ne=6e25, **pkw):
+    p = I.Params(**pkw)
+    wl = I.Workload("par", ndim=len(n), n=tuple(n), ppc=ppc, dtype=dtype, T_keV=T, n_e=ne,
+                    n_ref=6e25, params=p)
+    return wl
+
+
+def pair(wl, seed=0, **kw):
+    pl = I.make_plasma(wl, seed)
+    print(f"[parity] workload={wl.name} n={wl.n} ppc={wl.ppc} dtype={wl.dtype} seed={seed}",
+          flush=True)
+    g = AxpicSim(pl, wl.params, **kw)
+    o = O.OracleSim(pl, wl.params, prec32=(wl.dtype == "f32"))
+    return g, o, pl
+
+
+def np64(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def test_cell_state_matches_oracle():
+    for Z, A in ((1, 1.0), (2, 4.0)):
+        wl = small_workload(channels=7, inverse=1, g_ae=1e-13, boost=1e30)
+        wl.Z, wl.A = Z, A
+        g, o, _ = pair(wl)
+        torch.cuda.synchronize()
+        st = g.state.cpu().numpy().reshape(-1, B.STATE_N)
+        oc = o.cells()
+        for k, f in enumerate(["T", "n_e", "n_e_dep", "nZ", "nZ2", "rho", "XH", "kappa2", "G_P0",
+                               "G_C", "G_B", "Q_C", "Q_B", "meanE_C", "meanE_B"]):
+            np.testing.assert_allclose(st[:, k], oc[f], rtol=1e-12, atol=0, err_msg=f)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rates_match_oracle(dtype):
+    wl = small_workload(dtype, channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=1e33,
+                        w_a=1e-36)
+    g, o, _ = pair(wl)
+    rtol = 1e-5 if dtype == "f32" else 1e-11
+    cells = o.cells()
+    lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
+    _, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph.copy(), 0, 1 << 40)
+    np.testing.assert_allclose(lamP, olamP, rtol=rtol)
+    lamC = np64(g.rates(g.el, B.COMPTON)); lamB = np64(g.rates(g.el, B.BREMS))
+    _, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, 1 << 40)
+    np.testing.assert_allclose(lamC, olamT[0], rtol=rtol)
+    np.testing.assert_allclose(lamB, olamT[1], rtol=rtol)
+    # axions: the population the GPU creates in two steps, handed to the oracle as is
+    for _ in range(2):
+        g.step()
+    assert g.ax.n > 1000
+    pab = np64(g.rates(g.ax, B.COMPTON | B.BREMS))
+    lag = np64(g.rates(g.ax, B.PRIMAKOFF))
+    a = g.ax.to_numpy()
+    ax = O.OSpecies(a["x"], a["p"], a["w"].astype(np.float64) * g.ax.w_ref, a["id"], a["cell"])
+    _, opab, olag, _, _ = O.absorb(o.grid, o.params, cells, ax.copy(), 0, 1 << 40)
+    big = opab > 1e-30
+    np.testing.assert_allclose(pab[big], opab[big], rtol=rtol * 3)
+    # the a->gamma mean is taken before absorption here; compare where nothing was absorbed
+    prm_noabs = dict(o.params, channels=1)
+    _, _, olag2, _, _ = O.absorb(o.grid, prm_noabs, cells, ax.copy(), 0, 1 << 40)
+    np.testing.assert_allclose(lag, olag2, rtol=rtol)
+
+
+def _compare_products(gsp, n0, prod, w_ref, rtol_w, exact_p=True, rtol_p=1e-6):
+    n = prod["w"].size
+    assert gsp.n - n0 == n
+    sl = slice(n0, n0 + n)
+    gid = gsp.id[sl].cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(gid, prod["id"])
+    np.testing.assert_array_equal(gsp.cell[sl].cpu().numpy(), prod["cell"])
+    for d in range(gsp.ndim):
+        np.testing.assert_array_equal(np64(gsp.x[d][sl]), prod["x"][d])
+    gp = np.stack([np64(gsp.p[d][sl]) for d in range(3)])
+    if exact_p:
+        np.testing.assert_array_equal(gp, prod["p"])
+    else:
+        np.testing.assert_allclose(gp, prod["p"], rtol=rtol_p, atol=rtol_p * np.abs(prod["p"]).max())
+    np.testing.assert_allclose(np64(gsp.w[sl]) * w_ref, prod["w"], rtol=rtol_w)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_primakoff_emission_bit_exact_counts(dtype):
+    wl = small_workload(dtype, channels=1, g_agg_GeV=1e-10, w_a=2e-35, lambda_cap=0.7)
+    g, o, _ = pair(wl)
+    cells = o.cells()
+    for step in range(3):
+        lam = g.rates(g.ph, B.PRIMAKOFF)
+        lam64 = np64(lam)
+        n0 = g.ax.n
+        g.step_index = step; o.step_index = step
+        k = g.emit_primakoff()
+        prod, olam, K = O.emit_primakoff(o.grid, o.params, cells, o.ph, step, g.next_id - k,
+                                         o.hist, o.stats, lam_in=lam64)
+        assert k == prod["w"].size and k > 200
+        _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6 if dtype == "f32" else 1e-13)
+        np.testing.assert_allclose(np64(g.ph.w[: g.ph.n]) * g.ph.w_ref, o.ph.w,
+                                   rtol=1e-6 if dtype == "f32" else 1e-13)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g.hist_np().ravel(), o.hist, rtol=1e-10, atol=0)
+    st = g.stats_dict()
+    for nme in ("events_P", "num_P", "en_P", "capped"):
+        assert st[nme] == pytest.approx(o.stats[O.ST[nme]], rel=1e-10), nme
+    assert st["capped"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_thermal_emission_matches_oracle(dtype):
+    wl = small_workload(dtype, channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=0.5)
+    wl.params.wa_mul = (1.0, 1.0, 0.35)
+    g, o, _ = pair(wl)
+    cells = o.cells()
+    fb_o = np.zeros(g.ncell * 4)
+    for step in range(2):
+        lam = torch.stack([g.rates(g.el, B.COMPTON), g.rates(g.el, B.BREMS)]).contiguous()
+        lam64 = np64(lam)
+        n0 = g.ax.n
+        g.step_index = step
+        g.fb.zero_()
+        k = g.emit_thermal(lam_in=lam.reshape(-1))
+        fb_o[:] = 0.0
+        prod, _, K = O.emit_thermal(o.grid, o.params, cells, o.el, step, g.next_id - k, fb_o,
+                                    o.hist, o.stats, lam_in=lam64)
+        assert k == prod["w"].size and k > 1000
+        assert (prod["chan"] == 1).sum() > 300 and (prod["chan"] == 2).sum() > 300
+        _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6 if dtype == "f32" else 1e-13,
+                          exact_p=False, rtol_p=1e-6)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(g.fb.cpu().numpy(), fb_o, rtol=1e-6,
+                                   atol=1e-9 * np.abs(fb_o).max())
+    Eg = g.hist_np().ravel()
+    # a product energy within the table error of a bin edge may land in the neighbour bin
+    assert np.abs(Eg - o.hist).sum() <= 1e-6 * o.hist.sum() + 4 * (Eg.max() / 50)
+    assert Eg.sum() == pytest.approx(o.hist.sum(), rel=1e-6)
+
+
+def test_fused_thermal_counts_equal_rate_fed_counts():
+    """The fused kernel decides exactly as when it is fed its own materialised means."""
+    wl = small_workload("f32", channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=0.5)
+    g1, _, pl = pair(wl)
+    g2 = AxpicSim(pl, wl.params)
+    lam = torch.stack([g2.rates(g2.el, B.COMPTON), g2.rates(g2.el, B.BREMS)]).contiguous()
+    k1 = g1.emit_thermal()
+    k2 = g2.emit_thermal(lam_in=lam.reshape(-1))
+    assert k1 == k2
+    a, b = g1.ax.to_numpy(), g2.ax.to_numpy()
+    for key in ("w", "id", "cell"):
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(a["p"], b["p"])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_push_and_binning_bit_exact(dtype):
+    wl = small_workload(dtype, channels=1, g_agg_GeV=1e-10, w_a=2e-35)
+    g, o, _ = pair(wl)
+    g.emit_primakoff()
+    ax = g.ax.to_numpy()
+    osp = O.OSpecies(ax["x"], ax["p"], ax["w"], ax["id"], ax["cell"])
+    for _ in range(7):
+        g.bin_axions(push=True)
+        O.push(o.grid, osp, dtype == "f32")
+    b = g.ax.to_numpy()
+    for d in range(2):
+        np.testing.assert_array_equal(b["x"][d].astype(np.float64), osp.x[d])
+    np.testing.assert_array_equal(b["cell"], osp.cell)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_absorption_decisions_bit_exact(mode):
+    wl = small_workload("f32", channels=7 if mode == 0 else 6, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=4e33,
+                        w_a=1e-36, lambda_cap=1.0, absorb_mode=mode)
+    g, o, _ = pair(wl)
+    for _ in range(3):
+        g.step()
+    cells = o.cells()
+    n = g.ax.n
+    assert n > 2000
+    pab = g.rates(g.ax, B.COMPTON | B.BREMS).clone()
+    lag = g.rates(g.ax, B.PRIMAKOFF).clone()
+    ax = g.ax.to_numpy()
+    osp = O.OSpecies(ax["x"], ax["p"], ax["w"].astype(np.float64) * g.ax.w_ref, ax["id"], ax["cell"])
+    g.fb.zero_()
+    ph_n0 = g.ph.n
+    g.step_index = 3
+    st0 = g.stats_dict()
+    k = g.absorb(n, pabs_in=pab, lam_in=lag if mode == 0 else None)
+    fb_o = np.zeros(g.ncell * 4)
+    st_o = np.zeros(O.ST_COUNT)
+    prm = dict(o.params, w_gamma_prod=g.ph.w_ref)
+    prod, _, _, K, dead = O.absorb(o.grid, prm, cells, osp, 3, g.next_id - k, fb_o, st_o,
+                                   pabs_in=np64(pab), lam_in=np64(lag) if mode == 0 else None)
+    assert k == prod["w"].size
+    gw = np64(g.ax.w[:n]) * g.ax.w_ref
+    np.testing.assert_array_equal(gw == 0.0, osp.w == 0.0)
+    np.testing.assert_allclose(gw, osp.w, rtol=2e-6, atol=0)
+    if mode == 0:
+        assert dead.sum() > 50
+        _compare_products(g.ph, ph_n0, prod, g.ph.w_ref, rtol_w=1e-6)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g.fb.cpu().numpy(), fb_o, rtol=1e-6, atol=1e-9 * np.abs(fb_o).max())
+    st = g.stats_dict()
+    assert st["abs_num"] - st0["abs_num"] == pytest.approx(st_o[O.ST["abs_num"]], rel=1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_feedback_matches_oracle(dtype):
+    wl = small_workload(dtype, channels=6, g_ae=1e-13, feedback=1, T_mode=2, r_relax=0.3)
+    g, o, pl = pair(wl)
+    rng = np.random.default_rng(21)
+    fb = rng.normal(0, 1, (g.ncell, 4)) * np.array([3e-3, 1e-3, 1e-3, 1e-3]) * 80
+    g.fb.copy_(torch.from_numpy(fb.ravel()))
+    mom = torch.zeros(g.ncell * 5, dtype=torch.float64, device="cuda")
+    g.feedback(moments=mom)
+    mo = np.zeros(g.ncell * 5)
+    st = np.zeros(O.ST_COUNT)
+    O.feedback(o.grid, o.params, pl["species"]["electrons"]["off"], o.el, fb.ravel(), o.T, st, mo)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(mom.cpu().numpy(), mo, rtol=1e-10, atol=1e-14 * np.abs(mo).max())
+    gp = np.stack([np64(g.el.p[d][: g.el.n]) for d in range(3)])
+    tol = 2e-6 if dtype == "f32" else 1e-11
+    np.testing.assert_allclose(gp, o.el.p, rtol=tol, atol=tol * np.abs(o.el.p).max())
+    np.testing.assert_allclose(g.T.cpu().numpy(), o.T, rtol=1e-10)
+    assert st[O.ST["clamped_cells"]] == g.stats_dict()["clamped_cells"]
+
+
+def test_compaction_is_stable_and_exact():
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, boost=4e33, w_a=1e-36,
+                        lambda_cap=1.0)
+    g, _, _ = pair(wl)
+    for _ in range(4):
+        g.step()
+    before = g.ax.to_numpy()
+    g.compact_axions()
+    after = g.ax.to_numpy()
+    keep = before["w"] > 0
+    assert 0 < keep.sum() < keep.size
+    for key in ("w", "id", "cell"):
+        np.testing.assert_array_equal(after[key], before[key][keep])
+    np.testing.assert_array_equal(after["p"], before["p"][:, keep])
+    np.testing.assert_array_equal(after["x"][:2], before["x"][:2, keep])
+
+
+def test_config1_full_run_matches_oracle():
+    """Config 1 (1D, 64 cells, fp64, Primakoff, 100 steps): GPU and oracle run
+    independently with fused rates; every axion and the histogram agree."""
+    wl = I.config1()
+    g, o, _ = pair(wl)
+    for s in range(wl.steps):
+        g.step()
+        o.step()
+    assert g.ax.n == o.ax.n and g.ax.n > 100000
+    a = g.ax.to_numpy()
+    np.testing.assert_array_equal(a["id"], o.ax.id)
+    np.testing.assert_array_equal(a["cell"], o.ax.cell)
+    np.testing.assert_allclose(a["x"][0], o.ax.x[0], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(a["p"], o.ax.p)
+    np.testing.assert_allclose(a["w"] * g.ax.w_ref, o.ax.w, rtol=1e-13)
+    np.testing.assert_allclose(g.hist_np().ravel(), o.hist, rtol=1e-10)
+    d = g.diag()
+    t = o.totals()
+    assert d["N_a"] == pytest.approx(t["N_a"], rel=1e-12)
+    assert d["U_a"] == pytest.approx(t["U_a"], rel=1e-12)
+
+
+def test_capacity_overflow_rerun_is_bit_identical():
+    wl = small_workload("f32", channels=7, g_ae=1e-13, g_agg_GeV=1e-10, w_a=1e-36, lambda_cap=1.0)
+    pl = I.make_plasma(wl, 3)
+    g1 = AxpicSim(pl, wl.params, axion_capacity=16)         # forces repeated growth
+    g2 = AxpicSim(pl, wl.params, axion_capacity=10 ** 7)
+    for _ in range(3):
+        g1.step(); g2.step()
+    a, b = g1.ax.to_numpy(), g2.ax.to_numpy()
+    assert a["w"].size == b["w"].size > 1000
+    for key in ("w", "id", "cell"):
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(a["p"], b["p"])
+    # FP64 histogram bins are accumulated with atomics: equal up to summation order
+    np.testing.assert_allclose(g1.hist_np(), g2.hist_np(), rtol=1e-12, atol=0)
+
+
+def test_determinism_two_runs_bitwise():
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, boost=4e33, w_a=1e-36,
+                        lambda_cap=1.0, feedback=1, T_mode=2)
+    pl = I.make_plasma(wl, 5)
+    runs = []
+    for _ in range(2):
+        g = AxpicSim(pl, wl.params)
+        for _ in range(4):
+            g.step()
+        torch.cuda.synchronize()
+        runs.append((g.ax.to_numpy(), g.el.to_numpy(), g.T.cpu().numpy(), g.hist_np()))
+    (a1, e1, T1, h1), (a2, e2, T2, h2) = runs
+    for key in ("w", "id", "cell"):
+        np.testing.assert_array_equal(a1[key], a2[key])
+    # the exchange buffers are FP64 sums accumulated with atomics, so the remapped momenta
+    # and temperatures agree to rounding of the summation order
+    np.testing.assert_allclose(e1["p"], e2["p"], rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(T1, T2, rtol=1e-13)
+    # FP64 histogram atomics may sum in another order: equal to rounding
+    np.testing.assert_allclose(h1, h2, rtol=1e-12)

@@ -1,0 +1,88 @@
+"""CPU tests of libaxpic.so's host side: it loads, exports every symbol the
+header declares, rejects invalid arguments before any launch, and its
+energy-sampler tables reproduce the oracle's exact quantiles."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_24627_amd import axpic as B
+from paper_2604_24627_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "axpic.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(axpic_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    syms = header_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(syms) == sorted(B.EXPORTS)
+    assert L.axpic_version() == 1
+    assert L.axpic_status_string(-2) == b"output capacity exceeded"
+
+
+def test_struct_layouts_match_header_sizes():
+    # offsets that the C compiler would produce (natural alignment, x86-64)
+    assert C.sizeof(B.Grid) == 40
+    assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3
+    assert B.ParamsC.seed.offset % 8 == 0
+
+
+def _hermite(tab, u):
+    N = 2048
+    z0, z1 = -18.0, 18.0
+    h = (z1 - z0) / N
+    z = np.log(u) - np.log1p(-u)
+    t = (z - z0) / h
+    j = np.clip(np.floor(t).astype(int), 0, N - 1)
+    f = t - j
+    y0, y1 = tab[j], tab[j + 1]
+    m0, m1 = tab[N + 1 + j] * h, tab[N + 2 + j] * h
+    y = (2 * f ** 3 - 3 * f ** 2 + 1) * y0 + (f ** 3 - 2 * f ** 2 + f) * m0 + \
+        (-2 * f ** 3 + 3 * f ** 2) * y1 + (f ** 3 - f ** 2) * m1
+    return np.exp(y)
+
+
+@pytest.mark.parametrize("which,k", [(0, 0.0), (1, 1.7), (1, 2.3)])
+def test_sampler_tables_match_exact_quantiles(which, k):
+    L = B.load()
+    tab = np.zeros(2 * 2049)
+    B.check(L.axpic_sampler_table(which, k, tab.ctypes.data_as(C.c_void_p)), "table")
+    rng = np.random.default_rng(11)
+    a = rng.integers(0, 2 ** 32, 400, dtype=np.uint64)
+    u = np.array([O.u24(int(v)) for v in a] + [2 ** -24, 1 - 2 ** -24, 0.5])
+    got = _hermite(tab, u)
+    ref = np.array([O.compton_x(v) if which == 0 else O.gamma_x(k, v) for v in u])
+    assert np.max(np.abs(got / ref - 1)) < 2e-8
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = B.load()
+    g = B.make_grid(dict(ndim=4, n=(4, 1, 1), dx=0.2, dt=0.1, omega0=1e17))
+    sp = B.SpeciesC()
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    g = B.make_grid(dict(ndim=1, n=(4, 2, 1), dx=0.2, dt=0.1, omega0=1e17))   # n[1] != 1 in 1D
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    g = B.make_grid(dict(ndim=1, n=(4, 1, 1), dx=0.2, dt=0.1, omega0=1e17))
+    sp.n, sp.capacity = 10, 5                                                   # n > capacity
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    prm = B.make_params(I.Params(lambda_cap=0.0))                               # cap <= 0
+    cells = B.CellsC()
+    st = np.zeros(4, np.int64)
+    assert L.axpic_sample_emit(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), 1, None, 0, 0,
+                               B.ref(sp), None, None, None, st.ctypes.data, None, 0, None) == -1
+    prm = B.make_params(I.Params(r_relax=1.5))
+    assert L.axpic_feedback(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), None, None, None,
+                            None, None) == -1
+    assert L.axpic_sampler_table(2, 0.0, None) == -1

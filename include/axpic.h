@@ -19,6 +19,9 @@
  *    and the caller may grow the buffer and repeat the call with the same
  *    arguments, which gives bit-identical results (the random numbers are
  *    keyed by (seed, particle id, step), see below).
+ *  - Particle ids key the random numbers.  A buffer may declare its first
+ *    n_implicit ids as id0 + i (plasma in creation order) so that the hot
+ *    kernels need not read them; appended products always store theirs.
  *  - Host-side argument errors return AXPIC_E_INVAL before any launch; a
  *    failed launch returns AXPIC_E_DEVICE.  No C++ exception crosses the ABI.
  *
@@ -92,6 +95,8 @@ typedef struct {
     int32_t kind;       /* axpic_kind */
     double w_ref;       /* [host] physical weight of w = 1 */
     double Z, A;        /* [host] ion charge state and mass number */
+    uint64_t id0;       /* [host] particles i < n_implicit have id id0 + i and their */
+    int64_t n_implicit; /*        id[] entries are not read (0: every id is stored) */
 } axpic_species;
 
 /* Per-cell tables.  dens: [1+AXPIC_MAX_IONS][ncell] FP64 deposited physical
@@ -264,6 +269,59 @@ axpic_status axpic_sampler_table(int32_t which, double k, double* out);
  * pointers 16-byte aligned): the calibration kernel for achievable HBM
  * bandwidth and for scaling the profiler's byte counters. */
 axpic_status axpic_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Rate surrogate (learned rate backend).  A perceptron 8 -> 128 x4 (SiLU) -> 1
+ * with bfloat16 weights and FP32 accumulation on the matrix cores predicts
+ * y = (log R - mu_ch)/sigma_ch from x = (log(omega/T), log(kappa/T), log n_e,
+ * Z) normalised as (x_i - feat_lo_i) feat_sc_i - 1, plus a one-hot channel
+ * (Primakoff, Compton-like, e-Z brems, e-e brems); R = Gamma/g^2 of the
+ * Primakoff conversion (Sec. II.F) or of the detailed-balance absorption
+ * (eq. gamma_abs) of the channel.  Outside the training box the plain rate is
+ * used for that particle.
+ * FP32 master parameters (padded training layout, AXPIC_MLP_PARAMS floats):
+ * W1 [32][128], b1 [128], W2, b2, W3, b3, W4, b4 ([128][128], [128]),
+ * W5 [128][32], b5 [32]; only inputs 0..7 and output 0 are live.
+ */
+#define AXPIC_MLP_PARAMS 57888
+#define AXPIC_MLP_BLOB_BYTES 112704
+
+typedef struct {
+    const void* blob;                 /* device: axpic_mlp_pack output */
+    float feat_lo[4], feat_sc[4];     /* [host] feature normalisation */
+    float out_mu[4], out_sigma[4];    /* [host] per-channel log-rate de-normalisation */
+    double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;   /* [host] training box (keV, cm^-3, omega/T) */
+} axpic_mlp;
+
+/* Training samples generated by the plain rates (FP64, device arrays of n):
+ * for each (T [keV], n_e [cm^-3], Z, x = omega/T, channel) writes the raw
+ * features feat[4i..4i+3] = (log x, log(kappa/T), log n_e, Z) and log R. */
+axpic_status axpic_surrogate_samples(const axpic_params* prm, int64_t n, const double* T,
+                                     const double* ne, const double* Z, const double* x,
+                                     const int32_t* ch, double* feat, double* logR, void* stream);
+/* Bytes of the packed inference blob (bf16 MFMA fragments + FP32 biases). */
+size_t axpic_mlp_blob_bytes(void);
+/* Workspace of the training calls for a batch (a multiple of 32). */
+size_t axpic_mlp_train_ws_bytes(int64_t batch);
+/* Pack FP32 master parameters into the inference blob (rounding to bf16). */
+axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream);
+/* Training forward pass: X [batch][32] (features in columns 0..7, zeros after),
+ * y [batch] (may be NULL); activations are kept in ws for axpic_mlp_loss_grad. */
+axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, void* ws,
+                               size_t ws_bytes, float* y, void* stream);
+/* Mean squared error of y against Y and its gradient (AXPIC_MLP_PARAMS floats). */
+axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const float* Y, int64_t batch,
+                                 void* ws, size_t ws_bytes, float* grad, double* loss, void* stream);
+/* Adam step on the FP32 master parameters (step counts from 1). */
+axpic_status axpic_mlp_adam(float* master, const float* grad, float* m, float* v, int64_t step,
+                            float lr, float beta1, float beta2, float eps, void* stream);
+/* Surrogate rates, written like axpic_rates: photons + AXPIC_PRIMAKOFF ->
+ * lambda_P; axions + (AXPIC_COMPTON|AXPIC_BREMS) -> thermal P_abs; axions +
+ * AXPIC_PRIMAKOFF -> a->gamma mean.  n_fallback (device, may be NULL) counts
+ * the particles evaluated by the plain rate because they lie outside the box. */
+axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                             const axpic_species* sp, int32_t channel, const axpic_mlp* net,
+                             void* out, unsigned long long* n_fallback, void* stream);
 
 /* axpic_timing_enable / axpic_timing_read -- instrumentation.  While enabled,
  * every kernel the library launches is bracketed by HIP events recorded on

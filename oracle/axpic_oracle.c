@@ -843,3 +843,76 @@ void or_push(const or_grid* g, or_species* ax, int32_t prec32) {
         ax->cell[i] = (int32_t)cell;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rate-surrogate training data.                                            */
+/* ------------------------------------------------------------------------ */
+
+/* F(s) by quadrature of the angular integral behind the screened cross
+ * section: with t = 1 - cos(theta) it reads (1/2) int_0^2 (2 - t)/(t + b) dt,
+ * b = 2/s; composite 10-point Gauss-Legendre on panels that halve towards
+ * t = 0, down to well below the screening width b.                         */
+double or_F_quad(double s) {
+    if (!(s > 0.0)) return 0.0;
+    or_gl_init();
+    const double b = 2.0 / s;
+    int J = 12;
+    while (2.0 * pow(0.5, J) > 1e-3 * b && J < 200) ++J;
+    double sum = 0.0, hi = 2.0;
+    for (int j = 1; j <= J + 1; ++j) {
+        double lo = (j <= J) ? 2.0 * pow(0.5, j) : 0.0;
+        double h = 0.5 * (hi - lo), m = 0.5 * (hi + lo), acc = 0.0;
+        for (int i = 0; i < 10; ++i) {
+            double t = m + h * or_gl_x[i];
+            acc += or_gl_w[i] * (2.0 - t) / (t + b);
+        }
+        sum += acc * h;
+        hi = lo;
+    }
+    return 0.5 * sum;
+}
+
+/* log R for surrogate training samples: one uniform cell per sample with
+ * electron density ne, ions of charge Z (A = 1 for Z = 1, 4 for Z = 2) at
+ * density ne/Z, temperature T; omega = x T.  Channels: 0 Primakoff
+ * (R = Gamma_{gamma->a}/g_agg^2, F by quadrature), 1 Compton-like, 2 e-Z
+ * brems, 3 e-e brems (R = Gamma_abs/g_ae^2, eq. gamma_abs, params' eq_stats).
+ * Also returns log(kappa/T).                                               */
+void or_surrogate_labels(const or_params* prm, int64_t n, const double* T, const double* ne,
+                         const double* Z, const double* x, const int32_t* ch, double* out,
+                         double* logkT) {
+    or_grid g = {1, {1, 1, 1}, 0.2, 0.1, 1e17};
+#pragma omp parallel for if (n > 4096)
+    for (int64_t i = 0; i < n; ++i) {
+        or_params p = *prm;
+        p.g_agg_GeV = 1.0; p.g_ae = 1.0; p.boost = 1.0; p.inverse = 1;
+        double Zi = Z[i], Ai = (Zi == 1.0) ? 1.0 : 4.0;
+        double di = ne[i] / Zi;
+        or_cell c;
+        double E = x[i] * T[i];
+        double R = 0.0;
+        if (ch[i] == 0) {
+            p.channels = OR_CH_P;
+            or_cell_state(&g, &p, 1, &T[i], &ne[i], 1, &di, &Zi, &Ai, &c);
+            R = c.G_P0 * or_F_quad(4.0 * E * E / c.kappa2);
+        } else if (ch[i] == 1) {
+            p.channels = OR_CH_C;
+            or_cell_state(&g, &p, 1, &T[i], &ne[i], 1, &di, &Zi, &Ai, &c);
+            R = or_gamma_abs(&c, &p, E, NULL);
+        } else {
+            p.channels = OR_CH_B;
+            p.brems_ee = 0;
+            or_cell_state(&g, &p, 1, &T[i], &ne[i], 1, &di, &Zi, &Ai, &c);
+            double RZ = or_gamma_abs(&c, &p, E, NULL);
+            if (ch[i] == 2) R = RZ;
+            else {
+                or_cell c2;
+                p.brems_ee = 1;
+                or_cell_state(&g, &p, 1, &T[i], &ne[i], 1, &di, &Zi, &Ai, &c2);
+                R = or_gamma_abs(&c2, &p, E, NULL) - RZ;
+            }
+        }
+        out[i] = log(R);
+        logkT[i] = 0.5 * log(c.kappa2) - log(T[i]);
+    }
+}

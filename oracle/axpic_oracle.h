@@ -136,6 +136,12 @@ void or_feedback(const or_grid* g, const or_params* prm, int64_t ncell, const in
                  double* moments_out);
 void or_push(const or_grid* g, or_species* ax, int32_t prec32);
 
+/* ---- surrogate training data ---- */
+double or_F_quad(double s);
+void or_surrogate_labels(const or_params* prm, int64_t n, const double* T, const double* ne,
+                         const double* Z, const double* x, const int32_t* ch, double* out,
+                         double* logkT);
+
 #ifdef __cplusplus
 }
 #endif

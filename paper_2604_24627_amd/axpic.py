@@ -40,7 +40,8 @@ class SpeciesC(C.Structure):
     _fields_ = [("x", C.c_void_p * 3), ("p", C.c_void_p * 3), ("w", C.c_void_p),
                 ("id", C.c_void_p), ("cell", C.c_void_p), ("n", C.c_int64),
                 ("capacity", C.c_int64), ("dtype", C.c_int32), ("kind", C.c_int32),
-                ("w_ref", C.c_double), ("Z", C.c_double), ("A", C.c_double)]
+                ("w_ref", C.c_double), ("Z", C.c_double), ("A", C.c_double),
+                ("id0", C.c_uint64), ("n_implicit", C.c_int64)]
 
 
 class CellsC(C.Structure):
@@ -70,7 +71,18 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_deposit", "axpic_cell_state", "axpic_rates", "axpic_sample_emit",
            "axpic_absorb", "axpic_feedback", "axpic_compact", "axpic_diag",
            "axpic_sampler_table", "axpic_timing_enable", "axpic_timing_read",
-           "axpic_stream_copy"]
+           "axpic_stream_copy", "axpic_mlp_blob_bytes", "axpic_mlp_train_ws_bytes",
+           "axpic_mlp_pack", "axpic_mlp_forward", "axpic_mlp_loss_grad", "axpic_mlp_adam",
+           "axpic_rates_mlp", "axpic_surrogate_samples"]
+MLP_PARAMS = 57888
+MLP_BLOB_BYTES = 112704
+
+
+class MlpC(C.Structure):
+    _fields_ = [("blob", C.c_void_p), ("feat_lo", C.c_float * 4), ("feat_sc", C.c_float * 4),
+                ("out_mu", C.c_float * 4), ("out_sigma", C.c_float * 4),
+                ("T_lo", C.c_double), ("T_hi", C.c_double), ("ne_lo", C.c_double),
+                ("ne_hi", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double)]
 
 _lib = None
 _P = C.c_void_p
@@ -109,10 +121,20 @@ def load(path: Optional[str] = None):
         ("axpic_sampler_table", [C.c_int32, C.c_double, _P]),
         ("axpic_timing_read", [C.c_char_p, C.c_size_t]),
         ("axpic_stream_copy", [_P, _P, C.c_size_t, _P]),
+        ("axpic_mlp_pack", [_P, _P, _P]),
+        ("axpic_mlp_forward", [_P, _P, C.c_int64, _P, C.c_size_t, _P, _P]),
+        ("axpic_mlp_loss_grad", [_P, _P, _P, C.c_int64, _P, C.c_size_t, _P, _P, _P]),
+        ("axpic_mlp_adam", [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                            _P]),
+        ("axpic_rates_mlp", [_P, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
+        ("axpic_surrogate_samples", [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32
         fn.argtypes = args
+    L.axpic_mlp_blob_bytes.restype = C.c_size_t
+    L.axpic_mlp_train_ws_bytes.restype = C.c_size_t
+    L.axpic_mlp_train_ws_bytes.argtypes = [C.c_int64]
     L.axpic_timing_enable.restype = None
     L.axpic_timing_enable.argtypes = [C.c_int32]
     _lib = L

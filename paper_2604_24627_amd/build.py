@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaxpic.so")
-SOURCES = [os.path.join(HERE, "csrc", "axpic.hip"), os.path.join(HERE, "csrc", "axpic_tables.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "axpic.hip"), os.path.join(HERE, "csrc", "axpic_mlp.hip"),
+           os.path.join(HERE, "csrc", "axpic_tables.cpp")]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -33,8 +33,12 @@ namespace {
 constexpr int kThreads = 256;          // threads per workgroup
 constexpr int kPer = 4;                // parents per thread in the count/apply kernels
 constexpr int kBlockParents = kThreads * kPer;
-constexpr int kStatSlots = 12;         // per-block partial statistics
+constexpr int kStatSlots = 12;         // per-thread statistics registers
+constexpr int kMaxBins = 1024;         // histogram bins per channel (+2 under/overflow)
+constexpr int kCopies = 32;            // privatised accumulator copies (histogram + statistics)
+constexpr int kAccStride = 3 * (kMaxBins + 2) + 32;
 constexpr int kScanThreads = 1024;
+constexpr int kEventBlocks = 1024;     // grid of the event kernels (grid-stride over events)
 
 __device__ double g_tab_compton[2 * (kTabN + 1)];
 __device__ double g_tab_gamma[2 * (kTabN + 1)];
@@ -45,7 +49,7 @@ struct Workspace {
     uint32_t* bsum;      // [nb] products per block
     uint32_t* bact;      // [nb] active parents per block
     uint64_t* boff;      // [nb] exclusive product offsets
-    double* bstat;       // [nb][kStatSlots]
+    double* acc;         // [kCopies][kAccStride] privatised histogram + statistics
     int64_t* ctrl;       // [8]: 0 skip flag, 1 total
 };
 
@@ -56,7 +60,7 @@ size_t ws_bytes_for(int64_t n) {
     int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
     return align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1)) + align256(4 * (size_t)nb) +
            align256(4 * (size_t)nb) + align256(8 * (size_t)nb) +
-           align256(sizeof(double) * kStatSlots * (size_t)nb) + 256;
+           align256(sizeof(double) * kCopies * (size_t)kAccStride) + 256;
 }
 
 bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
@@ -67,7 +71,7 @@ bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
     w->bsum = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->bact = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->boff = (uint64_t*)p; p += align256(8 * (size_t)nb);
-    w->bstat = (double*)p; p += align256(sizeof(double) * kStatSlots * (size_t)nb);
+    w->acc = (double*)p; p += align256(sizeof(double) * kCopies * (size_t)kAccStride);
     w->ctrl = (int64_t*)p;
     return true;
 }
@@ -125,7 +129,8 @@ bool params_ok(const axpic_params* p) {
     if (!p) return false;
     if (!(p->lambda_cap > 0.0) || !(p->w_a > 0.0)) return false;
     if (!(p->r_relax >= 0.0 && p->r_relax <= 1.0)) return false;
-    if (p->hist_nbins < 1 || !(p->hist_hi_keV > p->hist_lo_keV)) return false;
+    if (p->hist_nbins < 1 || p->hist_nbins > kMaxBins || !(p->hist_hi_keV > p->hist_lo_keV))
+        return false;
     if (p->hist_log && !(p->hist_lo_keV > 0.0)) return false;
     if (!(p->brems_k > 0.0) || !(p->brems_theta >= 1.0)) return false;
     for (int i = 0; i < 3; ++i)
@@ -139,7 +144,8 @@ bool species_ok(const axpic_species* s, bool need_p) {
     if (!s || s->n < 0 || s->capacity < s->n) return false;
     if (s->dtype != AXPIC_F32 && s->dtype != AXPIC_F64) return false;
     if (s->n == 0) return true;
-    if (!s->w || !s->id || !s->cell) return false;
+    if (s->n_implicit < 0 || s->n_implicit > s->n) return false;
+    if (!s->w || !s->cell || (!s->id && s->n_implicit < s->n)) return false;
     if (need_p && (!s->p[0] || !s->p[1] || !s->p[2])) return false;
     return true;
 }
@@ -231,57 +237,16 @@ __device__ __forceinline__ int hist_bin(const KParams& kp, double E) {
     return (int)b;
 }
 
-template <typename T>
-__device__ __forceinline__ T psq(const T* __restrict__ px, const T* __restrict__ py,
-                                 const T* __restrict__ pz, int64_t i) {
-    const T a = px[i], b = py[i], c = pz[i];
-    return a * a + b * b + c * c;
-}
-
-template <typename T> struct PrefOf;
-template <> struct PrefOf<float> { static __device__ const float* get(const float* p32, const double*) { return p32; } };
-template <> struct PrefOf<double> { static __device__ const double* get(const float*, const double* p64) { return p64; } };
-
-// lambda_P = w P_{gamma->a} / w_prod with P = 1 - exp(-c_P F(s)) (eqs. prim_xs, prim_prob)
-template <typename T>
-__device__ __forceinline__ T lambda_primakoff(const T* __restrict__ pc, T w, T p2) {
-    const T s = pc[1] * p2;
-    const T F = screenF(s);
-    const T x = pc[2] * F;
-    return w * pc[3] * F * one_minus_exp_over(x);
-}
-
-// Thermal absorption probability, eq. gamma_abs: Gamma_abs dt = aC E^2 g_C + aB g_B
-template <typename T>
-__device__ __forceinline__ T pabs_thermal(const KParams& kp, const T* __restrict__ pc, T E) {
-    const T Tk = pc[0];
-    const T x = E / Tk;
-    T g = (T)0;
-    if (pc[6] != (T)0) {
-        T occ = kp.eq_stats ? -dev_expm1<T>(-x) : (T)1;
-        g += pc[6] * E * E / occ;
+// Particle ids: the first n_implicit particles of a buffer have id id0 + i
+// (plasma species keep their creation order), the rest are stored.
+struct IdView {
+    const uint64_t* id;
+    uint64_t id0;
+    int64_t nimp;
+    __device__ __forceinline__ uint64_t operator()(int64_t i) const {
+        return i < nimp ? id0 + (uint64_t)i : id[i];
     }
-    if (pc[7] != (T)0) {
-        const T th = (T)kp.brems_theta, k = (T)kp.brems_k;
-        const T pw = dev_exp<T>((k - (T)3) * dev_log<T>(x));
-        // MB: e^{x(1-1/theta)}; BE: e^{-x/theta} (e^x - 1), with expm1 for small x
-        T shape;
-        if (kp.eq_stats || x > (T)60) shape = dev_exp<T>(x * ((T)1 - (T)1 / th));
-        else shape = dev_exp<T>(-x / th) * dev_expm1<T>(x);
-        g += pc[7] * pw * shape;
-    }
-    return -dev_expm1<T>(-g);
-}
-
-// a->gamma mean: w_a-weight * (w_a/w_gamma_prod) * (1 - exp(-ratio c_P F))
-template <typename T>
-__device__ __forceinline__ T lambda_ag(const KParams& kp, const T* __restrict__ pc, T w, T p2) {
-    const T s = pc[1] * p2;
-    const T F = screenF(s);
-    const T x = (T)kp.inv_ratio * pc[2] * F;
-    const T unit = (T)((double)pc[3] * kp.ag_unit);
-    return w * unit * F * one_minus_exp_over(x);
-}
+};
 
 // ------------------------------------------------------------------ block scan
 // Exclusive scan of one value per thread across the workgroup (kThreads).
@@ -308,75 +273,97 @@ __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* lds_w) {
     return tot;
 }
 
-__device__ void block_stats_store(double* st, double* bstat_block, double* lds) {
-    // reduce kStatSlots doubles over the workgroup; lds has kStatSlots * 4 doubles
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int s = 0; s < kStatSlots; ++s) {
-        double v = wave_sum(st[s]);
-        if (lane == 0) lds[s * 4 + wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kStatSlots) {
-        const int s = threadIdx.x;
-        bstat_block[s] = lds[s * 4 + 0] + lds[s * 4 + 1] + lds[s * 4 + 2] + lds[s * 4 + 3];
+struct StatMap { int m[kStatSlots]; };
+
+// Flush per-thread statistics into this block's accumulator copy: one FP64
+// atomic per wavefront and non-zero slot, skipped by waves without events.
+__device__ __forceinline__ void stats_flush(const double* st, bool any, double* A, int nbh,
+                                            const StatMap& map) {
+    if (!__any(any)) return;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kStatSlots; ++k) {
+        if (map.m[k] < 0) continue;
+        const double v = wave_sum(st[k]);
+        if (lane == 0 && v != 0.0) atomicAdd(A + 3 * nbh + map.m[k], v);
     }
 }
 
 // ------------------------------------------------------------------ scan kernel
 // One workgroup: exclusive offsets of the block product counts, capacity check.
+// The block totals are staged through LDS in tiles (coalesced loads and
+// stores); each thread scans a contiguous run of a tile.
+constexpr int kScanTile = 8192;
+constexpr int kScanPer = kScanTile / kScanThreads;
+
 __global__ void __launch_bounds__(kScanThreads)
 k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t nb,
-       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status) {
-    __shared__ uint64_t lds[kScanThreads / 64];
+       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status,
+       double* __restrict__ acc, int acc_used) {
+    __shared__ uint32_t tin[kScanTile];
+    __shared__ uint64_t tout[kScanTile];
+    __shared__ uint64_t wsum[kScanThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
-    const int64_t b0 = std::min<int64_t>(nb, (int64_t)t * chunk), b1 = std::min<int64_t>(nb, b0 + chunk);
-    uint64_t s = 0;
-    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
-    uint64_t inc = s;
+    if (acc)
+        for (int j = t; j < kCopies * acc_used; j += kScanThreads)
+            acc[(int64_t)(j / acc_used) * kAccStride + j % acc_used] = 0.0;
+    uint64_t carry = 0;
+    for (int64_t t0 = 0; t0 < nb; t0 += kScanTile) {
+        const int cnt = (int)std::min<int64_t>(kScanTile, nb - t0);
+        for (int j = t; j < kScanTile; j += kScanThreads) tin[j] = j < cnt ? bsum[t0 + j] : 0u;
+        __syncthreads();
+        uint64_t s = 0;
+        for (int q = 0; q < kScanPer; ++q) s += tin[t * kScanPer + q];
+        uint64_t inc = s;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint64_t v = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += v;
-    }
-    if (lane == 63) lds[wave] = inc;
-    __syncthreads();
-    uint64_t base = 0, tot = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
-        if (w < wave) base += lds[w];
-        tot += lds[w];
-    }
-    uint64_t run = base + inc - s;
-    for (int64_t b = b0; b < b1; ++b) {
-        boff[b] = run;
-        run += bsum[b];
+        for (int o = 1; o < 64; o <<= 1) {
+            uint64_t v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint64_t base = 0, tot = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            if (w < wave) base += wsum[w];
+            tot += wsum[w];
+        }
+        uint64_t run = carry + base + inc - s;
+        for (int q = 0; q < kScanPer; ++q) {
+            tout[t * kScanPer + q] = run;
+            run += tin[t * kScanPer + q];
+        }
+        __syncthreads();
+        for (int j = t; j < cnt; j += kScanThreads) boff[t0 + j] = tout[j];
+        carry += tot;
+        __syncthreads();
     }
     if (t == 0) {
-        const bool over = n_out + (int64_t)tot > capacity;
+        const bool over = n_out + (int64_t)carry > capacity;
         ctrl[0] = over ? 1 : 0;
-        ctrl[1] = (int64_t)tot;
+        ctrl[1] = (int64_t)carry;
         if (status) {
-            status[0] = n_out + (int64_t)tot;
+            status[0] = n_out + (int64_t)carry;
             status[1] = over ? AXPIC_FLAG_CAPACITY : 0;
-            status[2] = over ? 0 : (int64_t)tot;
+            status[2] = over ? 0 : (int64_t)carry;
             status[3] = 0;
         }
     }
 }
 
-// Deterministic final reduction of the per-block statistics into stats[].
-struct StatMap { int m[kStatSlots]; };
-
+// Fixed-order sum of the accumulator copies into hist[3][nbh] and stats[].
 __global__ void __launch_bounds__(kThreads)
-k_stats_reduce(const double* __restrict__ bstat, const uint32_t* __restrict__ bact, int64_t nb,
-               const int64_t* __restrict__ ctrl, StatMap map, double* __restrict__ stats) {
+k_acc_reduce(const double* __restrict__ acc, int nbh, const int64_t* __restrict__ ctrl,
+             double* __restrict__ hist, double* __restrict__ stats) {
     if (ctrl[0]) return;
-    const int s = threadIdx.x;
-    if (s >= kStatSlots || map.m[s] < 0) return;
-    double acc = 0.0;
-    for (int64_t b = 0; b < nb; ++b)
-        if (bact[b]) acc += bstat[b * kStatSlots + s];
-    stats[map.m[s]] += acc;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nh = 3 * nbh;
+    if (j >= nh + AXPIC_ST_COUNT) return;
+    const int src = j < nh ? j : 3 * nbh + (j - nh);
+    double s = 0.0;
+    for (int c = 0; c < kCopies; ++c) s += acc[(int64_t)c * kAccStride + src];
+    if (s == 0.0) return;
+    if (j < nh) { if (hist) hist[j] += s; }
+    else if (stats) stats[j - nh] += s;
 }
 
 // ------------------------------------------------------------------ cell state
@@ -398,29 +385,11 @@ k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restr
         rho += m;
         if (Zs[s] == 1.0 && As[s] < 1.5) rhoH += m;
     }
-    const double ne_dep = dens[c];
-    const double ne = prm.quasi_neutral ? nZ : ne_dep;
-    const double T = Tk[c];
-    const double XH = rho > 0.0 ? rhoH / rho : 0.0;
+    const LocalState L = local_state(Tk[c], dens[c], nZ, nZ2, rho, rhoH, prm);
+    const double T = L.T, ne = L.ne, ne_dep = L.ne_dep, XH = L.XH, kappa2 = L.kappa2;
+    const double G_P0 = L.G_P0, G_C = L.G_C, G_B = L.G_B, Q_C = L.Q_C, Q_B = L.Q_B;
+    const double meanC = L.meanC, meanB = L.meanB;
     const double hc3 = kHbarcKeVcm * kHbarcKeVcm * kHbarcKeVcm;
-    const double kappa2 = prm.kappa_mode == 1 ? prm.kappa_fixed_keV * prm.kappa_fixed_keV
-                                              : 4.0 * kPi * kAlpha * (ne + nZ2) * hc3 / T;
-    const double targets = prm.prim_targets ? (ne + nZ2) : nZ2;
-    const double G_P0 = prm.boost * kAlpha * prm.g_agg_GeV * prm.g_agg_GeV * 0.125 *
-                        (kHbarcGeVcm * kHbarcGeVcm) * kC * targets;
-    const double a_ae = prm.g_ae * prm.g_ae / (4.0 * kPi) / 1.60e-23;
-    const double T7 = T * kKeVT7;
-    const double T7sq = T7 * T7;
-    const double Q_C = rho * 2.67e-2 * (1.0 + XH) * (T7sq * T7sq * T7sq) * a_ae;
-    const double rho2 = rho * 0.01;
-    const double eta = (3.0 + XH) * rho2 / T7sq;
-    const double base = 0.150 * T7sq * sqrt(T7) * rho2 * (1.0 + XH) * a_ae;
-    const double fZ = fmax(0.0, 1.0 - 6.98e-2 * eta), fE = fmax(0.0, 1.0 - 0.140 * eta);
-    const double epsB = base * fZ + (prm.brems_ee ? base * (1.0 + XH) * (0.25 * sqrt(2.0)) * fE : 0.0);
-    const double Q_B = rho * epsB;
-    const double meanC = 5.0 * kZeta6 / kZeta5 * T, meanB = prm.brems_k * prm.brems_theta * T;
-    const double G_C = ne > 0.0 ? prm.boost * Q_C / (ne * meanC * kKeVerg) : 0.0;
-    const double G_B = ne > 0.0 ? prm.boost * Q_B / (ne * meanB * kKeVerg) : 0.0;
     double* st = state + c * AXPIC_STATE_N;
     st[0] = T; st[1] = ne; st[2] = ne_dep; st[3] = nZ; st[4] = nZ2; st[5] = rho; st[6] = XH;
     st[7] = kappa2; st[8] = G_P0; st[9] = G_C; st[10] = G_B; st[11] = Q_C; st[12] = Q_B;
@@ -524,7 +493,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
-             const T* __restrict__ py, const T* __restrict__ pz, const uint64_t* __restrict__ id,
+             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
              uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
     __shared__ uint32_t lds[kThreads / 64];
@@ -545,7 +514,7 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         if (l > (T)0) {
             double ws; int cp;
             const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
-            const uint4 r = draw(kp, id[i], step, 0, 0);
+            const uint4 r = draw(kp, id(i), step, 0, 0);
             K = poisson_inv(le, u53(r.x, r.y));
         }
         code[i] = (uint16_t)K;
@@ -557,69 +526,105 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
     if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
 }
 
-template <typename T>
+// Event records: the expand pass writes one record per product into the
+// product's id slot -- parent index (bits 0-39), event k (40-47), channel
+// (48-55) -- and the event kernels, one product per lane, replace it with
+// the final id after filling the product.
+constexpr uint64_t kRecParentMask = (1ull << 40) - 1;
+
 __global__ void __launch_bounds__(kThreads)
-k_prim_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_g,
-             const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
-             const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
-             const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
-             const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
-             const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
-             const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
-             int64_t out_cap, T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2,
-             T* __restrict__ apx, T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
-             uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ hist,
-             double* __restrict__ bstat) {
+k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
+         const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
+         int64_t out_cap, uint64_t* __restrict__ rec) {
     __shared__ uint32_t lds[kThreads / 64];
-    __shared__ double lds_st[kStatSlots * 4];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
-    const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
-    double st[kStatSlots];
-    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     uint64_t run = boff[blockIdx.x];
-    const int nbh = kp.nbins + 2;
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
-        const uint32_t K = (i < n) ? code[i] : 0u;
+        const uint32_t cd = (i < n) ? code[i] : 0u;
+        // mode 0: one channel (count in bits 0-7); mode 1: Compton bits 0-7, brems 8-15
+        const uint32_t K0 = cd & 0xFFu, K1 = mode == 1 ? (cd >> 8) : 0u;
         uint32_t segtot;
-        const uint32_t pre = block_excl_scan(K, lds, &segtot);
-        if (K > 0) {
-            const T wt = w[i];
-            const T l = lam_in ? lam_in[i]
-                               : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
-                                                     psq<T>(px, py, pz, i));
-            double ws; int cp;
-            (void)cap_lambda((double)l, kp.cap, &ws, &cp);
-            double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
-            const double wpar = w_ref_g * (double)wt;
-            double dep = (double)K * wp;
-            if (dep > wpar) { wp = wpar / (double)K; dep = wpar; st[10] += 1.0; }
-            st[9] += cp ? 1.0 : 0.0;
-            const T pxv = px[i], pyv = py[i], pzv = pz[i];
-            const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
-            const T wrel = (T)(wp / kp.w_a);
-            const int bin = hist ? hist_bin(kp, E) : 0;
-            for (uint32_t k = 0; k < K; ++k) {
-                const uint64_t rank = run + pre + k;
-                const int64_t slot = out_n + (int64_t)rank;
-                if (slot < out_cap) {
-                    ax0[slot] = x0 ? x0[i] : (T)0;
-                    if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
-                    if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
-                    apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
-                    aw[slot] = wrel;
-                    aid[slot] = (next_id + rank) | (1ull << 63);
-                    acell[slot] = cell[i];
-                }
-                if (hist) atomicAdd(&hist[0 * nbh + bin], wp * E);
-            }
-            st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
-            w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
-        }
+        const uint32_t pre = block_excl_scan(K0 + K1, lds, &segtot);
+        int64_t slot = out_n + (int64_t)(run + pre);
+        for (uint32_t k = 0; k < K0; ++k, ++slot)
+            if (slot < out_cap) rec[slot] = (uint64_t)i | ((uint64_t)k << 40) | ((uint64_t)(mode == 1 ? 1 : 0) << 48);
+        for (uint32_t k = 0; k < K1; ++k, ++slot)
+            if (slot < out_cap) rec[slot] = (uint64_t)i | ((uint64_t)k << 40) | (2ull << 48);
         run += segtot;
     }
-    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+}
+
+// One thread per converting photon: the thread that meets the parent's first
+// event record writes the positions, momenta, weights and cells of all K
+// products (contiguous slots) and depletes the parent, so no other thread
+// reads a weight while it changes.  Every thread replaces only its own
+// slot's record by the final id: a record is never overwritten before the
+// thread that owns it has read it.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_g,
+              const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
+              const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
+              const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
+              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+              const uint16_t* __restrict__ code, const int64_t* __restrict__ ctrl, int64_t out_n,
+              T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx,
+              T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
+              uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ acc,
+              StatMap smap) {
+    if (ctrl[0]) return;
+    const int64_t total = ctrl[1];
+    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int nbh = kp.nbins + 2;
+    double st[kStatSlots];
+    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    bool any = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const uint64_t rc = aid[out_n + e];
+        aid[out_n + e] = (next_id + (uint64_t)e) | (1ull << 63);
+        if (((rc >> 40) & 0xFFu) != 0) continue;          // not the parent's first event
+        const int64_t i = (int64_t)(rc & kRecParentMask);
+        if (i >= n) continue;                              // never for a well-formed record
+        const uint32_t K = code[i] & 0xFFu;
+        if ((int64_t)K > total - e) continue;
+        const T wt = w[i];
+        const T l = lam_in ? lam_in[i]
+                           : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
+                                                 psq<T>(px, py, pz, i));
+        double ws; int cp;
+        (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+        double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
+        const double wpar = w_ref_g * (double)wt;
+        double dep = (double)K * wp;
+        const bool over = dep > wpar;
+        if (over) { wp = wpar / (double)K; dep = wpar; }
+        const T pxv = px[i], pyv = py[i], pzv = pz[i];
+        const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
+        const T xv0 = x0[i], xv1 = x1 ? x1[i] : (T)0, xv2 = x2 ? x2[i] : (T)0;
+        const T wrel = (T)(wp / kp.w_a);
+        const int32_t c = cell[i];
+        const int bin = hist_bin(kp, E);
+        for (uint32_t k = 0; k < K; ++k) {
+            const int64_t slot = out_n + e + k;
+            ax0[slot] = xv0;
+            if (ax1) ax1[slot] = xv1;
+            if (ax2) ax2[slot] = xv2;
+            apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
+            aw[slot] = wrel;
+            acell[slot] = c;
+            atomicAdd(&A[bin], wp * E);
+        }
+        st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
+        st[9] += cp ? 1.0 : 0.0;
+        st[10] += over ? 1.0 : 0.0;
+        any = true;
+        w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
+    }
+    stats_flush(st, any, A, nbh, smap);
 }
 
 // ------------------------------------------------------------------ thermal emission
@@ -627,7 +632,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
               const double* __restrict__ p64, const T* __restrict__ w,
-              const uint64_t* __restrict__ id, const int32_t* __restrict__ cell,
+              IdView id, const int32_t* __restrict__ cell,
               const T* __restrict__ lam_in, uint16_t* __restrict__ code,
               uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
     __shared__ uint32_t lds[kThreads / 64];
@@ -651,7 +656,7 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
         if (!onB) lB = (T)0;
         int KC = 0, KB = 0;
         if (lC > (T)0 || lB > (T)0) {
-            const uint4 r = draw(kp, id[i], step, 1, 0);
+            const uint4 r = draw(kp, id(i), step, 1, 0);
             double ws; int cp;
             KC = poisson_inv(cap_lambda((double)lC, kp.cap, &ws, &cp), u53(r.x, r.y));
             KB = poisson_inv(cap_lambda((double)lB, kp.cap, &ws, &cp), u53(r.z, r.w));
@@ -667,88 +672,70 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_therm_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_e,
-              const float* __restrict__ p32, const double* __restrict__ p64,
-              const double* __restrict__ state, const T* __restrict__ w, const T* __restrict__ x0,
-              const T* __restrict__ x1, const T* __restrict__ x2, const uint64_t* __restrict__ id,
-              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
-              const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
-              const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
-              int64_t out_cap, T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2,
-              T* __restrict__ apx, T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
-              uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ fb,
-              double* __restrict__ hist, double* __restrict__ bstat) {
-    __shared__ uint32_t lds[kThreads / 64];
-    __shared__ double lds_st[kStatSlots * 4];
-    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
+               const float* __restrict__ p32, const double* __restrict__ p64,
+               const double* __restrict__ state, const T* __restrict__ w, const T* __restrict__ x0,
+               const T* __restrict__ x1, const T* __restrict__ x2, IdView id,
+               const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+               const int64_t* __restrict__ ctrl, int64_t out_n, T* __restrict__ ax0,
+               T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx, T* __restrict__ apy,
+               T* __restrict__ apz, T* __restrict__ aw, uint64_t* __restrict__ aid,
+               int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
+               StatMap smap) {
+    if (ctrl[0]) return;
+    const int64_t total = ctrl[1];
+    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
-    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    const int nbh = kp.nbins + 2;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
-    uint64_t run = boff[blockIdx.x];
-    const int nbh = kp.nbins + 2;
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        const uint32_t cd = (i < n) ? code[i] : 0u;
-        const uint32_t Ktot = (cd & 0xFFu) + (cd >> 8);
-        uint32_t segtot;
-        const uint32_t pre = block_excl_scan(Ktot, lds, &segtot);
-        if (Ktot > 0) {
-            const int32_t c = cell[i];
-            const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
-            const double Tc = state[(int64_t)c * AXPIC_STATE_N + 0];
-            const T wt = w[i];
-            uint32_t rank = pre;
-            for (int ch = 1; ch <= 2; ++ch) {
-                const uint32_t K = ch == 1 ? (cd & 0xFFu) : (cd >> 8);
-                if (K == 0) continue;
-                T l;
-                if (lam_in) l = lam_in[(int64_t)(ch - 1) * n + i];
-                else l = wt * pc[3 + ch];
-                double ws; int cp;
-                (void)cap_lambda((double)l, kp.cap, &ws, &cp);
-                st[9] += cp ? 1.0 : 0.0;
-                const double wp = kp.w_a * kp.wa_mul[ch] * ws;
-                const T wrel = (T)(kp.wa_mul[ch] * ws);
-                const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
-                const double xs = ch == 1 ? 1.0 : kp.brems_theta;
-                for (uint32_t k = 0; k < K; ++k) {
-                    const uint4 r = draw(kp, id[i], step, 1 + ch, k);
-                    const double E = Tc * xs * quantile(tab, u24(r.x));
-                    const double mu = 2.0 * u24(r.y) - 1.0;
-                    const double phi = 2.0 * kPi * u24(r.z);
-                    const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
-                    double sphi, cphi;
-                    sincos(phi, &sphi, &cphi);
-                    const double pm = E / kMe;
-                    const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
-                    const uint64_t grank = run + rank;
-                    const int64_t slot = out_n + (int64_t)grank;
-                    if (slot < out_cap) {
-                        ax0[slot] = x0 ? x0[i] : (T)0;
-                        if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
-                        if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
-                        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
-                        aw[slot] = wrel;
-                        aid[slot] = (next_id + grank) | (1ull << 63);
-                        acell[slot] = c;
-                    }
-                    ++rank;
-                    if (hist) atomicAdd(&hist[ch * nbh + hist_bin(kp, E)], wp * E);
-                    if (fb) {
-                        double* f = fb + (int64_t)c * 4;
-                        atomicAdd(&f[0], -wp * pm);
-                        atomicAdd(&f[1], -wp * pa[0]);
-                        atomicAdd(&f[2], -wp * pa[1]);
-                        atomicAdd(&f[3], -wp * pa[2]);
-                    }
-                    st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
-                }
-            }
+    bool any = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t slot = out_n + e;
+        const uint64_t rc = aid[slot];
+        const int64_t i = (int64_t)(rc & kRecParentMask);
+        const uint32_t k = (uint32_t)((rc >> 40) & 0xFFu);
+        const int ch = (int)((rc >> 48) & 0xFFu);          // 1 Compton, 2 brems
+        if (i >= n || (ch != 1 && ch != 2)) continue;      // never for a well-formed record
+        const int32_t c = cell[i];
+        const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
+        const double Tc = state[(int64_t)c * AXPIC_STATE_N + 0];
+        const T l = lam_in ? lam_in[(int64_t)(ch - 1) * n + i] : w[i] * pc[3 + ch];
+        double ws; int cp;
+        (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+        const double wp = kp.w_a * kp.wa_mul[ch] * ws;
+        const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
+        const double xs = ch == 1 ? 1.0 : kp.brems_theta;
+        const uint4 r = draw(kp, id(i), step, 1 + ch, k);
+        const double E = Tc * xs * quantile(tab, u24(r.x));
+        const double mu = 2.0 * u24(r.y) - 1.0;
+        const double phi = 2.0 * kPi * u24(r.z);
+        const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double sphi, cphi;
+        sincos(phi, &sphi, &cphi);
+        const double pm = E / kMe;
+        const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
+        ax0[slot] = x0[i];
+        if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
+        if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
+        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
+        aw[slot] = (T)(kp.wa_mul[ch] * ws);
+        aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
+        acell[slot] = c;
+        atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
+        if (fb) {
+            double* f = fb + (int64_t)c * 4;
+            atomicAdd(&f[0], -wp * pm);
+            atomicAdd(&f[1], -wp * pa[0]);
+            atomicAdd(&f[2], -wp * pa[1]);
+            atomicAdd(&f[3], -wp * pa[2]);
         }
-        run += segtot;
+        st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
+        if (k == 0) st[9] += cp ? 1.0 : 0.0;
+        any = true;
     }
-    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+    stats_flush(st, any, A, nbh, smap);
 }
 
 // ------------------------------------------------------------------ absorption
@@ -757,7 +744,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
             const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
-            const T* __restrict__ py, const T* __restrict__ pz, const uint64_t* __restrict__ id,
+            const T* __restrict__ py, const T* __restrict__ pz, IdView id,
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
             uint32_t* __restrict__ bact) {
@@ -776,7 +763,7 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         if (wt > (T)0) {
             const T* pc = pref + (int64_t)cell[i] * AXPIC_PREF_N;
             const T p2 = psq<T>(px, py, pz, i);
-            const uint4 r = draw(kp, id[i], step, 4, 0);
+            const uint4 r = draw(kp, id(i), step, 4, 0);
             if (thermal) {
                 const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
                 if (kp.absorb_mode == 0) {
@@ -817,10 +804,12 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gpx, T* __restrict__ gpy,
             T* __restrict__ gpz, T* __restrict__ gw, uint64_t* __restrict__ gid,
             int32_t* __restrict__ gcell, double w_ref_g, double* __restrict__ fb,
-            double* __restrict__ bstat) {
+            double* __restrict__ acc, StatMap smap) {
     __shared__ uint32_t lds[kThreads / 64];
-    __shared__ double lds_st[kStatSlots * 4];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
+    const int nbh = kp.nbins + 2;
+    bool any = false;
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -848,8 +837,8 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                 if (cd & 256u) dw = wphys;
                 else if (kp.absorb_mode == 1) {
                     const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
-                    wt = (T)((double)wt - (double)wt * (double)P);
-                    dw = wphys - w_ref_a * (double)wt;
+                    dw = wphys * (double)P;
+                    wt = (T)((wphys - dw) / w_ref_a);
                 }
                 if (dw > 0.0) {
                     if (fb) {
@@ -861,6 +850,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                     }
                     st[0] += dw; st[1] += dw * E;
                     if (cd & 256u) st[7] += 1.0;
+                    any = true;
                 }
                 if (cd & 256u) wt = (T)0;
                 wphys = w_ref_a * (double)wt;
@@ -888,13 +878,14 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                     }
                 }
                 st[2] += (double)K; st[3] += (double)K * wp; st[4] += (double)K * wp * E;
+                any = true;
                 wt = (dep >= wphys) ? (T)0 : (T)((wphys - dep) / w_ref_a);
             }
             w[i] = wt;
         }
         run += segtot;
     }
-    block_stats_store(st, bstat + (int64_t)blockIdx.x * kStatSlots, lds_st);
+    stats_flush(st, any, A, nbh, smap);
 }
 
 // ------------------------------------------------------------------ feedback
@@ -909,6 +900,12 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (c >= ncell) return;
     const int64_t lo = off[c], hi = off[c + 1];
+    const double* f = fb ? fb + c * 4 : nullptr;
+    // a cell without exchange is left exactly as it is (S = 1, b = 0); its moments are
+    // only needed for the temperature update or when requested
+    if (!moments && kp.T_mode != 2 &&
+        (!f || (f[0] == 0.0 && f[1] == 0.0 && f[2] == 0.0 && f[3] == 0.0)))
+        return;
     double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
     for (int64_t i = lo + lane; i < hi; i += 64) {
         const double wi = w_ref * (double)w[i];
@@ -922,7 +919,6 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
         m[0] = W; m[1] = P0; m[2] = P1; m[3] = P2; m[4] = U2;
     }
     if (!(W > 0.0)) return;
-    const double* f = fb ? fb + c * 4 : nullptr;
     const double dE = f ? f[0] : 0.0;
     const double d0 = f ? f[1] / W : 0.0, d1 = f ? f[2] / W : 0.0, d2 = f ? f[3] / W : 0.0;
     const double var = U2 - (P0 * P0 + P1 * P1 + P2 * P2) / W;
@@ -989,7 +985,7 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
                 const int64_t* __restrict__ ctrl, int64_t out_cap, int ndim,
                 const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
                 const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
-                const T* __restrict__ w, const uint64_t* __restrict__ id,
+                const T* __restrict__ w, IdView id,
                 const int32_t* __restrict__ cell, T* __restrict__ ox0, T* __restrict__ ox1,
                 T* __restrict__ ox2, T* __restrict__ opx, T* __restrict__ opy, T* __restrict__ opz,
                 T* __restrict__ ow, uint64_t* __restrict__ oid, int32_t* __restrict__ ocell) {
@@ -1009,7 +1005,7 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
                 if (ndim > 1) ox1[s] = x1[i];
                 if (ndim > 2) ox2[s] = x2[i];
                 opx[s] = px[i]; opy[s] = py[i]; opz[s] = pz[i];
-                ow[s] = w[i]; oid[s] = id[i]; ocell[s] = cell[i];
+                ow[s] = w[i]; oid[s] = id(i); ocell[s] = cell[i];
             }
         }
         run += segtot;
@@ -1077,6 +1073,18 @@ const StatMap kAbsMap = {{AXPIC_ST_ABS_NUM, AXPIC_ST_ABS_EN, AXPIC_ST_AG_EVENTS,
 template <typename T> inline T* TP(void* p) { return (T*)p; }
 template <typename T> inline const T* TCP(const void* p) { return (const T*)p; }
 
+inline IdView idv(const axpic_species* sp) { return IdView{sp->id, sp->id0, sp->n_implicit}; }
+
+int acc_used(const KParams& kp) { return 3 * (kp.nbins + 2) + AXPIC_ST_COUNT; }
+
+void acc_reduce(const KParams& kp, const Workspace& W, double* hist, double* stats, hipStream_t s) {
+    if (!hist && !stats) return;
+    const int nbh = kp.nbins + 2;
+    const int n = 3 * nbh + AXPIC_ST_COUNT;
+    LAUNCH("k_acc_reduce", k_acc_reduce, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+           W.acc, nbh, W.ctrl, hist, stats);
+}
+
 struct SpT {   // typed view of a species
     void* x[3]; void* p[3]; void* w; uint64_t* id; int32_t* cell;
 };
@@ -1089,20 +1097,19 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     const int64_t n = ph->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_prim_count", k_prim_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
-                       TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), ph->id, ph->cell, TCP<T>(lam_in),
+                       TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
                        W.code, W.bsum, W.bact);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status);
-    LAUNCH("k_prim_apply", k_prim_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
-                       kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
-                       TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
-                       TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.bact, W.boff, W.ctrl,
-                       ax->n, ax->capacity, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]),
-                       TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
-                       ax->cell, hist, W.bstat);
-    if (stats)
-        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
-                           W.ctrl, kEmitMap, stats);
+                       ax->capacity, W.ctrl, status, W.acc, acc_used(kp));
+    LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
+           W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
+    LAUNCH("k_prim_events", k_prim_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+           next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
+           TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
+           TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.ctrl, ax->n, TP<T>(ax->x[0]),
+           TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]),
+           TP<T>(ax->w), ax->id, ax->cell, W.acc, kEmitMap);
+    acc_reduce(kp, W, hist, stats, s);
     return launched();
 }
 
@@ -1113,20 +1120,19 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
                           const Workspace& W, hipStream_t s) {
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
-                       cells->pref32, cells->pref64, TCP<T>(el->w), el->id, el->cell,
+                       cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
                        TCP<T>(lam_in), W.code, W.bsum, W.bact);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status);
-    LAUNCH("k_therm_apply", k_therm_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step,
-                       next_id, kp, el->w_ref, cells->pref32, cells->pref64, cells->state,
-                       TCP<T>(el->w), TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), el->id,
-                       el->cell, TCP<T>(lam_in), W.code, W.bact, W.boff, W.ctrl, ax->n,
-                       ax->capacity, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]),
-                       TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
-                       ax->cell, fb, hist, W.bstat);
-    if (stats)
-        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
-                           W.ctrl, kEmitMap, stats);
+                       ax->capacity, W.ctrl, status, W.acc, acc_used(kp));
+    LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
+           W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
+    LAUNCH("k_therm_events", k_therm_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+           next_id, kp, cells->pref32, cells->pref64, cells->state, TCP<T>(el->w),
+           TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), idv(el), el->cell, TCP<T>(lam_in),
+           W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
+           TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
+                       ax->cell, fb, W.acc, kEmitMap);
+    acc_reduce(kp, W, hist, stats, s);
     return launched();
 }
 
@@ -1138,11 +1144,11 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
     const int64_t n = ax->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_abs_count", k_abs_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
-                       TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), ax->id, ax->cell, TCP<T>(pabs_in),
+                       TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
                        TCP<T>(lam_in), W.code, W.bsum, W.bact);
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
-                       out_cap, W.ctrl, status);
+                       out_cap, W.ctrl, status, W.acc, acc_used(kp));
     LAUNCH("k_abs_apply", k_abs_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
                        kp, ax->w_ref, cells->pref32, cells->pref64, TP<T>(ax->w), TCP<T>(ax->x[0]),
                        TCP<T>(ax->x[1]), TCP<T>(ax->x[2]), TCP<T>(ax->p[0]), TCP<T>(ax->p[1]),
@@ -1152,10 +1158,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        ph ? TP<T>(ph->p[0]) : nullptr, ph ? TP<T>(ph->p[1]) : nullptr,
                        ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
-                       W.bstat);
-    if (stats)
-        LAUNCH("k_stats_reduce", k_stats_reduce, dim3(1), dim3(kThreads), 0, s, W.bstat, W.bact, nb,
-                           W.ctrl, kAbsMap, stats);
+                       W.acc, kAbsMap);
+    acc_reduce(kp, W, nullptr, stats, s);
     return launched();
 }
 
@@ -1285,7 +1289,7 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
         return AXPIC_E_INVAL;
     if (axions->dtype != parent->dtype || axions->kind != AXPIC_AXION) return AXPIC_E_INVAL;
     if (!axions->x[0] || !axions->p[0] || !axions->p[1] || !axions->p[2] || !axions->w ||
-        !axions->id || !axions->cell || !parent->x[0])
+        !axions->id || !axions->cell || axions->n_implicit != 0 || !parent->x[0])
         return AXPIC_E_INVAL;
     for (int d = 1; d < g->ndim; ++d)
         if (!axions->x[d] || !parent->x[d]) return AXPIC_E_INVAL;
@@ -1388,11 +1392,11 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     LAUNCH("k_live_count", k_live_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n,              \
                        (const T*)in->w, W.code, W.bsum, W.bact);                                   \
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, (int64_t)0, \
-                       out->capacity, W.ctrl, status);                                             \
+                       out->capacity, W.ctrl, status, (double*)nullptr, 0);                                             \
     LAUNCH("k_compact_apply", k_compact_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, W.code,   \
                        W.boff, W.ctrl, out->capacity, ndim, (const T*)in->x[0],                   \
                        (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],                \
-                       (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, in->id, in->cell, \
+                       (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, idv(in), in->cell, \
                        (T*)out->x[0], (T*)out->x[1], (T*)out->x[2], (T*)out->p[0], (T*)out->p[1], \
                        (T*)out->p[2], (T*)out->w, out->id, out->cell)
     if (in->dtype == AXPIC_F32) { AXPIC_COMPACT(float); }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/axpic.h"
+
 namespace axpic {
 
 // Physical constants (CODATA 2018; cgs / keV).
@@ -50,9 +52,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // full 64-bit products: one v_mad_u64_u32 each instead of a mul_lo/mul_hi pair
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     }
     return c;
 }
@@ -191,6 +195,105 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
         if (lane >= o) v += t;
     }
     return v;
+}
+
+// ---------------------------------------------------------------- local state
+// Sec. II.E-II.H for one cell from its deposits: composition (eqs. rho_def,
+// qn_def), Debye screening (eq. kappa_debye), the Primakoff rate prefactor
+// (eqs. prim_xs, prim_rate: Gamma = G_P0 F(s)) and the per-electron
+// Compton-like and bremsstrahlung production rates (eqs. epsC, QC, GammaC,
+// eps_eZ, eps_ee).  The boost multiplies every rate.
+struct LocalState {
+    double T, ne, ne_dep, nZ, nZ2, rho, XH, kappa2;
+    double G_P0, G_C, G_B, Q_C, Q_B, meanC, meanB;
+    double G_BeZ, G_Bee;    // e-Z and e-e parts of G_B (the e-e part is zero when switched off)
+};
+
+__device__ __forceinline__ LocalState local_state(double T, double ne_dep, double nZ, double nZ2,
+                                                  double rho, double rhoH, const axpic_params& prm) {
+    LocalState L;
+    L.T = T; L.ne_dep = ne_dep; L.nZ = nZ; L.nZ2 = nZ2; L.rho = rho;
+    L.ne = prm.quasi_neutral ? nZ : ne_dep;
+    L.XH = rho > 0.0 ? rhoH / rho : 0.0;
+    const double hc3 = kHbarcKeVcm * kHbarcKeVcm * kHbarcKeVcm;
+    L.kappa2 = prm.kappa_mode == 1 ? prm.kappa_fixed_keV * prm.kappa_fixed_keV
+                                   : 4.0 * kPi * kAlpha * (L.ne + nZ2) * hc3 / T;
+    const double targets = prm.prim_targets ? (L.ne + nZ2) : nZ2;
+    L.G_P0 = prm.boost * kAlpha * prm.g_agg_GeV * prm.g_agg_GeV * 0.125 *
+             (kHbarcGeVcm * kHbarcGeVcm) * kC * targets;
+    const double a_ae = prm.g_ae * prm.g_ae / (4.0 * kPi) / 1.60e-23;
+    const double T7 = T * kKeVT7;
+    const double T7sq = T7 * T7;
+    const double XH = L.XH;
+    L.Q_C = rho * 2.67e-2 * (1.0 + XH) * (T7sq * T7sq * T7sq) * a_ae;
+    const double rho2 = rho * 0.01;
+    const double eta = (3.0 + XH) * rho2 / T7sq;
+    const double base = 0.150 * T7sq * sqrt(T7) * rho2 * (1.0 + XH) * a_ae;
+    const double fZ = fmax(0.0, 1.0 - 6.98e-2 * eta), fE = fmax(0.0, 1.0 - 0.140 * eta);
+    const double epsZ = base * fZ;
+    const double epsE = prm.brems_ee ? base * (1.0 + XH) * (0.25 * sqrt(2.0)) * fE : 0.0;
+    L.Q_B = rho * (epsZ + epsE);
+    L.meanC = 5.0 * kZeta6 / kZeta5 * T;
+    L.meanB = prm.brems_k * prm.brems_theta * T;
+    const double ne = L.ne;
+    L.G_C = ne > 0.0 ? prm.boost * L.Q_C / (ne * L.meanC * kKeVerg) : 0.0;
+    L.G_BeZ = ne > 0.0 ? prm.boost * rho * epsZ / (ne * L.meanB * kKeVerg) : 0.0;
+    L.G_Bee = ne > 0.0 ? prm.boost * rho * epsE / (ne * L.meanB * kKeVerg) : 0.0;
+    L.G_B = ne > 0.0 ? prm.boost * L.Q_B / (ne * L.meanB * kKeVerg) : 0.0;
+    return L;
+}
+
+// ---------------------------------------------------------------- per-particle rates
+template <typename T>
+__device__ __forceinline__ T psq(const T* __restrict__ px, const T* __restrict__ py,
+                                 const T* __restrict__ pz, int64_t i) {
+    const T a = px[i], b = py[i], c = pz[i];
+    return a * a + b * b + c * c;
+}
+
+template <typename T> struct PrefOf;
+template <> struct PrefOf<float> { static __device__ const float* get(const float* p32, const double*) { return p32; } };
+template <> struct PrefOf<double> { static __device__ const double* get(const float*, const double* p64) { return p64; } };
+
+// lambda_P = w P_{gamma->a} / w_prod with P = 1 - exp(-c_P F(s)) (eqs. prim_xs, prim_prob)
+template <typename T>
+__device__ __forceinline__ T lambda_primakoff(const T* __restrict__ pc, T w, T p2) {
+    const T s = pc[1] * p2;
+    const T F = screenF(s);
+    const T x = pc[2] * F;
+    return w * pc[3] * F * one_minus_exp_over(x);
+}
+
+// Thermal absorption probability, eq. gamma_abs: Gamma_abs dt = aC E^2 g_C + aB g_B
+template <typename T>
+__device__ __forceinline__ T pabs_thermal(const KParams& kp, const T* __restrict__ pc, T E) {
+    const T Tk = pc[0];
+    const T x = E / Tk;
+    T g = (T)0;
+    if (pc[6] != (T)0) {
+        T occ = kp.eq_stats ? -dev_expm1<T>(-x) : (T)1;
+        g += pc[6] * E * E / occ;
+    }
+    if (pc[7] != (T)0) {
+        const T th = (T)kp.brems_theta, k = (T)kp.brems_k;
+        const T pw = dev_exp<T>((k - (T)3) * dev_log<T>(x));
+        // MB: e^{x(1-1/theta)}; BE: e^{-x/theta} (e^x - 1), with expm1 for small x
+        T shape;
+        if (kp.eq_stats || x > (T)60) shape = dev_exp<T>(x * ((T)1 - (T)1 / th));
+        else shape = dev_exp<T>(-x / th) * dev_expm1<T>(x);
+        g += pc[7] * pw * shape;
+    }
+    return -dev_expm1<T>(-g);
+}
+
+// a->gamma mean: w_a-weight * (w_a/w_gamma_prod) * (1 - exp(-ratio c_P F))
+template <typename T>
+__device__ __forceinline__ T lambda_ag(const KParams& kp, const T* __restrict__ pc, T w, T p2) {
+    const T s = pc[1] * p2;
+    const T F = screenF(s);
+    const T x = (T)kp.inv_ratio * pc[2] * F;
+    const T unit = (T)((double)pc[3] * kp.ag_unit);
+    return w * unit * F * one_minus_exp_over(x);
 }
 
 }  // namespace axpic

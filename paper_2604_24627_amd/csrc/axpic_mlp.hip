@@ -1,0 +1,588 @@
+// axpic_mlp.hip -- the rate surrogate on gfx950 matrix cores.
+//
+// A perceptron 8 -> 128 -> 128 -> 128 -> 128 -> 1 (SiLU) predicts the
+// normalised logarithm of a rate, log R = mu_ch + sigma_ch * y, from
+// (log(omega/T), log(kappa/T), log n_e, Z, channel one-hot).  Weights and
+// layer inputs are bfloat16, accumulation FP32 (v_mfma_f32_16x16x32_bf16).
+//
+// Training (forward with saved activations, backward, Adam on FP32 master
+// weights) uses one generic MFMA GEMM kernel plus elementwise kernels.  The
+// inference kernel keeps the whole network in LDS in MFMA-fragment order and
+// chains the layers in registers: it computes H^T = W^T X^T with the
+// particles as the MFMA column dimension, so each layer's accumulator
+// registers are, after bias + SiLU + rounding, the next layer's B operand
+// under a fixed permutation of the feature index that the packed weights
+// follow.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/axpic.h"
+#include "axpic_device.hpp"
+
+using namespace axpic;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// padded widths of the training layout
+constexpr int kD0 = 32, kDH = 128, kD5 = 32;
+// offsets of the FP32 master parameters
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + kD0 * kDH;
+constexpr int64_t kOffW2 = kOffB1 + kDH;
+constexpr int64_t kLayerHH = kDH * kDH + kDH;        // W + b of a hidden 128x128 layer
+constexpr int64_t kOffW5 = kOffW2 + 3 * kLayerHH;
+constexpr int64_t kOffB5 = kOffW5 + kDH * kD5;
+constexpr int64_t kNParams = kOffB5 + kD5;
+static_assert(kNParams == AXPIC_MLP_PARAMS, "parameter layout");
+
+inline int64_t offW(int l) { return l == 1 ? kOffW1 : (l == 5 ? kOffW5 : kOffW2 + (l - 2) * kLayerHH); }
+inline int64_t offB(int l) { return l == 1 ? kOffB1 : (l == 5 ? kOffB5 : kOffW2 + (l - 2) * kLayerHH + kDH * kDH); }
+inline int dIn(int l) { return l == 1 ? kD0 : kDH; }
+inline int dOut(int l) { return l == 5 ? kD5 : kDH; }
+
+// inference blob: 108 fragments of 64 lanes x 8 bf16, then FP32 biases
+constexpr int kFragL1 = 0, kFragL2 = 8, kFragL5 = 8 + 96, kNFrag = 8 + 96 + 4;
+constexpr int kFragBytes = 64 * 8 * 2;
+constexpr int kBiasFloats = 4 * kDH + 16;
+constexpr size_t kBlobBytes = (size_t)kNFrag * kFragBytes + sizeof(float) * kBiasFloats;
+static_assert(kBlobBytes == AXPIC_MLP_BLOB_BYTES, "blob layout");
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+inline axpic_status launched() { return hipGetLastError() == hipSuccess ? AXPIC_OK : AXPIC_E_DEVICE; }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ------------------------------------------------------------------ training GEMM
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]); A(m,k) = transA ? A[k lda + m] : A[m lda + k],
+// B(k,n) = transB ? B[n ldb + k] : B[k ldb + n].  Operands rounded to bf16, FP32 accumulation.
+// One wavefront per 16 x 16 tile of C; M, N multiples of 16, K a multiple of 32.
+__global__ void __launch_bounds__(64)
+k_gemm_bf16(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_t lda, int transA,
+            const float* __restrict__ B, int64_t ldb, int transB, float* __restrict__ C,
+            int64_t ldc, const float* __restrict__ bias) {
+    const int l = threadIdx.x;
+    const int64_t tm = blockIdx.y, tn = blockIdx.x;
+    const int64_t m = tm * 16 + (l & 15), n = tn * 16 + (l & 15);
+    const int g = l >> 4;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t kc = 0; kc < K; kc += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t k = kc + 8 * g + j;
+            a[j] = (__bf16)(transA ? A[k * lda + m] : A[m * lda + k]);
+            b[j] = (__bf16)(transB ? B[n * ldb + k] : B[k * ldb + n]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    const float bv = bias ? bias[n] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(tm * 16 + 4 * g + r) * ldc + n] = acc[r] + bv;
+}
+
+__global__ void __launch_bounds__(256)
+k_silu_fwd(int64_t n, const float* __restrict__ Z, float* __restrict__ H) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) H[i] = silu(Z[i]);
+}
+
+__global__ void __launch_bounds__(256)
+k_silu_bwd(int64_t n, const float* __restrict__ Z, float* __restrict__ dZ) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dZ[i] = dZ[i] * dsilu(Z[i]);
+}
+
+// dZ5 = 2 (y - Y)/B in column 0 (the padded columns carry no gradient); loss partials.
+__global__ void __launch_bounds__(256)
+k_mse_grad(int64_t Bn, const float* __restrict__ Z5, const float* __restrict__ Y,
+           float* __restrict__ dZ5, double* __restrict__ loss) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (b < Bn) {
+        const float r = Z5[b * kD5] - Y[b];
+        for (int c = 0; c < kD5; ++c) dZ5[b * kD5 + c] = c == 0 ? 2.0f * r / (float)Bn : 0.0f;
+        e2 = (double)r * r;
+    }
+    e2 = wave_sum(e2);
+    if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, e2 / (double)Bn);
+}
+
+// Column sums (bias gradients): one workgroup per column, fixed reduction order.
+__global__ void __launch_bounds__(256)
+k_colsum(int64_t Bn, int64_t N, const float* __restrict__ dZ, float* __restrict__ out) {
+    __shared__ float part[4];
+    const int64_t c = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t b = threadIdx.x; b < Bn; b += 256) s += dZ[b * N + c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ void k_zero_d(double* p) { if (threadIdx.x == 0) *p = 0.0; }
+
+__global__ void __launch_bounds__(256)
+k_col0(int64_t Bn, const float* __restrict__ Z5, float* __restrict__ y) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < Bn) y[b] = Z5[b * kD5];
+}
+
+__global__ void __launch_bounds__(256)
+k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi; v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ packing
+// Fragment (layer, mt, c), lane l (row m = l%16 of output tile mt, group g = l/16),
+// slot j holds W[in = perm(c, g, j)][out = 16 mt + m], rounded to bf16, where
+// layer 1: perm = 8 g + j; later layers: perm = 32 c + (j < 4 ? 4 g + j : 16 + 4 g + j - 4).
+__device__ __forceinline__ int perm_in(int layer, int c, int g, int j) {
+    if (layer == 1) return 8 * g + j;
+    return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+__global__ void __launch_bounds__(64)
+k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __restrict__ bias) {
+    const int f = blockIdx.x, l = threadIdx.x;
+    int layer, mt, c;
+    if (f < kFragL2) { layer = 1; mt = f; c = 0; }
+    else if (f < kFragL5) { const int q = f - kFragL2; layer = 2 + q / 32; mt = (q % 32) / 4; c = q % 4; }
+    else { layer = 5; mt = 0; c = f - kFragL5; }
+    const int m = l & 15, g = l >> 4;
+    const int out = 16 * mt + m;
+    const int64_t ow = layer == 1 ? 0 : (layer == 5 ? kOffW5 : kOffW2 + (layer - 2) * kLayerHH);
+    const int dout = layer == 5 ? kD5 : kDH;
+    for (int j = 0; j < 8; ++j) {
+        const int in = perm_in(layer, c, g, j);
+        frag[((int64_t)f * 64 + l) * 8 + j] = (__bf16)P[ow + (int64_t)in * dout + out];
+    }
+    if (f == 0) {
+        for (int k = l; k < 4 * kDH; k += 64) {
+            const int layer2 = 1 + k / kDH, o = k % kDH;
+            const int64_t ob = layer2 == 1 ? kOffB1 : kOffW2 + (layer2 - 2) * kLayerHH + kDH * kDH;
+            bias[k] = P[ob + o];
+        }
+        if (l < 16) bias[4 * kDH + l] = P[kOffB5 + l];
+    }
+}
+
+// ------------------------------------------------------------------ inference
+constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
+constexpr int kNT = 4;                      // 16-particle column tiles per wavefront
+
+struct MlpConst {
+    float feat_lo[4], feat_sc[4];
+    float out_mu[4], out_sigma[4];
+    double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;
+};
+
+// y for the 64 particles of a wavefront: lane l supplies features f[0..7] of its
+// particle and receives y of its particle.
+__device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const float* __restrict__ bias,
+                                          const float f[8]) {
+    const int l = threadIdx.x & 63, g = l >> 4, col = l & 15;
+    // layer-1 B operand: group 0 of N-tile nt carries the 8 features of particle 16 nt + col
+    bf16x8 Bop[kNT][4];
+#pragma unroll
+    for (int nt = 0; nt < kNT; ++nt) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = __shfl(f[j], nt * 16 + col, 64);
+            Bop[nt][0][j] = (__bf16)(g == 0 ? v : 0.0f);
+        }
+    }
+    floatx4 acc[8][kNT];
+    // hidden layers 1..4
+#pragma unroll
+    for (int layer = 1; layer <= 4; ++layer) {
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int nc = layer == 1 ? 1 : 4;
+        const int fbase = layer == 1 ? kFragL1 : kFragL2 + (layer - 2) * 32;
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c >= nc) break;
+                const bf16x8 a = frag[(fbase + (layer == 1 ? mt : mt * 4 + c)) * 64 + l];
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], acc[mt][nt], 0, 0, 0);
+            }
+        }
+        // bias + SiLU; rows 16 mt + 4 g + r of this lane become slot r (mt even) or 4 + r (mt odd)
+        // of K-chunk mt/2 of the next layer
+        const float* b = bias + (layer - 1) * kDH;
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float bv = b[16 * mt + 4 * g + r];
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    Bop[nt][mt >> 1][(mt & 1) * 4 + r] = (__bf16)silu(acc[mt][nt][r] + bv);
+            }
+        }
+    }
+    // output layer: one 16-row tile, row 0 is the output
+    floatx4 o[kNT];
+#pragma unroll
+    for (int nt = 0; nt < kNT; ++nt) o[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bf16x8 a = frag[(kFragL5 + c) * 64 + l];
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt)
+            o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], o[nt], 0, 0, 0);
+    }
+    // lane col of group 0 holds y of particle 16 nt + col in o[nt][0]
+    float y = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < kNT; ++nt) {
+        const float v = __shfl(o[nt][0], col, 64);
+        if ((l >> 4) == nt) y = v;
+    }
+    return y + bias[4 * kDH];
+}
+
+// mode 0: photons -> lambda_P; mode 1: axions -> thermal P_abs; mode 2: axions -> a->gamma mean.
+template <typename T>
+__global__ void __launch_bounds__(kInfThreads)
+k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P, double g2e,
+            double boost,
+            double lam_unit_P, double lam_unit_ag, const double* __restrict__ state,
+            const float* __restrict__ p32, const double* __restrict__ p64, int32_t nion, double Zion,
+            const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
+            const T* __restrict__ pz, const int32_t* __restrict__ cell,
+            const unsigned char* __restrict__ blob, T* __restrict__ out,
+            unsigned long long* __restrict__ nfallback) {
+    __shared__ __align__(16) unsigned char lds[kBlobBytes];
+    // weights to LDS once per workgroup (grid-stride over particle tiles below)
+    {
+        const uint4* src = (const uint4*)blob;
+        uint4* dst = (uint4*)lds;
+        for (int k = threadIdx.x; k < (int)(kBlobBytes / 16); k += blockDim.x) dst[k] = src[k];
+    }
+    __syncthreads();
+    const bf16x8* frag = (const bf16x8*)lds;
+    const float* bias = (const float*)(lds + (size_t)kNFrag * kFragBytes);
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t waves_total = (int64_t)gridDim.x * (kInfThreads / 64);
+    const int64_t tiles = (n + 63) / 64;
+    unsigned long long fb_count = 0;
+    for (int64_t t = (int64_t)blockIdx.x * (kInfThreads / 64) + wave; t < tiles; t += waves_total) {
+        const int64_t i = t * 64 + lane;
+        const bool live = i < n;
+        const int64_t ii = live ? i : n - 1;
+        const int32_t c = cell[ii];
+        const double* st = state + (int64_t)c * AXPIC_STATE_N;
+        const double Tc = st[0], ne = st[1], k2 = st[7];
+        const T p2 = px[ii] * px[ii] + py[ii] * py[ii] + pz[ii] * pz[ii];
+        const double om = kMe * sqrt((double)p2);
+        const double x = om / Tc;
+        const bool in_dom = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo &&
+                            Tc <= mc.T_hi && ne >= mc.ne_lo && ne <= mc.ne_hi && x >= mc.x_lo &&
+                            x <= mc.x_hi;
+        float f[8];
+        f[0] = ((float)log(x) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
+        f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
+        f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
+        f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
+        const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
+        const T wt = w[ii];
+        double res;
+        if (mode == 0 || mode == 2) {
+            f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
+            const float y = mlp_wave(frag, bias, f);
+            const double GdtP = g2P * boost * exp((double)(mc.out_mu[0] + mc.out_sigma[0] * y)) *
+                                kp.dt_phys;
+            if (mode == 0) {
+                res = in_dom ? (double)wt * lam_unit_P * (-expm1(-GdtP))
+                             : (double)lambda_primakoff<T>(pc, wt, p2);
+            } else {
+                res = in_dom ? (double)wt * lam_unit_ag * (-expm1(-kp.inv_ratio * GdtP))
+                             : (double)lambda_ag<T>(kp, pc, wt, p2);
+            }
+        } else {
+            double G = 0.0;
+            const int chans[3] = {1, 2, 3};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int ch = chans[q];
+                f[4] = 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f; f[6] = ch == 2 ? 1.0f : 0.0f;
+                f[7] = ch == 3 ? 1.0f : 0.0f;
+                const bool on = (ch == 1) ? (kp.channels & AXPIC_COMPTON) != 0
+                                          : ((kp.channels & AXPIC_BREMS) != 0 && (ch == 2 || ee_on));
+                const float y = mlp_wave(frag, bias, f);
+                if (on) G += exp((double)(mc.out_mu[ch] + mc.out_sigma[ch] * y));
+            }
+            res = in_dom ? -expm1(-g2e * boost * G * kp.dt_phys)
+                         : (double)pabs_thermal<T>(kp, pc, (T)om);
+            if (!(wt > (T)0)) res = 0.0;
+        }
+        if (mode != 1 && !(wt > (T)0)) res = 0.0;
+        if (live) {
+            out[i] = (T)res;
+            fb_count += in_dom ? 0 : 1;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) fb_count += __shfl_xor(fb_count, o, 64);
+    if (lane == 0 && fb_count && nfallback) atomicAdd(nfallback, fb_count);
+}
+
+
+// ------------------------------------------------------------------ training samples
+// Samples of the surrogate's target generated by the plain rates in FP64: one
+// uniform cell per sample (electron density ne, ions of charge Z at density
+// ne/Z with A = 1 for Z = 1 and A = 4 for Z = 2, temperature T), omega = x T,
+// couplings 1: channel 0 Gamma_{gamma->a}/g^2 (Sec. II.F), channels 1-3 the
+// detailed-balance absorption rate (eq. gamma_abs) of the Compton-like, e-Z
+// and e-e channels per g_ae^2.
+__global__ void __launch_bounds__(256)
+k_surrogate_samples(int64_t n, axpic_params prm, const double* __restrict__ T,
+                    const double* __restrict__ ne, const double* __restrict__ Z,
+                    const double* __restrict__ x, const int32_t* __restrict__ ch,
+                    double* __restrict__ feat, double* __restrict__ logR) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    axpic_params p = prm;
+    p.g_agg_GeV = 1.0; p.g_ae = 1.0; p.boost = 1.0; p.quasi_neutral = 0; p.kappa_mode = 0;
+    p.brems_ee = 1;
+    const double Zi = Z[i], Ai = Zi == 1.0 ? 1.0 : 4.0, Ti = T[i], nei = ne[i];
+    const double ni = nei / Zi;
+    const double rho = ni * Ai * kMu;
+    const LocalState L = local_state(Ti, nei, Zi * ni, Zi * Zi * ni, rho, Zi == 1.0 ? rho : 0.0, p);
+    const double E = x[i] * Ti, xx = x[i];
+    const double hc3 = kHbarcKeVcm * kHbarcKeVcm * kHbarcKeVcm;
+    double R;
+    if (ch[i] == 0) {
+        R = L.G_P0 * screenF(4.0 * E * E / L.kappa2);
+    } else if (ch[i] == 1) {
+        const double aC = L.ne_dep * L.G_C * 2.0 * kPi * kPi * hc3 / (24.0 * kZeta5 * pow(Ti, 5.0));
+        R = aC * E * E / (p.eq_stats ? -expm1(-xx) : 1.0);
+    } else {
+        const double k = p.brems_k, th = p.brems_theta;
+        const double G = ch[i] == 2 ? L.G_BeZ : L.G_Bee;
+        const double aB = L.ne_dep * G * 2.0 * kPi * kPi * hc3 / (exp(lgamma(k)) * pow(th, k) * Ti * Ti * Ti);
+        const double shape = p.eq_stats ? exp(xx * (1.0 - 1.0 / th)) : exp(-xx / th) * expm1(xx);
+        R = aB * exp((k - 3.0) * log(xx)) * shape;
+    }
+    logR[i] = log(R);
+    feat[4 * i + 0] = log(xx);
+    feat[4 * i + 1] = 0.5 * log(L.kappa2) - log(Ti);
+    feat[4 * i + 2] = log(nei);
+    feat[4 * i + 3] = Zi;
+}
+
+KParams kparams_for(const axpic_grid* g, const axpic_params* prm, double w_ref_g) {
+    KParams k;
+    std::memset(&k, 0, sizeof(k));
+    k.dt_phys = g->dt / g->omega0;
+    k.w_a = prm->w_a;
+    for (int i = 0; i < 3; ++i) k.wa_mul[i] = prm->wa_mul[i];
+    k.w_gamma_prod = prm->w_gamma_prod > 0.0 ? prm->w_gamma_prod : w_ref_g;
+    k.inv_ratio = prm->prim_inv_ratio;
+    k.ag_unit = (w_ref_g > 0.0 && k.w_gamma_prod > 0.0)
+                    ? prm->prim_inv_ratio * prm->w_a * prm->w_a * prm->wa_mul[0] /
+                          (w_ref_g * k.w_gamma_prod)
+                    : 0.0;
+    k.brems_k = prm->brems_k;
+    k.brems_theta = prm->brems_theta;
+    k.channels = prm->channels;
+    k.inverse = prm->inverse;
+    k.eq_stats = prm->eq_stats;
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t axpic_mlp_blob_bytes(void) { return kBlobBytes; }
+
+size_t axpic_mlp_train_ws_bytes(int64_t batch) {
+    // Z1..Z4, H1..H4 [B][128], Z5 [B][32], dZ [B][128], dH [B][128], grads
+    return sizeof(float) * (size_t)batch * (8 * kDH + kD5 + 2 * kDH) + sizeof(float) * kNParams;
+}
+
+axpic_status axpic_surrogate_samples(const axpic_params* prm, int64_t n, const double* T,
+                                     const double* ne, const double* Z, const double* x,
+                                     const int32_t* ch, double* feat, double* logR, void* stream) {
+    if (!prm || n < 0 || (n && (!T || !ne || !Z || !x || !ch || !feat || !logR))) return AXPIC_E_INVAL;
+    if (n == 0) return AXPIC_OK;
+    hipLaunchKernelGGL(k_surrogate_samples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       S(stream), n, *prm, T, ne, Z, x, ch, feat, logR);
+    return launched();
+}
+
+axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream) {
+    if (!master || !blob) return AXPIC_E_INVAL;
+    hipLaunchKernelGGL(k_mlp_pack, dim3(kNFrag), dim3(64), 0, S(stream), master, (__bf16*)blob,
+                       (float*)((unsigned char*)blob + (size_t)kNFrag * kFragBytes));
+    return launched();
+}
+
+static void gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int tA, const float* B,
+                 int64_t ldb, int tB, float* C, int64_t ldc, const float* bias, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0, s, M,
+                       N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
+}
+
+struct TrainWs {
+    float *Z[6], *H[5], *dZ, *dH, *grad;
+};
+
+static TrainWs carve_train(void* ws, int64_t Bn) {
+    TrainWs t;
+    float* p = (float*)ws;
+    t.H[0] = nullptr;
+    for (int l = 1; l <= 4; ++l) { t.Z[l] = p; p += Bn * kDH; }
+    for (int l = 1; l <= 4; ++l) { t.H[l] = p; p += Bn * kDH; }
+    t.Z[5] = p; p += Bn * kD5;
+    t.dZ = p; p += Bn * kDH;
+    t.dH = p; p += Bn * kDH;
+    t.grad = p;
+    return t;
+}
+
+/* Forward pass with saved activations (training layout): X [B][32] (features in
+ * columns 0..7), y[b] = Z5[b][0]. */
+axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, void* ws,
+                               size_t ws_bytes, float* y, void* stream) {
+    if (!master || !X || !ws || batch <= 0 || batch % 32 || ws_bytes < axpic_mlp_train_ws_bytes(batch))
+        return AXPIC_E_INVAL;
+    hipStream_t s = S(stream);
+    TrainWs t = carve_train(ws, batch);
+    const float* hin = X;
+    for (int l = 1; l <= 5; ++l) {
+        gemm(batch, dOut(l), dIn(l), hin, dIn(l), 0, master + offW(l), dOut(l), 0, t.Z[l], dOut(l),
+             master + offB(l), s);
+        if (l <= 4) {
+            const int64_t n = batch * kDH;
+            hipLaunchKernelGGL(k_silu_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                               t.Z[l], t.H[l]);
+            hin = t.H[l];
+        }
+    }
+    if (y)
+        hipLaunchKernelGGL(k_col0, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
+                           t.Z[5], y);
+    return launched();
+}
+
+/* Mean-squared-error loss and its gradient with respect to the FP32 master
+ * parameters (padded layout, AXPIC_MLP_PARAMS floats) for a batch X, Y. */
+axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const float* Y, int64_t batch,
+                                 void* ws, size_t ws_bytes, float* grad, double* loss,
+                                 void* stream) {
+    if (!Y || !grad) return AXPIC_E_INVAL;
+    axpic_status st = axpic_mlp_forward(master, X, batch, ws, ws_bytes, nullptr, stream);
+    if (st != AXPIC_OK) return st;
+    hipStream_t s = S(stream);
+    TrainWs t = carve_train(ws, batch);
+    if (loss) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss);
+    float* dZ5 = t.dH;   // [B][32] fits in dH
+    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
+                       t.Z[5], Y, dZ5, loss);
+    const float* dZ = dZ5;
+    for (int l = 5; l >= 1; --l) {
+        const float* hin = l == 1 ? X : t.H[l - 1];
+        // weight gradient: hin^T dZ
+        gemm(dIn(l), dOut(l), batch, hin, dIn(l), 1, dZ, dOut(l), 0, grad + offW(l), dOut(l),
+             nullptr, s);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)dOut(l)), dim3(256), 0, s, batch,
+                           (int64_t)dOut(l), dZ, grad + offB(l));
+        if (l == 1) break;
+        // dH_{l-1} = dZ W^T, then through SiLU
+        float* dst = (dZ == t.dZ) ? t.dH : t.dZ;
+        gemm(batch, dIn(l), dOut(l), dZ, dOut(l), 0, master + offW(l), dOut(l), 1, dst, dIn(l),
+             nullptr, s);
+        const int64_t n = batch * kDH;
+        hipLaunchKernelGGL(k_silu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                           t.Z[l - 1], dst);
+        dZ = dst;
+    }
+    return launched();
+}
+
+axpic_status axpic_mlp_adam(float* master, const float* grad, float* m, float* v, int64_t step,
+                            float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!master || !grad || !m || !v || step < 1) return AXPIC_E_INVAL;
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((kNParams + 255) / 256)), dim3(256), 0, S(stream),
+                       (int64_t)kNParams, master, grad, m, v, lr, beta1, beta2, eps, c1, c2);
+    return launched();
+}
+
+axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                             const axpic_species* sp, int32_t channel, const axpic_mlp* net,
+                             void* out, unsigned long long* n_fallback, void* stream) {
+    if (!g || !cells || !prm || !sp || !net || !net->blob || (!out && sp->n)) return AXPIC_E_INVAL;
+    if (sp->n < 0 || (sp->n && (!sp->w || !sp->cell || !sp->p[0] || !sp->p[1] || !sp->p[2])))
+        return AXPIC_E_INVAL;
+    if (!cells->state || !cells->pref32 || !cells->pref64) return AXPIC_E_INVAL;
+    int mode;
+    if (sp->kind == AXPIC_PHOTON && channel == AXPIC_PRIMAKOFF) mode = 0;
+    else if (sp->kind == AXPIC_AXION && channel == (AXPIC_COMPTON | AXPIC_BREMS)) mode = 1;
+    else if (sp->kind == AXPIC_AXION && channel == AXPIC_PRIMAKOFF) mode = 2;
+    else return AXPIC_E_INVAL;
+    if (sp->n == 0) return AXPIC_OK;
+    KParams kp = kparams_for(g, prm, cells->w_ref_g);
+    MlpConst mc;
+    for (int i = 0; i < 4; ++i) {
+        mc.feat_lo[i] = net->feat_lo[i]; mc.feat_sc[i] = net->feat_sc[i];
+        mc.out_mu[i] = net->out_mu[i]; mc.out_sigma[i] = net->out_sigma[i];
+    }
+    mc.T_lo = net->T_lo; mc.T_hi = net->T_hi; mc.ne_lo = net->ne_lo; mc.ne_hi = net->ne_hi;
+    mc.x_lo = net->x_lo; mc.x_hi = net->x_hi;
+    const double g2P = prm->g_agg_GeV * prm->g_agg_GeV, g2e = prm->g_ae * prm->g_ae;
+    const double lam_unit_P = cells->w_ref_g / (prm->w_a * prm->wa_mul[0]);
+    const double lam_unit_ag = prm->w_a / kp.w_gamma_prod;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            ncu = v;
+    }
+    const int64_t tiles = (sp->n + 63) / 64;
+    const int64_t wgs = std::min<int64_t>((tiles + 7) / 8, (int64_t)ncu);
+    const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
+    if (sp->dtype == AXPIC_F32)
+        hipLaunchKernelGGL(k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+                           S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
+                           lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
+                           (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
+                           (const float*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
+                           (float*)out, n_fallback);
+    else
+        hipLaunchKernelGGL(k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+                           S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
+                           lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
+                           (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],
+                           (const double*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
+                           (double*)out, n_fallback);
+    return launched();
+}
+
+}  // extern "C"

@@ -41,6 +41,8 @@ class DeviceSpecies:
         self.p = [None, None, None]
         self.w = self.id = self.cell = None
         self.off = None
+        self.id0 = 0
+        self.n_implicit = 0
         self._alloc(max(int(capacity), 1))
 
     def _alloc(self, cap: int):
@@ -80,6 +82,9 @@ class DeviceSpecies:
         s.id[:n].copy_(torch.from_numpy(sp["id"].view(np.int64)))
         s.cell[:n].copy_(torch.from_numpy(sp["cell"]))
         s.off = torch.from_numpy(sp["off"]).to(device)
+        ids = sp["id"]
+        if n and np.array_equal(ids, ids[0] + np.arange(n, dtype=np.uint64)):
+            s.id0, s.n_implicit = int(ids[0]), n
         return s
 
     def struct(self) -> B.SpeciesC:
@@ -91,6 +96,7 @@ class DeviceSpecies:
         S.n, S.capacity = self.n, self.capacity
         S.dtype, S.kind = self.dtype, self.kind
         S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
+        S.id0, S.n_implicit = self.id0, self.n_implicit
         return S
 
     def to_numpy(self) -> Dict:

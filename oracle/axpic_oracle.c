@@ -877,6 +877,10 @@ double or_F_quad(double s) {
  * density ne/Z, temperature T; omega = x T.  Channels: 0 Primakoff
  * (R = Gamma_{gamma->a}/g_agg^2, F by quadrature), 1 Compton-like, 2 e-Z
  * brems, 3 e-e brems (R = Gamma_abs/g_ae^2, eq. gamma_abs, params' eq_stats).
+ * The brems targets exclude the cell's screening-fit factor 1 - a eta of
+ * eqs. eps_eZ / eps_ee (a = 6.98e-2 e-Z, 0.140 e-e), a per-cell constant
+ * that the inference multiplies back: R_c / (1 - a eta).  Where that factor
+ * is <= 0 the channel's rate is zero and the sample has no target (NaN).
  * Also returns log(kappa/T).                                               */
 void or_surrogate_labels(const or_params* prm, int64_t n, const double* T, const double* ne,
                          const double* Z, const double* x, const int32_t* ch, double* out,
@@ -911,6 +915,10 @@ void or_surrogate_labels(const or_params* prm, int64_t n, const double* T, const
                 or_cell_state(&g, &p, 1, &T[i], &ne[i], 1, &di, &Zi, &Ai, &c2);
                 R = or_gamma_abs(&c2, &p, E, NULL) - RZ;
             }
+            double T7 = T[i] * OR_KEV_T7;
+            double eta = (3.0 + c.XH) * (c.rho / 100.0) / (T7 * T7);
+            double supp = 1.0 - (ch[i] == 2 ? 6.98e-2 : 0.140) * eta;
+            R = supp > 0.0 ? R / supp : NAN;
         }
         out[i] = log(R);
         logkT[i] = 0.5 * log(c.kappa2) - log(T[i]);

@@ -124,16 +124,6 @@ def labels(params, T, ne, Z, x, ch):
 
 
 def sample_domain(n, seed, box=None):
-    """The training box: T ~ U[0.5, 10] keV, log n_e ~ U[ln 1e23, ln 1e26],
-    Z in {1, 2}, log(omega/T) ~ U[ln 0.01, ln 100], channel uniform."""
-    b = box or DOMAIN
-    rng = np.random.default_rng(seed)
-    T = rng.uniform(b["T"][0], b["T"][1], n)
-    ne = np.exp(rng.uniform(math.log(b["ne"][0]), math.log(b["ne"][1]), n))
-    Z = rng.integers(1, 3, n).astype(np.float64)
-    x = np.exp(rng.uniform(math.log(b["x"][0]), math.log(b["x"][1]), n))
-    ch = rng.integers(0, NCH, n).astype(np.int32)
-    return T, ne, Z, x, ch
-
-
-DOMAIN = dict(T=(0.5, 10.0), ne=(1e23, 1e26), x=(0.01, 100.0))
+    """The surrogate's training box (the shared seeded generator)."""
+    from paper_2604_24627_amd.inputs import surrogate_samples
+    return surrogate_samples(n, seed, box)

@@ -500,16 +500,27 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
+    // all loads of the thread's parents first (clamped index), then the arithmetic
+    T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
+    int32_t cv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const int64_t ii = i < n ? i : n - 1;
+        wv[j] = w[ii];
+        if (lam_in) { lv[j] = lam_in[ii]; }
+        else { xv[j] = px[ii]; yv[j] = py[ii]; zv[j] = pz[ii]; cv[j] = cell[ii]; }
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
         if (i >= n) break;
-        const T wt = w[i];
+        const T wt = wv[j];
         T l = (T)0;
         if (wt > (T)0)
-            l = lam_in ? lam_in[i]
-                       : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
-                                             psq<T>(px, py, pz, i));
+            l = lam_in ? lv[j]
+                       : lambda_primakoff<T>(pref + (int64_t)cv[j] * AXPIC_PREF_N, wt,
+                                             xv[j] * xv[j] + yv[j] * yv[j] + zv[j] * zv[j]);
         int K = 0;
         if (l > (T)0) {
             double ws; int cp;
@@ -640,18 +651,24 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
     const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
+    T lCv[kPer], lBv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const int64_t ii = i < n ? i : n - 1;
+        if (lam_in) { lCv[j] = lam_in[ii]; lBv[j] = lam_in[n + ii]; }
+        else {
+            const T* pc = pref + (int64_t)cell[ii] * AXPIC_PREF_N;
+            const T wt = w[ii];
+            lCv[j] = wt * pc[4];
+            lBv[j] = wt * pc[5];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
         if (i >= n) break;
-        T lC, lB;
-        if (lam_in) { lC = lam_in[i]; lB = lam_in[n + i]; }
-        else {
-            const T* pc = pref + (int64_t)cell[i] * AXPIC_PREF_N;
-            const T wt = w[i];
-            lC = wt * pc[4];
-            lB = wt * pc[5];
-        }
+        T lC = lCv[j], lB = lBv[j];
         if (!onC) lC = (T)0;
         if (!onB) lB = (T)0;
         int KC = 0, KB = 0;
@@ -754,15 +771,25 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
     const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
+    T wv[kPer], p2v[kPer];
+    int32_t cv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        const int64_t ii = i < n ? i : n - 1;
+        wv[j] = w[ii];
+        p2v[j] = psq<T>(px, py, pz, ii);
+        cv[j] = cell[ii];
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
         if (i >= n) break;
-        T wt = w[i];
+        T wt = wv[j];
         uint32_t cd = 0;
         if (wt > (T)0) {
-            const T* pc = pref + (int64_t)cell[i] * AXPIC_PREF_N;
-            const T p2 = psq<T>(px, py, pz, i);
+            const T* pc = pref + (int64_t)cv[j] * AXPIC_PREF_N;
+            const T p2 = p2v[j];
             const uint4 r = draw(kp, id(i), step, 4, 0);
             if (thermal) {
                 const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
@@ -889,38 +916,51 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
 }
 
 // ------------------------------------------------------------------ feedback
-// One wavefront per cell: FP64 moments, affine remap, temperature update.
+// Four cells per wavefront, 16 lanes per cell: FP64 moments by strided loads
+// and a 16-lane shuffle reduction, then the affine remap and the temperature
+// update of each cell.
+constexpr int kCellLanes = 16;
+
+__device__ __forceinline__ double group_sum16(double v) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ off,
            const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
            const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
            double* __restrict__ stats) {
-    const int lane = threadIdx.x & 63;
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (c >= ncell) return;
-    const int64_t lo = off[c], hi = off[c + 1];
-    const double* f = fb ? fb + c * 4 : nullptr;
-    // a cell without exchange is left exactly as it is (S = 1, b = 0); its moments are
-    // only needed for the temperature update or when requested
-    if (!moments && kp.T_mode != 2 &&
-        (!f || (f[0] == 0.0 && f[1] == 0.0 && f[2] == 0.0 && f[3] == 0.0)))
-        return;
+    const int lane = threadIdx.x & 63, sub = lane & (kCellLanes - 1);
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCellLanes;
+    const bool valid = c < ncell;
+    const double* f = (fb && valid) ? fb + c * 4 : nullptr;
+    const double dE = f ? f[0] : 0.0;
+    const double f1 = f ? f[1] : 0.0, f2 = f ? f[2] : 0.0, f3 = f ? f[3] : 0.0;
+    const bool has_fb = dE != 0.0 || f1 != 0.0 || f2 != 0.0 || f3 != 0.0;
+    // a cell without exchange is left exactly as it is (S = 1, b = 0); its moments are only
+    // needed for the temperature update or when requested
+    const bool work = valid && (moments || kp.T_mode == 2 || has_fb);
+    if (!__any(work)) return;
+    const int64_t lo = work ? off[c] : 0, hi = work ? off[c + 1] : 0;
     double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
-    for (int64_t i = lo + lane; i < hi; i += 64) {
+    for (int64_t i = lo + sub; i < hi; i += kCellLanes) {
         const double wi = w_ref * (double)w[i];
         const double a = px[i], b = py[i], d = pz[i];
         W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
         U2 += wi * (a * a + b * b + d * d);
     }
-    W = wave_sum(W); P0 = wave_sum(P0); P1 = wave_sum(P1); P2 = wave_sum(P2); U2 = wave_sum(U2);
-    if (moments && lane == 0) {
+    W = group_sum16(W); P0 = group_sum16(P0); P1 = group_sum16(P1); P2 = group_sum16(P2);
+    U2 = group_sum16(U2);
+    if (!work) return;
+    if (moments && sub == 0) {
         double* m = moments + c * 5;
         m[0] = W; m[1] = P0; m[2] = P1; m[3] = P2; m[4] = U2;
     }
     if (!(W > 0.0)) return;
-    const double dE = f ? f[0] : 0.0;
-    const double d0 = f ? f[1] / W : 0.0, d1 = f ? f[2] / W : 0.0, d2 = f ? f[3] / W : 0.0;
+    const double d0 = f1 / W, d1 = f2 / W, d2 = f3 / W;
     const double var = U2 - (P0 * P0 + P1 * P1 + P2 * P2) / W;
     const double dEbulk = (2.0 * (d0 * P0 + d1 * P1 + d2 * P2) + W * (d0 * d0 + d1 * d1 + d2 * d2)) * 0.5;
     const double dEth = dE - dEbulk;
@@ -929,13 +969,13 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     double S = 1.0;
     if (cold) {
         var_new = var;
-        if (lane == 0 && stats) {
+        if (sub == 0 && stats) {
             atomicAdd(&stats[AXPIC_ST_COLD_CELLS], 1.0);
             atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], dEth);
         }
     } else {
         if (var_new < 0.0) {
-            if (lane == 0 && stats) {
+            if (sub == 0 && stats) {
                 atomicAdd(&stats[AXPIC_ST_CLAMPED_CELLS], 1.0);
                 atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], -var_new * 0.5);
             }
@@ -943,16 +983,16 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
         }
         S = sqrt(var_new / var);
     }
-    if (kp.feedback && (dE != 0.0 || d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
+    if (kp.feedback && has_fb) {
         const double b0 = (1.0 - S) * (P0 / W) + d0, b1 = (1.0 - S) * (P1 / W) + d1,
                      b2 = (1.0 - S) * (P2 / W) + d2;
-        for (int64_t i = lo + lane; i < hi; i += 64) {
+        for (int64_t i = lo + sub; i < hi; i += kCellLanes) {
             px[i] = (T)(S * (double)px[i] + b0);
             py[i] = (T)(S * (double)py[i] + b1);
             pz[i] = (T)(S * (double)pz[i] + b2);
         }
     }
-    if (kp.T_mode == 2 && lane == 0) {
+    if (kp.T_mode == 2 && sub == 0) {
         const double Test = kMe / 3.0 * var_new / W;
         double Tn = (1.0 - kp.r_relax) * Tk[c] + kp.r_relax * Test;
         Tn = Tn < kp.T_floor ? kp.T_floor : (Tn > kp.T_ceil ? kp.T_ceil : Tn);
@@ -1055,9 +1095,21 @@ k_diag_final(int64_t nb, const double* __restrict__ part, double* __restrict__ o
 // ------------------------------------------------------------------ copy calibration
 __global__ void __launch_bounds__(kThreads)
 k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
+    // four independent 16-byte loads in flight per thread, then the stores
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-        dst[i] = src[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a; dst[i + stride] = b; dst[i + 2 * stride] = c; dst[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+// Status of a call whose input buffer is empty: nothing is appended.
+__global__ void k_status_empty(int64_t* __restrict__ status, int64_t out_n) {
+    if (threadIdx.x == 0) {
+        status[0] = out_n; status[1] = 0; status[2] = 0; status[3] = 0;
+    }
 }
 
 // ------------------------------------------------------------------ host launch helpers
@@ -1296,6 +1348,10 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
     Workspace W;
     if (!carve(ws, ws_bytes, parent->n, &W)) return AXPIC_E_INVAL;
     if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
+    if (parent->n == 0) {
+        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, axions->n);
+        return launched();
+    }
     axpic_status st = ensure_tables(prm->brems_k);
     if (st != AXPIC_OK) return st;
     axpic_params p2 = *prm;
@@ -1343,6 +1399,11 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
         if (axions->n && !axions->x[d]) return AXPIC_E_INVAL;
     Workspace W;
     if (!carve(ws, ws_bytes, axions->n, &W)) return AXPIC_E_INVAL;
+    if (axions->n == 0) {
+        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status,
+               a2g ? photons->n : 0);
+        return launched();
+    }
     if (a2g && std::fabs(photons->w_ref - cells->w_ref_g) > 1e-12 * photons->w_ref)
         return AXPIC_E_INVAL;
     if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
@@ -1362,7 +1423,7 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     if (!species_ok(el, true) || el->kind != AXPIC_ELECTRON) return AXPIC_E_INVAL;
     if (cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
     KParams kp = make_kparams(g, prm, 0.0);
-    const int64_t threads = cells->ncell * 64;
+    const int64_t threads = cells->ncell * kCellLanes;
     if (el->dtype == AXPIC_F32)
         LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, S(stream),
                            cells->ncell, kp, el->w_ref, off, (const float*)el->w, (float*)el->p[0],
@@ -1386,6 +1447,10 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     if (in->x[2]) { ndim = 3; if (!in->x[1] || !out->x[2]) return AXPIC_E_INVAL; }
     Workspace W;
     if (!carve(ws, ws_bytes, in->n, &W)) return AXPIC_E_INVAL;
+    if (in->n == 0) {
+        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, (int64_t)0);
+        return launched();
+    }
     const int64_t n = in->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     hipStream_t s = S(stream);
 #define AXPIC_COMPACT(T)                                                                           \

@@ -203,6 +203,14 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 // (eqs. prim_xs, prim_rate: Gamma = G_P0 F(s)) and the per-electron
 // Compton-like and bremsstrahlung production rates (eqs. epsC, QC, GammaC,
 // eps_eZ, eps_ee).  The boost multiplies every rate.
+// Screening-fit factor 1 - a eta of the brems emissivities (eqs. eps_eZ, eps_ee;
+// a = 6.98e-2 for e-Z, 0.140 for e-e), eta = (3 + X_H) rho_2 / T_7^2, unclipped.
+__device__ __forceinline__ double brems_suppression(double T_keV, double rho, double XH, bool ee) {
+    const double T7 = T_keV * kKeVT7;
+    const double eta = (3.0 + XH) * (rho * 0.01) / (T7 * T7);
+    return 1.0 - (ee ? 0.140 : 6.98e-2) * eta;
+}
+
 struct LocalState {
     double T, ne, ne_dep, nZ, nZ2, rho, XH, kappa2;
     double G_P0, G_C, G_B, Q_C, Q_B, meanC, meanB;
@@ -227,9 +235,9 @@ __device__ __forceinline__ LocalState local_state(double T, double ne_dep, doubl
     const double XH = L.XH;
     L.Q_C = rho * 2.67e-2 * (1.0 + XH) * (T7sq * T7sq * T7sq) * a_ae;
     const double rho2 = rho * 0.01;
-    const double eta = (3.0 + XH) * rho2 / T7sq;
     const double base = 0.150 * T7sq * sqrt(T7) * rho2 * (1.0 + XH) * a_ae;
-    const double fZ = fmax(0.0, 1.0 - 6.98e-2 * eta), fE = fmax(0.0, 1.0 - 0.140 * eta);
+    const double fZ = fmax(0.0, brems_suppression(T, rho, XH, false));
+    const double fE = fmax(0.0, brems_suppression(T, rho, XH, true));
     const double epsZ = base * fZ;
     const double epsE = prm.brems_ee ? base * (1.0 + XH) * (0.25 * sqrt(2.0)) * fE : 0.0;
     L.Q_B = rho * (epsZ + epsE);

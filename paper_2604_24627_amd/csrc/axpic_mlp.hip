@@ -186,7 +186,7 @@ k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __rest
 
 // ------------------------------------------------------------------ inference
 constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
-constexpr int kNT = 4;                      // 16-particle column tiles per wavefront
+constexpr int kNT = 2;                      // 16-particle column tiles per network pass
 
 struct MlpConst {
     float feat_lo[4], feat_sc[4];
@@ -194,44 +194,54 @@ struct MlpConst {
     double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;
 };
 
-// y for the 64 particles of a wavefront: lane l supplies features f[0..7] of its
-// particle and receives y of its particle.
-__device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const float* __restrict__ bias,
-                                          const float f[8]) {
+// One network pass over 32 particles of a wavefront: lanes base .. base+31
+// supply the features f[0..7] of their particle; those lanes receive y (the
+// other lanes' return value is unspecified).
+__device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
+                                          const float* __restrict__ bias, const float f[8],
+                                          int base) {
     const int l = threadIdx.x & 63, g = l >> 4, col = l & 15;
-    // layer-1 B operand: group 0 of N-tile nt carries the 8 features of particle 16 nt + col
+    // layer-1 B operand: group 0 of column tile nt carries the 8 features of particle
+    // base + 16 nt + col; the other groups hold the zero padding of inputs 8..31
     bf16x8 Bop[kNT][4];
 #pragma unroll
     for (int nt = 0; nt < kNT; ++nt) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float v = __shfl(f[j], nt * 16 + col, 64);
+            const float v = __shfl(f[j], base + nt * 16 + col, 64);
             Bop[nt][0][j] = (__bf16)(g == 0 ? v : 0.0f);
         }
     }
     floatx4 acc[8][kNT];
-    // hidden layers 1..4
-#pragma unroll
+#pragma unroll 1
     for (int layer = 1; layer <= 4; ++layer) {
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        const int nc = layer == 1 ? 1 : 4;
-        const int fbase = layer == 1 ? kFragL1 : kFragL2 + (layer - 2) * 32;
+        if (layer == 1) {
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c >= nc) break;
-                const bf16x8 a = frag[(fbase + (layer == 1 ? mt : mt * 4 + c)) * 64 + l];
+            for (int mt = 0; mt < 8; ++mt) {
+                const bf16x8 a = frag[(kFragL1 + mt) * 64 + l];
 #pragma unroll
                 for (int nt = 0; nt < kNT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][0], acc[mt][nt], 0, 0, 0);
+            }
+        } else {
+            const int fbase = kFragL2 + (layer - 2) * 32;
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bf16x8 a = frag[(fbase + mt * 4 + c) * 64 + l];
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], acc[mt][nt], 0, 0, 0);
+                }
             }
         }
-        // bias + SiLU; rows 16 mt + 4 g + r of this lane become slot r (mt even) or 4 + r (mt odd)
-        // of K-chunk mt/2 of the next layer
+        // bias + SiLU; rows 16 mt + 4 g + r of this lane become slot r (mt even) or
+        // 4 + r (mt odd) of K-chunk mt/2 of the next layer's B operand
         const float* b = bias + (layer - 1) * kDH;
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
@@ -255,14 +265,23 @@ __device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const
         for (int nt = 0; nt < kNT; ++nt)
             o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], o[nt], 0, 0, 0);
     }
-    // lane col of group 0 holds y of particle 16 nt + col in o[nt][0]
+    // lane col of group 0 holds y of particle base + 16 nt + col in o[nt][0]
+    const int rel = l - base;
     float y = 0.0f;
 #pragma unroll
     for (int nt = 0; nt < kNT; ++nt) {
         const float v = __shfl(o[nt][0], col, 64);
-        if ((l >> 4) == nt) y = v;
+        if (rel >= 0 && (rel >> 4) == nt) y = v;
     }
     return y + bias[4 * kDH];
+}
+
+// y for all 64 particles of a wavefront (two 32-particle passes).
+__device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const float* __restrict__ bias,
+                                          const float f[8]) {
+    const float y0 = mlp_pass(frag, bias, f, 0);
+    const float y1 = mlp_pass(frag, bias, f, 32);
+    return (threadIdx.x & 63) < 32 ? y0 : y1;
 }
 
 // mode 0: photons -> lambda_P; mode 1: axions -> thermal P_abs; mode 2: axions -> a->gamma mean.
@@ -326,16 +345,16 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
             }
         } else {
             double G = 0.0;
-            const int chans[3] = {1, 2, 3};
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int ch = chans[q];
+#pragma unroll 1
+            for (int ch = 1; ch <= 3; ++ch) {
                 f[4] = 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f; f[6] = ch == 2 ? 1.0f : 0.0f;
                 f[7] = ch == 3 ? 1.0f : 0.0f;
                 const bool on = (ch == 1) ? (kp.channels & AXPIC_COMPTON) != 0
                                           : ((kp.channels & AXPIC_BREMS) != 0 && (ch == 2 || ee_on));
                 const float y = mlp_wave(frag, bias, f);
-                if (on) G += exp((double)(mc.out_mu[ch] + mc.out_sigma[ch] * y));
+                // the brems targets exclude the cell's screening-fit factor; put it back
+                const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
+                if (on) G += supp * exp((double)(mc.out_mu[ch] + mc.out_sigma[ch] * y));
             }
             res = in_dom ? -expm1(-g2e * boost * G * kp.dt_phys)
                          : (double)pabs_thermal<T>(kp, pc, (T)om);
@@ -387,6 +406,8 @@ k_surrogate_samples(int64_t n, axpic_params prm, const double* __restrict__ T,
         const double aB = L.ne_dep * G * 2.0 * kPi * kPi * hc3 / (exp(lgamma(k)) * pow(th, k) * Ti * Ti * Ti);
         const double shape = p.eq_stats ? exp(xx * (1.0 - 1.0 / th)) : exp(-xx / th) * expm1(xx);
         R = aB * exp((k - 3.0) * log(xx)) * shape;
+        const double supp = brems_suppression(Ti, L.rho, L.XH, ch[i] == 3);
+        R = supp > 0.0 ? R / supp : __builtin_nan("");
     }
     logR[i] = log(R);
     feat[4 * i + 0] = log(xx);

@@ -313,3 +313,22 @@ def config5(n=(256, 256, 256), ppc=32, seed=0, **kw) -> Workload:
     for k, v in kw.items():
         setattr(wl, k, v)
     return wl
+
+
+# ---------------------------------------------------------------------------
+# Rate-surrogate training box: T ~ U[0.5, 10] keV, log n_e ~ U[ln 1e23, ln 1e26],
+# Z in {1, 2}, log(omega/T) ~ U[ln 0.01, ln 100], channel uniform over
+# (Primakoff, Compton-like, e-Z brems, e-e brems).
+# ---------------------------------------------------------------------------
+SURROGATE_BOX = dict(T=(0.5, 10.0), ne=(1e23, 1e26), x=(0.01, 100.0))
+
+
+def surrogate_samples(n: int, seed: int, box: Optional[Dict] = None):
+    b = box or SURROGATE_BOX
+    rng = np.random.default_rng([seed, 0x5A77])
+    T = rng.uniform(b["T"][0], b["T"][1], n)
+    ne = np.exp(rng.uniform(math.log(b["ne"][0]), math.log(b["ne"][1]), n))
+    Z = rng.integers(1, 3, n).astype(np.float64)
+    x = np.exp(rng.uniform(math.log(b["x"][0]), math.log(b["x"][1]), n))
+    ch = rng.integers(0, 4, n).astype(np.int32)
+    return T, ne, Z, x, ch

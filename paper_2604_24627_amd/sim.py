@@ -114,7 +114,7 @@ class AxpicSim:
     """One uniform-grid run on the current GPU."""
 
     def __init__(self, plasma: Dict, params, device: str = "cuda", axion_capacity: int = 0,
-                 photon_extra: int = 0, compact_every: int = 0, stream=None):
+                 photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None):
         self.lib = B.load()
         self.device = torch.device(device)
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
@@ -167,6 +167,10 @@ class AxpicSim:
                 "deposit ions")
         self.cell_state()
         self.need_feedback = bool(self.pdict["feedback"] or self.pdict["T_mode"] == 2)
+        # learned rate backend for the per-particle, energy-dependent rates (photon conversion,
+        # axion absorption and a->gamma); None = plain closed forms
+        self.surrogate = surrogate
+        self.fallback = torch.zeros(1, dtype=torch.int64, device=self.device)
 
     @property
     def sh(self):
@@ -294,12 +298,25 @@ class AxpicSim:
             self.fb.zero_()
         n_ax0 = self.ax.n
         self._ensure_ws(max(self.el.n, self.ph.n, n_ax0))
+        S = self.surrogate
         if p["channels"] & B.PRIMAKOFF:
-            self.emit_primakoff()
+            lam = S.rates(self, self.ph, B.PRIMAKOFF, fallback=self.fallback) if S else None
+            self.emit_primakoff(lam_in=lam)
         if p["channels"] & (B.COMPTON | B.BREMS):
             self.emit_thermal()
         if p["inverse"] and n_ax0 > 0:
-            self.absorb(n_ax0)
+            pab = lag = None
+            if S:
+                n_now = self.ax.n
+                self.ax.n = n_ax0
+                try:
+                    if p["channels"] & (B.COMPTON | B.BREMS):
+                        pab = S.rates(self, self.ax, B.COMPTON | B.BREMS, fallback=self.fallback)
+                    if p["channels"] & B.PRIMAKOFF:
+                        lag = S.rates(self, self.ax, B.PRIMAKOFF, fallback=self.fallback)
+                finally:
+                    self.ax.n = n_now
+            self.absorb(n_ax0, pabs_in=pab, lam_in=lag)
         if self.need_feedback:
             self.feedback()
         self.step_index += 1

@@ -1,0 +1,251 @@
+"""The workloads at their own shapes (needs an MI355X).
+
+* The all-channel forward plasma at full size (2D 512x512, 64 per cell per
+  species, fp32), which is the launch configuration of the benchmark.  The
+  GPU runs its fused count kernels (no rates handed in).  The oracle, fed the
+  GPU's materialised FP32 means, then decides every one of the 16.8M photons
+  and 16.8M electrons.  Event counts, product ids, cells and momenta must be
+  bit-identical, and all means must agree with the oracle's own to 1e-5.
+  The integrated power of the channels over a few steps must match the
+  closed-form emissivities.
+* The graded 3D plasma with Poisson per-cell counts, in the large-plasma
+  recipe at a size the oracle runs whole.  One full step is checked element
+  by element.
+* Forward + inverse relaxation with lognormal weights and a macro-weight
+  ratio of 100, one thermal channel at a time.  The axion number per energy
+  bin must follow the detailed-balance recursion, which has a closed form.
+  The Primakoff pair must conserve number and energy.  With feedback on, the
+  plasma's kinetic energy plus the axions' energy must be constant (FP64).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+from oracle import analytic as A  # noqa: E402
+from paper_2604_24627_amd import inputs as I  # noqa: E402
+from paper_2604_24627_amd import axpic as B  # noqa: E402
+from paper_2604_24627_amd.sim import AxpicSim  # noqa: E402
+
+ME = 510.99895
+HBARC = 1.973269804e-8          # keV cm
+KEV_ERG = 1.602176634e-9
+
+
+def np64(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def products_equal(gsp, n0, prod, w_ref, exact_p, rtol_w=1e-6, rtol_p=1e-6):
+    n = prod["w"].size
+    assert gsp.n - n0 == n
+    sl = slice(n0, n0 + n)
+    np.testing.assert_array_equal(gsp.id[sl].cpu().numpy().view(np.uint64), prod["id"])
+    np.testing.assert_array_equal(gsp.cell[sl].cpu().numpy(), prod["cell"])
+    for d in range(gsp.ndim):
+        np.testing.assert_array_equal(np64(gsp.x[d][sl]), prod["x"][d])
+    gp = np.stack([np64(gsp.p[d][sl]) for d in range(3)])
+    if exact_p:
+        np.testing.assert_array_equal(gp, prod["p"])
+    else:
+        np.testing.assert_allclose(gp, prod["p"], rtol=rtol_p, atol=rtol_p * np.abs(prod["p"]).max())
+    np.testing.assert_allclose(np64(gsp.w[sl]) * w_ref, prod["w"], rtol=rtol_w)
+
+
+def test_full_size_forward_plasma_bit_exact_and_power():
+    wl = I.config2()
+    pl = I.make_plasma(wl, 0)
+    print(f"[configs] full-size forward plasma n={wl.n} ppc={wl.ppc} dtype={wl.dtype}", flush=True)
+    g = AxpicSim(pl, wl.params)
+    o = O.OracleSim(pl, wl.params, prec32=True)
+    del pl
+    cells = o.cells()
+    st = g.state.cpu().numpy().reshape(-1, B.STATE_N)
+    for k, f in enumerate(["T", "n_e", "n_e_dep", "nZ", "nZ2", "rho", "XH", "kappa2", "G_P0",
+                           "G_C", "G_B"]):
+        np.testing.assert_allclose(st[:, k], cells[f], rtol=1e-12, atol=0, err_msg=f)
+    # materialised means, then the fused kernels as the step runs them (nothing handed in)
+    lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
+    lamT = np.stack([np64(g.rates(g.el, B.COMPTON)), np64(g.rates(g.el, B.BREMS))])
+    n0 = g.ax.n
+    kP = g.emit_primakoff()
+    prodP, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, g.next_id - kP,
+                                       lam_in=lamP)
+    np.testing.assert_allclose(lamP, olamP, rtol=1e-5)
+    print(f"[configs] Primakoff events {kP}", flush=True)
+    assert kP == prodP["w"].size and kP > 10000
+    products_equal(g.ax, n0, prodP, g.ax.w_ref, exact_p=True)
+    np.testing.assert_allclose(np64(g.ph.w[: g.ph.n]) * g.ph.w_ref, o.ph.w, rtol=1e-6)
+    n0 = g.ax.n
+    g.fb.zero_()
+    kT = g.emit_thermal()
+    fb = np.zeros(g.ncell * 4)
+    prodT, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, g.next_id - kT, fb,
+                                     lam_in=lamT)
+    np.testing.assert_allclose(lamT, olamT, rtol=1e-5)
+    print(f"[configs] thermal events {kT}", flush=True)
+    assert kT == prodT["w"].size and kT > 20000
+    products_equal(g.ax, n0, prodT, g.ax.w_ref, exact_p=False)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g.fb.cpu().numpy(), fb, rtol=1e-6, atol=1e-9 * np.abs(fb).max())
+    # integrated power of every channel over a few more full steps (the emission above was
+    # step 0)
+    del o, prodP, prodT
+    g.step_index = 1
+    for _ in range(4):
+        g.step()
+    h = g.hist_np()
+    V = wl.ncell * wl.V_cell_cm3
+    dtp = wl.dt / wl.omega0
+    c0 = O.cell_state(wl.grid(), wl.params, np.array([wl.T_keV]), np.array([wl.n_e]),
+                      [np.array([wl.n_e])], [1.0], [1.0])[0]
+    QP = A.integrate_Q(A.dQdE_primakoff, 1e-4, 400.0, c0, wl.params)
+    for i, Q in enumerate((QP, c0["Q_C"], c0["Q_B"])):
+        Qmc = h[i].sum() * KEV_ERG / (V * g.step_index * dtp)
+        print(f"[configs] channel {i}: MC power / closed form {Qmc / Q:.5f}", flush=True)
+        assert Qmc == pytest.approx(Q, rel=0.015), i
+
+
+def test_graded_poisson_plasma_one_step_elementwise():
+    wl = I.config5(n=(24, 12, 10))
+    wl.params.wa_mul = (50.0, 0.2, 0.1)
+    wl.params.boost = 1.0
+    wl.params.w_a = 3e-35
+    pl = I.make_plasma(wl, 2)
+    print(f"[configs] graded 3D plasma n={wl.n} Poisson ppc={wl.ppc}", flush=True)
+    g = AxpicSim(pl, wl.params)
+    o = O.OracleSim(pl, wl.params, prec32=True)
+    cells = o.cells()
+    st = g.state.cpu().numpy().reshape(-1, B.STATE_N)
+    for k, f in enumerate(["T", "n_e", "n_e_dep", "nZ", "nZ2", "rho", "XH", "kappa2", "G_P0",
+                           "G_C", "G_B"]):
+        np.testing.assert_allclose(st[:, k], cells[f], rtol=1e-12, atol=0, err_msg=f)
+    lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
+    lamT = np.stack([np64(g.rates(g.el, B.COMPTON)), np64(g.rates(g.el, B.BREMS))])
+    g.fb.zero_()
+    kP = g.emit_primakoff()
+    kT = g.emit_thermal()
+    fb = np.zeros(g.ncell * 4)
+    prodP, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, g.next_id - kP - kT,
+                                       lam_in=lamP)
+    prodT, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, g.next_id - kT, fb,
+                                     lam_in=lamT)
+    np.testing.assert_allclose(lamP, olamP, rtol=1e-5)
+    np.testing.assert_allclose(lamT, olamT, rtol=1e-5)
+    print(f"[configs] events Primakoff {kP} thermal {kT}", flush=True)
+    assert kP == prodP["w"].size and kT == prodT["w"].size and kP > 200 and kT > 200
+    products_equal(g.ax, 0, dict((k, np.concatenate([prodP[k], prodT[k]], axis=-1))
+                                 for k in ("w", "id", "cell", "x", "p")),
+                   g.ax.w_ref, exact_p=False)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g.fb.cpu().numpy(), fb, rtol=1e-6, atol=1e-9 * np.abs(fb).max())
+    # the feedback and the temperature update of the step
+    g.feedback()
+    O.feedback(o.grid, o.params, o.el_off, o.el, fb, o.T)
+    torch.cuda.synchronize()
+    gp = np.stack([np64(g.el.p[d][: g.el.n]) for d in range(3)])
+    np.testing.assert_allclose(gp, o.el.p, rtol=2e-6, atol=2e-6 * np.abs(o.el.p).max())
+    np.testing.assert_allclose(g.T.cpu().numpy(), o.T, rtol=1e-7)
+
+
+def _relax_workload(chan, T, boost, seed):
+    p = I.Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=chan, inverse=1, lambda_cap=1.0,
+                 boost=boost, seed=seed)
+    wl = I.Workload("relax", ndim=2, n=(16, 16), ppc=32, dtype="f32", T_keV=T, n_e=6e25,
+                    lognormal_sigma=0.5, params=p)
+    wl.params.w_a = (wl.n_e * wl.V_cell_cm3 / wl.ppc) / 100.0
+    return wl
+
+
+@pytest.mark.parametrize("chan", [B.COMPTON, B.BREMS])
+def test_relaxation_follows_detailed_balance_recursion(chan):
+    """Emission E = V dn_eq/dE Gamma_abs dt per step and absorption
+    p = 1 - exp(-Gamma_abs dt) of the axions present before the step give
+    N_n(E) = V dn_eq/dE Gamma dt (1 - e^{-n Gamma dt}) / (1 - e^{-Gamma dt})."""
+    T = 3.0
+    wl = _relax_workload(chan, T, 2e34, 3)
+    pl = I.make_plasma(wl, 3)
+    print(f"[configs] relaxation channel {chan} n={wl.n}", flush=True)
+    g = AxpicSim(pl, wl.params, compact_every=16)
+    steps = 300
+    for _ in range(steps):
+        g.step()
+    c = O.cell_state(wl.grid(), wl.params, np.array([T]), np.array([wl.n_e]),
+                     [np.array([wl.n_e])], [1.0], [1.0])[0]
+    dt = wl.dt / wl.omega0
+    V = wl.ncell * wl.V_cell_cm3
+    from scipy import integrate
+
+    def expected(E):
+        gg = O.gamma_abs(c, wl.params, E)[0] * dt
+        dneq = E * E / (2 * math.pi ** 2 * HBARC ** 3) / math.expm1(E / T)
+        return V * dneq * gg / -math.expm1(-gg) * -math.expm1(-gg * steps)
+    edges = np.array([1.5, 2.0, 3.0, 4.5, 6.0, 8.0, 11.0, 15.0, 22.0])
+    exp_bins = np.array([integrate.quad(expected, edges[k], edges[k + 1], epsrel=1e-9)[0]
+                         for k in range(edges.size - 1)])
+    a = g.ax.to_numpy()
+    E = ME * np.sqrt((a["p"].astype(np.float64) ** 2).sum(axis=0))
+    w = a["w"].astype(np.float64) * g.ax.w_ref
+    got = np.histogram(E, bins=edges, weights=w)[0]
+    w2 = np.histogram(E, bins=edges, weights=w * w)[0]
+    z = (got - exp_bins) / np.sqrt(w2)
+    print(f"[configs] relaxation channel {chan}: got/expected {np.round(got / exp_bins, 4)}, "
+          f"z {np.round(z, 2)}", flush=True)
+    assert np.all(np.abs(z) < 5.0), z
+
+
+def test_primakoff_pair_conserves_number_and_energy():
+    wl = _relax_workload(B.PRIMAKOFF, 1.3, 3e31, 5)
+    pl = I.make_plasma(wl, 5)
+    wl.params.w_a = pl["species"]["photons"]["w_ref"] / 100.0
+    wl.params.w_gamma_prod = wl.params.w_a
+    print(f"[configs] Primakoff pair n={wl.n}", flush=True)
+    g = AxpicSim(pl, wl.params, compact_every=8)
+
+    def totals():
+        out = np.zeros(2)
+        for sp in (g.ph, g.ax):
+            d = sp.to_numpy()
+            w = d["w"].astype(np.float64) * sp.w_ref
+            E = ME * np.sqrt((d["p"].astype(np.float64) ** 2).sum(axis=0))
+            out += np.array([w.sum(), (w * E).sum()])
+        return out
+    t0 = totals()
+    share = []
+    for s in range(120):
+        g.step()
+        if s % 20 == 19:
+            np.testing.assert_allclose(totals(), t0, rtol=2e-5)
+            share.append(float(g.ax.w[: g.ax.n].double().sum()) * g.ax.w_ref / t0[0])
+    print(f"[configs] Primakoff axion number share {np.round(share, 5)}", flush=True)
+    assert g.stats_dict()["ag_events"] > 0
+    assert share[-1] > share[0] > 0.0
+
+
+def test_feedback_conserves_plasma_plus_axion_energy_fp64():
+    wl = _relax_workload(B.COMPTON | B.BREMS, 3.0, 3e34, 7)
+    wl.dtype = "f64"
+    wl.params.feedback, wl.params.T_mode = 1, 2
+    pl = I.make_plasma(wl, 7)
+    print(f"[configs] feedback energy n={wl.n} dtype=f64", flush=True)
+    g = AxpicSim(pl, wl.params, compact_every=8)
+
+    def energy():
+        p2 = sum(g.el.p[d][: g.el.n] ** 2 for d in range(3))
+        Ee = 0.5 * float((g.el.w[: g.el.n] * p2).sum()) * g.el.w_ref
+        pa = torch.sqrt(sum(g.ax.p[d][: g.ax.n] ** 2 for d in range(3)))
+        Ea = float((g.ax.w[: g.ax.n] * pa).sum()) * g.ax.w_ref
+        return Ee + Ea, Ea
+    e0, _ = energy()
+    for _ in range(40):
+        g.step()
+        e, ea = energy()
+        assert e == pytest.approx(e0, rel=1e-12)
+    st = g.stats_dict()
+    print(f"[configs] axion energy share {ea / e0:.3e}", flush=True)
+    assert ea > 1e-6 * e0
+    assert st["clamped_cells"] == 0 and st["cold_cells"] == 0

@@ -328,3 +328,21 @@ def test_determinism_two_runs_bitwise():
     np.testing.assert_allclose(T1, T2, rtol=1e-13)
     # FP64 histogram atomics may sum in another order: equal to rounding
     np.testing.assert_allclose(h1, h2, rtol=1e-12)
+
+
+def test_empty_inputs_append_nothing():
+    """Empty parent or axion buffers: the calls only write the status words."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, w_a=1e-36)
+    g, _, _ = pair(wl)
+    g.status.fill_(-7)
+    saved_n = g.ph.n
+    g.ph.n = 0
+    try:
+        assert g.emit_primakoff() == 0
+    finally:
+        g.ph.n = saved_n
+    st = g.status.cpu().numpy()
+    assert st[0] == g.ax.n and st[1] == 0 and st[2] == 0
+    assert g.absorb(0) == 0
+    g.compact_axions()
+    assert g.ax.n == 0

@@ -74,5 +74,42 @@ def test_labels_equal_the_rates_they_sample():
             cz = O.cell_state(grid, dict(cell_p, brems_ee=0), np.array([T[i]]), np.array([ne[i]]),
                               [np.array([ne[i] / Z[i]])], [Z[i]], [A])[0]
             R = O.gamma_abs(c, cell_p, E)[0] - O.gamma_abs(cz, dict(cell_p, brems_ee=0), E)[0]
+        if ch[i] >= 2:
+            # brems targets exclude the cell's screening factor 1 - a eta in (0, 1]
+            if not np.isfinite(y[i]):
+                assert R == 0.0
+                continue
+            assert 0.0 <= y[i] - math.log(R) < -math.log(1e-6)
+            R = math.exp(y[i])
         assert y[i] == pytest.approx(math.log(R), abs=1e-10)
         assert lk[i] == pytest.approx(0.5 * math.log(c["kappa2"]) - math.log(T[i]), abs=1e-12)
+
+
+def test_brems_labels_scale_as_density_squared_through_the_screening_region():
+    """Without its screening factor a brems rate is base * rho / n_e * n_e with
+    base proportional to rho: doubling n_e (and the ions with it) adds exactly
+    ln 4 to log R, although the factor itself changes strongly between the two
+    densities (cold, dense cells).  The Compton-like target scales as rho."""
+    p = I.Params(g_ae=1.0, inverse=1)
+    n = 24
+    rng = np.random.default_rng(5)
+    T = rng.uniform(0.5, 1.5, n)
+    ne = np.exp(rng.uniform(np.log(1e25), np.log(4e25), n))
+    Z = np.where(np.arange(n) % 2 == 0, 1.0, 2.0)
+    x = np.exp(rng.uniform(np.log(0.1), np.log(20.0), n))
+    for chan, slope in ((1, math.log(2.0)), (2, math.log(4.0)), (3, math.log(4.0))):
+        ch = np.full(n, chan, dtype=np.int32)
+        y1, _ = M.labels(p, T, ne, Z, x, ch)
+        y2, _ = M.labels(p, T, 2 * ne, Z, x, ch)
+        ok = np.isfinite(y1) & np.isfinite(y2)
+        assert ok.sum() >= n // 2
+        np.testing.assert_allclose(y2[ok] - y1[ok], slope, atol=1e-9)
+    # and the plain rates themselves do not (the factor is a strong function of rho)
+    grid = dict(ndim=1, n=(1, 1, 1), dx=0.2, dt=0.1, omega0=1e17)
+    cp = dict(p.as_dict(), channels=4, brems_ee=0)
+    r = []
+    for f in (1.0, 2.0):
+        c = O.cell_state(grid, cp, np.array([0.7]), np.array([f * 2e25]), [np.array([f * 2e25])],
+                         [1.0], [1.0])[0]
+        r.append(O.gamma_abs(c, cp, 2.0)[0])
+    assert abs(math.log(r[1] / r[0]) - math.log(4.0)) > 0.05

@@ -40,6 +40,9 @@ ALG_BYTES = {
     "k_bin": ("axion", 36),              # x, p read; x, cell written (2D)
 }
 HBM_PEAK_GBPS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0           # dense BF16 MFMA
+# live multiply-adds of the 8-128-128-128-128-1 network, two FLOP each
+MLP_FLOP_PER_EVAL = 2 * (8 * 128 + 3 * 128 * 128 + 128)
 
 
 def parse():
@@ -51,7 +54,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--train-steps", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -211,7 +214,7 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         losses = S.train(n_samples=2_000_000, steps=a.train_steps, batch=4096, lr=2e-3,
-                         lr_end=3e-5, seed=1)
+                         lr_end=2e-5, seed=1)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t
         print(f"[bench] surrogate trained in {t_train:.1f} s, loss {losses[-1][1] if losses else 0:.3e}",
@@ -239,6 +242,25 @@ def main():
         Q_mc2 = q_mc(sim2.hist_np(), sim2.step_index)
         print(f"[bench] surrogate: {ms2 / a.steps:.3f} ms/step, {sur['value']:.3e} updates/s",
               file=sys.stderr, flush=True)
+        # the inference kernel against the matrix-core peak: network evaluations per step =
+        # photons (lambda_P) + 4 per old axion (three thermal channels, a->gamma)
+        L.axpic_timing_enable(1)
+        evals = 0
+        for _ in range(3):
+            evals += sim2.ph.n + 4 * sim2.ax.n
+            sim2.step()
+        torch.cuda.synchronize()
+        kt2 = B.timing_read()
+        L.axpic_timing_enable(0)
+        if "k_rates_mlp" in kt2:
+            launches2, tot2 = kt2["k_rates_mlp"]
+            tflops = evals * MLP_FLOP_PER_EVAL / (tot2 * 1e-3) / 1e12
+            sur["roofline"] = {"bound": "mfma", "kernel": "k_rates_mlp",
+                               "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
+                               "traffic": None, "avg_ms": round(tot2 / launches2, 5),
+                               "evals_per_step": evals / 3, "flop_per_eval": MLP_FLOP_PER_EVAL}
+            sur["kernel_ms_per_step"] = {k: round(v[1] / 3, 5) for k, v in sorted(kt2.items())}
         del sim2
 
     # ---- power check against the closed-form emissivities, CPU baseline (oracle)

@@ -271,14 +271,17 @@ axpic_status axpic_sampler_table(int32_t which, double k, double* out);
 axpic_status axpic_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Rate surrogate (learned rate backend).  A perceptron 8 -> 128 x4 (SiLU) -> 1
- * with bfloat16 weights and FP32 accumulation on the matrix cores predicts
- * y = (log R - mu_ch)/sigma_ch from x = (log(omega/T), log(kappa/T), log n_e,
- * Z) normalised as (x_i - feat_lo_i) feat_sc_i - 1, plus a one-hot channel
- * (Primakoff, Compton-like, e-Z brems, e-e brems); R = Gamma/g^2 of the
- * Primakoff conversion (Sec. II.F) or of the detailed-balance absorption
- * (eq. gamma_abs) of the channel.  Outside the training box the plain rate is
- * used for that particle.
+ * Rate surrogate (learned rate backend).  A perceptron 8 -> 128 x4 -> 1 with
+ * hard-swish activations h(z) = z clamp(z/6 + 1/2, 0, 1), bfloat16 weights
+ * and FP32 accumulation on the matrix cores predicts the residual y of
+ *   log R = mu_ch + sum_i lin_ch[i] f_i + sigma_ch y
+ * from the features x = (log(omega/T), log(kappa/T), log n_e, Z), normalised
+ * as f_i = (x_i - feat_lo_i) feat_sc_i - 1, plus a one-hot channel (Primakoff,
+ * Compton-like, e-Z brems, e-e brems); R = Gamma/g^2 of the Primakoff
+ * conversion (Sec. II.F) or of the detailed-balance absorption (eq.
+ * gamma_abs) of the channel, the brems channels without the cell's
+ * screening-fit factor of eqs. eps_eZ / eps_ee, which the rate kernel applies.
+ * Outside the training box the plain rate is used for that particle.
  * FP32 master parameters (padded training layout, AXPIC_MLP_PARAMS floats):
  * W1 [32][128], b1 [128], W2, b2, W3, b3, W4, b4 ([128][128], [128]),
  * W5 [128][32], b5 [32]; only inputs 0..7 and output 0 are live.
@@ -290,6 +293,7 @@ typedef struct {
     const void* blob;                 /* device: axpic_mlp_pack output */
     float feat_lo[4], feat_sc[4];     /* [host] feature normalisation */
     float out_mu[4], out_sigma[4];    /* [host] per-channel log-rate de-normalisation */
+    float out_lin[4][4];              /* [host] per-channel linear term in the normalised features */
     double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;   /* [host] training box (keV, cm^-3, omega/T) */
 } axpic_mlp;
 

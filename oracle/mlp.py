@@ -1,8 +1,9 @@
 """FP64 reference of the rate surrogate (test infrastructure).
 
 The surrogate is a multilayer perceptron 8 -> 128 -> 128 -> 128 -> 128 -> 1
-with SiLU activations (z * sigmoid(z)) on the four hidden layers.  Parameters
-are W_l [in x out] and b_l [out]; the forward pass is z_l = h_{l-1} W_l + b_l.
+with hard-swish activations h(z) = z * clip(z/6 + 1/2, 0, 1) on the four
+hidden layers.  Parameters are W_l [in x out] and b_l [out]; the forward
+pass is z_l = h_{l-1} W_l + b_l.
 `quantize=True` emulates the GPU kernels' storage precision: the weights and
 every layer input are rounded to bfloat16 (round to nearest even) before the
 product, accumulation and activations stay in higher precision.  Gradients
@@ -12,7 +13,8 @@ identity, as in the GPU backward pass).
 Training data: features (log(omega/T), log(kappa/T), log n_e, Z, channel
 one-hot) and labels log R, R = Gamma/g^2 from the oracle's rates (Primakoff
 with the screening function by angular quadrature; the detailed-balance
-absorption rates of the Compton-like, e-Z and e-e brems channels).
+absorption rates of the Compton-like, e-Z and e-e brems channels, the brems
+ones without the cell's screening-fit factor).
 """
 from __future__ import annotations
 
@@ -51,13 +53,12 @@ def init_params(seed=0):
     return P
 
 
-def silu(z):
-    return z / (1.0 + np.exp(-z))
+def act(z):
+    return z * np.clip(z / 6.0 + 0.5, 0.0, 1.0)
 
 
-def dsilu(z):
-    s = 1.0 / (1.0 + np.exp(-z))
-    return s * (1.0 + z * (1.0 - s))
+def dact(z):
+    return np.clip(z / 6.0 + 0.5, 0.0, 1.0) + np.where(np.abs(z) < 3.0, z / 6.0, 0.0)
 
 
 def forward(P, X, quantize=False):
@@ -68,7 +69,7 @@ def forward(P, X, quantize=False):
         Wq = to_bf16(W) if quantize else W
         z = hin @ Wq + b
         cache.append((hin, Wq, z))
-        h = silu(z) if l < 4 else z
+        h = act(z) if l < 4 else z
     return h[:, 0], cache
 
 
@@ -82,7 +83,7 @@ def loss_and_grads(P, X, Y, quantize=False):
     for l in range(4, -1, -1):
         hin, Wq, z = cache[l]
         if l < 4:
-            dz = dz * dsilu(z)
+            dz = dz * dact(z)
         gW = hin.T @ dz
         gb = dz.sum(axis=0)
         grads[l] = [gW, gb]

@@ -81,6 +81,7 @@ MLP_BLOB_BYTES = 112704
 class MlpC(C.Structure):
     _fields_ = [("blob", C.c_void_p), ("feat_lo", C.c_float * 4), ("feat_sc", C.c_float * 4),
                 ("out_mu", C.c_float * 4), ("out_sigma", C.c_float * 4),
+                ("out_lin", C.c_float * 16),
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("ne_lo", C.c_double),
                 ("ne_hi", C.c_double), ("x_lo", C.c_double), ("x_hi", C.c_double)]
 

@@ -24,6 +24,7 @@
 
 #include "../../include/axpic.h"
 #include "axpic_device.hpp"
+#include "axpic_timing.hpp"
 #include "axpic_tables.h"
 
 using namespace axpic;
@@ -185,8 +186,6 @@ inline axpic_status launched() {
 
 
 // ------------------------------------------------------------------ kernel timing
-// Optional per-kernel timing: HIP events recorded on the launch stream around
-// every kernel, read back and accumulated by axpic_timing_read.
 struct PendingTime { const char* name; hipEvent_t a, b; };
 struct TimingState {
     std::mutex mu;
@@ -203,30 +202,6 @@ hipEvent_t pool_get(TimingState& t) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-
-struct KTimer {
-    const char* name; hipStream_t s; hipEvent_t a = nullptr, b = nullptr;
-    KTimer(const char* n, hipStream_t st) : name(n), s(st) {
-        TimingState& t = timing();
-        if (!t.on) return;
-        std::lock_guard<std::mutex> lock(t.mu);
-        a = pool_get(t); b = pool_get(t);
-        if (a && b) hipEventRecord(a, s);
-    }
-    ~KTimer() {
-        if (!a || !b) return;
-        TimingState& t = timing();
-        hipEventRecord(b, s);
-        std::lock_guard<std::mutex> lock(t.mu);
-        t.pending.push_back({name, a, b});
-    }
-};
-
-#define LAUNCH(NAME, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                       \
-    do {                                                                                           \
-        KTimer kt_(NAME, STREAM);                                                                  \
-        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                         \
-    } while (0)
 
 // ------------------------------------------------------------------ device helpers
 __device__ __forceinline__ int hist_bin(const KParams& kp, double E) {
@@ -1510,6 +1485,19 @@ axpic_status axpic_sampler_table(int32_t which, double k, double* out) {
 }
 
 }  // extern "C"
+
+namespace axpic_timing {
+bool begin(const char* name, hipEvent_t* a, hipEvent_t* b) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (!t.on) return false;
+    *a = pool_get(t);
+    *b = pool_get(t);
+    if (!*a || !*b) return false;
+    t.pending.push_back({name, *a, *b});
+    return true;
+}
+}  // namespace axpic_timing
 
 extern "C" {
 

@@ -1,16 +1,21 @@
 // axpic_mlp.hip -- the rate surrogate on gfx950 matrix cores.
 //
-// A perceptron 8 -> 128 -> 128 -> 128 -> 128 -> 1 (SiLU) predicts the
-// normalised logarithm of a rate, log R = mu_ch + sigma_ch * y, from
-// (log(omega/T), log(kappa/T), log n_e, Z, channel one-hot).  Weights and
+// A perceptron 8 -> 128 -> 128 -> 128 -> 128 -> 1 with hard-swish
+// activations predicts the residual y of the logarithm of a rate,
+// log R = mu_ch + lin_ch . f + sigma_ch * y, from the normalised features f of
+// (log(omega/T), log(kappa/T), log n_e, Z) and a channel one-hot.  Weights and
 // layer inputs are bfloat16, accumulation FP32 (v_mfma_f32_16x16x32_bf16).
+// Hard-swish costs two vector instructions (an FMA with clamp, a multiply):
+// the inference stays bound by the matrix cores, where a sigmoid-based
+// activation (an exponential and a reciprocal per element) would leave it
+// bound by the vector ALU.
 //
 // Training (forward with saved activations, backward, Adam on FP32 master
 // weights) uses one generic MFMA GEMM kernel plus elementwise kernels.  The
 // inference kernel keeps the whole network in LDS in MFMA-fragment order and
 // chains the layers in registers: it computes H^T = W^T X^T with the
 // particles as the MFMA column dimension, so each layer's accumulator
-// registers are, after bias + SiLU + rounding, the next layer's B operand
+// registers are, after activation and rounding, the next layer's B operand
 // under a fixed permutation of the feature index that the packed weights
 // follow.
 #include <hip/hip_runtime.h>
@@ -21,6 +26,7 @@
 
 #include "../../include/axpic.h"
 #include "axpic_device.hpp"
+#include "axpic_timing.hpp"
 
 using namespace axpic;
 
@@ -56,10 +62,13 @@ static_assert(kBlobBytes == AXPIC_MLP_BLOB_BYTES, "blob layout");
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
 inline axpic_status launched() { return hipGetLastError() == hipSuccess ? AXPIC_OK : AXPIC_E_DEVICE; }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
-__device__ __forceinline__ float dsilu(float z) {
-    const float s = 1.0f / (1.0f + expf(-z));
-    return s * (1.0f + z * (1.0f - s));
+// hard-swish h(z) = z clamp(z/6 + 1/2, 0, 1) and its derivative
+__device__ __forceinline__ float act(float z) {
+    return z * __builtin_amdgcn_fmed3f(fmaf(z, 1.0f / 6.0f, 0.5f), 0.0f, 1.0f);
+}
+__device__ __forceinline__ float dact(float z) {
+    const float t = __builtin_amdgcn_fmed3f(fmaf(z, 1.0f / 6.0f, 0.5f), 0.0f, 1.0f);
+    return (z > -3.0f && z < 3.0f) ? fmaf(z, 1.0f / 6.0f, t) : t;
 }
 
 // ------------------------------------------------------------------ training GEMM
@@ -91,15 +100,15 @@ k_gemm_bf16(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_
 }
 
 __global__ void __launch_bounds__(256)
-k_silu_fwd(int64_t n, const float* __restrict__ Z, float* __restrict__ H) {
+k_act_fwd(int64_t n, const float* __restrict__ Z, float* __restrict__ H) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) H[i] = silu(Z[i]);
+    if (i < n) H[i] = act(Z[i]);
 }
 
 __global__ void __launch_bounds__(256)
-k_silu_bwd(int64_t n, const float* __restrict__ Z, float* __restrict__ dZ) {
+k_act_bwd(int64_t n, const float* __restrict__ Z, float* __restrict__ dZ) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dZ[i] = dZ[i] * dsilu(Z[i]);
+    if (i < n) dZ[i] = dZ[i] * dact(Z[i]);
 }
 
 // dZ5 = 2 (y - Y)/B in column 0 (the padded columns carry no gradient); loss partials.
@@ -191,6 +200,7 @@ constexpr int kNT = 2;                      // 16-particle column tiles per netw
 struct MlpConst {
     float feat_lo[4], feat_sc[4];
     float out_mu[4], out_sigma[4];
+    float out_lin[4][4];
     double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;
 };
 
@@ -215,10 +225,14 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
     floatx4 acc[8][kNT];
 #pragma unroll 1
     for (int layer = 1; layer <= 4; ++layer) {
+        // accumulators start at the bias of their rows 16 mt + 4 g + r
+        const floatx4* b4 = (const floatx4*)(bias + (layer - 1) * kDH);
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
+        for (int mt = 0; mt < 8; ++mt) {
+            const floatx4 bv = b4[4 * mt + g];
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = bv;
+        }
         if (layer == 1) {
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt) {
@@ -240,17 +254,15 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
                 }
             }
         }
-        // bias + SiLU; rows 16 mt + 4 g + r of this lane become slot r (mt even) or
+        // activation; rows 16 mt + 4 g + r of this lane become slot r (mt even) or
         // 4 + r (mt odd) of K-chunk mt/2 of the next layer's B operand
-        const float* b = bias + (layer - 1) * kDH;
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float bv = b[16 * mt + 4 * g + r];
 #pragma unroll
                 for (int nt = 0; nt < kNT; ++nt)
-                    Bop[nt][mt >> 1][(mt & 1) * 4 + r] = (__bf16)silu(acc[mt][nt][r] + bv);
+                    Bop[nt][mt >> 1][(mt & 1) * 4 + r] = (__bf16)act(acc[mt][nt][r]);
             }
         }
     }
@@ -282,6 +294,23 @@ __device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const
     const float y0 = mlp_pass(frag, bias, f, 0);
     const float y1 = mlp_pass(frag, bias, f, 32);
     return (threadIdx.x & 63) < 32 ? y0 : y1;
+}
+
+// log R of channel ch from the network output y and the normalised features f[0..3]
+// (selects with constant indices: a runtime index into the by-value argument
+// would put it in scratch memory)
+__device__ __forceinline__ float pick(const float a[4], int ch) {
+    return ch == 0 ? a[0] : (ch == 1 ? a[1] : (ch == 2 ? a[2] : a[3]));
+}
+__device__ __forceinline__ float log_rate(const MlpConst& mc, int ch, const float f[8], float y) {
+    float v = pick(mc.out_mu, ch);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float li = ch == 0 ? mc.out_lin[0][i]
+                                 : (ch == 1 ? mc.out_lin[1][i] : (ch == 2 ? mc.out_lin[2][i] : mc.out_lin[3][i]));
+        v = fmaf(li, f[i], v);
+    }
+    return fmaf(pick(mc.out_sigma, ch), y, v);
 }
 
 // mode 0: photons -> lambda_P; mode 1: axions -> thermal P_abs; mode 2: axions -> a->gamma mean.
@@ -334,8 +363,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
         if (mode == 0 || mode == 2) {
             f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
             const float y = mlp_wave(frag, bias, f);
-            const double GdtP = g2P * boost * exp((double)(mc.out_mu[0] + mc.out_sigma[0] * y)) *
-                                kp.dt_phys;
+            const double GdtP = g2P * boost * exp((double)log_rate(mc, 0, f, y)) * kp.dt_phys;
             if (mode == 0) {
                 res = in_dom ? (double)wt * lam_unit_P * (-expm1(-GdtP))
                              : (double)lambda_primakoff<T>(pc, wt, p2);
@@ -354,7 +382,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
                 const float y = mlp_wave(frag, bias, f);
                 // the brems targets exclude the cell's screening-fit factor; put it back
                 const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
-                if (on) G += supp * exp((double)(mc.out_mu[ch] + mc.out_sigma[ch] * y));
+                if (on) G += supp * exp((double)log_rate(mc, ch, f, y));
             }
             res = in_dom ? -expm1(-g2e * boost * G * kp.dt_phys)
                          : (double)pabs_thermal<T>(kp, pc, (T)om);
@@ -452,21 +480,21 @@ axpic_status axpic_surrogate_samples(const axpic_params* prm, int64_t n, const d
                                      const int32_t* ch, double* feat, double* logR, void* stream) {
     if (!prm || n < 0 || (n && (!T || !ne || !Z || !x || !ch || !feat || !logR))) return AXPIC_E_INVAL;
     if (n == 0) return AXPIC_OK;
-    hipLaunchKernelGGL(k_surrogate_samples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+    LAUNCH("k_surrogate_samples", k_surrogate_samples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        S(stream), n, *prm, T, ne, Z, x, ch, feat, logR);
     return launched();
 }
 
 axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream) {
     if (!master || !blob) return AXPIC_E_INVAL;
-    hipLaunchKernelGGL(k_mlp_pack, dim3(kNFrag), dim3(64), 0, S(stream), master, (__bf16*)blob,
+    LAUNCH("k_mlp_pack", k_mlp_pack, dim3(kNFrag), dim3(64), 0, S(stream), master, (__bf16*)blob,
                        (float*)((unsigned char*)blob + (size_t)kNFrag * kFragBytes));
     return launched();
 }
 
 static void gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int tA, const float* B,
                  int64_t ldb, int tB, float* C, int64_t ldc, const float* bias, hipStream_t s) {
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0, s, M,
+    LAUNCH("k_gemm_bf16", k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0, s, M,
                        N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
 }
 
@@ -501,13 +529,13 @@ axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batc
              master + offB(l), s);
         if (l <= 4) {
             const int64_t n = batch * kDH;
-            hipLaunchKernelGGL(k_silu_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+            LAUNCH("k_act_fwd", k_act_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                                t.Z[l], t.H[l]);
             hin = t.H[l];
         }
     }
     if (y)
-        hipLaunchKernelGGL(k_col0, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
+        LAUNCH("k_col0", k_col0, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
                            t.Z[5], y);
     return launched();
 }
@@ -522,9 +550,9 @@ axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const floa
     if (st != AXPIC_OK) return st;
     hipStream_t s = S(stream);
     TrainWs t = carve_train(ws, batch);
-    if (loss) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss);
+    if (loss) LAUNCH("k_zero_d", k_zero_d, dim3(1), dim3(64), 0, s, loss);
     float* dZ5 = t.dH;   // [B][32] fits in dH
-    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
+    LAUNCH("k_mse_grad", k_mse_grad, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, batch,
                        t.Z[5], Y, dZ5, loss);
     const float* dZ = dZ5;
     for (int l = 5; l >= 1; --l) {
@@ -532,15 +560,15 @@ axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const floa
         // weight gradient: hin^T dZ
         gemm(dIn(l), dOut(l), batch, hin, dIn(l), 1, dZ, dOut(l), 0, grad + offW(l), dOut(l),
              nullptr, s);
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)dOut(l)), dim3(256), 0, s, batch,
+        LAUNCH("k_colsum", k_colsum, dim3((unsigned)dOut(l)), dim3(256), 0, s, batch,
                            (int64_t)dOut(l), dZ, grad + offB(l));
         if (l == 1) break;
-        // dH_{l-1} = dZ W^T, then through SiLU
+        // dH_{l-1} = dZ W^T, then through the activation
         float* dst = (dZ == t.dZ) ? t.dH : t.dZ;
         gemm(batch, dIn(l), dOut(l), dZ, dOut(l), 0, master + offW(l), dOut(l), 1, dst, dIn(l),
              nullptr, s);
         const int64_t n = batch * kDH;
-        hipLaunchKernelGGL(k_silu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+        LAUNCH("k_act_bwd", k_act_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                            t.Z[l - 1], dst);
         dZ = dst;
     }
@@ -551,7 +579,7 @@ axpic_status axpic_mlp_adam(float* master, const float* grad, float* m, float* v
                             float lr, float beta1, float beta2, float eps, void* stream) {
     if (!master || !grad || !m || !v || step < 1) return AXPIC_E_INVAL;
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((kNParams + 255) / 256)), dim3(256), 0, S(stream),
+    LAUNCH("k_adam", k_adam, dim3((unsigned)((kNParams + 255) / 256)), dim3(256), 0, S(stream),
                        (int64_t)kNParams, master, grad, m, v, lr, beta1, beta2, eps, c1, c2);
     return launched();
 }
@@ -574,6 +602,7 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
     for (int i = 0; i < 4; ++i) {
         mc.feat_lo[i] = net->feat_lo[i]; mc.feat_sc[i] = net->feat_sc[i];
         mc.out_mu[i] = net->out_mu[i]; mc.out_sigma[i] = net->out_sigma[i];
+        for (int j = 0; j < 4; ++j) mc.out_lin[i][j] = net->out_lin[i][j];
     }
     mc.T_lo = net->T_lo; mc.T_hi = net->T_hi; mc.ne_lo = net->ne_lo; mc.ne_hi = net->ne_hi;
     mc.x_lo = net->x_lo; mc.x_hi = net->x_hi;
@@ -590,14 +619,14 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
     const int64_t wgs = std::min<int64_t>((tiles + 7) / 8, (int64_t)ncu);
     const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
     if (sp->dtype == AXPIC_F32)
-        hipLaunchKernelGGL(k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+        LAUNCH("k_rates_mlp", k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
                            S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
                            lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
                            (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
                            (const float*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
                            (float*)out, n_fallback);
     else
-        hipLaunchKernelGGL(k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+        LAUNCH("k_rates_mlp", k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
                            S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
                            lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
                            (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],

@@ -111,7 +111,7 @@ def _small_plasma(T=3.0, ne=6e25, **pk):
 def trained():
     S = Surrogate(I.Params(), seed=0)
     t0 = time.time()
-    log = S.train(n_samples=1_000_000, steps=4000, batch=4096, lr=2e-3, lr_end=3e-5, seed=1,
+    log = S.train(n_samples=1_000_000, steps=20000, batch=4096, lr=2e-3, lr_end=2e-5, seed=1,
                   log=lambda s: print(s, flush=True))
     torch.cuda.synchronize()
     print(f"[surrogate] trained in {time.time() - t0:.1f} s, final loss {log[-1][1]:.3e}", flush=True)
@@ -131,15 +131,16 @@ def test_inference_kernel_reproduces_training_forward(trained):
     om = 510.99895 * np.sqrt((ph["p"].astype(np.float64) ** 2).sum(axis=0))
     feat = np.stack([np.log(om / Tc), 0.5 * np.log(k2) - np.log(Tc), np.log(nec),
                      np.full(om.size, 1.0)], axis=1)
-    n = om.size - om.size % 32
-    X = np.zeros((n, 32), dtype=np.float32)
-    X[:, :4] = (feat[:n] - S.norm["lo"]) * S.norm["sc"] - 1.0
-    X[:, 4] = 1.0
-    y = S.forward(torch.from_numpy(X).cuda()).double().cpu().numpy()
-    G = 1e-20 * 1e33 * np.exp(S.norm["mu"][0] + S.norm["sigma"][0] * y) * (0.1 / g.grid_d["omega0"])
-    lam_ref = ph["w"][:n] * (g.ph.w_ref / (g.pdict["w_a"] * g.pdict["wa_mul"][0])) * -np.expm1(-G)
-    inside = (om[:n] / Tc[:n] > 0.01) & (om[:n] / Tc[:n] < 100)
-    rel = np.abs(np.log(lam_mlp[:n][inside]) - np.log(lam_ref[inside]))
+    n = om.size
+    logR = S.predict_log(torch.from_numpy(feat).cuda(),
+                         torch.zeros(n, dtype=torch.int32, device="cuda")).cpu().numpy()
+    G = 1e-20 * 1e33 * np.exp(logR) * (0.1 / g.grid_d["omega0"])
+    lam_ref = ph["w"] * (g.ph.w_ref / (g.pdict["w_a"] * g.pdict["wa_mul"][0])) * -np.expm1(-G)
+    inside = (om / Tc > 0.01) & (om / Tc < 100)
+    assert inside.mean() > 0.9
+    rel = np.abs(np.log(lam_mlp[inside]) - np.log(lam_ref[inside]))
+    print(f"[surrogate] inference vs training forward: median |d log lambda| {np.median(rel):.2e}, "
+          f"max {rel.max():.2e}", flush=True)
     assert np.median(rel) < 2e-3 and rel.max() < 5e-2 * S.norm["sigma"][0]
 
 
@@ -150,21 +151,15 @@ def test_trained_surrogate_matches_oracle_rates(trained):
     ref, lk = M.labels(p, T, ne, Z, x, ch)
     keep = np.isfinite(ref)                                 # brems with a zero screening factor
     T, ne, Z, x, ch, ref, lk = (a[keep] for a in (T, ne, Z, x, ch, ref, lk))
-    n = ref.size - ref.size % 32
-    T, ne, Z, x, ch, ref, lk = (a[:n] for a in (T, ne, Z, x, ch, ref, lk))
     feat = np.stack([np.log(x), lk, np.log(ne), Z], axis=1)
-    X = np.zeros((n, 32), dtype=np.float32)
-    X[:, :4] = (feat - S.norm["lo"]) * S.norm["sc"] - 1.0
-    X[np.arange(n), 4 + ch] = 1.0
-    y = S.forward(torch.from_numpy(X).cuda()).double().cpu().numpy()
-    pred = S.norm["mu"][ch] + S.norm["sigma"][ch] * y
+    pred = S.predict_log(torch.from_numpy(feat).cuda(), torch.from_numpy(ch).cuda()).cpu().numpy()
     err = pred - ref
     for c in range(4):
         e = err[ch == c]
         print(f"[surrogate] channel {c}: rms log-rate error {np.sqrt(np.mean(e * e)):.2e}, "
               f"max {np.abs(e).max():.2e}", flush=True)
-        assert np.sqrt(np.mean(e * e)) < 0.03
-        assert abs(np.mean(e)) < 0.01
+        assert np.sqrt(np.mean(e * e)) < 0.02
+        assert abs(np.mean(e)) < 0.005
 
 
 def test_surrogate_power_within_one_percent_and_gain_reported(trained):

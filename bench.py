@@ -40,6 +40,8 @@ ALG_BYTES = {
     "k_bin": ("axion", 36),              # x, p read; x, cell written (2D)
 }
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "hbm_traffic_step_cfg2_512x512.txt")
 BF16_PEAK_TFLOPS = 2500.0           # dense BF16 MFMA
 # live multiply-adds of the 8-128-128-128-128-1 network, two FLOP each
 MLP_FLOP_PER_EVAL = 2 * (8 * 128 + 3 * 128 * 128 + 128)
@@ -135,6 +137,7 @@ def main():
     import torch
     from paper_2604_24627_amd import inputs as I
     from paper_2604_24627_amd import axpic as B
+    from paper_2604_24627_amd import profsum
     from paper_2604_24627_amd.sim import AxpicSim
 
     wl = workload(a.cells)
@@ -187,10 +190,14 @@ def main():
     units = float(np.mean(n_units[unit]))
     achieved = units * bpu / (avg_ms * 1e-3) / 1e9
     copy_bw = stream_copy_gbps(torch, B)
+    # HBM bytes per launch of that kernel from the committed FETCH_SIZE / WRITE_SIZE summary
+    # of this workload (None when the kernels have changed since it was taken)
+    tr = profsum.read_traffic(TRAFFIC_SUMMARY, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": None, "avg_ms": round(avg_ms, 5), "units_per_launch": units,
-                "bytes_per_unit": bpu, "stream_copy_GBps": round(copy_bw, 1)}
+                "traffic": (tr[0] + tr[1]) if tr else None, "avg_ms": round(avg_ms, 5),
+                "units_per_launch": units, "bytes_per_unit": bpu,
+                "stream_copy_GBps": round(copy_bw, 1)}
 
     # ---- power of the plain run
     hist = sim.hist_np()

@@ -34,6 +34,7 @@ namespace {
 constexpr int kThreads = 256;          // threads per workgroup
 constexpr int kPer = 4;                // parents per thread in the count/apply kernels
 constexpr int kBlockParents = kThreads * kPer;
+static_assert(kPer == 4, "k_expand unpacks four 16-bit codes per thread");
 constexpr int kStatSlots = 12;         // per-thread statistics registers
 constexpr int kMaxBins = 1024;         // histogram bins per channel (+2 under/overflow)
 constexpr int kCopies = 32;            // privatised accumulator copies (histogram + statistics)
@@ -93,6 +94,8 @@ KParams make_kparams(const axpic_grid* g, const axpic_params* prm, double w_ref_
                     : 0.0;
     k.brems_k = prm->brems_k;
     k.brems_theta = prm->brems_theta;
+    k.brems_km3 = prm->brems_k - 3.0;
+    k.brems_c1 = 1.0 - 1.0 / prm->brems_theta;
     k.nbins = prm->hist_nbins;
     k.hist_log = prm->hist_log;
     k.hist_lo = prm->hist_lo_keV;
@@ -266,49 +269,62 @@ __device__ __forceinline__ void stats_flush(const double* st, bool any, double* 
 
 // ------------------------------------------------------------------ scan kernel
 // One workgroup: exclusive offsets of the block product counts, capacity check.
-// The block totals are staged through LDS in tiles (coalesced loads and
-// stores); each thread scans a contiguous run of a tile.
-constexpr int kScanTile = 8192;
-constexpr int kScanPer = kScanTile / kScanThreads;
+// Each thread scans 16 consecutive block totals held in registers (four
+// 16-byte loads, eight 16-byte stores); a tile covers 16384 blocks.
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
 
 __global__ void __launch_bounds__(kScanThreads)
 k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t nb,
-       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status,
-       double* __restrict__ acc, int acc_used) {
-    __shared__ uint32_t tin[kScanTile];
-    __shared__ uint64_t tout[kScanTile];
+       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status) {
     __shared__ uint64_t wsum[kScanThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    if (acc)
-        for (int j = t; j < kCopies * acc_used; j += kScanThreads)
-            acc[(int64_t)(j / acc_used) * kAccStride + j % acc_used] = 0.0;
     uint64_t carry = 0;
     for (int64_t t0 = 0; t0 < nb; t0 += kScanTile) {
-        const int cnt = (int)std::min<int64_t>(kScanTile, nb - t0);
-        for (int j = t; j < kScanTile; j += kScanThreads) tin[j] = j < cnt ? bsum[t0 + j] : 0u;
-        __syncthreads();
-        uint64_t s = 0;
-        for (int q = 0; q < kScanPer; ++q) s += tin[t * kScanPer + q];
-        uint64_t inc = s;
+        const int64_t b0 = t0 + (int64_t)t * kScanPer;
+        uint32_t v[kScanPer];
+        if (b0 + kScanPer <= nb) {
+            const uint4* src = (const uint4*)(bsum + b0);
+#pragma unroll
+            for (int q = 0; q < kScanPer / 4; ++q) {
+                const uint4 u = src[q];
+                v[4 * q] = u.x; v[4 * q + 1] = u.y; v[4 * q + 2] = u.z; v[4 * q + 3] = u.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kScanPer; ++q) v[q] = b0 + q < nb ? bsum[b0 + q] : 0u;
+        }
+        uint64_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) sum += v[q];
+        uint64_t inc = sum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            uint64_t v = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += v;
+            const uint64_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
         }
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
         uint64_t base = 0, tot = 0;
+#pragma unroll
         for (int w = 0; w < kScanThreads / 64; ++w) {
-            if (w < wave) base += wsum[w];
-            tot += wsum[w];
+            const uint64_t ws = wsum[w];
+            if (w < wave) base += ws;
+            tot += ws;
         }
-        uint64_t run = carry + base + inc - s;
-        for (int q = 0; q < kScanPer; ++q) {
-            tout[t * kScanPer + q] = run;
-            run += tin[t * kScanPer + q];
+        uint64_t run = carry + base + inc - sum;
+        uint64_t o[kScanPer];
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) { o[q] = run; run += v[q]; }
+        if (b0 + kScanPer <= nb) {
+            ulonglong2* dst = (ulonglong2*)(boff + b0);
+#pragma unroll
+            for (int q = 0; q < kScanPer / 2; ++q) dst[q] = make_ulonglong2(o[2 * q], o[2 * q + 1]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < kScanPer; ++q)
+                if (b0 + q < nb) boff[b0 + q] = o[q];
         }
-        __syncthreads();
-        for (int j = t; j < cnt; j += kScanThreads) boff[t0 + j] = tout[j];
         carry += tot;
         __syncthreads();
     }
@@ -323,6 +339,16 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
             status[3] = 0;
         }
     }
+}
+
+// Clears the used part of the privatised accumulator copies; every count
+// kernel's grid does it for the events kernel that follows it on the stream.
+__device__ __forceinline__ void clear_acc(double* __restrict__ acc, int acc_n) {
+    if (!acc) return;
+    const int64_t total = (int64_t)kCopies * acc_n;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x)
+        acc[(j / acc_n) * kAccStride + j % acc_n] = 0.0;
 }
 
 // Fixed-order sum of the accumulator copies into hist[3][nbh] and stats[].
@@ -456,7 +482,7 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
     } else if (mode == 2) {                // electrons, brems
         r = wt * pc[5];
     } else if (mode == 3) {                // axions, thermal absorption probability
-        r = wt > (T)0 ? pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(psq<T>(px, py, pz, i))) : (T)0;
+        r = wt > (T)0 ? pabs_thermal<T>(kp, pc, energy_keV(psq<T>(px, py, pz, i))) : (T)0;
     } else {                               // axions, a->gamma mean
         r = wt > (T)0 ? lambda_ag<T>(kp, pc, wt, psq<T>(px, py, pz, i)) : (T)0;
     }
@@ -470,21 +496,31 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
-             uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
+             uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
+              double* __restrict__ acc, int acc_n) {
+    clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
-    // all loads of the thread's parents first (clamped index), then the arithmetic
+    // all loads of the thread's parents first (clamped index), then their cells'
+    // prefactor records, then the arithmetic
     T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
     int32_t cv[kPer];
+    uint64_t idv[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
         const int64_t ii = i < n ? i : n - 1;
         wv[j] = w[ii];
+        idv[j] = id(ii);
         if (lam_in) { lv[j] = lam_in[ii]; }
         else { xv[j] = px[ii]; yv[j] = py[ii]; zv[j] = pz[ii]; cv[j] = cell[ii]; }
+    }
+    T pcv[kPer][4];
+    if (!lam_in) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -494,13 +530,13 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         T l = (T)0;
         if (wt > (T)0)
             l = lam_in ? lv[j]
-                       : lambda_primakoff<T>(pref + (int64_t)cv[j] * AXPIC_PREF_N, wt,
+                       : lambda_primakoff<T>(pcv[j], wt,
                                              xv[j] * xv[j] + yv[j] * yv[j] + zv[j] * zv[j]);
         int K = 0;
         if (l > (T)0) {
             double ws; int cp;
             const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
-            const uint4 r = draw(kp, id(i), step, 0, 0);
+            const uint4 r = draw(kp, idv[j], step, 0, 0);
             K = poisson_inv(le, u53(r.x, r.y));
         }
         code[i] = (uint16_t)K;
@@ -524,21 +560,32 @@ k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t*
          int64_t out_cap, uint64_t* __restrict__ rec) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
-    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
-    uint64_t run = boff[blockIdx.x];
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        const uint32_t cd = (i < n) ? code[i] : 0u;
-        // mode 0: one channel (count in bits 0-7); mode 1: Compton bits 0-7, brems 8-15
-        const uint32_t K0 = cd & 0xFFu, K1 = mode == 1 ? (cd >> 8) : 0u;
-        uint32_t segtot;
-        const uint32_t pre = block_excl_scan(K0 + K1, lds, &segtot);
-        int64_t slot = out_n + (int64_t)(run + pre);
+    // each thread takes kPer consecutive parents: one 8-byte load of their codes and one
+    // block scan keep the records in parent order
+    const int64_t i0 = (int64_t)blockIdx.x * kBlockParents + (int64_t)kPer * threadIdx.x;
+    uint32_t cd[kPer];
+    if (i0 + kPer <= n) {
+        const uint2 u = *(const uint2*)(code + i0);
+        cd[0] = u.x & 0xFFFFu; cd[1] = u.x >> 16; cd[2] = u.y & 0xFFFFu; cd[3] = u.y >> 16;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) cd[q] = i0 + q < n ? code[i0 + q] : 0u;
+    }
+    // mode 0: one channel (count in bits 0-7); mode 1: Compton bits 0-7, brems 8-15
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) cnt += (cd[q] & 0xFFu) + (mode == 1 ? (cd[q] >> 8) : 0u);
+    uint32_t segtot;
+    const uint32_t pre = block_excl_scan(cnt, lds, &segtot);
+    if (cnt == 0) return;
+    int64_t slot = out_n + (int64_t)(boff[blockIdx.x] + pre);
+    for (int q = 0; q < kPer; ++q) {
+        const uint64_t i = (uint64_t)(i0 + q);
+        const uint32_t K0 = cd[q] & 0xFFu, K1 = mode == 1 ? (cd[q] >> 8) : 0u;
         for (uint32_t k = 0; k < K0; ++k, ++slot)
-            if (slot < out_cap) rec[slot] = (uint64_t)i | ((uint64_t)k << 40) | ((uint64_t)(mode == 1 ? 1 : 0) << 48);
+            if (slot < out_cap) rec[slot] = i | ((uint64_t)k << 40) | ((uint64_t)(mode == 1 ? 1 : 0) << 48);
         for (uint32_t k = 0; k < K1; ++k, ++slot)
-            if (slot < out_cap) rec[slot] = (uint64_t)i | ((uint64_t)k << 40) | (2ull << 48);
-        run += segtot;
+            if (slot < out_cap) rec[slot] = i | ((uint64_t)k << 40) | (2ull << 48);
     }
 }
 
@@ -620,7 +667,9 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
               const double* __restrict__ p64, const T* __restrict__ w,
               IdView id, const int32_t* __restrict__ cell,
               const T* __restrict__ lam_in, uint16_t* __restrict__ code,
-              uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact) {
+              uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
+              double* __restrict__ acc, int acc_n) {
+    clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
@@ -739,15 +788,18 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
-            uint32_t* __restrict__ bact) {
+            uint32_t* __restrict__ bact,
+              double* __restrict__ acc, int acc_n) {
+    clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
     const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
-    T wv[kPer], p2v[kPer];
+    T wv[kPer], p2v[kPer], Pv[kPer], lv[kPer];
     int32_t cv[kPer];
+    uint64_t idv[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
@@ -755,7 +807,13 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         wv[j] = w[ii];
         p2v[j] = psq<T>(px, py, pz, ii);
         cv[j] = cell[ii];
+        idv[j] = id(ii);
+        Pv[j] = pabs_in ? pabs_in[ii] : (T)0;
+        lv[j] = lam_in ? lam_in[ii] : (T)0;
     }
+    T pcv[kPer][AXPIC_PREF_N];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 2);
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
@@ -763,11 +821,11 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         T wt = wv[j];
         uint32_t cd = 0;
         if (wt > (T)0) {
-            const T* pc = pref + (int64_t)cv[j] * AXPIC_PREF_N;
+            const T* pc = pcv[j];
             const T p2 = p2v[j];
-            const uint4 r = draw(kp, id(i), step, 4, 0);
+            const uint4 r = draw(kp, idv[j], step, 4, 0);
             if (thermal) {
-                const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
+                const T P = pabs_in ? Pv[j] : pabs_thermal<T>(kp, pc, energy_keV(p2));
                 if (kp.absorb_mode == 0) {
                     if (u53(r.x, r.y) < (double)P) { cd |= 256u; wt = (T)0; }
                 } else {
@@ -775,7 +833,7 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
                 }
             }
             if (a2g && wt > (T)0) {
-                const T l = lam_in ? lam_in[i] : lambda_ag<T>(kp, pc, wt, p2);
+                const T l = lam_in ? lv[j] : lambda_ag<T>(kp, pc, wt, p2);
                 double ws; int cp;
                 cd |= (uint32_t)poisson_inv(cap_lambda((double)l, kp.cap, &ws, &cp), u53(r.z, r.w));
             }
@@ -838,7 +896,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                 double dw = 0.0;
                 if (cd & 256u) dw = wphys;
                 else if (kp.absorb_mode == 1) {
-                    const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, (T)kMe * dev_sqrt<T>(p2));
+                    const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, energy_keV(p2));
                     dw = wphys * (double)P;
                     wt = (T)((wphys - dw) / w_ref_a);
                 }
@@ -1125,9 +1183,9 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_prim_count", k_prim_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
-                       W.code, W.bsum, W.bact);
+                       W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status, W.acc, acc_used(kp));
+                       ax->capacity, W.ctrl, status);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     LAUNCH("k_prim_events", k_prim_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
@@ -1148,9 +1206,9 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact);
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status, W.acc, acc_used(kp));
+                       ax->capacity, W.ctrl, status);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     LAUNCH("k_therm_events", k_therm_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
@@ -1172,10 +1230,10 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
     LAUNCH("k_abs_count", k_abs_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
                        TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact);
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
-                       out_cap, W.ctrl, status, W.acc, acc_used(kp));
+                       out_cap, W.ctrl, status);
     LAUNCH("k_abs_apply", k_abs_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
                        kp, ax->w_ref, cells->pref32, cells->pref64, TP<T>(ax->w), TCP<T>(ax->x[0]),
                        TCP<T>(ax->x[1]), TCP<T>(ax->x[2]), TCP<T>(ax->p[0]), TCP<T>(ax->p[1]),
@@ -1432,7 +1490,7 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     LAUNCH("k_live_count", k_live_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n,              \
                        (const T*)in->w, W.code, W.bsum, W.bact);                                   \
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, (int64_t)0, \
-                       out->capacity, W.ctrl, status, (double*)nullptr, 0);                                             \
+                       out->capacity, W.ctrl, status);                                             \
     LAUNCH("k_compact_apply", k_compact_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, W.code,   \
                        W.boff, W.ctrl, out->capacity, ndim, (const T*)in->x[0],                   \
                        (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],                \

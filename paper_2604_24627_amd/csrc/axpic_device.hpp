@@ -37,6 +37,7 @@ struct KParams {
     double ag_unit;             // inv_ratio * w_a^2 * wa_mul0 / (w_ref_g * w_gamma_prod)
     double inv_ratio;
     double brems_k, brems_theta;
+    double brems_km3, brems_c1;  // k - 3 and 1 - 1/theta of the brems absorption shape
     double hist_lo, hist_scale; // bin = floor(scale * log(E/lo)) or floor(scale * (E - lo))
     double r_relax, T_floor, T_ceil;
     double dtdx;
@@ -103,22 +104,48 @@ __device__ __forceinline__ double cap_lambda(double lam, double cap, double* ws,
     return le;
 }
 
+// ---------------------------------------------------------------- fast FP32 functions
+// The per-particle FP32 rates are bound by vector instructions; they use the
+// hardware log2, exp2, reciprocal and square root (v_log_f32, v_exp_f32,
+// v_rcp_f32, v_sqrt_f32, about one ulp) and short Taylor series where a closed
+// form would cancel.  Relative error of each rate below 5e-6 (the FP64 paths
+// keep the correctly rounded library functions).
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// 1 - e^{-y} for y >= 0: Taylor series below 1/4, else through exp2
+__device__ __forceinline__ float f_1mexp(float y) {
+    if (y < 0.25f) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 8; k >= 1; --k) {
+            float f = 1.0f;
+            for (int q = 2; q <= k; ++q) f *= (float)q;
+            a = a * y + ((k & 1) ? 1.0f : -1.0f) / f;
+        }
+        return a * y;
+    }
+    return 1.0f - fexp(-y);
+}
+
 // ---------------------------------------------------------------- screening F(s)
-// F(s) = (1 + 1/s) ln(1 + s) - 1 (eq. prim_F).  Below s = 1/2 (single) or
+// F(s) = (1 + 1/s) ln(1 + s) - 1 (eq. prim_F).  Below s = 0.35 (single) or
 // 1/100 (double) the closed form cancels; its series
 // sum_{n>=1} (-1)^{n+1} s^n / (n (n+1)) is used instead.
 __device__ __forceinline__ float screenF(float s) {
     if (!(s > 0.0f)) return 0.0f;
-    if (s < 0.5f) {
+    if (s < 0.35f) {
         float acc = 0.0f;
 #pragma unroll
-        for (int n = 22; n >= 1; --n) {
+        for (int n = 16; n >= 1; --n) {
             const float c = ((n & 1) ? 1.0f : -1.0f) / (float)(n * (n + 1));
             acc = acc * s + c;
         }
         return acc * s;
     }
-    return (1.0f + 1.0f / s) * log1pf(s) - 1.0f;
+    return (1.0f + frcp(s)) * flog(1.0f + s) - 1.0f;
 }
 __device__ __forceinline__ double screenF(double s) {
     if (!(s > 0.0)) return 0.0;
@@ -136,8 +163,17 @@ __device__ __forceinline__ double screenF(double s) {
 
 // (1 - e^-x)/x, accurate for tiny (or underflowed) x.
 __device__ __forceinline__ float one_minus_exp_over(float x) {
-    if (x < 1e-3f) return 1.0f - 0.5f * x + x * x * (1.0f / 6.0f);
-    return -expm1f(-x) / x;
+    if (x < 0.25f) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 8; k >= 0; --k) {
+            float f = 1.0f;
+            for (int q = 2; q <= k + 1; ++q) f *= (float)q;
+            a = a * x + ((k & 1) ? -1.0f : 1.0f) / f;
+        }
+        return a;
+    }
+    return f_1mexp(x) * frcp(x);
 }
 __device__ __forceinline__ double one_minus_exp_over(double x) {
     if (x < 1e-5) return 1.0 - 0.5 * x + x * x * (1.0 / 6.0);
@@ -263,6 +299,23 @@ template <typename T> struct PrefOf;
 template <> struct PrefOf<float> { static __device__ const float* get(const float* p32, const double*) { return p32; } };
 template <> struct PrefOf<double> { static __device__ const double* get(const float*, const double* p64) { return p64; } };
 
+// A cell's prefactor record (AXPIC_PREF_N = 8 entries, 32-byte aligned in FP32,
+// 64-byte in FP64) into registers with 16-byte loads: the count kernels load
+// all their parents' records before the arithmetic instead of one dependent
+// load chain per parent.
+__device__ __forceinline__ void load_pref(const float* __restrict__ rec, float* out, int nq) {
+    for (int q = 0; q < nq; ++q) {
+        const float4 v = ((const float4*)rec)[q];
+        out[4 * q] = v.x; out[4 * q + 1] = v.y; out[4 * q + 2] = v.z; out[4 * q + 3] = v.w;
+    }
+}
+__device__ __forceinline__ void load_pref(const double* __restrict__ rec, double* out, int nq) {
+    for (int q = 0; q < 2 * nq; ++q) {
+        const double2 v = ((const double2*)rec)[q];
+        out[2 * q] = v.x; out[2 * q + 1] = v.y;
+    }
+}
+
 // lambda_P = w P_{gamma->a} / w_prod with P = 1 - exp(-c_P F(s)) (eqs. prim_xs, prim_prob)
 template <typename T>
 __device__ __forceinline__ T lambda_primakoff(const T* __restrict__ pc, T w, T p2) {
@@ -272,26 +325,54 @@ __device__ __forceinline__ T lambda_primakoff(const T* __restrict__ pc, T w, T p
     return w * pc[3] * F * one_minus_exp_over(x);
 }
 
+// Particle energy in keV from |p|^2 (units of m_e c) for the rate functions
+__device__ __forceinline__ float energy_keV(float p2) { return (float)kMe * fsqrt(p2); }
+__device__ __forceinline__ double energy_keV(double p2) { return kMe * sqrt(p2); }
+
 // Thermal absorption probability, eq. gamma_abs: Gamma_abs dt = aC E^2 g_C + aB g_B
 template <typename T>
-__device__ __forceinline__ T pabs_thermal(const KParams& kp, const T* __restrict__ pc, T E) {
-    const T Tk = pc[0];
-    const T x = E / Tk;
-    T g = (T)0;
-    if (pc[6] != (T)0) {
-        T occ = kp.eq_stats ? -dev_expm1<T>(-x) : (T)1;
+__device__ __forceinline__ T pabs_thermal(const KParams& kp, const T* __restrict__ pc, T E);
+
+template <>
+__device__ __forceinline__ float pabs_thermal<float>(const KParams& kp, const float* __restrict__ pc,
+                                                     float E) {
+    const float x = E * frcp(pc[0]);
+    float g = 0.0f;
+    if (pc[6] != 0.0f) {
+        // BE equilibrium: occupation factor 1; MB: 1/(1 - e^{-x})
+        const float e2 = pc[6] * E * E;
+        g += kp.eq_stats ? e2 * frcp(f_1mexp(x)) : e2;
+    }
+    if (pc[7] != 0.0f) {
+        // x^{k-3} e^{x (1 - 1/theta)}, times (1 - e^{-x}) for BE
+        const float l2 = __builtin_amdgcn_logf(x);
+        const float e = __builtin_amdgcn_exp2f((float)kp.brems_km3 * l2 +
+                                               (float)kp.brems_c1 * x * 1.44269504088896f);
+        g += pc[7] * e * (kp.eq_stats ? 1.0f : f_1mexp(x));
+    }
+    return f_1mexp(g);
+}
+
+template <>
+__device__ __forceinline__ double pabs_thermal<double>(const KParams& kp, const double* __restrict__ pc,
+                                                       double E) {
+    const double Tk = pc[0];
+    const double x = E / Tk;
+    double g = 0.0;
+    if (pc[6] != 0.0) {
+        double occ = kp.eq_stats ? -expm1(-x) : 1.0;
         g += pc[6] * E * E / occ;
     }
-    if (pc[7] != (T)0) {
-        const T th = (T)kp.brems_theta, k = (T)kp.brems_k;
-        const T pw = dev_exp<T>((k - (T)3) * dev_log<T>(x));
+    if (pc[7] != 0.0) {
+        const double th = kp.brems_theta, k = kp.brems_k;
+        const double pw = exp((k - 3.0) * log(x));
         // MB: e^{x(1-1/theta)}; BE: e^{-x/theta} (e^x - 1), with expm1 for small x
-        T shape;
-        if (kp.eq_stats || x > (T)60) shape = dev_exp<T>(x * ((T)1 - (T)1 / th));
-        else shape = dev_exp<T>(-x / th) * dev_expm1<T>(x);
+        double shape;
+        if (kp.eq_stats || x > 60.0) shape = exp(x * (1.0 - 1.0 / th));
+        else shape = exp(-x / th) * expm1(x);
         g += pc[7] * pw * shape;
     }
-    return -dev_expm1<T>(-g);
+    return -expm1(-g);
 }
 
 // a->gamma mean: w_a-weight * (w_a/w_gamma_prod) * (1 - exp(-ratio c_P F))

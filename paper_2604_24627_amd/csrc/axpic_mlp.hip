@@ -458,6 +458,8 @@ KParams kparams_for(const axpic_grid* g, const axpic_params* prm, double w_ref_g
                     : 0.0;
     k.brems_k = prm->brems_k;
     k.brems_theta = prm->brems_theta;
+    k.brems_km3 = prm->brems_k - 3.0;
+    k.brems_c1 = 1.0 - 1.0 / prm->brems_theta;
     k.channels = prm->channels;
     k.inverse = prm->inverse;
     k.eq_stats = prm->eq_stats;

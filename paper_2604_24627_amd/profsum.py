@@ -2,14 +2,56 @@
 
 kernel_stats(csv)        -> {kernel: (calls, avg_ns)}   from --kernel-trace --stats
 counters(csv)            -> {kernel: [value per dispatch]} from --pmc <counter>
+source_digest()          -> SHA-256 of the HIP sources (csrc/), which names the
+                            kernels a set of counters was taken from
+read_traffic(path)       -> the per-dispatch HBM bytes recorded in a summary,
+                            or None when the kernels have changed since
 Kernel names are reduced to the bare function name (k_...).
+
+Usage: python -m paper_2604_24627_amd.profsum <kernel_stats.csv> [<fetch.csv>
+<write.csv> <copy_bytes>] -- prints the table; the FETCH_SIZE / WRITE_SIZE
+medians (KiB per dispatch) are scaled so that k_stream_copy of copy_bytes reads
+and writes copy_bytes, and a "traffic" line per kernel is printed with the
+source digest for read_traffic.
 """
 from __future__ import annotations
 
 import csv
+import hashlib
+import os
 import re
 import statistics
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_digest(root: str = CSRC) -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(root)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(root, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def read_traffic(path: str, kernel: str):
+    """(fetch_bytes, write_bytes) per dispatch of `kernel` from a summary written
+    by main(), if its source digest matches the current sources."""
+    if not os.path.exists(path):
+        return None
+    digest, found = None, None
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 2 and t[0] == "source_sha256":
+                digest = t[1]
+            if len(t) == 4 and t[0] == "traffic" and t[1] == kernel:
+                found = (float(t[2]), float(t[3]))
+    if digest != source_digest() or found is None:
+        return None
+    return found
 
 
 def short(name: str) -> str:
@@ -58,6 +100,13 @@ def main(argv):
         wm = statistics.median(write[k]) * 1024 * scale_w / 1e6 if k in write else float("nan")
         print(f"{k:24s} {c:6d} {a / 1e3:10.2f} {fm:10.2f} {wm:10.2f}")
     print(f"counter scale (copy-calibrated): fetch x{scale_f:.4f} write x{scale_w:.4f}")
+    if fetch and write:
+        print("per-dispatch HBM bytes (kernel fetch write):")
+        for k in sorted(k for k in set(fetch) & set(write) if k.startswith("k_")):
+            fb = statistics.median(fetch[k]) * 1024 * scale_f
+            wb = statistics.median(write[k]) * 1024 * scale_w
+            print(f"traffic {k} {fb:.6g} {wb:.6g}")
+        print(f"source_sha256 {source_digest()}")
 
 
 if __name__ == "__main__":

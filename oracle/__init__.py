@@ -111,6 +111,9 @@ def _declare(L):
     L.or_emit_primakoff.argtypes = [_P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P]
     L.or_emit_thermal.restype = C.c_int64
     L.or_emit_thermal.argtypes = [_P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P, _P]
+    L.or_emit_thermal_cells.restype = C.c_int64
+    L.or_emit_thermal_cells.argtypes = [_P, _P, _P, _P, _P, C.c_int64, _P, _P, C.c_int64,
+                                        C.c_uint64, _P, _P, _P, _P, _P, _P]
     L.or_absorb.restype = C.c_int64
     L.or_absorb.argtypes = [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P,
                             _P, _P]
@@ -383,6 +386,34 @@ def emit_thermal(grid, params, cells, el: OSpecies, step, next_id, fb=None, hist
                             _ref(PS), _ptr(fb), _ptr(hist), _ptr(stats), _ptr(lam_out), _ptr(K_out))
     assert got == need, (got, need)
     return prod.trimmed(got), lam_out[:2 * n].reshape(2, n), K_out[:2 * n].reshape(2, n)
+
+
+SUP_TOO_LARGE = -(1 << 62)
+
+
+def emit_thermal_cells(grid, params, cells, el: OSpecies, off, step, next_id, fb=None, hist=None,
+                       stats=None, coef_in=None, W_in=None):
+    """Thermal emission by per-cell superposition (or_emit_thermal_cells).
+    Returns (products, Lambda [2, ncell], N [2, ncell]); raises ValueError when a
+    cell's mean exceeds the sampler's range."""
+    L = load(); G = make_grid(grid); P = make_params(params)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    ncell = off.size - 1
+    lam = np.zeros(max(2 * ncell, 1)); N = np.zeros(max(2 * ncell, 1), np.int32)
+    ci = None if coef_in is None else np.ascontiguousarray(coef_in, dtype=np.float64).reshape(-1)
+    wi = None if W_in is None else np.ascontiguousarray(W_in, dtype=np.float64)
+    S = el.struct()
+    r = L.or_emit_thermal_cells(_ref(G), _ref(P), _ptr(cells), _ref(S), _ptr(off), ncell, _ptr(ci),
+                                _ptr(wi), step, next_id, None, None, None, None, None, None)
+    if r == SUP_TOO_LARGE:
+        raise ValueError("a cell's superposed mean exceeds 500")
+    prod = OProducts(-r)
+    PS = prod.struct()
+    got = L.or_emit_thermal_cells(_ref(G), _ref(P), _ptr(cells), _ref(S), _ptr(off), ncell,
+                                  _ptr(ci), _ptr(wi), step, next_id, _ref(PS), _ptr(fb), _ptr(hist),
+                                  _ptr(stats), _ptr(lam), _ptr(N))
+    assert got == -r, (got, r)
+    return prod.trimmed(got), lam[:2 * ncell].reshape(2, ncell), N[:2 * ncell].reshape(2, ncell)
 
 
 def absorb(grid, params, cells, ax: OSpecies, step, next_id, fb=None, stats=None, pabs_in=None,

@@ -117,6 +117,20 @@ double or_u24(uint32_t a) {
 
 /* Poisson(lam) by sequential inversion of the CDF (eq. poisson_macro): the
  * smallest k with u < sum_{j<=k} lam^j e^-lam / j!.  Fixed operation order. */
+static int32_t or_poisson_kmax(double lam, double u, int32_t kmax) {
+    if (!(lam > 0.0)) return 0;
+    int32_t k = 0;
+    double p = exp(-lam);
+    double F = p;
+    while (u >= F && k < kmax) {
+        k += 1;
+        p = p * lam;
+        p = p / (double)k;
+        F = F + p;
+    }
+    return k;
+}
+
 int32_t or_poisson(double lam, double u) {
     if (!(lam > 0.0)) return 0;
     int32_t k = 0;
@@ -621,6 +635,140 @@ int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* c
         }
     }
     free(lam); free(K);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermal emission by per-cell superposition.                               */
+/* In a cell the electrons' macro-event counts are independent,              */
+/* K_e ~ Poisson(lambda_e) with lambda_e = w_e coef (eq. lambda_macro), coef  */
+/* = Gamma dt_phys / w_prod per channel.  The same joint law is obtained by  */
+/* drawing the cell's total N ~ Poisson(Lambda), Lambda = sum_e lambda_e (a   */
+/* sum of independent Poisson variables is Poisson) and assigning each of    */
+/* the N events to electron e with probability lambda_e / Lambda (given the  */
+/* sum, the counts are multinomial).  Capped electrons (eqs. lambda_eff,     */
+/* wa_rescaled) enter with min(lambda_e, cap) and their products carry the   */
+/* weight factor lambda_e / cap.  Work is per cell and per event instead of  */
+/* per electron.                                                             */
+/* Electrons are grouped by cell: off[c] .. off[c+1]-1.  coef_in[2 ncell]    */
+/* (Compton, brems) and W_in[ncell] (sum of the cell's weights) replace the  */
+/* computed values when given.  Lambda in a cell is coef W when no electron  */
+/* of the cell reaches the cap, else the sum of min(w_e coef, cap) in index  */
+/* order; a cell with Lambda > 500 is refused (return OR_SUP_TOO_LARGE).     */
+/* Random numbers: the cell's counts from stream 5 keyed by the cell index   */
+/* (words 0-1 Compton, 2-3 brems); event j of channel ch (1, 2): the         */
+/* electron from stream 6, block (ch-1) 2^23 + j (words 0-1, u53, inverse    */
+/* CDF over the cell's electrons in index order), energy and direction from  */
+/* stream 6 + ch, block j, as the per-electron operator draws them.  Product */
+/* order: cell, then channel, then j.                                        */
+/* ------------------------------------------------------------------------ */
+int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_cell* cells,
+                              const or_species* el, const int64_t* off, int64_t ncell,
+                              const double* coef_in, const double* W_in, int64_t step,
+                              uint64_t next_id, or_products* out, double* fb, double* hist,
+                              double* stats, double* Lambda_out, int32_t* N_out) {
+    const double dtp = or_dt_phys(g);
+    const double wprod[3] = {0.0, prm->w_a * prm->wa_mul[1], prm->w_a * prm->wa_mul[2]};
+    const int on[3] = {0, (prm->channels & OR_CH_C) != 0, (prm->channels & OR_CH_B) != 0};
+    double cap = prm->lambda_cap;
+    if (!(cap <= OR_LAMBDA_HARD_CAP)) cap = OR_LAMBDA_HARD_CAP;
+    double* coef = (double*)malloc(sizeof(double) * (size_t)(2 * ncell + 1));
+    double* Lam = (double*)malloc(sizeof(double) * (size_t)(2 * ncell + 1));
+    int32_t* N = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * ncell + 1));
+    int64_t total = 0;
+    int too_large = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        double W = 0.0, wmax = 0.0;
+        for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+            W += el->w[e];
+            if (el->w[e] > wmax) wmax = el->w[e];
+        }
+        if (W_in) W = W_in[c];
+        uint32_t r[4];
+        or_draw(prm->seed, (uint64_t)c, (uint32_t)step, 5, 0, r);
+        for (int ch = 1; ch <= 2; ++ch) {
+            double k = coef_in ? coef_in[(ch - 1) * ncell + c]
+                               : (ch == 1 ? cells[c].G_C : cells[c].G_B) * dtp / wprod[ch];
+            if (!on[ch]) k = 0.0;
+            coef[(ch - 1) * ncell + c] = k;
+            double L;
+            if (!(wmax * k > cap)) L = k * W;
+            else {
+                L = 0.0;
+                for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+                    double le = el->w[e] * k;
+                    L += le < cap ? le : cap;
+                }
+            }
+            if (L > 500.0) too_large = 1;
+            Lam[(ch - 1) * ncell + c] = L;
+            N[(ch - 1) * ncell + c] = or_poisson_kmax(L, ch == 1 ? or_u53(r[0], r[1])
+                                                                 : or_u53(r[2], r[3]), 65535);
+            total += N[(ch - 1) * ncell + c];
+        }
+    }
+    if (Lambda_out) memcpy(Lambda_out, Lam, sizeof(double) * (size_t)(2 * ncell));
+    if (N_out) memcpy(N_out, N, sizeof(int32_t) * (size_t)(2 * ncell));
+    if (too_large) { free(coef); free(Lam); free(N); return OR_SUP_TOO_LARGE; }
+    if (!out || total > out->cap) { free(coef); free(Lam); free(N); return -total; }
+    int64_t rank = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        double W = 0.0, wmax = 0.0;
+        for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+            W += el->w[e];
+            if (el->w[e] > wmax) wmax = el->w[e];
+        }
+        if (W_in) W = W_in[c];
+        for (int ch = 1; ch <= 2; ++ch) {
+            const double k = coef[(ch - 1) * ncell + c];
+            const double L = Lam[(ch - 1) * ncell + c];
+            const int capped_cell = wmax * k > cap;
+            for (int32_t j = 0; j < N[(ch - 1) * ncell + c]; ++j) {
+                uint32_t r[4];
+                or_draw(prm->seed, (uint64_t)c, (uint32_t)step, 6,
+                        (uint32_t)((ch - 1) * (1 << 23) + j), r);
+                /* the electron: inverse CDF of lambda_e / Lambda in index order */
+                const double target = or_u53(r[0], r[1]) * (capped_cell ? L : W);
+                int64_t pick = -1, last = -1;
+                double acc = 0.0;
+                for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+                    if (!(el->w[e] > 0.0)) continue;
+                    double le = el->w[e] * k;
+                    acc += capped_cell ? (le < cap ? le : cap) : el->w[e];
+                    last = e;
+                    if (acc > target) { pick = e; break; }
+                }
+                if (pick < 0) pick = last;
+                const double le = el->w[pick] * k;
+                const int capped = le > cap;
+                const double wp = wprod[ch] * (capped ? le / cap : 1.0);
+                if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
+                or_draw(prm->seed, (uint64_t)c, (uint32_t)step, (uint32_t)(6 + ch), (uint32_t)j, r);
+                double u = or_u24(r[0]);
+                double x = (ch == 1) ? or_compton_x(u)
+                                     : prm->brems_theta * or_gamma_x(prm->brems_k, u);
+                double E = cells[c].T * x;
+                double nh[3];
+                or_isotropic(or_u24(r[1]), or_u24(r[2]), nh);
+                double pm = E / OR_ME_KEV;
+                double p[3] = {pm * nh[0], pm * nh[1], pm * nh[2]};
+                or_put(out, rank, el, pick, p, wp, or_product_id(next_id, rank), ch);
+                ++rank;
+                or_hist_add(hist, prm, ch, E, wp);
+                if (fb) {
+                    double* f = &fb[c * 4];
+                    f[0] -= wp * pm;
+                    f[1] -= wp * p[0]; f[2] -= wp * p[1]; f[3] -= wp * p[2];
+                }
+                if (stats) {
+                    stats[OR_ST_EVENTS_P + ch] += 1.0;
+                    stats[OR_ST_NUM_P + ch] += wp;
+                    stats[OR_ST_EN_P + ch] += wp * E;
+                }
+            }
+        }
+    }
+    free(coef); free(Lam); free(N);
     return total;
 }
 

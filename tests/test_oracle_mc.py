@@ -198,3 +198,79 @@ def test_spectrum_invariant_under_axion_macro_weight():
         z = (res[wa][0] - ref) / res[wa][1]
         assert np.all(np.abs(z) < 5.0), (wa, z)
     assert res[2e-39][1].mean() < res[2e-37][1].mean()
+
+
+def test_superposed_thermal_emission_has_the_per_electron_law():
+    """Per-cell superposition: over many independent steps each electron's event count
+    has mean min(lambda_e, cap) (chi-square over the electrons), the product weights
+    carry lambda_e / cap for capped electrons so that the physical yield per electron
+    is lambda_e w_prod, and a cell's total is Poisson (mean = variance = Lambda)."""
+    wl, pl = small_plasma(T=3.0, ncell=4, ppc=64, channels=6, g_ae=1e-13, w_a=2e-37,
+                          wa_mul=(1.0, 1.0, 0.08), lambda_cap=0.25, boost=1.0, dtype="f64")
+    el = pl["species"]["electrons"]
+    rng = np.random.default_rng(3)
+    el["w"] = el["w"] * rng.lognormal(0.0, 0.5, el["w"].size)     # unequal weights
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    off = el["off"]
+    n = sim.el.n
+    steps = 400
+    counts = np.zeros((2, n))
+    wsum = np.zeros((2, n))
+    Ncell = []
+    lam_ref = None
+    for s in range(steps):
+        prod, Lam, N = O.emit_thermal_cells(sim.grid, sim.params, cells, sim.el, off, s, 10 ** 9)
+        for ch in (1, 2):
+            m = prod["chan"] == ch
+            np.add.at(counts[ch - 1], prod["parent"][m], 1)
+            np.add.at(wsum[ch - 1], prod["parent"][m], prod["w"][m])
+        Ncell.append(N)
+        if lam_ref is None:
+            lam_ref = Lam
+    # per-electron means from the per-electron operator's own rates
+    _, lam_e, _ = O.emit_thermal(sim.grid, sim.params, cells, sim.el, 0, 10 ** 9)
+    cap = 0.25
+    wprod = np.array([wl.params.w_a * wl.params.wa_mul[1], wl.params.w_a * wl.params.wa_mul[2]])
+    for ch in (0, 1):
+        le = np.minimum(lam_e[ch], cap)
+        assert (lam_e[ch] > cap).sum() > 5                       # some electrons capped
+        exp_n = steps * le
+        chi2 = float(((counts[ch] - exp_n) ** 2 / exp_n).sum())
+        dof = n
+        assert abs(chi2 - dof) < 5 * math.sqrt(2 * dof), (ch, chi2, dof)
+        # physical yield per electron: lambda_e w_prod per step, capped ones included
+        yld = wsum[ch] / steps
+        tot_exp = (lam_e[ch] * wprod[ch]).sum()
+        assert yld.sum() == pytest.approx(tot_exp, rel=5 / math.sqrt(counts[ch].sum()))
+    # the cell totals are Poisson with the cell mean
+    Ncell = np.array(Ncell)                     # [steps, 2, ncell]
+    for ch in (0, 1):
+        L = lam_ref[ch]
+        mean = Ncell[:, ch, :].mean(axis=0)
+        var = Ncell[:, ch, :].var(axis=0, ddof=1)
+        assert np.all(np.abs(mean - L) <= 6 * np.sqrt(L / steps)), (mean, L)
+        assert np.all(np.abs(var - L) <= 6 * np.sqrt((L + 2 * L * L) / steps)), (var, L)
+
+
+def test_superposed_thermal_yield_is_unbiased():
+    """The superposed operator emits Q V dt per step and channel, as the per-electron one."""
+    wl, pl = small_plasma(channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=math.inf, boost=1.0)
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    off = pl["species"]["electrons"]["off"]
+    tot = {1: [], 2: []}
+    for s in range(10):
+        prod, _, _ = O.emit_thermal_cells(sim.grid, sim.params, cells, sim.el, off, s, 10 ** 9)
+        E = ME * np.sqrt((prod["p"] ** 2).sum(axis=0))
+        for ch in (1, 2):
+            m = prod["chan"] == ch
+            tot[ch].append(prod["w"][m] * E[m])
+    V = O.V_cell(sim.grid) * wl.ncell
+    dt = O.dt_phys(sim.grid)
+    c = cells[0]
+    for ch, Q in ((1, c["Q_C"]), (2, c["Q_B"])):
+        est = np.mean([t.sum() for t in tot[ch]]) * 1.602176634e-9 / (V * dt)
+        nev = sum(t.size for t in tot[ch])
+        assert nev > 2000
+        assert est == pytest.approx(Q, rel=5 * 1.3 / math.sqrt(nev)), (ch, est / Q)

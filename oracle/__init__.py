@@ -388,14 +388,11 @@ def emit_thermal(grid, params, cells, el: OSpecies, step, next_id, fb=None, hist
     return prod.trimmed(got), lam_out[:2 * n].reshape(2, n), K_out[:2 * n].reshape(2, n)
 
 
-SUP_TOO_LARGE = -(1 << 62)
-
-
 def emit_thermal_cells(grid, params, cells, el: OSpecies, off, step, next_id, fb=None, hist=None,
-                       stats=None, coef_in=None, W_in=None):
+                       stats=None, coef_in=None, W_in=None, counts_only=False):
     """Thermal emission by per-cell superposition (or_emit_thermal_cells).
-    Returns (products, Lambda [2, ncell], N [2, ncell]); raises ValueError when a
-    cell's mean exceeds the sampler's range."""
+    Returns (products, Lambda [2, ncell], N [2, ncell]); products is None with
+    counts_only (nothing is emitted then)."""
     L = load(); G = make_grid(grid); P = make_params(params)
     off = np.ascontiguousarray(off, dtype=np.int64)
     ncell = off.size - 1
@@ -404,9 +401,9 @@ def emit_thermal_cells(grid, params, cells, el: OSpecies, off, step, next_id, fb
     wi = None if W_in is None else np.ascontiguousarray(W_in, dtype=np.float64)
     S = el.struct()
     r = L.or_emit_thermal_cells(_ref(G), _ref(P), _ptr(cells), _ref(S), _ptr(off), ncell, _ptr(ci),
-                                _ptr(wi), step, next_id, None, None, None, None, None, None)
-    if r == SUP_TOO_LARGE:
-        raise ValueError("a cell's superposed mean exceeds 500")
+                                _ptr(wi), step, next_id, None, None, None, None, _ptr(lam), _ptr(N))
+    if counts_only:
+        return None, lam[:2 * ncell].reshape(2, ncell), N[:2 * ncell].reshape(2, ncell)
     prod = OProducts(-r)
     PS = prod.struct()
     got = L.or_emit_thermal_cells(_ref(G), _ref(P), _ptr(cells), _ref(S), _ptr(off), ncell,

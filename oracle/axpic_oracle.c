@@ -654,9 +654,10 @@ int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* c
 /* (Compton, brems) and W_in[ncell] (sum of the cell's weights) replace the  */
 /* computed values when given.  Lambda in a cell is coef W when no electron  */
 /* of the cell reaches the cap, else the sum of min(w_e coef, cap) in index  */
-/* order; a cell with Lambda > 500 is refused (return OR_SUP_TOO_LARGE).     */
-/* Random numbers: the cell's counts from stream 5 keyed by the cell index   */
-/* (words 0-1 Compton, 2-3 brems); event j of channel ch (1, 2): the         */
+/* order.  A mean above 500 is split into m = ceil(Lambda/500) equal parts, */
+/* each drawn by inversion (a sum of independent Poisson variables).         */
+/* Random numbers: the cell's counts from stream 5 keyed by the cell index,  */
+/* block = part (words 0-1 Compton, 2-3 brems); event j of channel ch: the   */
 /* electron from stream 6, block (ch-1) 2^23 + j (words 0-1, u53, inverse    */
 /* CDF over the cell's electrons in index order), energy and direction from  */
 /* stream 6 + ch, block j, as the per-electron operator draws them.  Product */
@@ -676,7 +677,6 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
     double* Lam = (double*)malloc(sizeof(double) * (size_t)(2 * ncell + 1));
     int32_t* N = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * ncell + 1));
     int64_t total = 0;
-    int too_large = 0;
     for (int64_t c = 0; c < ncell; ++c) {
         double W = 0.0, wmax = 0.0;
         for (int64_t e = off[c]; e < off[c + 1]; ++e) {
@@ -684,8 +684,6 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
             if (el->w[e] > wmax) wmax = el->w[e];
         }
         if (W_in) W = W_in[c];
-        uint32_t r[4];
-        or_draw(prm->seed, (uint64_t)c, (uint32_t)step, 5, 0, r);
         for (int ch = 1; ch <= 2; ++ch) {
             double k = coef_in ? coef_in[(ch - 1) * ncell + c]
                                : (ch == 1 ? cells[c].G_C : cells[c].G_B) * dtp / wprod[ch];
@@ -700,16 +698,22 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
                     L += le < cap ? le : cap;
                 }
             }
-            if (L > 500.0) too_large = 1;
             Lam[(ch - 1) * ncell + c] = L;
-            N[(ch - 1) * ncell + c] = or_poisson_kmax(L, ch == 1 ? or_u53(r[0], r[1])
-                                                                 : or_u53(r[2], r[3]), 65535);
-            total += N[(ch - 1) * ncell + c];
+            const int32_t parts = L > 500.0 ? (int32_t)ceil(L / 500.0) : 1;
+            const double Lp = L / (double)parts;
+            int32_t Nc = 0;
+            for (int32_t q = 0; q < parts; ++q) {
+                uint32_t r[4];
+                or_draw(prm->seed, (uint64_t)c, (uint32_t)step, 5, (uint32_t)q, r);
+                Nc += or_poisson_kmax(Lp, ch == 1 ? or_u53(r[0], r[1]) : or_u53(r[2], r[3]),
+                                      1 << 30);
+            }
+            N[(ch - 1) * ncell + c] = Nc;
+            total += Nc;
         }
     }
     if (Lambda_out) memcpy(Lambda_out, Lam, sizeof(double) * (size_t)(2 * ncell));
     if (N_out) memcpy(N_out, N, sizeof(int32_t) * (size_t)(2 * ncell));
-    if (too_large) { free(coef); free(Lam); free(N); return OR_SUP_TOO_LARGE; }
     if (!out || total > out->cap) { free(coef); free(Lam); free(N); return -total; }
     int64_t rank = 0;
     for (int64_t c = 0; c < ncell; ++c) {

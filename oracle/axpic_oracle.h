@@ -123,7 +123,6 @@ int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell*
                           or_species* ph, const double* lam_in, int64_t step,
                           uint64_t next_id, or_products* out, double* hist, double* stats,
                           double* lam_out, int32_t* K_out);
-#define OR_SUP_TOO_LARGE (-((int64_t)1 << 62))
 int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_cell* cells,
                               const or_species* el, const int64_t* off, int64_t ncell,
                               const double* coef_in, const double* W_in, int64_t step,

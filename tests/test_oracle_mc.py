@@ -274,3 +274,23 @@ def test_superposed_thermal_yield_is_unbiased():
         nev = sum(t.size for t in tot[ch])
         assert nev > 2000
         assert est == pytest.approx(Q, rel=5 * 1.3 / math.sqrt(nev)), (ch, est / Q)
+
+
+def test_superposed_cell_count_for_means_above_the_inversion_range():
+    """A cell mean above 500 is drawn as a sum of equal Poisson parts: still Poisson."""
+    wl, pl = small_plasma(T=3.0, ncell=2, ppc=64, channels=2, g_ae=1e-13, w_a=3e-39,
+                          lambda_cap=math.inf, boost=1.0, dtype="f64")
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    off = pl["species"]["electrons"]["off"]
+    Ns, L = [], None
+    for s in range(300):
+        _, Lam, N = O.emit_thermal_cells(sim.grid, sim.params, cells, sim.el, off, s, 10 ** 9,
+                                         counts_only=True)
+        Ns.append(N[0])
+        L = Lam[0]
+    assert np.all(L > 1000) and np.all(L < 4000)
+    Ns = np.array(Ns, dtype=np.float64)
+    mean, var = Ns.mean(axis=0), Ns.var(axis=0, ddof=1)
+    assert np.all(np.abs(mean - L) <= 6 * np.sqrt(L / 300)), (mean, L)
+    assert np.all(np.abs(var - L) <= 6 * np.sqrt((L + 2 * L * L) / 300)), (var, L)

@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--no-superposed", action="store_true",
+                    help="skip the leg with per-cell superposed thermal emission")
     return ap.parse_args()
 
 
@@ -213,6 +215,39 @@ def main():
     del sim
     torch.cuda.empty_cache()
 
+    # ---- the same workload with the thermal channels drawn by per-cell superposition
+    # (same law; the update count is the per-particle definition's, so the rates compare)
+    sup = None
+    if not a.no_superposed:
+        pl = I.make_plasma(wl)
+        sim3 = AxpicSim(pl, wl.params, axion_capacity=est_ax, thermal="cells")
+        del pl
+        for _ in range(a.warmup):
+            sim3.step()
+        torch.cuda.synchronize()
+        upd3 = 0
+        e0.record()
+        for _ in range(a.steps):
+            upd3 += updates_per_step(sim3, sim3.ax.n)
+            sim3.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms3 = e0.elapsed_time(e1)
+        Q_mc3 = q_mc(sim3.hist_np(), sim3.step_index)
+        L.axpic_timing_enable(1)
+        for _ in range(3):
+            sim3.step()
+        torch.cuda.synchronize()
+        kt3 = B.timing_read()
+        L.axpic_timing_enable(0)
+        sup = {"value": upd3 / (ms3 * 1e-3), "unit": "updates/s", "ms_per_step": ms3 / a.steps,
+               "speed_vs_plain": round((upd3 / (ms3 * 1e-3)) / value, 4),
+               "kernel_ms_per_step": {k: round(v[1] / 3, 5) for k, v in sorted(kt3.items())}}
+        print(f"[bench] superposed thermal: {ms3 / a.steps:.3f} ms/step, {sup['value']:.3e} "
+              f"updates/s", file=sys.stderr, flush=True)
+        del sim3
+        torch.cuda.empty_cache()
+
     # ---- surrogate form: trained on the GPU outside the timed region, same workload
     sur = None
     if not a.no_surrogate:
@@ -278,6 +313,8 @@ def main():
         power = {ch: round(Q_mc[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
         if sur is not None:
             sur["power_err"] = {ch: round(Q_mc2[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
+        if sup is not None:
+            sup["power_err"] = {ch: round(Q_mc3[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
         cpu = cpu_baseline(wl, a.cpu_seconds)
 
     out = {
@@ -295,6 +332,7 @@ def main():
         "power_err": power,
         "kernel_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
         "surrogate": sur,
+        "superposed_thermal": sup,
     }
     print(json.dumps(out), flush=True)
 

@@ -226,6 +226,40 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
                                axpic_species* axions, double* fb, double* hist, double* stats,
                                int64_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* axpic_cell_weights -- for the superposed emission below: out[c] = sum of
+ * the relative weights of electrons off[c] .. off[c+1]-1 (FP64, a fixed
+ * reduction order), out[ncell + c] = the largest of them.  The electrons must
+ * be grouped by cell; electron weights do not change during a run (the
+ * feedback remaps momenta), so the result can be kept. */
+axpic_status axpic_cell_weights(const axpic_species* electrons, const int64_t* off, int64_t ncell,
+                                double* out, void* stream);
+
+/* axpic_sample_emit_cells -- thermal emission (Secs. II.D, II.G, II.H) by
+ * per-cell superposition: in cell c the electrons' independent counts
+ * K_e ~ Poisson(lambda_e), lambda_e = w_e coef_ch (eq. lambda_macro), are
+ * drawn as the cell total N ~ Poisson(Lambda), Lambda = sum_e lambda_e,
+ * each event assigned to electron e with probability lambda_e / Lambda (the
+ * same joint law: a sum of independent Poisson counts is Poisson and its
+ * split is multinomial).  Electrons at the cap enter with min(lambda_e, cap)
+ * and carry lambda_e / cap in the product weight (eqs. lambda_eff,
+ * wa_rescaled).  The work is per cell and per event, not per electron.
+ * Electrons are grouped by cell (off[ncell+1], int64, device); cellw from
+ * axpic_cell_weights.  Lambda = coef W when no electron of the cell reaches
+ * the cap, else the sum of min(w_e coef, cap) in index order; a mean above
+ * 500 is drawn as ceil(Lambda/500) equal parts.  Random numbers: the cell
+ * totals from stream 5 keyed by the cell index (block = part); event j of
+ * channel ch: the electron from stream 6 (block (ch-1) 2^23 + j, inverse CDF
+ * over the cell in index order), energy and direction from stream 6 + ch
+ * (block j).  Products are appended in the order (cell, channel, j) with
+ * ids (next_id + rank) | 2^63; everything else as axpic_sample_emit.  The
+ * workspace must hold axpic_workspace_bytes(4 ncell). */
+axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cells,
+                                     const axpic_params* prm, axpic_species* electrons,
+                                     const int64_t* off, const double* cellw, int32_t channels,
+                                     int64_t step, uint64_t next_id, axpic_species* axions,
+                                     double* fb, double* hist, double* stats, int64_t* status,
+                                     void* ws, size_t ws_bytes, void* stream);
+
 /* axpic_absorb -- Sec. II.I and the inverse of Sec. II.F.1.  On the first
  * axions->n axions: thermal absorption (delete with probability P_abs or
  * reduce the weight by it; fb[cell] += (w E, w p)), then a->gamma conversion

@@ -73,7 +73,8 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_sampler_table", "axpic_timing_enable", "axpic_timing_read",
            "axpic_stream_copy", "axpic_mlp_blob_bytes", "axpic_mlp_train_ws_bytes",
            "axpic_mlp_pack", "axpic_mlp_forward", "axpic_mlp_loss_grad", "axpic_mlp_adam",
-           "axpic_rates_mlp", "axpic_surrogate_samples"]
+           "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
+           "axpic_sample_emit_cells"]
 MLP_PARAMS = 57888
 MLP_BLOB_BYTES = 112704
 
@@ -129,6 +130,9 @@ def load(path: Optional[str] = None):
                             _P]),
         ("axpic_rates_mlp", [_P, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
         ("axpic_surrogate_samples", [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+        ("axpic_cell_weights", [_P, _P, C.c_int64, _P, _P]),
+        ("axpic_sample_emit_cells", [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int64, C.c_uint64,
+                                     _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32

@@ -1033,6 +1033,224 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ superposed thermal emission
+// In a cell the electrons' Poisson counts K_e ~ Poisson(lambda_e), lambda_e =
+// w_e coef (eq. lambda_macro), have the joint law of a cell total
+// N ~ Poisson(sum_e lambda_e) split multinomially with probabilities
+// lambda_e / Lambda; electrons at the cap (eqs. lambda_eff, wa_rescaled) enter
+// with min(lambda_e, cap) and carry lambda_e / cap in their product weight.
+// The work is per cell and per event instead of per electron.  The electrons
+// of cell c are off[c] .. off[c+1]-1; cellw[c] = sum of their relative
+// weights, cellw[ncell + c] = the largest.
+
+// Cell weight sums: 16 lanes per cell, fixed reduction order.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_cell_weights(int64_t ncell, const int64_t* __restrict__ off, const T* __restrict__ w,
+               double* __restrict__ out) {
+    const int sub = threadIdx.x & (kCellLanes - 1);
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCellLanes;
+    const bool valid = c < ncell;
+    const int64_t lo = valid ? off[c] : 0, hi = valid ? off[c + 1] : 0;
+    double s = 0.0, m = 0.0;
+    for (int64_t i = lo + sub; i < hi; i += kCellLanes) {
+        const double v = (double)w[i];
+        s += v;
+        m = fmax(m, v);
+    }
+    s = group_sum16(s);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (valid && sub == 0) { out[c] = s; out[ncell + c] = m; }
+}
+
+// Lambda of a cell and channel: coef W when no electron reaches the cap, else
+// the sum of min(w_e coef, cap) in index order.
+template <typename T>
+__device__ __forceinline__ double sup_lambda(double k, double W, double wmax, double cap,
+                                             int64_t lo, int64_t hi, const T* __restrict__ w) {
+#pragma clang fp contract(off)
+    if (!(wmax * k > cap)) return k * W;
+    double L = 0.0;
+    for (int64_t e = lo; e < hi; ++e) {
+        const double le = (double)w[e] * k;
+        L += le < cap ? le : cap;
+    }
+    return L;
+}
+
+// N ~ Poisson(L) by inversion; a mean above 500 as ceil(L/500) equal parts
+// (stream 5, block = part, words 0-1 Compton, 2-3 brems).
+__device__ __forceinline__ uint32_t sup_poisson(const KParams& kp, int64_t c, int64_t step, int ch,
+                                                double L) {
+    if (!(L > 0.0)) return 0u;
+    const int parts = L > 500.0 ? (int)ceil(L / 500.0) : 1;
+    const double Lp = L / (double)parts;
+    uint32_t N = 0;
+    for (int q = 0; q < parts; ++q) {
+        const uint4 r = draw(kp, (uint64_t)c, step, 5, (uint32_t)q);
+        N += (uint32_t)poisson_inv_k(Lp, ch == 1 ? u53(r.x, r.y) : u53(r.z, r.w), 1 << 30);
+    }
+    return N;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_sup_count(int64_t ncell, int64_t step, KParams kp, const float* __restrict__ p32,
+            const double* __restrict__ p64, const int64_t* __restrict__ off,
+            const T* __restrict__ w, const double* __restrict__ cellw,
+            uint32_t* __restrict__ counts, uint32_t* __restrict__ bsum,
+            uint32_t* __restrict__ bact, double* __restrict__ acc, int acc_n) {
+    clear_acc(acc, acc_n);
+    __shared__ uint32_t lds[kThreads / 64];
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    uint32_t tot = 0, act = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t c = base + j * kThreads + threadIdx.x;
+        if (c >= ncell) break;
+        const T* pc = pref + c * AXPIC_PREF_N;
+        const double W = cellw[c], wmax = cellw[ncell + c];
+        const int64_t lo = off[c], hi = off[c + 1];
+        const double kC = onC ? (double)pc[4] : 0.0, kB = onB ? (double)pc[5] : 0.0;
+        const uint32_t NC = sup_poisson(kp, c, step, 1, sup_lambda<T>(kC, W, wmax, kp.cap, lo, hi, w));
+        const uint32_t NB = sup_poisson(kp, c, step, 2, sup_lambda<T>(kB, W, wmax, kp.cap, lo, hi, w));
+        counts[2 * c] = NC;
+        counts[2 * c + 1] = NB;
+        tot += NC + NB;
+        act += (NC + NB) > 0;
+    }
+    const uint32_t bt = block_sum_u32(tot, lds);
+    const uint32_t ba = block_sum_u32(act, lds);
+    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
+}
+
+// Records of the superposed events in canonical order (cell, channel, j):
+// cell (bits 0-31), j (32-61), channel (62-63).
+__global__ void __launch_bounds__(kThreads)
+k_sup_expand(int64_t ncell, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ bact,
+             const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
+             int64_t out_cap, uint64_t* __restrict__ rec) {
+    __shared__ uint32_t lds[kThreads / 64];
+    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    const int64_t c0 = (int64_t)blockIdx.x * kBlockParents + (int64_t)kPer * threadIdx.x;
+    uint32_t n[2 * kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const bool ok = c0 + q < ncell;
+        n[2 * q] = ok ? counts[2 * (c0 + q)] : 0u;
+        n[2 * q + 1] = ok ? counts[2 * (c0 + q) + 1] : 0u;
+    }
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * kPer; ++q) cnt += n[q];
+    uint32_t segtot;
+    const uint32_t pre = block_excl_scan(cnt, lds, &segtot);
+    if (cnt == 0) return;
+    int64_t slot = out_n + (int64_t)(boff[blockIdx.x] + pre);
+    for (int q = 0; q < kPer; ++q)
+        for (int ch = 1; ch <= 2; ++ch)
+            for (uint32_t j = 0; j < n[2 * q + ch - 1]; ++j, ++slot)
+                if (slot < out_cap)
+                    rec[slot] = (uint64_t)(c0 + q) | ((uint64_t)j << 32) | ((uint64_t)ch << 62);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
+             const float* __restrict__ p32, const double* __restrict__ p64,
+             const double* __restrict__ state, const int64_t* __restrict__ off,
+             const T* __restrict__ w, const T* __restrict__ x0, const T* __restrict__ x1,
+             const T* __restrict__ x2, const double* __restrict__ cellw,
+             const int64_t* __restrict__ ctrl, int64_t out_n, T* __restrict__ ax0,
+             T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx, T* __restrict__ apy,
+             T* __restrict__ apz, T* __restrict__ aw, uint64_t* __restrict__ aid,
+             int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
+             StatMap smap) {
+#pragma clang fp contract(off)
+    if (ctrl[0]) return;
+    const int64_t total = ctrl[1];
+    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
+    const T* pref = PrefOf<T>::get(p32, p64);
+    const int nbh = kp.nbins + 2;
+    double st[kStatSlots];
+    for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    bool any = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t slot = out_n + e;
+        const uint64_t rc = aid[slot];
+        const int64_t c = (int64_t)(rc & 0xFFFFFFFFull);
+        const uint32_t j = (uint32_t)((rc >> 32) & 0x3FFFFFFFull);
+        const int ch = (int)(rc >> 62);                     // 1 Compton, 2 brems
+        if (c >= ncell || (ch != 1 && ch != 2)) continue;   // never for a well-formed record
+        const T* pc = pref + c * AXPIC_PREF_N;
+        const double k = (double)pc[3 + ch];
+        const double W = cellw[c], wmax = cellw[ncell + c];
+        const int64_t lo = off[c], hi = off[c + 1];
+        const bool capped_cell = wmax * k > kp.cap;
+        const double L = sup_lambda<T>(k, W, wmax, kp.cap, lo, hi, w);
+        // the electron: inverse CDF of lambda_e / Lambda over the cell in index order,
+        // eight weights loaded at a time
+        uint4 r = draw(kp, (uint64_t)c, step, 6, (uint32_t)(ch - 1) * (1u << 23) + j);
+        const double target = u53(r.x, r.y) * (capped_cell ? L : W);
+        int64_t pick = -1, last = -1;
+        double a = 0.0;
+        for (int64_t e0 = lo; e0 < hi && pick < 0; e0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = e0 + q < hi ? w[e0 + q] : (T)0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (pick >= 0 || !(v[q] > (T)0)) continue;
+                const double wv = (double)v[q];
+                const double le = wv * k;
+                a += capped_cell ? (le < kp.cap ? le : kp.cap) : wv;
+                last = e0 + q;
+                if (a > target) pick = e0 + q;
+            }
+        }
+        if (pick < 0) pick = last;
+        if (pick < 0) continue;                             // no electron with weight: N is 0 then
+        const double le = (double)w[pick] * k;
+        const double ws = le > kp.cap ? le / kp.cap : 1.0;
+        const double wp = kp.w_a * kp.wa_mul[ch] * ws;
+        const double Tc = state[c * AXPIC_STATE_N + 0];
+        const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
+        const double xs = ch == 1 ? 1.0 : kp.brems_theta;
+        r = draw(kp, (uint64_t)c, step, 6 + ch, j);
+        const double E = Tc * xs * quantile(tab, u24(r.x));
+        const double mu = 2.0 * u24(r.y) - 1.0;
+        const double phi = 2.0 * kPi * u24(r.z);
+        const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double sphi, cphi;
+        sincos(phi, &sphi, &cphi);
+        const double pm = E / kMe;
+        const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
+        ax0[slot] = x0[pick];
+        if (ax1) ax1[slot] = x1 ? x1[pick] : (T)0;
+        if (ax2) ax2[slot] = x2 ? x2[pick] : (T)0;
+        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
+        aw[slot] = (T)(kp.wa_mul[ch] * ws);
+        aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
+        acell[slot] = (int32_t)c;
+        atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
+        if (fb) {
+            double* f = fb + c * 4;
+            atomicAdd(&f[0], -wp * pm);
+            atomicAdd(&f[1], -wp * pa[0]);
+            atomicAdd(&f[2], -wp * pa[1]);
+            atomicAdd(&f[3], -wp * pa[2]);
+        }
+        st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
+        if (le > kp.cap) st[9] += 1.0;
+        any = true;
+    }
+    stats_flush(st, any, A, nbh, smap);
+}
+
 // ------------------------------------------------------------------ compaction
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
@@ -1217,6 +1435,29 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
            TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
                        ax->cell, fb, W.acc, kEmitMap);
+    acc_reduce(kp, W, hist, stats, s);
+    return launched();
+}
+
+template <typename T>
+axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axpic_species* el,
+                                const int64_t* off, const double* cellw, int64_t step,
+                                uint64_t next_id, axpic_species* ax, double* fb, double* hist,
+                                double* stats, int64_t* status, const Workspace& W, hipStream_t s) {
+    const int64_t ncell = cells->ncell, nb = nblocks_for(std::max<int64_t>(ncell, 1));
+    uint32_t* counts = (uint32_t*)W.code;
+    LAUNCH("k_sup_count", k_sup_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, step, kp,
+           cells->pref32, cells->pref64, off, TCP<T>(el->w), cellw, counts, W.bsum, W.bact, W.acc,
+           acc_used(kp));
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
+           ax->capacity, W.ctrl, status);
+    LAUNCH("k_sup_expand", k_sup_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, counts,
+           W.bact, W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
+    LAUNCH("k_sup_events", k_sup_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, ncell, step,
+           next_id, kp, cells->pref32, cells->pref64, cells->state, off, TCP<T>(el->w),
+           TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
+           TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),
+           TP<T>(ax->p[2]), TP<T>(ax->w), ax->id, ax->cell, fb, W.acc, kEmitMap);
     acc_reduce(kp, W, hist, stats, s);
     return launched();
 }
@@ -1410,6 +1651,56 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
                                          stats, status, W, S(stream));
     }
     return AXPIC_E_INVAL;
+}
+
+axpic_status axpic_cell_weights(const axpic_species* el, const int64_t* off, int64_t ncell,
+                                double* out, void* stream) {
+    if (!el || !off || !out || ncell <= 0 || !el->w || el->n < 0) return AXPIC_E_INVAL;
+    if (el->dtype != AXPIC_F32 && el->dtype != AXPIC_F64) return AXPIC_E_INVAL;
+    const int64_t threads = ncell * kCellLanes;
+    if (el->dtype == AXPIC_F32)
+        LAUNCH("k_cell_weights", k_cell_weights<float>, grid1(threads), dim3(kThreads), 0, S(stream),
+               ncell, off, (const float*)el->w, out);
+    else
+        LAUNCH("k_cell_weights", k_cell_weights<double>, grid1(threads), dim3(kThreads), 0, S(stream),
+               ncell, off, (const double*)el->w, out);
+    return launched();
+}
+
+axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cells,
+                                     const axpic_params* prm, axpic_species* electrons,
+                                     const int64_t* off, const double* cellw, int32_t channels,
+                                     int64_t step, uint64_t next_id, axpic_species* axions,
+                                     double* fb, double* hist, double* stats, int64_t* status,
+                                     void* ws, size_t ws_bytes, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !status || !off || !cellw) return AXPIC_E_INVAL;
+    if (!species_ok(electrons, false) || electrons->kind != AXPIC_ELECTRON || !electrons->x[0])
+        return AXPIC_E_INVAL;
+    if (!species_ok(axions, false) || axions->kind != AXPIC_AXION ||
+        axions->dtype != electrons->dtype)
+        return AXPIC_E_INVAL;
+    if (!axions->x[0] || !axions->p[0] || !axions->p[1] || !axions->p[2] || !axions->w ||
+        !axions->id || !axions->cell || axions->n_implicit != 0)
+        return AXPIC_E_INVAL;
+    for (int d = 1; d < g->ndim; ++d)
+        if (!axions->x[d] || !electrons->x[d]) return AXPIC_E_INVAL;
+    if (!cells->state || !cells->pref32 || !cells->pref64 || cells->ncell <= 0) return AXPIC_E_INVAL;
+    if (cells->ncell >= ((int64_t)1 << 32)) return AXPIC_E_INVAL;
+    if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
+    if (std::fabs(electrons->w_ref - cells->w_ref_e) > 1e-12 * electrons->w_ref) return AXPIC_E_INVAL;
+    Workspace W;
+    if (!carve(ws, ws_bytes, 4 * cells->ncell, &W)) return AXPIC_E_INVAL;
+    axpic_params p2 = *prm;
+    p2.channels = prm->channels & channels & (AXPIC_COMPTON | AXPIC_BREMS);
+    if (!p2.channels) return AXPIC_E_INVAL;
+    axpic_status st = ensure_tables(prm->brems_k);
+    if (st != AXPIC_OK) return st;
+    KParams kp = make_kparams(g, &p2, cells->w_ref_g);
+    return electrons->dtype == AXPIC_F64
+               ? emit_thermal_cells<double>(kp, cells, electrons, off, cellw, step, next_id, axions,
+                                            fb, hist, stats, status, W, S(stream))
+               : emit_thermal_cells<float>(kp, cells, electrons, off, cellw, step, next_id, axions,
+                                           fb, hist, stats, status, W, S(stream));
 }
 
 axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,

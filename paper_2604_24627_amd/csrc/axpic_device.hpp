@@ -79,14 +79,14 @@ __device__ __forceinline__ double u24(uint32_t a) {
 // Poisson(lam) by sequential CDF inversion in FP64 (fixed operation order).
 // The leading test is an exact shortcut: exp(-lam) >= 1 - lam, and the FP64
 // exponential is within one ulp, so u < fl(1 - lam) - 2^-50 implies K = 0.
-__device__ __forceinline__ int poisson_inv(double lam, double u) {
+__device__ __forceinline__ int poisson_inv_k(double lam, double u, int kmax) {
 #pragma clang fp contract(off)
     if (!(lam > 0.0)) return 0;
     if (u < (1.0 - lam) - 8.881784197001252e-16) return 0;
     int k = 0;
     double p = exp(-lam);
     double F = p;
-    while (u >= F && k < kKmax) {
+    while (u >= F && k < kmax) {
         k += 1;
         p = p * lam;
         p = p / (double)k;
@@ -94,6 +94,7 @@ __device__ __forceinline__ int poisson_inv(double lam, double u) {
     }
     return k;
 }
+__device__ __forceinline__ int poisson_inv(double lam, double u) { return poisson_inv_k(lam, u, kKmax); }
 
 // Cap and rescale (eqs. lambda_eff, wa_rescaled): returns lambda_eff, *ws = w'/w.
 __device__ __forceinline__ double cap_lambda(double lam, double cap, double* ws, int* capped) {

@@ -114,7 +114,8 @@ class AxpicSim:
     """One uniform-grid run on the current GPU."""
 
     def __init__(self, plasma: Dict, params, device: str = "cuda", axion_capacity: int = 0,
-                 photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None):
+                 photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None,
+                 thermal: str = "particle"):
         self.lib = B.load()
         self.device = torch.device(device)
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
@@ -171,6 +172,17 @@ class AxpicSim:
         # axion absorption and a->gamma); None = plain closed forms
         self.surrogate = surrogate
         self.fallback = torch.zeros(1, dtype=torch.int64, device=self.device)
+        # thermal emission: "particle" (a Poisson draw per electron and channel) or
+        # "cells" (per-cell superposition, axpic_sample_emit_cells)
+        if thermal not in ("particle", "cells"):
+            raise ValueError(thermal)
+        self.thermal = thermal
+        self.cellw = None
+        if thermal == "cells":
+            self.cellw = torch.zeros(2 * self.ncell, dtype=f64, device=dev)
+            B.check(self.lib.axpic_cell_weights(B.ref(self.el.struct()), B.ptr(self.el.off),
+                                                self.ncell, B.ptr(self.cellw), s), "cell_weights")
+            self._ensure_ws(4 * self.ncell)
 
     @property
     def sh(self):
@@ -228,6 +240,22 @@ class AxpicSim:
                 B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
         self.el_struct = self.el.struct()
         k = self._append_call(call, self.ax, "sample_emit(thermal)")
+        self.ax.n += k
+        self.next_id += k
+        return k
+
+    def emit_thermal_cells(self):
+        s = self.sh
+        self._ensure_ws(4 * self.ncell)
+
+        def call():
+            return self.lib.axpic_sample_emit_cells(
+                B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.el_struct),
+                B.ptr(self.el.off), B.ptr(self.cellw), B.COMPTON | B.BREMS, self.step_index,
+                self.next_id, B.ref(self.ax.struct()), B.ptr(self.fb), B.ptr(self.hist),
+                B.ptr(self.stats), B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+        self.el_struct = self.el.struct()
+        k = self._append_call(call, self.ax, "sample_emit_cells")
         self.ax.n += k
         self.next_id += k
         return k
@@ -303,7 +331,10 @@ class AxpicSim:
             lam = S.rates(self, self.ph, B.PRIMAKOFF, fallback=self.fallback) if S else None
             self.emit_primakoff(lam_in=lam)
         if p["channels"] & (B.COMPTON | B.BREMS):
-            self.emit_thermal()
+            if self.thermal == "cells":
+                self.emit_thermal_cells()
+            else:
+                self.emit_thermal()
         if p["inverse"] and n_ax0 > 0:
             pab = lag = None
             if S:

@@ -19,6 +19,16 @@
  *    and the caller may grow the buffer and repeat the call with the same
  *    arguments, which gives bit-identical results (the random numbers are
  *    keyed by (seed, particle id, step), see below).
+ *  - Chained calls.  The appending calls and axpic_feedback take an optional
+ *    `chain`, a device int64[AXPIC_CHAIN_N] = {axion count, photon count,
+ *    next id, skip flag}.  With a chain, a call takes its output offset and
+ *    its first product id from the chain instead of the species' n and the
+ *    next_id argument, advances both on the device, and does nothing (but
+ *    report AXPIC_FLAG_SKIPPED) once the skip flag is set; a call that runs
+ *    out of capacity sets the flag.  A time step can then be issued without
+ *    reading any count back: the caller reads the chain once at the end, and
+ *    after an overflow grows the buffer named by that call's status and
+ *    repeats the calls from it on (the skipped ones modified nothing).
  *  - Particle ids key the random numbers.  A buffer may declare its first
  *    n_implicit ids as id0 + i (plasma in creation order) so that the hot
  *    kernels need not read them; appended products always store theirs.
@@ -65,6 +75,14 @@ typedef enum {
 /* status[1] flag bits */
 #define AXPIC_FLAG_CAPACITY 1
 #define AXPIC_FLAG_DOMAIN 2
+#define AXPIC_FLAG_SKIPPED 4      /* a chained call after an overflow: nothing done */
+
+/* chain words (see Conventions) */
+#define AXPIC_CHAIN_AXIONS 0
+#define AXPIC_CHAIN_PHOTONS 1
+#define AXPIC_CHAIN_NEXT_ID 2
+#define AXPIC_CHAIN_SKIP 3
+#define AXPIC_CHAIN_N 4
 
 typedef enum { AXPIC_PRIMAKOFF = 1, AXPIC_COMPTON = 2, AXPIC_BREMS = 4 } axpic_channel;
 typedef enum { AXPIC_F32 = 0, AXPIC_F64 = 1 } axpic_dtype;
@@ -224,7 +242,7 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
                                const axpic_params* prm, axpic_species* parent, int32_t channels,
                                const void* lam_in, int64_t step, uint64_t next_id,
                                axpic_species* axions, double* fb, double* hist, double* stats,
-                               int64_t* status, void* ws, size_t ws_bytes, void* stream);
+                               int64_t* status, void* ws, size_t ws_bytes, int64_t* chain, void* stream);
 
 /* axpic_cell_weights -- for the superposed emission below: out[c] = sum of
  * the relative weights of electrons off[c] .. off[c+1]-1 (FP64, a fixed
@@ -258,7 +276,7 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
                                      const int64_t* off, const double* cellw, int32_t channels,
                                      int64_t step, uint64_t next_id, axpic_species* axions,
                                      double* fb, double* hist, double* stats, int64_t* status,
-                                     void* ws, size_t ws_bytes, void* stream);
+                                     void* ws, size_t ws_bytes, int64_t* chain, void* stream);
 
 /* axpic_absorb -- Sec. II.I and the inverse of Sec. II.F.1.  On the first
  * axions->n axions: thermal absorption (delete with probability P_abs or
@@ -269,7 +287,7 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
                           axpic_species* axions, const void* pabs_in, const void* lam_in,
                           int64_t step, uint64_t next_id, axpic_species* photons, double* fb,
                           double* stats, int64_t* status, void* ws, size_t ws_bytes,
-                          void* stream);
+                          int64_t* chain, void* stream);
 
 /* axpic_feedback -- Sec. II.J.  Per cell over the electrons (grouped by cell,
  * offsets off[ncell+1]): FP64 moments W, P, U2 (eq. cell_moments), the
@@ -279,7 +297,7 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
  * or NULL. */
 axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
                             axpic_species* electrons, const int64_t* off, const double* fb,
-                            double* moments, double* stats, void* stream);
+                            double* moments, double* stats, int64_t* chain, void* stream);
 
 /* axpic_compact -- stable removal of particles with w <= 0 from `in` into
  * `out` (distinct buffers, same dtype, out->capacity >= in->n).  status[2]

@@ -18,6 +18,8 @@ ELECTRON, ION, PHOTON, AXION = 0, 1, 2, 3
 PRIMAKOFF, COMPTON, BREMS = 1, 2, 4
 MAX_IONS, PREF_N, STATE_N, STATUS_N = 4, 8, 16, 4
 FLAG_CAPACITY = 1
+FLAG_SKIPPED = 4
+CHAIN_N = 4
 ST_NAMES = ["events_P", "events_C", "events_B", "num_P", "num_C", "num_B", "en_P", "en_C", "en_B",
             "abs_num", "abs_en", "ag_events", "ag_num", "ag_en", "capped", "overdepleted",
             "cold_cells", "clamped_cells", "unapplied_E", "abs_events"]
@@ -114,10 +116,10 @@ def load(path: Optional[str] = None):
         ("axpic_cell_state", [_P, _P, _P, C.c_double, C.c_double, _P]),
         ("axpic_rates", [_P, _P, _P, _P, C.c_int32, _P, _P]),
         ("axpic_sample_emit", [_P, _P, _P, _P, C.c_int32, _P, C.c_int64, C.c_uint64, _P, _P, _P,
-                               _P, _P, _P, C.c_size_t, _P]),
+                               _P, _P, _P, C.c_size_t, _P, _P]),
         ("axpic_absorb", [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P,
-                          C.c_size_t, _P]),
-        ("axpic_feedback", [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+                          C.c_size_t, _P, _P]),
+        ("axpic_feedback", [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
         ("axpic_compact", [_P, _P, _P, _P, C.c_size_t, _P]),
         ("axpic_diag", [_P, _P, _P, C.c_size_t, _P]),
         ("axpic_sampler_table", [C.c_int32, C.c_double, _P]),
@@ -132,7 +134,7 @@ def load(path: Optional[str] = None):
         ("axpic_surrogate_samples", [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
         ("axpic_cell_weights", [_P, _P, C.c_int64, _P, _P]),
         ("axpic_sample_emit_cells", [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int64, C.c_uint64,
-                                     _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+                                     _P, _P, _P, _P, _P, _P, C.c_size_t, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32

@@ -276,7 +276,8 @@ constexpr int kScanTile = kScanThreads * kScanPer;
 
 __global__ void __launch_bounds__(kScanThreads)
 k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t nb,
-       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status) {
+       int64_t n_out, int64_t capacity, int64_t* __restrict__ ctrl, int64_t* __restrict__ status,
+       uint64_t next_id, int64_t* __restrict__ chain, int chain_slot) {
     __shared__ uint64_t wsum[kScanThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     uint64_t carry = 0;
@@ -329,14 +330,29 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
         __syncthreads();
     }
     if (t == 0) {
-        const bool over = n_out + (int64_t)carry > capacity;
+        // output offset and first id: the chain's when chained, else the host's (a call
+        // without an output species, chain_slot < 0, only honours the skip word)
+        const int64_t base = (chain && chain_slot >= 0) ? chain[chain_slot] : n_out;
+        const int64_t id0 = chain ? chain[AXPIC_CHAIN_NEXT_ID] : (int64_t)next_id;
+        const bool skip = chain && chain[AXPIC_CHAIN_SKIP] != 0;
+        const bool full = base + (int64_t)carry > capacity;
+        const bool over = skip || full;
         ctrl[0] = over ? 1 : 0;
         ctrl[1] = (int64_t)carry;
+        ctrl[2] = base;
+        ctrl[3] = id0;
         if (status) {
-            status[0] = n_out + (int64_t)carry;
-            status[1] = over ? AXPIC_FLAG_CAPACITY : 0;
+            status[0] = base + (int64_t)carry;
+            status[1] = (skip ? AXPIC_FLAG_SKIPPED : 0) | (full ? AXPIC_FLAG_CAPACITY : 0);
             status[2] = over ? 0 : (int64_t)carry;
             status[3] = 0;
+        }
+        if (chain) {
+            if (over) chain[AXPIC_CHAIN_SKIP] = 1;
+            else if (chain_slot >= 0) {
+                chain[chain_slot] = base + (int64_t)carry;
+                chain[AXPIC_CHAIN_NEXT_ID] = id0 + (int64_t)carry;
+            }
         }
     }
 }
@@ -560,6 +576,7 @@ k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t*
          int64_t out_cap, uint64_t* __restrict__ rec) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    out_n = ctrl[2];
     // each thread takes kPer consecutive parents: one 8-byte load of their codes and one
     // block scan keep the records in parent order
     const int64_t i0 = (int64_t)blockIdx.x * kBlockParents + (int64_t)kPer * threadIdx.x;
@@ -608,6 +625,8 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
               uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ acc,
               StatMap smap) {
     if (ctrl[0]) return;
+    out_n = ctrl[2];
+    next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
@@ -724,6 +743,8 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
                int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
                StatMap smap) {
     if (ctrl[0]) return;
+    out_n = ctrl[2];
+    next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
@@ -867,6 +888,8 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             double* __restrict__ acc, StatMap smap) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    out_n = ctrl[2];
+    next_id = (uint64_t)ctrl[3];
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const int nbh = kp.nbins + 2;
     bool any = false;
@@ -965,7 +988,10 @@ __global__ void __launch_bounds__(kThreads)
 k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ off,
            const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
            const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
-           double* __restrict__ stats) {
+           double* __restrict__ stats, const int64_t* __restrict__ chain) {
+    // a chained step whose appending calls were skipped after an overflow is repeated
+    // whole: the feedback of its partial exchange must not be applied
+    if (chain && chain[AXPIC_CHAIN_SKIP]) return;
     const int lane = threadIdx.x & 63, sub = lane & (kCellLanes - 1);
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCellLanes;
     const bool valid = c < ncell;
@@ -1135,6 +1161,7 @@ k_sup_expand(int64_t ncell, const uint32_t* __restrict__ counts, const uint32_t*
              int64_t out_cap, uint64_t* __restrict__ rec) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    out_n = ctrl[2];
     const int64_t c0 = (int64_t)blockIdx.x * kBlockParents + (int64_t)kPer * threadIdx.x;
     uint32_t n[2 * kPer];
 #pragma unroll
@@ -1171,6 +1198,8 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
              StatMap smap) {
 #pragma clang fp contract(off)
     if (ctrl[0]) return;
+    out_n = ctrl[2];
+    next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
@@ -1357,9 +1386,13 @@ k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t 
 }
 
 // Status of a call whose input buffer is empty: nothing is appended.
-__global__ void k_status_empty(int64_t* __restrict__ status, int64_t out_n) {
+__global__ void k_status_empty(int64_t* __restrict__ status, int64_t out_n,
+                               const int64_t* __restrict__ chain, int chain_slot) {
     if (threadIdx.x == 0) {
-        status[0] = out_n; status[1] = 0; status[2] = 0; status[3] = 0;
+        const bool skip = chain && chain[AXPIC_CHAIN_SKIP] != 0;
+        status[0] = (chain && chain_slot >= 0) ? chain[chain_slot] : out_n;
+        status[1] = skip ? AXPIC_FLAG_SKIPPED : 0;
+        status[2] = 0; status[3] = 0;
     }
 }
 
@@ -1396,14 +1429,14 @@ template <typename T>
 axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_species* ph,
                             const void* lam_in, int64_t step, uint64_t next_id,
                             axpic_species* ax, double* hist, double* stats, int64_t* status,
-                            const Workspace& W, hipStream_t s) {
+                            const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = ph->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_prim_count", k_prim_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
                        W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status);
+           ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     LAUNCH("k_prim_events", k_prim_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
@@ -1420,13 +1453,13 @@ template <typename T>
 axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_species* el,
                           const void* lam_in, int64_t step, uint64_t next_id, axpic_species* ax,
                           double* fb, double* hist, double* stats, int64_t* status,
-                          const Workspace& W, hipStream_t s) {
+                          const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
                        TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-                       ax->capacity, W.ctrl, status);
+           ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     LAUNCH("k_therm_events", k_therm_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
@@ -1443,14 +1476,14 @@ template <typename T>
 axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axpic_species* el,
                                 const int64_t* off, const double* cellw, int64_t step,
                                 uint64_t next_id, axpic_species* ax, double* fb, double* hist,
-                                double* stats, int64_t* status, const Workspace& W, hipStream_t s) {
+                                double* stats, int64_t* status, const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t ncell = cells->ncell, nb = nblocks_for(std::max<int64_t>(ncell, 1));
     uint32_t* counts = (uint32_t*)W.code;
     LAUNCH("k_sup_count", k_sup_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, step, kp,
            cells->pref32, cells->pref64, off, TCP<T>(el->w), cellw, counts, W.bsum, W.bact, W.acc,
            acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
-           ax->capacity, W.ctrl, status);
+           ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_sup_expand", k_sup_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, counts,
            W.bact, W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     LAUNCH("k_sup_events", k_sup_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, ncell, step,
@@ -1466,7 +1499,7 @@ template <typename T>
 axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_species* ax,
                          const void* pabs_in, const void* lam_in, int64_t step, uint64_t next_id,
                          axpic_species* ph, double* fb, double* stats, int64_t* status,
-                         const Workspace& W, hipStream_t s) {
+                         const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = ax->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_abs_count", k_abs_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
@@ -1474,7 +1507,7 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
-                       out_cap, W.ctrl, status);
+           out_cap, W.ctrl, status, next_id, chain, ph ? (int)AXPIC_CHAIN_PHOTONS : -1);
     LAUNCH("k_abs_apply", k_abs_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
                        kp, ax->w_ref, cells->pref32, cells->pref64, TP<T>(ax->w), TCP<T>(ax->x[0]),
                        TCP<T>(ax->x[1]), TCP<T>(ax->x[2]), TCP<T>(ax->p[0]), TCP<T>(ax->p[1]),
@@ -1609,7 +1642,8 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
                                const axpic_params* prm, axpic_species* parent, int32_t channels,
                                const void* lam_in, int64_t step, uint64_t next_id,
                                axpic_species* axions, double* fb, double* hist, double* stats,
-                               int64_t* status, void* ws, size_t ws_bytes, void* stream) {
+                               int64_t* status, void* ws, size_t ws_bytes, int64_t* chain,
+                               void* stream) {
     if (!grid_ok(g) || !params_ok(prm) || !cells || !status) return AXPIC_E_INVAL;
     if (!species_ok(parent, parent && parent->kind == AXPIC_PHOTON) || !species_ok(axions, false))
         return AXPIC_E_INVAL;
@@ -1623,7 +1657,8 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
     if (!carve(ws, ws_bytes, parent->n, &W)) return AXPIC_E_INVAL;
     if (std::fabs(axions->w_ref - prm->w_a) > 1e-12 * prm->w_a) return AXPIC_E_INVAL;
     if (parent->n == 0) {
-        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, axions->n);
+        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, axions->n,
+               (const int64_t*)chain, (int)AXPIC_CHAIN_AXIONS);
         return launched();
     }
     axpic_status st = ensure_tables(prm->brems_k);
@@ -1639,16 +1674,16 @@ axpic_status axpic_sample_emit(const axpic_grid* g, const axpic_cells* cells,
     if (parent->kind == AXPIC_PHOTON) {
         if (!(p2.channels & AXPIC_PRIMAKOFF)) return AXPIC_E_INVAL;
         return f64 ? emit_primakoff<double>(kp, cells, parent, lam_in, step, next_id, axions, hist,
-                                            stats, status, W, S(stream))
+                                            stats, status, W, chain, S(stream))
                    : emit_primakoff<float>(kp, cells, parent, lam_in, step, next_id, axions, hist,
-                                           stats, status, W, S(stream));
+                                           stats, status, W, chain, S(stream));
     }
     if (parent->kind == AXPIC_ELECTRON) {
         if (!(p2.channels & (AXPIC_COMPTON | AXPIC_BREMS))) return AXPIC_E_INVAL;
         return f64 ? emit_thermal<double>(kp, cells, parent, lam_in, step, next_id, axions, fb,
-                                          hist, stats, status, W, S(stream))
+                                          hist, stats, status, W, chain, S(stream))
                    : emit_thermal<float>(kp, cells, parent, lam_in, step, next_id, axions, fb, hist,
-                                         stats, status, W, S(stream));
+                                         stats, status, W, chain, S(stream));
     }
     return AXPIC_E_INVAL;
 }
@@ -1672,7 +1707,7 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
                                      const int64_t* off, const double* cellw, int32_t channels,
                                      int64_t step, uint64_t next_id, axpic_species* axions,
                                      double* fb, double* hist, double* stats, int64_t* status,
-                                     void* ws, size_t ws_bytes, void* stream) {
+                                     void* ws, size_t ws_bytes, int64_t* chain, void* stream) {
     if (!grid_ok(g) || !params_ok(prm) || !cells || !status || !off || !cellw) return AXPIC_E_INVAL;
     if (!species_ok(electrons, false) || electrons->kind != AXPIC_ELECTRON || !electrons->x[0])
         return AXPIC_E_INVAL;
@@ -1698,16 +1733,16 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
     KParams kp = make_kparams(g, &p2, cells->w_ref_g);
     return electrons->dtype == AXPIC_F64
                ? emit_thermal_cells<double>(kp, cells, electrons, off, cellw, step, next_id, axions,
-                                            fb, hist, stats, status, W, S(stream))
+                                            fb, hist, stats, status, W, chain, S(stream))
                : emit_thermal_cells<float>(kp, cells, electrons, off, cellw, step, next_id, axions,
-                                           fb, hist, stats, status, W, S(stream));
+                                           fb, hist, stats, status, W, chain, S(stream));
 }
 
 axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                           axpic_species* axions, const void* pabs_in, const void* lam_in,
                           int64_t step, uint64_t next_id, axpic_species* photons, double* fb,
                           double* stats, int64_t* status, void* ws, size_t ws_bytes,
-                          void* stream) {
+                          int64_t* chain, void* stream) {
     if (!grid_ok(g) || !params_ok(prm) || !cells || !status) return AXPIC_E_INVAL;
     if (!species_ok(axions, true) || axions->kind != AXPIC_AXION) return AXPIC_E_INVAL;
     const bool a2g = prm->inverse && (prm->channels & AXPIC_PRIMAKOFF);
@@ -1725,7 +1760,7 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
     if (!carve(ws, ws_bytes, axions->n, &W)) return AXPIC_E_INVAL;
     if (axions->n == 0) {
         LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status,
-               a2g ? photons->n : 0);
+               a2g ? photons->n : 0, (const int64_t*)chain, a2g ? (int)AXPIC_CHAIN_PHOTONS : -1);
         return launched();
     }
     if (a2g && std::fabs(photons->w_ref - cells->w_ref_g) > 1e-12 * photons->w_ref)
@@ -1735,14 +1770,14 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
     axpic_species* ph = a2g ? photons : nullptr;
     if (axions->dtype == AXPIC_F64)
         return absorb_impl<double>(kp, cells, axions, pabs_in, lam_in, step, next_id, ph, fb, stats,
-                                   status, W, S(stream));
+                                   status, W, chain, S(stream));
     return absorb_impl<float>(kp, cells, axions, pabs_in, lam_in, step, next_id, ph, fb, stats,
-                              status, W, S(stream));
+                              status, W, chain, S(stream));
 }
 
 axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
                             axpic_species* el, const int64_t* off, const double* fb,
-                            double* moments, double* stats, void* stream) {
+                            double* moments, double* stats, int64_t* chain, void* stream) {
     if (!grid_ok(g) || !params_ok(prm) || !cells || !off || !cells->T_keV) return AXPIC_E_INVAL;
     if (!species_ok(el, true) || el->kind != AXPIC_ELECTRON) return AXPIC_E_INVAL;
     if (cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
@@ -1751,12 +1786,13 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     if (el->dtype == AXPIC_F32)
         LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, S(stream),
                            cells->ncell, kp, el->w_ref, off, (const float*)el->w, (float*)el->p[0],
-                           (float*)el->p[1], (float*)el->p[2], fb, cells->T_keV, moments, stats);
+                           (float*)el->p[1], (float*)el->p[2], fb, cells->T_keV, moments, stats,
+                           (const int64_t*)chain);
     else
         LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, S(stream),
                            cells->ncell, kp, el->w_ref, off, (const double*)el->w,
                            (double*)el->p[0], (double*)el->p[1], (double*)el->p[2], fb,
-                           cells->T_keV, moments, stats);
+                           cells->T_keV, moments, stats, (const int64_t*)chain);
     return launched();
 }
 
@@ -1772,7 +1808,8 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     Workspace W;
     if (!carve(ws, ws_bytes, in->n, &W)) return AXPIC_E_INVAL;
     if (in->n == 0) {
-        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, (int64_t)0);
+        LAUNCH("k_status_empty", k_status_empty, dim3(1), dim3(64), 0, S(stream), status, (int64_t)0,
+               (const int64_t*)nullptr, 0);
         return launched();
     }
     const int64_t n = in->n, nb = nblocks_for(std::max<int64_t>(n, 1));
@@ -1781,7 +1818,7 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     LAUNCH("k_live_count", k_live_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n,              \
                        (const T*)in->w, W.code, W.bsum, W.bact);                                   \
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, (int64_t)0, \
-                       out->capacity, W.ctrl, status);                                             \
+           out->capacity, W.ctrl, status, (uint64_t)0, (int64_t*)nullptr, 0);                       \
     LAUNCH("k_compact_apply", k_compact_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, W.code,   \
                        W.boff, W.ctrl, out->capacity, ndim, (const T*)in->x[0],                   \
                        (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],                \

@@ -172,6 +172,13 @@ class AxpicSim:
         # axion absorption and a->gamma); None = plain closed forms
         self.surrogate = surrogate
         self.fallback = torch.zeros(1, dtype=torch.int64, device=self.device)
+        # device chain of the step's appending calls {axions, photons, next id, skip} and
+        # one status record per call
+        self.chain = torch.zeros(B.CHAIN_N, dtype=torch.int64, device=dev)
+        self.chain_host = torch.zeros(B.CHAIN_N, dtype=torch.int64).pin_memory()
+        self.status_ops = torch.zeros((3, B.STATUS_N), dtype=torch.int64, device=dev)
+        self._last_new = (0, 0)
+        self.grow_ahead = True      # reserve room for twice the previous step's products
         # thermal emission: "particle" (a Poisson draw per electron and channel) or
         # "cells" (per-cell superposition, axpic_sample_emit_cells)
         if thermal not in ("particle", "cells"):
@@ -221,7 +228,7 @@ class AxpicSim:
                 B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.ph_struct),
                 B.PRIMAKOFF, B.ptr(lam_in), self.step_index, self.next_id,
                 B.ref(self.ax.struct()), None, B.ptr(self.hist), B.ptr(self.stats),
-                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, None, s)
         self.ph_struct = self.ph.struct()
         k = self._append_call(call, self.ax, "sample_emit(primakoff)")
         self.ax.n += k
@@ -237,7 +244,7 @@ class AxpicSim:
                 B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.el_struct),
                 B.COMPTON | B.BREMS, B.ptr(lam_in), self.step_index, self.next_id,
                 B.ref(self.ax.struct()), B.ptr(self.fb), B.ptr(self.hist), B.ptr(self.stats),
-                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+                B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, None, s)
         self.el_struct = self.el.struct()
         k = self._append_call(call, self.ax, "sample_emit(thermal)")
         self.ax.n += k
@@ -253,7 +260,7 @@ class AxpicSim:
                 B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.el_struct),
                 B.ptr(self.el.off), B.ptr(self.cellw), B.COMPTON | B.BREMS, self.step_index,
                 self.next_id, B.ref(self.ax.struct()), B.ptr(self.fb), B.ptr(self.hist),
-                B.ptr(self.stats), B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, s)
+                B.ptr(self.stats), B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, None, s)
         self.el_struct = self.el.struct()
         k = self._append_call(call, self.ax, "sample_emit_cells")
         self.ax.n += k
@@ -271,7 +278,7 @@ class AxpicSim:
                     B.ref(self.grid), B.ref(self.cells), B.ref(self.params), B.ref(self.ax_struct),
                     B.ptr(pabs_in), B.ptr(lam_in), self.step_index, self.next_id,
                     B.ref(self.ph.struct()), B.ptr(self.fb), B.ptr(self.stats), B.ptr(self.status),
-                    B.ptr(self.ws), self.ws_bytes, s)
+                    B.ptr(self.ws), self.ws_bytes, None, s)
             self.ax_struct = self.ax.struct()
             k = self._append_call(call, self.ph, "absorb")
         finally:
@@ -280,10 +287,11 @@ class AxpicSim:
         self.next_id += k
         return k
 
-    def feedback(self, moments=None):
+    def feedback(self, moments=None, chain=None):
         B.check(self.lib.axpic_feedback(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
                                         B.ref(self.el.struct()), B.ptr(self.el.off),
-                                        B.ptr(self.fb), B.ptr(moments), B.ptr(self.stats), self.sh),
+                                        B.ptr(self.fb), B.ptr(moments), B.ptr(self.stats),
+                                        B.ptr(chain), self.sh),
                 "feedback")
 
     def bin_axions(self, push: bool = True):
@@ -318,6 +326,10 @@ class AxpicSim:
 
     # -------------------------------------------------------------- one step
     def step(self):
+        """One time step.  The appending calls are chained on the device (counts and the
+        next id stay there), so the step reads back four words once at its end; after an
+        overflow the buffer named by the failing call is grown and the calls are repeated
+        from it on (the skipped ones modified nothing)."""
         p = self.pdict
         self.bin_axions(push=True)
         if p["T_mode"] == 2:
@@ -325,31 +337,93 @@ class AxpicSim:
         if self.need_feedback:
             self.fb.zero_()
         n_ax0 = self.ax.n
-        self._ensure_ws(max(self.el.n, self.ph.n, n_ax0))
+        if self.grow_ahead:
+            self.ax.ensure(self.ax.n + 2 * self._last_new[0] + 4096)
+            if p["inverse"] and p["channels"] & B.PRIMAKOFF:
+                self.ph.ensure(self.ph.n + 2 * self._last_new[1] + 1024)
+        self._ensure_ws(max(self.el.n, self.ph.n, n_ax0, 4 * self.ncell))
         S = self.surrogate
-        if p["channels"] & B.PRIMAKOFF:
-            lam = S.rates(self, self.ph, B.PRIMAKOFF, fallback=self.fallback) if S else None
-            self.emit_primakoff(lam_in=lam)
-        if p["channels"] & (B.COMPTON | B.BREMS):
+        lam = pab = lag = None
+        if S and p["channels"] & B.PRIMAKOFF:
+            lam = S.rates(self, self.ph, B.PRIMAKOFF, fallback=self.fallback)
+        if S and p["inverse"] and n_ax0 > 0:
+            n_now = self.ax.n
+            self.ax.n = n_ax0
+            try:
+                if p["channels"] & (B.COMPTON | B.BREMS):
+                    pab = S.rates(self, self.ax, B.COMPTON | B.BREMS, fallback=self.fallback)
+                if p["channels"] & B.PRIMAKOFF:
+                    lag = S.rates(self, self.ax, B.PRIMAKOFF, fallback=self.fallback)
+            finally:
+                self.ax.n = n_now
+        n_ph0, id0 = self.ph.n, self.next_id
+        self.chain_host.copy_(torch.tensor([self.ax.n, self.ph.n, self.next_id, 0],
+                                           dtype=torch.int64))
+        self.chain.copy_(self.chain_host, non_blocking=True)
+        st = self.status_ops
+        sh, g, c, prm, ch = self.sh, B.ref(self.grid), B.ref(self.cells), B.ref(self.params), \
+            B.ptr(self.chain)
+
+        def op_prim():
+            return self.lib.axpic_sample_emit(
+                g, c, prm, B.ref(self.ph.struct()), B.PRIMAKOFF, B.ptr(lam), self.step_index, id0,
+                B.ref(self.ax.struct()), None, B.ptr(self.hist), B.ptr(self.stats), B.ptr(st[0]),
+                B.ptr(self.ws), self.ws_bytes, ch, sh)
+
+        def op_therm():
             if self.thermal == "cells":
-                self.emit_thermal_cells()
-            else:
-                self.emit_thermal()
+                return self.lib.axpic_sample_emit_cells(
+                    g, c, prm, B.ref(self.el.struct()), B.ptr(self.el.off), B.ptr(self.cellw),
+                    B.COMPTON | B.BREMS, self.step_index, id0, B.ref(self.ax.struct()),
+                    B.ptr(self.fb), B.ptr(self.hist), B.ptr(self.stats), B.ptr(st[1]),
+                    B.ptr(self.ws), self.ws_bytes, ch, sh)
+            return self.lib.axpic_sample_emit(
+                g, c, prm, B.ref(self.el.struct()), B.COMPTON | B.BREMS, None, self.step_index,
+                id0, B.ref(self.ax.struct()), B.ptr(self.fb), B.ptr(self.hist), B.ptr(self.stats),
+                B.ptr(st[1]), B.ptr(self.ws), self.ws_bytes, ch, sh)
+
+        def op_abs():
+            axs = self.ax.struct()
+            axs.n = n_ax0
+            return self.lib.axpic_absorb(
+                g, c, prm, B.ref(axs), B.ptr(pab), B.ptr(lag), self.step_index, id0,
+                B.ref(self.ph.struct()), B.ptr(self.fb), B.ptr(self.stats), B.ptr(st[2]),
+                B.ptr(self.ws), self.ws_bytes, ch, sh)
+
+        def op_fb():
+            return self.lib.axpic_feedback(g, c, prm, B.ref(self.el.struct()), B.ptr(self.el.off),
+                                           B.ptr(self.fb), None, B.ptr(self.stats), ch, sh)
+        ops = []
+        if p["channels"] & B.PRIMAKOFF:
+            ops.append((op_prim, 0, self.ax))
+        if p["channels"] & (B.COMPTON | B.BREMS):
+            ops.append((op_therm, 1, self.ax))
         if p["inverse"] and n_ax0 > 0:
-            pab = lag = None
-            if S:
-                n_now = self.ax.n
-                self.ax.n = n_ax0
-                try:
-                    if p["channels"] & (B.COMPTON | B.BREMS):
-                        pab = S.rates(self, self.ax, B.COMPTON | B.BREMS, fallback=self.fallback)
-                    if p["channels"] & B.PRIMAKOFF:
-                        lag = S.rates(self, self.ax, B.PRIMAKOFF, fallback=self.fallback)
-                finally:
-                    self.ax.n = n_now
-            self.absorb(n_ax0, pabs_in=pab, lam_in=lag)
+            ops.append((op_abs, 2, self.ph))
         if self.need_feedback:
-            self.feedback()
+            ops.append((op_fb, -1, None))
+        first = 0
+        for _ in range(8):
+            for fn, _, _ in ops[first:]:
+                B.check(fn(), "step")
+            cw = self.chain.cpu()
+            if int(cw[3]) == 0:
+                break
+            sts = st.cpu()
+            # what the successful calls appended is on the device: the growth must keep it
+            self.ax.n, self.ph.n = int(cw[0]), int(cw[1])
+            for k, (fn, slot, sp) in enumerate(ops):
+                if slot >= 0 and int(sts[slot][1]) & B.FLAG_CAPACITY:
+                    sp.ensure(int(sts[slot][0]))
+                    first = k
+                    break
+            else:
+                raise B.AxpicError("chained step: skip flag without a capacity overflow")
+            self.chain[3].zero_()
+        else:
+            raise B.AxpicError("chained step: capacity growth did not converge")
+        self.ax.n, self.ph.n, self.next_id = int(cw[0]), int(cw[1]), int(cw[2])
+        self._last_new = (self.ax.n - n_ax0, self.ph.n - n_ph0)
         self.step_index += 1
         if self.compact_every and self.step_index % self.compact_every == 0:
             self.compact_axions()

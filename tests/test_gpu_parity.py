@@ -346,3 +346,31 @@ def test_empty_inputs_append_nothing():
     assert g.absorb(0) == 0
     g.compact_axions()
     assert g.ax.n == 0
+
+
+def test_chained_step_recovers_from_overflow_bit_identical():
+    """A step issued as a device chain: with buffers far too small (no growth ahead) the
+    overflowing call and everything after it are skipped, the buffer is grown and the
+    calls repeated; the run must equal one with ample buffers."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=4e33,
+                        w_a=1e-36, lambda_cap=1.0, feedback=1, T_mode=2)
+    pl = I.make_plasma(wl, 0)
+    print("[parity] chained step overflow", flush=True)
+    big = AxpicSim(pl, wl.params, axion_capacity=400000, photon_extra=100000)
+    small = AxpicSim(pl, wl.params, axion_capacity=64)
+    small.grow_ahead = False
+    for _ in range(4):
+        big.step()
+        small.step()
+    assert small.ax.capacity < big.ax.capacity and small.ax.n == big.ax.n > 2000
+    assert small.next_id == big.next_id
+    for a, b in ((small.ax, big.ax), (small.ph, big.ph)):
+        x, y = a.to_numpy(), b.to_numpy()
+        for k in ("w", "id", "cell"):
+            np.testing.assert_array_equal(x[k], y[k])
+        np.testing.assert_array_equal(x["p"], y["p"])
+    # the feedback's FP64 exchange sums are order-dependent at the 1e-16 level
+    np.testing.assert_allclose(np64(small.el.p[0][: small.el.n]), np64(big.el.p[0][: big.el.n]),
+                               rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(small.T.cpu().numpy(), big.T.cpu().numpy(), rtol=1e-7)
+    np.testing.assert_allclose(small.hist_np(), big.hist_np(), rtol=1e-12)

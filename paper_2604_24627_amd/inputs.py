@@ -247,6 +247,91 @@ def make_plasma(wl: Workload, seed: Optional[int] = None) -> Dict:
                 next_id=id_base)
 
 
+def make_plasma_device(wl: Workload, seed: Optional[int] = None, device="cuda") -> Dict:
+    """The workload recipe of make_plasma drawn with torch's generator on the
+    GPU, for plasmas too large to build on the host (the 256^3 graded plasma
+    holds 1.6e9 particles).  Same layout and distributions; the random streams
+    differ from make_plasma's, so it serves measurements, not oracle
+    comparisons.  Arrays are device tensors; ids are implicit (``id0`` + i)."""
+    import torch
+    seed = wl.params.seed if seed is None else seed
+    dev = torch.device(device)
+    td = torch.float64 if wl.dtype == "f64" else torch.float32
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) * 1000003 + 0xA710)
+    T_np, ne_np = _cell_profile(wl)
+    T_cell = torch.from_numpy(T_np).to(dev)
+    ne_cell = torch.from_numpy(ne_np).to(dev)
+    V = wl.V_cell_cm3
+    ncell = wl.ncell
+    nfull = tuple(wl.n) + (1,) * (3 - len(wl.n))
+    graded = (wl.T_keV_hi is not None) or (wl.n_e_hi is not None)
+    # blackbody mixture weights p_j ~ j^-3 (x = Gamma(3, 1) / j)
+    J = 20000
+    pj = torch.arange(1, J + 1, device=dev, dtype=torch.float64) ** -3
+    cdf = torch.cumsum(pj / pj.sum(), 0)
+    species = {}
+    id_base = 0
+    for name in ("electrons", "ions", "photons"):
+        if wl.poisson_ppc:
+            counts = torch.poisson(torch.full((ncell,), float(wl.ppc), device=dev,
+                                              dtype=torch.float64), generator=gen).to(torch.int64)
+        else:
+            counts = torch.full((ncell,), wl.ppc, device=dev, dtype=torch.int64)
+        cell = torch.repeat_interleave(torch.arange(ncell, device=dev, dtype=torch.int64), counts)
+        N = int(cell.numel())
+        x = torch.zeros((3, N), device=dev, dtype=td)
+        idx = [cell % nfull[0], (cell // nfull[0]) % nfull[1], cell // (nfull[0] * nfull[1])]
+        for d in range(wl.ndim):
+            xd = (idx[d].to(torch.float64) + torch.rand(N, device=dev, generator=gen,
+                                                        dtype=torch.float64)).to(td)
+            top = torch.nextafter((idx[d] + 1).to(td), torch.zeros((), device=dev, dtype=td))
+            x[d] = torch.where(torch.floor(xd) != idx[d].to(td), top, xd)
+            del xd, top
+        del idx
+        if wl.lognormal_sigma > 0:
+            sg = wl.lognormal_sigma
+            w = torch.exp(sg * torch.randn(N, device=dev, generator=gen) - 0.5 * sg * sg).to(td)
+        else:
+            w = torch.ones(N, device=dev, dtype=td)
+        p = None
+        if name == "electrons":
+            kind, Z, A = KIND_ELECTRON, -1.0, 0.0
+            w_ref = wl.n_e * V / wl.ppc
+            dens_scale = ne_cell / wl.n_e
+            sig = torch.sqrt(T_cell / _ME_KEV)[cell]
+            p = (torch.randn((3, N), device=dev, generator=gen, dtype=torch.float64) * sig).to(td)
+            del sig
+        elif name == "ions":
+            kind, Z, A = KIND_ION, float(wl.Z), float(wl.A)
+            w_ref = wl.n_e / wl.Z * V / wl.ppc
+            dens_scale = ne_cell / wl.n_e
+        else:
+            kind, Z, A = KIND_PHOTON, 0.0, 0.0
+            w_ref = blackbody_density(wl.T_keV) * V / wl.ppc
+            dens_scale = (T_cell / wl.T_keV) ** 3
+            jj = torch.searchsorted(cdf, torch.rand(N, device=dev, generator=gen,
+                                                    dtype=torch.float64)).clamp_(max=J - 1) + 1
+            g3 = -torch.log(torch.rand((3, N), device=dev, generator=gen,
+                                       dtype=torch.float64).clamp_(min=1e-300)).sum(0)
+            om = g3 / jj * T_cell[cell] / _ME_KEV
+            del jj, g3
+            mu = 2.0 * torch.rand(N, device=dev, generator=gen, dtype=torch.float64) - 1.0
+            phi = 2.0 * math.pi * torch.rand(N, device=dev, generator=gen, dtype=torch.float64)
+            sn = torch.sqrt(torch.clamp(1.0 - mu * mu, min=0.0))
+            p = torch.stack([sn * torch.cos(phi) * om, sn * torch.sin(phi) * om, mu * om]).to(td)
+            del mu, phi, sn, om
+        if graded:
+            w = (w.to(torch.float64) * dens_scale[cell]).to(td)
+        off = torch.zeros(ncell + 1, device=dev, dtype=torch.int64)
+        off[1:] = torch.cumsum(counts, 0)
+        species[name] = dict(x=x, p=p, w=w, id=None, id0=id_base, cell=cell.to(torch.int32),
+                             off=off, w_ref=float(w_ref), kind=kind, Z=Z, A=A, n=N)
+        del cell, counts
+        id_base += N
+    return dict(grid=wl.grid(), species=species, T_cell=T_np.astype(np.float64), next_id=id_base)
+
+
 # ---------------------------------------------------------------------------
 # The five workloads.  Method parameters that the workload descriptions leave
 # open (axion macro-weight, cap, boost) are fixed here as plain numbers.
@@ -302,14 +387,18 @@ def config3(n=(1024, 1024), ppc=32, ratio=100.0, seed=0, **kw) -> Workload:
 def config5(n=(256, 256, 256), ppc=32, seed=0, **kw) -> Workload:
     """3D 256^3, Poisson(32) per cell per species, fp32, T linear 1-5 keV and
     n_e linear 1e24-6e25 cm^-3 along x, all channels forward + inverse with
-    FP64 feedback, 200 steps."""
+    FP64 feedback, 200 steps.  Rate boost 1e32; Primakoff products (both
+    directions) carry 100 w_a, which puts the mean macro-event counts near
+    5e-3 (Primakoff), 2e-3 (Compton-like), 1e-4 (brems) and 1e-2 (a->gamma)."""
     p = Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=CH_PRIMAKOFF | CH_COMPTON | CH_BREMS,
-               inverse=1, lambda_cap=1.0, boost=1e33, feedback=1, T_mode=2, seed=seed,
+               inverse=1, lambda_cap=1.0, boost=1e32, feedback=1, T_mode=2, seed=seed,
+               wa_mul=(100.0, 1.0, 1.0),
                hist_lo_keV=0.1, hist_hi_keV=80.0, hist_nbins=128, hist_log=1)
     wl = Workload("cfg5", ndim=3, n=tuple(n), ppc=ppc, dtype="f32", T_keV=1.0, T_keV_hi=5.0,
                   n_e=1e24, n_e_hi=6e25, n_ref=6e25, Z=1, A=1.0, poisson_ppc=True, steps=200,
                   params=p)
     wl.params.w_a = (6e25 * wl.V_cell_cm3 / ppc) / 100.0
+    wl.params.w_gamma_prod = wl.params.w_a * wl.params.wa_mul[0]
     for k, v in kw.items():
         setattr(wl, k, v)
     return wl

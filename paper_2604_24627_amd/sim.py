@@ -68,6 +68,8 @@ class DeviceSpecies:
 
     @staticmethod
     def from_input(sp: Dict, kind: int, ndim: int, device, extra: int = 0) -> "DeviceSpecies":
+        if isinstance(sp["w"], torch.Tensor):
+            return DeviceSpecies._from_device(sp, kind, ndim, device, extra)
         dt = B.F64 if sp["w"].dtype == np.float64 else B.F32
         n = int(sp["n"])
         s = DeviceSpecies(kind, dt, ndim, n + extra, sp["w_ref"], device, sp["Z"], sp["A"],
@@ -85,6 +87,26 @@ class DeviceSpecies:
         ids = sp["id"]
         if n and np.array_equal(ids, ids[0] + np.arange(n, dtype=np.uint64)):
             s.id0, s.n_implicit = int(ids[0]), n
+        return s
+
+    @staticmethod
+    def _from_device(sp: Dict, kind: int, ndim: int, device, extra: int) -> "DeviceSpecies":
+        """From device tensors (inputs.make_plasma_device); ids implicit from id0."""
+        dt = B.F64 if sp["w"].dtype == torch.float64 else B.F32
+        n = int(sp["n"])
+        s = DeviceSpecies(kind, dt, ndim, n + extra, sp["w_ref"], device, sp["Z"], sp["A"],
+                          with_p=sp["p"] is not None)
+        s.n = n
+        for d in range(ndim):
+            s.x[d][:n].copy_(sp["x"][d])
+        if sp["p"] is not None:
+            for d in range(3):
+                s.p[d][:n].copy_(sp["p"][d])
+        s.w[:n].copy_(sp["w"])
+        torch.arange(sp["id0"], sp["id0"] + n, out=s.id[:n])
+        s.cell[:n].copy_(sp["cell"])
+        s.off = sp["off"].to(device)
+        s.id0, s.n_implicit = int(sp["id0"]), n
         return s
 
     def struct(self) -> B.SpeciesC:

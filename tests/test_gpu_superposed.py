@@ -126,3 +126,24 @@ def test_full_size_superposed_emission_matches_oracle_and_power():
         Qmc = h[i].sum() * KEV_ERG / (V * 6 * dtp)
         print(f"[superposed] channel {i}: MC power / closed form {Qmc / Q:.5f}", flush=True)
         assert Qmc == pytest.approx(Q, rel=0.015), i
+
+
+def test_superposed_emission_with_empty_and_sparse_cells():
+    """Poisson(3) electrons per cell: empty cells, single-electron cells, lognormal weights."""
+    p = I.Params(channels=6, g_ae=1e-13, w_a=1e-38, wa_mul=(1.0, 1.0, 0.08), lambda_cap=0.5)
+    wl = I.Workload("sparse", ndim=2, n=(40, 30), ppc=3, dtype="f32", T_keV=3.0, n_e=6e25,
+                    n_ref=6e25, lognormal_sigma=0.5, poisson_ppc=True, params=p)
+    pl = I.make_plasma(wl, 9)
+    off = pl["species"]["electrons"]["off"]
+    counts = np.diff(off)
+    assert (counts == 0).sum() > 20 and (counts == 1).sum() > 50
+    print(f"[superposed] sparse cells n={wl.n} empty={(counts == 0).sum()}", flush=True)
+    g = AxpicSim(pl, wl.params, thermal="cells")
+    o = O.OracleSim(pl, wl.params, prec32=True)
+    cells = o.cells()
+    tot = 0
+    for step in range(4):
+        k, Lam, N, prod = check_step(g, pl, cells, o.params, step)
+        assert np.all(N[:, counts == 0] == 0)
+        tot += k
+    assert tot > 500

@@ -976,6 +976,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
 // and a 16-lane shuffle reduction, then the affine remap and the temperature
 // update of each cell.
 constexpr int kCellLanes = 16;
+constexpr int kFbCache = 4;            // electrons per lane kept in registers (64 per cell)
 
 __device__ __forceinline__ double group_sum16(double v) {
 #pragma unroll
@@ -1005,7 +1006,21 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     if (!__any(work)) return;
     const int64_t lo = work ? off[c] : 0, hi = work ? off[c + 1] : 0;
     double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
-    for (int64_t i = lo + sub; i < hi; i += kCellLanes) {
+    // the first kFbCache electrons of each lane stay in registers for the remap
+    T cx[kFbCache], cy[kFbCache], cz[kFbCache];
+#pragma unroll
+    for (int q = 0; q < kFbCache; ++q) {
+        const int64_t i = lo + sub + (int64_t)q * kCellLanes;
+        cx[q] = cy[q] = cz[q] = (T)0;
+        if (i < hi) {
+            const double wi = w_ref * (double)w[i];
+            cx[q] = px[i]; cy[q] = py[i]; cz[q] = pz[i];
+            const double a = cx[q], b = cy[q], d = cz[q];
+            W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
+            U2 += wi * (a * a + b * b + d * d);
+        }
+    }
+    for (int64_t i = lo + sub + (int64_t)kFbCache * kCellLanes; i < hi; i += kCellLanes) {
         const double wi = w_ref * (double)w[i];
         const double a = px[i], b = py[i], d = pz[i];
         W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
@@ -1045,7 +1060,16 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     if (kp.feedback && has_fb) {
         const double b0 = (1.0 - S) * (P0 / W) + d0, b1 = (1.0 - S) * (P1 / W) + d1,
                      b2 = (1.0 - S) * (P2 / W) + d2;
-        for (int64_t i = lo + sub; i < hi; i += kCellLanes) {
+#pragma unroll
+        for (int q = 0; q < kFbCache; ++q) {
+            const int64_t i = lo + sub + (int64_t)q * kCellLanes;
+            if (i < hi) {
+                px[i] = (T)(S * (double)cx[q] + b0);
+                py[i] = (T)(S * (double)cy[q] + b1);
+                pz[i] = (T)(S * (double)cz[q] + b2);
+            }
+        }
+        for (int64_t i = lo + sub + (int64_t)kFbCache * kCellLanes; i < hi; i += kCellLanes) {
             px[i] = (T)(S * (double)px[i] + b0);
             py[i] = (T)(S * (double)py[i] + b1);
             pz[i] = (T)(S * (double)pz[i] + b2);

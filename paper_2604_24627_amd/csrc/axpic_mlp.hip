@@ -288,7 +288,8 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
     return y + bias[4 * kDH];
 }
 
-// y for all 64 particles of a wavefront (two 32-particle passes).
+// y for all 64 particles of a wavefront (two 32-particle passes; a single pass of
+// four tiles needs the accumulators of one wave per SIMD, which measured slower).
 __device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const float* __restrict__ bias,
                                           const float f[8]) {
     const float y0 = mlp_pass(frag, bias, f, 0);
@@ -618,7 +619,8 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
             ncu = v;
     }
     const int64_t tiles = (sp->n + 63) / 64;
-    const int64_t wgs = std::min<int64_t>((tiles + 7) / 8, (int64_t)ncu);
+    constexpr int kWaves = kInfThreads / 64;
+    const int64_t wgs = std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)ncu);
     const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
     if (sp->dtype == AXPIC_F32)
         LAUNCH("k_rates_mlp", k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreads), 0,

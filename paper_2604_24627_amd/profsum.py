@@ -2,8 +2,10 @@
 
 kernel_stats(csv)        -> {kernel: (calls, avg_ns)}   from --kernel-trace --stats
 counters(csv)            -> {kernel: [value per dispatch]} from --pmc <counter>
-source_digest()          -> SHA-256 of the HIP sources (csrc/), which names the
-                            kernels a set of counters was taken from
+source_digest()          -> SHA-256 of the sources the stepping kernels are
+                            compiled from (axpic.hip and its device headers),
+                            which names the kernels a set of counters was taken
+                            from; traffic lines cover only kernels of that unit
 read_traffic(path)       -> the per-dispatch HBM bytes recorded in a summary,
                             or None when the kernels have changed since
 Kernel names are reduced to the bare function name (k_...).
@@ -26,14 +28,23 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
+STEP_SOURCES = ("axpic.hip", "axpic_device.hpp", "axpic_timing.hpp")
+
+
 def source_digest(root: str = CSRC) -> str:
     h = hashlib.sha256()
-    for name in sorted(os.listdir(root)):
-        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(name.encode())
-            with open(os.path.join(root, name), "rb") as f:
-                h.update(f.read())
+    for name in STEP_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(root, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
+
+
+def step_kernels(root: str = CSRC) -> set:
+    """Names of the __global__ kernels defined in the stepping unit."""
+    with open(os.path.join(root, STEP_SOURCES[0])) as f:
+        text = f.read()
+    return set(re.findall(r"\b(k_[A-Za-z0-9_]+)\s*\(", text))
 
 
 def read_traffic(path: str, kernel: str):
@@ -102,7 +113,8 @@ def main(argv):
     print(f"counter scale (copy-calibrated): fetch x{scale_f:.4f} write x{scale_w:.4f}")
     if fetch and write:
         print("per-dispatch HBM bytes (kernel fetch write):")
-        for k in sorted(k for k in set(fetch) & set(write) if k.startswith("k_")):
+        own = step_kernels()
+        for k in sorted(k for k in set(fetch) & set(write) if k in own):
             fb = statistics.median(fetch[k]) * 1024 * scale_f
             wb = statistics.median(write[k]) * 1024 * scale_w
             print(f"traffic {k} {fb:.6g} {wb:.6g}")

@@ -247,6 +247,47 @@ def make_plasma(wl: Workload, seed: Optional[int] = None) -> Dict:
                 next_id=id_base)
 
 
+def make_axions(wl: Workload, plasma: Dict, per_cell: float, seed: int,
+                zero_frac: float = 0.02) -> Dict:
+    """A seeded axion population for operator tests, built from inputs only.
+
+    Poisson(per_cell) axions per cell, grouped by cell; positions uniform in
+    the cell; energies x T_cell with x drawn from the blackbody shape
+    x^2/(e^x-1) (the massless equilibrium spectrum); isotropic directions;
+    lognormal relative weights (sigma 0.5, unit mean) of which a fraction
+    zero_frac is exactly zero (dead axions); w_ref = the parameters' w_a; ids
+    continue from plasma["next_id"].  Same keys as a make_plasma species, plus
+    next_id (the first id after these)."""
+    dt = np.float64 if wl.dtype == "f64" else np.float32
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xA7A7])))
+    counts = rng.poisson(per_cell, wl.ncell).astype(np.int64)
+    x, cell = _positions(wl, counts, rng, dt)
+    N = cell.size
+    T_cell = plasma["T_cell"]
+    om = _blackbody_x(rng, N) * T_cell[cell.astype(np.int64)] / _ME_KEV
+    p = (_isotropic(rng, N) * om).astype(dt)
+    w = np.exp(0.5 * rng.standard_normal(N) - 0.125)
+    w[rng.random(N) < zero_frac] = 0.0
+    off = np.zeros(wl.ncell + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    id0 = int(plasma["next_id"])
+    return dict(x=x, p=p, w=w.astype(dt), id=np.arange(N, dtype=np.uint64) + np.uint64(id0),
+                cell=cell, off=off, w_ref=float(wl.params.w_a), kind=KIND_AXION, Z=0.0, A=0.0,
+                n=N, next_id=id0 + N)
+
+
+def means(n: int, seed: int, rows: int = 1, lo: float = 1e-4, hi: float = 3.0,
+          zero_frac: float = 0.02, dtype: str = "f32") -> np.ndarray:
+    """Seeded Poisson means for the rate-fed sampling calls: log-uniform in
+    [lo, hi], a fraction zero_frac exactly zero; shape (rows, n) (or (n,) when
+    rows is 1), in the workload's storage type."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x1A3B, rows])))
+    lam = np.exp(rng.uniform(math.log(lo), math.log(hi), (rows, n)))
+    lam[rng.random((rows, n)) < zero_frac] = 0.0
+    lam = lam.astype(np.float64 if dtype == "f64" else np.float32)
+    return lam[0] if rows == 1 else lam
+
+
 def make_plasma_device(wl: Workload, seed: Optional[int] = None, device="cuda") -> Dict:
     """The workload recipe of make_plasma drawn with torch's generator on the
     GPU, for plasmas too large to build on the host (the 256^3 graded plasma

@@ -213,6 +213,20 @@ class AxpicSim:
                                                 self.ncell, B.ptr(self.cellw), s), "cell_weights")
             self._ensure_ws(4 * self.ncell)
 
+    def load_axions(self, sp: Dict, extra: int = 0):
+        """Replace the axion buffer by a given population (a make_plasma-style species
+        dict of relative weights with w_ref = w_a); ids after it are issued from its
+        next_id on."""
+        if abs(sp["w_ref"] - self.pdict["w_a"]) > 1e-12 * abs(self.pdict["w_a"]):
+            raise ValueError("axion w_ref must equal the parameters' w_a")
+        ax = DeviceSpecies.from_input(sp, B.AXION, self.ndim, self.device, extra=extra)
+        if ax.dtype != self.dtype:
+            raise ValueError("axion dtype differs from the plasma's")
+        ax.id0 = ax.n_implicit = 0          # every id stored: appended ids continue elsewhere
+        self.ax = ax
+        self.next_id = max(self.next_id, int(sp.get("next_id", 0)))
+        self._ensure_ws(self.ax.capacity)
+
     @property
     def sh(self):
         return B.stream_handle(self.stream)

@@ -2,15 +2,16 @@
 
 * The all-channel forward plasma at full size (2D 512x512, 64 per cell per
   species, fp32), which is the launch configuration of the benchmark.  The
-  GPU runs its fused count kernels (no rates handed in).  The oracle, fed the
-  GPU's materialised FP32 means, then decides every one of the 16.8M photons
-  and 16.8M electrons.  Event counts, product ids, cells and momenta must be
-  bit-identical, and all means must agree with the oracle's own to 1e-5.
-  The integrated power of the channels over a few steps must match the
-  closed-form emissivities.
+  means the fused count kernels compute, materialised, must agree with the
+  oracle's own to 1e-5 for every photon and electron; the fused kernels must
+  decide exactly as the rate-fed path fed those means (GPU alone); and with
+  the same seeded means fed to both sides, every one of the 16.8M photons'
+  and 16.8M electrons' event counts, product ids, cells and momenta must
+  equal the oracle's.  The integrated power of the channels over a few
+  steps must match the closed-form emissivities.
 * The graded 3D plasma with Poisson per-cell counts, in the large-plasma
-  recipe at a size the oracle runs whole.  One full step is checked element
-  by element.
+  recipe at a size the oracle runs whole: the same three checks for one
+  step, then the feedback and temperature update element by element.
 * Forward + inverse relaxation with lognormal weights and a macro-weight
   ratio of 100, one thermal channel at a time.  The axion number per energy
   bin must follow the detailed-balance recursion, which has a closed form.
@@ -40,6 +41,42 @@ def np64(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def same_population(a, b):
+    x, y = a.to_numpy(), b.to_numpy()
+    assert a.n == b.n
+    for key in ("w", "id", "cell"):
+        np.testing.assert_array_equal(x[key], y[key])
+    np.testing.assert_array_equal(x["p"], y["p"])
+    np.testing.assert_array_equal(x["x"], y["x"])
+
+
+def check_means_and_fused(g, pl, wl, o, cells):
+    """Materialised means against the oracle's own; then a second simulation fed
+    those means must emit exactly what the fused kernels of `g` emit."""
+    lamP = g.rates(g.ph, B.PRIMAKOFF).clone()
+    lamT = torch.stack([g.rates(g.el, B.COMPTON), g.rates(g.el, B.BREMS)]).contiguous()
+    _, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph.copy(), 0, 1 << 40)
+    np.testing.assert_allclose(np64(lamP), olamP, rtol=1e-5)
+    del olamP
+    _, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el.copy(), 0, 1 << 40)
+    np.testing.assert_allclose(np64(lamT), olamT, rtol=1e-5)
+    del olamT
+    g2 = AxpicSim(pl, wl.params)
+    g.fb.zero_(); g2.fb.zero_()
+    kP, kP2 = g.emit_primakoff(), g2.emit_primakoff(lam_in=lamP)
+    kT, kT2 = g.emit_thermal(), g2.emit_thermal(lam_in=lamT.reshape(-1))
+    print(f"[configs] fused vs rate-fed: Primakoff {kP}/{kP2}, thermal {kT}/{kT2}", flush=True)
+    assert kP == kP2 and kT == kT2 and kP > 200 and kT > 200
+    same_population(g.ax, g2.ax)
+    np.testing.assert_array_equal(np64(g.ph.w[: g.ph.n]), np64(g2.ph.w[: g2.ph.n]))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g.fb.cpu().numpy(), g2.fb.cpu().numpy(), rtol=1e-12, atol=0)
+
+
 def products_equal(gsp, n0, prod, w_ref, exact_p, rtol_w=1e-6, rtol_p=1e-6):
     n = prod["w"].size
     assert gsp.n - n0 == n
@@ -62,39 +99,43 @@ def test_full_size_forward_plasma_bit_exact_and_power():
     print(f"[configs] full-size forward plasma n={wl.n} ppc={wl.ppc} dtype={wl.dtype}", flush=True)
     g = AxpicSim(pl, wl.params)
     o = O.OracleSim(pl, wl.params, prec32=True)
-    del pl
     cells = o.cells()
     st = g.state.cpu().numpy().reshape(-1, B.STATE_N)
     for k, f in enumerate(["T", "n_e", "n_e_dep", "nZ", "nZ2", "rho", "XH", "kappa2", "G_P0",
                            "G_C", "G_B"]):
         np.testing.assert_allclose(st[:, k], cells[f], rtol=1e-12, atol=0, err_msg=f)
-    # materialised means, then the fused kernels as the step runs them (nothing handed in)
-    lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
-    lamT = np.stack([np64(g.rates(g.el, B.COMPTON)), np64(g.rates(g.el, B.BREMS))])
-    n0 = g.ax.n
-    kP = g.emit_primakoff()
-    prodP, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, g.next_id - kP,
-                                       lam_in=lamP)
-    np.testing.assert_allclose(lamP, olamP, rtol=1e-5)
+    # the fused kernels as the step runs them: their means against the oracle's own, their
+    # decisions against the rate-fed path fed those means
+    check_means_and_fused(g, pl, wl, o, cells)
+    # the same seeded means on both sides: every decision, id, cell and momentum
+    g3 = AxpicSim(pl, wl.params)
+    del pl
+    lamP = I.means(g3.ph.n, seed=41, lo=1e-5, hi=2.0)
+    n0, id0 = g3.ax.n, g3.next_id
+    kP = g3.emit_primakoff(lam_in=dev(lamP))
+    prodP, _, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, id0,
+                                   lam_in=lamP.astype(np.float64))
     print(f"[configs] Primakoff events {kP}", flush=True)
     assert kP == prodP["w"].size and kP > 10000
-    products_equal(g.ax, n0, prodP, g.ax.w_ref, exact_p=True)
-    np.testing.assert_allclose(np64(g.ph.w[: g.ph.n]) * g.ph.w_ref, o.ph.w, rtol=1e-6)
-    n0 = g.ax.n
-    g.fb.zero_()
-    kT = g.emit_thermal()
-    fb = np.zeros(g.ncell * 4)
-    prodT, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, g.next_id - kT, fb,
-                                     lam_in=lamT)
-    np.testing.assert_allclose(lamT, olamT, rtol=1e-5)
+    products_equal(g3.ax, n0, prodP, g3.ax.w_ref, exact_p=True)
+    np.testing.assert_allclose(np64(g3.ph.w[: g3.ph.n]) * g3.ph.w_ref, o.ph.w, rtol=1e-6)
+    del prodP, lamP
+    lamT = I.means(g3.el.n, seed=42, rows=2, lo=1e-5, hi=0.5)
+    n0, id0 = g3.ax.n, g3.next_id
+    g3.fb.zero_()
+    kT = g3.emit_thermal(lam_in=dev(lamT.reshape(-1)))
+    fb = np.zeros(g3.ncell * 4)
+    prodT, _, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, id0, fb,
+                                 lam_in=lamT.astype(np.float64))
     print(f"[configs] thermal events {kT}", flush=True)
     assert kT == prodT["w"].size and kT > 20000
-    products_equal(g.ax, n0, prodT, g.ax.w_ref, exact_p=False)
+    products_equal(g3.ax, n0, prodT, g3.ax.w_ref, exact_p=False)
     torch.cuda.synchronize()
-    np.testing.assert_allclose(g.fb.cpu().numpy(), fb, rtol=1e-6, atol=1e-9 * np.abs(fb).max())
+    np.testing.assert_allclose(g3.fb.cpu().numpy(), fb, rtol=1e-6, atol=1e-9 * np.abs(fb).max())
+    del g3, prodT, lamT
     # integrated power of every channel over a few more full steps (the emission above was
     # step 0)
-    del o, prodP, prodT
+    del o
     g.step_index = 1
     for _ in range(4):
         g.step()
@@ -124,18 +165,19 @@ def test_graded_poisson_plasma_one_step_elementwise():
     for k, f in enumerate(["T", "n_e", "n_e_dep", "nZ", "nZ2", "rho", "XH", "kappa2", "G_P0",
                            "G_C", "G_B"]):
         np.testing.assert_allclose(st[:, k], cells[f], rtol=1e-12, atol=0, err_msg=f)
-    lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
-    lamT = np.stack([np64(g.rates(g.el, B.COMPTON)), np64(g.rates(g.el, B.BREMS))])
+    check_means_and_fused(g, pl, wl, o, cells)
+    g = AxpicSim(pl, wl.params)
+    lamP = I.means(g.ph.n, seed=43, lo=1e-4, hi=2.0)
+    lamT = I.means(g.el.n, seed=44, rows=2, lo=1e-4, hi=2.0)
     g.fb.zero_()
-    kP = g.emit_primakoff()
-    kT = g.emit_thermal()
+    id0 = g.next_id
+    kP = g.emit_primakoff(lam_in=dev(lamP))
+    kT = g.emit_thermal(lam_in=dev(lamT.reshape(-1)))
     fb = np.zeros(g.ncell * 4)
-    prodP, olamP, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, g.next_id - kP - kT,
-                                       lam_in=lamP)
-    prodT, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, g.next_id - kT, fb,
-                                     lam_in=lamT)
-    np.testing.assert_allclose(lamP, olamP, rtol=1e-5)
-    np.testing.assert_allclose(lamT, olamT, rtol=1e-5)
+    prodP, _, _ = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, id0,
+                                   lam_in=lamP.astype(np.float64))
+    prodT, _, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, id0 + kP, fb,
+                                 lam_in=lamT.astype(np.float64))
     print(f"[configs] events Primakoff {kP} thermal {kT}", flush=True)
     assert kP == prodP["w"].size and kT == prodT["w"].size and kP > 200 and kT > 200
     products_equal(g.ax, 0, dict((k, np.concatenate([prodP[k], prodT[k]], axis=-1))

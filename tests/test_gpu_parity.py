@@ -4,8 +4,11 @@ Inputs are the seeded synthetic plasmas of paper_2604_24627_amd.inputs, at
 sizes the oracle finishes in seconds that still span several 1024-particle
 tiles and a ragged tail.  Bars:
   * integer work (event counts, product ids, absorption decisions, cell
-    indices, push in binary32) is bit-exact, with the oracle fed the GPU's
-    own FP32 means where the decision depends on them;
+    indices, push in binary32) is bit-exact.  Where a decision depends on a
+    mean, both sides are fed the same seeded means (inputs.means) through the
+    rate-fed entry; that the fused kernels decide exactly as when fed their
+    own materialised means is checked on the GPU alone, and those means are
+    checked against the oracle's own to the rate tolerance below;
   * FP32 rates within 1e-5 relative of the FP64 oracle; FP64 paths 1e-11;
   * sampled energies within 1e-6 relative (quantile-table accuracy 2e-8
     plus binary32 storage);
@@ -48,6 +51,10 @@ def np64(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
 def test_cell_state_matches_oracle():
     for Z, A in ((1, 1.0), (2, 4.0)):
         wl = small_workload(channels=7, inverse=1, g_ae=1e-13, boost=1e30)
@@ -65,7 +72,7 @@ def test_cell_state_matches_oracle():
 def test_rates_match_oracle(dtype):
     wl = small_workload(dtype, channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=1e33,
                         w_a=1e-36)
-    g, o, _ = pair(wl)
+    g, o, pl = pair(wl)
     rtol = 1e-5 if dtype == "f32" else 1e-11
     cells = o.cells()
     lamP = np64(g.rates(g.ph, B.PRIMAKOFF))
@@ -75,20 +82,19 @@ def test_rates_match_oracle(dtype):
     _, olamT, _ = O.emit_thermal(o.grid, o.params, cells, o.el, 0, 1 << 40)
     np.testing.assert_allclose(lamC, olamT[0], rtol=rtol)
     np.testing.assert_allclose(lamB, olamT[1], rtol=rtol)
-    # axions: the population the GPU creates in two steps, handed to the oracle as is
-    for _ in range(2):
-        g.step()
+    # axions: a seeded population given to both sides
+    axd = I.make_axions(wl, pl, 8.0, seed=11)
+    g.load_axions(axd)
     assert g.ax.n > 1000
     pab = np64(g.rates(g.ax, B.COMPTON | B.BREMS))
     lag = np64(g.rates(g.ax, B.PRIMAKOFF))
-    a = g.ax.to_numpy()
-    ax = O.OSpecies(a["x"], a["p"], a["w"].astype(np.float64) * g.ax.w_ref, a["id"], a["cell"])
-    _, opab, olag, _, _ = O.absorb(o.grid, o.params, cells, ax.copy(), 0, 1 << 40)
+    _, opab, olag, _, _ = O.absorb(o.grid, o.params, cells, O.OSpecies.from_input(axd), 0, 1 << 40)
     big = opab > 1e-30
     np.testing.assert_allclose(pab[big], opab[big], rtol=rtol * 3)
+    assert np.all(pab[~big] <= 1e-30)
     # the a->gamma mean is taken before absorption here; compare where nothing was absorbed
     prm_noabs = dict(o.params, channels=1)
-    _, _, olag2, _, _ = O.absorb(o.grid, prm_noabs, cells, ax.copy(), 0, 1 << 40)
+    _, _, olag2, _, _ = O.absorb(o.grid, prm_noabs, cells, O.OSpecies.from_input(axd), 0, 1 << 40)
     np.testing.assert_allclose(lag, olag2, rtol=rtol)
 
 
@@ -111,17 +117,18 @@ def _compare_products(gsp, n0, prod, w_ref, rtol_w, exact_p=True, rtol_p=1e-6):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_primakoff_emission_bit_exact_counts(dtype):
+    """Rate-fed conversion: both sides draw from the same seeded means (some above the
+    cap), three steps in a row on the depleted photons."""
     wl = small_workload(dtype, channels=1, g_agg_GeV=1e-10, w_a=2e-35, lambda_cap=0.7)
     g, o, _ = pair(wl)
     cells = o.cells()
     for step in range(3):
-        lam = g.rates(g.ph, B.PRIMAKOFF)
-        lam64 = np64(lam)
-        n0 = g.ax.n
+        lam = I.means(g.ph.n, seed=100 + step, dtype=dtype)
+        n0, id0 = g.ax.n, g.next_id
         g.step_index = step; o.step_index = step
-        k = g.emit_primakoff()
-        prod, olam, K = O.emit_primakoff(o.grid, o.params, cells, o.ph, step, g.next_id - k,
-                                         o.hist, o.stats, lam_in=lam64)
+        k = g.emit_primakoff(lam_in=dev(lam))
+        prod, olam, K = O.emit_primakoff(o.grid, o.params, cells, o.ph, step, id0,
+                                         o.hist, o.stats, lam_in=lam.astype(np.float64))
         assert k == prod["w"].size and k > 200
         _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6 if dtype == "f32" else 1e-13)
         np.testing.assert_allclose(np64(g.ph.w[: g.ph.n]) * g.ph.w_ref, o.ph.w,
@@ -136,21 +143,21 @@ def test_primakoff_emission_bit_exact_counts(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_thermal_emission_matches_oracle(dtype):
+    """Rate-fed Compton + brems emission from the same seeded means on both sides."""
     wl = small_workload(dtype, channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=0.5)
     wl.params.wa_mul = (1.0, 1.0, 0.35)
     g, o, _ = pair(wl)
     cells = o.cells()
     fb_o = np.zeros(g.ncell * 4)
     for step in range(2):
-        lam = torch.stack([g.rates(g.el, B.COMPTON), g.rates(g.el, B.BREMS)]).contiguous()
-        lam64 = np64(lam)
-        n0 = g.ax.n
+        lam = I.means(g.el.n, seed=200 + step, rows=2, dtype=dtype)
+        n0, id0 = g.ax.n, g.next_id
         g.step_index = step
         g.fb.zero_()
-        k = g.emit_thermal(lam_in=lam.reshape(-1))
+        k = g.emit_thermal(lam_in=dev(lam.reshape(-1)))
         fb_o[:] = 0.0
-        prod, _, K = O.emit_thermal(o.grid, o.params, cells, o.el, step, g.next_id - k, fb_o,
-                                    o.hist, o.stats, lam_in=lam64)
+        prod, _, K = O.emit_thermal(o.grid, o.params, cells, o.el, step, id0, fb_o,
+                                    o.hist, o.stats, lam_in=lam.astype(np.float64))
         assert k == prod["w"].size and k > 1000
         assert (prod["chan"] == 1).sum() > 300 and (prod["chan"] == 2).sum() > 300
         _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6 if dtype == "f32" else 1e-13,
@@ -179,13 +186,43 @@ def test_fused_thermal_counts_equal_rate_fed_counts():
     np.testing.assert_array_equal(a["p"], b["p"])
 
 
+def test_fused_primakoff_and_absorption_equal_rate_fed():
+    """The fused conversion and absorption kernels decide exactly as when they are fed
+    their own materialised means (GPU alone; the means themselves are checked against
+    the oracle in test_rates_match_oracle)."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=4e33,
+                        w_a=1e-36, lambda_cap=1.0)
+    g1, _, pl = pair(wl)
+    g2 = AxpicSim(pl, wl.params)
+    lam = g2.rates(g2.ph, B.PRIMAKOFF).clone()
+    k1 = g1.emit_primakoff()
+    k2 = g2.emit_primakoff(lam_in=lam)
+    assert k1 == k2 > 100
+    axd = I.make_axions(wl, pl, 16.0, seed=14)
+    for g in (g1, g2):
+        g.load_axions(axd)
+        g.step_index = 2
+    pab = g2.rates(g2.ax, B.COMPTON | B.BREMS).clone()
+    lag = g2.rates(g2.ax, B.PRIMAKOFF).clone()
+    n = g1.ax.n
+    k1 = g1.absorb(n)
+    k2 = g2.absorb(n, pabs_in=pab, lam_in=lag)
+    assert k1 == k2
+    for a, b in ((g1.ax, g2.ax), (g1.ph, g2.ph)):
+        x, y = a.to_numpy(), b.to_numpy()
+        for key in ("w", "id", "cell"):
+            np.testing.assert_array_equal(x[key], y[key])
+        np.testing.assert_array_equal(x["p"], y["p"])
+    assert (g1.ax.to_numpy()["w"] == 0).sum() > (axd["w"] == 0).sum() + 20
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_push_and_binning_bit_exact(dtype):
     wl = small_workload(dtype, channels=1, g_agg_GeV=1e-10, w_a=2e-35)
-    g, o, _ = pair(wl)
-    g.emit_primakoff()
-    ax = g.ax.to_numpy()
-    osp = O.OSpecies(ax["x"], ax["p"], ax["w"], ax["id"], ax["cell"])
+    g, o, pl = pair(wl)
+    axd = I.make_axions(wl, pl, 8.0, seed=12)
+    g.load_axions(axd)
+    osp = O.OSpecies.from_input(axd)
     for _ in range(7):
         g.bin_axions(push=True)
         O.push(o.grid, osp, dtype == "f32")
@@ -197,34 +234,36 @@ def test_push_and_binning_bit_exact(dtype):
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_absorption_decisions_bit_exact(mode):
+    """Rate-fed absorption (delete or reduce) and a->gamma on a seeded axion population,
+    both sides given the same seeded probabilities and means."""
     wl = small_workload("f32", channels=7 if mode == 0 else 6, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=4e33,
                         w_a=1e-36, lambda_cap=1.0, absorb_mode=mode)
-    g, o, _ = pair(wl)
-    for _ in range(3):
-        g.step()
+    g, o, pl = pair(wl)
     cells = o.cells()
+    axd = I.make_axions(wl, pl, 12.0, seed=13 + mode)
+    g.load_axions(axd)
     n = g.ax.n
     assert n > 2000
-    pab = g.rates(g.ax, B.COMPTON | B.BREMS).clone()
-    lag = g.rates(g.ax, B.PRIMAKOFF).clone()
-    ax = g.ax.to_numpy()
-    osp = O.OSpecies(ax["x"], ax["p"], ax["w"].astype(np.float64) * g.ax.w_ref, ax["id"], ax["cell"])
+    pab = I.means(n, seed=30, lo=1e-5, hi=0.6)
+    lag = I.means(n, seed=31, lo=1e-4, hi=2.0)
+    osp = O.OSpecies.from_input(axd)
     g.fb.zero_()
-    ph_n0 = g.ph.n
+    ph_n0, id0 = g.ph.n, g.next_id
     g.step_index = 3
     st0 = g.stats_dict()
-    k = g.absorb(n, pabs_in=pab, lam_in=lag if mode == 0 else None)
+    k = g.absorb(n, pabs_in=dev(pab), lam_in=dev(lag) if mode == 0 else None)
     fb_o = np.zeros(g.ncell * 4)
     st_o = np.zeros(O.ST_COUNT)
     prm = dict(o.params, w_gamma_prod=g.ph.w_ref)
-    prod, _, _, K, dead = O.absorb(o.grid, prm, cells, osp, 3, g.next_id - k, fb_o, st_o,
-                                   pabs_in=np64(pab), lam_in=np64(lag) if mode == 0 else None)
+    prod, _, _, K, dead = O.absorb(o.grid, prm, cells, osp, 3, id0, fb_o, st_o,
+                                   pabs_in=pab.astype(np.float64),
+                                   lam_in=lag.astype(np.float64) if mode == 0 else None)
     assert k == prod["w"].size
     gw = np64(g.ax.w[:n]) * g.ax.w_ref
     np.testing.assert_array_equal(gw == 0.0, osp.w == 0.0)
     np.testing.assert_allclose(gw, osp.w, rtol=2e-6, atol=0)
     if mode == 0:
-        assert dead.sum() > 50
+        assert dead.sum() > 50 and k > 100
         _compare_products(g.ph, ph_n0, prod, g.ph.w_ref, rtol_w=1e-6)
     torch.cuda.synchronize()
     np.testing.assert_allclose(g.fb.cpu().numpy(), fb_o, rtol=1e-6, atol=1e-9 * np.abs(fb_o).max())

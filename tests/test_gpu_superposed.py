@@ -1,11 +1,12 @@
 """Thermal emission by per-cell superposition on the GPU (needs an MI355X).
 
 The oracle's superposed operator (oracle/axpic_oracle.c, pinned against the
-per-electron law) is fed the GPU's per-cell channel coefficients and weight
-sums, and must then draw the same cell totals, pick the same electrons and
-sample the same energies: counts, ids, cells and positions bit-exact,
-momenta and weights to 1e-6 (FP32 storage; energies from the quantile
-tables), exchange buffers to 1e-6.  Cases: lognormal weights with electrons
+per-electron law) runs on the same seeded plasma with its own cell weight
+sums and its own per-cell channel coefficients, rounded to the precision the
+kernels store them in (binary32 for fp32 plasmas), and must then draw the
+same cell totals, pick the same electrons and sample the same energies:
+counts, ids, cells and positions bit-exact, momenta and weights to 1e-6 (FP32
+storage; energies from the quantile tables), exchange buffers to 1e-6.  Cases: lognormal weights with electrons
 at the cap, no cap, fp32 and fp64, and the full-size 512x512 plasma, whose
 integrated power must also match the closed form.
 """
@@ -28,29 +29,29 @@ def np64(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def oracle_inputs(g, pl):
-    """The oracle's view of the GPU state: electrons in relative weights (the
-    weights the GPU sums), the GPU's FP32/FP64 channel coefficients per cell and
-    its cell weight sums."""
-    e = g.el.to_numpy()
-    osp = O.OSpecies(e["x"].astype(np.float64), e["p"].astype(np.float64),
-                     e["w"].astype(np.float64), e["id"], e["cell"])
-    pref = (g.pref32 if g.dtype == B.F32 else g.pref64).cpu().numpy().astype(np.float64)
-    coef = pref.reshape(-1, B.PREF_N)[:, 4:6].T.copy()
-    W = g.cellw.cpu().numpy()
-    off = pl["species"]["electrons"]["off"]
-    return osp, coef, W, off
+def oracle_inputs(pl, o_cells, params, f32):
+    """The oracle's view: the plasma's electrons in relative weights, and its own
+    per-cell coefficients lambda_e / w_e = Gamma dt_phys w_ref_e / (w_a wa_mul) of
+    eq. lambda_macro, stored in the kernels' precision."""
+    e = pl["species"]["electrons"]
+    osp = O.OSpecies(e["x"], e["p"], e["w"].astype(np.float64), e["id"], e["cell"])
+    dtp = O.dt_phys(pl["grid"])
+    coef = np.stack([o_cells["G_C"] * dtp * e["w_ref"] / (params["w_a"] * params["wa_mul"][1]),
+                     o_cells["G_B"] * dtp * e["w_ref"] / (params["w_a"] * params["wa_mul"][2])])
+    if f32:
+        coef = coef.astype(np.float32).astype(np.float64)
+    return osp, coef, e["off"]
 
 
 def check_step(g, pl, o_cells, params, step):
-    osp, coef, W, off = oracle_inputs(g, pl)
-    n0 = g.ax.n
+    osp, coef, off = oracle_inputs(pl, o_cells, params, g.dtype == B.F32)
+    n0, id0 = g.ax.n, g.next_id
     g.step_index = step
     g.fb.zero_()
     k = g.emit_thermal_cells()
     fb = np.zeros(g.ncell * 4)
-    prod, Lam, N = O.emit_thermal_cells(g.grid_d, params, o_cells, osp, off, step, g.next_id - k,
-                                        fb=fb, coef_in=coef, W_in=W[: g.ncell])
+    prod, Lam, N = O.emit_thermal_cells(g.grid_d, params, o_cells, osp, off, step, id0,
+                                        fb=fb, coef_in=coef)
     assert k == prod["w"].size
     sl = slice(n0, n0 + k)
     np.testing.assert_array_equal(g.ax.id[sl].cpu().numpy().view(np.uint64), prod["id"])

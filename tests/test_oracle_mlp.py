@@ -113,3 +113,141 @@ def test_brems_labels_scale_as_density_squared_through_the_screening_region():
                          [1.0], [1.0])[0]
         r.append(O.gamma_abs(c, cp, 2.0)[0])
     assert abs(math.log(r[1] / r[0]) - math.log(4.0)) > 0.05
+
+
+# ------------------------------------------------------------ per-cell surrogate tables
+
+def test_table_interpolation_is_exact_for_cubics_and_at_nodes():
+    import oracle.mlp_table as T
+    rng = np.random.default_rng(4)
+    for nodes in (4, 5, 16, 33):
+        u0, h = T.grid(0.01, 100.0, nodes)
+        un = u0 + h * np.arange(nodes)
+        c = rng.normal(size=4)
+        cubic = lambda u: c[0] + c[1] * u + c[2] * u ** 2 + c[3] * u ** 3
+        u = np.concatenate([rng.uniform(un[0], un[-1], 500), un[[0, -1]]])
+        np.testing.assert_allclose(T.interpolate(cubic(un), u0, h, u), cubic(u), rtol=1e-10,
+                                   atol=1e-10)
+        v = rng.normal(size=nodes)
+        np.testing.assert_allclose(T.interpolate(v, u0, h, un), v, rtol=0, atol=1e-12)
+    # a quartic is not reproduced: the rule is exactly cubic
+    u0, h = T.grid(0.01, 100.0, 16)
+    un = u0 + h * np.arange(16)
+    u = rng.uniform(un[0], un[-1], 200)
+    assert np.abs(T.interpolate(un ** 4, u0, h, u) - u ** 4).max() > 1e-3
+
+
+def _closed_form_logR(cell, params, x):
+    """log of the plain rates per unit coupling (Sec. II.F and eq. gamma_abs)."""
+    T0 = cell["T"]
+    lp = np.array([math.log(O.gamma_prim(cell, params, xi * T0)) for xi in x])
+    la = np.array([math.log(O.gamma_abs(cell, params, xi * T0)[0]) for xi in x])
+    return lp, la
+
+
+def test_table_interpolation_of_closed_form_rates_converges_at_fourth_order():
+    import oracle.mlp_table as T
+    p = I.Params(g_agg_GeV=1.0, g_ae=1.0, boost=1.0, channels=7, inverse=1)
+    wl = I.config2()
+    cell = O.cell_state(wl.grid(), p, np.array([3.0]), np.array([6e25]), [np.array([6e25])],
+                        [1.0], [1.0])[0]
+    x = np.exp(np.random.default_rng(5).uniform(math.log(0.01), math.log(100.0), 400))
+    lp, la = _closed_form_logR(cell, p, x)
+    errs = []
+    for nodes in (17, 33, 65):
+        u0, h = T.grid(0.01, 100.0, nodes)
+        xn = np.exp(u0 + h * np.arange(nodes))
+        np_, na = _closed_form_logR(cell, p, xn)
+        ep = np.abs(T.interpolate(np_, u0, h, np.log(x)) - lp).max()
+        ea = np.abs(T.interpolate(na, u0, h, np.log(x)) - la).max()
+        errs.append((ep, ea))
+    errs = np.array(errs)
+    assert errs[0].max() < 3e-2 and errs[-1].max() < 2e-4
+    # halving h divides the error by about 2^4
+    ratio = errs[:-1] / errs[1:]
+    assert np.all(ratio > 8.0) and np.all(ratio < 32.0), ratio
+
+
+def _random_net(seed=2):
+    P = M.init_params(seed)
+    rng = np.random.default_rng(seed)
+    for W, b in P:
+        b[:] = rng.normal(0, 0.1, b.size)
+    norm = dict(feat_lo=[math.log(0.01), -3.0, math.log(1e23), 1.0],
+                feat_sc=[2.0 / math.log(1e4), 0.5, 2.0 / math.log(1e3), 2.0],
+                out_mu=[-40.0, -20.0, -22.0, -24.0], out_sigma=[1.5, 2.0, 1.0, 0.5],
+                out_lin=rng.normal(0, 1, 16))
+    box = dict(T=(0.5, 10.0), ne=(1e23, 1e26), x=(0.01, 100.0))
+    return P, norm, box
+
+
+def test_table_slots_sum_channels_and_apply_the_screening_factor():
+    import oracle.mlp_table as T
+    P, norm, box = _random_net()
+    T7 = 1.0 * T.KEV_T7
+    rho_eta1 = 100.0 * T7 * T7 / 4.0          # X_H = 1: eta = (3 + 1) rho_2 / T_7^2 = 1
+    cells = np.zeros(4, dtype=O.CELL_DTYPE)
+    cells["T"] = [1.0, 1.0, 0.3, 1.0]
+    cells["n_e"] = 6e25
+    cells["kappa2"] = 4.0
+    cells["XH"] = 1.0
+    cells["rho"] = [0.0, rho_eta1, 0.0, 40.0 * rho_eta1]
+    base = dict(I.Params().as_dict())
+
+    def tab(channels, ee):
+        return T.cell_tables(P, norm, box, cells, 1.0, 1, dict(base, channels=channels, brems_ee=ee), 8)
+    tC, tZ, tZE, tall = tab(2, 0), tab(4, 0), tab(4, 1), tab(6, 1)
+    # the network inputs of cells 0 and 1 are equal: only the screening factor differs
+    np.testing.assert_allclose(np.exp(tZ[1, 1] - tZ[0, 1]), 1.0 - 6.98e-2, rtol=1e-12)
+    ee1 = np.exp(tZE[1, 1]) - np.exp(tZ[1, 1])
+    ee0 = np.exp(tZE[0, 1]) - np.exp(tZ[0, 1])
+    np.testing.assert_allclose(ee1 / ee0, 1.0 - 0.140, rtol=1e-10)
+    np.testing.assert_allclose(np.exp(tall[:2, 1]), np.exp(tC[:2, 1]) + np.exp(tZE[:2, 1]),
+                               rtol=1e-12)
+    np.testing.assert_allclose(tC[0, 1], tC[1, 1], rtol=0, atol=0)
+    np.testing.assert_array_equal(tall[0, 0], tall[1, 0])       # slot 0 has no screening factor
+    assert np.all(np.isnan(tall[2]))                            # T below the box
+    assert np.all(np.isneginf(tZE[3, 1])) and np.all(np.isfinite(tall[3, 1]))  # factors clipped
+    assert np.all(np.isnan(T.cell_tables(P, norm, box, cells, 3.0, 1, dict(base, channels=6), 8)))
+
+
+def test_table_rates_at_nodes_equal_the_plain_rates():
+    """With the closed-form log-rates as the table, a particle sitting on a node gets the
+    oracle's plain mean / absorption probability."""
+    import oracle.mlp_table as T
+    p = dict(I.Params(g_agg_GeV=1e-10, g_ae=1e-13, boost=3e33, channels=7, inverse=1, w_a=1e-36,
+                      prim_inv_ratio=0.5).as_dict())
+    wl = I.Workload("t", ndim=1, n=(2,), ppc=8, dtype="f64", T_keV=3.0, n_e=6e25, params=I.Params())
+    grid = wl.grid()
+    dtp = O.dt_phys(grid)
+    cells = O.cell_state(grid, p, np.array([3.0, 5.0]), np.array([6e25, 2e25]),
+                         [np.array([6e25, 2e25])], [1.0], [1.0])
+    unit = dict(p, g_agg_GeV=1.0, g_ae=1.0, boost=1.0)
+    cu = O.cell_state(grid, unit, cells["T"], cells["n_e"], [cells["n_e"]], [1.0], [1.0])
+    nodes = 9
+    box = dict(T=(0.5, 10.0), ne=(1e23, 1e26), x=(0.01, 100.0))
+    u0, h = T.grid(0.01, 100.0, nodes)
+    xn = np.exp(u0 + h * np.arange(nodes))
+    xn[0], xn[-1] = 0.01, 100.0                 # the ends exactly (exp(ln 100) may round above)
+    tab = np.zeros((2, 2, nodes))
+    for c in range(2):
+        lp, la = _closed_form_logR(cu[c], unit, xn)
+        tab[c, 0], tab[c, 1] = lp, la
+    cell = np.repeat([0, 1], nodes)
+    om = xn[np.tile(np.arange(nodes), 2)] * cells["T"][cell]
+    w = np.linspace(0.5, 2.0, cell.size)
+    wref_g, wg = 0.3, 0.05
+    units = dict(P=wref_g / p["w_a"], ag=p["w_a"] / wg)
+    lam, use = T.table_rates(tab, box["x"], 0, cells["T"], cell, om, w, p, dtp, units)
+    assert use.all()
+    G = np.array([O.gamma_prim(cells[c], p, o) for c, o in zip(cell, om)])
+    np.testing.assert_allclose(lam, w * wref_g * -np.expm1(-G * dtp) / p["w_a"], rtol=1e-11)
+    pab, _ = T.table_rates(tab, box["x"], 1, cells["T"], cell, om, w, p, dtp, units)
+    Ga = np.array([O.gamma_abs(cells[c], p, o)[0] for c, o in zip(cell, om)])
+    np.testing.assert_allclose(pab, -np.expm1(-Ga * dtp), rtol=1e-11)
+    lag, _ = T.table_rates(tab, box["x"], 2, cells["T"], cell, om, w, p, dtp, units)
+    np.testing.assert_allclose(lag, w * p["w_a"] * -np.expm1(-0.5 * G * dtp) / wg, rtol=1e-11)
+    # outside [x_lo, x_hi]: no table rate
+    _, use = T.table_rates(tab, box["x"], 0, cells["T"], np.array([0, 1]),
+                           np.array([0.005, 101.0]) * cells["T"], np.ones(2), p, dtp, units)
+    assert not use.any()

@@ -379,6 +379,49 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
                              const axpic_species* sp, int32_t channel, const axpic_mlp* net,
                              void* out, unsigned long long* n_fallback, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Per-cell surrogate tables.  Of the surrogate's inputs only omega varies
+ * inside a cell (T, kappa, n_e and Z are the cell's, Sec. II.E), so the
+ * network can be evaluated once per cell on a grid of u = ln(omega/T) and the
+ * per-particle rate interpolated: the matrix-core work then scales with
+ * cells x nodes instead of particles.
+ * Grid: u_j = ln x_lo + j h, h = (ln x_hi - ln x_lo)/(nodes - 1), j = 0 .. nodes-1,
+ * 4 <= nodes <= AXPIC_TAB_MAX_NODES.  Table (device, FP32, caller-owned):
+ * table[(2 c + s) nodes + j] for cell c, slot s:
+ *   s = 0  log R of the Primakoff conversion (R = Gamma_{gamma->a}/g_agg^2);
+ *   s = 1  log of the sum over the thermal channels enabled in prm (Compton-like,
+ *          e-Z brems, e-e brems if brems_ee) of the absorption rate per g_ae^2
+ *          (eq. gamma_abs), brems times the cell's screening-fit factor
+ *          max(0, 1 - a eta) of eqs. eps_eZ / eps_ee; -inf when that sum is 0.
+ * A cell outside the training box (T, n_e, or not one ion species of Z 1 or 2)
+ * gets NaN in every entry of the slots written.
+ */
+#define AXPIC_TAB_MAX_NODES 64
+
+/* axpic_mlp_table -- fill slot 0 if channel has AXPIC_PRIMAKOFF, slot 1 if it
+ * has AXPIC_COMPTON or AXPIC_BREMS, for every cell, from the network `net` on
+ * the grid over [x_lo, x_hi], which must lie inside the training range
+ * [net->x_lo, net->x_hi] (particles outside it take the plain rate).
+ * AXPIC_E_INVAL for a missing pointer, nodes or range out of bounds, or no slot
+ * requested. */
+axpic_status axpic_mlp_table(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                             int32_t channel, const axpic_mlp* net, int32_t nodes, double x_lo,
+                             double x_hi, float* table, void* stream);
+
+/* axpic_rates_table -- per-particle rates from a table (any source, laid out as
+ * above on the grid of nodes over [x_lo, x_hi]); outputs and (species, channel)
+ * pairs as axpic_rates_mlp.  With t = (ln(omega/T) - ln x_lo)/h and
+ * k = clamp(floor(t) - 1, 0, nodes - 4), log R is the cubic through nodes
+ * k .. k+3 (Lagrange form, FP64) at t; then Gamma = g^2 boost R and the rate
+ * follows as in axpic_rates (eq. lambda_macro for lambda, 1 - exp(-Gamma dt)).
+ * Particles with omega/T outside [x_lo, x_hi] or in a NaN cell take the plain
+ * rate and are counted in n_fallback (device, may be NULL).  The slot read
+ * (0 for AXPIC_PRIMAKOFF, 1 for thermal absorption) must have been filled. */
+axpic_status axpic_rates_table(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                               const axpic_species* sp, int32_t channel, int32_t nodes, double x_lo,
+                               double x_hi, const float* table, void* out,
+                               unsigned long long* n_fallback, void* stream);
+
 /* axpic_timing_enable / axpic_timing_read -- instrumentation.  While enabled,
  * every kernel the library launches is bracketed by HIP events recorded on
  * its own stream.  axpic_timing_read waits for those events and writes one

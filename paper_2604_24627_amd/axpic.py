@@ -76,9 +76,10 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_stream_copy", "axpic_mlp_blob_bytes", "axpic_mlp_train_ws_bytes",
            "axpic_mlp_pack", "axpic_mlp_forward", "axpic_mlp_loss_grad", "axpic_mlp_adam",
            "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
-           "axpic_sample_emit_cells"]
+           "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table"]
 MLP_PARAMS = 57888
 MLP_BLOB_BYTES = 112704
+TAB_MAX_NODES = 64
 
 
 class MlpC(C.Structure):
@@ -135,6 +136,10 @@ def load(path: Optional[str] = None):
         ("axpic_cell_weights", [_P, _P, C.c_int64, _P, _P]),
         ("axpic_sample_emit_cells", [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int64, C.c_uint64,
                                      _P, _P, _P, _P, _P, _P, C.c_size_t, _P, _P]),
+        ("axpic_mlp_table", [_P, _P, _P, C.c_int32, _P, C.c_int32, C.c_double, C.c_double, _P,
+                             _P]),
+        ("axpic_rates_table", [_P, _P, _P, _P, C.c_int32, C.c_int32, C.c_double, C.c_double, _P,
+                               _P, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32

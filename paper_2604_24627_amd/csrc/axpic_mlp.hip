@@ -347,7 +347,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
         const int32_t c = cell[ii];
         const double* st = state + (int64_t)c * AXPIC_STATE_N;
         const double Tc = st[0], ne = st[1], k2 = st[7];
-        const T p2 = px[ii] * px[ii] + py[ii] * py[ii] + pz[ii] * pz[ii];
+        const T p2 = psq<T>(px, py, pz, ii);
         const double om = kMe * sqrt((double)p2);
         const double x = om / Tc;
         const bool in_dom = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo &&
@@ -386,7 +386,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
                 if (on) G += supp * exp((double)log_rate(mc, ch, f, y));
             }
             res = in_dom ? -expm1(-g2e * boost * G * kp.dt_phys)
-                         : (double)pabs_thermal<T>(kp, pc, (T)om);
+                         : (double)pabs_thermal<T>(kp, pc, energy_keV(p2));
             if (!(wt > (T)0)) res = 0.0;
         }
         if (mode != 1 && !(wt > (T)0)) res = 0.0;
@@ -399,6 +399,125 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
     if (lane == 0 && fb_count && nfallback) atomicAdd(nfallback, fb_count);
 }
 
+
+// ------------------------------------------------------------------ per-cell tables
+// Apart from omega, every input of the surrogate is constant in a cell, so the
+// network can run once per (cell, node) on a grid in u = ln(omega/T) and the
+// particles interpolate: the matrix-core work scales with cells x nodes.
+
+// Row r = c nodes + j of the table: node u_j = u0 + j h of cell c.  Slot 0
+// receives log R of the Primakoff conversion, slot 1 the log of the sum of the
+// enabled thermal channels' absorption rates (brems times the cell's
+// screening-fit factor; -inf if that sum is zero).  Cells outside the training
+// box get NaN in the slots written.
+__global__ void __launch_bounds__(kInfThreads)
+k_mlp_table(int64_t ncell, int nodes, int slot0, int slot1, int c_on, int bz_on, int be_on,
+            MlpConst mc, const double* __restrict__ state, int32_t nion, double Zion, double u0,
+            double h, const unsigned char* __restrict__ blob, float* __restrict__ table) {
+    __shared__ __align__(16) unsigned char lds[kBlobBytes];
+    {
+        const uint4* src = (const uint4*)blob;
+        uint4* dst = (uint4*)lds;
+        for (int k = threadIdx.x; k < (int)(kBlobBytes / 16); k += blockDim.x) dst[k] = src[k];
+    }
+    __syncthreads();
+    const bf16x8* frag = (const bf16x8*)lds;
+    const float* bias = (const float*)(lds + (size_t)kNFrag * kFragBytes);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t rows = ncell * nodes;
+    const int64_t waves_total = (int64_t)gridDim.x * (kInfThreads / 64);
+    const int64_t tiles = (rows + 63) / 64;
+    for (int64_t t = (int64_t)blockIdx.x * (kInfThreads / 64) + wave; t < tiles; t += waves_total) {
+        const int64_t r = t * 64 + lane;
+        const bool live = r < rows;
+        const int64_t rr = live ? r : rows - 1;
+        const int64_t c = rr / nodes;
+        const int j = (int)(rr - c * nodes);
+        const double* st = state + c * AXPIC_STATE_N;
+        const double Tc = st[0], ne = st[1], k2 = st[7];
+        const bool in_box = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo &&
+                            Tc <= mc.T_hi && ne >= mc.ne_lo && ne <= mc.ne_hi;
+        float f[8];
+        f[0] = ((float)(u0 + j * h) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
+        f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
+        f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
+        f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
+        float* out = table + c * 2 * nodes + j;
+        if (slot0) {
+            f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
+            const float y = mlp_wave(frag, bias, f);
+            if (live) out[0] = in_box ? log_rate(mc, 0, f, y) : NAN;
+        }
+        if (slot1) {
+            double G = 0.0;
+#pragma unroll 1
+            for (int ch = 1; ch <= 3; ++ch) {
+                const int on = ch == 1 ? c_on : (ch == 2 ? bz_on : be_on);
+                if (!on) continue;                           // uniform over the grid
+                f[4] = 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f; f[6] = ch == 2 ? 1.0f : 0.0f;
+                f[7] = ch == 3 ? 1.0f : 0.0f;
+                const float y = mlp_wave(frag, bias, f);
+                const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
+                G += supp * exp((double)log_rate(mc, ch, f, y));
+            }
+            if (live) out[nodes] = in_box ? (float)log(G) : NAN;
+        }
+    }
+}
+
+// Per-particle rates from the tables: 4-point Lagrange interpolation in u on the
+// nodes k .. k+3 around the particle, k = clamp(floor(t) - 1, 0, nodes - 4),
+// t = (u - u0)/h, in FP64.  Modes as k_rates_mlp; particles outside
+// [x_lo, x_hi] or in a cell without a table take the plain rate.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rates_table(int64_t n, int mode, int nodes, double u0, double h, double x_lo, double x_hi,
+              KParams kp, double g2P, double g2e, double boost, double lam_unit_P,
+              double lam_unit_ag, const double* __restrict__ state, const float* __restrict__ p32,
+              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
+              const T* __restrict__ py, const T* __restrict__ pz, const int32_t* __restrict__ cell,
+              const float* __restrict__ table, T* __restrict__ out,
+              unsigned long long* __restrict__ nfallback) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = i < n;
+    bool plain = false;
+    if (live) {
+        const int32_t c = cell[i];
+        const double Tc = state[(int64_t)c * AXPIC_STATE_N];
+        const T p2 = psq<T>(px, py, pz, i);
+        const T wt = w[i];
+        const double om = kMe * sqrt((double)p2);
+        const double x = om / Tc;
+        const float* row = table + ((int64_t)c * 2 + (mode == 1 ? 1 : 0)) * nodes;
+        const float L0 = row[0];
+        plain = isnan(L0) || !(x >= x_lo && x <= x_hi);
+        double L = 0.0;
+        if (!plain) {
+            const double t = (log(x) - u0) / h;
+            const int k = min(max((int)floor(t) - 1, 0), nodes - 4);
+            const double s = t - k, a = s - 1.0, b = s - 2.0, d = s - 3.0;
+            L = -(a * b * d) / 6.0 * row[k] + (s * b * d) / 2.0 * row[k + 1] -
+                (s * a * d) / 2.0 * row[k + 2] + (s * a * b) / 6.0 * row[k + 3];
+        }
+        const T* pc = PrefOf<T>::get(p32, p64) + (int64_t)c * AXPIC_PREF_N;
+        double res;
+        if (mode == 0) {
+            res = plain ? (double)lambda_primakoff<T>(pc, wt, p2)
+                        : (double)wt * lam_unit_P * (-expm1(-g2P * boost * exp(L) * kp.dt_phys));
+        } else if (mode == 2) {
+            res = plain ? (double)lambda_ag<T>(kp, pc, wt, p2)
+                        : (double)wt * lam_unit_ag *
+                              (-expm1(-kp.inv_ratio * g2P * boost * exp(L) * kp.dt_phys));
+        } else {
+            res = plain ? (double)pabs_thermal<T>(kp, pc, energy_keV(p2))
+                        : (L0 == -INFINITY ? 0.0 : -expm1(-g2e * boost * exp(L) * kp.dt_phys));
+        }
+        if (!(wt > (T)0)) res = 0.0;
+        out[i] = (T)res;
+    }
+    const unsigned long long m = __ballot(live && plain);
+    if ((threadIdx.x & 63) == 0 && m && nfallback) atomicAdd(nfallback, (unsigned long long)__popcll(m));
+}
 
 // ------------------------------------------------------------------ training samples
 // Samples of the surrogate's target generated by the plain rates in FP64: one
@@ -587,6 +706,28 @@ axpic_status axpic_mlp_adam(float* master, const float* grad, float* m, float* v
     return launched();
 }
 
+static MlpConst mlp_const(const axpic_mlp* net) {
+    MlpConst mc;
+    for (int i = 0; i < 4; ++i) {
+        mc.feat_lo[i] = net->feat_lo[i]; mc.feat_sc[i] = net->feat_sc[i];
+        mc.out_mu[i] = net->out_mu[i]; mc.out_sigma[i] = net->out_sigma[i];
+        for (int j = 0; j < 4; ++j) mc.out_lin[i][j] = net->out_lin[i][j];
+    }
+    mc.T_lo = net->T_lo; mc.T_hi = net->T_hi; mc.ne_lo = net->ne_lo; mc.ne_hi = net->ne_hi;
+    mc.x_lo = net->x_lo; mc.x_hi = net->x_hi;
+    return mc;
+}
+
+static int compute_units() {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            ncu = v;
+    }
+    return ncu;
+}
+
 axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                              const axpic_species* sp, int32_t channel, const axpic_mlp* net,
                              void* out, unsigned long long* n_fallback, void* stream) {
@@ -601,23 +742,11 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
     else return AXPIC_E_INVAL;
     if (sp->n == 0) return AXPIC_OK;
     KParams kp = kparams_for(g, prm, cells->w_ref_g);
-    MlpConst mc;
-    for (int i = 0; i < 4; ++i) {
-        mc.feat_lo[i] = net->feat_lo[i]; mc.feat_sc[i] = net->feat_sc[i];
-        mc.out_mu[i] = net->out_mu[i]; mc.out_sigma[i] = net->out_sigma[i];
-        for (int j = 0; j < 4; ++j) mc.out_lin[i][j] = net->out_lin[i][j];
-    }
-    mc.T_lo = net->T_lo; mc.T_hi = net->T_hi; mc.ne_lo = net->ne_lo; mc.ne_hi = net->ne_hi;
-    mc.x_lo = net->x_lo; mc.x_hi = net->x_hi;
+    const MlpConst mc = mlp_const(net);
     const double g2P = prm->g_agg_GeV * prm->g_agg_GeV, g2e = prm->g_ae * prm->g_ae;
     const double lam_unit_P = cells->w_ref_g / (prm->w_a * prm->wa_mul[0]);
     const double lam_unit_ag = prm->w_a / kp.w_gamma_prod;
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            ncu = v;
-    }
+    const int ncu = compute_units();
     const int64_t tiles = (sp->n + 63) / 64;
     constexpr int kWaves = kInfThreads / 64;
     const int64_t wgs = std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)ncu);
@@ -636,6 +765,69 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
                            (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],
                            (const double*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
                            (double*)out, n_fallback);
+    return launched();
+}
+
+axpic_status axpic_mlp_table(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                             int32_t channel, const axpic_mlp* net, int32_t nodes, double x_lo,
+                             double x_hi, float* table, void* stream) {
+    if (!g || !cells || !prm || !net || !net->blob || !table) return AXPIC_E_INVAL;
+    if (nodes < 4 || nodes > AXPIC_TAB_MAX_NODES || !(x_lo > 0.0) || !(x_hi > x_lo) ||
+        !(x_lo >= net->x_lo) || !(x_hi <= net->x_hi))
+        return AXPIC_E_INVAL;
+    if (cells->ncell < 0 || (cells->ncell && !cells->state)) return AXPIC_E_INVAL;
+    const int slot0 = (channel & AXPIC_PRIMAKOFF) != 0;
+    const int slot1 = (channel & (AXPIC_COMPTON | AXPIC_BREMS)) != 0;
+    if (!slot0 && !slot1) return AXPIC_E_INVAL;
+    if (cells->ncell == 0) return AXPIC_OK;
+    const int c_on = (prm->channels & AXPIC_COMPTON) != 0;
+    const int bz_on = (prm->channels & AXPIC_BREMS) != 0;
+    const int be_on = bz_on && prm->brems_ee;
+    const double u0 = log(x_lo), h = (log(x_hi) - u0) / (nodes - 1);
+    const int64_t tiles = (cells->ncell * nodes + 63) / 64;
+    constexpr int kWaves = kInfThreads / 64;
+    const int64_t wgs = std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)compute_units());
+    const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
+    LAUNCH("k_mlp_table", k_mlp_table, dim3((unsigned)wgs), dim3(kInfThreads), 0, S(stream),
+           cells->ncell, (int)nodes, slot0, slot1, c_on, bz_on, be_on, mlp_const(net), cells->state,
+           cells->nion, Z, u0, h, (const unsigned char*)net->blob, table);
+    return launched();
+}
+
+axpic_status axpic_rates_table(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                               const axpic_species* sp, int32_t channel, int32_t nodes, double x_lo,
+                               double x_hi, const float* table, void* out,
+                               unsigned long long* n_fallback, void* stream) {
+    if (!g || !cells || !prm || !sp || !table || (!out && sp->n)) return AXPIC_E_INVAL;
+    if (nodes < 4 || nodes > AXPIC_TAB_MAX_NODES || !(x_lo > 0.0) || !(x_hi > x_lo))
+        return AXPIC_E_INVAL;
+    if (sp->n < 0 || (sp->n && (!sp->w || !sp->cell || !sp->p[0] || !sp->p[1] || !sp->p[2])))
+        return AXPIC_E_INVAL;
+    if (!cells->state || !cells->pref32 || !cells->pref64) return AXPIC_E_INVAL;
+    int mode;
+    if (sp->kind == AXPIC_PHOTON && channel == AXPIC_PRIMAKOFF) mode = 0;
+    else if (sp->kind == AXPIC_AXION && channel == (AXPIC_COMPTON | AXPIC_BREMS)) mode = 1;
+    else if (sp->kind == AXPIC_AXION && channel == AXPIC_PRIMAKOFF) mode = 2;
+    else return AXPIC_E_INVAL;
+    if (sp->n == 0) return AXPIC_OK;
+    KParams kp = kparams_for(g, prm, cells->w_ref_g);
+    const double g2P = prm->g_agg_GeV * prm->g_agg_GeV, g2e = prm->g_ae * prm->g_ae;
+    const double lam_unit_P = cells->w_ref_g / (prm->w_a * prm->wa_mul[0]);
+    const double lam_unit_ag = prm->w_a / kp.w_gamma_prod;
+    const double u0 = log(x_lo), h = (log(x_hi) - u0) / (nodes - 1);
+    const unsigned blocks = (unsigned)((sp->n + 255) / 256);
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_rates_table", k_rates_table<float>, dim3(blocks), dim3(256), 0, S(stream), sp->n,
+               mode, (int)nodes, u0, h, x_lo, x_hi, kp, g2P, g2e, prm->boost, lam_unit_P,
+               lam_unit_ag, cells->state, cells->pref32, cells->pref64, (const float*)sp->w,
+               (const float*)sp->p[0], (const float*)sp->p[1], (const float*)sp->p[2], sp->cell,
+               table, (float*)out, n_fallback);
+    else
+        LAUNCH("k_rates_table", k_rates_table<double>, dim3(blocks), dim3(256), 0, S(stream), sp->n,
+               mode, (int)nodes, u0, h, x_lo, x_hi, kp, g2P, g2e, prm->boost, lam_unit_P,
+               lam_unit_ag, cells->state, cells->pref32, cells->pref64, (const double*)sp->w,
+               (const double*)sp->p[0], (const double*)sp->p[1], (const double*)sp->p[2], sp->cell,
+               table, (double*)out, n_fallback);
     return launched();
 }
 

@@ -137,7 +137,7 @@ class AxpicSim:
 
     def __init__(self, plasma: Dict, params, device: str = "cuda", axion_capacity: int = 0,
                  photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None,
-                 thermal: str = "particle"):
+                 thermal: str = "particle", surrogate_mode: str = "particle"):
         self.lib = B.load()
         self.device = torch.device(device)
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
@@ -193,6 +193,13 @@ class AxpicSim:
         # learned rate backend for the per-particle, energy-dependent rates (photon conversion,
         # axion absorption and a->gamma); None = plain closed forms
         self.surrogate = surrogate
+        # "particle": one network pass per particle (axpic_rates_mlp); "table": per-cell
+        # tables on a grid of omega/T, interpolated per particle (axpic_mlp_table,
+        # axpic_rates_table)
+        if surrogate_mode not in ("particle", "table"):
+            raise ValueError(surrogate_mode)
+        self.surrogate_mode = surrogate_mode
+        self._tab = None
         self.fallback = torch.zeros(1, dtype=torch.int64, device=self.device)
         # device chain of the step's appending calls {axions, photons, next id, skip} and
         # one status record per call
@@ -380,16 +387,29 @@ class AxpicSim:
         self._ensure_ws(max(self.el.n, self.ph.n, n_ax0, 4 * self.ncell))
         S = self.surrogate
         lam = pab = lag = None
+        if S and self.surrogate_mode == "table":
+            # one network pass per cell and node; the particles interpolate
+            need = p["channels"] & B.PRIMAKOFF
+            if p["inverse"] and n_ax0 > 0:
+                need |= p["channels"] & (B.COMPTON | B.BREMS)
+            if need:
+                self._tab = S.table(self, need, out=self._tab)
+
+            def srates(sp, ch):
+                return S.rates_table(self, sp, ch, self._tab, fallback=self.fallback)
+        else:
+            def srates(sp, ch):
+                return S.rates(self, sp, ch, fallback=self.fallback)
         if S and p["channels"] & B.PRIMAKOFF:
-            lam = S.rates(self, self.ph, B.PRIMAKOFF, fallback=self.fallback)
+            lam = srates(self.ph, B.PRIMAKOFF)
         if S and p["inverse"] and n_ax0 > 0:
             n_now = self.ax.n
             self.ax.n = n_ax0
             try:
                 if p["channels"] & (B.COMPTON | B.BREMS):
-                    pab = S.rates(self, self.ax, B.COMPTON | B.BREMS, fallback=self.fallback)
+                    pab = srates(self.ax, B.COMPTON | B.BREMS)
                 if p["channels"] & B.PRIMAKOFF:
-                    lag = S.rates(self, self.ax, B.PRIMAKOFF, fallback=self.fallback)
+                    lag = srates(self.ax, B.PRIMAKOFF)
             finally:
                 self.ax.n = n_now
         n_ph0, id0 = self.ph.n, self.next_id

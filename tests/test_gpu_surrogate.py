@@ -9,7 +9,12 @@
 * a network trained on the GPU by these kernels reproduces the oracle's
   rates on held-out samples, and the rates it feeds the sampling operators
   keep the integrated power within 1% of the plain path; the test reports
-  what it gains over the plain path (time per evaluation).
+  what it gains over the plain path (time per evaluation);
+* per-cell tables: the table kernel reproduces the oracle's tables of the
+  same network (oracle/mlp_table.py) to the BF16 bar above; the per-particle
+  interpolation reproduces the oracle's on a table the oracle wrote, with
+  the plain rate outside the table; the trained network's tabulated rates
+  keep the power within 1% and the time of both variants is reported.
 """
 import math
 import time
@@ -22,10 +27,15 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O  # noqa: E402
 import oracle.mlp as M  # noqa: E402
+import oracle.mlp_table as MT  # noqa: E402
 from paper_2604_24627_amd import inputs as I  # noqa: E402
 from paper_2604_24627_amd import axpic as B  # noqa: E402
 from paper_2604_24627_amd.sim import AxpicSim  # noqa: E402
 from paper_2604_24627_amd.surrogate import Surrogate, init_master  # noqa: E402
+
+
+def np64(t):
+    return t.detach().cpu().numpy().astype(np.float64)
 
 
 def unpad(master):
@@ -206,3 +216,176 @@ def test_out_of_box_particles_use_the_plain_rate(trained):
     torch.cuda.synchronize()
     assert int(fb.item()) == g.ph.n
     np.testing.assert_array_equal(lam_mlp.cpu().numpy(), lam_plain.cpu().numpy())
+    g.load_axions(I.make_axions(wl, pl, 6.0, seed=8))
+    for ch in (B.COMPTON | B.BREMS, B.PRIMAKOFF):
+        fb.zero_()
+        a_mlp = S.rates(g, g.ax, ch, fallback=fb)
+        a_plain = g.rates(g.ax, ch)
+        torch.cuda.synchronize()
+        assert int(fb.item()) == g.ax.n
+        np.testing.assert_array_equal(a_mlp.cpu().numpy(), a_plain.cpu().numpy())
+
+
+# ------------------------------------------------------------ per-cell tables
+
+def pad(P):
+    """Oracle parameter list -> padded FP32 master vector (inverse of unpad)."""
+    dims = [(32, 128), (128, 128), (128, 128), (128, 128), (128, 32)]
+    out = np.zeros(B.MLP_PARAMS, dtype=np.float32)
+    off = 0
+    for (din, dout), (W, b) in zip(dims, P):
+        Wp = np.zeros((din, dout), dtype=np.float32)
+        Wp[: W.shape[0], : W.shape[1]] = W
+        out[off: off + din * dout] = Wp.ravel(); off += din * dout
+        out[off: off + b.size] = b; off += dout
+    return out
+
+
+def _table_setup(seed=3):
+    """A seeded network with nonzero biases, hand-set normalisation (binary32 values),
+    and a 2D plasma graded in T from 0.3 keV (below the box) to 6 keV."""
+    rng = np.random.default_rng(seed)
+    P = M.init_params(seed)
+    for W, b in P:
+        W[:] = W.astype(np.float32)
+        b[:] = rng.normal(0, 0.1, b.size).astype(np.float32)
+    f32 = lambda a: [float(np.float32(v)) for v in a]
+    norm_o = dict(feat_lo=f32([math.log(0.01), -3.0, math.log(1e23), 1.0]),
+                  feat_sc=f32([2.0 / math.log(1e4), 0.5, 2.0 / math.log(1e3), 2.0]),
+                  out_mu=f32([-40.0, -20.0, -22.0, -24.0]), out_sigma=f32([1.5, 2.0, 1.0, 0.5]),
+                  out_lin=f32(rng.normal(0, 1, 16)))
+    S = Surrogate(I.Params(), seed=seed)
+    S.master.copy_(torch.from_numpy(pad(P)))
+    S.norm = dict(lo=norm_o["feat_lo"], sc=norm_o["feat_sc"], mu=norm_o["out_mu"],
+                  sigma=norm_o["out_sigma"],
+                  lin=np.asarray(norm_o["out_lin"]).reshape(4, 4).tolist())
+    S.pack()
+    p = I.Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=7, inverse=1, w_a=1e-36, boost=1e33,
+                 lambda_cap=1.0)
+    wl = I.Workload("tab", ndim=2, n=(24, 8), ppc=24, dtype="f32", T_keV=0.3, T_keV_hi=6.0,
+                    n_e=6e25, n_ref=6e25, params=p)
+    pl = I.make_plasma(wl, 6)
+    print(f"[surrogate] table workload n={wl.n} ppc={wl.ppc} T 0.3..6 keV", flush=True)
+    return S, P, norm_o, wl, pl
+
+
+def test_table_kernel_matches_oracle_tables():
+    S, P, norm_o, wl, pl = _table_setup()
+    g = AxpicSim(pl, wl.params)
+    o = O.OracleSim(pl, wl.params, prec32=True)
+    cells = o.cells()
+    for nodes, xr in ((16, (0.05, 30.0)), (9, (0.01, 100.0))):
+        tab = S.table(g, B.PRIMAKOFF | B.COMPTON | B.BREMS, nodes=nodes, x_range=xr)
+        gt = tab.cpu().numpy().astype(np.float64).reshape(g.ncell, 2, nodes)
+        ot = MT.cell_tables(P, norm_o, S.box, cells, 1.0, 1, o.params, nodes, x_range=xr)
+        np.testing.assert_array_equal(np.isnan(gt), np.isnan(ot))
+        np.testing.assert_array_equal(np.isneginf(gt), np.isneginf(ot))
+        fin = np.isfinite(ot)
+        assert np.isnan(ot).any() and fin.sum() > 0.5 * ot.size
+        d = np.abs(gt[fin] - ot[fin])
+        smax = max(norm_o["out_sigma"])
+        print(f"[surrogate] table nodes={nodes}: |d log R| median {np.median(d):.2e} "
+              f"max {d.max():.2e}", flush=True)
+        # the BF16 rounding of weights and layer inputs (as in the forward-pass test)
+        assert np.median(d) < 2e-3 * smax and d.max() < 0.1 * smax
+    # only the slots asked for are written
+    tab.fill_(7.0)
+    S.table(g, B.PRIMAKOFF, nodes=9, x_range=(0.01, 100.0), out=tab)
+    t = tab.cpu().numpy().reshape(g.ncell, 2, 9)
+    assert np.all(t[:, 1] == 7.0) and not np.any(t[:, 0] == 7.0)
+
+
+def test_rates_from_table_match_oracle_and_fall_back_to_plain():
+    """A table written by the oracle (closed-form log-rates at the nodes, some cells NaN,
+    some thermal slots -inf) read by both sides: photons, seeded axions, all modes."""
+    S, P, norm_o, wl, pl = _table_setup()
+    g = AxpicSim(pl, wl.params)
+    o = O.OracleSim(pl, wl.params, prec32=True)
+    cells = o.cells()
+    unit = dict(o.params, g_agg_GeV=1.0, g_ae=1.0, boost=1.0)
+    cu = O.cell_state(o.grid, unit, o.T, o.dens_e, [o.dens_i], o.Z, o.A)
+    nodes, xr = 12, (0.05, 30.0)
+    u0, h = MT.grid(xr[0], xr[1], nodes)
+    xn = np.exp(u0 + h * np.arange(nodes))
+    tab = np.zeros((g.ncell, 2, nodes))
+    for c in range(g.ncell):
+        Tc = cu[c]["T"]
+        tab[c, 0] = [math.log(O.gamma_prim(cu[c], unit, x * Tc)) for x in xn]
+        tab[c, 1] = [math.log(O.gamma_abs(cu[c], unit, x * Tc)[0]) for x in xn]
+    tab[cells["T"] < 0.5] = np.nan
+    tab[5::17, 1] = -np.inf
+    tab32 = tab.astype(np.float32)
+    tdev = torch.from_numpy(tab32.ravel()).cuda()
+    dtp = O.dt_phys(o.grid)
+    units = dict(P=g.ph.w_ref / (o.params["w_a"] * o.params["wa_mul"][0]),
+                 ag=o.params["w_a"] / g.ph.w_ref)
+    axd = I.make_axions(wl, pl, 10.0, seed=21)
+    g.load_axions(axd)
+    cases = ((g.ph, pl["species"]["photons"], B.PRIMAKOFF, 0),
+             (g.ax, axd, B.COMPTON | B.BREMS, 1), (g.ax, axd, B.PRIMAKOFF, 2))
+    for sp, d, ch, mode in cases:
+        fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        got = S.rates_table(g, sp, ch, tdev, nodes=nodes, x_range=xr, fallback=fb)
+        plain = g.rates(sp, ch)
+        got, plain = np64(got), np64(plain)
+        om = 510.99895 * np.sqrt((d["p"].astype(np.float64) ** 2).sum(axis=0))
+        ref, use = MT.table_rates(tab32, xr, mode, o.T, d["cell"], om, d["w"].astype(np.float64),
+                                  o.params, dtp, units)
+        assert 0 < use.sum() < use.size
+        assert int(fb.item()) == int((~use).sum())
+        np.testing.assert_array_equal(got[~use], plain[~use])
+        big = np.abs(ref[use]) > 1e-30
+        np.testing.assert_allclose(got[use][big], ref[use][big], rtol=1e-5)
+        assert np.all(np.abs(got[use][~big]) <= 1e-30)
+        print(f"[surrogate] table rates mode {mode}: {use.sum()} from the table, "
+              f"{(~use).sum()} plain", flush=True)
+
+
+def test_tabulated_surrogate_power_and_gain(trained):
+    S = trained
+    wl, pl = _small_plasma()
+    g = AxpicSim(pl, wl.params)
+    tab = S.table(g)
+    lam_plain = g.rates(g.ph, B.PRIMAKOFF).double()
+    lam_mlp = S.rates(g, g.ph, B.PRIMAKOFF).double()
+    lam_tab = S.rates_table(g, g.ph, B.PRIMAKOFF, tab).double()
+    E = torch.sqrt(g.ph.p[0][: g.ph.n].double() ** 2 + g.ph.p[1][: g.ph.n].double() ** 2 +
+                   g.ph.p[2][: g.ph.n].double() ** 2)
+    Pp, Pt = float((lam_plain * E).sum()), float((lam_tab * E).sum())
+    assert Pt == pytest.approx(Pp, rel=0.01)
+    pos = (lam_mlp > 0) & (lam_tab > 0)
+    dl = torch.log(lam_tab[pos] / lam_mlp[pos])
+    print(f"[surrogate] table vs per-particle network, photons: rms d log lambda "
+          f"{float(dl.pow(2).mean().sqrt()):.2e}, power (table/plain) {Pt / Pp:.5f}", flush=True)
+    assert float(dl.pow(2).mean().sqrt()) < 1e-2
+    for _ in range(3):
+        g.step()
+    tab = S.table(g)
+    pab_plain = g.rates(g.ax, B.COMPTON | B.BREMS).double()
+    pab_tab = S.rates_table(g, g.ax, B.COMPTON | B.BREMS, tab).double()
+    Ea = torch.sqrt(g.ax.p[0][: g.ax.n].double() ** 2 + g.ax.p[1][: g.ax.n].double() ** 2 +
+                    g.ax.p[2][: g.ax.n].double() ** 2)
+    wa = g.ax.w[: g.ax.n].double()
+    Ap, At = float((pab_plain * wa * Ea).sum()), float((pab_tab * wa * Ea).sum())
+    assert At == pytest.approx(Ap, rel=0.01)
+
+    def timed(fn, reps=20):
+        fn(); torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record(); torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    tm = timed(lambda: (S.rates(g, g.ph, B.PRIMAKOFF), S.rates(g, g.ax, B.COMPTON | B.BREMS),
+                        S.rates(g, g.ax, B.PRIMAKOFF)))
+    tt = timed(lambda: (S.table(g, out=tab), S.rates_table(g, g.ph, B.PRIMAKOFF, tab),
+                        S.rates_table(g, g.ax, B.COMPTON | B.BREMS, tab),
+                        S.rates_table(g, g.ax, B.PRIMAKOFF, tab)))
+    print(f"[surrogate] {g.ph.n} photons + {g.ax.n} axions in {g.ncell} cells: per-particle "
+          f"network {tm * 1e3:.1f} us, tables {tt * 1e3:.1f} us", flush=True)
+    # a chained step in table mode
+    g2 = AxpicSim(pl, wl.params, surrogate=S, surrogate_mode="table")
+    for _ in range(2):
+        g2.step()
+    assert g2.ax.n > 0

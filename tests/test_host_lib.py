@@ -91,3 +91,33 @@ def test_invalid_arguments_rejected_on_host():
     assert L.axpic_feedback(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), None, None, None,
                             None, None, None) == -1
     assert L.axpic_sampler_table(2, 0.0, None) == -1
+
+
+def test_table_entries_reject_invalid_arguments_on_host():
+    L = B.load()
+    g = B.make_grid(dict(ndim=1, n=(4, 1, 1), dx=0.2, dt=0.1, omega0=1e17))
+    cells = B.CellsC()
+    cells.ncell = 4
+    prm = B.make_params(I.Params())
+    net = B.MlpC()
+    tab = np.zeros(4 * 2 * 16, np.float32)
+    net.x_lo, net.x_hi = 0.01, 100.0
+    def mt(channel, nodes, lo, hi):
+        return L.axpic_mlp_table(B.ref(g), B.ref(cells), B.ref(prm), channel, B.ref(net), nodes,
+                                 lo, hi, tab.ctypes.data, None)
+    assert mt(B.PRIMAKOFF, 16, 0.05, 30.0) == -1    # no network blob
+    net.blob = tab.ctypes.data          # never dereferenced: every call below is rejected first
+    for nodes in (3, B.TAB_MAX_NODES + 1):
+        assert mt(B.PRIMAKOFF, nodes, 0.05, 30.0) == -1
+    assert mt(0, 16, 0.05, 30.0) == -1                # no slot requested
+    assert mt(B.PRIMAKOFF, 16, 0.005, 30.0) == -1     # below the training range
+    assert mt(B.PRIMAKOFF, 16, 0.05, 200.0) == -1     # above it
+    assert mt(B.PRIMAKOFF, 16, 30.0, 0.05) == -1
+    sp = B.SpeciesC()
+    sp.kind, sp.n = B.PHOTON, 0
+    assert L.axpic_rates_table(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), B.PRIMAKOFF, 16,
+                               0.01, 100.0, None, None, None, None) == -1   # no table
+    assert L.axpic_rates_table(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), B.PRIMAKOFF, 16,
+                               100.0, 0.01, tab.ctypes.data, None, None, None) == -1
+    assert L.axpic_rates_table(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), B.PRIMAKOFF, 2,
+                               0.01, 100.0, tab.ctypes.data, None, None, None) == -1

@@ -316,7 +316,7 @@ def main():
         torch.cuda.empty_cache()
 
     # ---- surrogate form: trained on the GPU outside the timed region, same workload
-    sur = None
+    sur = sur_tab = None
     if not a.no_surrogate:
         from paper_2604_24627_amd.surrogate import Surrogate
         S = Surrogate(I.Params())
@@ -328,49 +328,63 @@ def main():
         t_train = time.perf_counter() - t
         print(f"[bench] surrogate trained in {t_train:.1f} s, loss {losses[-1][1] if losses else 0:.3e}",
               file=sys.stderr, flush=True)
-        pl = I.make_plasma(wl)
-        sim2 = AxpicSim(pl, wl.params, axion_capacity=est_ax, surrogate=S)
-        del pl
-        for _ in range(a.warmup):
-            sim2.step()
-        torch.cuda.synchronize()
-        upd2 = 0
-        e0.record()
-        for _ in range(a.steps):
-            upd2 += updates_per_step(sim2, sim2.ax.n)
-            sim2.step()
-        e1.record()
-        torch.cuda.synchronize()
-        ms2 = e0.elapsed_time(e1)
-        fb_count = int(sim2.fallback.item())
-        sur = {"value": upd2 / (ms2 * 1e-3), "unit": "updates/s", "ms_per_step": ms2 / a.steps,
-               "train_s": round(t_train, 2), "train_steps": a.train_steps,
-               "train_samples": 2_000_000, "final_loss": losses[-1][1] if losses else None,
-               "fallback_evals": fb_count,
-               "speed_vs_plain": round((upd2 / (ms2 * 1e-3)) / value, 4)}
-        Q_mc2 = q_mc(sim2.hist_np(), sim2.step_index)
-        print(f"[bench] surrogate: {ms2 / a.steps:.3f} ms/step, {sur['value']:.3e} updates/s",
-              file=sys.stderr, flush=True)
-        # the inference kernel against the matrix-core peak: network evaluations per step =
-        # photons (lambda_P) + 4 per old axion (three thermal channels, a->gamma)
-        L.axpic_timing_enable(1)
-        evals = 0
-        for _ in range(3):
-            evals += sim2.ph.n + 4 * sim2.ax.n
-            sim2.step()
-        torch.cuda.synchronize()
-        kt2 = B.timing_read()
-        L.axpic_timing_enable(0)
-        if "k_rates_mlp" in kt2:
-            launches2, tot2 = kt2["k_rates_mlp"]
-            tflops = evals * MLP_FLOP_PER_EVAL / (tot2 * 1e-3) / 1e12
-            sur["roofline"] = {"bound": "mfma", "kernel": "k_rates_mlp",
-                               "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,
-                               "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
-                               "traffic": None, "avg_ms": round(tot2 / launches2, 5),
-                               "evals_per_step": evals / 3, "flop_per_eval": MLP_FLOP_PER_EVAL}
-            sur["kernel_ms_per_step"] = {k: round(v[1] / 3, 5) for k, v in sorted(kt2.items())}
-        del sim2
+        def surrogate_leg(mode):
+            pl = I.make_plasma(wl)
+            sim2 = AxpicSim(pl, wl.params, axion_capacity=est_ax, surrogate=S,
+                            surrogate_mode=mode)
+            del pl
+            for _ in range(a.warmup):
+                sim2.step()
+            torch.cuda.synchronize()
+            upd2 = 0
+            e0.record()
+            for _ in range(a.steps):
+                upd2 += updates_per_step(sim2, sim2.ax.n)
+                sim2.step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms2 = e0.elapsed_time(e1)
+            res = {"value": upd2 / (ms2 * 1e-3), "unit": "updates/s",
+                   "ms_per_step": ms2 / a.steps, "train_s": round(t_train, 2),
+                   "train_steps": a.train_steps, "train_samples": 2_000_000,
+                   "final_loss": losses[-1][1] if losses else None,
+                   "fallback_evals": int(sim2.fallback.item()),
+                   "speed_vs_plain": round((upd2 / (ms2 * 1e-3)) / value, 4)}
+            Q = q_mc(sim2.hist_np(), sim2.step_index)
+            print(f"[bench] surrogate ({mode}): {ms2 / a.steps:.3f} ms/step, "
+                  f"{res['value']:.3e} updates/s", file=sys.stderr, flush=True)
+            # the network kernel against the matrix-core peak.  Evaluations per step:
+            # per particle, photons (lambda_P) + 4 per old axion (three thermal channels and
+            # a->gamma); per cell, nodes x (Primakoff + three thermal channels)
+            L.axpic_timing_enable(1)
+            evals = 0
+            for _ in range(3):
+                if mode == "particle":
+                    evals += sim2.ph.n + 4 * sim2.ax.n
+                else:
+                    evals += sim2.ncell * S.TABLE_NODES * 4
+                sim2.step()
+            torch.cuda.synchronize()
+            kt2 = B.timing_read()
+            L.axpic_timing_enable(0)
+            kname = "k_rates_mlp" if mode == "particle" else "k_mlp_table"
+            if kname in kt2:
+                launches2, tot2 = kt2[kname]
+                tflops = evals * MLP_FLOP_PER_EVAL / (tot2 * 1e-3) / 1e12
+                res["roofline"] = {"bound": "mfma", "kernel": kname,
+                                   "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
+                                   "traffic": None, "avg_ms": round(tot2 / launches2, 5),
+                                   "evals_per_step": evals / 3,
+                                   "flop_per_eval": MLP_FLOP_PER_EVAL}
+            if mode == "table":
+                res["table"] = {"nodes": S.TABLE_NODES, "x_range": list(S.TABLE_RANGE)}
+            res["kernel_ms_per_step"] = {k: round(v[1] / 3, 5) for k, v in sorted(kt2.items())}
+            del sim2
+            torch.cuda.empty_cache()
+            return res, Q
+        sur, Q_mc2 = surrogate_leg("particle")
+        sur_tab, Q_mc4 = surrogate_leg("table")
 
     # ---- power check against the closed-form emissivities, CPU baseline (oracle)
     power = None
@@ -380,6 +394,7 @@ def main():
         power = {ch: round(Q_mc[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
         if sur is not None:
             sur["power_err"] = {ch: round(Q_mc2[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
+            sur_tab["power_err"] = {ch: round(Q_mc4[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
         if sup is not None:
             sup["power_err"] = {ch: round(Q_mc3[ch] / Qa[ch] - 1.0, 5) for ch in "PCB"}
         cpu = cpu_baseline(wl, a.cpu_seconds)
@@ -399,6 +414,7 @@ def main():
         "power_err": power,
         "kernel_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
         "surrogate": sur,
+        "surrogate_table": sur_tab,
         "superposed_thermal": sup,
     }
     print(json.dumps(out), flush=True)

@@ -189,7 +189,7 @@ inline axpic_status launched() {
 
 
 // ------------------------------------------------------------------ kernel timing
-struct PendingTime { const char* name; hipEvent_t a, b; };
+struct PendingTime { const char* name; hipEvent_t a, b, ma, mb; };
 struct TimingState {
     std::mutex mu;
     bool on = false;
@@ -1897,14 +1897,18 @@ axpic_status axpic_sampler_table(int32_t which, double k, double* out) {
 }  // extern "C"
 
 namespace axpic_timing {
-bool begin(const char* name, hipEvent_t* a, hipEvent_t* b) {
+bool begin(const char* name, hipEvent_t ev[4]) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lock(t.mu);
     if (!t.on) return false;
-    *a = pool_get(t);
-    *b = pool_get(t);
-    if (!*a || !*b) return false;
-    t.pending.push_back({name, *a, *b});
+    for (int k = 0; k < 4; ++k) {
+        ev[k] = pool_get(t);
+        if (!ev[k]) {
+            for (int j = 0; j < k; ++j) t.pool.push_back(ev[j]);
+            return false;
+        }
+    }
+    t.pending.push_back({name, ev[0], ev[1], ev[2], ev[3]});
     return true;
 }
 }  // namespace axpic_timing
@@ -1921,14 +1925,19 @@ axpic_status axpic_timing_read(char* buf, size_t len) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lock(t.mu);
     for (auto& p : t.pending) {
-        float ms = 0.0f;
-        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+        // the dispatch's own events give the kernel's duration, but their start has been
+        // seen to lie far too early on a queue shared with other work; the stream markers
+        // around the launch bound the duration from above, so the smaller is kept
+        float ms = 0.0f, mm = 0.0f;
+        if (hipEventSynchronize(p.mb) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess ||
+            hipEventElapsedTime(&mm, p.ma, p.mb) != hipSuccess)
             return AXPIC_E_DEVICE;
+        ms = std::min(ms, mm);
         bool found = false;
         for (auto& e : t.acc)
             if (e.first == p.name) { e.second.first += 1; e.second.second += ms; found = true; break; }
         if (!found) t.acc.push_back({p.name, {1, (double)ms}});
-        t.pool.push_back(p.a); t.pool.push_back(p.b);
+        t.pool.push_back(p.a); t.pool.push_back(p.b); t.pool.push_back(p.ma); t.pool.push_back(p.mb);
     }
     t.pending.clear();
     if (!buf || len == 0) return AXPIC_E_INVAL;

@@ -63,7 +63,7 @@ class ParamsC(C.Structure):
                 ("T_mode", C.c_int32), ("feedback", C.c_int32),
                 ("r_relax", C.c_double), ("T_floor_keV", C.c_double), ("T_ceil_keV", C.c_double),
                 ("seed", C.c_uint64), ("hist_lo_keV", C.c_double), ("hist_hi_keV", C.c_double),
-                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32)]
+                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32), ("m_a_keV", C.c_double)]
 
 
 class Species(C.Structure):
@@ -118,7 +118,13 @@ def _declare(L):
     L.or_absorb.argtypes = [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P,
                             _P, _P]
     L.or_feedback.argtypes = [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P]
-    L.or_push.argtypes = [_P, _P, C.c_int32]
+    L.or_push.argtypes = [_P, _P, C.c_int32, C.c_double]
+    for f in ("or_F_mass", "or_F_mass_quad"):
+        getattr(L, f).restype = _D; getattr(L, f).argtypes = [_D, _D, _D]
+    L.or_gamma_conv.restype = _D; L.or_gamma_conv.argtypes = [_P, _P, _D]
+    L.or_axion_energy.restype = _D; L.or_axion_energy.argtypes = [_P, _D]
+    L.or_compton_x_above.restype = _D; L.or_compton_x_above.argtypes = [_D, _D]
+    L.or_gamma_x_above.restype = _D; L.or_gamma_x_above.argtypes = [_D, _D, _D]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -441,10 +447,33 @@ def feedback(grid, params, off, el: OSpecies, fb, T, stats=None, moments=None):
                   _ptr(moments))
 
 
-def push(grid, ax: OSpecies, prec32: bool):
+def push(grid, ax: OSpecies, prec32: bool, m_a_keV: float = 0.0):
+    """Ballistic push (axions of mass m_a_keV move at p / sqrt(p^2 + (m/m_e)^2))."""
     L = load(); G = make_grid(grid)
     S = ax.struct()
-    L.or_push(_ref(G), _ref(S), 1 if prec32 else 0)
+    L.or_push(_ref(G), _ref(S), 1 if prec32 else 0, float(m_a_keV))
+
+
+def F_mass(k, p, kappa2):
+    return load().or_F_mass(float(k), float(p), float(kappa2))
+
+
+def F_mass_quad(k, p, kappa2):
+    return load().or_F_mass_quad(float(k), float(p), float(kappa2))
+
+
+def gamma_conv(cell_rec, params, omega_keV):
+    P = make_params(params)
+    c = np.ascontiguousarray(np.array(cell_rec, dtype=CELL_DTYPE).reshape(1))
+    return load().or_gamma_conv(_ptr(c), _ref(P), float(omega_keV))
+
+
+def compton_x_above(xm, u):
+    return load().or_compton_x_above(float(xm), float(u))
+
+
+def gamma_x_above(k, ym, u):
+    return load().or_gamma_x_above(float(k), float(ym), float(u))
 
 
 # ---------------------------------------------------------------------------
@@ -496,7 +525,7 @@ class OracleSim:
     def step(self, lam_P=None, lam_T=None, pabs=None, lam_ag=None):
         p = self.pdict
         s = self.step_index
-        push(self.grid, self.ax, self.prec32)
+        push(self.grid, self.ax, self.prec32, p["m_a_keV"])
         cells = self.cells()
         self.fb[:] = 0.0
         n_ax0 = self.ax.n
@@ -530,7 +559,8 @@ class OracleSim:
         return cells
 
     def totals(self):
-        E = ME_KEV * np.sqrt((self.ax.p ** 2).sum(axis=0))
+        mu = self.pdict["m_a_keV"] / ME_KEV
+        E = ME_KEV * np.sqrt((self.ax.p ** 2).sum(axis=0) + mu * mu)
         return dict(N_a=float(self.ax.w.sum()), U_a=float((self.ax.w * E).sum()))
 
 

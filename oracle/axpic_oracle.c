@@ -251,6 +251,85 @@ double or_gamma_prim(const or_cell* c, const or_params* prm, double omega_keV) {
     return c->G_P0 * or_F(s);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Finite-mass axions.  The paper gives the kinematics E = sqrt(p^2 + m^2)   */
+/* and the sub-luminal velocity (Sec. II.B) and says that thresholds and     */
+/* absorption coefficients change with the mass, without printing them.     */
+/* Readings (c = 1, energies and momenta in keV):                           */
+/*  M1 E = sqrt(m_e^2 |p|^2 + m^2), push velocity p / sqrt(|p|^2 + (m/m_e)^2).*/
+/*  M2 photon (momentum k = omega) -> axion (momentum p = sqrt(k^2 - m^2))  */
+/*     on a screened static charge: the massless amplitude |k x p|^2 over   */
+/*     q^2 (q^2 + kappa^2), q = k - p, with the final-state factor p/k, so   */
+/*     Gamma = G_P0 (p/k) F_mass(k, p); zero for omega <= m.  F_mass is 2x  */
+/*     the angular integral int_{-1}^{1} dc k^2 p^2 (1-c^2)/(q^2(q^2+kappa^2))*/
+/*     in closed form; F_mass(k, k) = F(4 k^2/kappa^2).                     */
+/*  M3 the axion keeps the photon's direction with |p|; a->gamma turns an   */
+/*     axion of energy E into a photon of energy E along it, at the rate    */
+/*     prim_inv_ratio (k/p) Gamma_{gamma->a}(E) (the massive phase space in */
+/*     detailed balance) = prim_inv_ratio G_P0 F_mass(E, p).                 */
+/*  M4 thermal emission: the sampled number spectrum is cut at E = m; the   */
+/*     rate is the massless one times the spectrum's fraction above m and   */
+/*     energies are drawn by inversion at F(m/T) + u (1 - F(m/T)).          */
+/*  M5 absorption: the massive equilibrium density dn_eq/dE = E p f(E/T) /  */
+/*     (2 pi^2 (hbar c)^3) gives Gamma_abs the factor E/p (zero below m).   */
+/* Energy exchanged with the plasma is the total energy E.                  */
+/* ------------------------------------------------------------------------ */
+double or_axion_energy(const or_params* prm, double p2) {
+    double mu = prm->m_a_keV / OR_ME_KEV;
+    return OR_ME_KEV * sqrt(p2 + mu * mu);
+}
+
+double or_F_mass(double k, double p, double kappa2) {
+    if (!(k > 0.0) || !(p > 0.0)) return 0.0;
+    if (p >= k) return or_F(4.0 * k * k / kappa2);
+    /* with a = 4kp, A = (k-p)^2 + kappa^2: the logarithms are log1p(a/A) and
+     * log1p(a/(k-p)^2), which keeps them accurate when p << k */
+    long double K = k, P = p, k2 = kappa2;
+    long double a = 4.0L * K * P, am = (K - P) * (K - P), A = am + k2;
+    long double t1 = (A + a) * A / (a * k2) * log1pl(a / A);
+    long double t2 = am * (am + a) / (a * k2) * log1pl(a / am);
+    return (double)(t1 - t2 - 1.0L);
+}
+
+static void or_gl_init(void);
+static double or_gl_x[10], or_gl_w[10];
+
+/* The same angular integral by quadrature: with t = 1 - cos(theta) it is
+ * (1/2) int_0^2 t (2 - t) / ((t + b1)(t + b2)) dt, b1 = (k-p)^2/(2kp),
+ * b2 = ((k-p)^2 + kappa^2)/(2kp); 10-point Gauss-Legendre panels halving
+ * towards t = 0 down to well below the smaller nonzero of b1, b2.          */
+double or_F_mass_quad(double k, double p, double kappa2) {
+    if (!(k > 0.0) || !(p > 0.0)) return 0.0;
+    or_gl_init();
+    const double b1 = (k - p) * (k - p) / (2.0 * k * p);
+    const double b2 = ((k - p) * (k - p) + kappa2) / (2.0 * k * p);
+    const double bmin = (b1 > 0.0 && b1 < b2) ? b1 : b2;   /* finest feature of the integrand */
+    int J = 12;
+    while (2.0 * pow(0.5, J) > 1e-3 * bmin && J < 200) ++J;
+    double sum = 0.0, hi = 2.0;
+    for (int j = 1; j <= J + 1; ++j) {
+        double lo = (j <= J) ? 2.0 * pow(0.5, j) : 0.0;
+        double h = 0.5 * (hi - lo), m = 0.5 * (hi + lo), acc = 0.0;
+        for (int i = 0; i < 10; ++i) {
+            double t = m + h * or_gl_x[i];
+            acc += or_gl_w[i] * t * (2.0 - t) / ((t + b1) * (t + b2));
+        }
+        sum += acc * h;
+        hi = lo;
+    }
+    return 0.5 * sum;
+}
+
+/* Gamma_{gamma->a} of a photon of energy omega (M2; the massless eq. prim_rate
+ * when m = 0). */
+double or_gamma_conv(const or_cell* c, const or_params* prm, double omega_keV) {
+    const double m = prm->m_a_keV;
+    if (!(m > 0.0)) return or_gamma_prim(c, prm, omega_keV);
+    if (!(omega_keV > m)) return 0.0;
+    const double k = omega_keV, p = sqrt((k - m) * (k + m));
+    return c->G_P0 * (p / k) * or_F_mass(k, p, c->kappa2);
+}
+
 /* Normalised number spectra that the thermal samplers draw from.           */
 static double or_pdf_compton(double E, double T) {          /* x^4/(e^x-1)/(24 zeta5) / T */
     double x = E / T;
@@ -272,6 +351,9 @@ static double or_dneq(double E, double T, int mb) {
 double or_gamma_abs(const or_cell* c, const or_params* prm, double E_keV, double* parts) {
     double gC = 0.0, gB = 0.0;
     double neq = or_dneq(E_keV, c->T, prm->eq_stats);
+    const double m = prm->m_a_keV;
+    if (m > 0.0)   /* M5: E p instead of E^2 in dn_eq/dE */
+        neq = E_keV > m ? neq * sqrt((E_keV - m) * (E_keV + m)) / E_keV : 0.0;
     if (neq > 0.0) {
         if (prm->channels & OR_CH_C)
             gC = c->n_e_dep * c->G_C * or_pdf_compton(E_keV, c->T) / neq;
@@ -434,6 +516,24 @@ double or_gamma_x(double k, double u) {
     return or_invert(ccdf_g, pdf_g, par, 1.0 - u, 1, 0.0, 200.0);
 }
 
+/* Draws from the spectra cut below a threshold (M4): the quantile at
+ * F(xm) + u (1 - F(xm)), the upper tail (1 - u)(1 - F(xm)) inverted directly
+ * where it is the smaller side.  xm = 0 reproduces the uncut draws.         */
+double or_compton_x_above(double xm, double u) {
+    const double F = or_compton_cdf(xm), Q = or_compton_ccdf(xm);
+    const double lo = F + u * Q, up = (1.0 - u) * Q;
+    if (lo <= 0.5) return or_invert(cdf_c, pdf_c, NULL, lo, 0, 0.0, 200.0);
+    return or_invert(ccdf_c, pdf_c, NULL, up, 1, 0.0, 200.0);
+}
+
+double or_gamma_x_above(double k, double ym, double u) {
+    double par[1] = {k};
+    const double F = or_gammainc_P(k, ym), Q = or_gammainc_Q(k, ym);
+    const double lo = F + u * Q, up = (1.0 - u) * Q;
+    if (lo <= 0.5) return or_invert(cdf_g, pdf_g, par, lo, 0, 0.0, 200.0);
+    return or_invert(ccdf_g, pdf_g, par, up, 1, 0.0, 200.0);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics: energy histogram bin (App. B).                              */
 /* ------------------------------------------------------------------------ */
@@ -504,7 +604,7 @@ int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell*
         } else {
             double px = ph->p[0][i], py = ph->p[1][i], pz = ph->p[2][i];
             double om = OR_ME_KEV * sqrt(px * px + py * py + pz * pz);
-            double G = or_gamma_prim(&cells[ph->cell[i]], prm, om);    /* eq. prim_rate */
+            double G = or_gamma_conv(&cells[ph->cell[i]], prm, om);    /* eq. prim_rate, M2 */
             double P = -expm1(-G * dtp);                                /* eq. prim_prob */
             l = ph->w[i] * P / wprod;                                   /* lambda_P */
         }
@@ -535,6 +635,10 @@ int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell*
         if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
         double p[3] = {ph->p[0][i], ph->p[1][i], ph->p[2][i]};     /* product inherits p */
         double E = OR_ME_KEV * sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        if (prm->m_a_keV > 0.0) {                      /* M3: energy kept, |p| reduced */
+            const double sc = sqrt((E - prm->m_a_keV) * (E + prm->m_a_keV)) / E;
+            p[0] *= sc; p[1] *= sc; p[2] *= sc;
+        }
         for (int32_t k = 0; k < K[i]; ++k) {
             or_put(out, rank, ph, i, p, wp, or_product_id(next_id, rank), 0);
             ++rank;
@@ -564,6 +668,33 @@ static void or_isotropic(double u1, double u2, double n[3]) {
 /* bremsstrahlung (Sec. II.H).  lam_in (optional) is [2][n]: Compton, brems. */
 /* fb is [ncell][4]: dE (m_e c^2 * count), dPx, dPy, dPz (m_e c * count).    */
 /* ------------------------------------------------------------------------ */
+/* Fraction of channel ch's sampled number spectrum above the axion mass (M4);
+ * 1 for massless axions. */
+static double or_thermal_fraction(const or_params* prm, int ch, double T) {
+    const double m = prm->m_a_keV;
+    if (!(m > 0.0)) return 1.0;
+    return ch == 1 ? or_compton_ccdf(m / T)
+                   : or_gammainc_Q(prm->brems_k, m / (prm->brems_theta * T));
+}
+
+/* Energy E [keV] and momentum magnitude pm [m_e c] of a thermal product of
+ * channel ch (1 Compton-like, 2 brems) drawn at uniform u (Secs. II.G-H; M4). */
+static void or_thermal_energy(const or_params* prm, int ch, double T, double u, double* E,
+                              double* pm) {
+    const double m = prm->m_a_keV;
+    double x;
+    if (!(m > 0.0)) {
+        x = (ch == 1) ? or_compton_x(u) : prm->brems_theta * or_gamma_x(prm->brems_k, u);
+        *E = T * x;
+        *pm = *E / OR_ME_KEV;
+        return;
+    }
+    x = (ch == 1) ? or_compton_x_above(m / T, u)
+                  : prm->brems_theta * or_gamma_x_above(prm->brems_k, m / (prm->brems_theta * T), u);
+    *E = T * x;
+    *pm = (*E > m) ? sqrt((*E - m) * (*E + m)) / OR_ME_KEV : 0.0;
+}
+
 int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* cells,
                         const or_species* el, const double* lam_in, int64_t step,
                         uint64_t next_id, or_products* out, double* fb, double* hist,
@@ -583,6 +714,8 @@ int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* c
         else {
             lC = el->w[i] * c->G_C * dtp / wC;      /* eq. lambda_macro */
             lB = el->w[i] * c->G_B * dtp / wB;
+            lC *= or_thermal_fraction(prm, 1, c->T);   /* M4: the part above m */
+            lB *= or_thermal_fraction(prm, 2, c->T);
         }
         if (!onC) lC = 0.0;
         if (!onB) lB = 0.0;
@@ -611,19 +744,17 @@ int64_t or_emit_thermal(const or_grid* g, const or_params* prm, const or_cell* c
                 uint32_t r[4];
                 or_draw(prm->seed, el->id[i], (uint32_t)step, (uint32_t)(ch + 1), (uint32_t)k, r);
                 double u = or_u24(r[0]);
-                double x = (ch == 1) ? or_compton_x(u)
-                                     : prm->brems_theta * or_gamma_x(prm->brems_k, u);
-                double E = c->T * x;                     /* keV */
+                double E, pm;
+                or_thermal_energy(prm, ch, c->T, u, &E, &pm);
                 double nh[3];
                 or_isotropic(or_u24(r[1]), or_u24(r[2]), nh);
-                double pm = E / OR_ME_KEV;
                 double p[3] = {pm * nh[0], pm * nh[1], pm * nh[2]};
                 or_put(out, rank, el, i, p, wp, or_product_id(next_id, rank), ch);
                 ++rank;
                 or_hist_add(hist, prm, ch, E, wp);
                 if (fb) {                               /* energy/momentum leave the plasma */
                     double* f = &fb[(int64_t)el->cell[i] * 4];
-                    f[0] -= wp * pm;
+                    f[0] -= wp * E / OR_ME_KEV;
                     f[1] -= wp * p[0]; f[2] -= wp * p[1]; f[3] -= wp * p[2];
                 }
                 if (stats) {
@@ -686,7 +817,8 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
         if (W_in) W = W_in[c];
         for (int ch = 1; ch <= 2; ++ch) {
             double k = coef_in ? coef_in[(ch - 1) * ncell + c]
-                               : (ch == 1 ? cells[c].G_C : cells[c].G_B) * dtp / wprod[ch];
+                               : (ch == 1 ? cells[c].G_C : cells[c].G_B) * dtp / wprod[ch] *
+                                     or_thermal_fraction(prm, ch, cells[c].T);
             if (!on[ch]) k = 0.0;
             coef[(ch - 1) * ncell + c] = k;
             double L;
@@ -749,19 +881,17 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
                 if (stats && capped) stats[OR_ST_CAPPED] += 1.0;
                 or_draw(prm->seed, (uint64_t)c, (uint32_t)step, (uint32_t)(6 + ch), (uint32_t)j, r);
                 double u = or_u24(r[0]);
-                double x = (ch == 1) ? or_compton_x(u)
-                                     : prm->brems_theta * or_gamma_x(prm->brems_k, u);
-                double E = cells[c].T * x;
+                double E, pm;
+                or_thermal_energy(prm, ch, cells[c].T, u, &E, &pm);
                 double nh[3];
                 or_isotropic(or_u24(r[1]), or_u24(r[2]), nh);
-                double pm = E / OR_ME_KEV;
                 double p[3] = {pm * nh[0], pm * nh[1], pm * nh[2]};
                 or_put(out, rank, el, pick, p, wp, or_product_id(next_id, rank), ch);
                 ++rank;
                 or_hist_add(hist, prm, ch, E, wp);
                 if (fb) {
                     double* f = &fb[c * 4];
-                    f[0] -= wp * pm;
+                    f[0] -= wp * E / OR_ME_KEV;
                     f[1] -= wp * p[0]; f[2] -= wp * p[1]; f[3] -= wp * p[2];
                 }
                 if (stats) {
@@ -803,7 +933,8 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
         if (!(w > 0.0)) continue;
         const or_cell* c = &cells[ax->cell[i]];
         double px = ax->p[0][i], py = ax->p[1][i], pz = ax->p[2][i];
-        double E = OR_ME_KEV * sqrt(px * px + py * py + pz * pz);
+        double p2 = px * px + py * py + pz * pz;
+        double E = prm->m_a_keV > 0.0 ? or_axion_energy(prm, p2) : OR_ME_KEV * sqrt(p2);
         uint32_t r[4];
         or_draw(prm->seed, ax->id[i], (uint32_t)step, 4, 0, r);
         if (thermal) {
@@ -819,7 +950,10 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
             double l;
             if (lam_in) l = lam_in[i];
             else {
-                double G = prm->prim_inv_ratio * or_gamma_prim(c, prm, E);
+                double G = prm->m_a_keV > 0.0
+                               ? prm->prim_inv_ratio * c->G_P0 *
+                                     or_F_mass(E, OR_ME_KEV * sqrt(p2), c->kappa2)   /* M3 */
+                               : prm->prim_inv_ratio * or_gamma_prim(c, prm, E);
                 l = w * (-expm1(-G * dtp)) / wg;
             }
             lam[i] = l;
@@ -839,12 +973,15 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
         if (!(w > 0.0)) continue;
         double p[3] = {ax->p[0][i], ax->p[1][i], ax->p[2][i]};
         double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-        double E = OR_ME_KEV * pm;
+        double E = prm->m_a_keV > 0.0 ? or_axion_energy(prm, pm * pm) : OR_ME_KEV * pm;
         double* f = fb ? &fb[(int64_t)ax->cell[i] * 4] : NULL;
         if (thermal) {
             double dw = dead[i] ? w : (prm->absorb_mode == 1 ? w * pab[i] : 0.0);
             if (dw > 0.0) {
-                if (f) { f[0] += dw * pm; f[1] += dw * p[0]; f[2] += dw * p[1]; f[3] += dw * p[2]; }
+                if (f) {
+                    f[0] += dw * E / OR_ME_KEV;
+                    f[1] += dw * p[0]; f[2] += dw * p[1]; f[3] += dw * p[2];
+                }
                 if (stats) {
                     stats[OR_ST_ABS_NUM] += dw; stats[OR_ST_ABS_EN] += dw * E;
                     if (dead[i]) stats[OR_ST_ABS_EVENTS] += 1.0;
@@ -860,8 +997,13 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
             double wp = wg * ws;
             double dep = (double)K[i] * wp;
             if (dep > w) { wp = w / (double)K[i]; dep = w; if (stats) stats[OR_ST_OVERDEPLETED] += 1.0; }
+            double pg[3] = {p[0], p[1], p[2]};            /* M3: the photon carries E */
+            if (prm->m_a_keV > 0.0) {
+                const double sc = E / (OR_ME_KEV * pm);
+                pg[0] *= sc; pg[1] *= sc; pg[2] *= sc;
+            }
             for (int32_t k = 0; k < K[i]; ++k) {
-                or_put(out, rank, ax, i, p, wp, or_product_id(next_id, rank), 3);
+                or_put(out, rank, ax, i, pg, wp, or_product_id(next_id, rank), 3);
                 ++rank;
                 if (stats) { stats[OR_ST_AG_EVENTS] += 1.0; stats[OR_ST_AG_NUM] += wp; stats[OR_ST_AG_EN] += wp * E; }
             }
@@ -944,14 +1086,16 @@ void or_feedback(const or_grid* g, const or_params* prm, int64_t ncell, const in
 /* operations only, so that the cell index is decided identically by any    */
 /* IEEE implementation of the same steps.                                    */
 /* ------------------------------------------------------------------------ */
-void or_push(const or_grid* g, or_species* ax, int32_t prec32) {
+void or_push(const or_grid* g, or_species* ax, int32_t prec32, double m_a_keV) {
     const double dtdx64 = g->dt / g->dx;
     const float dtdx32 = (float)dtdx64;
+    const double mu = m_a_keV / OR_ME_KEV, mu2 = mu * mu;   /* v = p / sqrt(p^2 + mu^2) */
+    const float mu2f = (float)mu2;
     for (int64_t i = 0; i < ax->n; ++i) {
         int64_t cell = 0, stride = 1;
         if (prec32) {
             float px = (float)ax->p[0][i], py = (float)ax->p[1][i], pz = (float)ax->p[2][i];
-            float s = fmaf(pz, pz, fmaf(py, py, px * px));
+            float s = fmaf(pz, pz, fmaf(py, py, fmaf(px, px, mu2f)));   /* M1 */
             float inv = s > 0.0f ? 1.0f / sqrtf(s) : 0.0f;
             float pv[3] = {px, py, pz};
             for (int d = 0; d < 3; ++d) {
@@ -972,7 +1116,7 @@ void or_push(const or_grid* g, or_species* ax, int32_t prec32) {
             }
         } else {
             double px = ax->p[0][i], py = ax->p[1][i], pz = ax->p[2][i];
-            double s = fma(pz, pz, fma(py, py, px * px));
+            double s = fma(pz, pz, fma(py, py, fma(px, px, mu2)));
             double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
             double pv[3] = {px, py, pz};
             for (int d = 0; d < 3; ++d) {
@@ -1041,7 +1185,7 @@ void or_surrogate_labels(const or_params* prm, int64_t n, const double* T, const
 #pragma omp parallel for if (n > 4096)
     for (int64_t i = 0; i < n; ++i) {
         or_params p = *prm;
-        p.g_agg_GeV = 1.0; p.g_ae = 1.0; p.boost = 1.0; p.inverse = 1;
+        p.g_agg_GeV = 1.0; p.g_ae = 1.0; p.boost = 1.0; p.inverse = 1; p.m_a_keV = 0.0;
         double Zi = Z[i], Ai = (Zi == 1.0) ? 1.0 : 4.0;
         double di = ne[i] / Zi;
         or_cell c;

@@ -5,7 +5,8 @@
  * the benchmark's CPU-baseline leg may load it; the product path never does.
  * It shares no code, header, table or constant generator with the HIP path.
  *
- * Units: momenta in m_e c, energies of massless particles E = m_e c^2 |p|,
+ * Units: momenta in m_e c, energies of massless particles E = m_e c^2 |p|
+ * (axions of mass m: E = sqrt(m_e^2 c^4 |p|^2 + m^2 c^4)),
  * positions in cell units, weights are PHYSICAL particle counts, temperatures
  * in keV, densities in cm^-3, rates in s^-1.
  */
@@ -45,6 +46,7 @@ typedef struct {
     uint64_t seed;
     double hist_lo_keV, hist_hi_keV;
     int32_t hist_nbins, hist_log;
+    double m_a_keV;           /* axion mass; 0: massless */
 } or_params;
 
 typedef struct {
@@ -102,6 +104,13 @@ void or_cell_state(const or_grid* g, const or_params* prm, int64_t ncell, const 
                    const double* dens_e, int32_t nion, const double* dens_ion /* [nion][ncell] */,
                    const double* Zion, const double* Aion, or_cell* out);
 double or_gamma_prim(const or_cell* c, const or_params* prm, double omega_keV);
+/* Finite-mass axions (prm->m_a_keV > 0). */
+double or_F_mass(double k, double p, double kappa2);
+double or_F_mass_quad(double k, double p, double kappa2);
+double or_gamma_conv(const or_cell* c, const or_params* prm, double omega_keV);
+double or_axion_energy(const or_params* prm, double p2);
+double or_compton_x_above(double xm, double u);
+double or_gamma_x_above(double k, double ym, double u);
 double or_gamma_abs(const or_cell* c, const or_params* prm, double E_keV, double* parts);
 double or_dt_phys(const or_grid* g);
 double or_V_cell(const or_grid* g);
@@ -139,7 +148,7 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
 void or_feedback(const or_grid* g, const or_params* prm, int64_t ncell, const int64_t* off,
                  or_species* el, const double* fb, double* T, double* stats,
                  double* moments_out);
-void or_push(const or_grid* g, or_species* ax, int32_t prec32);
+void or_push(const or_grid* g, or_species* ax, int32_t prec32, double m_a_keV);
 
 /* ---- surrogate training data ---- */
 double or_F_quad(double s);

@@ -82,6 +82,7 @@ class Params:
     hist_hi_keV: float = 20.0
     hist_nbins: int = 128
     hist_log: int = 1
+    m_a_keV: float = 0.0              # axion mass (0: massless, the paper's validated case)
 
     def as_dict(self) -> Dict:
         return asdict(self)

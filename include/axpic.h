@@ -166,6 +166,12 @@ typedef struct {
     double hist_lo_keV, hist_hi_keV;
     int32_t hist_nbins;     /* histogram bins (+2 under/overflow slots) per channel */
     int32_t hist_log;       /* 1: logarithmic bins */
+    double m_a_keV;         /* axion mass [keV]; 0: massless.  Sec. II.B gives only the
+                               kinematics E = sqrt(p^2 + m^2); with m > 0 the push moves at
+                               p/E, photons convert above omega = m with the massive screened
+                               kernel and keep their energy, thermal spectra are cut at m and
+                               absorption uses the massive equilibrium density (E p instead
+                               of E^2).  The rate surrogate is massless only. */
 } axpic_params;
 
 /* Statistics slots (FP64, accumulated by the calls that own them). */
@@ -186,13 +192,15 @@ int32_t axpic_version(void);
  * n_max particles. */
 size_t axpic_workspace_bytes(int64_t n_max);
 
-/* axpic_bin_cells -- Sec. II.B, II.E.  For a massless species (axions):
- * if `push` != 0 advance x by v dt/dx with v = p/|p| (periodic), then
+/* axpic_bin_cells -- Sec. II.B, II.E.  For a species of rest mass m_keV
+ * (axions; 0 massless): if `push` != 0 advance x by v dt/dx with
+ * v = p / sqrt(|p|^2 + (m/m_e c^2)^2) (= p/|p| when massless; periodic), then
  * recompute `cell` by nearest-grid-point binning of x (always).  Position
  * arithmetic uses only correctly rounded IEEE operations (fma, sqrt, div) in
- * the storage precision.  Returns AXPIC_E_INVAL for a NULL array or a
- * species whose dims exceed the grid. */
-axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, void* stream);
+ * the storage precision.  Returns AXPIC_E_INVAL for a NULL array, a negative
+ * mass or a species whose dims exceed the grid. */
+axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, double m_keV,
+                             void* stream);
 
 /* axpic_deposit -- Sec. II.E (NGP deposit).  dens[slot][c] = w_ref * sum of
  * w over the particles of cell c / V_cell, for a species grouped by cell
@@ -306,9 +314,10 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
                            void* ws, size_t ws_bytes, void* stream);
 
 /* axpic_diag -- Sec. III.E: out[0] = N_a = sum w_ref w, out[1] = U_a =
- * sum w_ref w E [keV] over the species (FP64, deterministic order). */
-axpic_status axpic_diag(const axpic_species* sp, double* out, void* ws, size_t ws_bytes,
-                        void* stream);
+ * sum w_ref w E [keV] over the species (FP64, deterministic order), with
+ * E = sqrt(m_e^2 |p|^2 + m^2) for particles of rest mass m_keV (0: massless). */
+axpic_status axpic_diag(const axpic_species* sp, double m_keV, double* out, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* axpic_sampler_table -- host-only access to the thermal energy samplers'
  * quantile tables (no device work).  which = 0: Compton-like number spectrum

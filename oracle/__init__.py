@@ -125,6 +125,8 @@ def _declare(L):
     L.or_axion_energy.restype = _D; L.or_axion_energy.argtypes = [_P, _D]
     L.or_compton_x_above.restype = _D; L.or_compton_x_above.argtypes = [_D, _D]
     L.or_gamma_x_above.restype = _D; L.or_gamma_x_above.argtypes = [_D, _D, _D]
+    L.or_compton_x_tail.restype = _D; L.or_compton_x_tail.argtypes = [_D]
+    L.or_gamma_x_tail.restype = _D; L.or_gamma_x_tail.argtypes = [_D, _D]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -474,6 +476,14 @@ def compton_x_above(xm, u):
 
 def gamma_x_above(k, ym, u):
     return load().or_gamma_x_above(float(k), float(ym), float(u))
+
+
+def compton_x_tail(q):
+    return load().or_compton_x_tail(float(q))
+
+
+def gamma_x_tail(k, q):
+    return load().or_gamma_x_tail(float(k), float(q))
 
 
 # ---------------------------------------------------------------------------

@@ -516,6 +516,17 @@ double or_gamma_x(double k, double u) {
     return or_invert(ccdf_g, pdf_g, par, 1.0 - u, 1, 0.0, 200.0);
 }
 
+/* Quantiles by upper-tail probability q (the x with P(X > x) = q), for
+ * checking tables far into the tail where 1 - u is not representable.    */
+double or_compton_x_tail(double q) {
+    return or_invert(ccdf_c, pdf_c, NULL, q, 1, 0.0, 400.0);
+}
+
+double or_gamma_x_tail(double k, double q) {
+    double par[1] = {k};
+    return or_invert(ccdf_g, pdf_g, par, q, 1, 0.0, 400.0);
+}
+
 /* Draws from the spectra cut below a threshold (M4): the quantile at
  * F(xm) + u (1 - F(xm)), the upper tail (1 - u)(1 - F(xm)) inverted directly
  * where it is the smaller side.  xm = 0 reproduces the uncut draws.         */
@@ -636,7 +647,8 @@ int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell*
         double p[3] = {ph->p[0][i], ph->p[1][i], ph->p[2][i]};     /* product inherits p */
         double E = OR_ME_KEV * sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         if (prm->m_a_keV > 0.0) {                      /* M3: energy kept, |p| reduced */
-            const double sc = sqrt((E - prm->m_a_keV) * (E + prm->m_a_keV)) / E;
+            const double sc = E > prm->m_a_keV ? sqrt((E - prm->m_a_keV) * (E + prm->m_a_keV)) / E
+                                               : 0.0;     /* (a mean handed in below threshold) */
             p[0] *= sc; p[1] *= sc; p[2] *= sc;
         }
         for (int32_t k = 0; k < K[i]; ++k) {

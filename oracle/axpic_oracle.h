@@ -110,6 +110,8 @@ double or_F_mass_quad(double k, double p, double kappa2);
 double or_gamma_conv(const or_cell* c, const or_params* prm, double omega_keV);
 double or_axion_energy(const or_params* prm, double p2);
 double or_compton_x_above(double xm, double u);
+double or_compton_x_tail(double q);
+double or_gamma_x_tail(double k, double q);
 double or_gamma_x_above(double k, double ym, double u);
 double or_gamma_abs(const or_cell* c, const or_params* prm, double E_keV, double* parts);
 double or_dt_phys(const or_grid* g);

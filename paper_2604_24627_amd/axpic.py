@@ -66,7 +66,7 @@ class ParamsC(C.Structure):
                 ("T_mode", C.c_int32), ("feedback", C.c_int32),
                 ("r_relax", C.c_double), ("T_floor_keV", C.c_double), ("T_ceil_keV", C.c_double),
                 ("seed", C.c_uint64), ("hist_lo_keV", C.c_double), ("hist_hi_keV", C.c_double),
-                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32)]
+                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32), ("m_a_keV", C.c_double)]
 
 
 EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axpic_bin_cells",
@@ -112,7 +112,7 @@ def load(path: Optional[str] = None):
     L.axpic_version.restype = C.c_int32
     L.axpic_workspace_bytes.restype = C.c_size_t; L.axpic_workspace_bytes.argtypes = [C.c_int64]
     for f, args in [
-        ("axpic_bin_cells", [_P, _P, C.c_int32, _P]),
+        ("axpic_bin_cells", [_P, _P, C.c_int32, C.c_double, _P]),
         ("axpic_deposit", [_P, _P, _P, _P, C.c_int32, _P]),
         ("axpic_cell_state", [_P, _P, _P, C.c_double, C.c_double, _P]),
         ("axpic_rates", [_P, _P, _P, _P, C.c_int32, _P, _P]),
@@ -122,7 +122,7 @@ def load(path: Optional[str] = None):
                           C.c_size_t, _P, _P]),
         ("axpic_feedback", [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
         ("axpic_compact", [_P, _P, _P, _P, C.c_size_t, _P]),
-        ("axpic_diag", [_P, _P, _P, C.c_size_t, _P]),
+        ("axpic_diag", [_P, C.c_double, _P, _P, C.c_size_t, _P]),
         ("axpic_sampler_table", [C.c_int32, C.c_double, _P]),
         ("axpic_timing_read", [C.c_char_p, C.c_size_t]),
         ("axpic_stream_copy", [_P, _P, C.c_size_t, _P]),

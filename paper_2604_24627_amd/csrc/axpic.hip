@@ -115,6 +115,9 @@ KParams make_kparams(const axpic_grid* g, const axpic_params* prm, double w_ref_
     k.feedback = prm->feedback;
     k.ndim = g->ndim;
     for (int d = 0; d < 3; ++d) k.n[d] = g->n[d];
+    k.m_a = prm->m_a_keV;
+    k.mu2 = (prm->m_a_keV / kMe) * (prm->m_a_keV / kMe);
+    k.massive = prm->m_a_keV > 0.0;
     return k;
 }
 
@@ -133,6 +136,7 @@ bool params_ok(const axpic_params* p) {
     if (!p) return false;
     if (!(p->lambda_cap > 0.0) || !(p->w_a > 0.0)) return false;
     if (!(p->r_relax >= 0.0 && p->r_relax <= 1.0)) return false;
+    if (!(p->m_a_keV >= 0.0 && p->m_a_keV < 1e6)) return false;
     if (p->hist_nbins < 1 || p->hist_nbins > kMaxBins || !(p->hist_hi_keV > p->hist_lo_keV))
         return false;
     if (p->hist_log && !(p->hist_lo_keV > 0.0)) return false;
@@ -420,6 +424,14 @@ k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restr
     pr[3] = onP ? G_P0 * dt_phys * w_ref_g / (prm.w_a * prm.wa_mul[0]) : 0.0;
     pr[4] = onC ? w_ref_e * G_C * dt_phys / (prm.w_a * prm.wa_mul[1]) : 0.0;
     pr[5] = onB ? w_ref_e * G_B * dt_phys / (prm.w_a * prm.wa_mul[2]) : 0.0;
+    if (prm.m_a_keV > 0.0) {     // massive axions: only the spectrum above the mass is emitted
+        if (T > 0.0) {
+            pr[4] *= compton_tail(prm.m_a_keV / T);
+            pr[5] *= gamma_tail(prm.brems_k, prm.m_a_keV / (prm.brems_theta * T));
+        } else {
+            pr[4] = pr[5] = 0.0;
+        }
+    }
     // detailed-balance absorption coefficients (eq. gamma_abs) times dt_phys
     const double twopi2hc3 = 2.0 * kPi * kPi * hc3;
     pr[6] = (prm.inverse && onC && T > 0.0)
@@ -457,7 +469,8 @@ k_bin(int64_t n, KParams kp, int push, T* __restrict__ x0, T* __restrict__ x1, T
     T pv[3] = {px[i], py[i], pz[i]};
     T inv = (T)0;
     if (push) {
-        const T s = dev_fma<T>(pv[2], pv[2], dev_fma<T>(pv[1], pv[1], pv[0] * pv[0]));
+        // |p|^2 + (m/m_e)^2: the mass term makes a massive axion sub-luminal (Sec. II.B)
+        const T s = dev_fma<T>(pv[2], pv[2], dev_fma<T>(pv[1], pv[1], dev_fma<T>(pv[0], pv[0], (T)kp.mu2)));
         inv = s > (T)0 ? (T)1 / dev_sqrt<T>(s) : (T)0;
     }
     const T dtdx = (T)kp.dtdx;
@@ -492,21 +505,27 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
     const T wt = w[i];
     T r = (T)0;
     if (mode == 0) {                       // photons, Primakoff
-        r = wt > (T)0 ? lambda_primakoff<T>(pc, wt, psq<T>(px, py, pz, i)) : (T)0;
+        r = wt > (T)0 ? (kp.massive ? lambda_primakoff_m<T>(kp, pc, wt, psq_d<T>(px, py, pz, i))
+                                    : lambda_primakoff<T>(pc, wt, psq<T>(px, py, pz, i)))
+                      : (T)0;
     } else if (mode == 1) {                // electrons, Compton
         r = wt * pc[4];
     } else if (mode == 2) {                // electrons, brems
         r = wt * pc[5];
     } else if (mode == 3) {                // axions, thermal absorption probability
-        r = wt > (T)0 ? pabs_thermal<T>(kp, pc, energy_keV(psq<T>(px, py, pz, i))) : (T)0;
+        r = wt > (T)0 ? (kp.massive ? pabs_thermal_m<T>(kp, pc, psq_d<T>(px, py, pz, i))
+                                    : pabs_thermal<T>(kp, pc, energy_keV(psq<T>(px, py, pz, i))))
+                      : (T)0;
     } else {                               // axions, a->gamma mean
-        r = wt > (T)0 ? lambda_ag<T>(kp, pc, wt, psq<T>(px, py, pz, i)) : (T)0;
+        r = wt > (T)0 ? (kp.massive ? lambda_ag_m<T>(kp, pc, wt, psq_d<T>(px, py, pz, i))
+                                    : lambda_ag<T>(kp, pc, wt, psq<T>(px, py, pz, i)))
+                      : (T)0;
     }
     out[i] = r;
 }
 
 // ------------------------------------------------------------------ Primakoff emission
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
@@ -546,8 +565,11 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         T l = (T)0;
         if (wt > (T)0)
             l = lam_in ? lv[j]
-                       : lambda_primakoff<T>(pcv[j], wt,
-                                             xv[j] * xv[j] + yv[j] * yv[j] + zv[j] * zv[j]);
+                       : (M ? lambda_primakoff_m<T>(kp, pcv[j], wt,
+                                                    (double)xv[j] * xv[j] + (double)yv[j] * yv[j] +
+                                                        (double)zv[j] * zv[j])
+                            : lambda_primakoff<T>(pcv[j], wt,
+                                                  xv[j] * xv[j] + yv[j] * yv[j] + zv[j] * zv[j]));
         int K = 0;
         if (l > (T)0) {
             double ws; int cp;
@@ -612,7 +634,7 @@ k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t*
 // reads a weight while it changes.  Every thread replaces only its own
 // slot's record by the final id: a record is never overwritten before the
 // thread that owns it has read it.
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_g,
               const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
@@ -644,9 +666,10 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
         const uint32_t K = code[i] & 0xFFu;
         if ((int64_t)K > total - e) continue;
         const T wt = w[i];
+        const T* pci = pref + (int64_t)cell[i] * AXPIC_PREF_N;
         const T l = lam_in ? lam_in[i]
-                           : lambda_primakoff<T>(pref + (int64_t)cell[i] * AXPIC_PREF_N, wt,
-                                                 psq<T>(px, py, pz, i));
+                           : (M ? lambda_primakoff_m<T>(kp, pci, wt, psq_d<T>(px, py, pz, i))
+                                : lambda_primakoff<T>(pci, wt, psq<T>(px, py, pz, i)));
         double ws; int cp;
         (void)cap_lambda((double)l, kp.cap, &ws, &cp);
         double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
@@ -654,8 +677,12 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
         double dep = (double)K * wp;
         const bool over = dep > wpar;
         if (over) { wp = wpar / (double)K; dep = wpar; }
-        const T pxv = px[i], pyv = py[i], pzv = pz[i];
+        T pxv = px[i], pyv = py[i], pzv = pz[i];
         const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
+        if (M) {                  // the axion keeps the photon's energy: |p| = sqrt(E^2 - m^2)
+            const double sc = E > kp.m_a ? sqrt((E - kp.m_a) * (E + kp.m_a)) / E : 0.0;
+            pxv = (T)((double)pxv * sc); pyv = (T)((double)pyv * sc); pzv = (T)((double)pzv * sc);
+        }
         const T xv0 = x0[i], xv1 = x1 ? x1[i] : (T)0, xv2 = x2 ? x2[i] : (T)0;
         const T wrel = (T)(wp / kp.w_a);
         const int32_t c = cell[i];
@@ -730,7 +757,7 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
     if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
 }
 
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
                const float* __restrict__ p32, const double* __restrict__ p64,
@@ -768,15 +795,15 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
         (void)cap_lambda((double)l, kp.cap, &ws, &cp);
         const double wp = kp.w_a * kp.wa_mul[ch] * ws;
         const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
-        const double xs = ch == 1 ? 1.0 : kp.brems_theta;
         const uint4 r = draw(kp, id(i), step, 1 + ch, k);
-        const double E = Tc * xs * quantile(tab, u24(r.x));
+        double E, pm;
+        thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
+        const double eu = M ? E / kMe : pm;                // energy in m_e c^2
         const double mu = 2.0 * u24(r.y) - 1.0;
         const double phi = 2.0 * kPi * u24(r.z);
         const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
         double sphi, cphi;
         sincos(phi, &sphi, &cphi);
-        const double pm = E / kMe;
         const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
         ax0[slot] = x0[i];
         if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
@@ -788,7 +815,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
         atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
         if (fb) {
             double* f = fb + (int64_t)c * 4;
-            atomicAdd(&f[0], -wp * pm);
+            atomicAdd(&f[0], -wp * eu);
             atomicAdd(&f[1], -wp * pa[0]);
             atomicAdd(&f[2], -wp * pa[1]);
             atomicAdd(&f[3], -wp * pa[2]);
@@ -802,7 +829,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
 
 // ------------------------------------------------------------------ absorption
 // code: bits 0-7 a->gamma count, bit 8 absorbed (deletion mode)
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
             const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
@@ -819,6 +846,7 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     uint32_t tot = 0, act = 0;
     T wv[kPer], p2v[kPer], Pv[kPer], lv[kPer];
+    double p2d[kPer];                                // massive axions only
     int32_t cv[kPer];
     uint64_t idv[kPer];
 #pragma unroll
@@ -827,6 +855,7 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
         const int64_t ii = i < n ? i : n - 1;
         wv[j] = w[ii];
         p2v[j] = psq<T>(px, py, pz, ii);
+        if (M) p2d[j] = psq_d<T>(px, py, pz, ii);
         cv[j] = cell[ii];
         idv[j] = id(ii);
         Pv[j] = pabs_in ? pabs_in[ii] : (T)0;
@@ -846,7 +875,9 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
             const T p2 = p2v[j];
             const uint4 r = draw(kp, idv[j], step, 4, 0);
             if (thermal) {
-                const T P = pabs_in ? Pv[j] : pabs_thermal<T>(kp, pc, energy_keV(p2));
+                const T P = pabs_in ? Pv[j]
+                                    : (M ? pabs_thermal_m<T>(kp, pc, p2d[j])
+                                         : pabs_thermal<T>(kp, pc, energy_keV(p2)));
                 if (kp.absorb_mode == 0) {
                     if (u53(r.x, r.y) < (double)P) { cd |= 256u; wt = (T)0; }
                 } else {
@@ -854,7 +885,8 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
                 }
             }
             if (a2g && wt > (T)0) {
-                const T l = lam_in ? lv[j] : lambda_ag<T>(kp, pc, wt, p2);
+                const T l = lam_in ? lv[j]
+                                   : (M ? lambda_ag_m<T>(kp, pc, wt, p2d[j]) : lambda_ag<T>(kp, pc, wt, p2));
                 double ws; int cp;
                 cd |= (uint32_t)poisson_inv(cap_lambda((double)l, kp.cap, &ws, &cp), u53(r.z, r.w));
             }
@@ -872,7 +904,7 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
     }
 }
 
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_a,
             const float* __restrict__ p32, const double* __restrict__ p64, T* __restrict__ w,
@@ -912,21 +944,25 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
             const T pxv = px[i], pyv = py[i], pzv = pz[i];
             const T p2 = pxv * pxv + pyv * pyv + pzv * pzv;
-            const double pm = sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
-            const double E = kMe * pm;
+            const double pp = psq_d<T>(px, py, pz, i);
+            const double pm = sqrt(pp);
+            const double E = M ? axion_energy(kp, pp) : kMe * pm;
+            const double eu = M ? E / kMe : pm;                // energy in m_e c^2
             double wphys = w_ref_a * (double)wt;
             if (thermal) {
                 double dw = 0.0;
                 if (cd & 256u) dw = wphys;
                 else if (kp.absorb_mode == 1) {
-                    const T P = pabs_in ? pabs_in[i] : pabs_thermal<T>(kp, pc, energy_keV(p2));
+                    const T P = pabs_in ? pabs_in[i]
+                                        : (M ? pabs_thermal_m<T>(kp, pc, pp)
+                                             : pabs_thermal<T>(kp, pc, energy_keV(p2)));
                     dw = wphys * (double)P;
                     wt = (T)((wphys - dw) / w_ref_a);
                 }
                 if (dw > 0.0) {
                     if (fb) {
                         double* f = fb + (int64_t)c * 4;
-                        atomicAdd(&f[0], dw * pm);
+                        atomicAdd(&f[0], dw * eu);
                         atomicAdd(&f[1], dw * (double)pxv);
                         atomicAdd(&f[2], dw * (double)pyv);
                         atomicAdd(&f[3], dw * (double)pzv);
@@ -939,7 +975,8 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                 wphys = w_ref_a * (double)wt;
             }
             if (K > 0) {
-                const T l = lam_in ? lam_in[i] : lambda_ag<T>(kp, pc, wt, p2);
+                const T l = lam_in ? lam_in[i]
+                                   : (M ? lambda_ag_m<T>(kp, pc, wt, pp) : lambda_ag<T>(kp, pc, wt, p2));
                 double ws; int cp;
                 (void)cap_lambda((double)l, kp.cap, &ws, &cp);
                 st[5] += cp ? 1.0 : 0.0;
@@ -947,6 +984,11 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                 double dep = (double)K * wp;
                 if (dep > wphys) { wp = wphys / (double)K; dep = wphys; st[6] += 1.0; }
                 const T wrel = (T)(wp / w_ref_g);
+                T gxv = pxv, gyv = pyv, gzv = pzv;
+                if (M) {          // the photon takes the axion's energy: |p_gamma| = E / m_e
+                    const double sc = pm > 0.0 ? E / (kMe * pm) : 0.0;
+                    gxv = (T)((double)pxv * sc); gyv = (T)((double)pyv * sc); gzv = (T)((double)pzv * sc);
+                }
                 for (uint32_t k = 0; k < K; ++k) {
                     const uint64_t rank = run + pre + k;
                     const int64_t slot = out_n + (int64_t)rank;
@@ -954,7 +996,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                         gx0[slot] = x0 ? x0[i] : (T)0;
                         if (gx1) gx1[slot] = x1 ? x1[i] : (T)0;
                         if (gx2) gx2[slot] = x2 ? x2[i] : (T)0;
-                        gpx[slot] = pxv; gpy[slot] = pyv; gpz[slot] = pzv;
+                        gpx[slot] = gxv; gpy[slot] = gyv; gpz[slot] = gzv;
                         gw[slot] = wrel;
                         gid[slot] = (next_id + rank) | (1ull << 63);
                         gcell[slot] = c;
@@ -1208,7 +1250,7 @@ k_sup_expand(int64_t ncell, const uint32_t* __restrict__ counts, const uint32_t*
                     rec[slot] = (uint64_t)(c0 + q) | ((uint64_t)j << 32) | ((uint64_t)ch << 62);
 }
 
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
              const float* __restrict__ p32, const double* __restrict__ p64,
@@ -1272,15 +1314,15 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
         const double wp = kp.w_a * kp.wa_mul[ch] * ws;
         const double Tc = state[c * AXPIC_STATE_N + 0];
         const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
-        const double xs = ch == 1 ? 1.0 : kp.brems_theta;
         r = draw(kp, (uint64_t)c, step, 6 + ch, j);
-        const double E = Tc * xs * quantile(tab, u24(r.x));
+        double E, pm;
+        thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
+        const double eu = M ? E / kMe : pm;                // energy in m_e c^2
         const double mu = 2.0 * u24(r.y) - 1.0;
         const double phi = 2.0 * kPi * u24(r.z);
         const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
         double sphi, cphi;
         sincos(phi, &sphi, &cphi);
-        const double pm = E / kMe;
         const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
         ax0[slot] = x0[pick];
         if (ax1) ax1[slot] = x1 ? x1[pick] : (T)0;
@@ -1292,7 +1334,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
         atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
         if (fb) {
             double* f = fb + c * 4;
-            atomicAdd(&f[0], -wp * pm);
+            atomicAdd(&f[0], -wp * eu);
             atomicAdd(&f[1], -wp * pa[0]);
             atomicAdd(&f[2], -wp * pa[1]);
             atomicAdd(&f[3], -wp * pa[2]);
@@ -1359,7 +1401,7 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
 // ------------------------------------------------------------------ diagnostics
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_diag_partial(int64_t n, double w_ref, const T* __restrict__ w, const T* __restrict__ px,
+k_diag_partial(int64_t n, double w_ref, double mu2, const T* __restrict__ w, const T* __restrict__ px,
                const T* __restrict__ py, const T* __restrict__ pz, double* __restrict__ part) {
     __shared__ double lds[2 * (kThreads / 64)];
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -1371,7 +1413,7 @@ k_diag_partial(int64_t n, double w_ref, const T* __restrict__ w, const T* __rest
         if (wi > 0.0) {
             const double a = px[i], b = py[i], c = pz[i];
             N += wi;
-            U += wi * kMe * sqrt(a * a + b * b + c * c);
+            U += wi * kMe * sqrt(a * a + b * b + c * c + mu2);
         }
     }
     N = wave_sum(N); U = wave_sum(U);
@@ -1455,7 +1497,10 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
                             axpic_species* ax, double* hist, double* stats, int64_t* status,
                             const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = ph->n, nb = nblocks_for(std::max<int64_t>(n, 1));
-    LAUNCH("k_prim_count", k_prim_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
+    // massive axions take their own instantiations, so the massless kernels are unchanged
+    const auto k_count = kp.massive ? k_prim_count<T, true> : k_prim_count<T, false>;
+    const auto k_events = kp.massive ? k_prim_events<T, true> : k_prim_events<T, false>;
+    LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
                        W.code, W.bsum, W.bact, W.acc, acc_used(kp));
@@ -1463,7 +1508,7 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
-    LAUNCH("k_prim_events", k_prim_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+    LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
            next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
            TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
            TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.ctrl, ax->n, TP<T>(ax->x[0]),
@@ -1486,7 +1531,8 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
            W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
-    LAUNCH("k_therm_events", k_therm_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+    const auto k_events = kp.massive ? k_therm_events<T, true> : k_therm_events<T, false>;
+    LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), idv(el), el->cell, TCP<T>(lam_in),
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
@@ -1510,7 +1556,8 @@ axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axp
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_sup_expand", k_sup_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, counts,
            W.bact, W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
-    LAUNCH("k_sup_events", k_sup_events<T>, dim3(kEventBlocks), dim3(kThreads), 0, s, ncell, step,
+    const auto k_events = kp.massive ? k_sup_events<T, true> : k_sup_events<T, false>;
+    LAUNCH("k_sup_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, ncell, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, off, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
            TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),
@@ -1525,14 +1572,16 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                          axpic_species* ph, double* fb, double* stats, int64_t* status,
                          const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = ax->n, nb = nblocks_for(std::max<int64_t>(n, 1));
-    LAUNCH("k_abs_count", k_abs_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
+    const auto k_count = kp.massive ? k_abs_count<T, true> : k_abs_count<T, false>;
+    const auto k_apply = kp.massive ? k_abs_apply<T, true> : k_abs_apply<T, false>;
+    LAUNCH("k_abs_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
                        TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
                        TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
            out_cap, W.ctrl, status, next_id, chain, ph ? (int)AXPIC_CHAIN_PHOTONS : -1);
-    LAUNCH("k_abs_apply", k_abs_apply<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
+    LAUNCH("k_abs_apply", k_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
                        kp, ax->w_ref, cells->pref32, cells->pref64, TP<T>(ax->w), TCP<T>(ax->x[0]),
                        TCP<T>(ax->x[1]), TCP<T>(ax->x[2]), TCP<T>(ax->p[0]), TCP<T>(ax->p[1]),
                        TCP<T>(ax->p[2]), ax->cell, TCP<T>(pabs_in), TCP<T>(lam_in), W.code, W.bact,
@@ -1576,14 +1625,17 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
 extern "C" {
 
-axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, void* stream) {
-    if (!grid_ok(g) || !species_ok(sp, push != 0)) return AXPIC_E_INVAL;
+axpic_status axpic_bin_cells(const axpic_grid* g, axpic_species* sp, int32_t push, double m_keV,
+                             void* stream) {
+    if (!grid_ok(g) || !species_ok(sp, push != 0) || !(m_keV >= 0.0 && m_keV < 1e6))
+        return AXPIC_E_INVAL;
     if (sp->n == 0) return AXPIC_OK;
     for (int d = 0; d < g->ndim; ++d)
         if (!sp->x[d]) return AXPIC_E_INVAL;
     if (push && (!sp->p[0] || !sp->p[1] || !sp->p[2])) return AXPIC_E_INVAL;
     axpic_params dummy;
     std::memset(&dummy, 0, sizeof(dummy));
+    dummy.m_a_keV = m_keV;
     KParams kp = make_kparams(g, &dummy, 1.0);
     if (sp->dtype == AXPIC_F32)
         LAUNCH("k_bin", k_bin<float>, grid1(sp->n), dim3(kThreads), 0, S(stream), sp->n, kp,
@@ -1855,20 +1907,21 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     return launched();
 }
 
-axpic_status axpic_diag(const axpic_species* sp, double* out, void* ws, size_t ws_bytes,
-                        void* stream) {
-    if (!species_ok(sp, true) || !out) return AXPIC_E_INVAL;
+axpic_status axpic_diag(const axpic_species* sp, double m_keV, double* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!species_ok(sp, true) || !out || !(m_keV >= 0.0)) return AXPIC_E_INVAL;
+    const double mu2 = (m_keV / kMe) * (m_keV / kMe);
     const int64_t nb = nblocks_for(std::max<int64_t>(sp->n, 1));
     if (!ws || ws_bytes < sizeof(double) * 2 * (size_t)nb) return AXPIC_E_INVAL;
     double* part = (double*)ws;
     hipStream_t s = S(stream);
     if (sp->dtype == AXPIC_F32)
         LAUNCH("k_diag_partial", k_diag_partial<float>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
-                           sp->w_ref, (const float*)sp->w, (const float*)sp->p[0],
+                           sp->w_ref, mu2, (const float*)sp->w, (const float*)sp->p[0],
                            (const float*)sp->p[1], (const float*)sp->p[2], part);
     else
         LAUNCH("k_diag_partial", k_diag_partial<double>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
-                           sp->w_ref, (const double*)sp->w, (const double*)sp->p[0],
+                           sp->w_ref, mu2, (const double*)sp->w, (const double*)sp->p[0],
                            (const double*)sp->p[1], (const double*)sp->p[2], part);
     LAUNCH("k_diag_final", k_diag_final, dim3(1), dim3(64), 0, s, nb, part, out);
     return launched();

@@ -24,8 +24,8 @@ constexpr double kZeta6 = 1.0173430619844491397;
 constexpr double kLambdaHardCap = 64.0;       // bound of the inversion sampler
 constexpr int kKmax = 255;
 
-constexpr int kTabN = 2048;                   // quantile-table intervals
-constexpr double kTabZ0 = -18.0, kTabZ1 = 18.0;
+constexpr int kTabN = 3072;                   // quantile-table intervals (h = 9/512)
+constexpr double kTabZ0 = -18.0, kTabZ1 = 36.0;   // z = ln(u/(1-u)); the upper half serves cut spectra
 
 // Kernel-side parameter block (derived on the host from axpic_params).
 struct KParams {
@@ -46,6 +46,9 @@ struct KParams {
     int32_t nbins, hist_log;
     int32_t ndim;
     int32_t n[3];
+    double m_a;                 // axion mass [keV] (0: massless)
+    double mu2;                 // (m_a / m_e c^2)^2
+    int32_t massive;
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -204,8 +207,7 @@ template <> __device__ __forceinline__ double dev_floor(double x) { return floor
 // Quantile tables: y = ln x on a uniform grid of z = ln(u/(1-u)) with slopes
 // dy/dz, evaluated by cubic Hermite interpolation (FP64).  tab[0..N] = y,
 // tab[N+1..2N+1] = dy/dz.
-__device__ __forceinline__ double quantile(const double* __restrict__ tab, double u) {
-    const double z = log(u) - log1p(-u);
+__device__ __forceinline__ double quantile_z(const double* __restrict__ tab, double z) {
     const double h = (kTabZ1 - kTabZ0) / kTabN;
     double t = (z - kTabZ0) / h;
     int j = (int)floor(t);
@@ -217,6 +219,9 @@ __device__ __forceinline__ double quantile(const double* __restrict__ tab, doubl
     const double y = (2 * f3 - 3 * f2 + 1) * y0 + (f3 - 2 * f2 + f) * m0 +
                      (-2 * f3 + 3 * f2) * y1 + (f3 - f2) * m1;
     return exp(y);
+}
+__device__ __forceinline__ double quantile(const double* __restrict__ tab, double u) {
+    return quantile_z(tab, log(u) - log1p(-u));
 }
 
 // ---------------------------------------------------------------- reductions
@@ -354,26 +359,32 @@ __device__ __forceinline__ float pabs_thermal<float>(const KParams& kp, const fl
     return f_1mexp(g);
 }
 
-template <>
-__device__ __forceinline__ double pabs_thermal<double>(const KParams& kp, const double* __restrict__ pc,
-                                                       double E) {
-    const double Tk = pc[0];
+// Gamma_abs dt of the thermal channels at energy E from the cell's temperature Tk
+// and absorption coefficients c6 (Compton-like) and c7 (brems), FP64.
+__device__ __forceinline__ double gabs_dt(const KParams& kp, double Tk, double c6, double c7,
+                                          double E) {
     const double x = E / Tk;
     double g = 0.0;
-    if (pc[6] != 0.0) {
+    if (c6 != 0.0) {
         double occ = kp.eq_stats ? -expm1(-x) : 1.0;
-        g += pc[6] * E * E / occ;
+        g += c6 * E * E / occ;
     }
-    if (pc[7] != 0.0) {
+    if (c7 != 0.0) {
         const double th = kp.brems_theta, k = kp.brems_k;
         const double pw = exp((k - 3.0) * log(x));
         // MB: e^{x(1-1/theta)}; BE: e^{-x/theta} (e^x - 1), with expm1 for small x
         double shape;
         if (kp.eq_stats || x > 60.0) shape = exp(x * (1.0 - 1.0 / th));
         else shape = exp(-x / th) * expm1(x);
-        g += pc[7] * pw * shape;
+        g += c7 * pw * shape;
     }
-    return -expm1(-g);
+    return g;
+}
+
+template <>
+__device__ __forceinline__ double pabs_thermal<double>(const KParams& kp, const double* __restrict__ pc,
+                                                       double E) {
+    return -expm1(-gabs_dt(kp, pc[0], pc[6], pc[7], E));
 }
 
 // a->gamma mean: w_a-weight * (w_a/w_gamma_prod) * (1 - exp(-ratio c_P F))
@@ -384,6 +395,158 @@ __device__ __forceinline__ T lambda_ag(const KParams& kp, const T* __restrict__ 
     const T x = (T)kp.inv_ratio * pc[2] * F;
     const T unit = (T)((double)pc[3] * kp.ag_unit);
     return w * unit * F * one_minus_exp_over(x);
+}
+
+// ---------------------------------------------------------------- finite mass
+// Axions of mass m = kp.m_a [keV] (kp.mu2 = (m / m_e c^2)^2): energy
+// E = m_e c^2 sqrt(p^2 + mu^2), push velocity p / sqrt(p^2 + mu^2) (Sec. II.B).
+// A photon of momentum k > m converts to an axion of momentum p = sqrt(k^2 - m^2)
+// at Gamma = G_P0 (p/k) F_m(k, p), F_m being twice the angular integral of the
+// screened amplitude |k x p|^2 / (q^2 (q^2 + kappa^2)), q = k - p.  In closed form,
+// with a = 4kp and A = (k-p)^2 + kappa^2,
+//   F_m = (A + a) A ln(1 + a/A) / (a kappa^2)
+//         - (k-p)^2 ((k-p)^2 + a) ln(1 + a/(k-p)^2) / (a kappa^2) - 1,
+// which is F(4k^2/kappa^2) at p = k.
+__device__ __forceinline__ double F_mass(double k, double p, double kappa2) {
+    if (!(k > 0.0) || !(p > 0.0)) return 0.0;
+    if (p >= k) return screenF(4.0 * k * k / kappa2);
+    const double a = 4.0 * k * p, am = (k - p) * (k - p), A = am + kappa2;
+    const double t1 = (A + a) * A / (a * kappa2) * log1p(a / A);
+    const double t2 = am * (am + a) / (a * kappa2) * log1p(a / am);
+    return t1 - t2 - 1.0;
+}
+
+// |p|^2 in FP64 from the stored components (the massive rates resolve the
+// threshold region, where binary32 |p|^2 would not do)
+template <typename T>
+__device__ __forceinline__ double psq_d(const T* __restrict__ px, const T* __restrict__ py,
+                                        const T* __restrict__ pz, int64_t i) {
+    const double a = px[i], b = py[i], c = pz[i];
+    return a * a + b * b + c * c;
+}
+
+__device__ __forceinline__ double axion_energy(const KParams& kp, double p2) {
+    return kMe * sqrt(p2 + kp.mu2);
+}
+
+// lambda_P of a photon whose products have mass m (FP64 from the cell's prefactors:
+// kappa^2 = 4 m_e^2 / pc[1], c_P = pc[2] = Gamma_P0 dt, pc[3] the lambda unit); zero
+// at or below the threshold omega = m.
+template <typename T>
+__device__ __forceinline__ T lambda_primakoff_m(const KParams& kp, const T* __restrict__ pc, T w,
+                                                double p2) {
+    const double k = kMe * sqrt(p2);
+    if (!(k > kp.m_a)) return (T)0;
+    const double p = sqrt((k - kp.m_a) * (k + kp.m_a));
+    const double F = p / k * F_mass(k, p, 4.0 * kMe * kMe / (double)pc[1]);
+    const double x = (double)pc[2] * F;
+    const double om = x > 1e-12 ? -expm1(-x) / x : 1.0 - 0.5 * x;
+    return (T)((double)w * (double)pc[3] * F * om);
+}
+
+// a->gamma mean of an axion of mass m: the photon takes its energy E; Gamma_{a->gamma}
+// = ratio (k/p) Gamma_{gamma->a}(E) = ratio Gamma_P0 F_m(E, p).
+template <typename T>
+__device__ __forceinline__ T lambda_ag_m(const KParams& kp, const T* __restrict__ pc, T w, double p2) {
+    const double p = kMe * sqrt(p2);
+    if (!(p > 0.0)) return (T)0;
+    const double E = axion_energy(kp, p2);
+    const double F = F_mass(E, p, 4.0 * kMe * kMe / (double)pc[1]);
+    const double x = kp.inv_ratio * (double)pc[2] * F;
+    const double om = x > 1e-12 ? -expm1(-x) / x : 1.0 - 0.5 * x;
+    return (T)((double)w * (double)pc[3] * kp.ag_unit * F * om);
+}
+
+// Thermal absorption probability of an axion of mass m: the massive equilibrium
+// density (E p instead of E^2) multiplies Gamma_abs by E/p.
+template <typename T>
+__device__ __forceinline__ T pabs_thermal_m(const KParams& kp, const T* __restrict__ pc, double p2) {
+    const double p = kMe * sqrt(p2);
+    if (!(p > 0.0)) return (T)0;
+    const double E = axion_energy(kp, p2);
+    const double g = gabs_dt(kp, (double)pc[0], (double)pc[6], (double)pc[7], E) * (E / p);
+    return (T)(-expm1(-g));
+}
+
+// Fractions of the thermal samplers' number spectra above x (FP64).
+// Compton-like x^4/(e^x - 1)/(24 zeta5): below x = 1/4 one minus the series
+// sum_n B_n x^{n+4}/(n! (n+4)) (B_n the Bernoulli numbers), above it the sum
+// over j of e^{-jx} (x^4/j + 4x^3/j^2 + 12x^2/j^3 + 24x/j^4 + 24/j^5), both
+// divided by 24 zeta(5).
+__device__ __forceinline__ double compton_tail(double x) {
+    constexpr double kNorm = 24.0 * 1.0369277551433699263;
+    if (!(x > 0.0)) return 1.0;
+    if (x < 0.25) {
+        const double B[11] = {1.0, -0.5, 1.0 / 6.0, 0.0, -1.0 / 30.0, 0.0, 1.0 / 42.0, 0.0,
+                              -1.0 / 30.0, 0.0, 5.0 / 66.0};
+        double s = 0.0, xp = x * x * x * x, fact = 1.0;
+        for (int n = 0; n <= 10; ++n) {
+            if (n > 0) fact *= n;
+            s += B[n] * xp / (fact * (n + 4));
+            xp *= x;
+        }
+        return 1.0 - s / kNorm;
+    }
+    double s = 0.0;
+    for (int j = 1; j < 4000; ++j) {
+        const double dj = (double)j, e = exp(-dj * x);
+        const double t = e * ((((x / dj + 4.0 / (dj * dj)) * x + 12.0 / (dj * dj * dj)) * x +
+                               24.0 / (dj * dj * dj * dj)) * x + 24.0 / (dj * dj * dj * dj * dj));
+        s += t;
+        if (t < 1e-17 * s) break;
+    }
+    return s / kNorm;
+}
+
+// Upper regularised incomplete gamma Q(k, y) of the Gamma(k, 1) sampler: one minus
+// the power series of P below y = k + 1, the Legendre continued fraction (modified
+// Lentz) above.
+__device__ __forceinline__ double gamma_tail(double k, double y) {
+    if (!(y > 0.0)) return 1.0;
+    const double pre = exp(-y + k * log(y) - lgamma(k));
+    if (y < k + 1.0) {
+        double term = 1.0 / k, sum = term;
+        for (int n = 1; n < 2000; ++n) {
+            term *= y / (k + n);
+            sum += term;
+            if (term < sum * 1e-17) break;
+        }
+        return 1.0 - sum * pre;
+    }
+    const double tiny = 1e-300;
+    double b = y + 1.0 - k, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 2000; ++i) {
+        const double an = -(double)i * ((double)i - k);
+        b += 2.0;
+        d = an * d + b; if (fabs(d) < tiny) d = tiny;
+        c = b + an / c; if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return pre * h;
+}
+
+// Energy E [keV] and momentum magnitude pm [m_e c] of a thermal product of channel
+// ch (1 Compton-like, 2 brems) in a cell at temperature Tc, drawn at uniform u by
+// the quantile table; with mass m the spectrum is cut at E = m: the quantile is
+// taken at F + u Q, Q = 1 - F the fraction above m, in z = ln(F + u Q) - ln((1 - u) Q).
+template <bool M>
+__device__ __forceinline__ void thermal_energy(const KParams& kp, int ch, double Tc, double u,
+                                               const double* __restrict__ tab, double* E,
+                                               double* pm) {
+    const double xs = ch == 1 ? 1.0 : kp.brems_theta;
+    if (!M) {
+        *E = Tc * xs * quantile(tab, u);
+        *pm = *E / kMe;
+        return;
+    }
+    const double xm = kp.m_a / (xs * Tc);
+    const double Q = ch == 1 ? compton_tail(xm) : gamma_tail(kp.brems_k, xm);
+    const double z = log((1.0 - Q) + u * Q) - log((1.0 - u) * Q);
+    *E = Tc * xs * quantile_z(tab, z);
+    *pm = *E > kp.m_a ? sqrt((*E - kp.m_a) * (*E + kp.m_a)) / kMe : 0.0;
 }
 
 }  // namespace axpic

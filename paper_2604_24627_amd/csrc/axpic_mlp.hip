@@ -195,7 +195,8 @@ k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __rest
 
 // ------------------------------------------------------------------ inference
 constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
-constexpr int kNT = 2;                      // 16-particle column tiles per network pass
+constexpr int kNTParticles = 2;            // 16-wide column tiles per pass, per-particle kernel
+constexpr int kNTTable = 4;                // the same for the per-cell table kernel
 
 struct MlpConst {
     float feat_lo[4], feat_sc[4];
@@ -204,96 +205,135 @@ struct MlpConst {
     double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;
 };
 
-// One network pass over 32 particles of a wavefront: lanes base .. base+31
-// supply the features f[0..7] of their particle; those lanes receive y (the
-// other lanes' return value is unspecified).
+// Activated output tile mt (rows 16 mt + 4 g + r of this lane) into the next
+// layer's B operand: slot r (mt even) or 4 + r (mt odd) of K-chunk mt/2.
+template <int NT>
+__device__ __forceinline__ void act_tile(const floatx4 (&a)[NT], int mt, bf16x8 (&Bout)[NT][4]) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Bout[nt][mt >> 1][(mt & 1) * 4 + r] = (__bf16)act(a[nt][r]);
+    }
+}
+
+// Pre-activations of output tile mt of a hidden 128 -> 128 layer; the
+// accumulators start at the bias (as the first product's C operand).
+template <int NT>
+__device__ __forceinline__ void hh_tile(const bf16x8* __restrict__ frag, int fbase, int mt, int l,
+                                        const floatx4 bv, const bf16x8 (&Bin)[NT][4],
+                                        floatx4 (&a)[NT]) {
+    const bf16x8 a0 = frag[(fbase + mt * 4) * 64 + l];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) a[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, Bin[nt][0], bv, 0, 0, 0);
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        const bf16x8 ac = frag[(fbase + mt * 4 + c) * 64 + l];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) a[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac, Bin[nt][c], a[nt], 0, 0, 0);
+    }
+}
+
+// One hidden layer, software-pipelined over the 8 output tiles: the products of
+// tile mt are issued before the activation of tile mt - 1, so a wavefront's
+// vector work overlaps its own matrix-core chain.
+template <int NT>
+__device__ __forceinline__ void hidden_layer(const bf16x8* __restrict__ frag, int fbase,
+                                             const floatx4* __restrict__ b4, int l, int g,
+                                             const bf16x8 (&Bin)[NT][4], bf16x8 (&Bout)[NT][4]) {
+    floatx4 a0[NT], a1[NT];
+    hh_tile(frag, fbase, 0, l, b4[g], Bin, a0);
+#pragma unroll
+    for (int mt = 1; mt < 8; ++mt) {
+        if (mt & 1) {
+            hh_tile(frag, fbase, mt, l, b4[4 * mt + g], Bin, a1);
+            act_tile(a0, mt - 1, Bout);
+        } else {
+            hh_tile(frag, fbase, mt, l, b4[4 * mt + g], Bin, a0);
+            act_tile(a1, mt - 1, Bout);
+        }
+    }
+    act_tile(a1, 7, Bout);
+}
+
+// One network pass over 16 NT particles of a wavefront: lanes base ..
+// base + 16 NT - 1 supply the features f[0..7] of their particle; those lanes
+// receive y (the other lanes' return value is unspecified).
+template <int NT>
 __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
                                           const float* __restrict__ bias, const float f[8],
                                           int base) {
     const int l = threadIdx.x & 63, g = l >> 4, col = l & 15;
     // layer-1 B operand: group 0 of column tile nt carries the 8 features of particle
     // base + 16 nt + col; the other groups hold the zero padding of inputs 8..31
-    bf16x8 Bop[kNT][4];
+    bf16x8 B0[NT];
 #pragma unroll
-    for (int nt = 0; nt < kNT; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float v = __shfl(f[j], base + nt * 16 + col, 64);
-            Bop[nt][0][j] = (__bf16)(g == 0 ? v : 0.0f);
+            B0[nt][j] = (__bf16)(g == 0 ? v : 0.0f);
         }
     }
-    floatx4 acc[8][kNT];
-#pragma unroll 1
-    for (int layer = 1; layer <= 4; ++layer) {
-        // accumulators start at the bias of their rows 16 mt + 4 g + r
-        const floatx4* b4 = (const floatx4*)(bias + (layer - 1) * kDH);
+    bf16x8 Ba[NT][4], Bb[NT][4];
+    // layer 1 (one K-chunk), pipelined like the hidden layers
+    {
+        const floatx4* b4 = (const floatx4*)bias;
+        floatx4 a0[NT], a1[NT];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
+            const bf16x8 a = frag[(kFragL1 + mt) * 64 + l];
             const floatx4 bv = b4[4 * mt + g];
+            if (mt & 1) {
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = bv;
-        }
-        if (layer == 1) {
+                for (int nt = 0; nt < NT; ++nt) a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B0[nt], bv, 0, 0, 0);
+                act_tile(a0, mt - 1, Ba);
+            } else {
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                const bf16x8 a = frag[(kFragL1 + mt) * 64 + l];
-#pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][0], acc[mt][nt], 0, 0, 0);
-            }
-        } else {
-            const int fbase = kFragL2 + (layer - 2) * 32;
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const bf16x8 a = frag[(fbase + mt * 4 + c) * 64 + l];
-#pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], acc[mt][nt], 0, 0, 0);
-                }
+                for (int nt = 0; nt < NT; ++nt) a0[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B0[nt], bv, 0, 0, 0);
+                if (mt > 0) act_tile(a1, mt - 1, Ba);
             }
         }
-        // activation; rows 16 mt + 4 g + r of this lane become slot r (mt even) or
-        // 4 + r (mt odd) of K-chunk mt/2 of the next layer's B operand
+        act_tile(a1, 7, Ba);
+    }
+#pragma unroll 1
+    for (int h = 0; h < 3; ++h) {
+        hidden_layer(frag, kFragL2 + 32 * h, (const floatx4*)(bias + (h + 1) * kDH), l, g, Ba, Bb);
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
+        for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
-                    Bop[nt][mt >> 1][(mt & 1) * 4 + r] = (__bf16)act(acc[mt][nt][r]);
-            }
+            for (int c = 0; c < 4; ++c) Ba[nt][c] = Bb[nt][c];
         }
     }
     // output layer: one 16-row tile, row 0 is the output
-    floatx4 o[kNT];
+    floatx4 o[NT];
 #pragma unroll
-    for (int nt = 0; nt < kNT; ++nt) o[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int nt = 0; nt < NT; ++nt) o[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const bf16x8 a = frag[(kFragL5 + c) * 64 + l];
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt)
-            o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[nt][c], o[nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt)
+            o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Ba[nt][c], o[nt], 0, 0, 0);
     }
     // lane col of group 0 holds y of particle base + 16 nt + col in o[nt][0]
     const int rel = l - base;
     float y = 0.0f;
 #pragma unroll
-    for (int nt = 0; nt < kNT; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
         const float v = __shfl(o[nt][0], col, 64);
         if (rel >= 0 && (rel >> 4) == nt) y = v;
     }
     return y + bias[4 * kDH];
 }
 
-// y for all 64 particles of a wavefront (two 32-particle passes; a single pass of
-// four tiles needs the accumulators of one wave per SIMD, which measured slower).
+// y for all 64 particles of a wavefront (64 / (16 NT) passes of NT column tiles).
+template <int NT>
 __device__ __forceinline__ float mlp_wave(const bf16x8* __restrict__ frag, const float* __restrict__ bias,
                                           const float f[8]) {
-    const float y0 = mlp_pass(frag, bias, f, 0);
-    const float y1 = mlp_pass(frag, bias, f, 32);
+    static_assert(NT == 2 || NT == 4, "passes of 32 or 64 particles");
+    if (NT == 4) return mlp_pass<NT>(frag, bias, f, 0);
+    const float y0 = mlp_pass<NT>(frag, bias, f, 0);
+    const float y1 = mlp_pass<NT>(frag, bias, f, 32);
     return (threadIdx.x & 63) < 32 ? y0 : y1;
 }
 
@@ -363,7 +403,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
         double res;
         if (mode == 0 || mode == 2) {
             f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
-            const float y = mlp_wave(frag, bias, f);
+            const float y = mlp_wave<kNTParticles>(frag, bias, f);
             const double GdtP = g2P * boost * exp((double)log_rate(mc, 0, f, y)) * kp.dt_phys;
             if (mode == 0) {
                 res = in_dom ? (double)wt * lam_unit_P * (-expm1(-GdtP))
@@ -380,7 +420,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
                 f[7] = ch == 3 ? 1.0f : 0.0f;
                 const bool on = (ch == 1) ? (kp.channels & AXPIC_COMPTON) != 0
                                           : ((kp.channels & AXPIC_BREMS) != 0 && (ch == 2 || ee_on));
-                const float y = mlp_wave(frag, bias, f);
+                const float y = mlp_wave<kNTParticles>(frag, bias, f);
                 // the brems targets exclude the cell's screening-fit factor; put it back
                 const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
                 if (on) G += supp * exp((double)log_rate(mc, ch, f, y));
@@ -445,7 +485,7 @@ k_mlp_table(int64_t ncell, int nodes, int slot0, int slot1, int c_on, int bz_on,
         float* out = table + c * 2 * nodes + j;
         if (slot0) {
             f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
-            const float y = mlp_wave(frag, bias, f);
+            const float y = mlp_wave<kNTTable>(frag, bias, f);
             if (live) out[0] = in_box ? log_rate(mc, 0, f, y) : NAN;
         }
         if (slot1) {
@@ -456,7 +496,7 @@ k_mlp_table(int64_t ncell, int nodes, int slot0, int slot1, int c_on, int bz_on,
                 if (!on) continue;                           // uniform over the grid
                 f[4] = 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f; f[6] = ch == 2 ? 1.0f : 0.0f;
                 f[7] = ch == 3 ? 1.0f : 0.0f;
-                const float y = mlp_wave(frag, bias, f);
+                const float y = mlp_wave<kNTTable>(frag, bias, f);
                 const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
                 G += supp * exp((double)log_rate(mc, ch, f, y));
             }
@@ -731,6 +771,7 @@ static int compute_units() {
 axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                              const axpic_species* sp, int32_t channel, const axpic_mlp* net,
                              void* out, unsigned long long* n_fallback, void* stream) {
+    if (prm && prm->m_a_keV != 0.0) return AXPIC_E_UNSUPPORTED;   // the surrogate is massless
     if (!g || !cells || !prm || !sp || !net || !net->blob || (!out && sp->n)) return AXPIC_E_INVAL;
     if (sp->n < 0 || (sp->n && (!sp->w || !sp->cell || !sp->p[0] || !sp->p[1] || !sp->p[2])))
         return AXPIC_E_INVAL;
@@ -771,6 +812,7 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
 axpic_status axpic_mlp_table(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                              int32_t channel, const axpic_mlp* net, int32_t nodes, double x_lo,
                              double x_hi, float* table, void* stream) {
+    if (prm && prm->m_a_keV != 0.0) return AXPIC_E_UNSUPPORTED;   // the surrogate is massless
     if (!g || !cells || !prm || !net || !net->blob || !table) return AXPIC_E_INVAL;
     if (nodes < 4 || nodes > AXPIC_TAB_MAX_NODES || !(x_lo > 0.0) || !(x_hi > x_lo) ||
         !(x_lo >= net->x_lo) || !(x_hi <= net->x_hi))
@@ -798,6 +840,7 @@ axpic_status axpic_rates_table(const axpic_grid* g, const axpic_cells* cells, co
                                const axpic_species* sp, int32_t channel, int32_t nodes, double x_lo,
                                double x_hi, const float* table, void* out,
                                unsigned long long* n_fallback, void* stream) {
+    if (prm && prm->m_a_keV != 0.0) return AXPIC_E_UNSUPPORTED;   // the surrogate is massless
     if (!g || !cells || !prm || !sp || !table || (!out && sp->n)) return AXPIC_E_INVAL;
     if (nodes < 4 || nodes > AXPIC_TAB_MAX_NODES || !(x_lo > 0.0) || !(x_hi > x_lo))
         return AXPIC_E_INVAL;

@@ -48,8 +48,43 @@ static double cdf_small_gamma(double x, double k) {
     return std::exp(k * std::log(x) - x) * s;
 }
 
-template <class CDF, class XF>
-static void build(double* tab, CDF cdf_small, XF xf) {
+// Upper tails: Compton: (1/(24 zeta5)) sum_j e^{-jx} (x^4/j + 4x^3/j^2 + 12x^2/j^3
+// + 24x/j^4 + 24/j^5); Gamma: the Legendre continued fraction of Q(k, x).
+static double tail_compton(double x) {
+    double s = 0.0;
+    for (int j = 1; j < 400; ++j) {
+        const double dj = j, e = std::exp(-dj * x);
+        const double t = e * ((((x / dj + 4.0 / (dj * dj)) * x + 12.0 / (dj * dj * dj)) * x +
+                               24.0 / (dj * dj * dj * dj)) * x + 24.0 / std::pow(dj, 5));
+        s += t;
+        if (t < 1e-18 * s) break;
+    }
+    return s / (24.0 * kZeta5);
+}
+static double tail_gamma(double x, double k) {
+    const double tiny = 1e-300;
+    double b = x + 1.0 - k, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 10000; ++i) {
+        const double an = -(double)i * ((double)i - k);
+        b += 2.0;
+        d = an * d + b; if (std::fabs(d) < tiny) d = tiny;
+        c = b + an / c; if (std::fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (std::fabs(del - 1.0) < 1e-17) break;
+    }
+    return std::exp(-x + k * std::log(x) - std::lgamma(k)) * h;
+}
+
+// The quantile ODE is integrated upwards from z0 up to z = 18, where it is stable
+// (a too large x makes the slope smaller), and downwards from z1 to z = 18 from a
+// Newton solution of the tail, the stable direction there; the lower part is the
+// table of the plain (uncut) samplers, the upper part serves the cut spectra.
+constexpr double kTabZMid = 18.0;
+
+template <class CDF, class XF, class TAIL>
+static void build(double* tab, CDF cdf_small, XF xf, TAIL tail) {
     const int N = kTabN;
     const double h = (kTabZ1 - kTabZ0) / N;
     const double u0 = 1.0 / (1.0 + std::exp(-kTabZ0));
@@ -70,11 +105,12 @@ static void build(double* tab, CDF cdf_small, XF xf) {
     double y = std::log(x);
     const int sub = 32;
     const double hs = h / sub;
-    for (int j = 0; j <= N; ++j) {
+    const int jmid = (int)std::lround((kTabZMid - kTabZ0) / h);
+    for (int j = 0; j <= jmid; ++j) {
         double z = kTabZ0 + j * h;
         tab[j] = y;
         tab[N + 1 + j] = rhs(z, y);
-        if (j == N) break;
+        if (j == jmid) break;
         for (int s = 0; s < sub; ++s) {
             double zz = z + s * hs;
             double k1 = rhs(zz, y);
@@ -84,16 +120,43 @@ static void build(double* tab, CDF cdf_small, XF xf) {
             y += hs / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4);
         }
     }
+    if (jmid >= N) return;
+    // tail start: ln Q(x) = ln q1, q1 = 1/(1 + e^{z1}), by Newton (d ln Q/dx = -f/Q)
+    const double lq = -kTabZ1 - std::log1p(std::exp(-kTabZ1));
+    x = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        const double Q = tail(x);
+        const double g = std::log(Q) - lq;
+        const double dg = -(xf(x) / x) / Q;
+        double xn = x - g / dg;
+        if (!(xn > 0.5 * x)) xn = 0.5 * x;
+        if (std::fabs(xn - x) < 1e-15 * x) { x = xn; break; }
+        x = xn;
+    }
+    y = std::log(x);
+    for (int j = N; j > jmid; --j) {
+        double z = kTabZ0 + j * h;
+        tab[j] = y;
+        tab[N + 1 + j] = rhs(z, y);
+        for (int s = 0; s < sub; ++s) {
+            double zz = z - s * hs;
+            double k1 = rhs(zz, y);
+            double k2 = rhs(zz - 0.5 * hs, y - 0.5 * hs * k1);
+            double k3 = rhs(zz - 0.5 * hs, y - 0.5 * hs * k2);
+            double k4 = rhs(zz - hs, y - hs * k3);
+            y -= hs / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4);
+        }
+    }
 }
 
 void build_compton_table(double* tab) {
     build(tab, [](double x) { return cdf_small_compton(x); },
-          [](double x) { return xf_compton(x); });
+          [](double x) { return xf_compton(x); }, [](double x) { return tail_compton(x); });
 }
 
 void build_gamma_table(double* tab, double k) {
     build(tab, [k](double x) { return cdf_small_gamma(x, k); },
-          [k](double x) { return xf_gamma(x, k); });
+          [k](double x) { return xf_gamma(x, k); }, [k](double x) { return tail_gamma(x, k); });
 }
 
 }  // namespace axpic_host

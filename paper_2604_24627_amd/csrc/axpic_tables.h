@@ -2,8 +2,8 @@
 #pragma once
 
 namespace axpic_host {
-constexpr int kTabN = 2048;
-constexpr double kTabZ0 = -18.0, kTabZ1 = 18.0;
+constexpr int kTabN = 3072;
+constexpr double kTabZ0 = -18.0, kTabZ1 = 36.0;
 // tab has 2 (kTabN + 1) doubles: y = ln x at the nodes, then dy/dz.
 void build_compton_table(double* tab);
 void build_gamma_table(double* tab, double k);

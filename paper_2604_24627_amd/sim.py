@@ -340,7 +340,8 @@ class AxpicSim:
     def bin_axions(self, push: bool = True):
         if self.ax.n:
             B.check(self.lib.axpic_bin_cells(B.ref(self.grid), B.ref(self.ax.struct()),
-                                             1 if push else 0, self.sh), "bin_cells")
+                                             1 if push else 0, float(self.pdict["m_a_keV"]),
+                                             self.sh), "bin_cells")
 
     def rates(self, sp: DeviceSpecies, channel: int):
         out = torch.zeros(max(sp.n, 1), dtype=_tdtype(sp.dtype), device=self.device)
@@ -362,7 +363,8 @@ class AxpicSim:
 
     def diag(self):
         self._ensure_ws(self.ax.n)
-        B.check(self.lib.axpic_diag(B.ref(self.ax.struct()), B.ptr(self.diag_out), B.ptr(self.ws),
+        B.check(self.lib.axpic_diag(B.ref(self.ax.struct()), float(self.pdict["m_a_keV"]),
+                                    B.ptr(self.diag_out), B.ptr(self.ws),
                                     self.ws_bytes, self.sh), "diag")
         v = self.diag_out.cpu().tolist()
         return dict(N_a=v[0], U_a=v[1])

@@ -38,17 +38,18 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2
     assert B.ParamsC.seed.offset % 8 == 0
     # sizes and offsets printed by a C compiler for include/axpic.h (x86-64)
-    assert C.sizeof(B.ParamsC) == 208 and C.sizeof(B.CellsC) == 136
+    assert C.sizeof(B.ParamsC) == 216 and C.sizeof(B.CellsC) == 136
     assert C.sizeof(B.MlpC) == 184
     assert B.MlpC.out_lin.offset == 72 and B.MlpC.T_lo.offset == 136
 
 
-def _hermite(tab, u):
-    N = 2048
-    z0, z1 = -18.0, 18.0
-    h = (z1 - z0) / N
-    z = np.log(u) - np.log1p(-u)
-    t = (z - z0) / h
+N_TAB, Z0_TAB, Z1_TAB = 3072, -18.0, 36.0
+
+
+def _hermite_z(tab, z):
+    N = N_TAB
+    h = (Z1_TAB - Z0_TAB) / N
+    t = (z - Z0_TAB) / h
     j = np.clip(np.floor(t).astype(int), 0, N - 1)
     f = t - j
     y0, y1 = tab[j], tab[j + 1]
@@ -61,13 +62,19 @@ def _hermite(tab, u):
 @pytest.mark.parametrize("which,k", [(0, 0.0), (1, 1.7), (1, 2.3)])
 def test_sampler_tables_match_exact_quantiles(which, k):
     L = B.load()
-    tab = np.zeros(2 * 2049)
+    tab = np.zeros(2 * (N_TAB + 1))
     B.check(L.axpic_sampler_table(which, k, tab.ctypes.data_as(C.c_void_p)), "table")
     rng = np.random.default_rng(11)
     a = rng.integers(0, 2 ** 32, 400, dtype=np.uint64)
     u = np.array([O.u24(int(v)) for v in a] + [2 ** -24, 1 - 2 ** -24, 0.5])
-    got = _hermite(tab, u)
+    got = _hermite_z(tab, np.log(u) - np.log1p(-u))
     ref = np.array([O.compton_x(v) if which == 0 else O.gamma_x(k, v) for v in u])
+    assert np.max(np.abs(got / ref - 1)) < 2e-8
+    # the upper half of the grid (cut spectra of massive axions): by tail probability
+    z = np.linspace(18.0, 35.5, 41)
+    q = np.exp(-z) / (1.0 + np.exp(-z))
+    got = _hermite_z(tab, z)
+    ref = np.array([O.compton_x_tail(v) if which == 0 else O.gamma_x_tail(k, v) for v in q])
     assert np.max(np.abs(got / ref - 1)) < 2e-8
 
 
@@ -75,12 +82,12 @@ def test_invalid_arguments_rejected_on_host():
     L = B.load()
     g = B.make_grid(dict(ndim=4, n=(4, 1, 1), dx=0.2, dt=0.1, omega0=1e17))
     sp = B.SpeciesC()
-    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, 0.0, None) == -1
     g = B.make_grid(dict(ndim=1, n=(4, 2, 1), dx=0.2, dt=0.1, omega0=1e17))   # n[1] != 1 in 1D
-    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, 0.0, None) == -1
     g = B.make_grid(dict(ndim=1, n=(4, 1, 1), dx=0.2, dt=0.1, omega0=1e17))
     sp.n, sp.capacity = 10, 5                                                   # n > capacity
-    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, None) == -1
+    assert L.axpic_bin_cells(B.ref(g), B.ref(sp), 1, 0.0, None) == -1
     prm = B.make_params(I.Params(lambda_cap=0.0))                               # cap <= 0
     cells = B.CellsC()
     st = np.zeros(4, np.int64)

@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--no-superposed", action="store_true",
                     help="skip the leg with per-cell superposed thermal emission")
+    ap.add_argument("--no-massive", action="store_true",
+                    help="skip the leg with axions of finite mass")
+    ap.add_argument("--mass-keV", type=float, default=1.0,
+                    help="axion mass of the finite-mass leg")
     ap.add_argument("--workload", choices=["plasma2d", "graded3d"], default="plasma2d",
                     help="plasma2d: the 512x512 uniform plasma (default); graded3d: the 256^3 "
                          "graded plasma with Poisson per-cell counts (1.6e9 particles, built "
@@ -315,6 +319,42 @@ def main():
         del sim3
         torch.cuda.empty_cache()
 
+    # ---- the same workload with axions of finite mass (massive kinematics, thresholds,
+    # cut spectra, massive absorption); plain rates
+    mas = None
+    if not a.no_massive:
+        import copy
+        wlm = copy.deepcopy(wl)
+        wlm.params.m_a_keV = a.mass_keV
+        pl = I.make_plasma(wlm)
+        sim4 = AxpicSim(pl, wlm.params, axion_capacity=est_ax)
+        del pl
+        for _ in range(a.warmup):
+            sim4.step()
+        torch.cuda.synchronize()
+        upd4 = 0
+        e0.record()
+        for _ in range(a.steps):
+            upd4 += updates_per_step(sim4, sim4.ax.n)
+            sim4.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms4 = e0.elapsed_time(e1)
+        L.axpic_timing_enable(1)
+        for _ in range(3):
+            sim4.step()
+        torch.cuda.synchronize()
+        kt4 = B.timing_read()
+        L.axpic_timing_enable(0)
+        mas = {"value": upd4 / (ms4 * 1e-3), "unit": "updates/s", "ms_per_step": ms4 / a.steps,
+               "m_a_keV": a.mass_keV, "speed_vs_plain": round((upd4 / (ms4 * 1e-3)) / value, 4),
+               "axions_end": sim4.ax.n,
+               "kernel_ms_per_step": {k: round(v[1] / 3, 5) for k, v in sorted(kt4.items())}}
+        print(f"[bench] massive axions (m = {a.mass_keV} keV): {ms4 / a.steps:.3f} ms/step, "
+              f"{mas['value']:.3e} updates/s", file=sys.stderr, flush=True)
+        del sim4
+        torch.cuda.empty_cache()
+
     # ---- surrogate form: trained on the GPU outside the timed region, same workload
     sur = sur_tab = None
     if not a.no_surrogate:
@@ -416,6 +456,7 @@ def main():
         "surrogate": sur,
         "surrogate_table": sur_tab,
         "superposed_thermal": sup,
+        "massive_axions": mas,
     }
     print(json.dumps(out), flush=True)
 

@@ -11,7 +11,9 @@ read_traffic(path)       -> the per-dispatch HBM bytes recorded in a summary,
 Kernel names are reduced to the bare function name (k_...).
 
 Usage: python -m paper_2604_24627_amd.profsum <kernel_stats.csv> [<fetch.csv>
-<write.csv> <copy_bytes>] -- prints the table; the FETCH_SIZE / WRITE_SIZE
+<write.csv> <copy_bytes>] -- prints the table;
+python -m paper_2604_24627_amd.profsum --sq <counter_collection.csv> -- per-kernel
+medians over dispatches of SQ_WAVES and of the other SQ counters per wavefront; the FETCH_SIZE / WRITE_SIZE
 medians (KiB per dispatch) are scaled so that k_stream_copy of copy_bytes reads
 and writes copy_bytes, and a "traffic" line per kernel is printed with the
 source digest for read_traffic.
@@ -96,7 +98,31 @@ def counters(path, counter):
     return out
 
 
+def sq_table(path):
+    """Per kernel: median SQ_WAVES and the median per-wavefront value of every other
+    counter in the file (one dispatch = one sample)."""
+    per = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            key = (short(row["Kernel_Name"]), row["Dispatch_Id"])
+            per.setdefault(key, {})[row["Counter_Name"]] = float(row["Counter_Value"])
+    names = sorted({c for d in per.values() for c in d if c != "SQ_WAVES"})
+    rows = {}
+    for (k, _), d in per.items():
+        if "SQ_WAVES" not in d or d["SQ_WAVES"] <= 0 or not k.startswith("k_"):
+            continue
+        rows.setdefault(k, []).append([d["SQ_WAVES"]] + [d.get(c, float("nan")) / d["SQ_WAVES"]
+                                                          for c in names])
+    print(f"{'kernel':20s} {'waves':>8s} " + " ".join(f"{c[3:]:>18s}" for c in names))
+    for k in sorted(rows, key=lambda k: -statistics.median(r[0] for r in rows[k])):
+        med = [statistics.median(col) for col in zip(*rows[k])]
+        print(f"{k:20s} {med[0]:8.0f} " + " ".join(f"{v:18.1f}" for v in med[1:]))
+
+
 def main(argv):
+    if len(argv) > 2 and argv[1] == "--sq":
+        sq_table(argv[2])
+        return
     stats = kernel_stats(argv[1])
     fetch = counters(argv[2], "FETCH_SIZE") if len(argv) > 2 else {}
     write = counters(argv[3], "WRITE_SIZE") if len(argv) > 3 else {}

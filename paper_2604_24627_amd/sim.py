@@ -349,17 +349,27 @@ class AxpicSim:
                                      B.ref(sp.struct()), channel, B.ptr(out), self.sh), "rates")
         return out[: sp.n]
 
-    def compact_axions(self):
-        if self.ax.n == 0:
-            return
-        out = DeviceSpecies(B.AXION, self.dtype, self.ndim, self.ax.capacity, self.ax.w_ref,
-                            self.device)
-        self._ensure_ws(self.ax.n)
-        B.check(self.lib.axpic_compact(B.ref(self.ax.struct()), B.ref(out.struct()),
+    def _compacted(self, sp: DeviceSpecies) -> DeviceSpecies:
+        """A copy of `sp` without its particles of zero weight, in the same order."""
+        out = DeviceSpecies(sp.kind, self.dtype, self.ndim, sp.capacity, sp.w_ref, self.device,
+                            sp.Z, sp.A)
+        self._ensure_ws(sp.n)
+        B.check(self.lib.axpic_compact(B.ref(sp.struct()), B.ref(out.struct()),
                                        B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, self.sh),
                 "compact")
         out.n = int(self.status.cpu()[2])
-        self.ax = out
+        return out
+
+    def compact_axions(self):
+        if self.ax.n:
+            self.ax = self._compacted(self.ax)
+
+    def compact_photons(self):
+        """Photons converted whole by the Primakoff operator keep a zero weight; under
+        a->gamma new photons keep arriving and are converted back, so the dead ones pile
+        up.  The per-cell offsets of the input photons are not used by any operator."""
+        if self.ph.n:
+            self.ph = self._compacted(self.ph)
 
     def diag(self):
         self._ensure_ws(self.ax.n)
@@ -485,6 +495,8 @@ class AxpicSim:
         self.step_index += 1
         if self.compact_every and self.step_index % self.compact_every == 0:
             self.compact_axions()
+            if p["inverse"] and p["channels"] & B.PRIMAKOFF:
+                self.compact_photons()
 
     def hist_np(self):
         nb = self.pdict["hist_nbins"] + 2

@@ -2,9 +2,10 @@
 
 * The uniform all-channel forward plasmas, 512x512 cells with 64 particles per
   cell and species (fp32), over the grid T in {1.3, 3, 5} keV x n_e in
-  {1e25, 6e25} cm^-3 x Z in {1, 2}: the integrated power of each channel over
-  a few steps against the closed-form emissivity over the histogram range,
-  and the binned spectra (App. B) bin by bin against the closed-form spectra.
+  {1e25, 6e25} cm^-3 x Z in {1, 2}, 500 steps each: the integrated power of
+  each channel against the closed-form emissivity over the histogram range,
+  and the binned spectra (App. B) bin by bin against the closed-form spectra,
+  to statistical bars.
 * The forward + inverse relaxation at 1024x1024 cells, 32 per cell and
   species, lognormal weights, electron-to-axion macro-weight ratio 100, FP64
   feedback with the temperature evolved: the axion number and energy reach
@@ -280,10 +281,26 @@ def _closed_forms(wl):
     return c0, [A.dQdE_primakoff, A.dQdE_compton, A.dQdE_brems]
 
 
+def _photon_fractions(edges, T):
+    """Fraction of blackbody photons in each histogram bin (closed-form total density
+    2 zeta(3) T^3 / (pi^2 (hbar c)^3))."""
+    from scipy import integrate
+    tot = 2.0 * ZETA3 * T ** 3 / (math.pi ** 2 * HBARC ** 3)
+    f = lambda x: float(A.dn_blackbody(np.array([x]), T)[0])
+    return np.array([integrate.quad(f, edges[k], edges[k + 1], epsrel=1e-10)[0]
+                     for k in range(edges.size - 1)]) / tot
+
+
 @pytest.mark.parametrize("T,ne,Z", GRID, ids=[f"T{t}-ne{n:.0e}-Z{z}" for t, n, z in GRID])
 def test_forward_plasma_grid_power_and_spectra(T, ne, Z):
-    wl = I.config2(T_keV=T, n_e=ne, Z=Z)
-    log(f"forward plasma T={T} n_e={ne:.0e} Z={Z} n={wl.n} ppc={wl.ppc}")
+    """Each plasma is run for its full 500 steps (seeds 0..11 over the grid).  The bars
+    are statistical: the compound-Poisson variance of the macro-events of each bin
+    (every event adds w E with E below the bin's upper edge, so sigma^2 <= w E_hi X), plus,
+    for Primakoff, the sampling variance of the frozen photon population in the bin
+    (multinomial, relative variance 1 / N_photons in the bin)."""
+    seed = GRID.index((T, ne, Z))
+    wl = I.config2(T_keV=T, n_e=ne, Z=Z, seed=seed)
+    log(f"forward plasma T={T} n_e={ne:.0e} Z={Z} n={wl.n} ppc={wl.ppc} seed={seed}")
     c0, fns = _closed_forms(wl)
     lo, hi = wl.params.hist_lo_keV, wl.params.hist_hi_keV
     V = wl.ncell * wl.V_cell_cm3
@@ -295,8 +312,8 @@ def test_forward_plasma_grid_power_and_spectra(T, ne, Z):
     rate = [q / (e * KEV_ERG) * V * dtp for q, e in zip(Q, meanE)]
     assert min(Q) > 0.0
     wl.params.wa_mul = tuple(r / (wl.params.w_a * 5e4) for r in rate)
-    pl = I.make_plasma_device(wl, 0)
-    sel = pick_cells(wl.ncell, 64, seed=int(T * 10) + Z, must=(0, wl.ncell - 1))
+    pl = I.make_plasma_device(wl, seed)
+    sel = pick_cells(wl.ncell, 64, seed=seed, must=(0, wl.ncell - 1))
     S = Sample(pl, wl.params, sel)
     g = AxpicSim(pl, wl.params)
     check_state(g, S)
@@ -304,28 +321,36 @@ def test_forward_plasma_grid_power_and_spectra(T, ne, Z):
     del g
     check_fused(pl, wl.params)
     g = AxpicSim(pl, wl.params)
-    seeded_chain(g, S, seed=70 + Z)
+    seeded_chain(g, S, seed=70 + seed)
     del g
-    g = AxpicSim(pl, wl.params)
+    g = AxpicSim(pl, wl.params, axion_capacity=int(1.6e8))
+    n_ph = pl["species"]["photons"]["n"]
     del pl
-    steps = 4
-    for _ in range(steps):
+    steps = wl.steps
+    for s in range(steps):
         g.step()
+        if s % 100 == 99:
+            log(f"step {s + 1}: {g.ax.n} axions")
     h = g.hist_np()
     nb = wl.params.hist_nbins
     e = A.hist_edges(wl.params)
     t_tot = steps * dtp
+    Nph = n_ph * _photon_fractions(e, T)
     for i, fn in enumerate(fns):
         Qmc = h[i][:nb].sum() * KEV_ERG / (V * t_tot)
         wprod = wl.params.w_a * wl.params.wa_mul[i]
         X = A.binned_expectation(fn, wl.params, c0, wl.params) * V * t_tot / KEV_ERG
+        var = wprod * e[1:] * X
+        if i == 0:
+            var = var + X * X / np.maximum(Nph, 1.0)
+        sQ = math.sqrt(var.sum()) / X.sum()
         ev = X / (wprod * np.sqrt(e[:-1] * e[1:]))
         use = ev > 30.0
-        z = (h[i][:nb] - X)[use] / np.sqrt(wprod * e[1:][use] * X[use])
+        z = (h[i][:nb] - X)[use] / np.sqrt(var[use])
         chi2 = float((z * z).mean())
-        log(f"channel {i}: power MC / closed form {Qmc / Q[i]:.5f}, {int(use.sum())} bins, "
-            f"max |z| {np.abs(z).max():.2f}, chi2/bin {chi2:.3f}")
-        assert Qmc == pytest.approx(Q[i], rel=0.015), i
+        log(f"channel {i}: power MC / closed form {Qmc / Q[i]:.6f} (sigma {sQ:.1e}), "
+            f"{int(use.sum())} bins, max |z| {np.abs(z).max():.2f}, chi2/bin {chi2:.3f}")
+        assert abs(Qmc / Q[i] - 1.0) < 5.0 * sQ + 1e-4, i
         assert use.sum() >= 40
         assert np.abs(z).max() < 5.5, i
         assert chi2 < 1.6, i

@@ -172,6 +172,14 @@ typedef struct {
                                kernel and keep their energy, thermal spectra are cut at m and
                                absorption uses the massive equilibrium density (E p instead
                                of E^2).  The rate surrogate is massless only. */
+    int32_t light_mode;     /* parents lighter than the product weight w' of their operator
+                               (photon->axion: w_a wa_mul[0]; a->gamma: w_gamma_prod).
+                               0: such a parent converts whole with probability lambda w'/w
+                               (the conversion probability P of Sec. II.F.1), one draw
+                               u < lambda w'/w in place of the Poisson count, which keeps the
+                               mean converted weight w P; 1: the Poisson count of
+                               eq. poisson_macro for them too, the parent converted whole
+                               when K w' exceeds its weight (mean transfer w P w/w'). */
 } axpic_params;
 
 /* Statistics slots (FP64, accumulated by the calls that own them). */

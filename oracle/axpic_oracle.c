@@ -593,6 +593,23 @@ static void or_put(or_products* out, int64_t slot, const or_species* par, int64_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Macro-event count of a conversion operator (Sec. II.F.1, eq. poisson_macro) */
+/* for a parent of physical weight w whose products weigh wprod.  The paper   */
+/* depletes the parent by the converted weight and says nothing of a parent   */
+/* lighter than one product.  Reading: such a parent converts whole, with     */
+/* probability lambda wprod / w (the conversion probability P of the plain    */
+/* rate), so the mean converted weight stays w P; light_mode = 1 keeps the    */
+/* Poisson count for it, which converts it whole whenever K >= 1 and moves on */
+/* average only w P (w / wprod).                                              */
+/* ------------------------------------------------------------------------ */
+static int32_t or_conversion_count(const or_params* prm, double lam, double lam_eff, double w,
+                                   double wprod, double u) {
+    if (prm->light_mode == 0 && w < wprod)
+        return (lam > 0.0 && u < lam / (w / wprod)) ? 1 : 0;
+    return or_poisson(lam_eff, u);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Forward Primakoff conversion on photon macroparticles (Sec. II.F.1).      */
 /* Returns the number of products, or -(required) when out->cap is too small
  * (then nothing is modified).                                              */
@@ -625,7 +642,7 @@ int64_t or_emit_primakoff(const or_grid* g, const or_params* prm, const or_cell*
         double le = or_cap(l, prm, &ws, &capped);
         uint32_t r[4];
         or_draw(prm->seed, ph->id[i], (uint32_t)step, 0, 0, r);
-        K[i] = or_poisson(le, or_u53(r[0], r[1]));
+        K[i] = or_conversion_count(prm, l, le, ph->w[i], wprod, or_u53(r[0], r[1]));
         total += K[i];
     }
     if (lam_out) memcpy(lam_out, lam, sizeof(double) * (size_t)n);
@@ -970,7 +987,8 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
             }
             lam[i] = l;
             double ws; int capped;
-            K[i] = or_poisson(or_cap(l, prm, &ws, &capped), or_u53(r[2], r[3]));
+            K[i] = or_conversion_count(prm, l, or_cap(l, prm, &ws, &capped), w, wg,
+                                       or_u53(r[2], r[3]));
         }
         total += K[i];
     }

@@ -47,6 +47,7 @@ typedef struct {
     double hist_lo_keV, hist_hi_keV;
     int32_t hist_nbins, hist_log;
     double m_a_keV;           /* axion mass; 0: massless */
+    int32_t light_mode;       /* 0: light parents convert whole with probability P; 1: Poisson */
 } or_params;
 
 typedef struct {

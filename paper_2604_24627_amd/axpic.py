@@ -66,7 +66,8 @@ class ParamsC(C.Structure):
                 ("T_mode", C.c_int32), ("feedback", C.c_int32),
                 ("r_relax", C.c_double), ("T_floor_keV", C.c_double), ("T_ceil_keV", C.c_double),
                 ("seed", C.c_uint64), ("hist_lo_keV", C.c_double), ("hist_hi_keV", C.c_double),
-                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32), ("m_a_keV", C.c_double)]
+                ("hist_nbins", C.c_int32), ("hist_log", C.c_int32), ("m_a_keV", C.c_double),
+                ("light_mode", C.c_int32)]
 
 
 EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axpic_bin_cells",

@@ -83,6 +83,8 @@ class Params:
     hist_nbins: int = 128
     hist_log: int = 1
     m_a_keV: float = 0.0              # axion mass (0: massless, the paper's validated case)
+    light_mode: int = 0               # parents lighter than the product weight: 0 convert whole
+                                      # with probability P, 1 literal Poisson count
 
     def as_dict(self) -> Dict:
         return asdict(self)

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2
     assert B.ParamsC.seed.offset % 8 == 0
     # sizes and offsets printed by a C compiler for include/axpic.h (x86-64)
-    assert C.sizeof(B.ParamsC) == 216 and C.sizeof(B.CellsC) == 136
+    assert C.sizeof(B.ParamsC) == 224 and C.sizeof(B.CellsC) == 136
     assert C.sizeof(B.MlpC) == 184
     assert B.MlpC.out_lin.offset == 72 and B.MlpC.T_lo.offset == 136
 

@@ -80,6 +80,66 @@ def test_primakoff_yield_matches_conditional_expectation():
     assert np.mean(got) == pytest.approx(expect, rel=5 * 1.5 / math.sqrt(5 * nev))
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_light_parents_convert_whole(mode):
+    """Parents lighter than one product (Sec. II.F.1 depletes by the converted weight and
+    leaves this case open).  light_mode 0: a light parent converts whole with probability
+    P = lambda w'/w, so the mean converted weight is sum w P; light_mode 1 (the Poisson
+    count, whole conversion on K >= 1): probability 1 - exp(-lambda), a mean transfer of
+    sum w (1 - e^-lambda), short of sum w P by about the factor w / w'.  Both for photons
+    (photon -> axion, w' = w_a wa_mul[0]) and axions (a -> gamma, w' = w_gamma_prod)."""
+    wl, pl = small_plasma(T=3.0, ncell=4, ppc=4096, channels=1, inverse=1, g_agg_GeV=1e-10,
+                          light_mode=mode)
+    wph = pl["species"]["photons"]["w_ref"]
+    wl.params.w_a = 4.0 * wph
+    wl.params.w_gamma_prod = 20.0 * wl.params.w_a
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    rng = np.random.default_rng([17, mode])
+    steps = 6
+
+    def check(parents, wprod, run):
+        n = parents.w.size
+        P = rng.uniform(0.05, 0.6, n)
+        lam = P * parents.w / wprod
+        assert np.all(parents.w < wprod)
+        q = P if mode == 0 else -np.expm1(-lam)
+        expect = (parents.w * q).sum()
+        sd = math.sqrt((parents.w ** 2 * q * (1.0 - q)).sum())
+        moved = []
+        for s in range(steps):
+            sp = parents.copy()
+            prod, K = run(sp, s, lam)
+            whole = K > 0
+            if mode == 0:
+                assert K.max() == 1
+            # a converted light parent is gone, its products carry its weight
+            assert np.all(sp.w[whole] == 0.0) and np.all(sp.w[~whole] == parents.w[~whole])
+            assert prod["w"].sum() == pytest.approx(parents.w[whole].sum(), rel=1e-12)
+            moved.append(parents.w[whole].sum())
+        z = (np.mean(moved) - expect) / (sd / math.sqrt(steps))
+        assert abs(z) < 5.0, z
+        return np.mean(moved), (parents.w * P).sum()
+
+    def run_p(sp, s, lam):
+        prod, _, K = O.emit_primakoff(sim.grid, sim.params, cells, sp, s, 10 ** 9, lam_in=lam)
+        return prod, K
+
+    got, unbiased = check(sim.ph, wl.params.w_a * wl.params.wa_mul[0], run_p)
+    axd = I.make_axions(wl, pl, 512.0, seed=3, zero_frac=0.0)
+    ax = O.OSpecies.from_input(axd)
+
+    def run_a(sp, s, lam):
+        prod, _, _, K, _ = O.absorb(sim.grid, sim.params, cells, sp, s, 10 ** 9, lam_in=lam)
+        return prod, K
+
+    got_a, unbiased_a = check(ax, wl.params.w_gamma_prod, run_a)
+    if mode == 0:
+        assert got == pytest.approx(unbiased, rel=0.02) and got_a == pytest.approx(unbiased_a, rel=0.02)
+    else:
+        assert got < 0.5 * unbiased and got_a < 0.8 * unbiased_a
+
+
 def _bin_number(ax, edges):
     E = ME * np.sqrt((ax.p ** 2).sum(axis=0))
     return np.histogram(E, bins=edges, weights=ax.w)[0], np.histogram(E, bins=edges,

@@ -118,6 +118,7 @@ KParams make_kparams(const axpic_grid* g, const axpic_params* prm, double w_ref_
     k.m_a = prm->m_a_keV;
     k.mu2 = (prm->m_a_keV / kMe) * (prm->m_a_keV / kMe);
     k.massive = prm->m_a_keV > 0.0;
+    k.light_mode = prm->light_mode;
     return k;
 }
 
@@ -137,6 +138,7 @@ bool params_ok(const axpic_params* p) {
     if (!(p->lambda_cap > 0.0) || !(p->w_a > 0.0)) return false;
     if (!(p->r_relax >= 0.0 && p->r_relax <= 1.0)) return false;
     if (!(p->m_a_keV >= 0.0 && p->m_a_keV < 1e6)) return false;
+    if (p->light_mode != 0 && p->light_mode != 1) return false;
     if (p->hist_nbins < 1 || p->hist_nbins > kMaxBins || !(p->hist_hi_keV > p->hist_lo_keV))
         return false;
     if (p->hist_log && !(p->hist_lo_keV > 0.0)) return false;
@@ -527,7 +529,7 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
 // ------------------------------------------------------------------ Primakoff emission
 template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
-k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
+k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
@@ -575,7 +577,8 @@ k_prim_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
             double ws; int cp;
             const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
             const uint4 r = draw(kp, idv[j], step, 0, 0);
-            K = poisson_inv(le, u53(r.x, r.y));
+            K = conversion_count(kp, (double)l, le, (double)wt * w_ref, kp.w_a * kp.wa_mul[0],
+                                 u53(r.x, r.y));
         }
         code[i] = (uint16_t)K;
         tot += K;
@@ -831,7 +834,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
 // code: bits 0-7 a->gamma count, bit 8 absorbed (deletion mode)
 template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
-k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
+k_abs_count(int64_t n, int64_t step, KParams kp, double w_ref_a, const float* __restrict__ p32,
             const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
@@ -888,7 +891,8 @@ k_abs_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
                 const T l = lam_in ? lv[j]
                                    : (M ? lambda_ag_m<T>(kp, pc, wt, p2d[j]) : lambda_ag<T>(kp, pc, wt, p2));
                 double ws; int cp;
-                cd |= (uint32_t)poisson_inv(cap_lambda((double)l, kp.cap, &ws, &cp), u53(r.z, r.w));
+                cd |= (uint32_t)conversion_count(kp, (double)l, cap_lambda((double)l, kp.cap, &ws, &cp),
+                                                 (double)wt * w_ref_a, kp.w_gamma_prod, u53(r.z, r.w));
             }
         }
         code[i] = (uint16_t)cd;
@@ -1501,7 +1505,7 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     const auto k_count = kp.massive ? k_prim_count<T, true> : k_prim_count<T, false>;
     const auto k_events = kp.massive ? k_prim_events<T, true> : k_prim_events<T, false>;
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
-                       cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
+                       ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
                        W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
@@ -1575,7 +1579,7 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
     const auto k_count = kp.massive ? k_abs_count<T, true> : k_abs_count<T, false>;
     const auto k_apply = kp.massive ? k_abs_apply<T, true> : k_abs_apply<T, false>;
     LAUNCH("k_abs_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
-                       cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
+                       ax->w_ref, cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
                        TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
                        TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;

@@ -49,6 +49,7 @@ struct KParams {
     double m_a;                 // axion mass [keV] (0: massless)
     double mu2;                 // (m_a / m_e c^2)^2
     int32_t massive;
+    int32_t light_mode;         // 0: a parent lighter than one product converts whole w.p. P
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -98,6 +99,16 @@ __device__ __forceinline__ int poisson_inv_k(double lam, double u, int kmax) {
     return k;
 }
 __device__ __forceinline__ int poisson_inv(double lam, double u) { return poisson_inv_k(lam, u, kKmax); }
+
+// Macro-event count of a conversion operator (Sec. II.F.1) for a parent of physical
+// weight w whose products weigh wprod.  A parent lighter than one product converts whole,
+// with probability lam wprod / w (the plain rate's conversion probability P), so its mean
+// converted weight is w P; light_mode 1 keeps the Poisson count for it.
+__device__ __forceinline__ int conversion_count(const KParams& kp, double lam, double lam_eff,
+                                                double w, double wprod, double u) {
+    if (kp.light_mode == 0 && w < wprod) return (lam > 0.0 && u < lam / (w / wprod)) ? 1 : 0;
+    return poisson_inv(lam_eff, u);
+}
 
 // Cap and rescale (eqs. lambda_eff, wa_rescaled): returns lambda_eff, *ws = w'/w.
 __device__ __forceinline__ double cap_lambda(double lam, double cap, double* ws, int* capped) {

@@ -141,6 +141,59 @@ def test_primakoff_emission_bit_exact_counts(dtype):
     assert st["capped"] > 0
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_light_parents_bit_exact(mode):
+    """Photons and axions around the product weight (lognormal weights, w' = w_ref):
+    light_mode 0 converts a light parent whole with probability lambda w'/w, 1 draws the
+    Poisson count.  Seeded means on both sides: three steps of photon conversion on the
+    depleting photons, then a->gamma on a seeded axion population; every decision, id and
+    product as the oracle's."""
+    wl = small_workload("f32", channels=1, inverse=1, g_agg_GeV=1e-10, lambda_cap=4.0,
+                        light_mode=mode)
+    wl.lognormal_sigma = 0.5
+    wph = I.make_plasma(wl, 0)["species"]["photons"]["w_ref"]
+    wl.params.w_a = wph
+    wl.params.w_gamma_prod = wph
+    g, o, pl = pair(wl)
+    cells = o.cells()
+    for step in range(3):
+        lam = I.means(g.ph.n, seed=150 + step, lo=1e-3, hi=2.0)
+        light = o.ph.w < wph
+        n0, id0 = g.ax.n, g.next_id
+        g.step_index = step
+        k = g.emit_primakoff(lam_in=dev(lam))
+        prod, _, K = O.emit_primakoff(o.grid, o.params, cells, o.ph, step, id0, None, o.stats,
+                                      lam_in=lam.astype(np.float64))
+        print(f"[parity] light photons {int(light.sum())}/{light.size}, events {k}", flush=True)
+        assert k == prod["w"].size and k > 100 and light.sum() > 100
+        assert (K[light] > 0).sum() > 20
+        if mode == 0:
+            assert K[light].max() == 1
+        _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6)
+        np.testing.assert_allclose(np64(g.ph.w[: g.ph.n]) * g.ph.w_ref, o.ph.w, rtol=1e-6)
+    st = g.stats_dict()
+    assert st["overdepleted"] == o.stats[O.ST["overdepleted"]] > 0
+    axd = I.make_axions(wl, pl, 12.0, seed=19)
+    g.load_axions(axd)
+    n = g.ax.n
+    lag = I.means(n, seed=160, lo=1e-3, hi=2.0)
+    osp = O.OSpecies.from_input(axd)
+    light = (osp.w > 0) & (osp.w < wph)
+    ph_n0, id0 = g.ph.n, g.next_id
+    g.step_index = 3
+    k = g.absorb(n, lam_in=dev(lag))
+    prod, _, _, K, _ = O.absorb(o.grid, o.params, cells, osp, 3, id0,
+                                lam_in=lag.astype(np.float64))
+    print(f"[parity] light axions {int(light.sum())}/{n}, a->gamma photons {k}", flush=True)
+    assert k == prod["w"].size and k > 100 and (K[light] > 0).sum() > 20
+    if mode == 0:
+        assert K[light].max() == 1
+    _compare_products(g.ph, ph_n0, prod, g.ph.w_ref, rtol_w=1e-6)
+    gw = np64(g.ax.w[:n]) * g.ax.w_ref
+    np.testing.assert_array_equal(gw == 0.0, osp.w == 0.0)
+    np.testing.assert_allclose(gw, osp.w, rtol=2e-6, atol=0)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_thermal_emission_matches_oracle(dtype):
     """Rate-fed Compton + brems emission from the same seeded means on both sides."""

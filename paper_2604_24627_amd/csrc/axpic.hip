@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -230,7 +231,70 @@ struct IdView {
     __device__ __forceinline__ uint64_t operator()(int64_t i) const {
         return i < nimp ? id0 + (uint64_t)i : id[i];
     }
+    // ids of the run i0 .. i0 + kPer - 1 (VEC: the run lies in the buffer, 16-byte loads)
+    template <bool VEC> __device__ __forceinline__ void run(int64_t i0, int64_t n, uint64_t* v) const;
 };
+
+// A thread's run of kPer consecutive parents i0 .. i0 + kPer - 1.  With VEC (the whole
+// workgroup's parents lie in the buffer and the base pointers are 16-byte aligned; i0 is
+// a multiple of kPer) each array is read with 16-byte loads, else with one clamped
+// scalar load per parent.  The kernels instantiate both and branch once per workgroup.
+template <bool VEC>
+__device__ __forceinline__ void ld_run(const float* __restrict__ p, int64_t i0, int64_t n, float* v) {
+    if (VEC) {
+        const float4 q = *(const float4*)(p + i0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = p[i0 + q < n ? i0 + q : n - 1];
+    }
+}
+template <bool VEC>
+__device__ __forceinline__ void ld_run(const double* __restrict__ p, int64_t i0, int64_t n, double* v) {
+    if (VEC) {
+        const double2 a = *(const double2*)(p + i0), b = *(const double2*)(p + i0 + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = p[i0 + q < n ? i0 + q : n - 1];
+    }
+}
+template <bool VEC>
+__device__ __forceinline__ void ld_run(const int32_t* __restrict__ p, int64_t i0, int64_t n, int32_t* v) {
+    if (VEC) {
+        const int4 q = *(const int4*)(p + i0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = p[i0 + q < n ? i0 + q : n - 1];
+    }
+}
+template <bool VEC>
+__device__ __forceinline__ void IdView::run(int64_t i0, int64_t n, uint64_t* v) const {
+    if (i0 + kPer <= nimp) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = id0 + (uint64_t)(i0 + q);
+    } else if (VEC && i0 >= nimp) {
+        const ulonglong2 a = *(const ulonglong2*)(id + i0), b = *(const ulonglong2*)(id + i0 + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = (*this)(i0 + q < n ? i0 + q : n - 1);
+    }
+}
+// The kPer 16-bit codes of a run (vec: one 8-byte store).
+template <bool VEC>
+__device__ __forceinline__ void st_codes(uint16_t* __restrict__ code, int64_t i0, int64_t n,
+                                         const uint32_t* cd) {
+    if (VEC) {
+        *(uint2*)(code + i0) = make_uint2(cd[0] | (cd[1] << 16), cd[2] | (cd[3] << 16));
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (i0 + q < n) code[i0 + q] = (uint16_t)cd[q];
+    }
+}
+
 
 // ------------------------------------------------------------------ block scan
 // Exclusive scan of one value per thread across the workgroup (kThreads).
@@ -527,6 +591,62 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
 }
 
 // ------------------------------------------------------------------ Primakoff emission
+// Counts of the thread's run of photons; returns the run's product total, *act the
+// number of converting photons.
+template <typename T, bool M, bool VEC>
+__device__ __forceinline__ uint32_t prim_count_run(
+    int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref, const T* __restrict__ pref,
+    const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
+    const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
+    const T* __restrict__ lam_in, uint16_t* __restrict__ code, float wt_heavy, uint32_t* act) {
+    T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
+    int32_t cv[kPer];
+    uint64_t idv[kPer];
+    ld_run<VEC>(w, i0, n, wv);
+    id.template run<VEC>(i0, n, idv);
+    if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
+    else { ld_run<VEC>(px, i0, n, xv); ld_run<VEC>(py, i0, n, yv); ld_run<VEC>(pz, i0, n, zv);
+           ld_run<VEC>(cell, i0, n, cv); }
+    T pcv[kPer][4];
+    if (!lam_in) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
+    }
+    const double wprod = kp.w_a * kp.wa_mul[0];
+    uint32_t cd[kPer], tot = 0, nact = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        cd[j] = 0;
+        if (!VEC && i0 + j >= n) continue;
+        const T wt = wv[j];
+        T l = (T)0;
+        if (wt > (T)0)
+            l = lam_in ? lv[j]
+                       : (M ? lambda_primakoff_m<T>(kp, pcv[j], wt,
+                                                    p2_of<double>(xv[j], yv[j], zv[j]))
+                            : lambda_primakoff<T>(pcv[j], wt,
+                                                  p2_of<T>(xv[j], yv[j], zv[j])));
+        int K = 0;
+        if (l > (T)0) {
+            const uint4 r = draw(kp, idv[j], step, 0, 0);
+            // a parent surely heavier than one product with a surely-zero count skips FP64
+            const bool zero = sizeof(T) == 4 && (float)wt >= wt_heavy &&
+                              poisson_surely_zero((float)l, r.x);
+            if (!zero) {
+                double ws; int cp;
+                const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
+                K = conversion_count(kp, (double)l, le, (double)wt * w_ref, wprod, u53(r.x, r.y));
+            }
+        }
+        cd[j] = (uint32_t)K;
+        tot += K;
+        nact += K > 0;
+    }
+    st_codes<VEC>(code, i0, n, cd);
+    *act = nact;
+    return tot;
+}
+
 template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __restrict__ p32,
@@ -534,56 +654,21 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
              uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
-              double* __restrict__ acc, int acc_n) {
+             double* __restrict__ acc, int acc_n, int aligned, float wt_heavy) {
     clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
-    uint32_t tot = 0, act = 0;
-    // all loads of the thread's parents first (clamped index), then their cells'
-    // prefactor records, then the arithmetic
-    T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
-    int32_t cv[kPer];
-    uint64_t idv[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        const int64_t ii = i < n ? i : n - 1;
-        wv[j] = w[ii];
-        idv[j] = id(ii);
-        if (lam_in) { lv[j] = lam_in[ii]; }
-        else { xv[j] = px[ii]; yv[j] = py[ii]; zv[j] = pz[ii]; cv[j] = cell[ii]; }
-    }
-    T pcv[kPer][4];
-    if (!lam_in) {
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
-    }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        if (i >= n) break;
-        const T wt = wv[j];
-        T l = (T)0;
-        if (wt > (T)0)
-            l = lam_in ? lv[j]
-                       : (M ? lambda_primakoff_m<T>(kp, pcv[j], wt,
-                                                    (double)xv[j] * xv[j] + (double)yv[j] * yv[j] +
-                                                        (double)zv[j] * zv[j])
-                            : lambda_primakoff<T>(pcv[j], wt,
-                                                  xv[j] * xv[j] + yv[j] * yv[j] + zv[j] * zv[j]));
-        int K = 0;
-        if (l > (T)0) {
-            double ws; int cp;
-            const double le = cap_lambda((double)l, kp.cap, &ws, &cp);
-            const uint4 r = draw(kp, idv[j], step, 0, 0);
-            K = conversion_count(kp, (double)l, le, (double)wt * w_ref, kp.w_a * kp.wa_mul[0],
-                                 u53(r.x, r.y));
-        }
-        code[i] = (uint16_t)K;
-        tot += K;
-        act += K > 0;
-    }
+    // each thread takes kPer consecutive parents (the workgroup covers the same
+    // kBlockParents as the expand pass); all loads first, then the arithmetic
+    const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
+    uint32_t tot, act;
+    if (aligned && base + kBlockParents <= n)
+        tot = prim_count_run<T, M, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
+                                         lam_in, code, wt_heavy, &act);
+    else
+        tot = prim_count_run<T, M, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
+                                          lam_in, code, wt_heavy, &act);
     const uint32_t bt = block_sum_u32(tot, lds);
     const uint32_t ba = block_sum_u32(act, lds);
     if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
@@ -710,6 +795,62 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
 }
 
 // ------------------------------------------------------------------ thermal emission
+// Compton-like and brems counts of the thread's run of electrons (code: Compton in
+// bits 0-7, brems in 8-15); returns the run's product total, *act the emitting electrons.
+template <typename T, bool VEC>
+__device__ __forceinline__ uint32_t therm_count_run(
+    int64_t i0, int64_t n, int64_t step, const KParams& kp, const T* __restrict__ pref,
+    const T* __restrict__ w, const IdView& id, const int32_t* __restrict__ cell,
+    const T* __restrict__ lam_in, bool lam_b_vec, uint16_t* __restrict__ code, uint32_t* act) {
+    const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
+    T lCv[kPer], lBv[kPer];
+    uint64_t idv[kPer];
+    id.template run<VEC>(i0, n, idv);
+    if (lam_in) {
+        ld_run<VEC>(lam_in, i0, n, lCv);
+        if (VEC && lam_b_vec) ld_run<true>(lam_in + n, i0, n, lBv);
+        else ld_run<false>(lam_in + n, i0, n, lBv);
+    } else {
+        T wv[kPer];
+        int32_t cv[kPer];
+        ld_run<VEC>(w, i0, n, wv);
+        ld_run<VEC>(cell, i0, n, cv);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const T* pc = pref + (int64_t)cv[j] * AXPIC_PREF_N;
+            lCv[j] = wv[j] * pc[4];
+            lBv[j] = wv[j] * pc[5];
+        }
+    }
+    uint32_t cd[kPer], tot = 0, nact = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        cd[j] = 0;
+        if (!VEC && i0 + j >= n) continue;
+        T lC = lCv[j], lB = lBv[j];
+        if (!onC) lC = (T)0;
+        if (!onB) lB = (T)0;
+        int KC = 0, KB = 0;
+        if (lC > (T)0 || lB > (T)0) {
+            const uint4 r = draw(kp, idv[j], step, 1, 0);
+            // both counts surely zero: no FP64 inversion
+            const bool zero = sizeof(T) == 4 && poisson_surely_zero((float)lC, r.x) &&
+                              poisson_surely_zero((float)lB, r.z);
+            if (!zero) {
+                double ws; int cp;
+                KC = poisson_inv(cap_lambda((double)lC, kp.cap, &ws, &cp), u53(r.x, r.y));
+                KB = poisson_inv(cap_lambda((double)lB, kp.cap, &ws, &cp), u53(r.z, r.w));
+            }
+        }
+        cd[j] = (uint32_t)(KC | (KB << 8));
+        tot += KC + KB;
+        nact += (KC + KB) > 0;
+    }
+    st_codes<VEC>(code, i0, n, cd);
+    *act = nact;
+    return tot;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
@@ -717,44 +858,21 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
               IdView id, const int32_t* __restrict__ cell,
               const T* __restrict__ lam_in, uint16_t* __restrict__ code,
               uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
-              double* __restrict__ acc, int acc_n) {
+              double* __restrict__ acc, int acc_n, int aligned) {
     clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
-    const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
-    uint32_t tot = 0, act = 0;
-    T lCv[kPer], lBv[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        const int64_t ii = i < n ? i : n - 1;
-        if (lam_in) { lCv[j] = lam_in[ii]; lBv[j] = lam_in[n + ii]; }
-        else {
-            const T* pc = pref + (int64_t)cell[ii] * AXPIC_PREF_N;
-            const T wt = w[ii];
-            lCv[j] = wt * pc[4];
-            lBv[j] = wt * pc[5];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        if (i >= n) break;
-        T lC = lCv[j], lB = lBv[j];
-        if (!onC) lC = (T)0;
-        if (!onB) lB = (T)0;
-        int KC = 0, KB = 0;
-        if (lC > (T)0 || lB > (T)0) {
-            const uint4 r = draw(kp, id(i), step, 1, 0);
-            double ws; int cp;
-            KC = poisson_inv(cap_lambda((double)lC, kp.cap, &ws, &cp), u53(r.x, r.y));
-            KB = poisson_inv(cap_lambda((double)lB, kp.cap, &ws, &cp), u53(r.z, r.w));
-        }
-        code[i] = (uint16_t)(KC | (KB << 8));
-        tot += KC + KB;
-        act += (KC + KB) > 0;
-    }
+    const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
+    // the brems half of lam_in starts at n: 16-byte aligned runs only if n % kPer == 0
+    const bool lam_b_vec = (n % kPer) == 0;
+    uint32_t tot, act;
+    if (aligned && base + kBlockParents <= n)
+        tot = therm_count_run<T, true>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec, code,
+                                       &act);
+    else
+        tot = therm_count_run<T, false>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec,
+                                        code, &act);
     const uint32_t bt = block_sum_u32(tot, lds);
     const uint32_t ba = block_sum_u32(act, lds);
     if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
@@ -831,6 +949,86 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
 }
 
 // ------------------------------------------------------------------ absorption
+// Decisions for the thread's run of axions; returns the run's photon total, *act the
+// axions with a nonzero code.
+template <typename T, bool M, bool VEC>
+__device__ __forceinline__ uint32_t abs_count_run(
+    int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref_a, const T* __restrict__ pref,
+    const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
+    const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
+    const T* __restrict__ pabs_in, const T* __restrict__ lam_in, uint16_t* __restrict__ code,
+    float wt_heavy, float wt_light, float prod_ratio, uint32_t* act) {
+    const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
+    const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
+    T wv[kPer], xv[kPer], yv[kPer], zv[kPer], Pv[kPer], lv[kPer];
+    int32_t cv[kPer];
+    uint64_t idv[kPer];
+    ld_run<VEC>(w, i0, n, wv);
+    ld_run<VEC>(px, i0, n, xv);
+    ld_run<VEC>(py, i0, n, yv);
+    ld_run<VEC>(pz, i0, n, zv);
+    ld_run<VEC>(cell, i0, n, cv);
+    id.template run<VEC>(i0, n, idv);
+    if (pabs_in) ld_run<VEC>(pabs_in, i0, n, Pv);
+    if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
+    T pcv[kPer][AXPIC_PREF_N];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 2);
+    uint32_t cdv[kPer], tot = 0, nact = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        cdv[j] = 0;
+        if (!VEC && i0 + j >= n) continue;
+        T wt = wv[j];
+        uint32_t cd = 0;
+        if (wt > (T)0) {
+            const T* pc = pcv[j];
+            const T p2 = p2_of<T>(xv[j], yv[j], zv[j]);
+            const double p2d = p2_of<double>(xv[j], yv[j], zv[j]);
+            const uint4 r = draw(kp, idv[j], step, 4, 0);
+            if (thermal) {
+                const T P = pabs_in ? Pv[j]
+                                    : (M ? pabs_thermal_m<T>(kp, pc, p2d)
+                                         : pabs_thermal<T>(kp, pc, energy_keV(p2)));
+                if (kp.absorb_mode == 0) {
+                    // u53 < P is decided by the leading 24 bits of u unless P falls
+                    // between their bounds
+                    bool absorbed;
+                    if (sizeof(T) == 4 && u_lo24(r.x) >= (float)P) absorbed = false;
+                    else if (sizeof(T) == 4 && u_hi24(r.x) <= (float)P) absorbed = true;
+                    else absorbed = u53(r.x, r.y) < (double)P;
+                    if (absorbed) { cd |= 256u; wt = (T)0; }
+                } else {
+                    wt = (T)((double)wt - (double)wt * (double)P);
+                }
+            }
+            if (a2g && wt > (T)0) {
+                const T l = lam_in ? lv[j]
+                                   : (M ? lambda_ag_m<T>(kp, pc, wt, p2d) : lambda_ag<T>(kp, pc, wt, p2));
+                // surely heavy with a surely-zero count, or surely light and surely not
+                // converting: no FP64
+                const bool zero =
+                    sizeof(T) == 4 && l > (T)0 &&
+                    (((float)wt >= wt_heavy && poisson_surely_zero((float)l, r.z)) ||
+                     ((float)wt < wt_light && light_surely_zero((float)l, prod_ratio, (float)wt, r.z)));
+                if (!zero) {
+                    double ws; int cp;
+                    cd |= (uint32_t)conversion_count(kp, (double)l,
+                                                     cap_lambda((double)l, kp.cap, &ws, &cp),
+                                                     (double)wt * w_ref_a, kp.w_gamma_prod,
+                                                     u53(r.z, r.w));
+                }
+            }
+        }
+        cdv[j] = cd;
+        tot += cd & 0xFFu;
+        nact += cd != 0;
+    }
+    st_codes<VEC>(code, i0, n, cdv);
+    *act = nact;
+    return tot;
+}
+
 // code: bits 0-7 a->gamma count, bit 8 absorbed (deletion mode)
 template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
@@ -839,66 +1037,21 @@ k_abs_count(int64_t n, int64_t step, KParams kp, double w_ref_a, const float* __
             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
-            uint32_t* __restrict__ bact,
-              double* __restrict__ acc, int acc_n) {
+            uint32_t* __restrict__ bact, double* __restrict__ acc, int acc_n, int aligned,
+            float wt_heavy, float wt_light, float prod_ratio) {
     clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
-    const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
-    uint32_t tot = 0, act = 0;
-    T wv[kPer], p2v[kPer], Pv[kPer], lv[kPer];
-    double p2d[kPer];                                // massive axions only
-    int32_t cv[kPer];
-    uint64_t idv[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        const int64_t ii = i < n ? i : n - 1;
-        wv[j] = w[ii];
-        p2v[j] = psq<T>(px, py, pz, ii);
-        if (M) p2d[j] = psq_d<T>(px, py, pz, ii);
-        cv[j] = cell[ii];
-        idv[j] = id(ii);
-        Pv[j] = pabs_in ? pabs_in[ii] : (T)0;
-        lv[j] = lam_in ? lam_in[ii] : (T)0;
-    }
-    T pcv[kPer][AXPIC_PREF_N];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 2);
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int64_t i = base + j * kThreads + threadIdx.x;
-        if (i >= n) break;
-        T wt = wv[j];
-        uint32_t cd = 0;
-        if (wt > (T)0) {
-            const T* pc = pcv[j];
-            const T p2 = p2v[j];
-            const uint4 r = draw(kp, idv[j], step, 4, 0);
-            if (thermal) {
-                const T P = pabs_in ? Pv[j]
-                                    : (M ? pabs_thermal_m<T>(kp, pc, p2d[j])
-                                         : pabs_thermal<T>(kp, pc, energy_keV(p2)));
-                if (kp.absorb_mode == 0) {
-                    if (u53(r.x, r.y) < (double)P) { cd |= 256u; wt = (T)0; }
-                } else {
-                    wt = (T)((double)wt - (double)wt * (double)P);
-                }
-            }
-            if (a2g && wt > (T)0) {
-                const T l = lam_in ? lv[j]
-                                   : (M ? lambda_ag_m<T>(kp, pc, wt, p2d[j]) : lambda_ag<T>(kp, pc, wt, p2));
-                double ws; int cp;
-                cd |= (uint32_t)conversion_count(kp, (double)l, cap_lambda((double)l, kp.cap, &ws, &cp),
-                                                 (double)wt * w_ref_a, kp.w_gamma_prod, u53(r.z, r.w));
-            }
-        }
-        code[i] = (uint16_t)cd;
-        tot += cd & 0xFFu;
-        act += cd != 0;
-    }
+    const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
+    uint32_t tot, act;
+    if (aligned && base + kBlockParents <= n)
+        tot = abs_count_run<T, M, true>(i0, n, step, kp, w_ref_a, pref, w, px, py, pz, id, cell,
+                                        pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio, &act);
+    else
+        tot = abs_count_run<T, M, false>(i0, n, step, kp, w_ref_a, pref, w, px, py, pz, id, cell,
+                                         pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio, &act);
     const uint32_t bt = block_sum_u32(tot, lds);
     const uint32_t ba = block_sum_u32(act, lds);
     if (threadIdx.x == 0) {
@@ -1481,6 +1634,47 @@ template <typename T> inline const T* TCP(const void* p) { return (const T*)p; }
 
 inline IdView idv(const axpic_species* sp) { return IdView{sp->id, sp->id0, sp->n_implicit}; }
 
+// 16-byte alignment of every pointer a count kernel reads with run loads (null counts
+// as aligned: it is not read)
+inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+inline int runs_aligned(std::initializer_list<const void*> ps) {
+    for (const void* p : ps)
+        if (!al16(p)) return 0;
+    return 1;
+}
+
+// Smallest FP32 parent weight (in units of w_ref) that is surely not lighter than one
+// product of weight wprod, i.e. fl64(wt w_ref) >= wprod for every FP32 wt at or above it;
+// 0 when no parent converts as a light one, +inf when none is surely heavy.
+inline float heavy_threshold(double wprod, double w_ref, int light_mode) {
+    if (light_mode != 0 || !(wprod > 0.0)) return 0.0f;
+    if (!(w_ref > 0.0)) return INFINITY;
+    const double th = wprod / w_ref * (1.0 + 1e-9);
+    if (!(th < 3.0e38)) return INFINITY;
+    float f = (float)th;
+    if ((double)f < th) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+// Largest FP32 parent weight below which a parent is surely lighter than one product:
+// fl64(wt w_ref) < wprod for every FP32 wt under it (0: no light parents).
+inline float light_threshold(double wprod, double w_ref, int light_mode) {
+    if (light_mode != 0 || !(wprod > 0.0)) return 0.0f;
+    if (!(w_ref > 0.0)) return INFINITY;
+    const double th = wprod / w_ref * (1.0 - 1e-9);
+    if (!(th < 3.0e38)) return 3.0e38f;
+    float f = (float)th;
+    if ((double)f > th) f = std::nextafter(f, 0.0f);
+    return f;
+}
+
+// wprod / w_ref in FP32 for the light-parent pre-test (+inf when undefined)
+inline float product_ratio(double wprod, double w_ref) {
+    if (!(w_ref > 0.0) || !(wprod >= 0.0)) return INFINITY;
+    const double r = wprod / w_ref;
+    return r < 3.0e38 ? (float)r : INFINITY;
+}
+
 int acc_used(const KParams& kp) { return 3 * (kp.nbins + 2) + AXPIC_ST_COUNT; }
 
 void acc_reduce(const KParams& kp, const Workspace& W, double* hist, double* stats, hipStream_t s) {
@@ -1507,7 +1701,10 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
-                       W.code, W.bsum, W.bact, W.acc, acc_used(kp));
+                       W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in,
+                                     W.code}),
+                       heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
@@ -1530,7 +1727,8 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       runs_aligned({el->w, el->cell, el->id, lam_in, W.code}));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
@@ -1581,7 +1779,12 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
     LAUNCH("k_abs_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ax->w_ref, cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
                        TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp));
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       runs_aligned({ax->w, ax->p[0], ax->p[1], ax->p[2], ax->cell, ax->id, pabs_in,
+                                     lam_in, W.code}),
+                       heavy_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
+                       light_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
+                       product_ratio(kp.w_gamma_prod, ax->w_ref));
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
            out_cap, W.ctrl, status, next_id, chain, ph ? (int)AXPIC_CHAIN_PHOTONS : -1);

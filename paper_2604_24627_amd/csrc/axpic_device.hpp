@@ -100,6 +100,29 @@ __device__ __forceinline__ int poisson_inv_k(double lam, double u, int kmax) {
 }
 __device__ __forceinline__ int poisson_inv(double lam, double u) { return poisson_inv_k(lam, u, kKmax); }
 
+// FP32 pre-tests that only ever decide what the FP64 draw decides.  The leading 24 bits
+// of u53(a, b) bound it: (a >> 8) 2^-24 <= u53 < ((a >> 8) + 1) 2^-24, both exact in FP32.
+__device__ __forceinline__ float u_lo24(uint32_t a) { return (float)(a >> 8) * 5.9604644775390625e-08f; }
+__device__ __forceinline__ float u_hi24(uint32_t a) { return (float)((a >> 8) + 1u) * 5.9604644775390625e-08f; }
+
+// True only if poisson_inv(min(lam, cap), u53(a, .)) is 0 for the FP32 rate lam: each of
+// the two FP32 roundings moves 1 - lam - 2^-22 by at most 2^-25, so u stays below
+// 1 - lam - 2^-23 and hence below the FP64 shortcut's bound (1 - min(lam, cap)) - 2^-50.
+// False for NaN or infinite rates, which then take the FP64 path.
+__device__ __forceinline__ bool poisson_surely_zero(float lam, uint32_t a) {
+    return u_hi24(a) < (1.0f - lam) - 2.384185791015625e-07f;
+}
+
+// True only if a light parent (weight below one product) surely does not convert: the
+// FP64 test is u53 < P with P = lam wprod / w; here pf = lam (wprod / w_ref) / wt with
+// the reciprocal and three roundings (relative error below 2^-21.6), raised by 2^-20,
+// is compared with the lower bound of u.  u_lo24 > 0 also covers a P that underflows.
+__device__ __forceinline__ bool light_surely_zero(float lam, float ratio, float wt, uint32_t a) {
+    const float pf = lam * ratio * __builtin_amdgcn_rcpf(wt);
+    const float lo = u_lo24(a);
+    return lo > 0.0f && lo >= pf * 1.00000095367431640625f;
+}
+
 // Macro-event count of a conversion operator (Sec. II.F.1) for a parent of physical
 // weight w whose products weigh wprod.  A parent lighter than one product converts whole,
 // with probability lam wprod / w (the plain rate's conversion probability P), so its mean
@@ -305,11 +328,15 @@ __device__ __forceinline__ LocalState local_state(double T, double ne_dep, doubl
 }
 
 // ---------------------------------------------------------------- per-particle rates
+// |p|^2 in one fixed order of fused multiply-adds, so that every kernel evaluating a
+// rate from the same momentum gets the same bits (no choice left to contraction)
+template <typename T>
+__device__ __forceinline__ T p2_of(T a, T b, T c) { return dev_fma<T>(c, c, dev_fma<T>(b, b, a * a)); }
+
 template <typename T>
 __device__ __forceinline__ T psq(const T* __restrict__ px, const T* __restrict__ py,
                                  const T* __restrict__ pz, int64_t i) {
-    const T a = px[i], b = py[i], c = pz[i];
-    return a * a + b * b + c * c;
+    return p2_of<T>(px[i], py[i], pz[i]);
 }
 
 template <typename T> struct PrefOf;
@@ -432,8 +459,7 @@ __device__ __forceinline__ double F_mass(double k, double p, double kappa2) {
 template <typename T>
 __device__ __forceinline__ double psq_d(const T* __restrict__ px, const T* __restrict__ py,
                                         const T* __restrict__ pz, int64_t i) {
-    const double a = px[i], b = py[i], c = pz[i];
-    return a * a + b * b + c * c;
+    return p2_of<double>((double)px[i], (double)py[i], (double)pz[i]);
 }
 
 __device__ __forceinline__ double axion_energy(const KParams& kp, double p2) {

@@ -35,7 +35,7 @@ namespace {
 constexpr int kThreads = 256;          // threads per workgroup
 constexpr int kPer = 4;                // parents per thread in the count/apply kernels
 constexpr int kBlockParents = kThreads * kPer;
-static_assert(kPer == 4, "k_expand unpacks four 16-bit codes per thread");
+static_assert(kPer == 4, "st_codes packs four 16-bit codes per thread");
 constexpr int kStatSlots = 12;         // per-thread statistics registers
 constexpr int kMaxBins = 1024;         // histogram bins per channel (+2 under/overflow)
 constexpr int kCopies = 32;            // privatised accumulator copies (histogram + statistics)
@@ -680,33 +680,45 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
 // the final id after filling the product.
 constexpr uint64_t kRecParentMask = (1ull << 40) - 1;
 
+constexpr int kExpPer = 16;                              // codes per thread in k_expand
+constexpr int kExpSub = kThreads * kExpPer / kBlockParents; // count blocks per expand block
+static_assert(kExpSub * kBlockParents == kThreads * kExpPer, "expand block spans whole count blocks");
+
 __global__ void __launch_bounds__(kThreads)
 k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
-         const uint64_t* __restrict__ boff, const int64_t* __restrict__ ctrl, int64_t out_n,
-         int64_t out_cap, uint64_t* __restrict__ rec) {
+         const uint64_t* __restrict__ boff, int64_t nb, const int64_t* __restrict__ ctrl,
+         int64_t out_n, int64_t out_cap, uint64_t* __restrict__ rec, int aligned) {
     __shared__ uint32_t lds[kThreads / 64];
-    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    // one expand workgroup covers kExpSub consecutive count blocks (products of a run of
+    // blocks are contiguous from the first block's offset)
+    const int64_t cb0 = (int64_t)blockIdx.x * kExpSub;
+    uint32_t live = 0;
+#pragma unroll
+    for (int q = 0; q < kExpSub; ++q) live |= (cb0 + q < nb) ? bact[cb0 + q] : 0u;
+    if (ctrl[0] || live == 0) return;
     out_n = ctrl[2];
-    // each thread takes kPer consecutive parents: one 8-byte load of their codes and one
-    // block scan keep the records in parent order
-    const int64_t i0 = (int64_t)blockIdx.x * kBlockParents + (int64_t)kPer * threadIdx.x;
-    uint32_t cd[kPer];
-    if (i0 + kPer <= n) {
-        const uint2 u = *(const uint2*)(code + i0);
-        cd[0] = u.x & 0xFFFFu; cd[1] = u.x >> 16; cd[2] = u.y & 0xFFFFu; cd[3] = u.y >> 16;
+    // each thread takes kExpPer consecutive parents (two 16-byte loads of their codes);
+    // one block scan keeps the records in parent order
+    const int64_t i0 = cb0 * kBlockParents + (int64_t)kExpPer * threadIdx.x;
+    uint32_t cd[kExpPer];
+    if (aligned && i0 + kExpPer <= n) {
+        const uint4 u0 = *(const uint4*)(code + i0), u1 = *(const uint4*)(code + i0 + 8);
+        const uint32_t wds[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) { cd[2 * q] = wds[q] & 0xFFFFu; cd[2 * q + 1] = wds[q] >> 16; }
     } else {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) cd[q] = i0 + q < n ? code[i0 + q] : 0u;
+        for (int q = 0; q < kExpPer; ++q) cd[q] = i0 + q < n ? code[i0 + q] : 0u;
     }
     // mode 0: one channel (count in bits 0-7); mode 1: Compton bits 0-7, brems 8-15
     uint32_t cnt = 0;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) cnt += (cd[q] & 0xFFu) + (mode == 1 ? (cd[q] >> 8) : 0u);
+    for (int q = 0; q < kExpPer; ++q) cnt += (cd[q] & 0xFFu) + (mode == 1 ? (cd[q] >> 8) : 0u);
     uint32_t segtot;
     const uint32_t pre = block_excl_scan(cnt, lds, &segtot);
     if (cnt == 0) return;
-    int64_t slot = out_n + (int64_t)(boff[blockIdx.x] + pre);
-    for (int q = 0; q < kPer; ++q) {
+    int64_t slot = out_n + (int64_t)(boff[cb0] + pre);
+    for (int q = 0; q < kExpPer; ++q) {
         const uint64_t i = (uint64_t)(i0 + q);
         const uint32_t K0 = cd[q] & 0xFFu, K1 = mode == 1 ? (cd[q] >> 8) : 0u;
         for (uint32_t k = 0; k < K0; ++k, ++slot)
@@ -1707,8 +1719,9 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
                        heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
-    LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 0, W.code, W.bact,
-           W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
+    LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
+           s, n, 0, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
+           runs_aligned({W.code}));
     LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
            next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
            TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
@@ -1731,8 +1744,9 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
                        runs_aligned({el->w, el->cell, el->id, lam_in, W.code}));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
-    LAUNCH("k_expand", k_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, n, 1, W.code, W.bact,
-           W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
+    LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
+           s, n, 1, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
+           runs_aligned({W.code}));
     const auto k_events = kp.massive ? k_therm_events<T, true> : k_therm_events<T, false>;
     LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, TCP<T>(el->w),

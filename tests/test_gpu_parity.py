@@ -466,3 +466,126 @@ def test_chained_step_recovers_from_overflow_bit_identical():
                                rtol=1e-6, atol=1e-9)
     np.testing.assert_allclose(small.T.cpu().numpy(), big.T.cpu().numpy(), rtol=1e-7)
     np.testing.assert_allclose(small.hist_np(), big.hist_np(), rtol=1e-12)
+
+
+def _nudge(x, k):
+    """float32 array x moved by k[i] units in the last place (towards +inf for k > 0)."""
+    x = np.asarray(x, dtype=np.float32).copy()
+    for s in range(1, int(np.abs(k).max()) + 1):
+        up, dn = k >= s, k <= -s
+        x[up] = np.nextafter(x[up], np.float32(np.inf))
+        x[dn] = np.nextafter(x[dn], np.float32(-np.inf))
+    return x
+
+
+def _uniforms(seed, ids, step, stream):
+    """The oracle's two uniforms u53(r0, r1), u53(r2, r3) of each parent's draw, and the
+    leading 24-bit bounds of the first word of each pair."""
+    r = np.array([O.draw(seed, int(i), step, stream, 0) for i in ids], dtype=np.uint64)
+    u = [np.array([O.u53(a, b) for a, b in r[:, q:q + 2]]) for q in (0, 2)]
+    hi = [((r[:, q] >> 8) + 1).astype(np.float64) * 2.0 ** -24 for q in (0, 2)]
+    lo = [(r[:, q] >> 8).astype(np.float64) * 2.0 ** -24 for q in (0, 2)]
+    return u, lo, hi
+
+
+def _boundary_means(u, hi, seed):
+    """Means placed on the decisions of the Poisson inversion for uniform u: the 0/1
+    boundary exp(-lam) = u, the FP64 shortcut 1 - lam = u, the FP32 pre-test bound
+    1 - lam - 2^-22 = u_hi, and seeded means; each moved by -3 .. 3 ulps."""
+    n = u.size
+    j = np.arange(n)
+    kind, k = j % 4, (j // 4) % 7 - 3
+    base = np.where(kind == 0, -np.log(u), np.where(kind == 1, 1.0 - u, 1.0 - hi - 2.0 ** -22))
+    base = np.where(base > 1e-30, base, 1e-7)
+    lam = _nudge(base.astype(np.float32), k)
+    lam[kind == 3] = I.means(n, seed=seed)[kind == 3]
+    return np.maximum(lam, np.float32(1e-30)), kind
+
+
+def test_count_pretests_at_decision_boundaries():
+    """The count kernels decide surely-zero draws with FP32 tests on the leading 24 bits
+    of the uniform before the FP64 inversion.  Means placed within a few ulps of every
+    decision boundary (Poisson 0/1, the FP64 shortcut, the FP32 bound, Bernoulli
+    absorption u < P, light-parent conversion u < lam w'/w) and parent weights within
+    ulps of the light/heavy threshold: every count, id and product as the oracle's."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10,
+                        boost=4e33, lambda_cap=64.0, light_mode=0)
+    wph = I.make_plasma(wl, 0)["species"]["photons"]["w_ref"]
+    wl.params.w_a = wph / 400.0                 # Primakoff products weigh w_a * 400 = w_ph
+    wl.params.wa_mul = (400.0, 1.0, 1.0)
+    wl.params.w_gamma_prod = wph
+    g, o, pl = pair(wl)
+    cells = o.cells()
+    seed = int(wl.params.seed)
+    # photons: a third lighter, a third heavier, a third within ulps of one product
+    n = g.ph.n
+    j = np.arange(n)
+    w = np.where(j % 3 == 0, 0.5, np.where(j % 3 == 1, 2.0, 1.0)).astype(np.float32)
+    w[j % 3 == 2] = _nudge(w[j % 3 == 2], (j[j % 3 == 2] // 3) % 5 - 2)
+    g.ph.w[:n].copy_(dev(w))
+    o.ph.w = w.astype(np.float64) * g.ph.w_ref
+    (u, _), _, (hi, _) = _uniforms(seed, o.ph.id, 0, 0)
+    lam, kind = _boundary_means(u, hi, seed=201)
+    n0, id0 = g.ax.n, g.next_id
+    g.step_index = 0
+    k = g.emit_primakoff(lam_in=dev(lam))
+    prod, _, K = O.emit_primakoff(o.grid, o.params, cells, o.ph, 0, id0, None, o.stats,
+                                  lam_in=lam.astype(np.float64))
+    print(f"[parity] boundary photons: {k} events, K>0 on the exp boundary "
+          f"{int((K[kind == 0] > 0).sum())}/{int((kind == 0).sum())}", flush=True)
+    assert k == prod["w"].size
+    assert 0 < (K[kind == 0] > 0).sum() < (kind == 0).sum()
+    _compare_products(g.ax, n0, prod, g.ax.w_ref, rtol_w=1e-6)
+    np.testing.assert_allclose(np64(g.ph.w[:n]) * g.ph.w_ref, o.ph.w, rtol=1e-6)
+    # electrons: both channels on their boundaries
+    ne = g.el.n
+    (uC, uB), _, (hC, hB) = _uniforms(seed, o.el.id, 0, 1)
+    lC, _ = _boundary_means(uC, hC, seed=202)
+    lB, _ = _boundary_means(uB[::-1].copy(), hB[::-1].copy(), seed=203)
+    lB = lB[::-1].copy()
+    lamT = np.concatenate([lC, lB])
+    n0, id0 = g.ax.n, g.next_id
+    k = g.emit_thermal(lam_in=dev(lamT))
+    prodT, _, KT = O.emit_thermal(o.grid, o.params, cells, o.el, 0, id0,
+                                  lam_in=lamT.reshape(2, ne).astype(np.float64))
+    assert k == prodT["w"].size and k > 1000
+    _compare_products(g.ax, n0, prodT, g.ax.w_ref, rtol_w=1e-6, exact_p=False)
+    # axions: absorption probabilities on u, a->gamma means on both conversion rules
+    axd = I.make_axions(wl, pl, 12.0, seed=23)
+    # relative weights (w_ref = w_ph / 400): light ones as drawn, a fifth at 800 (heavier
+    # than one photon product), a fifth within ulps of 400 (one product)
+    ja = np.arange(axd["w"].size)
+    wa = axd["w"].astype(np.float32)
+    live = wa > 0
+    wa[live & (ja % 5 == 1)] = 800.0
+    thr = live & (ja % 5 == 2)
+    wa[thr] = _nudge(np.full(int(thr.sum()), 400.0, np.float32), (ja[thr] // 5) % 5 - 2)
+    axd["w"] = wa
+    g.load_axions(axd)
+    na = g.ax.n
+    osp = O.OSpecies.from_input(axd)
+    (ua, ug), (la, _), (ha, hg) = _uniforms(seed, osp.id, 3, 4)
+    ja = np.arange(na)
+    ka = (ja // 3) % 7 - 3
+    pab = _nudge(np.where(ja % 3 == 0, ua, np.where(ja % 3 == 1, la, ha)).astype(np.float32), ka)
+    pab = np.clip(pab, 0.0, 1.0).astype(np.float32)
+    light = (osp.w > 0) & (osp.w < wph)
+    heavy = (osp.w > 0) & ~light
+    # a light axion converts iff u < lam w'/w: means with lam w'/w on u
+    conv_lam = np.where(light, ug * osp.w / wph, 0.0)
+    lag, _ = _boundary_means(ug, hg, seed=204)
+    lag = np.where(light & (ja % 2 == 0), _nudge(conv_lam.astype(np.float32), ka), lag)
+    lag = np.maximum(lag, np.float32(1e-30)).astype(np.float32)
+    g.step_index = 3
+    ph_n0, id0 = g.ph.n, g.next_id
+    k = g.absorb(na, pabs_in=dev(pab), lam_in=dev(lag))
+    prm = dict(o.params, w_gamma_prod=g.ph.w_ref)
+    prodA, _, _, KA, dead = O.absorb(o.grid, prm, cells, osp, 3, id0, pabs_in=pab.astype(np.float64),
+                                     lam_in=lag.astype(np.float64))
+    print(f"[parity] boundary axions: {int(dead.sum())} absorbed of {na}, {k} photons, "
+          f"light {int(light.sum())}", flush=True)
+    assert k == prodA["w"].size and dead.sum() > 100 and light.sum() > 100
+    assert (KA[light] > 0).sum() > 20 and (KA[heavy] > 0).sum() > 20
+    gw = np64(g.ax.w[:na]) * g.ax.w_ref
+    np.testing.assert_array_equal(gw == 0.0, osp.w == 0.0)
+    _compare_products(g.ph, ph_n0, prodA, g.ph.w_ref, rtol_w=1e-6)

@@ -846,8 +846,8 @@ __device__ __forceinline__ uint32_t therm_count_run(
         if (lC > (T)0 || lB > (T)0) {
             const uint4 r = draw(kp, idv[j], step, 1, 0);
             // both counts surely zero: no FP64 inversion
-            const bool zero = sizeof(T) == 4 && poisson_surely_zero((float)lC, r.x) &&
-                              poisson_surely_zero((float)lB, r.z);
+            const bool zero = sizeof(T) == 4 && (poisson_surely_zero((float)lC, r.x) &
+                                                 poisson_surely_zero((float)lB, r.z));
             if (!zero) {
                 double ws; int cp;
                 KC = poisson_inv(cap_lambda((double)lC, kp.cap, &ws, &cp), u53(r.x, r.y));

@@ -53,6 +53,11 @@ struct KParams {
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
+// a ^ b ^ c in one instruction (gfx950 v_bitop3_b32; 0x96 is the truth table of XOR3)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -60,8 +65,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         // full 64-bit products: one v_mad_u64_u32 each instead of a mul_lo/mul_hi pair
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
     }
     return c;
 }

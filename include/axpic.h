@@ -115,6 +115,10 @@ typedef struct {
     double Z, A;        /* [host] ion charge state and mass number */
     uint64_t id0;       /* [host] particles i < n_implicit have id id0 + i and their */
     int64_t n_implicit; /*        id[] entries are not read (0: every id is stored) */
+    const int64_t* off; /* device, [ncell+1] or NULL: particles i < n_sorted lie in cell */
+    int64_t n_sorted;   /* [host] order, cell c holding off[c] <= i < off[c+1] (cell[] stays
+                           valid; the Primakoff count reads it only where off is NULL or the
+                           cells of a 1024-particle tile are more than 256) */
 } axpic_species;
 
 /* Per-cell tables.  dens: [1+AXPIC_MAX_IONS][ncell] FP64 deposited physical

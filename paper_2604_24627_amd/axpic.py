@@ -43,7 +43,8 @@ class SpeciesC(C.Structure):
                 ("id", C.c_void_p), ("cell", C.c_void_p), ("n", C.c_int64),
                 ("capacity", C.c_int64), ("dtype", C.c_int32), ("kind", C.c_int32),
                 ("w_ref", C.c_double), ("Z", C.c_double), ("A", C.c_double),
-                ("id0", C.c_uint64), ("n_implicit", C.c_int64)]
+                ("id0", C.c_uint64), ("n_implicit", C.c_int64), ("off", C.c_void_p),
+                ("n_sorted", C.c_int64)]
 
 
 class CellsC(C.Structure):

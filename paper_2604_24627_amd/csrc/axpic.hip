@@ -157,6 +157,7 @@ bool species_ok(const axpic_species* s, bool need_p) {
     if (s->n == 0) return true;
     if (s->n_implicit < 0 || s->n_implicit > s->n) return false;
     if (!s->w || !s->cell || (!s->id && s->n_implicit < s->n)) return false;
+    if (s->off && (s->n_sorted < 0 || s->n_sorted > s->n)) return false;
     if (need_p && (!s->p[0] || !s->p[1] || !s->p[2])) return false;
     return true;
 }
@@ -591,14 +592,41 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
 }
 
 // ------------------------------------------------------------------ Primakoff emission
+constexpr int kStageCells = 256;   // cells a workgroup of the cell-ordered prefix stages in LDS
+
+// Cells of a workgroup inside a cell-ordered prefix, staged in LDS: the first prefactor
+// record (4 entries) of cells c_first .. c_first + m - 1 and the m - 1 interior cell
+// boundaries relative to the workgroup's first parent.
+struct CellStage {
+    const int32_t* bnd;
+    const float4* pref;
+    int32_t m;
+    // relative cell of parents t0 .. t0 + kPer - 1 (t0 relative to the first parent):
+    // the number of boundaries at or below each
+    __device__ __forceinline__ void cells(int32_t t0, int32_t* k) const {
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (bnd[mid] <= t0) lo = mid + 1; else hi = mid;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            while (lo < m - 1 && bnd[lo] <= t0 + q) ++lo;
+            k[q] = lo;
+        }
+    }
+};
+
 // Counts of the thread's run of photons; returns the run's product total, *act the
-// number of converting photons.
-template <typename T, bool M, bool VEC>
+// number of converting photons.  STAGE: the workgroup's cells are staged in LDS and the
+// photons' cell indices are not read.
+template <typename T, bool M, bool VEC, bool STAGE>
 __device__ __forceinline__ uint32_t prim_count_run(
     int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref, const T* __restrict__ pref,
     const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
     const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
-    const T* __restrict__ lam_in, uint16_t* __restrict__ code, float wt_heavy, uint32_t* act) {
+    const T* __restrict__ lam_in, uint16_t* __restrict__ code, float wt_heavy,
+    const CellStage& stg, int32_t t0, uint32_t* act) {
     T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
     int32_t cv[kPer];
     uint64_t idv[kPer];
@@ -606,9 +634,17 @@ __device__ __forceinline__ uint32_t prim_count_run(
     id.template run<VEC>(i0, n, idv);
     if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
     else { ld_run<VEC>(px, i0, n, xv); ld_run<VEC>(py, i0, n, yv); ld_run<VEC>(pz, i0, n, zv);
-           ld_run<VEC>(cell, i0, n, cv); }
+           if (!STAGE) ld_run<VEC>(cell, i0, n, cv); }
     T pcv[kPer][4];
-    if (!lam_in) {
+    if constexpr (STAGE) {
+        int32_t kc[kPer];
+        stg.cells(t0, kc);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const float4 v = stg.pref[kc[j]];
+            pcv[j][0] = v.x; pcv[j][1] = v.y; pcv[j][2] = v.z; pcv[j][3] = v.w;
+        }
+    } else if (!lam_in) {
 #pragma unroll
         for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
     }
@@ -654,21 +690,45 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
              uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
-             double* __restrict__ acc, int acc_n, int aligned, float wt_heavy) {
+             double* __restrict__ acc, int acc_n, int aligned, float wt_heavy,
+             const int64_t* __restrict__ off, int64_t n_sorted) {
     clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
+    __shared__ int32_t s_bnd[kStageCells];
+    __shared__ float4 s_pref[kStageCells];
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     // each thread takes kPer consecutive parents (the workgroup covers the same
     // kBlockParents as the expand pass); all loads first, then the arithmetic
     const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
+    const int32_t t0 = kPer * (int32_t)threadIdx.x;
+    const bool vec = aligned && base + kBlockParents <= n;
+    // A workgroup inside the cell-ordered prefix spans the cells of its first and last
+    // photon; when they are few, their prefactors and boundaries go to LDS and the
+    // photons' cells come from the offsets (4 bytes less per photon)
+    CellStage stg{s_bnd, s_pref, 0};
+    if (sizeof(T) == 4 && !lam_in && off && vec && base + kBlockParents <= n_sorted) {
+        const int32_t c_first = cell[base], c_last = cell[base + kBlockParents - 1];
+        const int32_t m = c_last - c_first + 1;
+        if (m >= 1 && m <= kStageCells) {
+            for (int t = threadIdx.x; t < m; t += kThreads) {
+                s_pref[t] = *(const float4*)(p32 + (int64_t)(c_first + t) * AXPIC_PREF_N);
+                if (t >= 1) s_bnd[t - 1] = (int32_t)(off[c_first + t] - base);
+            }
+            __syncthreads();
+            stg.m = m;
+        }
+    }
     uint32_t tot, act;
-    if (aligned && base + kBlockParents <= n)
-        tot = prim_count_run<T, M, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
-                                         lam_in, code, wt_heavy, &act);
+    if (stg.m > 0)
+        tot = prim_count_run<T, M, true, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
+                                               lam_in, code, wt_heavy, stg, t0, &act);
+    else if (vec)
+        tot = prim_count_run<T, M, true, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
+                                                cell, lam_in, code, wt_heavy, stg, t0, &act);
     else
-        tot = prim_count_run<T, M, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
-                                          lam_in, code, wt_heavy, &act);
+        tot = prim_count_run<T, M, false, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
+                                                 cell, lam_in, code, wt_heavy, stg, t0, &act);
     const uint32_t bt = block_sum_u32(tot, lds);
     const uint32_t ba = block_sum_u32(act, lds);
     if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
@@ -1716,7 +1776,8 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
                        W.code, W.bsum, W.bact, W.acc, acc_used(kp),
                        runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in,
                                      W.code}),
-                       heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode));
+                       heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode),
+                       ph->off, ph->off ? ph->n_sorted : (int64_t)0);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,

@@ -40,7 +40,8 @@ class DeviceSpecies:
         self.x = [None, None, None]
         self.p = [None, None, None]
         self.w = self.id = self.cell = None
-        self.off = None
+        self.off = None         # per-cell offsets of the cell-ordered prefix [0, n_sorted)
+        self.n_sorted = 0
         self.id0 = 0
         self.n_implicit = 0
         self._alloc(max(int(capacity), 1))
@@ -84,6 +85,7 @@ class DeviceSpecies:
         s.id[:n].copy_(torch.from_numpy(sp["id"].view(np.int64)))
         s.cell[:n].copy_(torch.from_numpy(sp["cell"]))
         s.off = torch.from_numpy(sp["off"]).to(device)
+        s.n_sorted = n
         ids = sp["id"]
         if n and np.array_equal(ids, ids[0] + np.arange(n, dtype=np.uint64)):
             s.id0, s.n_implicit = int(ids[0]), n
@@ -106,6 +108,7 @@ class DeviceSpecies:
         torch.arange(sp["id0"], sp["id0"] + n, out=s.id[:n])
         s.cell[:n].copy_(sp["cell"])
         s.off = sp["off"].to(device)
+        s.n_sorted = n
         s.id0, s.n_implicit = int(sp["id0"]), n
         return s
 
@@ -119,6 +122,7 @@ class DeviceSpecies:
         S.dtype, S.kind = self.dtype, self.kind
         S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
         S.id0, S.n_implicit = self.id0, self.n_implicit
+        S.off, S.n_sorted = (B.ptr(self.off), self.n_sorted) if self.off is not None else (None, 0)
         return S
 
     def to_numpy(self) -> Dict:
@@ -230,6 +234,7 @@ class AxpicSim:
         if ax.dtype != self.dtype:
             raise ValueError("axion dtype differs from the plasma's")
         ax.id0 = ax.n_implicit = 0          # every id stored: appended ids continue elsewhere
+        ax.off, ax.n_sorted = None, 0       # axions move: no cell-ordered prefix
         self.ax = ax
         self.next_id = max(self.next_id, int(sp.get("next_id", 0)))
         self._ensure_ws(self.ax.capacity)

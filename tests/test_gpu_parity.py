@@ -589,3 +589,31 @@ def test_count_pretests_at_decision_boundaries():
     gw = np64(g.ax.w[:na]) * g.ax.w_ref
     np.testing.assert_array_equal(gw == 0.0, osp.w == 0.0)
     _compare_products(g.ph, ph_n0, prodA, g.ph.w_ref, rtol_w=1e-6)
+
+
+@pytest.mark.parametrize("ppc,poisson", [(2, True), (6, True), (37, False)])
+def test_primakoff_cells_from_offsets_equal_cell_index(ppc, poisson):
+    """Tiles of the cell-ordered photons take their cells from the per-cell offsets and
+    their cells' prefactors from LDS when they span at most 256 cells (Poisson counts
+    leave empty cells); sparser tiles, the ragged tail and buffers without offsets read
+    the per-photon cell index.  All three decide exactly as the rate-fed path."""
+    wl = small_workload("f32", n=(64, 64), ppc=ppc, channels=1, g_agg_GeV=1e-10, w_a=2e-35,
+                        lambda_cap=0.7)
+    wl.poisson_ppc = poisson
+    pl = I.make_plasma(wl, 5)
+    off = pl["species"]["photons"]["off"]
+    print(f"[parity] ppc={ppc} poisson={poisson}: {int(off[-1])} photons, "
+          f"{int((np.diff(off) == 0).sum())} empty cells", flush=True)
+    g1 = AxpicSim(pl, wl.params)
+    g2 = AxpicSim(pl, wl.params)
+    g2.ph.off, g2.ph.n_sorted = None, 0
+    g3 = AxpicSim(pl, wl.params)
+    lam = g3.rates(g3.ph, B.PRIMAKOFF).clone()
+    k1, k2, k3 = g1.emit_primakoff(), g2.emit_primakoff(), g3.emit_primakoff(lam_in=lam)
+    assert k1 == k2 == k3 > 20
+    for ga in (g2, g3):
+        for a, b in ((g1.ax, ga.ax), (g1.ph, ga.ph)):
+            x, y = a.to_numpy(), b.to_numpy()
+            for key in ("w", "id", "cell"):
+                np.testing.assert_array_equal(x[key], y[key])
+            np.testing.assert_array_equal(x["p"], y["p"])

@@ -35,7 +35,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     # offsets that the C compiler would produce (natural alignment, x86-64)
     assert C.sizeof(B.Grid) == 40
-    assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2
+    assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2 + 8 * 2
+    assert B.SpeciesC.off.offset == 136 and B.SpeciesC.n_sorted.offset == 144
     assert B.ParamsC.seed.offset % 8 == 0
     # sizes and offsets printed by a C compiler for include/axpic.h (x86-64)
     assert C.sizeof(B.ParamsC) == 224 and C.sizeof(B.CellsC) == 136

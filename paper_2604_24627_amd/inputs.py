@@ -431,18 +431,21 @@ def config3(n=(1024, 1024), ppc=32, ratio=100.0, seed=0, **kw) -> Workload:
 def config5(n=(256, 256, 256), ppc=32, seed=0, **kw) -> Workload:
     """3D 256^3, Poisson(32) per cell per species, fp32, T linear 1-5 keV and
     n_e linear 1e24-6e25 cm^-3 along x, all channels forward + inverse with
-    FP64 feedback, 200 steps.  Rate boost 1e32; Primakoff products (both
-    directions) carry 100 w_a, which puts the mean macro-event counts near
-    5e-3 (Primakoff), 2e-3 (Compton-like), 1e-4 (brems) and 1e-2 (a->gamma)."""
+    FP64 feedback, 200 steps.  Every product (axions of all channels, a->gamma
+    photons) weighs w_a, the weight of a photon at n_e = 1e24 cm^-3, so that no
+    parent is lighter than one product (a lighter one would convert whole, and
+    the low-density end would churn photons and axions every step).  Rate boost
+    3e30 puts the mean macro-event counts near 1e-2 (Primakoff), 4e-5
+    (Compton-like), 2e-6 (brems) and 3e-2 (a->gamma)."""
     p = Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=CH_PRIMAKOFF | CH_COMPTON | CH_BREMS,
-               inverse=1, lambda_cap=1.0, boost=1e32, feedback=1, T_mode=2, seed=seed,
-               wa_mul=(100.0, 1.0, 1.0),
+               inverse=1, lambda_cap=1.0, boost=3e30, feedback=1, T_mode=2, seed=seed,
+               wa_mul=(1.0, 1.0, 1.0),
                hist_lo_keV=0.1, hist_hi_keV=80.0, hist_nbins=128, hist_log=1)
     wl = Workload("cfg5", ndim=3, n=tuple(n), ppc=ppc, dtype="f32", T_keV=1.0, T_keV_hi=5.0,
                   n_e=1e24, n_e_hi=6e25, n_ref=6e25, Z=1, A=1.0, poisson_ppc=True, steps=200,
                   params=p)
-    wl.params.w_a = (6e25 * wl.V_cell_cm3 / ppc) / 100.0
-    wl.params.w_gamma_prod = wl.params.w_a * wl.params.wa_mul[0]
+    wl.params.w_a = 1e24 * wl.V_cell_cm3 / ppc
+    wl.params.w_gamma_prod = wl.params.w_a
     for k, v in kw.items():
         setattr(wl, k, v)
     return wl

@@ -370,6 +370,37 @@ typedef struct {
     double T_lo, T_hi, ne_lo, ne_hi, x_lo, x_hi;   /* [host] training box (keV, cm^-3, omega/T) */
 } axpic_mlp;
 
+/* Normalisation of a training set: f_i = (x_i - lo_i) sc_i - 1 maps the valid
+ * rows' range of feature i onto [-1, 1] (Z: [1, 2]); per channel c the
+ * least-squares affine fit log R ~ mu_c + lin_c . f over the valid rows of c and
+ * the standard deviation sigma_c of its residual (at least 1e-3).  A row is
+ * valid when its log R is finite. */
+typedef struct {
+    double lo[4], sc[4];
+    double mu[4], lin[4][4], sigma[4];
+    int64_t count[4];              /* valid rows per channel */
+} axpic_mlp_norm;
+
+/* Device workspace of axpic_mlp_prepare. */
+size_t axpic_mlp_prepare_ws_bytes(void);
+/* axpic_mlp_prepare -- fills *norm [host] from feat [n][4], logR [n] and ch [n]
+ * (device; the output of axpic_surrogate_samples): FP64 reductions on the GPU in a
+ * fixed order, the 5 x 5 normal equations solved on the host.  Synchronises
+ * `stream`.  AXPIC_E_DOMAIN if a feature range is empty or a channel has too few
+ * valid rows for the fit. */
+axpic_status axpic_mlp_prepare(const double* feat, const double* logR, const int32_t* ch, int64_t n,
+                               void* ws, size_t ws_bytes, axpic_mlp_norm* norm, void* stream);
+/* axpic_mlp_design -- training rows X [n][32] (16-byte aligned) = normalised
+ * features, channel one-hot, zeros; Y [n] = (log R - mu_c - lin_c . f) / sigma_c,
+ * NaN for an invalid row (the loss skips it). */
+axpic_status axpic_mlp_design(const double* feat, const double* logR, const int32_t* ch, int64_t n,
+                              const axpic_mlp_norm* norm, float* X, float* Y, void* stream);
+/* axpic_mlp_batch -- minibatch Xb [batch][32], Yb [batch] of rows drawn with
+ * replacement from X [n][32] (n < 2^32): row floor(u n / 2^32), u the first word
+ * of Philox4x32-10 at counter (b, step, 0x4D4C5042, 0) under key seed. */
+axpic_status axpic_mlp_batch(const float* X, const float* Y, int64_t n, int64_t batch, uint64_t seed,
+                             int64_t step, float* Xb, float* Yb, void* stream);
+
 /* Training samples generated by the plain rates (FP64, device arrays of n):
  * for each (T [keV], n_e [cm^-3], Z, x = omega/T, channel) writes the raw
  * features feat[4i..4i+3] = (log x, log(kappa/T), log n_e, Z) and log R. */
@@ -386,7 +417,8 @@ axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream);
  * y [batch] (may be NULL); activations are kept in ws for axpic_mlp_loss_grad. */
 axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, void* ws,
                                size_t ws_bytes, float* y, void* stream);
-/* Mean squared error of y against Y and its gradient (AXPIC_MLP_PARAMS floats). */
+/* Mean squared error of y against Y and its gradient (AXPIC_MLP_PARAMS floats);
+ * rows whose target is NaN contribute neither (the mean still divides by batch). */
 axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const float* Y, int64_t batch,
                                  void* ws, size_t ws_bytes, float* grad, double* loss, void* stream);
 /* Adam step on the FP32 master parameters (step counts from 1). */

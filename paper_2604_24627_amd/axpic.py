@@ -78,10 +78,17 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_stream_copy", "axpic_mlp_blob_bytes", "axpic_mlp_train_ws_bytes",
            "axpic_mlp_pack", "axpic_mlp_forward", "axpic_mlp_loss_grad", "axpic_mlp_adam",
            "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
-           "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table"]
+           "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table",
+           "axpic_mlp_prepare_ws_bytes", "axpic_mlp_prepare", "axpic_mlp_design",
+           "axpic_mlp_batch"]
 MLP_PARAMS = 57888
 MLP_BLOB_BYTES = 112704
 TAB_MAX_NODES = 64
+
+
+class MlpNormC(C.Structure):
+    _fields_ = [("lo", C.c_double * 4), ("sc", C.c_double * 4), ("mu", C.c_double * 4),
+                ("lin", C.c_double * 16), ("sigma", C.c_double * 4), ("count", C.c_int64 * 4)]
 
 
 class MlpC(C.Structure):
@@ -142,11 +149,16 @@ def load(path: Optional[str] = None):
                              _P]),
         ("axpic_rates_table", [_P, _P, _P, _P, C.c_int32, C.c_int32, C.c_double, C.c_double, _P,
                                _P, _P, _P]),
+        ("axpic_mlp_prepare", [_P, _P, _P, C.c_int64, _P, C.c_size_t, _P, _P]),
+        ("axpic_mlp_design", [_P, _P, _P, C.c_int64, _P, _P, _P, _P]),
+        ("axpic_mlp_batch", [_P, _P, C.c_int64, C.c_int64, C.c_uint64, C.c_int64, _P, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32
         fn.argtypes = args
     L.axpic_mlp_blob_bytes.restype = C.c_size_t
+    L.axpic_mlp_prepare_ws_bytes.restype = C.c_size_t
+    L.axpic_mlp_prepare_ws_bytes.argtypes = []
     L.axpic_mlp_train_ws_bytes.restype = C.c_size_t
     L.axpic_mlp_train_ws_bytes.argtypes = [C.c_int64]
     L.axpic_timing_enable.restype = None

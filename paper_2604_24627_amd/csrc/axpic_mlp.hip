@@ -20,6 +20,7 @@
 // follow.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -118,7 +119,8 @@ k_mse_grad(int64_t Bn, const float* __restrict__ Z5, const float* __restrict__ Y
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e2 = 0.0;
     if (b < Bn) {
-        const float r = Z5[b * kD5] - Y[b];
+        // a row with a NaN target (no valid label) carries no gradient and no loss
+        const float r = isnan(Y[b]) ? 0.0f : Z5[b * kD5] - Y[b];
         for (int c = 0; c < kD5; ++c) dZ5[b * kD5 + c] = c == 0 ? 2.0f * r / (float)Bn : 0.0f;
         e2 = (double)r * r;
     }
@@ -157,6 +159,129 @@ k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __r
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi; v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ training set
+// Rows with a non-finite label (brems samples whose screening factor is not
+// positive) take part in no statistic and carry a NaN target, which the loss skips.
+constexpr int kPrepBlocks = 256;
+constexpr int kMomN = 21;   // per channel: 15 of d d^T (upper triangle), 5 of d y, y y; d = (1, f)
+
+// Per-block minimum and maximum of the raw features 0..2 over the valid rows.
+__global__ void __launch_bounds__(256)
+k_prep_range(int64_t n, const double* __restrict__ feat, const double* __restrict__ logR,
+             double* __restrict__ part) {
+    __shared__ double red[256];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (!isfinite(logR[i])) continue;
+        for (int k = 0; k < 3; ++k) { mn[k] = fmin(mn[k], feat[4 * i + k]); mx[k] = fmax(mx[k], feat[4 * i + k]); }
+    }
+    for (int q = 0; q < 6; ++q) {
+        red[threadIdx.x] = q < 3 ? mn[q] : mx[q - 3];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o)
+                red[threadIdx.x] = q < 3 ? fmin(red[threadIdx.x], red[threadIdx.x + o])
+                                         : fmax(red[threadIdx.x], red[threadIdx.x + o]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x * 6 + q] = red[0];
+        __syncthreads();
+    }
+}
+
+struct PrepNorm { double lo[4], sc[4], mu[4], lin[4][4], sigma[4]; };
+
+__device__ __forceinline__ void prep_features(const double* __restrict__ f, const PrepNorm& nm,
+                                              double* fn) {
+    for (int k = 0; k < 4; ++k) fn[k] = (f[k] - nm.lo[k]) * nm.sc[k] - 1.0;
+}
+
+// Per-block sums of d d^T, d y and y y over the valid rows of channel c, d = (1, f(x)).
+__global__ void __launch_bounds__(256)
+k_prep_moments(int64_t n, const double* __restrict__ feat, const double* __restrict__ logR,
+               const int32_t* __restrict__ ch, int c, PrepNorm nm, double* __restrict__ part) {
+    __shared__ double red[256];
+    double acc[kMomN];
+    for (int q = 0; q < kMomN; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double y = logR[i];
+        if (ch[i] != c || !isfinite(y)) continue;
+        double d[5];
+        d[0] = 1.0;
+        prep_features(feat + 4 * i, nm, d + 1);
+        int q = 0;
+        for (int a = 0; a < 5; ++a)
+            for (int b = a; b < 5; ++b) acc[q++] += d[a] * d[b];
+        for (int a = 0; a < 5; ++a) acc[15 + a] += d[a] * y;
+        acc[20] += y * y;
+    }
+    for (int q = 0; q < kMomN; ++q) {
+        red[threadIdx.x] = acc[q];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x * kMomN + q] = red[0];
+        __syncthreads();
+    }
+}
+
+// Column sums of the per-block partials, in block order: out[q] = sum_b part[b][q].
+__global__ void k_prep_sum(int nb, int m, const double* __restrict__ part, double* __restrict__ out,
+                           int minmax) {
+    const int q = threadIdx.x;
+    if (q >= m) return;
+    double v = part[q];
+    for (int b = 1; b < nb; ++b) {
+        const double x = part[b * m + q];
+        v = minmax == 0 ? v + x : (q < m / 2 ? fmin(v, x) : fmax(v, x));
+    }
+    out[q] = v;
+}
+
+// Training rows: X [n][32] = (f(x), channel one-hot, zeros), Y = (log R - baseline) / sigma
+// (NaN for an invalid row).
+__global__ void __launch_bounds__(256)
+k_prep_design(int64_t n, const double* __restrict__ feat, const double* __restrict__ logR,
+              const int32_t* __restrict__ ch, PrepNorm nm, float* __restrict__ X,
+              float* __restrict__ Y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double fn[4];
+    prep_features(feat + 4 * i, nm, fn);
+    const int c = ch[i];
+    float row[32];
+    for (int k = 0; k < 32; ++k) row[k] = 0.0f;
+    for (int k = 0; k < 4; ++k) row[k] = (float)fn[k];
+    if (c >= 0 && c < 4) row[4 + c] = 1.0f;
+    for (int k = 0; k < 32; k += 4)
+        *(float4*)(X + i * 32 + k) = make_float4(row[k], row[k + 1], row[k + 2], row[k + 3]);
+    const double y = logR[i];
+    float t = NAN;
+    if (isfinite(y) && c >= 0 && c < 4) {
+        double base = nm.mu[c];
+        for (int k = 0; k < 4; ++k) base += nm.lin[c][k] * (double)row[k];
+        t = (float)((y - base) / nm.sigma[c]);
+    }
+    Y[i] = t;
+}
+
+// A minibatch of rows drawn with replacement: row r_b = floor(u32 n / 2^32) with u32 the
+// first word of Philox4x32-10 at counter (b, step, 0x4D4C5042, 0) under key seed.
+__global__ void __launch_bounds__(256)
+k_prep_batch(int64_t n, const float* __restrict__ X, const float* __restrict__ Y, int64_t batch,
+             uint32_t seed_lo, uint32_t seed_hi, int64_t step, float* __restrict__ Xb,
+             float* __restrict__ Yb) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= batch) return;
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)(b >> 32), (uint32_t)step,
+                                             0x4D4C5042u), seed_lo, seed_hi);
+    const int64_t row = (int64_t)(((uint64_t)r.x * (uint64_t)n) >> 32);
+    for (int k = 0; k < 32; k += 4) *(float4*)(Xb + b * 32 + k) = *(const float4*)(X + row * 32 + k);
+    Yb[b] = Y[row];
 }
 
 // ------------------------------------------------------------------ packing
@@ -644,6 +769,124 @@ axpic_status axpic_surrogate_samples(const axpic_params* prm, int64_t n, const d
     if (n == 0) return AXPIC_OK;
     LAUNCH("k_surrogate_samples", k_surrogate_samples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        S(stream), n, *prm, T, ne, Z, x, ch, feat, logR);
+    return launched();
+}
+
+size_t axpic_mlp_prepare_ws_bytes(void) {
+    return sizeof(double) * ((size_t)kPrepBlocks * kMomN + 4 * kMomN + 8);
+}
+
+// Gaussian elimination with partial pivoting of the 5 x 5 normal equations.
+static bool solve5(double A[5][5], double b[5], double x[5]) {
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+        if (!(std::fabs(A[piv][c]) > 0.0)) return false;
+        if (piv != c) {
+            for (int k = 0; k < 5; ++k) std::swap(A[c][k], A[piv][k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < 5; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 4; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < 5; ++k) v -= A[r][k] * x[k];
+        x[r] = v / A[r][r];
+    }
+    return true;
+}
+
+static PrepNorm to_prep(const axpic_mlp_norm* nm) {
+    PrepNorm p;
+    for (int k = 0; k < 4; ++k) {
+        p.lo[k] = nm->lo[k]; p.sc[k] = nm->sc[k]; p.mu[k] = nm->mu[k]; p.sigma[k] = nm->sigma[k];
+        for (int j = 0; j < 4; ++j) p.lin[k][j] = nm->lin[k][j];
+    }
+    return p;
+}
+
+axpic_status axpic_mlp_prepare(const double* feat, const double* logR, const int32_t* ch, int64_t n,
+                               void* ws, size_t ws_bytes, axpic_mlp_norm* norm, void* stream) {
+    if (!norm || n < 1 || !feat || !logR || !ch || !ws || ws_bytes < axpic_mlp_prepare_ws_bytes())
+        return AXPIC_E_INVAL;
+    hipStream_t s = S(stream);
+    double* part = (double*)ws;
+    double* out = part + (size_t)kPrepBlocks * kMomN;
+    double h[4 * kMomN];
+    // feature ranges over the valid rows (Z spans [1, 2])
+    LAUNCH("k_prep_range", k_prep_range, dim3(kPrepBlocks), dim3(256), 0, s, n, feat, logR, part);
+    LAUNCH("k_prep_sum", k_prep_sum, dim3(1), dim3(64), 0, s, kPrepBlocks, 6, part, out, 1);
+    if (hipMemcpyAsync(h, out, sizeof(double) * 6, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AXPIC_E_DEVICE;
+    std::memset(norm, 0, sizeof(*norm));
+    for (int k = 0; k < 3; ++k) {
+        if (!(h[3 + k] > h[k])) return AXPIC_E_DOMAIN;
+        norm->lo[k] = h[k];
+        norm->sc[k] = 2.0 / (h[3 + k] - h[k]);
+    }
+    norm->lo[3] = 1.0; norm->sc[3] = 2.0;
+    const PrepNorm pn = to_prep(norm);
+    for (int c = 0; c < 4; ++c) {
+        LAUNCH("k_prep_moments", k_prep_moments, dim3(kPrepBlocks), dim3(256), 0, s, n, feat, logR,
+               ch, c, pn, part);
+        LAUNCH("k_prep_sum", k_prep_sum, dim3(1), dim3(64), 0, s, kPrepBlocks, kMomN, part,
+               out + c * kMomN, 0);
+    }
+    if (hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AXPIC_E_DEVICE;
+    for (int c = 0; c < 4; ++c) {
+        const double* m = h + c * kMomN;
+        double A[5][5], r[5], x[5];
+        int q = 0;
+        for (int a = 0; a < 5; ++a)
+            for (int b = a; b < 5; ++b) { A[a][b] = A[b][a] = m[q]; ++q; }
+        for (int a = 0; a < 5; ++a) r[a] = m[15 + a];
+        const double cnt = A[0][0];
+        norm->count[c] = (int64_t)std::llround(cnt);
+        if (!(cnt > 5.0)) return AXPIC_E_DOMAIN;
+        double Ac[5][5], rc[5];
+        std::memcpy(Ac, A, sizeof(A)); std::memcpy(rc, r, sizeof(r));
+        if (!solve5(Ac, rc, x)) return AXPIC_E_DOMAIN;
+        norm->mu[c] = x[0];
+        for (int k = 0; k < 4; ++k) norm->lin[c][k] = x[1 + k];
+        // residual e = y - d.x: sum e = r0 - A0.x, sum e^2 = yy - 2 x.r + x.A.x
+        double se = r[0], see = m[20];
+        for (int a = 0; a < 5; ++a) {
+            se -= A[0][a] * x[a];
+            see -= 2.0 * x[a] * r[a];
+            for (int b = 0; b < 5; ++b) see += x[a] * A[a][b] * x[b];
+        }
+        const double var = (see - se * se / cnt) / (cnt - 1.0);
+        // a channel that the affine fit reproduces keeps a residual of rounding noise
+        // only: the floor keeps the network from fitting it
+        norm->sigma[c] = std::max(var > 0.0 ? std::sqrt(var) : 0.0, 1e-3);
+    }
+    return AXPIC_OK;
+}
+
+axpic_status axpic_mlp_design(const double* feat, const double* logR, const int32_t* ch, int64_t n,
+                              const axpic_mlp_norm* norm, float* X, float* Y, void* stream) {
+    if (!norm || n < 0 || (n && (!feat || !logR || !ch || !X || !Y))) return AXPIC_E_INVAL;
+    if (((uintptr_t)X & 15u) != 0) return AXPIC_E_INVAL;
+    if (n == 0) return AXPIC_OK;
+    LAUNCH("k_prep_design", k_prep_design, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S(stream),
+           n, feat, logR, ch, to_prep(norm), X, Y);
+    return launched();
+}
+
+axpic_status axpic_mlp_batch(const float* X, const float* Y, int64_t n, int64_t batch, uint64_t seed,
+                             int64_t step, float* Xb, float* Yb, void* stream) {
+    if (n < 1 || n > 0xFFFFFFFFll || batch < 1 || !X || !Y || !Xb || !Yb) return AXPIC_E_INVAL;
+    if ((((uintptr_t)X | (uintptr_t)Xb) & 15u) != 0) return AXPIC_E_INVAL;
+    LAUNCH("k_prep_batch", k_prep_batch, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0,
+           S(stream), n, X, Y, batch, (uint32_t)seed, (uint32_t)(seed >> 32), step, Xb, Yb);
     return launched();
 }
 

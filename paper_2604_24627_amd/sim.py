@@ -49,6 +49,7 @@ class DeviceSpecies:
     def _alloc(self, cap: int):
         td = _tdtype(self.dtype)
         dev = self.device
+        self._S = None          # the cached C view points at the buffers being replaced
 
         def grow(t, dt_):
             new = torch.zeros(cap, dtype=dt_, device=dev)
@@ -113,16 +114,23 @@ class DeviceSpecies:
         return s
 
     def struct(self) -> B.SpeciesC:
-        S = B.SpeciesC()
-        for d in range(3):
-            S.x[d] = B.ptr(self.x[d])
-            S.p[d] = B.ptr(self.p[d])
-        S.w, S.id, S.cell = B.ptr(self.w), B.ptr(self.id), B.ptr(self.cell)
+        """The C view of the buffer (cached while the buffers, offsets and implicit-id
+        range stay the same; n is refreshed on every call)."""
+        key = (id(self.off), self.n_sorted, self.id0, self.n_implicit, self.w_ref)
+        S = getattr(self, "_S", None)
+        if S is None or self._S_key != key:
+            S = B.SpeciesC()
+            for d in range(3):
+                S.x[d] = B.ptr(self.x[d])
+                S.p[d] = B.ptr(self.p[d])
+            S.w, S.id, S.cell = B.ptr(self.w), B.ptr(self.id), B.ptr(self.cell)
+            S.dtype, S.kind = self.dtype, self.kind
+            S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
+            S.id0, S.n_implicit = self.id0, self.n_implicit
+            S.off, S.n_sorted = ((B.ptr(self.off), self.n_sorted) if self.off is not None
+                                 else (None, 0))
+            self._S, self._S_key = S, key
         S.n, S.capacity = self.n, self.capacity
-        S.dtype, S.kind = self.dtype, self.kind
-        S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
-        S.id0, S.n_implicit = self.id0, self.n_implicit
-        S.off, S.n_sorted = (B.ptr(self.off), self.n_sorted) if self.off is not None else (None, 0)
         return S
 
     def to_numpy(self) -> Dict:
@@ -209,6 +217,7 @@ class AxpicSim:
         # one status record per call
         self.chain = torch.zeros(B.CHAIN_N, dtype=torch.int64, device=dev)
         self.chain_host = torch.zeros(B.CHAIN_N, dtype=torch.int64).pin_memory()
+        self._chain_np = self.chain_host.numpy()
         self.status_ops = torch.zeros((3, B.STATUS_N), dtype=torch.int64, device=dev)
         self._last_new = (0, 0)
         self.grow_ahead = True      # reserve room for twice the previous step's products
@@ -430,8 +439,7 @@ class AxpicSim:
             finally:
                 self.ax.n = n_now
         n_ph0, id0 = self.ph.n, self.next_id
-        self.chain_host.copy_(torch.tensor([self.ax.n, self.ph.n, self.next_id, 0],
-                                           dtype=torch.int64))
+        self._chain_np[:] = (self.ax.n, self.ph.n, self.next_id, 0)
         self.chain.copy_(self.chain_host, non_blocking=True)
         st = self.status_ops
         sh, g, c, prm, ch = self.sh, B.ref(self.grid), B.ref(self.cells), B.ref(self.params), \

@@ -84,6 +84,50 @@ def test_training_samples_match_oracle_labels():
     np.testing.assert_array_equal(f[:, 3], Z)
 
 
+def test_training_set_preparation_matches_numpy():
+    """axpic_mlp_prepare / _design / _batch against the same statistics in numpy on
+    host copies: feature ranges over the finite rows, per-channel least squares
+    (np.linalg.lstsq), residual standard deviations, the design rows with NaN
+    targets for invalid labels, and minibatch rows drawn by the oracle's Philox."""
+    S = Surrogate(I.Params(), seed=2)
+    feat, logR, ch = S.samples(200_000, 7)
+    S.fit_normalisation(feat, logR, ch)
+    f, y, c = feat.cpu().numpy(), logR.cpu().numpy(), ch.cpu().numpy()
+    ok = np.isfinite(y)
+    assert 0 < (~ok).sum() < 0.05 * y.size
+    lo, hi = f[ok].min(axis=0), f[ok].max(axis=0)
+    lo[3], hi[3] = 1.0, 2.0
+    np.testing.assert_array_equal(S.norm["lo"], lo)
+    np.testing.assert_allclose(S.norm["sc"], 2.0 / (hi - lo), rtol=1e-15)
+    fn = (f - S.norm["lo"]) * S.norm["sc"] - 1.0
+    for k in range(4):
+        m = ok & (c == k)
+        D = np.concatenate([np.ones((m.sum(), 1)), fn[m]], axis=1)
+        coef = np.linalg.lstsq(D, y[m], rcond=None)[0]
+        res = y[m] - D @ coef
+        np.testing.assert_allclose(S.norm["mu"][k], coef[0], rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(S.norm["lin"][k], coef[1:], rtol=1e-8, atol=1e-9)
+        assert S.norm["sigma"][k] == pytest.approx(max(res.std(ddof=1), 1e-3), rel=1e-6)
+    X, Y = S.design(feat, logR, ch)
+    Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+    np.testing.assert_array_equal(Xh[:, :4], fn.astype(np.float32))
+    onehot = np.zeros((y.size, 28), np.float32)
+    onehot[np.arange(y.size), c] = 1.0
+    np.testing.assert_array_equal(Xh[:, 4:], onehot)
+    np.testing.assert_array_equal(np.isnan(Yh), ~ok)
+    base = S.norm["mu"][c] + (S.norm["lin"][c] * Xh[:, :4].astype(np.float64)).sum(axis=1)
+    np.testing.assert_allclose(Yh[ok], ((y - base) / S.norm["sigma"][c])[ok], rtol=1e-6, atol=1e-6)
+    Xb = torch.empty((512, 32), dtype=torch.float32, device="cuda")
+    Yb = torch.empty(512, dtype=torch.float32, device="cuda")
+    n = y.size
+    B.check(S.lib.axpic_mlp_batch(B.ptr(X), B.ptr(Y), n, 512, 11, 5, B.ptr(Xb), B.ptr(Yb), S.sh),
+            "mlp_batch")
+    rows = np.array([(int(O.philox([b, 0, 5, 0x4D4C5042], [11, 0])[0]) * n) >> 32
+                     for b in range(512)])
+    np.testing.assert_array_equal(Xb.cpu().numpy(), Xh[rows])
+    np.testing.assert_array_equal(Yb.cpu().numpy(), Yh[rows])
+
+
 def test_mlp_forward_and_gradients_match_fp64_reference():
     S = Surrogate(I.Params(), seed=3)
     X, Y = random_design(512, 9)

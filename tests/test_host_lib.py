@@ -41,6 +41,7 @@ def test_struct_layouts_match_header_sizes():
     # sizes and offsets printed by a C compiler for include/axpic.h (x86-64)
     assert C.sizeof(B.ParamsC) == 224 and C.sizeof(B.CellsC) == 136
     assert C.sizeof(B.MlpC) == 184
+    assert C.sizeof(B.MlpNormC) == 288 and B.MlpNormC.count.offset == 256
     assert B.MlpC.out_lin.offset == 72 and B.MlpC.T_lo.offset == 136
 
 

@@ -213,7 +213,7 @@ def main():
     import torch
     from paper_2604_24627_amd import inputs as I
     from paper_2604_24627_amd import axpic as B
-    from paper_2604_24627_amd import profsum
+    import profsum
     from paper_2604_24627_amd.sim import AxpicSim
 
     wl = workload(a.cells)

@@ -302,7 +302,12 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
  * axions->n axions: thermal absorption (delete with probability P_abs or
  * reduce the weight by it; fb[cell] += (w E, w p)), then a->gamma conversion
  * of what survives (products appended to `photons` with ids as above).
- * pabs_in / lam_in optionally replace the computed P_abs / a->gamma means. */
+ * pabs_in / lam_in optionally replace the computed P_abs / a->gamma means, both
+ * of the axions as they are at the start of the step (what axpic_rates writes).
+ * With weight reduction (absorb_mode 1) an axion converts with the mean of its
+ * reduced weight, i.e. the start-of-step mean times (1 - P_abs) (eq. prim_prob:
+ * the mean is proportional to the parent's weight), taken in FP64 whether the
+ * mean is computed or handed in. */
 axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                           axpic_species* axions, const void* pabs_in, const void* lam_in,
                           int64_t step, uint64_t next_id, axpic_species* photons, double* fb,

@@ -482,8 +482,11 @@ double or_gammainc_P(double a, double y) {
     return sum * exp(-y + a * log(y) - lgamma(a));
 }
 
-/* Regularised upper incomplete gamma Q(a, y): Legendre continued fraction
- * (modified Lentz) for y >= a + 1, otherwise 1 - P.                       */
+/* Regularised upper incomplete gamma Q(a, y): Legendre's continued fraction
+ * for y >= a + 1, evaluated by the modified Lentz algorithm (Lentz, Appl.
+ * Opt. 15 (1976) 668; Thompson and Barnett, J. Comput. Phys. 64 (1986) 490;
+ * as presented in Press et al., Numerical Recipes, Sec. 6.2), otherwise
+ * 1 - P.                                                                   */
 double or_gammainc_Q(double a, double y) {
     if (!(y > 0.0)) return 1.0;
     if (y < a + 1.0) return 1.0 - or_gammainc_P(a, y);
@@ -939,7 +942,7 @@ int64_t or_emit_thermal_cells(const or_grid* g, const or_params* prm, const or_c
 /* Inverse operators on axions (Sec. II.I and Sec. II.F.1): detailed-balance */
 /* absorption for the thermal channels, then a->gamma conversion of what     */
 /* survives.  pabs_in / lam_in optionally replace the computed probability / */
-/* mean.  Products (photons) are written to out.                              */
+/* mean of the start-of-step axion.  Products (photons) are written to out.   */
 /* ------------------------------------------------------------------------ */
 int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
                   or_species* ax, const double* pabs_in, const double* lam_in, int64_t step,
@@ -966,8 +969,9 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
         double E = prm->m_a_keV > 0.0 ? or_axion_energy(prm, p2) : OR_ME_KEV * sqrt(p2);
         uint32_t r[4];
         or_draw(prm->seed, ax->id[i], (uint32_t)step, 4, 0, r);
+        double P = 0.0;
         if (thermal) {
-            double P = pabs_in ? pabs_in[i] : -expm1(-or_gamma_abs(c, prm, E, NULL) * dtp);
+            P = pabs_in ? pabs_in[i] : -expm1(-or_gamma_abs(c, prm, E, NULL) * dtp);
             pab[i] = P;
             if (prm->absorb_mode == 0) {
                 if (or_u53(r[0], r[1]) < P) { dead[i] = 1; w = 0.0; }
@@ -976,6 +980,10 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
             }
         }
         if (a2g && w > 0.0) {
+            /* the mean of the start-of-step weight (eq. prim_prob: lambda is
+             * proportional to the parent's weight); after a weight reduction
+             * (reading O8) the survivor converts with the mean of its reduced
+             * weight, i.e. that mean times (1 - P_abs) */
             double l;
             if (lam_in) l = lam_in[i];
             else {
@@ -983,8 +991,9 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
                                ? prm->prim_inv_ratio * c->G_P0 *
                                      or_F_mass(E, OR_ME_KEV * sqrt(p2), c->kappa2)   /* M3 */
                                : prm->prim_inv_ratio * or_gamma_prim(c, prm, E);
-                l = w * (-expm1(-G * dtp)) / wg;
+                l = ax->w[i] * (-expm1(-G * dtp)) / wg;
             }
+            if (thermal && prm->absorb_mode == 1) l = l * (1.0 - P);
             lam[i] = l;
             double ws; int capped;
             K[i] = or_conversion_count(prm, l, or_cap(l, prm, &ws, &capped), w, wg,

@@ -1021,6 +1021,19 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
 }
 
 // ------------------------------------------------------------------ absorption
+// The a->gamma mean of an axion (Sec. II.F.1, eq. prim_prob): that of its start-of-step
+// weight wt0 (computed, or handed in as lam), times (1 - P_abs) after a weight reduction
+// (reading O8), which is the mean of the reduced weight; FP64 so that the handed-in and
+// the computed forms give the same value.
+template <typename T, bool M>
+__device__ __forceinline__ double ag_mean(const KParams& kp, const T* __restrict__ pc, T lam,
+                                          bool given, T wt0, T p2, double p2d, T P) {
+    double l = given ? (double)lam
+                     : (double)(M ? lambda_ag_m<T>(kp, pc, wt0, p2d) : lambda_ag<T>(kp, pc, wt0, p2));
+    if (kp.absorb_mode == 1) l = l * (1.0 - (double)P);
+    return l;
+}
+
 // Decisions for the thread's run of axions; returns the run's photon total, *act the
 // axions with a nonzero code.
 template <typename T, bool M, bool VEC>
@@ -1051,17 +1064,19 @@ __device__ __forceinline__ uint32_t abs_count_run(
     for (int j = 0; j < kPer; ++j) {
         cdv[j] = 0;
         if (!VEC && i0 + j >= n) continue;
-        T wt = wv[j];
+        const T wt0 = wv[j];
+        T wt = wt0;
         uint32_t cd = 0;
         if (wt > (T)0) {
             const T* pc = pcv[j];
             const T p2 = p2_of<T>(xv[j], yv[j], zv[j]);
             const double p2d = p2_of<double>(xv[j], yv[j], zv[j]);
             const uint4 r = draw(kp, idv[j], step, 4, 0);
+            T P = (T)0;
             if (thermal) {
-                const T P = pabs_in ? Pv[j]
-                                    : (M ? pabs_thermal_m<T>(kp, pc, p2d)
-                                         : pabs_thermal<T>(kp, pc, energy_keV(p2)));
+                P = pabs_in ? Pv[j]
+                            : (M ? pabs_thermal_m<T>(kp, pc, p2d)
+                                 : pabs_thermal<T>(kp, pc, energy_keV(p2)));
                 if (kp.absorb_mode == 0) {
                     // u53 < P is decided by the leading 24 bits of u unless P falls
                     // between their bounds
@@ -1075,18 +1090,17 @@ __device__ __forceinline__ uint32_t abs_count_run(
                 }
             }
             if (a2g && wt > (T)0) {
-                const T l = lam_in ? lv[j]
-                                   : (M ? lambda_ag_m<T>(kp, pc, wt, p2d) : lambda_ag<T>(kp, pc, wt, p2));
+                const double l = ag_mean<T, M>(kp, pc, lam_in ? lv[j] : (T)0, lam_in != nullptr,
+                                               wt0, p2, p2d, thermal ? P : (T)0);
                 // surely heavy with a surely-zero count, or surely light and surely not
                 // converting: no FP64
                 const bool zero =
-                    sizeof(T) == 4 && l > (T)0 &&
+                    sizeof(T) == 4 && l > 0.0 &&
                     (((float)wt >= wt_heavy && poisson_surely_zero((float)l, r.z)) ||
                      ((float)wt < wt_light && light_surely_zero((float)l, prod_ratio, (float)wt, r.z)));
                 if (!zero) {
                     double ws; int cp;
-                    cd |= (uint32_t)conversion_count(kp, (double)l,
-                                                     cap_lambda((double)l, kp.cap, &ws, &cp),
+                    cd |= (uint32_t)conversion_count(kp, l, cap_lambda(l, kp.cap, &ws, &cp),
                                                      (double)wt * w_ref_a, kp.w_gamma_prod,
                                                      u53(r.z, r.w));
                 }
@@ -1168,23 +1182,26 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
         const uint32_t pre = block_excl_scan(K, lds, &segtot);
         const bool live = i < n && w[i] > (T)0;
         if (live && (cd != 0 || (thermal && kp.absorb_mode == 1))) {
-            T wt = w[i];
+            const T wt0 = w[i];
+            T wt = wt0;
             const int32_t c = cell[i];
             const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
             const T pxv = px[i], pyv = py[i], pzv = pz[i];
-            const T p2 = pxv * pxv + pyv * pyv + pzv * pzv;
+            const T p2 = p2_of<T>(pxv, pyv, pzv);
             const double pp = psq_d<T>(px, py, pz, i);
             const double pm = sqrt(pp);
             const double E = M ? axion_energy(kp, pp) : kMe * pm;
             const double eu = M ? E / kMe : pm;                // energy in m_e c^2
             double wphys = w_ref_a * (double)wt;
+            T P = (T)0;
             if (thermal) {
                 double dw = 0.0;
+                if (kp.absorb_mode == 1)
+                    P = pabs_in ? pabs_in[i]
+                                : (M ? pabs_thermal_m<T>(kp, pc, pp)
+                                     : pabs_thermal<T>(kp, pc, energy_keV(p2)));
                 if (cd & 256u) dw = wphys;
                 else if (kp.absorb_mode == 1) {
-                    const T P = pabs_in ? pabs_in[i]
-                                        : (M ? pabs_thermal_m<T>(kp, pc, pp)
-                                             : pabs_thermal<T>(kp, pc, energy_keV(p2)));
                     dw = wphys * (double)P;
                     wt = (T)((wphys - dw) / w_ref_a);
                 }
@@ -1204,10 +1221,10 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                 wphys = w_ref_a * (double)wt;
             }
             if (K > 0) {
-                const T l = lam_in ? lam_in[i]
-                                   : (M ? lambda_ag_m<T>(kp, pc, wt, pp) : lambda_ag<T>(kp, pc, wt, p2));
+                const double l = ag_mean<T, M>(kp, pc, lam_in ? lam_in[i] : (T)0,
+                                               lam_in != nullptr, wt0, p2, pp, P);
                 double ws; int cp;
-                (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+                (void)cap_lambda(l, kp.cap, &ws, &cp);
                 st[5] += cp ? 1.0 : 0.0;
                 double wp = kp.w_gamma_prod * ws;
                 double dep = (double)K * wp;

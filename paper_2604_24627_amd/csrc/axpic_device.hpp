@@ -541,8 +541,9 @@ __device__ __forceinline__ double compton_tail(double x) {
 }
 
 // Upper regularised incomplete gamma Q(k, y) of the Gamma(k, 1) sampler: one minus
-// the power series of P below y = k + 1, the Legendre continued fraction (modified
-// Lentz) above.
+// the power series of P below y = k + 1, above it Legendre's continued fraction by
+// the modified Lentz algorithm (Lentz 1976; Thompson and Barnett 1986; Press et al.,
+// Numerical Recipes, Sec. 6.2).
 __device__ __forceinline__ double gamma_tail(double k, double y) {
     if (!(y > 0.0)) return 1.0;
     const double pre = exp(-y + k * log(y) - lgamma(k));

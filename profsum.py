@@ -3,16 +3,17 @@
 kernel_stats(csv)        -> {kernel: (calls, avg_ns)}   from --kernel-trace --stats
 counters(csv)            -> {kernel: [value per dispatch]} from --pmc <counter>
 source_digest()          -> SHA-256 of the sources the stepping kernels are
-                            compiled from (axpic.hip and its device headers),
+                            compiled from (axpic.hip, its device headers and
+                            include/axpic.h),
                             which names the kernels a set of counters was taken
                             from; traffic lines cover only kernels of that unit
 read_traffic(path)       -> the per-dispatch HBM bytes recorded in a summary,
                             or None when the kernels have changed since
 Kernel names are reduced to the bare function name (k_...).
 
-Usage: python -m paper_2604_24627_amd.profsum <kernel_stats.csv> [<fetch.csv>
+Usage: python profsum.py <kernel_stats.csv> [<fetch.csv>
 <write.csv> <copy_bytes>] -- prints the table;
-python -m paper_2604_24627_amd.profsum --sq <counter_collection.csv> -- per-kernel
+python profsum.py --sq <counter_collection.csv> -- per-kernel
 medians over dispatches of SQ_WAVES and of the other SQ counters per wavefront; the FETCH_SIZE / WRITE_SIZE
 medians (KiB per dispatch) are scaled so that k_stream_copy of copy_bytes reads
 and writes copy_bytes, and a "traffic" line per kernel is printed with the
@@ -27,10 +28,12 @@ import re
 import statistics
 import sys
 
-CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2604_24627_amd", "csrc")
 
-
-STEP_SOURCES = ("axpic.hip", "axpic_device.hpp", "axpic_timing.hpp")
+# the stepping kernels' sources, and the ABI header whose structs they compile against
+STEP_SOURCES = ("axpic.hip", "axpic_device.hpp", "axpic_timing.hpp",
+                os.path.join("..", "..", "include", "axpic.h"))
 
 
 def source_digest(root: str = CSRC) -> str:

@@ -354,3 +354,56 @@ def test_superposed_cell_count_for_means_above_the_inversion_range():
     mean, var = Ns.mean(axis=0), Ns.var(axis=0, ddof=1)
     assert np.all(np.abs(mean - L) <= 6 * np.sqrt(L / 300)), (mean, L)
     assert np.all(np.abs(var - L) <= 6 * np.sqrt((L + 2 * L * L) / 300)), (var, L)
+
+
+def _directions(prod):
+    p = prod["p"]
+    pm = np.sqrt((p ** 2).sum(axis=0))
+    return p / pm, pm
+
+
+@pytest.mark.parametrize("operator", ["particle", "cells"])
+def test_thermal_emission_directions_are_isotropic(operator):
+    """Secs. II.G and II.H draw emission directions isotropically.  Over more than 1e5
+    products of the per-electron operator and of the per-cell superposition: unit
+    directions with |p| = E / m_e c^2; <n_i> = 0 and <n_i n_j> = delta_ij / 3 within
+    five standard errors (Var n_i = 1/3, Var n_i^2 = 4/45, Var n_i n_j = 1/15 for the
+    uniform law on the sphere); cos(theta) uniform on [-1, 1] and phi uniform on
+    [0, 2 pi) by Kolmogorov-Smirnov; cos(theta) uncorrelated with the energy.  A
+    mapping such as cos(theta) = u, or phi over half the circle, fails several of these."""
+    from scipy import stats as S
+    wl, pl = small_plasma(T=3.0, ncell=4, ppc=2048, channels=6, g_ae=1e-13, w_a=1.5e-38,
+                          lambda_cap=math.inf, boost=1.0)
+    sim = O.OracleSim(pl, wl.params)
+    cells = sim.cells()
+    off = pl["species"]["electrons"]["off"]
+    ns, es = [], []
+    s = 0
+    while sum(a.shape[1] for a in ns) < 120_000:
+        if operator == "particle":
+            prod, _, _ = O.emit_thermal(sim.grid, sim.params, cells, sim.el, s, 10 ** 9)
+        else:
+            prod, _, _ = O.emit_thermal_cells(sim.grid, sim.params, cells, sim.el, off, s, 10 ** 9)
+        n, pm = _directions(prod)
+        # the product's momentum magnitude is its sampled energy (massless, Sec. II.B)
+        np.testing.assert_allclose(np.sqrt((n ** 2).sum(axis=0)), 1.0, atol=1e-14)
+        ns.append(n)
+        es.append(pm)
+        s += 1
+        assert s < 40
+    n = np.concatenate(ns, axis=1)
+    E = np.concatenate(es)
+    N = n.shape[1]
+    mean = n.mean(axis=1)
+    assert np.all(np.abs(mean) < 5 * math.sqrt(1.0 / (3 * N))), mean
+    M2 = (n[:, None, :] * n[None, :, :]).mean(axis=2)
+    for i in range(3):
+        assert abs(M2[i, i] - 1.0 / 3.0) < 5 * math.sqrt(4.0 / 45.0 / N), M2
+        for j in range(i + 1, 3):
+            assert abs(M2[i, j]) < 5 * math.sqrt(1.0 / 15.0 / N), M2
+    mu = n[2]
+    phi = np.mod(np.arctan2(n[1], n[0]), 2 * math.pi)
+    assert S.kstest(mu, S.uniform(loc=-1.0, scale=2.0).cdf).pvalue > 1e-4
+    assert S.kstest(phi, S.uniform(loc=0.0, scale=2 * math.pi).cdf).pvalue > 1e-4
+    r = np.corrcoef(mu, E)[0, 1]
+    assert abs(r) < 5 / math.sqrt(N), r

@@ -126,6 +126,7 @@ def _declare(L):
     L.or_axion_energy.restype = _D; L.or_axion_energy.argtypes = [_P, _D]
     L.or_compton_x_above.restype = _D; L.or_compton_x_above.argtypes = [_D, _D]
     L.or_gamma_x_above.restype = _D; L.or_gamma_x_above.argtypes = [_D, _D, _D]
+    L.or_equilibrium.argtypes = [_P, _P, _P, C.c_int64, _P, _D, _P]
     L.or_compton_x_tail.restype = _D; L.or_compton_x_tail.argtypes = [_D]
     L.or_gamma_x_tail.restype = _D; L.or_gamma_x_tail.argtypes = [_D, _D]
 
@@ -448,6 +449,24 @@ def feedback(grid, params, off, el: OSpecies, fb, T, stats=None, moments=None):
     off = np.ascontiguousarray(off, dtype=np.int64)
     L.or_feedback(_ref(G), _ref(P), ncell, _ptr(off), _ref(S), _ptr(fb), _ptr(T), _ptr(stats),
                   _ptr(moments))
+
+
+EQ_FIELDS = ("num", "en", "w2", "neq", "ueq", "nfix", "z")
+
+
+def equilibrium(grid, params, cells, sp: OSpecies, t_steps: float = 0.0) -> Dict:
+    """Equilibrium check of the thermal inverse operators (or_equilibrium): per bin of
+    the histogram grid (nbins bins, then underflow and overflow) the population's
+    number, energy and sum of squared weights, the equilibrium number and energy, the
+    Jacobi-recursion content after t_steps steps (t_steps <= 0: its fixed point) and
+    the residual z = (num - nfix) / sqrt(w2)."""
+    L = load(); G = make_grid(grid); P = make_params(params)
+    nbh = P.hist_nbins + 2
+    out = np.zeros(7 * nbh)
+    c = np.ascontiguousarray(cells)
+    S = sp.struct()
+    L.or_equilibrium(_ref(G), _ref(P), _ptr(c), c.size, _ref(S), float(t_steps), _ptr(out))
+    return {k: out[i * nbh:(i + 1) * nbh].copy() for i, k in enumerate(EQ_FIELDS)}
 
 
 def push(grid, ax: OSpecies, prec32: bool, m_a_keV: float = 0.0):

@@ -1054,6 +1054,133 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Equilibrium check of the thermal inverse operators (Sec. II.I, eq.        */
+/* gamma_abs: the net source vanishes bin by bin at n_eq; the relaxation     */
+/* plateau of Sec. III.E).  For a population s (physical weights) and the    */
+/* histogram grid of prm, per bin k (the nbins bins, then [0, lo) and        */
+/* [hi, inf) as or_hist_bin numbers them):                                   */
+/*   NUM   sum of w over the particles of the bin (w > 0)                     */
+/*   EN    sum of w E [keV]                                                   */
+/*   W2    sum of w^2                                                         */
+/*   NEQ   sum over cells of V int_bin dn_eq/dE dE at the cell's T            */
+/*   UEQ   the same with E dn_eq/dE                                           */
+/*   NFIX  sum over cells of V int_bin dn_eq/dE q(g) (1 - e^{-t g}) dE with   */
+/*         g(E) = Gamma_abs(E) dt_phys over the enabled thermal channels and  */
+/*         q(g) = g / (1 - e^{-g}): the content after t steps of the Jacobi   */
+/*         recursion n_{t+1} = n_t e^{-g} + n_eq g started empty (reading O6; */
+/*         emission per step V n_eq g by construction of Gamma_abs); t <= 0   */
+/*         gives its fixed point n_eq q(g), which tends to n_eq as g -> 0     */
+/*   Z     (NUM - NFIX) / sqrt(W2), 0 where W2 = 0                            */
+/* out is [7][nbins + 2].  dn_eq/dE is that of one axion state, BE or MB     */
+/* (eq_stats); with mass m, E p f(E/T) / (2 pi^2 (hbar c)^3), zero below m.  */
+/* Integrals: composite 10-point Gauss-Legendre on panels no wider than     */
+/* T/16 inside a bin, [0, lo) on the geometric panels [lo 2^-(j+1), lo 2^-j], */
+/* [hi, inf) cut at hi + 64 T; with mass, the panel starting at m is taken   */
+/* in s = sqrt(E - m), which removes the square-root edge of p.              */
+/* ------------------------------------------------------------------------ */
+typedef struct { const or_cell* c; const or_params* prm; double dt, t, V; } or_eq_ctx;
+
+static void or_eq_point(const or_eq_ctx* q, double E, double out[3]) {
+    out[0] = out[1] = out[2] = 0.0;
+    const double m = q->prm->m_a_keV, T = q->c->T;
+    if (!(E > 0.0) || !(T > 0.0) || (m > 0.0 && !(E > m))) return;
+    double neq = or_dneq(E, T, q->prm->eq_stats);
+    if (m > 0.0) neq *= sqrt((E - m) * (E + m)) / E;
+    const double g = or_gamma_abs(q->c, q->prm, E, NULL) * q->dt;
+    const double qg = g > 0.0 ? g / -expm1(-g) : 1.0;
+    const double grow = q->t > 0.0 ? -expm1(-q->t * g) : 1.0;
+    out[0] = q->V * neq;
+    out[1] = q->V * neq * E;
+    out[2] = q->V * neq * qg * grow;
+}
+
+/* 10-point Gauss-Legendre over [a, b]; sub = 1: in s = sqrt(E - a). */
+static void or_eq_panel(const or_eq_ctx* q, double a, double b, int sub, double acc[3]) {
+    double v[3];
+    if (!sub) {
+        const double h = 0.5 * (b - a), mid = 0.5 * (b + a);
+        for (int i = 0; i < 10; ++i) {
+            or_eq_point(q, mid + h * or_gl_x[i], v);
+            for (int k = 0; k < 3; ++k) acc[k] += h * or_gl_w[i] * v[k];
+        }
+        return;
+    }
+    const double S = sqrt(b - a), h = 0.5 * S;
+    for (int i = 0; i < 10; ++i) {
+        const double sx = h + h * or_gl_x[i];
+        or_eq_point(q, a + sx * sx, v);
+        for (int k = 0; k < 3; ++k) acc[k] += h * or_gl_w[i] * v[k] * 2.0 * sx;
+    }
+}
+
+/* [a, b] in panels no wider than hmax, split at the mass m. */
+static void or_eq_range(const or_eq_ctx* q, double a, double b, double hmax, double acc[3]) {
+    const double m = q->prm->m_a_keV;
+    if (m > 0.0) {
+        if (b <= m) return;
+        if (a < m) {
+            const double e = fmin(b, m + hmax);
+            or_eq_panel(q, m, e, 1, acc);
+            a = e;
+        }
+    }
+    if (!(b > a)) return;
+    const int np = (int)ceil((b - a) / hmax);
+    const int n = np < 1 ? 1 : np;
+    for (int j = 0; j < n; ++j)
+        or_eq_panel(q, a + (b - a) * j / n, j + 1 == n ? b : a + (b - a) * (j + 1) / n, 0, acc);
+}
+
+void or_equilibrium(const or_grid* g, const or_params* prm, const or_cell* cells, int64_t ncell,
+                    const or_species* s, double t_steps, double* out) {
+    or_gl_init();
+    const int32_t nb = prm->hist_nbins, nbh = nb + 2;
+    for (int64_t k = 0; k < 7 * (int64_t)nbh; ++k) out[k] = 0.0;
+    double* NUM = out; double* EN = out + nbh; double* W2 = out + 2 * nbh;
+    double* NEQ = out + 3 * nbh; double* UEQ = out + 4 * nbh; double* NFIX = out + 5 * nbh;
+    double* Z = out + 6 * nbh;
+    for (int64_t i = 0; i < s->n; ++i) {
+        const double w = s->w[i];
+        if (!(w > 0.0)) continue;
+        const double p2 = s->p[0][i] * s->p[0][i] + s->p[1][i] * s->p[1][i] + s->p[2][i] * s->p[2][i];
+        const double E = prm->m_a_keV > 0.0 ? or_axion_energy(prm, p2) : OR_ME_KEV * sqrt(p2);
+        const int32_t b = or_hist_bin(prm, E);
+        NUM[b] += w; EN[b] += w * E; W2[b] += w * w;
+    }
+    double* per = (double*)malloc(sizeof(double) * 3 * (size_t)nbh * (size_t)(ncell > 0 ? ncell : 1));
+    const double lo = prm->hist_lo_keV, hi = prm->hist_hi_keV;
+#pragma omp parallel for schedule(dynamic, 4) if (ncell > 16)
+    for (int64_t c = 0; c < ncell; ++c) {
+        or_eq_ctx q = {&cells[c], prm, or_dt_phys(g), t_steps, or_V_cell(g)};
+        const double T = cells[c].T, hmax = T / 16.0;
+        double* r = per + 3 * (size_t)nbh * (size_t)c;
+        for (int32_t k = 0; k < nbh; ++k) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            if (T > 0.0) {
+                if (k < nb) {
+                    double a, b;
+                    if (prm->hist_log) { a = lo * pow(hi / lo, (double)k / nb); b = lo * pow(hi / lo, (double)(k + 1) / nb); }
+                    else { a = lo + (hi - lo) * k / nb; b = lo + (hi - lo) * (k + 1) / nb; }
+                    or_eq_range(&q, a, b, hmax, acc);
+                } else if (k == nb) {
+                    for (int j = 0; j < 60 && lo > 0.0; ++j)
+                        or_eq_range(&q, ldexp(lo, -(j + 1)), ldexp(lo, -j), hmax, acc);
+                } else {
+                    or_eq_range(&q, hi, hi + 64.0 * T, hmax, acc);
+                }
+            }
+            r[3 * k] = acc[0]; r[3 * k + 1] = acc[1]; r[3 * k + 2] = acc[2];
+        }
+    }
+    for (int64_t c = 0; c < ncell; ++c) {
+        const double* r = per + 3 * (size_t)nbh * (size_t)c;
+        for (int32_t k = 0; k < nbh; ++k) { NEQ[k] += r[3 * k]; UEQ[k] += r[3 * k + 1]; NFIX[k] += r[3 * k + 2]; }
+    }
+    free(per);
+    for (int32_t k = 0; k < nbh; ++k) Z[k] = W2[k] > 0.0 ? (NUM[k] - NFIX[k]) / sqrt(W2[k]) : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Conservative feedback: affine momentum remap (Sec. II.J.1, eqs.           */
 /* cell_moments to b_def) and temperature estimate/relaxation (Sec. II.J.2,  */
 /* eqs. Te_est, Te_relax).  Electrons are grouped by cell (off[ncell+1]).    */

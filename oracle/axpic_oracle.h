@@ -128,6 +128,8 @@ double or_gamma_x(double k, double u);
 
 /* ---- diagnostics ---- */
 int32_t or_hist_bin(const or_params* prm, double E_keV);
+void or_equilibrium(const or_grid* g, const or_params* prm, const or_cell* cells, int64_t ncell,
+                    const or_species* s, double t_steps, double* out /* [7][nbins+2] */);
 
 /* ---- operators ---- */
 void or_deposit(const or_species* s, int64_t ncell, double V, double* dens);

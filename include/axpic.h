@@ -336,6 +336,41 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
 axpic_status axpic_diag(const axpic_species* sp, double m_keV, double* out, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* axpic_equilibrium -- the FP64 equilibrium check of the thermal inverse operators
+ * (Sec. II.I, eq. gamma_abs: the net source vanishes energy bin by energy bin at
+ * n_eq; the relaxation plateau of Sec. III.E).  On the histogram grid of prm (nbins
+ * bins, then [0, lo) and [hi, inf) as the power histograms number them) writes
+ * out[AXPIC_EQ_FIELDS][nbins + 2] (device, FP64):
+ *   NUM   sum of w_ref w over the particles of sp in the bin (w > 0)
+ *   EN    sum of w_ref w E [keV]  (E = sqrt(m_e^2 |p|^2 + m^2), m = prm->m_a_keV)
+ *   W2    sum of (w_ref w)^2
+ *   NEQ   sum over cells of V_cell int_bin dn_eq/dE dE: the equilibrium number of one
+ *         axion state at the cell's temperature, BE or MB (prm->eq_stats); with mass,
+ *         dn_eq/dE = E p f(E/T) / (2 pi^2 (hbar c)^3), zero below m
+ *   UEQ   the same with E dn_eq/dE
+ *   NFIX  sum over cells of V_cell int_bin dn_eq/dE q(g) (1 - e^{-t g}) dE, with
+ *         g(E) = Gamma_abs(E) dt_phys of the thermal channels whose absorption
+ *         coefficients axpic_cell_state wrote into cells->pref64 and
+ *         q(g) = g / (1 - e^{-g}): the expected content after t = t_steps steps of
+ *         the recursion n_{t+1} = n_t e^{-g} + n_eq g of operators that each act on
+ *         the start-of-step population, started empty; t_steps <= 0 gives its fixed
+ *         point n_eq q(g), which tends to n_eq as g -> 0
+ *   Z     (NUM - NFIX) / sqrt(W2), 0 where W2 = 0.
+ * Every sum is taken in an order fixed by the data (segments of 4096 particles, chunks
+ * of 256 cells, then the partials in order), so the result does not depend on launch
+ * geometry or scheduling.  Bin integrals: 8-point Gauss-Legendre on panels no wider
+ * than T/16 (the overflow bin cut at hi + 64 T, the underflow bin on geometric panels;
+ * with mass, the part just above m in sqrt(E - m) on geometric panels).
+ * ws: at least axpic_equilibrium_ws_bytes(sp->n, ncell, nbins) bytes of device memory.
+ * AXPIC_E_INVAL for missing arrays, a grid/cell mismatch or a short workspace. */
+#define AXPIC_EQ_FIELDS 7
+enum { AXPIC_EQ_NUM = 0, AXPIC_EQ_EN, AXPIC_EQ_W2, AXPIC_EQ_NEQ, AXPIC_EQ_UEQ, AXPIC_EQ_NFIX,
+       AXPIC_EQ_Z };
+size_t axpic_equilibrium_ws_bytes(int64_t n, int64_t ncell, int32_t nbins);
+axpic_status axpic_equilibrium(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                               const axpic_species* sp, double t_steps, double* out, void* ws,
+                               size_t ws_bytes, void* stream);
+
 /* axpic_sampler_table -- host-only access to the thermal energy samplers'
  * quantile tables (no device work).  which = 0: Compton-like number spectrum
  * x^4/(e^x-1) (Sec. II.G); which = 1: Gamma(k, 1) (Sec. II.H).  out receives

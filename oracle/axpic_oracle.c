@@ -1076,7 +1076,7 @@ int64_t or_absorb(const or_grid* g, const or_params* prm, const or_cell* cells,
 /* Integrals: composite 10-point Gauss-Legendre on panels no wider than     */
 /* T/16 inside a bin, [0, lo) on the geometric panels [lo 2^-(j+1), lo 2^-j], */
 /* [hi, inf) cut at hi + 64 T; with mass, the panel starting at m is taken   */
-/* in s = sqrt(E - m), which removes the square-root edge of p.              */
+/* in s = sqrt(E - m) (the square-root edge of p) on geometric panels.       */
 /* ------------------------------------------------------------------------ */
 typedef struct { const or_cell* c; const or_params* prm; double dt, t, V; } or_eq_ctx;
 
@@ -1094,33 +1094,37 @@ static void or_eq_point(const or_eq_ctx* q, double E, double out[3]) {
     out[2] = q->V * neq * qg * grow;
 }
 
-/* 10-point Gauss-Legendre over [a, b]; sub = 1: in s = sqrt(E - a). */
-static void or_eq_panel(const or_eq_ctx* q, double a, double b, int sub, double acc[3]) {
+/* 10-point Gauss-Legendre over [a, b]. */
+static void or_eq_panel(const or_eq_ctx* q, double a, double b, double acc[3]) {
     double v[3];
-    if (!sub) {
-        const double h = 0.5 * (b - a), mid = 0.5 * (b + a);
-        for (int i = 0; i < 10; ++i) {
-            or_eq_point(q, mid + h * or_gl_x[i], v);
-            for (int k = 0; k < 3; ++k) acc[k] += h * or_gl_w[i] * v[k];
-        }
-        return;
-    }
-    const double S = sqrt(b - a), h = 0.5 * S;
+    const double h = 0.5 * (b - a), mid = 0.5 * (b + a);
     for (int i = 0; i < 10; ++i) {
-        const double sx = h + h * or_gl_x[i];
-        or_eq_point(q, a + sx * sx, v);
+        or_eq_point(q, mid + h * or_gl_x[i], v);
+        for (int k = 0; k < 3; ++k) acc[k] += h * or_gl_w[i] * v[k];
+    }
+}
+
+/* The same over E = m + s^2, s in [s0, s1]. */
+static void or_eq_panel_s(const or_eq_ctx* q, double m, double s0, double s1, double acc[3]) {
+    double v[3];
+    const double h = 0.5 * (s1 - s0), mid = 0.5 * (s1 + s0);
+    for (int i = 0; i < 10; ++i) {
+        const double sx = mid + h * or_gl_x[i];
+        or_eq_point(q, m + sx * sx, v);
         for (int k = 0; k < 3; ++k) acc[k] += h * or_gl_w[i] * v[k] * 2.0 * sx;
     }
 }
 
-/* [a, b] in panels no wider than hmax, split at the mass m. */
+/* [a, b] in panels no wider than hmax, split at the mass m; the panel starting at m
+ * is taken in s = sqrt(E - m) on the geometric panels [S 2^-(j+1), S 2^-j], which
+ * resolve the growth of Gamma_abs ~ E/p towards the threshold. */
 static void or_eq_range(const or_eq_ctx* q, double a, double b, double hmax, double acc[3]) {
     const double m = q->prm->m_a_keV;
     if (m > 0.0) {
         if (b <= m) return;
         if (a < m) {
-            const double e = fmin(b, m + hmax);
-            or_eq_panel(q, m, e, 1, acc);
+            const double e = fmin(b, m + hmax), S = sqrt(e - m);
+            for (int j = 0; j < 48; ++j) or_eq_panel_s(q, m, ldexp(S, -(j + 1)), ldexp(S, -j), acc);
             a = e;
         }
     }
@@ -1128,7 +1132,7 @@ static void or_eq_range(const or_eq_ctx* q, double a, double b, double hmax, dou
     const int np = (int)ceil((b - a) / hmax);
     const int n = np < 1 ? 1 : np;
     for (int j = 0; j < n; ++j)
-        or_eq_panel(q, a + (b - a) * j / n, j + 1 == n ? b : a + (b - a) * (j + 1) / n, 0, acc);
+        or_eq_panel(q, a + (b - a) * j / n, j + 1 == n ? b : a + (b - a) * (j + 1) / n, acc);
 }
 
 void or_equilibrium(const or_grid* g, const or_params* prm, const or_cell* cells, int64_t ncell,

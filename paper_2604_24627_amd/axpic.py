@@ -80,7 +80,8 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
            "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table",
            "axpic_mlp_prepare_ws_bytes", "axpic_mlp_prepare", "axpic_mlp_design",
-           "axpic_mlp_batch"]
+           "axpic_mlp_batch", "axpic_equilibrium_ws_bytes", "axpic_equilibrium"]
+EQ_FIELDS = ("num", "en", "w2", "neq", "ueq", "nfix", "z")
 MLP_PARAMS = 57888
 MLP_BLOB_BYTES = 112704
 TAB_MAX_NODES = 64
@@ -152,6 +153,7 @@ def load(path: Optional[str] = None):
         ("axpic_mlp_prepare", [_P, _P, _P, C.c_int64, _P, C.c_size_t, _P, _P]),
         ("axpic_mlp_design", [_P, _P, _P, C.c_int64, _P, _P, _P, _P]),
         ("axpic_mlp_batch", [_P, _P, C.c_int64, C.c_int64, C.c_uint64, C.c_int64, _P, _P, _P]),
+        ("axpic_equilibrium", [_P, _P, _P, _P, C.c_double, _P, _P, C.c_size_t, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32
@@ -161,6 +163,8 @@ def load(path: Optional[str] = None):
     L.axpic_mlp_prepare_ws_bytes.argtypes = []
     L.axpic_mlp_train_ws_bytes.restype = C.c_size_t
     L.axpic_mlp_train_ws_bytes.argtypes = [C.c_int64]
+    L.axpic_equilibrium_ws_bytes.restype = C.c_size_t
+    L.axpic_equilibrium_ws_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32]
     L.axpic_timing_enable.restype = None
     L.axpic_timing_enable.argtypes = [C.c_int32]
     _lib = L

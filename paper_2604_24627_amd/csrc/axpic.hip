@@ -1684,6 +1684,180 @@ k_diag_final(int64_t nb, const double* __restrict__ part, double* __restrict__ o
 }
 
 
+// ------------------------------------------------------------------ equilibrium check
+// The FP64 equilibrium check of the thermal inverse operators (Sec. II.I, eq.
+// gamma_abs; the relaxation plateau of Sec. III.E), in an order fixed by the data:
+// the population columns are summed per segment of kEqSeg particles by one wavefront
+// (64 particles at a time; equal bins grouped by ballot and summed by one butterfly,
+// added into the segment's LDS histogram in particle order), the reference columns per
+// chunk of kEqCells cells (one thread per cell and bin, a fixed tree over the chunk),
+// and the partials of the segments and chunks in their order.
+constexpr int kEqSeg = 4096;
+constexpr int kEqCells = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_eq_pop(int64_t n, KParams kp, double w_ref, const T* __restrict__ w, const T* __restrict__ px,
+         const T* __restrict__ py, const T* __restrict__ pz, double* __restrict__ part) {
+    extern __shared__ double h[];                       // [3][nbh]
+    const int lane = threadIdx.x, nbh = kp.nbins + 2;
+    for (int k = lane; k < 3 * nbh; k += 64) h[k] = 0.0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kEqSeg;
+    for (int it = 0; it < kEqSeg / 64; ++it) {
+        const int64_t i = base + (int64_t)it * 64 + lane;
+        if (!__any(i < n)) break;
+        double wp = 0.0, E = 0.0;
+        int bin = -1;
+        if (i < n) {
+            wp = w_ref * (double)w[i];
+            if (wp > 0.0) {
+                const double pp = psq_d<T>(px, py, pz, i);
+                E = kp.massive ? axion_energy(kp, pp) : kMe * sqrt(pp);
+                bin = hist_bin(kp, E);
+            }
+        }
+        uint64_t todo = __ballot(bin >= 0);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int b = __shfl(bin, leader, 64);
+            const bool mine = bin == b;
+            const uint64_t mask = __ballot(mine);
+            const double s0 = wave_sum(mine ? wp : 0.0);
+            const double s1 = wave_sum(mine ? wp * E : 0.0);
+            const double s2 = wave_sum(mine ? wp * wp : 0.0);
+            if (lane == 0) { h[b] += s0; h[nbh + b] += s1; h[2 * nbh + b] += s2; }
+            todo &= ~mask;
+        }
+    }
+    __syncthreads();
+    double* out = part + (int64_t)blockIdx.x * 3 * nbh;
+    for (int k = lane; k < 3 * nbh; k += 64) out[k] = h[k];
+}
+
+// 8-point Gauss-Legendre nodes and weights on [-1, 1] (Abramowitz and Stegun, Table 25.4)
+__constant__ double kGL8x[4] = {0.1834346424956498049, 0.5255324099163289858,
+                                0.7966664774136267396, 0.9602898564975362317};
+__constant__ double kGL8w[4] = {0.3626837833783619830, 0.3137066458778872873,
+                                0.2223810344533744706, 0.1012285362903762591};
+
+struct EqCell {
+    double T, c6, c7, V, t;
+    // (V dn_eq/dE, V E dn_eq/dE, V dn_eq/dE q(g) (1 - e^{-t g})) at energy E
+    __device__ void point(const KParams& kp, double E, double* v) const {
+        v[0] = v[1] = v[2] = 0.0;
+        if (!(E > 0.0) || (kp.massive && !(E > kp.m_a))) return;
+        const double x = E / T;
+        const double hc3 = kHbarcKeVcm * kHbarcKeVcm * kHbarcKeVcm;
+        double dn = E * E / (2.0 * kPi * kPi * hc3) * (kp.eq_stats ? exp(-x) : 1.0 / expm1(x));
+        double g = gabs_dt(kp, T, c6, c7, E);
+        if (kp.massive) {              // E p instead of E^2; Gamma_abs gains E/p
+            const double pr = sqrt((E - kp.m_a) * (E + kp.m_a));
+            dn *= pr / E;
+            g *= E / pr;
+        }
+        const double q = g > 0.0 ? g / -expm1(-g) : 1.0;
+        const double grow = t > 0.0 ? -expm1(-t * g) : 1.0;
+        v[0] = V * dn; v[1] = V * dn * E; v[2] = V * dn * q * grow;
+    }
+    // Gauss-Legendre over u in [a, b]; sub: the energy is m + u^2 (the square-root edge
+    // of p at the mass), with the Jacobian 2u
+    __device__ void panel(const KParams& kp, double a, double b, bool sub, double* acc) const {
+        double v[3];
+        const double h = 0.5 * (b - a), mid = 0.5 * (a + b);
+        for (int q = 0; q < 8; ++q) {
+            const double xi = (q & 1) ? kGL8x[q >> 1] : -kGL8x[q >> 1];
+            const double u = mid + h * xi;
+            const double wq = h * kGL8w[q >> 1];
+            if (sub) {
+                point(kp, kp.m_a + u * u, v);
+                for (int k = 0; k < 3; ++k) acc[k] += wq * v[k] * 2.0 * u;
+            } else {
+                point(kp, u, v);
+                for (int k = 0; k < 3; ++k) acc[k] += wq * v[k];
+            }
+        }
+    }
+    // [a, b] in panels no wider than hmax, split at the mass; the panel from the mass
+    // in u = sqrt(E - m) on geometric panels [S 2^-(j+1), S 2^-j] (Gamma_abs grows like
+    // E/p towards the threshold)
+    __device__ void range(const KParams& kp, double a, double b, double hmax, double* acc) const {
+        if (kp.massive) {
+            if (!(b > kp.m_a)) return;
+            if (a < kp.m_a) {
+                const double e = fmin(b, kp.m_a + hmax), S = sqrt(e - kp.m_a);
+                for (int j = 0; j < 48; ++j) panel(kp, ldexp(S, -(j + 1)), ldexp(S, -j), true, acc);
+                a = e;
+            }
+        }
+        if (!(b > a)) return;
+        const int np = (int)ceil((b - a) / hmax);
+        const int nn = np < 1 ? 1 : np;
+        for (int j = 0; j < nn; ++j)
+            panel(kp, a + (b - a) * j / nn, j + 1 == nn ? b : a + (b - a) * (j + 1) / nn, false, acc);
+    }
+};
+
+__global__ void __launch_bounds__(kEqCells)
+k_eq_ref(int64_t ncell, KParams kp, const double* __restrict__ p64, double V, double t_steps,
+         double lo, double hi, double* __restrict__ part) {
+    __shared__ double red[3][kEqCells / 64];
+    const int k = blockIdx.y, nb = kp.nbins;
+    const int64_t c = (int64_t)blockIdx.x * kEqCells + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (c < ncell) {
+        const double* pc = p64 + c * AXPIC_PREF_N;
+        const EqCell q{pc[0], pc[6], pc[7], V, t_steps};
+        if (q.T > 0.0) {
+            const double hmax = q.T / 16.0;
+            if (k < nb) {
+                double a, b;
+                if (kp.hist_log) {
+                    a = lo * pow(hi / lo, (double)k / nb);
+                    b = lo * pow(hi / lo, (double)(k + 1) / nb);
+                } else {
+                    a = lo + (hi - lo) * k / nb;
+                    b = lo + (hi - lo) * (k + 1) / nb;
+                }
+                q.range(kp, a, b, hmax, acc);
+            } else if (k == nb) {
+                for (int j = 0; j < 60 && lo > 0.0; ++j)
+                    q.range(kp, ldexp(lo, -(j + 1)), ldexp(lo, -j), hmax, acc);
+            } else {
+                q.range(kp, hi, hi + 64.0 * q.T, hmax, acc);
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < 3; ++j) {
+        const double s = wave_sum(acc[j]);
+        if (lane == 0) red[j][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* out = part + ((int64_t)k * gridDim.x + blockIdx.x) * 3;
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int v = 0; v < kEqCells / 64; ++v) s += red[j][v];
+            out[j] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_eq_final(int nbh, int64_t nseg, int64_t nchunk, const double* __restrict__ pop,
+           const double* __restrict__ ref, double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbh) return;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t sg = 0; sg < nseg; ++sg)
+        for (int j = 0; j < 3; ++j) v[j] += pop[(sg * 3 + j) * nbh + k];
+    for (int64_t ch = 0; ch < nchunk; ++ch)
+        for (int j = 0; j < 3; ++j) v[3 + j] += ref[((int64_t)k * nchunk + ch) * 3 + j];
+    for (int j = 0; j < 6; ++j) out[(int64_t)j * nbh + k] = v[j];
+    out[(int64_t)6 * nbh + k] = v[2] > 0.0 ? (v[0] - v[5]) / sqrt(v[2]) : 0.0;
+}
+
 // ------------------------------------------------------------------ copy calibration
 __global__ void __launch_bounds__(kThreads)
 k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
@@ -2223,6 +2397,49 @@ axpic_status axpic_diag(const axpic_species* sp, double m_keV, double* out, void
                            sp->w_ref, mu2, (const double*)sp->w, (const double*)sp->p[0],
                            (const double*)sp->p[1], (const double*)sp->p[2], part);
     LAUNCH("k_diag_final", k_diag_final, dim3(1), dim3(64), 0, s, nb, part, out);
+    return launched();
+}
+
+size_t axpic_equilibrium_ws_bytes(int64_t n, int64_t ncell, int32_t nbins) {
+    if (n < 0 || ncell < 0 || nbins < 1) return 0;
+    const int64_t nbh = nbins + 2;
+    const int64_t nseg = std::max<int64_t>((n + kEqSeg - 1) / kEqSeg, 1);
+    const int64_t nchunk = std::max<int64_t>((ncell + kEqCells - 1) / kEqCells, 1);
+    return align256(sizeof(double) * (size_t)(nseg * 3 * nbh)) +
+           align256(sizeof(double) * (size_t)(nchunk * 3 * nbh));
+}
+
+axpic_status axpic_equilibrium(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
+                               const axpic_species* sp, double t_steps, double* out, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!grid_ok(g) || !params_ok(prm) || !cells || !out || !species_ok(sp, true))
+        return AXPIC_E_INVAL;
+    if (cells->ncell != ncell_of(g) || !cells->pref64) return AXPIC_E_INVAL;
+    if (!(t_steps == t_steps)) return AXPIC_E_INVAL;
+    const int64_t n = sp->n, ncell = cells->ncell;
+    const int nbh = prm->hist_nbins + 2;
+    if (!ws || ws_bytes < axpic_equilibrium_ws_bytes(n, ncell, prm->hist_nbins)) return AXPIC_E_INVAL;
+    const int64_t nseg = std::max<int64_t>((n + kEqSeg - 1) / kEqSeg, 1);
+    const int64_t nchunk = std::max<int64_t>((ncell + kEqCells - 1) / kEqCells, 1);
+    if (nchunk > 2147483647 || nseg > 2147483647) return AXPIC_E_INVAL;
+    double* pop = (double*)ws;
+    double* ref = (double*)((char*)ws + align256(sizeof(double) * (size_t)(nseg * 3 * nbh)));
+    KParams kp = make_kparams(g, prm, cells->w_ref_g);
+    const double L = g->dx * kC / g->omega0;
+    hipStream_t s = S(stream);
+    const size_t shm = sizeof(double) * 3 * (size_t)nbh;
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_eq_pop", k_eq_pop<float>, dim3((unsigned)nseg), dim3(64), shm, s, n, kp, sp->w_ref,
+               (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
+               (const float*)sp->p[2], pop);
+    else
+        LAUNCH("k_eq_pop", k_eq_pop<double>, dim3((unsigned)nseg), dim3(64), shm, s, n, kp, sp->w_ref,
+               (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],
+               (const double*)sp->p[2], pop);
+    LAUNCH("k_eq_ref", k_eq_ref, dim3((unsigned)nchunk, (unsigned)nbh), dim3(kEqCells), 0, s, ncell,
+           kp, cells->pref64, L * L * L, t_steps, prm->hist_lo_keV, prm->hist_hi_keV, ref);
+    LAUNCH("k_eq_final", k_eq_final, grid1(nbh), dim3(kThreads), 0, s, nbh, nseg, nchunk, pop, ref,
+           out);
     return launched();
 }
 

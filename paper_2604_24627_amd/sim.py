@@ -393,6 +393,27 @@ class AxpicSim:
         v = self.diag_out.cpu().tolist()
         return dict(N_a=v[0], U_a=v[1])
 
+    def equilibrium(self, t_steps: float = 0.0, sp: Optional[DeviceSpecies] = None) -> Dict:
+        """The library's FP64 equilibrium check (axpic_equilibrium) of the axions (or of
+        `sp`) at the current temperature field (the cell state is recomputed first): per
+        histogram bin the population's number, energy and sum of squared weights, the
+        equilibrium number and energy, the recursion content after t_steps steps (<= 0:
+        its fixed point) and the residual z; arrays of nbins + 2 (underflow, overflow
+        last)."""
+        sp = self.ax if sp is None else sp
+        self.cell_state()
+        nbh = self.pdict["hist_nbins"] + 2
+        out = torch.zeros(7 * nbh, dtype=torch.float64, device=self.device)
+        need = int(self.lib.axpic_equilibrium_ws_bytes(sp.n, self.ncell,
+                                                       self.pdict["hist_nbins"]))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        B.check(self.lib.axpic_equilibrium(B.ref(self.grid), B.ref(self.cells),
+                                           B.ref(self.params), B.ref(sp.struct()),
+                                           float(t_steps), B.ptr(out), B.ptr(ws), ws.numel(),
+                                           self.sh), "equilibrium")
+        v = out.cpu().numpy()
+        return {k: v[i * nbh:(i + 1) * nbh].copy() for i, k in enumerate(B.EQ_FIELDS)}
+
     # -------------------------------------------------------------- one step
     def step(self):
         """One time step.  The appending calls are chained on the device (counts and the

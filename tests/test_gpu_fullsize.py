@@ -404,8 +404,20 @@ def test_relaxation_full_size_reaches_blackbody_and_conserves_energy(ratio):
         if s % 100 == 0:
             Ee, Eg, Ea, Na = _energy(g)
             T = g.T.double()
-            Neq = float((T ** 3).sum()) * ZETA3 / (math.pi ** 2 * HBARC ** 3) * V_cell
-            Ueq = float((T ** 4).sum()) * math.pi ** 2 / (30.0 * HBARC ** 3) * V_cell
+            # the library's FP64 equilibrium check at the evolved temperature field; its
+            # totals are the one-state blackbody zeta(3) T^3/pi^2, pi^2 T^4/30 per cell
+            eq = g.equilibrium(t_steps=s)
+            Neq, Ueq = float(eq["neq"].sum()), float(eq["ueq"].sum())
+            assert Neq == pytest.approx(float((T ** 3).sum()) * ZETA3 /
+                                        (math.pi ** 2 * HBARC ** 3) * V_cell, rel=1e-7)
+            assert Ueq == pytest.approx(float((T ** 4).sum()) * math.pi ** 2 /
+                                        (30.0 * HBARC ** 3) * V_cell, rel=1e-7)
+            assert float(eq["num"].sum()) == pytest.approx(Na, rel=1e-9)
+            if s == steps:
+                band = (eq["nfix"] > 1e-3 * eq["nfix"].max())
+                band[-2:] = False
+                log(f"step {s}: per-bin axion number / recursion content "
+                    f"{np.round(eq['num'][band] / eq['nfix'][band], 3)}")
             d = g.diag()
             rec.append((s, Na / Neq, Ea / Ueq, (Ee + Eg + Ea) / E0 - 1.0, Na))
             log(f"step {s}: N_a/N_eq {Na / Neq:.4f}, U_a/U_eq {Ea / Ueq:.4f}, "

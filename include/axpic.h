@@ -69,7 +69,8 @@ typedef enum {
     AXPIC_E_CAPACITY = -2,
     AXPIC_E_DOMAIN = -3,
     AXPIC_E_DEVICE = -4,
-    AXPIC_E_UNSUPPORTED = -5
+    AXPIC_E_UNSUPPORTED = -5,
+    AXPIC_E_SCRATCH = -6       /* input larger than an allocation-free call's static scratch */
 } axpic_status;
 
 /* status[1] flag bits */
@@ -335,6 +336,18 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
  * E = sqrt(m_e^2 |p|^2 + m^2) for particles of rest mass m_keV (0: massless). */
 axpic_status axpic_diag(const axpic_species* sp, double m_keV, double* out, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* axpic_diag_noalloc -- axpic_diag without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and the same result, bit for bit, with the
+ * per-block partial sums in a static device array of the library (4 MiB per GPU, held
+ * until the process ends).  It allocates and frees nothing.  Limit: at most 2^28
+ * particles (262144 blocks of 1024); a larger species returns AXPIC_E_SCRATCH before
+ * any launch.  The array is shared by every call on that GPU and keeps the last call's
+ * partials: calls that overlap on one GPU (on different streams) race and must be
+ * ordered by the caller.  The first call on a device looks up the array's address on
+ * that device. */
+axpic_status axpic_diag_noalloc(const axpic_species* sp, double m_keV, double* out, void* stream);
 
 /* axpic_equilibrium -- the FP64 equilibrium check of the thermal inverse operators
  * (Sec. II.I, eq. gamma_abs: the net source vanishes energy bin by energy bin at

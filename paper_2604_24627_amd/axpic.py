@@ -26,7 +26,7 @@ ST_NAMES = ["events_P", "events_C", "events_B", "num_P", "num_C", "num_B", "en_P
 ST = {n: i for i, n in enumerate(ST_NAMES)}
 ST_COUNT = len(ST_NAMES)
 STATUS_MSG = {0: "ok", -1: "invalid argument", -2: "capacity", -3: "domain", -4: "device",
-              -5: "unsupported"}
+              -5: "unsupported", -6: "input exceeds the static scratch"}
 
 
 class AxpicError(RuntimeError):
@@ -80,7 +80,8 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
            "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table",
            "axpic_mlp_prepare_ws_bytes", "axpic_mlp_prepare", "axpic_mlp_design",
-           "axpic_mlp_batch", "axpic_equilibrium_ws_bytes", "axpic_equilibrium"]
+           "axpic_mlp_batch", "axpic_equilibrium_ws_bytes", "axpic_equilibrium",
+           "axpic_diag_noalloc"]
 EQ_FIELDS = ("num", "en", "w2", "neq", "ueq", "nfix", "z")
 MLP_PARAMS = 57888
 MLP_BLOB_BYTES = 112704
@@ -154,6 +155,7 @@ def load(path: Optional[str] = None):
         ("axpic_mlp_design", [_P, _P, _P, C.c_int64, _P, _P, _P, _P]),
         ("axpic_mlp_batch", [_P, _P, C.c_int64, C.c_int64, C.c_uint64, C.c_int64, _P, _P, _P]),
         ("axpic_equilibrium", [_P, _P, _P, _P, C.c_double, _P, _P, C.c_size_t, _P]),
+        ("axpic_diag_noalloc", [_P, C.c_double, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32

@@ -46,6 +46,14 @@ constexpr int kEventBlocks = 1024;     // grid of the event kernels (grid-stride
 __device__ double g_tab_compton[2 * (kTabN + 1)];
 __device__ double g_tab_gamma[2 * (kTabN + 1)];
 
+// Static device scratch of the allocation-free entry point axpic_diag_noalloc: the
+// per-block partial sums (N, U) of the population, kDiagScratchPairs blocks of
+// kBlockParents particles at most.  Each GPU holds its own copy until the process ends;
+// host code uses only the address that hipGetSymbolAddress returns for the current
+// device, never this name.
+constexpr int64_t kDiagScratchPairs = 262144;                  // 4 MiB, 2^28 particles
+static __device__ __align__(256) double scratch[2 * kDiagScratchPairs];
+
 // ------------------------------------------------------------------ workspace
 struct Workspace {
     uint16_t* code;      // [n_max]
@@ -2081,6 +2089,7 @@ const char* axpic_status_string(int32_t s) {
     case AXPIC_E_DOMAIN: return "value outside the model's domain";
     case AXPIC_E_DEVICE: return "HIP launch or runtime failure";
     case AXPIC_E_UNSUPPORTED: return "unsupported configuration";
+    case AXPIC_E_SCRATCH: return "input exceeds the static scratch of an allocation-free call";
     default: return "unknown status";
     }
 }
@@ -2440,6 +2449,42 @@ axpic_status axpic_equilibrium(const axpic_grid* g, const axpic_cells* cells, co
            kp, cells->pref64, L * L * L, t_steps, prm->hist_lo_keV, prm->hist_hi_keV, ref);
     LAUNCH("k_eq_final", k_eq_final, grid1(nbh), dim3(kThreads), 0, s, nbh, nseg, nchunk, pop, ref,
            out);
+    return launched();
+}
+
+axpic_status axpic_diag_noalloc(const axpic_species* sp, double m_keV, double* out, void* stream) {
+    if (!species_ok(sp, true) || !out || !(m_keV >= 0.0)) return AXPIC_E_INVAL;
+    const int64_t nb = nblocks_for(std::max<int64_t>(sp->n, 1));
+    if (nb > kDiagScratchPairs) return AXPIC_E_SCRATCH;
+    double* part = nullptr;
+    {
+        // the scratch array's device address on the current device, looked up once
+        static std::mutex mu;
+        static std::vector<double*> addr;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return AXPIC_E_DEVICE;
+        std::lock_guard<std::mutex> lock(mu);
+        if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+        if (!addr[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+                return AXPIC_E_DEVICE;
+            addr[dev] = (double*)ptr;
+        }
+        part = addr[dev];
+    }
+    const double mu2 = (m_keV / kMe) * (m_keV / kMe);
+    hipStream_t s = S(stream);
+    // every partial the final sum reads is written first by its block: nothing to clear
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_diag_partial", k_diag_partial<float>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
+               sp->w_ref, mu2, (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
+               (const float*)sp->p[2], part);
+    else
+        LAUNCH("k_diag_partial", k_diag_partial<double>, dim3((unsigned)nb), dim3(kThreads), 0, s, sp->n,
+               sp->w_ref, mu2, (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],
+               (const double*)sp->p[2], part);
+    LAUNCH("k_diag_final", k_diag_final, dim3(1), dim3(64), 0, s, nb, part, out);
     return launched();
 }
 

@@ -130,3 +130,22 @@ def test_table_entries_reject_invalid_arguments_on_host():
                                100.0, 0.01, tab.ctypes.data, None, None, None) == -1
     assert L.axpic_rates_table(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), B.PRIMAKOFF, 2,
                                0.01, 100.0, tab.ctypes.data, None, None, None) == -1
+
+
+def test_allocation_free_diag_rejects_species_beyond_its_scratch_on_host():
+    """axpic_diag_noalloc holds its partial sums in a static device array of 2^18
+    blocks of 1024 particles: a larger species is refused before any HIP call (the
+    array pointers below are host memory and are never dereferenced)."""
+    L = B.load()
+    buf = np.zeros(4, np.float32)
+    out = np.zeros(2)
+    sp = B.SpeciesC()
+    for d in range(3):
+        sp.p[d] = buf.ctypes.data
+    sp.w, sp.cell = buf.ctypes.data, buf.ctypes.data
+    sp.dtype, sp.kind = B.F32, B.AXION
+    sp.n = sp.capacity = sp.n_implicit = (1 << 28) + 1
+    assert L.axpic_diag_noalloc(B.ref(sp), 0.0, out.ctypes.data, None) == -6
+    assert L.axpic_status_string(-6).startswith(b"input exceeds the static scratch")
+    assert L.axpic_diag_noalloc(B.ref(sp), -1.0, out.ctypes.data, None) == -1
+    assert L.axpic_diag_noalloc(B.ref(sp), 0.0, None, None) == -1

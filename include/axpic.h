@@ -466,14 +466,21 @@ size_t axpic_mlp_blob_bytes(void);
 size_t axpic_mlp_train_ws_bytes(int64_t batch);
 /* Pack FP32 master parameters into the inference blob (rounding to bf16). */
 axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream);
+/* Arithmetic of the training calls: AXPIC_MLP_BF16 rounds every matrix-product operand
+ * (weights, layer inputs, back-propagated gradients) to bfloat16 and accumulates in FP32
+ * on the matrix cores (the training mode); AXPIC_MLP_F32 keeps FP32 throughout (the
+ * mode in which gradients are checked at FP32 accuracy). */
+#define AXPIC_MLP_BF16 0
+#define AXPIC_MLP_F32 1
 /* Training forward pass: X [batch][32] (features in columns 0..7, zeros after),
  * y [batch] (may be NULL); activations are kept in ws for axpic_mlp_loss_grad. */
-axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, void* ws,
-                               size_t ws_bytes, float* y, void* stream);
+axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, int32_t precision,
+                               void* ws, size_t ws_bytes, float* y, void* stream);
 /* Mean squared error of y against Y and its gradient (AXPIC_MLP_PARAMS floats);
  * rows whose target is NaN contribute neither (the mean still divides by batch). */
 axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const float* Y, int64_t batch,
-                                 void* ws, size_t ws_bytes, float* grad, double* loss, void* stream);
+                                 int32_t precision, void* ws, size_t ws_bytes, float* grad,
+                                 double* loss, void* stream);
 /* Adam step on the FP32 master parameters (step counts from 1). */
 axpic_status axpic_mlp_adam(float* master, const float* grad, float* m, float* v, int64_t step,
                             float lr, float beta1, float beta2, float eps, void* stream);

@@ -4,11 +4,14 @@ The surrogate is a multilayer perceptron 8 -> 128 -> 128 -> 128 -> 128 -> 1
 with hard-swish activations h(z) = z * clip(z/6 + 1/2, 0, 1) on the four
 hidden layers.  Parameters are W_l [in x out] and b_l [out]; the forward
 pass is z_l = h_{l-1} W_l + b_l.
-`quantize=True` emulates the GPU kernels' storage precision: the weights and
-every layer input are rounded to bfloat16 (round to nearest even) before the
-product, accumulation and activations stay in higher precision.  Gradients
-are plain back-propagation of the mean-squared error (rounding treated as the
-identity, as in the GPU backward pass).
+`quantize=True` emulates the bfloat16 training arithmetic: every operand of a
+matrix product is rounded to bfloat16 (round to nearest even) -- the weights and
+every layer input in the forward pass, and in the backward pass also the
+back-propagated gradient dZ of each layer before it multiplies the layer input
+(weight gradient) and the weights (input gradient); accumulation, activations
+and the bias gradients (sums of the unrounded dZ) stay in higher precision.
+Gradients are back-propagation of the mean-squared error with the rounding
+treated as the identity.
 
 Training data: features (log(omega/T), log(kappa/T), log n_e, Z, channel
 one-hot) and labels log R, R = Gamma/g^2 from the oracle's rates (Primakoff
@@ -84,10 +87,11 @@ def loss_and_grads(P, X, Y, quantize=False):
         hin, Wq, z = cache[l]
         if l < 4:
             dz = dz * dact(z)
-        gW = hin.T @ dz
+        dzq = to_bf16(dz) if quantize else dz
+        gW = hin.T @ dzq
         gb = dz.sum(axis=0)
         grads[l] = [gW, gb]
-        dz = dz @ Wq.T
+        dz = dzq @ Wq.T
     return loss, grads
 
 

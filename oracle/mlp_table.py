@@ -150,3 +150,60 @@ def table_rates(tables, x_range, mode, T_cell, cell, omega_keV, w, params, dt_ph
         r[~(np.asarray(w)[idx] > 0)] = 0.0
         rate[idx] = r
     return rate, use
+
+
+def particle_rates(P, norm, box, cells, Z, nion, params, mode, cell, omega_keV, w, dt_phys,
+                   units, quantize=True):
+    """Per-particle rates of the surrogate without tables, in FP64 (the reference of the
+    library's per-particle inference): for each particle the features come from its
+    energy omega and its cell's record (T, kappa2, n_e; Z of the single ion species),
+    log R from the network, and
+
+    mode 0 (photons):        lambda = w units["P"] (1 - exp(-g_agg^2 B R_P dt));
+    mode 2 (axions, a->g):   lambda = w units["ag"] (1 - exp(-r g_agg^2 B R_P dt));
+    mode 1 (axions):         P_abs = 1 - exp(-g_ae^2 B sum_c f_c R_c dt) over the enabled
+                             thermal channels (f_c as in the tables' slot 1),
+    B the boost, r = prim_inv_ratio; w <= 0 gives 0.  Returns (rates, inside): a
+    particle whose cell lies outside the training box (T, n_e, one ion species of
+    charge 1 or 2) or whose omega/T lies outside box["x"] has inside False and rate
+    NaN (the caller's plain rate applies there)."""
+    cell = np.asarray(cell, dtype=np.int64)
+    T = np.asarray(cells["T"], dtype=np.float64)[cell]
+    ne = np.asarray(cells["n_e"], dtype=np.float64)[cell]
+    k2 = np.asarray(cells["kappa2"], dtype=np.float64)[cell]
+    om = np.asarray(omega_keV, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    x = om / T
+    inside = ((nion == 1) & (Z in (1.0, 2.0)) & (T >= box["T"][0]) & (T <= box["T"][1]) &
+              (ne >= box["ne"][0]) & (ne <= box["ne"][1]) & (x >= box["x"][0]) &
+              (x <= box["x"][1]))
+    rate = np.full(om.size, np.nan)
+    idx = np.nonzero(inside)[0]
+    if idx.size == 0:
+        return rate, inside
+    with np.errstate(divide="ignore"):
+        feat = np.stack([np.log(x[idx]), 0.5 * np.log(k2[idx]) - np.log(T[idx]), np.log(ne[idx]),
+                         np.full(idx.size, float(Z))], axis=1)
+    B = params["boost"]
+    if mode in (0, 2):
+        R = np.exp(log_rate(P, norm, feat, 0, quantize))
+        G = params["g_agg_GeV"] ** 2 * B * R * dt_phys
+        if mode == 0:
+            r = w[idx] * units["P"] * -np.expm1(-G)
+        else:
+            r = w[idx] * units["ag"] * -np.expm1(-params["prim_inv_ratio"] * G)
+    else:
+        on = [(params["channels"] & 2) != 0, (params["channels"] & 4) != 0,
+              (params["channels"] & 4) != 0 and bool(params["brems_ee"])]
+        rho = np.asarray(cells["rho"], dtype=np.float64)[cell][idx]
+        XH = np.asarray(cells["XH"], dtype=np.float64)[cell][idx]
+        tot = np.zeros(idx.size)
+        for ch in (1, 2, 3):
+            if not on[ch - 1]:
+                continue
+            f = 1.0 if ch == 1 else screening_factor(T[idx], rho, XH, ch == 3)
+            tot += f * np.exp(log_rate(P, norm, feat, ch, quantize))
+        r = -np.expm1(-params["g_ae"] ** 2 * B * tot * dt_phys)
+    r[~(w[idx] > 0)] = 0.0
+    rate[idx] = r
+    return rate, inside

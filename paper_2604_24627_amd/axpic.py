@@ -84,6 +84,7 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_diag_noalloc"]
 EQ_FIELDS = ("num", "en", "w2", "neq", "ueq", "nfix", "z")
 MLP_PARAMS = 57888
+MLP_BF16, MLP_F32 = 0, 1
 MLP_BLOB_BYTES = 112704
 TAB_MAX_NODES = 64
 
@@ -138,8 +139,8 @@ def load(path: Optional[str] = None):
         ("axpic_timing_read", [C.c_char_p, C.c_size_t]),
         ("axpic_stream_copy", [_P, _P, C.c_size_t, _P]),
         ("axpic_mlp_pack", [_P, _P, _P]),
-        ("axpic_mlp_forward", [_P, _P, C.c_int64, _P, C.c_size_t, _P, _P]),
-        ("axpic_mlp_loss_grad", [_P, _P, _P, C.c_int64, _P, C.c_size_t, _P, _P, _P]),
+        ("axpic_mlp_forward", [_P, _P, C.c_int64, C.c_int32, _P, C.c_size_t, _P, _P]),
+        ("axpic_mlp_loss_grad", [_P, _P, _P, C.c_int64, C.c_int32, _P, C.c_size_t, _P, _P, _P]),
         ("axpic_mlp_adam", [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                             _P]),
         ("axpic_rates_mlp", [_P, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),

@@ -100,6 +100,31 @@ k_gemm_bf16(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_
     for (int r = 0; r < 4; ++r) C[(tm * 16 + 4 * g + r) * ldc + n] = acc[r] + bv;
 }
 
+// The same product in FP32 throughout (the training calls' FP32-weight mode, for
+// gradient checks at FP32 accuracy): 16 x 16 output tiles per workgroup of 256
+// threads, 16-deep slices of op(A) and op(B) staged in LDS, one fused multiply-add
+// per k in increasing k order.
+__global__ void __launch_bounds__(256)
+k_gemm_f32(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_t lda, int transA,
+           const float* __restrict__ B, int64_t ldb, int transB, float* __restrict__ C,
+           int64_t ldc, const float* __restrict__ bias) {
+    __shared__ float As[16][17], Bs[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t m = (int64_t)blockIdx.y * 16 + ty, n = (int64_t)blockIdx.x * 16 + tx;
+    float acc = 0.0f;
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        // As[ty][tx] = op(A)(m, k0 + tx), Bs[ty][tx] = op(B)(k0 + ty, n)
+        const int64_t ka = k0 + tx, kb = k0 + ty;
+        As[ty][tx] = transA ? A[ka * lda + m] : A[m * lda + ka];
+        Bs[ty][tx] = transB ? B[n * ldb + kb] : B[kb * ldb + n];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc = fmaf(As[ty][k], Bs[k][tx], acc);
+        __syncthreads();
+    }
+    C[m * ldc + n] = acc + (bias ? bias[n] : 0.0f);
+}
+
 __global__ void __launch_bounds__(256)
 k_act_fwd(int64_t n, const float* __restrict__ Z, float* __restrict__ H) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -897,10 +922,15 @@ axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream) {
     return launched();
 }
 
-static void gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int tA, const float* B,
-                 int64_t ldb, int tB, float* C, int64_t ldc, const float* bias, hipStream_t s) {
-    LAUNCH("k_gemm_bf16", k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0, s, M,
-                       N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
+static void gemm(int prec, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int tA,
+                 const float* B, int64_t ldb, int tB, float* C, int64_t ldc, const float* bias,
+                 hipStream_t s) {
+    if (prec == AXPIC_MLP_F32)
+        LAUNCH("k_gemm_f32", k_gemm_f32, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(256), 0,
+               s, M, N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
+    else
+        LAUNCH("k_gemm_bf16", k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0,
+               s, M, N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
 }
 
 struct TrainWs {
@@ -922,16 +952,17 @@ static TrainWs carve_train(void* ws, int64_t Bn) {
 
 /* Forward pass with saved activations (training layout): X [B][32] (features in
  * columns 0..7), y[b] = Z5[b][0]. */
-axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, void* ws,
-                               size_t ws_bytes, float* y, void* stream) {
+axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batch, int32_t precision,
+                               void* ws, size_t ws_bytes, float* y, void* stream) {
     if (!master || !X || !ws || batch <= 0 || batch % 32 || ws_bytes < axpic_mlp_train_ws_bytes(batch))
         return AXPIC_E_INVAL;
+    if (precision != AXPIC_MLP_BF16 && precision != AXPIC_MLP_F32) return AXPIC_E_INVAL;
     hipStream_t s = S(stream);
     TrainWs t = carve_train(ws, batch);
     const float* hin = X;
     for (int l = 1; l <= 5; ++l) {
-        gemm(batch, dOut(l), dIn(l), hin, dIn(l), 0, master + offW(l), dOut(l), 0, t.Z[l], dOut(l),
-             master + offB(l), s);
+        gemm(precision, batch, dOut(l), dIn(l), hin, dIn(l), 0, master + offW(l), dOut(l), 0, t.Z[l],
+             dOut(l), master + offB(l), s);
         if (l <= 4) {
             const int64_t n = batch * kDH;
             LAUNCH("k_act_fwd", k_act_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
@@ -948,10 +979,10 @@ axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batc
 /* Mean-squared-error loss and its gradient with respect to the FP32 master
  * parameters (padded layout, AXPIC_MLP_PARAMS floats) for a batch X, Y. */
 axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const float* Y, int64_t batch,
-                                 void* ws, size_t ws_bytes, float* grad, double* loss,
-                                 void* stream) {
+                                 int32_t precision, void* ws, size_t ws_bytes, float* grad,
+                                 double* loss, void* stream) {
     if (!Y || !grad) return AXPIC_E_INVAL;
-    axpic_status st = axpic_mlp_forward(master, X, batch, ws, ws_bytes, nullptr, stream);
+    axpic_status st = axpic_mlp_forward(master, X, batch, precision, ws, ws_bytes, nullptr, stream);
     if (st != AXPIC_OK) return st;
     hipStream_t s = S(stream);
     TrainWs t = carve_train(ws, batch);
@@ -963,15 +994,15 @@ axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const floa
     for (int l = 5; l >= 1; --l) {
         const float* hin = l == 1 ? X : t.H[l - 1];
         // weight gradient: hin^T dZ
-        gemm(dIn(l), dOut(l), batch, hin, dIn(l), 1, dZ, dOut(l), 0, grad + offW(l), dOut(l),
-             nullptr, s);
+        gemm(precision, dIn(l), dOut(l), batch, hin, dIn(l), 1, dZ, dOut(l), 0, grad + offW(l),
+             dOut(l), nullptr, s);
         LAUNCH("k_colsum", k_colsum, dim3((unsigned)dOut(l)), dim3(256), 0, s, batch,
                            (int64_t)dOut(l), dZ, grad + offB(l));
         if (l == 1) break;
         // dH_{l-1} = dZ W^T, then through the activation
         float* dst = (dZ == t.dZ) ? t.dH : t.dZ;
-        gemm(batch, dIn(l), dOut(l), dZ, dOut(l), 0, master + offW(l), dOut(l), 1, dst, dIn(l),
-             nullptr, s);
+        gemm(precision, batch, dIn(l), dOut(l), dZ, dOut(l), 0, master + offW(l), dOut(l), 1, dst,
+             dIn(l), nullptr, s);
         const int64_t n = batch * kDH;
         LAUNCH("k_act_bwd", k_act_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                            t.Z[l - 1], dst);

@@ -33,6 +33,8 @@ from paper_2604_24627_amd import axpic as B  # noqa: E402
 from paper_2604_24627_amd.sim import AxpicSim  # noqa: E402
 from paper_2604_24627_amd.surrogate import Surrogate, init_master  # noqa: E402
 
+ME = 510.99895              # m_e c^2 [keV]
+
 
 def np64(t):
     return t.detach().cpu().numpy().astype(np.float64)
@@ -128,26 +130,47 @@ def test_training_set_preparation_matches_numpy():
     np.testing.assert_array_equal(Yb.cpu().numpy(), Yh[rows])
 
 
-def test_mlp_forward_and_gradients_match_fp64_reference():
+@pytest.mark.parametrize("precision", ["bf16", "f32"])
+def test_mlp_forward_and_gradients_match_fp64_reference(precision):
+    """Forward pass, loss and every gradient entry against the FP64 reference
+    (oracle/mlp.py, whose back-propagation is pinned by central differences).
+    FP32-weight mode: no rounding on either side; each entry within 1e-3 relative,
+    with a floor of 1e-4 of the tensor's largest entry (an entry that is a sum of
+    512 terms cancelling to a small value carries the FP32 rounding of the terms,
+    ~1e-6 of the tensor's scale).  BF16 mode: the reference rounds every product
+    operand where the kernels do (weights, layer inputs, back-propagated gradients);
+    each entry within 1e-2 relative with a floor of 1e-2 of the tensor's largest
+    (FP32 against FP64 values can round to neighbouring bfloat16 numbers)."""
     S = Surrogate(I.Params(), seed=3)
     X, Y = random_design(512, 9)
     Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
-    y = S.forward(Xt).cpu().numpy().astype(np.float64)
+    prec = B.MLP_F32 if precision == "f32" else B.MLP_BF16
+    q = precision == "bf16"
+    y = S.forward(Xt, precision=prec).cpu().numpy().astype(np.float64)
     P = unpad(S.master.cpu().numpy())
-    yref, _ = M.forward(P, X[:, :8].astype(np.float64), quantize=True)
-    assert np.max(np.abs(y - yref)) < 2e-2 * (1 + np.abs(yref).max())
-    assert np.mean(np.abs(y - yref)) < 2e-3
-    g, loss = S.loss_grad(Xt, Yt)
+    yref, _ = M.forward(P, X[:, :8].astype(np.float64), quantize=q)
+    if q:
+        assert np.max(np.abs(y - yref)) < 2e-2 * (1 + np.abs(yref).max())
+        assert np.mean(np.abs(y - yref)) < 2e-3
+    else:
+        np.testing.assert_allclose(y, yref, rtol=1e-4, atol=1e-5 * np.abs(yref).max())
+    g, loss = S.loss_grad(Xt, Yt, precision=prec)
     torch.cuda.synchronize()
     lref, gref = M.loss_and_grads(P, X[:, :8].astype(np.float64), Y.astype(np.float64),
-                                  quantize=True)
-    assert float(loss.item()) == pytest.approx(lref, rel=2e-2)
+                                  quantize=q)
+    assert float(loss.item()) == pytest.approx(lref, rel=2e-2 if q else 1e-5)
     G = grads_unpad(g.cpu().numpy())
+    rtol, floor = (1e-2, 1e-2) if q else (1e-3, 1e-4)
+    worst = 0.0
     for l in range(5):
         for k in range(2):
             a, b = G[l][k], gref[l][k]
-            err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-            assert err < 2e-2, (l, k, err)
+            scale = np.abs(b).max()
+            err = np.abs(a - b) / (np.abs(b) + floor * scale)
+            worst = max(worst, float(err.max()))
+            assert err.max() < rtol, (precision, l, k, float(err.max()))
+    print(f"[surrogate] {precision} gradients: largest entry error {worst:.2e} "
+          f"(bar {rtol:g})", flush=True)
     # padded entries carry no gradient
     gfull = g.cpu().numpy()
     assert np.all(gfull[8 * 128: 32 * 128] == 0.0)
@@ -246,8 +269,13 @@ def test_surrogate_power_within_one_percent_and_gain_reported(trained):
         return e0.elapsed_time(e1) / reps
     tp = timed(lambda: g.rates(g.ph, B.PRIMAKOFF))
     tm = timed(lambda: S.rates(g, g.ph, B.PRIMAKOFF))
+    gain = tp / tm
     print(f"[surrogate] photon rates: plain {tp * 1e3:.1f} us, surrogate {tm * 1e3:.1f} us "
-          f"for {g.ph.n} photons; gain (plain/surrogate time) {tp / tm:.3f}", flush=True)
+          f"for {g.ph.n} photons; gain (plain/surrogate time) {gain:.3f}", flush=True)
+    # per particle the network (~1e5 FLOP on the matrix cores) costs more than the closed
+    # forms (~1e2 vector instructions), so the gain is below one; the floor guards the
+    # inference kernel against a slowdown of more than 20x against the plain rates
+    assert 0.05 < gain < 1.0, gain
 
 
 def test_out_of_box_particles_use_the_plain_rate(trained):
@@ -270,6 +298,143 @@ def test_out_of_box_particles_use_the_plain_rate(trained):
         np.testing.assert_array_equal(a_mlp.cpu().numpy(), a_plain.cpu().numpy())
 
 
+# ------------------------------------------------------------ per-particle inference
+
+def _seeded_net(seed=3):
+    """A seeded network with nonzero biases and hand-set normalisation (binary32 values):
+    the oracle's parameter list, its normalisation dict, and the library's Surrogate
+    holding the same weights."""
+    rng = np.random.default_rng(seed)
+    P = M.init_params(seed)
+    for W, b in P:
+        W[:] = W.astype(np.float32)
+        b[:] = rng.normal(0, 0.1, b.size).astype(np.float32)
+    f32 = lambda a: [float(np.float32(v)) for v in a]
+    norm_o = dict(feat_lo=f32([math.log(0.01), -3.0, math.log(1e23), 1.0]),
+                  feat_sc=f32([2.0 / math.log(1e4), 0.5, 2.0 / math.log(1e3), 2.0]),
+                  out_mu=f32([-40.0, -20.0, -22.0, -24.0]), out_sigma=f32([1.5, 2.0, 1.0, 0.5]),
+                  out_lin=f32(rng.normal(0, 1, 16)))
+    S = Surrogate(I.Params(), seed=seed)
+    S.master.copy_(torch.from_numpy(pad(P)))
+    S.norm = dict(lo=norm_o["feat_lo"], sc=norm_o["feat_sc"], mu=norm_o["out_mu"],
+                  sigma=norm_o["out_sigma"],
+                  lin=np.asarray(norm_o["out_lin"]).reshape(4, 4).tolist())
+    S.pack()
+    return S, P, norm_o
+
+
+def _interleave(p):
+    """Momenta of every fourth particle scaled down by 1e3 and of every fourth (offset 3)
+    up by 40: omega/T leaves the training range [0.01, 100] for most of them, so the
+    lanes of each wavefront alternate between the network and the plain rate."""
+    p = np.array(p, copy=True)
+    p[:, 1::4] *= 1e-3
+    p[:, 3::4] *= 40.0
+    return p
+
+
+def _check_particle_rates(got, plain, ref, inside, n_fb, what, dtype):
+    """got: the library's rates; plain: its plain rates; ref, inside: the oracle's
+    (compared where the oracle's value is a normal number of the storage type)."""
+    assert 0 < inside.sum() < inside.size
+    assert n_fb == int((~inside).sum()), (n_fb, int((~inside).sum()))
+    np.testing.assert_array_equal(got[~inside], plain[~inside])
+    gi, ri = got[inside], ref[inside]
+    tiny = np.finfo(np.float32 if dtype == "f32" else np.float64).tiny
+    np.testing.assert_array_equal(gi == 0.0, ri == 0.0)
+    pos = ri > 16 * tiny
+    assert pos.mean() > 0.9
+    d = np.abs(np.log(gi[pos]) - np.log(ri[pos]))
+    print(f"[surrogate] inference {what}: {int(inside.sum())} network lanes, "
+          f"{int((~inside).sum())} plain; |d log rate| median {np.median(d):.2e} "
+          f"max {d.max():.2e}", flush=True)
+    return d
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_inference_kernel_matches_oracle_network(dtype):
+    """axpic_rates_mlp against the oracle's FP64 network with the same bfloat16 rounding
+    points (oracle/mlp_table.particle_rates) on a seeded network: photons (lambda_P) and
+    a seeded axion population (thermal P_abs summed over Compton-like, e-Z and e-e
+    brems; a->gamma means), in a plasma graded from 0.3 keV (cells below the 0.5 keV
+    edge of the box) to 6 keV, with lanes inside and outside the omega/T range
+    alternating within every wavefront and a ragged last wavefront.  Lanes outside the
+    box carry exactly the plain rate, and their count is the oracle's; inside it,
+    |d log rate| is held to the bfloat16 bar of the forward pass (median < 2e-3 and
+    maximum < 0.1 of the largest output scale)."""
+    S, P, norm_o = _seeded_net()
+    # a->gamma products light enough (w_a / w_gamma_prod = 1e20) that this network's
+    # conversion means lie in binary32's normal range
+    p = I.Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=7, inverse=1, w_a=1e-36, boost=1e33,
+                 lambda_cap=1.0, brems_ee=1, prim_inv_ratio=0.7, w_gamma_prod=1e-56)
+    wl = I.Workload("inf", ndim=2, n=(24, 9), ppc=23, dtype=dtype, T_keV=0.3, T_keV_hi=6.0,
+                    n_e=6e25, n_ref=6e25, params=p)
+    pl = I.make_plasma(wl, 6)
+    ph = pl["species"]["photons"]
+    ph["p"] = _interleave(ph["p"]).astype(ph["p"].dtype)
+    assert ph["n"] % 64 != 0
+    print(f"[surrogate] inference workload n={wl.n} ppc={wl.ppc} dtype={dtype}", flush=True)
+    g = AxpicSim(pl, wl.params)
+    o = O.OracleSim(pl, wl.params, prec32=(dtype == "f32"))
+    cells = o.cells()
+    dtp = O.dt_phys(o.grid)
+    units = dict(P=g.ph.w_ref / (o.params["w_a"] * o.params["wa_mul"][0]),
+                 ag=o.params["w_a"] / o.params["w_gamma_prod"])
+    axd = I.make_axions(wl, pl, 10.0, seed=21)
+    axd["p"] = _interleave(axd["p"]).astype(axd["p"].dtype)
+    g.load_axions(axd)
+    assert axd["n"] % 64 != 0
+    smax = max(norm_o["out_sigma"])
+    for sp, d, ch, mode in ((g.ph, ph, B.PRIMAKOFF, 0), (g.ax, axd, B.COMPTON | B.BREMS, 1),
+                            (g.ax, axd, B.PRIMAKOFF, 2)):
+        fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        got = np64(S.rates(g, sp, ch, fallback=fb))
+        plain = np64(g.rates(sp, ch))
+        torch.cuda.synchronize()
+        om = ME * np.sqrt((d["p"].astype(np.float64) ** 2).sum(axis=0))
+        w = d["w"].astype(np.float64)
+        ref, inside = MT.particle_rates(P, norm_o, S.box, cells, 1.0, 1, o.params, mode,
+                                        d["cell"], om, w, dtp, units)
+        dd = _check_particle_rates(got, plain, ref, inside, int(fb.item()), f"mode {mode}",
+                                   dtype)
+        assert np.median(dd) < 2e-3 * smax and dd.max() < 0.1 * smax
+
+
+def test_inference_kernel_full_size_sampled_photons():
+    """One launch over the 16.8 M photons of the 512^2 forward plasma (64 per cell, the
+    benchmark's launch), seeded network: the photons of a seeded sample of cells against
+    the oracle's network at the bfloat16 bar, every lane inside the box."""
+    from test_gpu_fullsize import Sample, pick_cells
+    S, P, norm_o = _seeded_net(5)
+    wl = I.config2()
+    pl = I.make_plasma_device(wl, 0)
+    g = AxpicSim(pl, wl.params)
+    sel = pick_cells(wl.ncell, 48, seed=9, must=(0, wl.ncell - 1))
+    Smp = Sample(pl, wl.params, sel)
+    del pl
+    fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    got = S.rates(g, g.ph, B.PRIMAKOFF, fallback=fb)
+    torch.cuda.synchronize()
+    print(f"[surrogate] full-size inference over {g.ph.n} photons, "
+          f"{int(fb.item())} plain", flush=True)
+    mine = np64(got[torch.from_numpy(Smp.idx["photons"]).cuda()])
+    plain = np64(g.rates(g.ph, B.PRIMAKOFF)[torch.from_numpy(Smp.idx["photons"]).cuda()])
+    om = ME * np.sqrt((Smp.ph.p ** 2).sum(axis=0))
+    units = dict(P=g.ph.w_ref / (wl.params.w_a * wl.params.wa_mul[0]), ag=1.0)
+    ref, inside = MT.particle_rates(P, norm_o, S.box, Smp.cells, 1.0, 1, Smp.params, 0,
+                                    Smp.ph.cell, om, Smp.ph.w / g.ph.w_ref,
+                                    O.dt_phys(Smp.grid), units)
+    assert inside.mean() > 0.99
+    n_out = int((~inside).sum())
+    np.testing.assert_array_equal(mine[~inside], plain[~inside])
+    pos = ref > 0
+    d = np.abs(np.log(mine[inside & pos]) - np.log(ref[inside & pos]))
+    smax = max(norm_o["out_sigma"])
+    print(f"[surrogate] full-size sample: {mine.size} photons ({n_out} plain), |d log rate| "
+          f"median {np.median(d):.2e} max {d.max():.2e}", flush=True)
+    assert np.median(d) < 2e-3 * smax and d.max() < 0.1 * smax
+
+
 # ------------------------------------------------------------ per-cell tables
 
 def pad(P):
@@ -288,22 +453,7 @@ def pad(P):
 def _table_setup(seed=3):
     """A seeded network with nonzero biases, hand-set normalisation (binary32 values),
     and a 2D plasma graded in T from 0.3 keV (below the box) to 6 keV."""
-    rng = np.random.default_rng(seed)
-    P = M.init_params(seed)
-    for W, b in P:
-        W[:] = W.astype(np.float32)
-        b[:] = rng.normal(0, 0.1, b.size).astype(np.float32)
-    f32 = lambda a: [float(np.float32(v)) for v in a]
-    norm_o = dict(feat_lo=f32([math.log(0.01), -3.0, math.log(1e23), 1.0]),
-                  feat_sc=f32([2.0 / math.log(1e4), 0.5, 2.0 / math.log(1e3), 2.0]),
-                  out_mu=f32([-40.0, -20.0, -22.0, -24.0]), out_sigma=f32([1.5, 2.0, 1.0, 0.5]),
-                  out_lin=f32(rng.normal(0, 1, 16)))
-    S = Surrogate(I.Params(), seed=seed)
-    S.master.copy_(torch.from_numpy(pad(P)))
-    S.norm = dict(lo=norm_o["feat_lo"], sc=norm_o["feat_sc"], mu=norm_o["out_mu"],
-                  sigma=norm_o["out_sigma"],
-                  lin=np.asarray(norm_o["out_lin"]).reshape(4, 4).tolist())
-    S.pack()
+    S, P, norm_o = _seeded_net(seed)
     p = I.Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=7, inverse=1, w_a=1e-36, boost=1e33,
                  lambda_cap=1.0)
     wl = I.Workload("tab", ndim=2, n=(24, 8), ppc=24, dtype="f32", T_keV=0.3, T_keV_hi=6.0,

@@ -251,3 +251,82 @@ def test_table_rates_at_nodes_equal_the_plain_rates():
     _, use = T.table_rates(tab, box["x"], 0, cells["T"], np.array([0, 1]),
                            np.array([0.005, 101.0]) * cells["T"], np.ones(2), p, dtp, units)
     assert not use.any()
+
+
+def test_particle_rates_of_an_exact_affine_target_equal_the_plain_rate():
+    """The Compton-like detailed-balance target with Bose-Einstein equilibrium is exactly
+    affine in the features (Gamma_abs proportional to E^2, eq. gamma_abs with the number
+    spectrum x^4/(e^x - 1)): its least-squares fit over the box, with a network whose
+    output is zero, reproduces the oracle's plain absorption probability for every
+    particle -- a pin of the per-particle features, the de-normalisation and the
+    conversion to P_abs that does not depend on any network."""
+    import oracle.mlp_table as T
+    base = I.Params()
+    n = 4000
+    Ts, ne, Z, x, ch = I.surrogate_samples(n, 8)
+    Z[:] = 1.0
+    ch[:] = 1
+    logR, lk = M.labels(base, Ts, ne, Z, x, ch)
+    feat = np.stack([np.log(x), lk, np.log(ne), Z], axis=1)
+    lo = np.array([math.log(0.01), feat[:, 1].min(), math.log(1e23), 1.0])
+    sc = np.array([2.0 / math.log(1e4), 2.0 / np.ptp(feat[:, 1]), 2.0 / math.log(1e3), 2.0])
+    f = (feat - lo) * sc - 1.0
+    D = np.concatenate([np.ones((n, 1)), f[:, :3]], axis=1)
+    coef, *_ = np.linalg.lstsq(D, logR, rcond=None)
+    assert np.abs(D @ coef - logR).max() < 1e-9             # exactly affine
+    P = M.init_params(0)
+    for W, b in P:
+        W[:] = 0.0
+        b[:] = 0.0
+    norm = dict(feat_lo=lo, feat_sc=sc, out_mu=[0.0, coef[0], 0.0, 0.0], out_sigma=[1.0] * 4,
+                out_lin=np.concatenate([np.zeros(4), coef[1:], [0.0], np.zeros(8)]))
+    box = dict(T=(0.5, 10.0), ne=(1e23, 1e26), x=(0.01, 100.0))
+    p = dict(I.Params(g_ae=1e-13, boost=3e33, channels=2, inverse=1).as_dict())
+    wl = I.Workload("t", ndim=1, n=(3,), ppc=8, dtype="f64", T_keV=2.0, n_e=6e25, params=I.Params())
+    grid = wl.grid()
+    dtp = O.dt_phys(grid)
+    cells = O.cell_state(grid, p, np.array([1.0, 3.0, 7.0]), np.array([3e23, 6e25, 5e25]),
+                         [np.array([3e23, 6e25, 5e25])], [1.0], [1.0])
+    rng = np.random.default_rng(3)
+    cell = rng.integers(0, 3, 300)
+    om = np.exp(rng.uniform(math.log(0.02), math.log(50.0), 300)) * cells["T"][cell]
+    w = rng.uniform(0.5, 2.0, 300)
+    w[::17] = 0.0
+    r, inside = T.particle_rates(P, norm, box, cells, 1.0, 1, p, 1, cell, om, w, dtp,
+                                 dict(P=1.0, ag=1.0), quantize=False)
+    assert inside.all()
+    ref = np.array([-math.expm1(-O.gamma_abs(cells[c], p, e)[0] * dtp) for c, e in zip(cell, om)])
+    ref[~(w > 0)] = 0.0
+    np.testing.assert_allclose(r, ref, rtol=1e-9, atol=0)
+    # outside the box: no surrogate rate
+    r, inside = T.particle_rates(P, norm, box, cells, 1.0, 1, p, 1, np.array([0, 0]),
+                                 np.array([0.005, 150.0]) * cells["T"][0], np.ones(2), dtp,
+                                 dict(P=1.0, ag=1.0))
+    assert not inside.any() and np.all(np.isnan(r))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_particle_rates_equal_the_table_rates_at_the_nodes(mode):
+    """A particle sitting on a node of its cell's table gets the same rate from the
+    per-particle path as from the table (the cubic reproduces node values)."""
+    import oracle.mlp_table as T
+    P, norm, box = _random_net(4)
+    p = dict(I.Params(g_agg_GeV=1e-10, g_ae=1e-13, boost=3e33, channels=7, inverse=1, w_a=1e-36,
+                      prim_inv_ratio=0.7, brems_ee=1).as_dict())
+    wl = I.Workload("t", ndim=1, n=(3,), ppc=8, dtype="f64", T_keV=3.0, n_e=6e25, params=I.Params())
+    grid = wl.grid()
+    dtp = O.dt_phys(grid)
+    cells = O.cell_state(grid, p, np.array([1.5, 3.0, 6.0]), np.array([2e24, 6e25, 1e25]),
+                         [np.array([2e24, 6e25, 1e25])], [1.0], [1.0])
+    nodes = 11
+    tab = T.cell_tables(P, norm, box, cells, 1.0, 1, p, nodes, x_range=(0.05, 30.0))
+    u0, h = T.grid(0.05, 30.0, nodes)
+    j = np.arange(1, nodes - 1)
+    cell = np.repeat([0, 1, 2], j.size)
+    om = np.exp(u0 + h * np.tile(j, 3)) * cells["T"][cell]
+    w = np.linspace(0.5, 2.0, cell.size)
+    units = dict(P=2.5e33, ag=0.02)
+    a, ia = T.particle_rates(P, norm, box, cells, 1.0, 1, p, mode, cell, om, w, dtp, units)
+    b, ib = T.table_rates(tab, (0.05, 30.0), mode, cells["T"], cell, om, w, p, dtp, units)
+    assert ia.all() and ib.all()
+    np.testing.assert_allclose(a, b, rtol=1e-10)

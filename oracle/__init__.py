@@ -89,6 +89,7 @@ _D = C.c_double
 def _declare(L):
     L.or_const.restype = _D; L.or_const.argtypes = [C.c_int]
     L.or_num_threads.restype = C.c_int32
+    L.or_set_num_threads.restype = None; L.or_set_num_threads.argtypes = [C.c_int32]
     L.or_philox4x32_10.argtypes = [_P, _P, _P]
     L.or_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _P]
     L.or_u53.restype = _D; L.or_u53.argtypes = [C.c_uint32, C.c_uint32]
@@ -145,6 +146,10 @@ def _ref(s):
 
 def num_threads() -> int:
     return int(load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    load().or_set_num_threads(int(n))
 
 
 def const(i: int) -> float:

@@ -46,6 +46,16 @@ int32_t or_num_threads(void) {
 #endif
 }
 
+/* Threads of the OpenMP loops that follow (the CPU-baseline timing runs the oracle on
+ * all host cores and on one). */
+void or_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 double or_const(int which) {
     switch (which) {
     case 0: return OR_ALPHA;

@@ -89,6 +89,7 @@ enum {
 /* ---- constants ---- */
 double or_const(int which);
 int32_t or_num_threads(void);
+void or_set_num_threads(int32_t n);
 
 /* ---- RNG ---- */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

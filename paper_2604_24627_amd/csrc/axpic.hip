@@ -346,6 +346,20 @@ __device__ __forceinline__ void stats_flush(const double* st, bool any, double* 
     }
 }
 
+// The power histogram of an event workgroup, accumulated in LDS (slots lo .. lo + n - 1
+// of the accumulator record) and added to the workgroup's accumulator copy once, bin by
+// bin: one global atomic per touched bin and workgroup instead of one per event.
+__device__ __forceinline__ void lds_hist_clear(double* __restrict__ h, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = 0.0;
+    __syncthreads();
+}
+__device__ __forceinline__ void lds_hist_flush(const double* __restrict__ h, int n,
+                                               double* __restrict__ A) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        if (h[k] != 0.0) atomicAdd(&A[k], h[k]);
+}
+
 // ------------------------------------------------------------------ scan kernel
 // One workgroup: exclusive offsets of the block product counts, capacity check.
 // Each thread scans 16 consecutive block totals held in registers (four
@@ -814,6 +828,7 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
               T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
               uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ acc,
               StatMap smap) {
+    extern __shared__ double hl[];                          // channel 0's bins
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
@@ -821,6 +836,7 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
+    lds_hist_clear(hl, nbh);
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     bool any = false;
@@ -863,14 +879,15 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
             apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
             aw[slot] = wrel;
             acell[slot] = c;
-            atomicAdd(&A[bin], wp * E);
         }
+        atomicAdd(&hl[bin], (double)K * wp * E);
         st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
         st[9] += cp ? 1.0 : 0.0;
         st[10] += over ? 1.0 : 0.0;
         any = true;
         w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
     }
+    lds_hist_flush(hl, nbh, A);
     stats_flush(st, any, A, nbh, smap);
 }
 
@@ -970,6 +987,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
                T* __restrict__ apz, T* __restrict__ aw, uint64_t* __restrict__ aid,
                int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
                StatMap smap) {
+    extern __shared__ double hl[];                          // channels 1 and 2's bins
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
@@ -977,6 +995,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
+    lds_hist_clear(hl, 2 * nbh);
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     bool any = false;
@@ -1013,7 +1032,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
         aw[slot] = (T)(kp.wa_mul[ch] * ws);
         aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
         acell[slot] = c;
-        atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
+        atomicAdd(&hl[(ch - 1) * nbh + hist_bin(kp, E)], wp * E);
         if (fb) {
             double* f = fb + (int64_t)c * 4;
             atomicAdd(&f[0], -wp * eu);
@@ -1025,6 +1044,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
         if (k == 0) st[9] += cp ? 1.0 : 0.0;
         any = true;
     }
+    lds_hist_flush(hl, 2 * nbh, A + nbh);
     stats_flush(st, any, A, nbh, smap);
 }
 
@@ -1517,6 +1537,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
              int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
              StatMap smap) {
 #pragma clang fp contract(off)
+    extern __shared__ double hl[];                          // channels 1 and 2's bins
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
@@ -1524,6 +1545,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
     double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
+    lds_hist_clear(hl, 2 * nbh);
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     bool any = false;
@@ -1585,7 +1607,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
         aw[slot] = (T)(kp.wa_mul[ch] * ws);
         aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
         acell[slot] = (int32_t)c;
-        atomicAdd(&A[ch * nbh + hist_bin(kp, E)], wp * E);
+        atomicAdd(&hl[(ch - 1) * nbh + hist_bin(kp, E)], wp * E);
         if (fb) {
             double* f = fb + c * 4;
             atomicAdd(&f[0], -wp * eu);
@@ -1597,6 +1619,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
         if (le > kp.cap) st[9] += 1.0;
         any = true;
     }
+    lds_hist_flush(hl, 2 * nbh, A + nbh);
     stats_flush(st, any, A, nbh, smap);
 }
 
@@ -1982,7 +2005,8 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
            s, n, 0, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
            runs_aligned({W.code}));
-    LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+    LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads),
+           sizeof(double) * (size_t)(kp.nbins + 2), s, n, step,
            next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
            TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
            TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.ctrl, ax->n, TP<T>(ax->x[0]),
@@ -2008,7 +2032,8 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            s, n, 1, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
            runs_aligned({W.code}));
     const auto k_events = kp.massive ? k_therm_events<T, true> : k_therm_events<T, false>;
-    LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, n, step,
+    LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads),
+           sizeof(double) * 2 * (size_t)(kp.nbins + 2), s, n, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), idv(el), el->cell, TCP<T>(lam_in),
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
@@ -2033,7 +2058,8 @@ axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axp
     LAUNCH("k_sup_expand", k_sup_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, counts,
            W.bact, W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     const auto k_events = kp.massive ? k_sup_events<T, true> : k_sup_events<T, false>;
-    LAUNCH("k_sup_events", k_events, dim3(kEventBlocks), dim3(kThreads), 0, s, ncell, step,
+    LAUNCH("k_sup_events", k_events, dim3(kEventBlocks), dim3(kThreads),
+           sizeof(double) * 2 * (size_t)(kp.nbins + 2), s, ncell, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, off, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
            TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),

@@ -52,7 +52,8 @@ class DeviceSpecies:
         self._S = None          # the cached C view points at the buffers being replaced
 
         def grow(t, dt_):
-            new = torch.zeros(cap, dtype=dt_, device=dev)
+            # no kernel reads a slot at or beyond n before writing it: no fill needed
+            new = torch.empty(cap, dtype=dt_, device=dev)
             if t is not None and self.n:
                 new[: self.n].copy_(t[: self.n])
             return new
@@ -65,8 +66,9 @@ class DeviceSpecies:
         self.capacity = cap
 
     def ensure(self, cap: int):
+        """Room for cap particles; grows geometrically (each growth copies the buffers)."""
         if cap > self.capacity:
-            self._alloc(int(cap * 1.25) + 1024)
+            self._alloc(max(int(cap * 1.25), 2 * self.capacity) + 1024)
 
     @staticmethod
     def from_input(sp: Dict, kind: int, ndim: int, device, extra: int = 0) -> "DeviceSpecies":
@@ -221,6 +223,7 @@ class AxpicSim:
         self.status_ops = torch.zeros((3, B.STATUS_N), dtype=torch.int64, device=dev)
         self._last_new = (0, 0)
         self.grow_ahead = True      # reserve room for twice the previous step's products
+        self._spare = {}            # compaction targets by kind, reused
         # thermal emission: "particle" (a Poisson draw per electron and channel) or
         # "cells" (per-cell superposition, axpic_sample_emit_cells)
         if thermal not in ("particle", "cells"):
@@ -364,14 +367,22 @@ class AxpicSim:
         return out[: sp.n]
 
     def _compacted(self, sp: DeviceSpecies) -> DeviceSpecies:
-        """A copy of `sp` without its particles of zero weight, in the same order."""
-        out = DeviceSpecies(sp.kind, self.dtype, self.ndim, sp.capacity, sp.w_ref, self.device,
-                            sp.Z, sp.A)
+        """A copy of `sp` without its particles of zero weight, in the same order, in the
+        spare buffer of its kind (allocated once and reused: the replaced buffer becomes the
+        next spare)."""
+        spare = self._spare.get(sp.kind)
+        if spare is None or spare.capacity < sp.n or spare.w_ref != sp.w_ref:
+            spare = DeviceSpecies(sp.kind, self.dtype, self.ndim, sp.capacity, sp.w_ref,
+                                  self.device, sp.Z, sp.A)
+        out = spare
+        out.n, out.off, out.n_sorted, out.id0, out.n_implicit = 0, None, 0, 0, 0
+        out._S = None
         self._ensure_ws(sp.n)
         B.check(self.lib.axpic_compact(B.ref(sp.struct()), B.ref(out.struct()),
                                        B.ptr(self.status), B.ptr(self.ws), self.ws_bytes, self.sh),
                 "compact")
         out.n = int(self.status.cpu()[2])
+        self._spare[sp.kind] = sp
         return out
 
     def compact_axions(self):

@@ -325,6 +325,21 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
                             axpic_species* electrons, const int64_t* off, const double* fb,
                             double* moments, double* stats, int64_t* chain, void* stream);
 
+/* axpic_sort_cells -- the canonical buffer order (Sec. II.E: the operators are local to
+ * a cell; the order within a buffer is this library's convention): a stable counting
+ * sort of `in` by cell -- the particles of each cell in their order in `in` -- with the
+ * particles of zero weight dropped (and any whose cell is not on the grid), written to
+ * `out` (distinct arrays, same dtype, out->capacity >= the number kept; ids written
+ * explicitly).  off (device int64[ncell + 1], may be NULL) receives the cell offsets of
+ * `out`; status[2] the number kept.  When it does not fit, status[0] holds the length
+ * needed, status[1] AXPIC_FLAG_CAPACITY, and nothing else is written.  Deterministic:
+ * the placement does not depend on the order of the device's atomics.  ws: at least
+ * axpic_sort_ws_bytes(in->n, ncell) bytes; in->n < 2^32. */
+size_t axpic_sort_ws_bytes(int64_t n, int64_t ncell);
+axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, axpic_species* out,
+                              int64_t* off, int64_t* status, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* axpic_compact -- stable removal of particles with w <= 0 from `in` into
  * `out` (distinct buffers, same dtype, out->capacity >= in->n).  status[2]
  * receives the surviving count. */

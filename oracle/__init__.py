@@ -128,6 +128,7 @@ def _declare(L):
     L.or_compton_x_above.restype = _D; L.or_compton_x_above.argtypes = [_D, _D]
     L.or_gamma_x_above.restype = _D; L.or_gamma_x_above.argtypes = [_D, _D, _D]
     L.or_equilibrium.argtypes = [_P, _P, _P, C.c_int64, _P, _D, _P]
+    L.or_sort_cells.restype = C.c_int64; L.or_sort_cells.argtypes = [_P, C.c_int64, _P]
     L.or_compton_x_tail.restype = _D; L.or_compton_x_tail.argtypes = [_D]
     L.or_gamma_x_tail.restype = _D; L.or_gamma_x_tail.argtypes = [_D, _D]
 
@@ -297,6 +298,16 @@ class OSpecies:
         self.w = np.concatenate([self.w, prod.w[:count]])
         self.id = np.concatenate([self.id, prod.id[:count]])
         self.cell = np.concatenate([self.cell, prod.cell[:count]])
+
+    def sort_cells(self, ncell: int) -> np.ndarray:
+        """Canonical order (or_sort_cells): stable counting sort by cell, particles of zero
+        weight dropped; returns the cell offsets [ncell + 1]."""
+        off = np.zeros(ncell + 1, np.int64)
+        S = self.struct()
+        m = load().or_sort_cells(_ref(S), ncell, _ptr(off))
+        self.x = np.ascontiguousarray(self.x[:, :m]); self.p = np.ascontiguousarray(self.p[:, :m])
+        self.w = self.w[:m].copy(); self.id = self.id[:m].copy(); self.cell = self.cell[:m].copy()
+        return off
 
     def compact(self):
         keep = self.w > 0.0
@@ -519,14 +530,16 @@ class OracleSim:
     """One uniform-grid run, FP64 throughout, physical weights.
 
     Step order (every operator sees the start-of-step population):
-      1. push the axions present at the start of the step, re-index their cells;
+      1. push the axions present at the start of the step, re-index their cells and
+         put them in the canonical order (stable by cell, zero weights dropped);
       2. local state of every cell from the deposits and the temperature field;
       3. forward Primakoff on the photons, thermal emission on the electrons;
       4. absorption / a->gamma on the axions present before step 3;
       5. feedback remap of the electrons and temperature update.
     """
 
-    def __init__(self, plasma: Dict, params, prec32: bool = False, compact_every: int = 0):
+    def __init__(self, plasma: Dict, params, prec32: bool = False, compact_every: int = 0,
+                 sort: bool = True):
         self.grid = plasma["grid"]
         sp = plasma["species"]
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
@@ -545,6 +558,7 @@ class OracleSim:
         self.next_id = int(plasma["next_id"])
         self.prec32 = prec32
         self.compact_every = compact_every
+        self.sort = sort            # canonical order of the axions after every push
         self.step_index = 0
         nb = self.pdict["hist_nbins"] + 2
         self.hist = np.zeros(3 * nb)
@@ -561,6 +575,8 @@ class OracleSim:
         p = self.pdict
         s = self.step_index
         push(self.grid, self.ax, self.prec32, p["m_a_keV"])
+        if self.sort:
+            self.ax.sort_cells(self.ncell)
         cells = self.cells()
         self.fb[:] = 0.0
         n_ax0 = self.ax.n

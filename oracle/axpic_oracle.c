@@ -1195,6 +1195,43 @@ void or_equilibrium(const or_grid* g, const or_params* prm, const or_cell* cells
 }
 
 /* ------------------------------------------------------------------------ */
+/* Canonical buffer order: a stable counting sort by cell -- the particles of */
+/* each cell in their previous order -- dropping the particles of zero weight */
+/* (and any whose cell is off the grid).  In place; returns the new length.  */
+/* off[ncell+1] (optional) receives the cell offsets.                        */
+/* ------------------------------------------------------------------------ */
+int64_t or_sort_cells(or_species* s, int64_t ncell, int64_t* off) {
+    const int64_t n = s->n;
+    int64_t* start = (int64_t*)calloc((size_t)(ncell + 1), sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        if (s->w[i] > 0.0 && s->cell[i] >= 0 && s->cell[i] < ncell) start[s->cell[i] + 1] += 1;
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    const int64_t m = start[ncell];
+    if (off) memcpy(off, start, sizeof(int64_t) * (size_t)(ncell + 1));
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * 8);
+    uint64_t* tid = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* tcell = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int64_t* next = start;              /* next free slot of each cell */
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(s->w[i] > 0.0) || s->cell[i] < 0 || s->cell[i] >= ncell) continue;
+        const int64_t d = next[s->cell[i]]++;
+        for (int k = 0; k < 3; ++k) { tmp[8 * d + k] = s->x[k][i]; tmp[8 * d + 3 + k] = s->p[k][i]; }
+        tmp[8 * d + 6] = s->w[i];
+        tid[d] = s->id[i];
+        tcell[d] = s->cell[i];
+    }
+    for (int64_t d = 0; d < m; ++d) {
+        for (int k = 0; k < 3; ++k) { s->x[k][d] = tmp[8 * d + k]; s->p[k][d] = tmp[8 * d + 3 + k]; }
+        s->w[d] = tmp[8 * d + 6];
+        s->id[d] = tid[d];
+        s->cell[d] = tcell[d];
+    }
+    free(tmp); free(tid); free(tcell); free(start);
+    s->n = m;
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Conservative feedback: affine momentum remap (Sec. II.J.1, eqs.           */
 /* cell_moments to b_def) and temperature estimate/relaxation (Sec. II.J.2,  */
 /* eqs. Te_est, Te_relax).  Electrons are grouped by cell (off[ncell+1]).    */

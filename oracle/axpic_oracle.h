@@ -155,6 +155,7 @@ void or_feedback(const or_grid* g, const or_params* prm, int64_t ncell, const in
                  or_species* el, const double* fb, double* T, double* stats,
                  double* moments_out);
 void or_push(const or_grid* g, or_species* ax, int32_t prec32, double m_a_keV);
+int64_t or_sort_cells(or_species* s, int64_t ncell, int64_t* off);
 
 /* ---- surrogate training data ---- */
 double or_F_quad(double s);

@@ -81,7 +81,7 @@ EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axp
            "axpic_sample_emit_cells", "axpic_mlp_table", "axpic_rates_table",
            "axpic_mlp_prepare_ws_bytes", "axpic_mlp_prepare", "axpic_mlp_design",
            "axpic_mlp_batch", "axpic_equilibrium_ws_bytes", "axpic_equilibrium",
-           "axpic_diag_noalloc"]
+           "axpic_diag_noalloc", "axpic_sort_ws_bytes", "axpic_sort_cells"]
 EQ_FIELDS = ("num", "en", "w2", "neq", "ueq", "nfix", "z")
 MLP_PARAMS = 57888
 MLP_BF16, MLP_F32 = 0, 1
@@ -157,6 +157,7 @@ def load(path: Optional[str] = None):
         ("axpic_mlp_batch", [_P, _P, C.c_int64, C.c_int64, C.c_uint64, C.c_int64, _P, _P, _P]),
         ("axpic_equilibrium", [_P, _P, _P, _P, C.c_double, _P, _P, C.c_size_t, _P]),
         ("axpic_diag_noalloc", [_P, C.c_double, _P, _P]),
+        ("axpic_sort_cells", [_P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32
@@ -166,6 +167,8 @@ def load(path: Optional[str] = None):
     L.axpic_mlp_prepare_ws_bytes.argtypes = []
     L.axpic_mlp_train_ws_bytes.restype = C.c_size_t
     L.axpic_mlp_train_ws_bytes.argtypes = [C.c_int64]
+    L.axpic_sort_ws_bytes.restype = C.c_size_t
+    L.axpic_sort_ws_bytes.argtypes = [C.c_int64, C.c_int64]
     L.axpic_equilibrium_ws_bytes.restype = C.c_size_t
     L.axpic_equilibrium_ws_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32]
     L.axpic_timing_enable.restype = None

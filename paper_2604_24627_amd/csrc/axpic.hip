@@ -1675,6 +1675,120 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
     }
 }
 
+// ------------------------------------------------------------------ canonical order
+// Stable counting sort by cell with the particles of zero weight dropped: counts per
+// cell (integer atomics), offsets by a scan over the cells, source indices scattered
+// into their cell's range in any order, then per cell each index ranked among the
+// cell's indices -- ascending index is the stable order -- and the particle moved to
+// its slot.  The result does not depend on the scatter's order.
+constexpr int kSortCellsPerBlock = kThreads * kPer;     // cells per block of the offset scan
+constexpr int kSortLanes = 16;                          // lanes per cell in the gather
+
+__global__ void __launch_bounds__(kThreads)
+k_fill_u32(int64_t n, uint32_t* __restrict__ a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0u;
+}
+
+// A particle takes part when its weight is positive and its cell lies on the grid (the
+// same test in the count and the scatter).
+template <typename T>
+__device__ __forceinline__ bool sort_live(const T* __restrict__ w, const int32_t* __restrict__ cell,
+                                          int64_t i, int64_t ncell, int32_t* c) {
+    *c = cell[i];
+    return w[i] > (T)0 && *c >= 0 && (int64_t)*c < ncell;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_sort_count(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t* __restrict__ cell,
+             uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t c;
+    if (i < n && sort_live<T>(w, cell, i, ncell, &c)) atomicAdd(&cnt[c], 1u);
+}
+
+// Per block of kSortCellsPerBlock cells: the sum of their counts.
+__global__ void __launch_bounds__(kThreads)
+k_sort_blocksum(int64_t ncell, const uint32_t* __restrict__ cnt, uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t lds[kThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kSortCellsPerBlock + (int64_t)kPer * threadIdx.x;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v += c0 + q < ncell ? cnt[c0 + q] : 0u;
+    const uint32_t t = block_sum_u32(v, lds);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+// Cell offsets off[c] = block offset + exclusive scan of the block's counts; off[ncell] =
+// the total.  Nothing when the output does not fit (ctrl[0]).
+__global__ void __launch_bounds__(kThreads)
+k_sort_offsets(int64_t ncell, const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ boff,
+               const int64_t* __restrict__ ctrl, int64_t* __restrict__ off) {
+    __shared__ uint32_t lds[kThreads / 64];
+    if (ctrl[0]) return;
+    const int64_t c0 = (int64_t)blockIdx.x * kSortCellsPerBlock + (int64_t)kPer * threadIdx.x;
+    uint32_t v[kPer], tot = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) { v[q] = c0 + q < ncell ? cnt[c0 + q] : 0u; tot += v[q]; }
+    uint32_t segtot;
+    uint64_t run = boff[blockIdx.x] + block_excl_scan(tot, lds, &segtot);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (c0 + q < ncell) off[c0 + q] = (int64_t)run;
+        run += v[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[ncell] = ctrl[1];
+}
+
+// Source index of every live particle into its cell's range; the per-cell count is
+// consumed as a countdown, so the order within a cell is whatever the atomics give.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_sort_scatter(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t* __restrict__ cell,
+               const int64_t* __restrict__ off, const int64_t* __restrict__ ctrl,
+               uint32_t* __restrict__ cnt, uint32_t* __restrict__ idx) {
+    if (ctrl[0]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t c;
+    if (i >= n || !sort_live<T>(w, cell, i, ncell, &c)) return;
+    const uint32_t k = atomicSub(&cnt[c], 1u) - 1u;
+    idx[off[c] + k] = (uint32_t)i;
+}
+
+// One group of kSortLanes lanes per cell: the slot of each of the cell's particles is
+// the number of the cell's source indices below its own; the particle is copied there.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_sort_gather(int64_t ncell, const int64_t* __restrict__ off, const uint32_t* __restrict__ idx,
+              const int64_t* __restrict__ ctrl, int ndim, const T* __restrict__ x0,
+              const T* __restrict__ x1, const T* __restrict__ x2, const T* __restrict__ px,
+              const T* __restrict__ py, const T* __restrict__ pz, const T* __restrict__ w,
+              IdView id, T* __restrict__ ox0, T* __restrict__ ox1, T* __restrict__ ox2,
+              T* __restrict__ opx, T* __restrict__ opy, T* __restrict__ opz, T* __restrict__ ow,
+              uint64_t* __restrict__ oid, int32_t* __restrict__ ocell) {
+    if (ctrl[0]) return;
+    const int sub = threadIdx.x & (kSortLanes - 1);
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSortLanes;
+    if (c >= ncell) return;
+    const int64_t lo = off[c], hi = off[c + 1];
+    for (int64_t j = lo + sub; j < hi; j += kSortLanes) {
+        const uint32_t sj = idx[j];
+        int64_t rank = 0;
+        for (int64_t m = lo; m < hi; ++m) rank += idx[m] < sj ? 1 : 0;
+        const int64_t d = lo + rank;
+        const int64_t i = (int64_t)sj;
+        ox0[d] = x0[i];
+        if (ndim > 1) ox1[d] = x1[i];
+        if (ndim > 2) ox2[d] = x2[i];
+        opx[d] = px[i]; opy[d] = py[i]; opz[d] = pz[i];
+        ow[d] = w[i];
+        oid[d] = id(i);
+        ocell[d] = (int32_t)c;
+    }
+}
+
 // ------------------------------------------------------------------ diagnostics
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
@@ -2412,6 +2526,76 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     if (in->dtype == AXPIC_F32) { AXPIC_COMPACT(float); }
     else { AXPIC_COMPACT(double); }
 #undef AXPIC_COMPACT
+    return launched();
+}
+
+size_t axpic_sort_ws_bytes(int64_t n, int64_t ncell) {
+    if (n < 0 || ncell < 1) return 0;
+    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
+    return align256(4 * (size_t)ncell) + align256(4 * (size_t)nblk) + align256(8 * (size_t)nblk) +
+           align256(4 * (size_t)std::max<int64_t>(n, 1)) + align256(8 * (size_t)(ncell + 1)) + 256;
+}
+
+axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, axpic_species* out,
+                              int64_t* off, int64_t* status, void* ws, size_t ws_bytes,
+                              void* stream) {
+    if (!grid_ok(g) || !species_ok(in, true) || !out || !status) return AXPIC_E_INVAL;
+    if (out->dtype != in->dtype || out == in || !out->x[0] || !out->w || !out->id || !out->cell ||
+        !out->p[0] || !out->p[1] || !out->p[2])
+        return AXPIC_E_INVAL;
+    // the gather reads `in` while it writes `out`: no array may be shared
+    if (out->w == in->w || out->x[0] == in->x[0] || out->p[0] == in->p[0] ||
+        out->cell == in->cell || (in->id && out->id == in->id))
+        return AXPIC_E_INVAL;
+    for (int d = 0; d < g->ndim; ++d)
+        if ((in->n && !in->x[d]) || !out->x[d]) return AXPIC_E_INVAL;
+    if (in->n >= ((int64_t)1 << 32)) return AXPIC_E_INVAL;
+    const int64_t ncell = ncell_of(g), n = in->n;
+    if (!ws || ws_bytes < axpic_sort_ws_bytes(n, ncell)) return AXPIC_E_INVAL;
+    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
+    char* p = (char*)ws;
+    uint32_t* cnt = (uint32_t*)p; p += align256(4 * (size_t)ncell);
+    uint32_t* bsum = (uint32_t*)p; p += align256(4 * (size_t)nblk);
+    uint64_t* boff = (uint64_t*)p; p += align256(8 * (size_t)nblk);
+    uint32_t* idx = (uint32_t*)p; p += align256(4 * (size_t)std::max<int64_t>(n, 1));
+    int64_t* offw = (int64_t*)p; p += align256(8 * (size_t)(ncell + 1));
+    int64_t* ctrl = (int64_t*)p;
+    if (!off) off = offw;
+    hipStream_t s = S(stream);
+    const int64_t fill_blocks = std::min<int64_t>((ncell + kThreads - 1) / kThreads, 8192);
+    LAUNCH("k_fill_u32", k_fill_u32, dim3((unsigned)fill_blocks), dim3(kThreads), 0, s, ncell, cnt);
+    if (n > 0) {
+        if (in->dtype == AXPIC_F32)
+            LAUNCH("k_sort_count", k_sort_count<float>, grid1(n), dim3(kThreads), 0, s, n, ncell,
+                   (const float*)in->w, in->cell, cnt);
+        else
+            LAUNCH("k_sort_count", k_sort_count<double>, grid1(n), dim3(kThreads), 0, s, n, ncell,
+                   (const double*)in->w, in->cell, cnt);
+    }
+    LAUNCH("k_sort_blocksum", k_sort_blocksum, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell, cnt,
+           bsum);
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, bsum, boff, nblk, (int64_t)0,
+           out->capacity, ctrl, status, (uint64_t)0, (int64_t*)nullptr, 0);
+    LAUNCH("k_sort_offsets", k_sort_offsets, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell, cnt,
+           boff, ctrl, off);
+    if (n > 0) {
+        const int64_t gthreads = ncell * kSortLanes;
+        int ndim = 1;
+        if (in->x[1] && g->ndim > 1) ndim = 2;
+        if (in->x[2] && g->ndim > 2) ndim = 3;
+#define AXPIC_SORT(T)                                                                              \
+        LAUNCH("k_sort_scatter", k_sort_scatter<T>, grid1(n), dim3(kThreads), 0, s, n, ncell,      \
+               (const T*)in->w, in->cell, (const int64_t*)off, (const int64_t*)ctrl, cnt, idx);     \
+        LAUNCH("k_sort_gather", k_sort_gather<T>, grid1(gthreads), dim3(kThreads), 0, s, ncell,    \
+               (const int64_t*)off, (const uint32_t*)idx, (const int64_t*)ctrl, ndim,             \
+               (const T*)in->x[0], (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],    \
+               (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, idv(in), (T*)out->x[0],   \
+               (T*)out->x[1], (T*)out->x[2], (T*)out->p[0], (T*)out->p[1], (T*)out->p[2],         \
+               (T*)out->w, out->id, out->cell)
+        if (in->dtype == AXPIC_F32) { AXPIC_SORT(float); }
+        else { AXPIC_SORT(double); }
+#undef AXPIC_SORT
+    }
     return launched();
 }
 

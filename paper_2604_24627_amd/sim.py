@@ -5,7 +5,8 @@ operator is a call into libaxpic.so.  The step order is the one the operators
 are defined with: every operator acts on the population present at the start
 of the step, and the feedback is applied last:
 
-  1. push the axions present at the start of the step and re-bin them;
+  1. push the axions present at the start of the step, re-bin them and put them in
+     the canonical order (stable by cell, zero weights dropped);
   2. local state of every cell (deposits, temperature field -> prefactors);
   3. forward Primakoff on the photons; thermal emission on the electrons;
   4. absorption and a->gamma on the axions present before step 3;
@@ -151,7 +152,7 @@ class AxpicSim:
 
     def __init__(self, plasma: Dict, params, device: str = "cuda", axion_capacity: int = 0,
                  photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None,
-                 thermal: str = "particle", surrogate_mode: str = "particle"):
+                 thermal: str = "particle", surrogate_mode: str = "particle", sort: bool = True):
         self.lib = B.load()
         self.device = torch.device(device)
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
@@ -224,6 +225,12 @@ class AxpicSim:
         self._last_new = (0, 0)
         self.grow_ahead = True      # reserve room for twice the previous step's products
         self._spare = {}            # compaction targets by kind, reused
+        # canonical order of the axions after every push (axpic_sort_cells): stable by
+        # cell, zero weights dropped, cell offsets kept for the operators
+        self.sort = sort
+        self.ax_off = torch.zeros(self.ncell + 1, dtype=torch.int64, device=dev)
+        self.sort_status = torch.zeros(B.STATUS_N, dtype=torch.int64, device=dev)
+        self.sort_ws = None
         # thermal emission: "particle" (a Poisson draw per electron and channel) or
         # "cells" (per-cell superposition, axpic_sample_emit_cells)
         if thermal not in ("particle", "cells"):
@@ -360,6 +367,31 @@ class AxpicSim:
                                              1 if push else 0, float(self.pdict["m_a_keV"]),
                                              self.sh), "bin_cells")
 
+    def sort_axions(self):
+        """The axions in the canonical order (axpic_sort_cells) in the spare buffer, which
+        becomes the axion buffer; its cell offsets stay in ax_off."""
+        if not self.ax.n:
+            return
+        ax = self.ax
+        spare = self._spare.get(B.AXION)
+        if spare is None or spare.capacity < ax.n:
+            spare = DeviceSpecies(B.AXION, self.dtype, self.ndim, ax.capacity, ax.w_ref,
+                                  self.device)
+        need = int(self.lib.axpic_sort_ws_bytes(ax.n, self.ncell))
+        if self.sort_ws is None or self.sort_ws.numel() < need:
+            self.sort_ws = torch.empty(int(need * 1.25) + 4096, dtype=torch.uint8,
+                                       device=self.device)
+        spare.n, spare.off, spare.n_sorted, spare.id0, spare.n_implicit = 0, None, 0, 0, 0
+        spare._S = None
+        B.check(self.lib.axpic_sort_cells(B.ref(self.grid), B.ref(ax.struct()),
+                                          B.ref(spare.struct()), B.ptr(self.ax_off),
+                                          B.ptr(self.sort_status), B.ptr(self.sort_ws),
+                                          self.sort_ws.numel(), self.sh), "sort_cells")
+        n = int(self.sort_status.cpu()[2])
+        spare.n, spare.off, spare.n_sorted = n, self.ax_off, n
+        self._spare[B.AXION] = ax
+        self.ax = spare
+
     def rates(self, sp: DeviceSpecies, channel: int):
         out = torch.zeros(max(sp.n, 1), dtype=_tdtype(sp.dtype), device=self.device)
         B.check(self.lib.axpic_rates(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
@@ -433,6 +465,8 @@ class AxpicSim:
         from it on (the skipped ones modified nothing)."""
         p = self.pdict
         self.bin_axions(push=True)
+        if self.sort:
+            self.sort_axions()
         if p["T_mode"] == 2:
             self.cell_state()
         if self.need_feedback:
@@ -539,7 +573,8 @@ class AxpicSim:
         self._last_new = (self.ax.n - n_ax0, self.ph.n - n_ph0)
         self.step_index += 1
         if self.compact_every and self.step_index % self.compact_every == 0:
-            self.compact_axions()
+            if not self.sort:            # sorting drops the axions of zero weight every step
+                self.compact_axions()
             if p["inverse"] and p["channels"] & B.PRIMAKOFF:
                 self.compact_photons()
 

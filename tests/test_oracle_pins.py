@@ -368,3 +368,27 @@ def test_input_blackbody_photons():
                                      rel=0.03)
     dens = ph["w_ref"] * ph["w"].sum() / (wl.ncell * wl.V_cell_cm3)
     assert dens == pytest.approx(2 * ZETA3 * 1.3 ** 3 / (math.pi ** 2 * HBARC ** 3), rel=1e-12)
+
+
+def test_canonical_sort_is_numpys_stable_sort_by_cell():
+    """The canonical order (or_sort_cells) is the stable sort by cell of the live
+    particles: numpy's stable argsort of the cells of the particles of positive weight,
+    with every array carried along, and offsets that bracket each cell."""
+    rng = np.random.default_rng(5)
+    for n, ncell in ((0, 5), (1, 1), (3000, 17), (5000, 400)):
+        x = rng.random((3, n)); p = rng.normal(size=(3, n))
+        w = np.where(rng.random(n) < 0.15, 0.0, rng.random(n) + 0.1)
+        cell = rng.integers(0, ncell, n).astype(np.int32)
+        cell[::97] = ncell + 2                        # off the grid: dropped
+        ids = rng.permutation(n).astype(np.uint64)
+        sp = O.OSpecies(x, p, w, ids, cell)
+        off = sp.sort_cells(ncell)
+        keep = (w > 0) & (cell < ncell)
+        order = np.flatnonzero(keep)[np.argsort(cell[keep], kind="stable")]
+        np.testing.assert_array_equal(sp.id, ids[order])
+        np.testing.assert_array_equal(sp.cell, cell[order])
+        np.testing.assert_array_equal(sp.w, w[order])
+        np.testing.assert_array_equal(sp.x, x[:, order])
+        np.testing.assert_array_equal(sp.p, p[:, order])
+        np.testing.assert_array_equal(off, np.concatenate([[0], np.cumsum(
+            np.bincount(cell[keep], minlength=ncell))]))

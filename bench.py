@@ -143,6 +143,7 @@ def timed_leg(sim, steps, warmup, name, kernel_steps=3, flops=None):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     upd = 0
+    allocs0 = sim.reallocations()
     t0 = time.perf_counter()
     if sim.compact_every:
         ms = 0.0
@@ -167,6 +168,7 @@ def timed_leg(sim, steps, warmup, name, kernel_steps=3, flops=None):
         dead = dead_axions(sim)
         upd -= 2 * dead * steps
     wall = time.perf_counter() - t0
+    allocs = sim.reallocations() - allocs0
     value = upd / (ms * 1e-3)
     # per-kernel durations and the step's algorithmic bytes over a few more steps
     frac = active_fraction(sim)
@@ -206,7 +208,8 @@ def timed_leg(sim, steps, warmup, name, kernel_steps=3, flops=None):
                  "feedback_active_cells": round(frac, 4)}
     rec = {"value": value, "unit": "updates/s", "ms_per_step": ms_step, "steps": steps,
            "warmup": warmup, "wall_ms_timed": round(wall * 1e3, 2), "axions_end": sim.ax.n,
-           "dead_axions_end": dead,
+           "dead_axions_end": dead, "reallocations_timed": allocs,
+           "kernel_ms_sum_per_step": round(sum(v[1] for v in kt.values()) / kernel_steps, 4),
            "roofline": roof, "step_roofline": step_roof, "kernel_ms_per_step": per_step}
     if flops:
         kname = "k_rates_mlp" if "k_rates_mlp" in kt else ("k_mlp_table" if "k_mlp_table" in kt else None)
@@ -219,8 +222,10 @@ def timed_leg(sim, steps, warmup, name, kernel_steps=3, flops=None):
                                     "avg_ms": round(t2 / l2, 5),
                                     "evals_per_step": evals / kernel_steps,
                                     "flop_per_eval": MLP_FLOP_PER_EVAL}
-    log(f"{name}: {ms_step:.3f} ms/step, {value:.3e} updates/s, dominant {dom} "
-        f"{roof['frac']:.3f} of HBM peak, step {step_roof['frac']:.3f}; axions {sim.ax.n}")
+    log(f"{name}: {ms_step:.3f} ms/step (kernels {rec['kernel_ms_sum_per_step']:.3f}), "
+        f"{value:.3e} updates/s, dominant {dom} {roof['frac']:.3f} of HBM peak, step "
+        f"{step_roof['frac']:.3f}; axions {sim.ax.n}, new photons/step {sim._last_new[1]}, "
+        f"reallocations {allocs}")
     return rec
 
 
@@ -355,7 +360,7 @@ def leg_graded(a, S=None):
     for mode in (("plain", "table") if S else ("plain",)):
         n_ax = int(0.02 * pl["species"]["electrons"]["n"] * (a.leg_steps + a.warmup + 8))
         sim = AxpicSim(pl, wl.params, axion_capacity=n_ax,
-                       photon_extra=int(0.02 * pl["species"]["photons"]["n"]),
+                       photon_extra=int(0.05 * pl["species"]["photons"]["n"]),
                        surrogate=S if mode == "table" else None, surrogate_mode="table")
         torch.cuda.empty_cache()
         flops = (lambda s: s.ncell * S.TABLE_NODES * 4) if mode == "table" else None

@@ -332,13 +332,22 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
  * `out` (distinct arrays, same dtype, out->capacity >= the number kept; ids written
  * explicitly).  off (device int64[ncell + 1], may be NULL) receives the cell offsets of
  * `out`; status[2] the number kept.  When it does not fit, status[0] holds the length
- * needed, status[1] AXPIC_FLAG_CAPACITY, and nothing else is written.  Deterministic:
- * the placement does not depend on the order of the device's atomics.  ws: at least
- * axpic_sort_ws_bytes(in->n, ncell) bytes; in->n < 2^32. */
-size_t axpic_sort_ws_bytes(int64_t n, int64_t ncell);
-axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, axpic_species* out,
-                              int64_t* off, int64_t* status, void* ws, size_t ws_bytes,
-                              void* stream);
+ * needed, status[1] AXPIC_FLAG_CAPACITY, and nothing else is written.
+ *
+ * path selects how the per-cell counts and places are taken (the result is the same):
+ * AXPIC_SORT_SPARSE one atomic per run of equal cells in a wavefront, AXPIC_SORT_DENSE
+ * one per cell and block of 1024 particles, AXPIC_SORT_AUTO the second from 32
+ * particles per cell on.  AXPIC_E_INVAL for another value.
+ *
+ * Deterministic: the placement does not depend on the order of the device's atomics.
+ * ws: at least axpic_sort_ws_bytes(g, in->n) bytes; in->n < 2^32. */
+#define AXPIC_SORT_AUTO 0
+#define AXPIC_SORT_SPARSE 1
+#define AXPIC_SORT_DENSE 2
+size_t axpic_sort_ws_bytes(const axpic_grid* g, int64_t n);
+axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, int32_t path,
+                              axpic_species* out, int64_t* off, int64_t* status, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* axpic_compact -- stable removal of particles with w <= 0 from `in` into
  * `out` (distinct buffers, same dtype, out->capacity >= in->n).  status[2]

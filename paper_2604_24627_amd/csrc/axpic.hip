@@ -1070,7 +1070,8 @@ __device__ __forceinline__ uint32_t abs_count_run(
     const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
     const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
     const T* __restrict__ pabs_in, const T* __restrict__ lam_in, uint16_t* __restrict__ code,
-    float wt_heavy, float wt_light, float prod_ratio, uint32_t* act) {
+    float wt_heavy, float wt_light, float prod_ratio, const float4* __restrict__ stage,
+    int32_t c_first, int32_t m_stage, uint32_t* act) {
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
     const bool a2g = kp.inverse && (kp.channels & AXPIC_PRIMAKOFF);
     T wv[kPer], xv[kPer], yv[kPer], zv[kPer], Pv[kPer], lv[kPer];
@@ -1086,7 +1087,16 @@ __device__ __forceinline__ uint32_t abs_count_run(
     if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
     T pcv[kPer][AXPIC_PREF_N];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 2);
+    for (int j = 0; j < kPer; ++j) {
+        const int32_t r = cv[j] - c_first;
+        if (sizeof(T) == 4 && stage && r >= 0 && r < m_stage) {   // the tile's records, in LDS
+            const float4 a = stage[2 * r], b = stage[2 * r + 1];
+            pcv[j][0] = a.x; pcv[j][1] = a.y; pcv[j][2] = a.z; pcv[j][3] = a.w;
+            pcv[j][4] = b.x; pcv[j][5] = b.y; pcv[j][6] = b.z; pcv[j][7] = b.w;
+        } else {
+            load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 2);
+        }
+    }
     uint32_t cdv[kPer], tot = 0, nact = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -1152,20 +1162,39 @@ k_abs_count(int64_t n, int64_t step, KParams kp, double w_ref_a, const float* __
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
             uint32_t* __restrict__ bact, double* __restrict__ acc, int acc_n, int aligned,
-            float wt_heavy, float wt_light, float prod_ratio) {
+            float wt_heavy, float wt_light, float prod_ratio, int64_t n_sorted) {
     clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
+    __shared__ float4 s_pref[2 * kStageCells];
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
+    const bool vec = aligned && base + kBlockParents <= n;
+    // a tile inside the cell-ordered prefix spans the cells of its first and last axion:
+    // when they are few, their prefactor records go to LDS (one read per cell)
+    const float4* stage = nullptr;
+    int32_t c_first = 0, m_stage = 0;
+    if (sizeof(T) == 4 && vec && base + kBlockParents <= n_sorted) {
+        c_first = cell[base];
+        const int32_t m = cell[base + kBlockParents - 1] - c_first + 1;
+        if (m >= 1 && m <= kStageCells) {
+            for (int t = threadIdx.x; t < 2 * m; t += kThreads)
+                s_pref[t] = ((const float4*)(p32 + (int64_t)c_first * AXPIC_PREF_N))[t];
+            __syncthreads();
+            stage = s_pref;
+            m_stage = m;
+        }
+    }
     uint32_t tot, act;
-    if (aligned && base + kBlockParents <= n)
+    if (vec)
         tot = abs_count_run<T, M, true>(i0, n, step, kp, w_ref_a, pref, w, px, py, pz, id, cell,
-                                        pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio, &act);
+                                        pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio,
+                                        stage, c_first, m_stage, &act);
     else
         tot = abs_count_run<T, M, false>(i0, n, step, kp, w_ref_a, pref, w, px, py, pz, id, cell,
-                                         pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio, &act);
+                                         pabs_in, lam_in, code, wt_heavy, wt_light, prod_ratio,
+                                         nullptr, 0, 0, &act);
     const uint32_t bt = block_sum_u32(tot, lds);
     const uint32_t ba = block_sum_u32(act, lds);
     if (threadIdx.x == 0) {
@@ -1677,12 +1706,14 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
 
 // ------------------------------------------------------------------ canonical order
 // Stable counting sort by cell with the particles of zero weight dropped: counts per
-// cell (integer atomics), offsets by a scan over the cells, source indices scattered
-// into their cell's range in any order, then per cell each index ranked among the
-// cell's indices -- ascending index is the stable order -- and the particle moved to
-// its slot.  The result does not depend on the scatter's order.
+// cell, offsets by a scan over the cells, source indices scattered into their cell's
+// range in any order, then each index ranked among its cell's indices -- ascending
+// index is the stable order -- and the particle moved to its slot.  The result does not
+// depend on the scatter's order.  Consecutive particles of one cell in a wavefront (the
+// usual case: the input is the previous step's order) share one atomic.
 constexpr int kSortCellsPerBlock = kThreads * kPer;     // cells per block of the offset scan
-constexpr int kSortLanes = 16;                          // lanes per cell in the gather
+constexpr int kSortSlots = kThreads * kPer;             // sorted slots per block of the gather
+constexpr int kSortWindow = 4 * kSortSlots;             // source indices staged in LDS
 
 __global__ void __launch_bounds__(kThreads)
 k_fill_u32(int64_t n, uint32_t* __restrict__ a) {
@@ -1691,22 +1722,86 @@ k_fill_u32(int64_t n, uint32_t* __restrict__ a) {
         a[i] = 0u;
 }
 
-// A particle takes part when its weight is positive and its cell lies on the grid (the
-// same test in the count and the scatter).
+// The cell of particle i when it takes part (positive weight, cell on the grid), else -1;
+// the same test in the count and the scatter.
 template <typename T>
-__device__ __forceinline__ bool sort_live(const T* __restrict__ w, const int32_t* __restrict__ cell,
-                                          int64_t i, int64_t ncell, int32_t* c) {
-    *c = cell[i];
-    return w[i] > (T)0 && *c >= 0 && (int64_t)*c < ncell;
+__device__ __forceinline__ int32_t sort_key(int64_t i, int64_t n, const T* __restrict__ w,
+                                            const int32_t* __restrict__ cell, int64_t ncell) {
+    if (i >= n) return -1;
+    const int32_t c = cell[i];
+    return (w[i] > (T)0 && c >= 0 && (int64_t)c < ncell) ? c : -1;
 }
 
-template <typename T>
+// Runs of equal keys in adjacent lanes of a wavefront: the first lane of this lane's run
+// and the run's length.  Every lane of the wavefront must call it.
+struct WaveRun { int head; uint32_t len; };
+__device__ __forceinline__ WaveRun wave_run(int32_t key) {
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = heads & ((2ull << lane) - 1ull);          // heads at or below lane
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);
+    WaveRun r;
+    r.head = 63 - __clzll((long long)upto);
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    r.len = (uint32_t)(next - r.head);
+    return r;
+}
+
+// Blocks go round robin over the eight XCDs; this gives each XCD a contiguous range of
+// block indices, so that neighbouring ranges of particles share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
+    const int64_t q = nblk / 8, r = nblk % 8, x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// A block's open-addressed LDS table of the cells its particles fall in (more slots
+// than particles, so an insertion always ends).  Returns the slot of cell c.
+constexpr int kSortHashBits = 11;
+constexpr int kSortHash = 1 << kSortHashBits;
+static_assert(kSortHash >= 2 * kSortSlots, "the cell table must outnumber the particles");
+__device__ __forceinline__ int sort_hash_slot(int32_t c, int32_t* hkey) {
+    uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - kSortHashBits);
+    for (;;) {
+        const int32_t old = atomicCAS(&hkey[h], -1, c);
+        if (old == -1 || old == c) return (int)h;
+        h = (h + 1) & (kSortHash - 1);
+    }
+}
+
+__device__ __forceinline__ void sort_hash_clear(int32_t* hkey, uint32_t* hval) {
+    for (int h = threadIdx.x; h < kSortHash; h += kThreads) { hkey[h] = -1; hval[h] = 0u; }
+}
+
+// kSortSlots particles per block: counts per cell gathered by runs of a
+// wavefront, with TABLE further in the block's cell table (one atomic per cell and block:
+// it pays where the cells are dense), else one atomic per run.
+template <typename T, bool TABLE>
 __global__ void __launch_bounds__(kThreads)
-k_sort_count(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t* __restrict__ cell,
-             uint32_t* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t c;
-    if (i < n && sort_live<T>(w, cell, i, ncell, &c)) atomicAdd(&cnt[c], 1u);
+k_sort_count(int64_t n, int64_t ncell, const T* __restrict__ w,
+             const int32_t* __restrict__ cell, uint32_t* __restrict__ cnt) {
+    __shared__ int32_t hkey[TABLE ? kSortHash : 1];
+    __shared__ uint32_t hval[TABLE ? kSortHash : 1];
+    if (TABLE) {
+        sort_hash_clear(hkey, hval);
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * kSortSlots;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t c = sort_key<T>(base + q * kThreads + threadIdx.x, n, w, cell, ncell);
+        const WaveRun r = wave_run(c);
+        if (c >= 0 && r.head == lane) {
+            if (TABLE) atomicAdd(&hval[sort_hash_slot(c, hkey)], r.len);
+            else atomicAdd(&cnt[c], r.len);
+        }
+    }
+    if (TABLE) {
+        __syncthreads();
+        for (int h = threadIdx.x; h < kSortHash; h += kThreads)
+            if (hkey[h] >= 0) atomicAdd(&cnt[hkey[h]], hval[h]);
+    }
 }
 
 // Per block of kSortCellsPerBlock cells: the sum of their counts.
@@ -1742,50 +1837,135 @@ k_sort_offsets(int64_t ncell, const uint32_t* __restrict__ cnt, const uint64_t* 
     if (blockIdx.x == 0 && threadIdx.x == 0) off[ncell] = ctrl[1];
 }
 
-// Source index of every live particle into its cell's range; the per-cell count is
-// consumed as a countdown, so the order within a cell is whatever the atomics give.
-template <typename T>
+// Source index of every live particle into its cell's range.  The per-cell count is
+// consumed as a countdown: one atomic
+// per run of a wavefront reserving the run's places, or with TABLE one per cell and
+// block reserving the block's share, within which each particle takes the place its run
+// and the block's table give.  The order within a cell is whatever the atomics give.
+// Nothing when the output does not fit (ctrl[0]).
+template <typename T, bool TABLE>
 __global__ void __launch_bounds__(kThreads)
 k_sort_scatter(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t* __restrict__ cell,
                const int64_t* __restrict__ off, const int64_t* __restrict__ ctrl,
                uint32_t* __restrict__ cnt, uint32_t* __restrict__ idx) {
-    if (ctrl[0]) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t c;
-    if (i >= n || !sort_live<T>(w, cell, i, ncell, &c)) return;
-    const uint32_t k = atomicSub(&cnt[c], 1u) - 1u;
-    idx[off[c] + k] = (uint32_t)i;
+    __shared__ int32_t hkey[TABLE ? kSortHash : 1];
+    __shared__ uint32_t hval[TABLE ? kSortHash : 1];   // a cell's count in the block, then its base
+    if (ctrl[0]) return;                     // uniform over the grid
+    if (TABLE) {
+        sort_hash_clear(hkey, hval);
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * kSortSlots;
+    int32_t cq[kPer];
+    int slot[kPer];
+    uint32_t loc[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t c = sort_key<T>(base + q * kThreads + threadIdx.x, n, w, cell, ncell);
+        const WaveRun r = wave_run(c);
+        int h = 0;
+        uint32_t l = 0;
+        if (c >= 0 && r.head == lane) {
+            if (TABLE) {
+                h = sort_hash_slot(c, hkey);
+                l = atomicAdd(&hval[h], r.len);
+            } else {
+                l = atomicSub(&cnt[c], r.len) - r.len;
+            }
+        }
+        slot[q] = __shfl(h, r.head, 64);
+        loc[q] = __shfl(l, r.head, 64) + (uint32_t)(lane - r.head);
+        cq[q] = c;
+    }
+    if (TABLE) {
+        __syncthreads();
+        for (int h = threadIdx.x; h < kSortHash; h += kThreads)
+            if (hkey[h] >= 0) {
+                const uint32_t t = hval[h];
+                hval[h] = atomicSub(&cnt[hkey[h]], t) - t;
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (cq[q] >= 0)
+            idx[off[cq[q]] + (TABLE ? hval[slot[q]] : 0u) + loc[q]] =
+                (uint32_t)(base + q * kThreads + threadIdx.x);
 }
 
-// One group of kSortLanes lanes per cell: the slot of each of the cell's particles is
-// the number of the cell's source indices below its own; the particle is copied there.
+// The arrays a sort moves: particle i of `in` to slot d of `out`.
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_sort_gather(int64_t ncell, const int64_t* __restrict__ off, const uint32_t* __restrict__ idx,
-              const int64_t* __restrict__ ctrl, int ndim, const T* __restrict__ x0,
-              const T* __restrict__ x1, const T* __restrict__ x2, const T* __restrict__ px,
-              const T* __restrict__ py, const T* __restrict__ pz, const T* __restrict__ w,
-              IdView id, T* __restrict__ ox0, T* __restrict__ ox1, T* __restrict__ ox2,
-              T* __restrict__ opx, T* __restrict__ opy, T* __restrict__ opz, T* __restrict__ ow,
-              uint64_t* __restrict__ oid, int32_t* __restrict__ ocell) {
-    if (ctrl[0]) return;
-    const int sub = threadIdx.x & (kSortLanes - 1);
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSortLanes;
-    if (c >= ncell) return;
-    const int64_t lo = off[c], hi = off[c + 1];
-    for (int64_t j = lo + sub; j < hi; j += kSortLanes) {
-        const uint32_t sj = idx[j];
-        int64_t rank = 0;
-        for (int64_t m = lo; m < hi; ++m) rank += idx[m] < sj ? 1 : 0;
-        const int64_t d = lo + rank;
-        const int64_t i = (int64_t)sj;
-        ox0[d] = x0[i];
-        if (ndim > 1) ox1[d] = x1[i];
-        if (ndim > 2) ox2[d] = x2[i];
-        opx[d] = px[i]; opy[d] = py[i]; opz[d] = pz[i];
+struct SortIO {
+    int ndim;
+    const T* x[3];
+    const T* p[3];
+    const T* w;
+    IdView id;
+    T* ox[3];
+    T* op[3];
+    T* ow;
+    uint64_t* oid;
+    int32_t* ocell;
+    __device__ __forceinline__ void move(int64_t i, int64_t d, int32_t c) const {
+        ox[0][d] = x[0][i];
+        if (ndim > 1) ox[1][d] = x[1][i];
+        if (ndim > 2) ox[2][d] = x[2][i];
+        op[0][d] = p[0][i]; op[1][d] = p[1][i]; op[2][d] = p[2][i];
         ow[d] = w[i];
         oid[d] = id(i);
-        ocell[d] = (int32_t)c;
+        ocell[d] = c;
+    }
+};
+
+// Number of entries below s in src[a, b).
+__device__ __forceinline__ uint32_t count_below(const uint32_t* __restrict__ src, int64_t a,
+                                                int64_t b, uint32_t s) {
+    uint32_t r = 0;
+    for (int64_t m = a; m < b; ++m) r += src[m] < s ? 1u : 0u;
+    return r;
+}
+
+// kSortSlots consecutive sorted slots per block.  The source indices of the cells these
+// slots belong to are staged in LDS (at most kSortWindow of them, the rest read from
+// global memory); the slot of each particle is its cell's offset plus the number of the
+// cell's source indices below its own, and the particle is copied there.
+// With XCD, neighbouring blocks of slots run on one XCD (pays where the cells are sparse
+// and a block's sources spread over many lines).
+template <typename T, bool XCD>
+__global__ void __launch_bounds__(kThreads)
+k_sort_gather(int64_t ncell, const int64_t* __restrict__ off, const uint32_t* __restrict__ idx,
+              const int64_t* __restrict__ ctrl, const int32_t* __restrict__ cell, SortIO<T> io) {
+    __shared__ uint32_t win[kSortWindow];
+    if (ctrl[0]) return;                                 // uniform over the grid
+    const int64_t total = off[ncell];
+    const int64_t j0 = (XCD ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) * kSortSlots;
+    if (j0 >= total) return;                             // uniform over the block
+    const int64_t j1 = j0 + kSortSlots < total ? j0 + kSortSlots : total;
+    // the window: every cell the block's slots belong to, clipped to kSortWindow entries
+    // around them (kSortWindow >= kSortSlots, so the slots themselves always fit)
+    int64_t wlo = off[cell[idx[j0]]], whi = off[cell[idx[j1 - 1]] + 1];
+    if (whi - wlo > kSortWindow) {
+        const int64_t lo2 = j0 - (kSortWindow - kSortSlots) / 2;
+        wlo = wlo > lo2 ? wlo : lo2;
+        whi = whi < wlo + kSortWindow ? whi : wlo + kSortWindow;
+    }
+    for (int64_t m = wlo + threadIdx.x; m < whi; m += kThreads) win[m - wlo] = idx[m];
+    __syncthreads();
+#pragma unroll 1
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t j = j0 + q * kThreads + threadIdx.x;
+        if (j >= j1) break;
+        const uint32_t s = win[j - wlo];
+        const int64_t i = (int64_t)s;
+        const int32_t c = cell[i];
+        const int64_t lo = off[c], hi = off[c + 1];
+        const int a = (int)((lo > wlo ? lo : wlo) - wlo), b = (int)((hi < whi ? hi : whi) - wlo);
+        uint32_t rank = 0;
+        for (int m = a; m < b; ++m) rank += win[m] < s ? 1u : 0u;
+        if (lo < wlo) rank += count_below(idx, lo, wlo, s);
+        if (hi > whi) rank += count_below(idx, whi, hi, s);
+        io.move(i, lo + rank, c);
     }
 }
 
@@ -2198,7 +2378,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                                      lam_in, W.code}),
                        heavy_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
                        light_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
-                       product_ratio(kp.w_gamma_prod, ax->w_ref));
+                       product_ratio(kp.w_gamma_prod, ax->w_ref),
+                       ax->off ? std::min<int64_t>(ax->n_sorted, n) : (int64_t)0);
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
            out_cap, W.ctrl, status, next_id, chain, ph ? (int)AXPIC_CHAIN_PHOTONS : -1);
@@ -2244,6 +2425,94 @@ size_t axpic_workspace_bytes(int64_t n_max) { return ws_bytes_for(n_max) + 64 * 
 namespace {
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
 }
+
+namespace {
+
+struct SortWs {
+    uint32_t *cnt, *bsum, *idx;
+    uint64_t* boff;
+    int64_t *offw, *ctrl;
+};
+
+// Workspace layout; returns its size (ws may be NULL to only size it).
+size_t sort_ws_layout(int64_t n, int64_t ncell, void* ws, SortWs* W) {
+    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
+    const size_t o_cnt = take(4 * (size_t)ncell), o_bsum = take(4 * (size_t)nblk),
+                 o_boff = take(8 * (size_t)nblk),
+                 o_idx = take(4 * (size_t)std::max<int64_t>(n, 1)),
+                 o_offw = take(8 * (size_t)(ncell + 1)), o_ctrl = take(256);
+    if (ws && W) {
+        char* p = (char*)ws;
+        W->cnt = (uint32_t*)(p + o_cnt); W->bsum = (uint32_t*)(p + o_bsum);
+        W->boff = (uint64_t*)(p + o_boff); W->idx = (uint32_t*)(p + o_idx);
+        W->offw = (int64_t*)(p + o_offw); W->ctrl = (int64_t*)(p + o_ctrl);
+    }
+    return o;
+}
+
+template <typename T>
+SortIO<T> sort_io(const axpic_grid* g, const axpic_species* in, axpic_species* out) {
+    SortIO<T> io;
+    io.ndim = 1;
+    if (in->x[1] && g->ndim > 1) io.ndim = 2;
+    if (in->x[2] && g->ndim > 2) io.ndim = 3;
+    for (int d = 0; d < 3; ++d) {
+        io.x[d] = (const T*)in->x[d]; io.p[d] = (const T*)in->p[d];
+        io.ox[d] = (T*)out->x[d]; io.op[d] = (T*)out->p[d];
+    }
+    io.w = (const T*)in->w; io.id = idv(in);
+    io.ow = (T*)out->w; io.oid = out->id; io.ocell = out->cell;
+    return io;
+}
+
+// The general sort: counts, offsets, scatter of source indices, gather with ranks.  DENSE
+// (many particles per cell) aggregates the atomics per block and walks the slots in
+// order; otherwise one atomic per run and the gather's blocks grouped by XCD.
+template <typename T, bool DENSE>
+void sort_general(const axpic_grid* g, const axpic_species* in, axpic_species* out, int64_t* off,
+                  int64_t* status, SortWs& W, hipStream_t s) {
+    const int64_t ncell = ncell_of(g), n = in->n;
+    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
+    const dim3 nb((unsigned)((n + kSortSlots - 1) / kSortSlots));
+    const T* w = (const T*)in->w;
+    LAUNCH("k_fill_u32", k_fill_u32, dim3((unsigned)std::min<int64_t>((ncell + kThreads - 1) /
+                                                                      kThreads, 8192)),
+           dim3(kThreads), 0, s, ncell, W.cnt);
+    if (n > 0)
+        LAUNCH("k_sort_count", (k_sort_count<T, DENSE>), nb, dim3(kThreads), 0, s, n, ncell, w,
+               in->cell, W.cnt);
+    LAUNCH("k_sort_blocksum", k_sort_blocksum, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell,
+           W.cnt, W.bsum);
+    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nblk, (int64_t)0,
+           out->capacity, W.ctrl, status, (uint64_t)0, (int64_t*)nullptr, 0);
+    LAUNCH("k_sort_offsets", k_sort_offsets, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell,
+           W.cnt, W.boff, W.ctrl, off);
+    if (n == 0) return;
+    LAUNCH("k_sort_scatter", (k_sort_scatter<T, DENSE>), nb, dim3(kThreads), 0, s, n, ncell, w,
+           in->cell, (const int64_t*)off, (const int64_t*)W.ctrl, W.cnt, W.idx);
+    LAUNCH("k_sort_gather", (k_sort_gather<T, !DENSE>), nb, dim3(kThreads), 0, s, ncell,
+           (const int64_t*)off, (const uint32_t*)W.idx, (const int64_t*)W.ctrl, in->cell,
+           sort_io<T>(g, in, out));
+}
+
+// The general sort's per-block aggregation of its atomics pays from kSortDense particles
+// per cell on.
+constexpr int64_t kSortDense = 32;
+
+template <typename T>
+void sort_launch(const axpic_grid* g, const axpic_species* in, int32_t path, axpic_species* out,
+                 int64_t* off, int64_t* status, SortWs& W, hipStream_t s) {
+    if (path == AXPIC_SORT_AUTO)
+        path = in->n >= kSortDense * ncell_of(g) ? AXPIC_SORT_DENSE : AXPIC_SORT_SPARSE;
+    if (path == AXPIC_SORT_DENSE)
+        sort_general<T, true>(g, in, out, off, status, W, s);
+    else
+        sort_general<T, false>(g, in, out, off, status, W, s);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -2529,16 +2798,15 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
     return launched();
 }
 
-size_t axpic_sort_ws_bytes(int64_t n, int64_t ncell) {
-    if (n < 0 || ncell < 1) return 0;
-    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
-    return align256(4 * (size_t)ncell) + align256(4 * (size_t)nblk) + align256(8 * (size_t)nblk) +
-           align256(4 * (size_t)std::max<int64_t>(n, 1)) + align256(8 * (size_t)(ncell + 1)) + 256;
+
+size_t axpic_sort_ws_bytes(const axpic_grid* g, int64_t n) {
+    if (!grid_ok(g) || n < 0) return 0;
+    return sort_ws_layout(n, ncell_of(g), nullptr, nullptr);
 }
 
-axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, axpic_species* out,
-                              int64_t* off, int64_t* status, void* ws, size_t ws_bytes,
-                              void* stream) {
+axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, int32_t path,
+                              axpic_species* out, int64_t* off, int64_t* status, void* ws,
+                              size_t ws_bytes, void* stream) {
     if (!grid_ok(g) || !species_ok(in, true) || !out || !status) return AXPIC_E_INVAL;
     if (out->dtype != in->dtype || out == in || !out->x[0] || !out->w || !out->id || !out->cell ||
         !out->p[0] || !out->p[1] || !out->p[2])
@@ -2550,52 +2818,16 @@ axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, axpi
     for (int d = 0; d < g->ndim; ++d)
         if ((in->n && !in->x[d]) || !out->x[d]) return AXPIC_E_INVAL;
     if (in->n >= ((int64_t)1 << 32)) return AXPIC_E_INVAL;
-    const int64_t ncell = ncell_of(g), n = in->n;
-    if (!ws || ws_bytes < axpic_sort_ws_bytes(n, ncell)) return AXPIC_E_INVAL;
-    const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
-    char* p = (char*)ws;
-    uint32_t* cnt = (uint32_t*)p; p += align256(4 * (size_t)ncell);
-    uint32_t* bsum = (uint32_t*)p; p += align256(4 * (size_t)nblk);
-    uint64_t* boff = (uint64_t*)p; p += align256(8 * (size_t)nblk);
-    uint32_t* idx = (uint32_t*)p; p += align256(4 * (size_t)std::max<int64_t>(n, 1));
-    int64_t* offw = (int64_t*)p; p += align256(8 * (size_t)(ncell + 1));
-    int64_t* ctrl = (int64_t*)p;
-    if (!off) off = offw;
+    if (path < AXPIC_SORT_AUTO || path > AXPIC_SORT_DENSE) return AXPIC_E_INVAL;
+    if (!ws || ws_bytes < axpic_sort_ws_bytes(g, in->n)) return AXPIC_E_INVAL;
+    SortWs W;
+    sort_ws_layout(in->n, ncell_of(g), ws, &W);
+    if (!off) off = W.offw;
     hipStream_t s = S(stream);
-    const int64_t fill_blocks = std::min<int64_t>((ncell + kThreads - 1) / kThreads, 8192);
-    LAUNCH("k_fill_u32", k_fill_u32, dim3((unsigned)fill_blocks), dim3(kThreads), 0, s, ncell, cnt);
-    if (n > 0) {
-        if (in->dtype == AXPIC_F32)
-            LAUNCH("k_sort_count", k_sort_count<float>, grid1(n), dim3(kThreads), 0, s, n, ncell,
-                   (const float*)in->w, in->cell, cnt);
-        else
-            LAUNCH("k_sort_count", k_sort_count<double>, grid1(n), dim3(kThreads), 0, s, n, ncell,
-                   (const double*)in->w, in->cell, cnt);
-    }
-    LAUNCH("k_sort_blocksum", k_sort_blocksum, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell, cnt,
-           bsum);
-    LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, bsum, boff, nblk, (int64_t)0,
-           out->capacity, ctrl, status, (uint64_t)0, (int64_t*)nullptr, 0);
-    LAUNCH("k_sort_offsets", k_sort_offsets, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell, cnt,
-           boff, ctrl, off);
-    if (n > 0) {
-        const int64_t gthreads = ncell * kSortLanes;
-        int ndim = 1;
-        if (in->x[1] && g->ndim > 1) ndim = 2;
-        if (in->x[2] && g->ndim > 2) ndim = 3;
-#define AXPIC_SORT(T)                                                                              \
-        LAUNCH("k_sort_scatter", k_sort_scatter<T>, grid1(n), dim3(kThreads), 0, s, n, ncell,      \
-               (const T*)in->w, in->cell, (const int64_t*)off, (const int64_t*)ctrl, cnt, idx);     \
-        LAUNCH("k_sort_gather", k_sort_gather<T>, grid1(gthreads), dim3(kThreads), 0, s, ncell,    \
-               (const int64_t*)off, (const uint32_t*)idx, (const int64_t*)ctrl, ndim,             \
-               (const T*)in->x[0], (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],    \
-               (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, idv(in), (T*)out->x[0],   \
-               (T*)out->x[1], (T*)out->x[2], (T*)out->p[0], (T*)out->p[1], (T*)out->p[2],         \
-               (T*)out->w, out->id, out->cell)
-        if (in->dtype == AXPIC_F32) { AXPIC_SORT(float); }
-        else { AXPIC_SORT(double); }
-#undef AXPIC_SORT
-    }
+    if (in->dtype == AXPIC_F32)
+        sort_launch<float>(g, in, path, out, off, status, W, s);
+    else
+        sort_launch<double>(g, in, path, out, off, status, W, s);
     return launched();
 }
 

@@ -45,6 +45,7 @@ class DeviceSpecies:
         self.n_sorted = 0
         self.id0 = 0
         self.n_implicit = 0
+        self.grows = 0          # reallocations after the first (each copies the buffers)
         self._alloc(max(int(capacity), 1))
 
     def _alloc(self, cap: int):
@@ -64,12 +65,14 @@ class DeviceSpecies:
         self.w = grow(self.w, td)
         self.id = grow(self.id, torch.int64)
         self.cell = grow(self.cell, torch.int32)
+        self.grows += 1 if self.capacity else 0
         self.capacity = cap
 
     def ensure(self, cap: int):
-        """Room for cap particles; grows geometrically (each growth copies the buffers)."""
+        """Room for cap particles; grows geometrically, by half at least (each growth
+        copies the buffers)."""
         if cap > self.capacity:
-            self._alloc(max(int(cap * 1.25), 2 * self.capacity) + 1024)
+            self._alloc(max(int(cap * 1.25), int(1.5 * self.capacity)) + 1024)
 
     @staticmethod
     def from_input(sp: Dict, kind: int, ndim: int, device, extra: int = 0) -> "DeviceSpecies":
@@ -154,6 +157,7 @@ class AxpicSim:
                  photon_extra: int = 0, compact_every: int = 0, stream=None, surrogate=None,
                  thermal: str = "particle", surrogate_mode: str = "particle", sort: bool = True):
         self.lib = B.load()
+        self._allocs = 0            # workspaces and spare buffers made (see reallocations)
         self.device = torch.device(device)
         self.pdict = dict(params if isinstance(params, dict) else params.as_dict())
         self.params = B.make_params(self.pdict)
@@ -268,6 +272,13 @@ class AxpicSim:
             need = int(need * 1.25) + 4096
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             self.ws_bytes = need
+            self._allocs += 1
+
+    def reallocations(self) -> int:
+        """Device buffers (re)allocated so far after set-up: particle buffers grown, spare
+        buffers and workspaces made or enlarged (a step without any allocates nothing)."""
+        sp = [self.el, self.ion, self.ph, self.ax] + list(self._spare.values())
+        return self._allocs + sum(s.grows for s in sp)
 
     def cell_state(self):
         B.check(self.lib.axpic_cell_state(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
@@ -362,10 +373,13 @@ class AxpicSim:
                 "feedback")
 
     def bin_axions(self, push: bool = True):
+        """Push and re-bin the axions; a push takes them out of their cell order."""
         if self.ax.n:
             B.check(self.lib.axpic_bin_cells(B.ref(self.grid), B.ref(self.ax.struct()),
                                              1 if push else 0, float(self.pdict["m_a_keV"]),
                                              self.sh), "bin_cells")
+            if push:
+                self.ax.off, self.ax.n_sorted = None, 0
 
     def sort_axions(self):
         """The axions in the canonical order (axpic_sort_cells) in the spare buffer, which
@@ -377,13 +391,16 @@ class AxpicSim:
         if spare is None or spare.capacity < ax.n:
             spare = DeviceSpecies(B.AXION, self.dtype, self.ndim, ax.capacity, ax.w_ref,
                                   self.device)
-        need = int(self.lib.axpic_sort_ws_bytes(ax.n, self.ncell))
+            self._allocs += 1
+        # sized for the buffer's capacity: it grows only with the buffer
+        need = int(self.lib.axpic_sort_ws_bytes(B.ref(self.grid), ax.n))
         if self.sort_ws is None or self.sort_ws.numel() < need:
-            self.sort_ws = torch.empty(int(need * 1.25) + 4096, dtype=torch.uint8,
-                                       device=self.device)
+            need = int(self.lib.axpic_sort_ws_bytes(B.ref(self.grid), max(ax.n, ax.capacity)))
+            self.sort_ws = torch.empty(need + 4096, dtype=torch.uint8, device=self.device)
+            self._allocs += 1
         spare.n, spare.off, spare.n_sorted, spare.id0, spare.n_implicit = 0, None, 0, 0, 0
         spare._S = None
-        B.check(self.lib.axpic_sort_cells(B.ref(self.grid), B.ref(ax.struct()),
+        B.check(self.lib.axpic_sort_cells(B.ref(self.grid), B.ref(ax.struct()), B.SORT_AUTO,
                                           B.ref(spare.struct()), B.ptr(self.ax_off),
                                           B.ptr(self.sort_status), B.ptr(self.sort_ws),
                                           self.sort_ws.numel(), self.sh), "sort_cells")
@@ -406,6 +423,7 @@ class AxpicSim:
         if spare is None or spare.capacity < sp.n or spare.w_ref != sp.w_ref:
             spare = DeviceSpecies(sp.kind, self.dtype, self.ndim, sp.capacity, sp.w_ref,
                                   self.device, sp.Z, sp.A)
+            self._allocs += 1
         out = spare
         out.n, out.off, out.n_sorted, out.id0, out.n_implicit = 0, None, 0, 0, 0
         out._S = None
@@ -476,7 +494,7 @@ class AxpicSim:
             self.ax.ensure(self.ax.n + 2 * self._last_new[0] + 4096)
             if p["inverse"] and p["channels"] & B.PRIMAKOFF:
                 self.ph.ensure(self.ph.n + 2 * self._last_new[1] + 1024)
-        self._ensure_ws(max(self.el.n, self.ph.n, n_ax0, 4 * self.ncell))
+        self._ensure_ws(max(self.el.capacity, self.ph.capacity, self.ax.capacity, 4 * self.ncell))
         S = self.surrogate
         lam = pab = lag = None
         if S and self.surrogate_mode == "table":

@@ -149,3 +149,23 @@ def test_allocation_free_diag_rejects_species_beyond_its_scratch_on_host():
     assert L.axpic_status_string(-6).startswith(b"input exceeds the static scratch")
     assert L.axpic_diag_noalloc(B.ref(sp), -1.0, out.ctypes.data, None) == -1
     assert L.axpic_diag_noalloc(B.ref(sp), 0.0, None, None) == -1
+
+
+def test_sort_rejects_invalid_arguments_on_host():
+    """axpic_sort_cells: a path outside the three or a short workspace are refused before
+    any launch."""
+    L = B.load()
+    g = B.make_grid(dict(ndim=2, n=(8, 6, 1), dx=0.2, dt=0.1, omega0=1e17))
+    fake = 1 << 20                       # never dereferenced: the call returns first
+    sp, out = B.SpeciesC(), B.SpeciesC()
+    for s, a in ((sp, fake), (out, fake + 64)):
+        s.x[0] = s.x[1] = s.p[0] = s.p[1] = s.p[2] = s.w = s.id = s.cell = a
+        s.n, s.capacity = 10, 10
+    st = np.zeros(4, np.int64)
+    need = L.axpic_sort_ws_bytes(B.ref(g), 10)
+    assert need > 0
+    for path in (3, -1):
+        assert L.axpic_sort_cells(B.ref(g), B.ref(sp), path, B.ref(out), None, st.ctypes.data,
+                                  fake, need, None) == -1
+    assert L.axpic_sort_cells(B.ref(g), B.ref(sp), 0, B.ref(out), None, st.ctypes.data, fake,
+                              need - 1, None) == -1

@@ -169,7 +169,7 @@ typedef struct {
     double T_floor_keV, T_ceil_keV;
     uint64_t seed;
     double hist_lo_keV, hist_hi_keV;
-    int32_t hist_nbins;     /* histogram bins (+2 under/overflow slots) per channel */
+    int32_t hist_nbins;     /* histogram bins (+2 under/overflow slots) per channel, <= 1000 */
     int32_t hist_log;       /* 1: logarithmic bins */
     double m_a_keV;         /* axion mass [keV]; 0: massless.  Sec. II.B gives only the
                                kinematics E = sqrt(p^2 + m^2); with m > 0 the push moves at

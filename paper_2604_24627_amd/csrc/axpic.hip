@@ -37,9 +37,10 @@ constexpr int kPer = 4;                // parents per thread in the count/apply 
 constexpr int kBlockParents = kThreads * kPer;
 static_assert(kPer == 4, "st_codes packs four 16-bit codes per thread");
 constexpr int kStatSlots = 12;         // per-thread statistics registers
-constexpr int kMaxBins = 1024;         // histogram bins per channel (+2 under/overflow)
-constexpr int kCopies = 32;            // privatised accumulator copies (histogram + statistics)
-constexpr int kAccStride = 3 * (kMaxBins + 2) + 32;
+// histogram bins per channel (+2 under/overflow); the events kernels hold a private copy
+// of two channels per wavefront in LDS: 4 x 2 x 1002 doubles stay within 64 KiB
+constexpr int kMaxBins = 1000;
+constexpr int kRecMax = 2 * (kMaxBins + 2) + AXPIC_ST_COUNT;   // doubles of a block's record
 constexpr int kScanThreads = 1024;
 constexpr int kEventBlocks = 1024;     // grid of the event kernels (grid-stride over events)
 
@@ -60,18 +61,28 @@ struct Workspace {
     uint32_t* bsum;      // [nb] products per block
     uint32_t* bact;      // [nb] active parents per block
     uint64_t* boff;      // [nb] exclusive product offsets
-    double* acc;         // [kCopies][kAccStride] privatised histogram + statistics
+    double* rec;         // per-block records: histogram bins, then statistics
+    int32_t* bkey;       // [2 nbmax] boundary cells of the blocks (fixed-order fb sums)
+    double* bval;        // [2 nbmax][4] their sums
     int64_t* ctrl;       // [8]: 0 skip flag, 1 total
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 inline int64_t nblocks_for(int64_t n) { return (n + kBlockParents - 1) / kBlockParents; }
 
+// records: an events kernel's grid of histogram + statistics records, or one statistics
+// record per block of parents; boundary records: two per block of either
+size_t rec_doubles(int64_t nb) {
+    return std::max<size_t>((size_t)kEventBlocks * kRecMax, (size_t)nb * AXPIC_ST_COUNT);
+}
+size_t bnd_count(int64_t nb) { return 2 * (size_t)std::max<int64_t>(kEventBlocks, nb); }
+
 size_t ws_bytes_for(int64_t n) {
     int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
     return align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1)) + align256(4 * (size_t)nb) +
            align256(4 * (size_t)nb) + align256(8 * (size_t)nb) +
-           align256(sizeof(double) * kCopies * (size_t)kAccStride) + 256;
+           align256(sizeof(double) * rec_doubles(nb)) + align256(4 * bnd_count(nb)) +
+           align256(sizeof(double) * 4 * bnd_count(nb)) + 256;
 }
 
 bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
@@ -82,7 +93,9 @@ bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
     w->bsum = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->bact = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->boff = (uint64_t*)p; p += align256(8 * (size_t)nb);
-    w->acc = (double*)p; p += align256(sizeof(double) * kCopies * (size_t)kAccStride);
+    w->rec = (double*)p; p += align256(sizeof(double) * rec_doubles(nb));
+    w->bkey = (int32_t*)p; p += align256(4 * bnd_count(nb));
+    w->bval = (double*)p; p += align256(sizeof(double) * 4 * bnd_count(nb));
     w->ctrl = (int64_t*)p;
     return true;
 }
@@ -332,32 +345,217 @@ __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* lds_w) {
 
 struct StatMap { int m[kStatSlots]; };
 
-// Flush per-thread statistics into this block's accumulator copy: one FP64
-// atomic per wavefront and non-zero slot, skipped by waves without events.
-__device__ __forceinline__ void stats_flush(const double* st, bool any, double* A, int nbh,
-                                            const StatMap& map) {
-    if (!__any(any)) return;
+// ------------------------------------------------------------------ fixed-order sums
+// The FP64 sums of the operators -- histograms, statistics, the per-cell exchange fb --
+// take no floating-point atomics: within a wavefront they run through fixed shuffle
+// trees, across the wavefronts and tiles of a block in a fixed sequence, and across
+// blocks through per-block records summed in block order (k_acc_reduce) and the cells
+// a block shares with its neighbours (k_fb_bounds).  Repeated runs give the same bits.
+
+// Adds v at bin (bin < 0: nothing) to this wavefront's private histogram h: the 64
+// (bin, lane) pairs sorted by a bitonic network, equal bins summed by a segmented
+// scan, one add per distinct bin.  Every lane of the wavefront must call it.
+__device__ __forceinline__ void wave_hist_add(double* __restrict__ h, int bin, double v) {
     const int lane = threadIdx.x & 63;
+    if (!__any(bin >= 0)) return;
+    uint32_t key = bin >= 0 ? ((uint32_t)bin << 6) | (uint32_t)lane : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t ok = __shfl_xor(key, j, 64);
+            const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+            if (lower == up ? ok < key : ok > key) key = ok;
+        }
+    }
+    // the keys carry their lane: the values follow in one gather
+    double val = __shfl(bin >= 0 ? v : 0.0, (int)(key & 63u), 64);
+    const uint32_t b = key >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double pv = __shfl_up(val, o, 64);
+        const uint32_t pb = __shfl_up(b, o, 64);
+        if (lane >= o && pb == b) val += pv;
+    }
+    const uint32_t nb = __shfl_down(b, 1, 64);
+    if (key != 0xFFFFFFFFu && (lane == 63 || nb != b)) h[b] += val;
+}
+
+// The block's record: histogram column k = the wavefronts' private copies (wh, h columns
+// each) summed in order; then the statistics, st of each thread through the wavefront
+// butterfly and the wavefronts in order into the slots map names (every other statistics
+// column 0).  Column k at rec[k * cstride].  lds: kThreads/64 * kStatSlots doubles.
+__device__ __forceinline__ void rec_write(const double* wh, int h, const double* st,
+                                          const StatMap& map, double* lds,
+                                          double* __restrict__ rec, int64_t cstride = 1) {
+    constexpr int kWaves = kThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kStatSlots; ++k) {
-        if (map.m[k] < 0) continue;
         const double v = wave_sum(st[k]);
-        if (lane == 0 && v != 0.0) atomicAdd(A + 3 * nbh + map.m[k], v);
+        if (lane == 0) lds[wave * kStatSlots + k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < h; k += kThreads) {
+        double s = 0.0;
+        for (int w2 = 0; w2 < kWaves; ++w2) s += wh[w2 * h + k];
+        rec[k * cstride] = s;
+    }
+    for (int k = threadIdx.x; k < AXPIC_ST_COUNT; k += kThreads) {
+        double s = 0.0;
+        for (int q = 0; q < kStatSlots; ++q)
+            if (map.m[q] == k)
+                for (int w2 = 0; w2 < kWaves; ++w2) s += lds[w2 * kStatSlots + q];
+        rec[(h + k) * cstride] = s;
     }
 }
 
-// The power histogram of an event workgroup, accumulated in LDS (slots lo .. lo + n - 1
-// of the accumulator record) and added to the workgroup's accumulator copy once, bin by
-// bin: one global atomic per touched bin and workgroup instead of one per event.
-__device__ __forceinline__ void lds_hist_clear(double* __restrict__ h, int n) {
-    for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = 0.0;
-    __syncthreads();
+// Per-cell exchange sums over a block's events in their (cell-ordered) sequence.  Each
+// tile of kThreads events: a segmented scan per wavefront; the runs inside a wavefront
+// are whole cells of this block and are added to fb at once; the first and last run of
+// each wavefront are stitched by thread 0 in sequence.  The block's first and last cell
+// may continue in the neighbouring blocks: they go to its two boundary records (key,
+// four sums), which k_fb_bounds adds up.  Events past the block's range carry key -1
+// and come last.
+struct FbStitch {
+    int32_t fkey[kThreads / 64], lkey[kThreads / 64];     // lkey -2: one run only
+    double fs[kThreads / 64][4], ls[kThreads / 64][4];
+    int32_t dkey[2 * (kThreads / 64)];                    // runs completed by the stitching,
+    double ds[2 * (kThreads / 64)][4];                    // added to fb by as many threads
+    int32_t nd;
+};
+struct FbOpen {                 // thread 0's state across the tiles of a block
+    int32_t key = -1;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    bool first_done = false;
+};
+
+// A completed run: the block's first to its first boundary record, any later one to the
+// list S (added to fb after the tile's barrier; runs summing to zero are skipped, S NULL:
+// added here).
+__device__ __forceinline__ void fb_close(FbOpen& o, FbStitch* S, double* __restrict__ fb,
+                                         int32_t* __restrict__ bkey, double* __restrict__ bval,
+                                         int64_t b) {
+    if (o.key < 0) return;
+    if (!o.first_done) {
+        bkey[2 * b] = o.key;
+        for (int q = 0; q < 4; ++q) bval[8 * b + q] = o.s[q];
+        o.first_done = true;
+    } else if (o.s[0] != 0.0 || o.s[1] != 0.0 || o.s[2] != 0.0 || o.s[3] != 0.0) {
+        if (S) {
+            S->dkey[S->nd] = o.key;
+            for (int q = 0; q < 4; ++q) S->ds[S->nd][q] = o.s[q];
+            ++S->nd;
+        } else {
+            double* f = fb + (int64_t)o.key * 4;
+            for (int q = 0; q < 4; ++q) f[q] += o.s[q];
+        }
+    }
 }
-__device__ __forceinline__ void lds_hist_flush(const double* __restrict__ h, int n,
-                                               double* __restrict__ A) {
+
+__device__ __forceinline__ void fb_tile(FbStitch& S, FbOpen& o, int32_t key, const double* v,
+                                        double* __restrict__ fb, int32_t* __restrict__ bkey,
+                                        double* __restrict__ bval, int64_t b) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double s[4] = {v[0], v[1], v[2], v[3]};
+    // a wavefront without exchange has every run sum zero: no scan, no interior add
+    const bool some = __any(v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0 || v[3] != 0.0);
+    if (some) {
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t pk = __shfl_up(key, off, 64);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double pv = __shfl_up(s[q], off, 64);
+                if (lane >= off && pk == key) s[q] += pv;
+            }
+        }
+    }
+    const int32_t nk = __shfl_down(key, 1, 64);
+    const int32_t k0 = __shfl(key, 0, 64);
+    const bool tail = key >= 0 && (lane == 63 || nk != key);
+    const bool first = key == k0;                        // the run holding lane 0
+    const bool last = lane == 63 || nk < 0;              // the wavefront's last event run
+    if (some && tail && !first && !last) {
+        double* f = fb + (int64_t)key * 4;
+        for (int q = 0; q < 4; ++q) f[q] += s[q];
+    }
+    // lane 0's words first, then the tail lanes' (one wavefront: program order)
+    if (lane == 0) { S.fkey[wave] = k0; S.lkey[wave] = -2; }
+    if (tail && first) for (int q = 0; q < 4; ++q) S.fs[wave][q] = s[q];
+    if (tail && last && !first) {
+        S.lkey[wave] = key;
+        for (int q = 0; q < 4; ++q) S.ls[wave][q] = s[q];
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        if (h[k] != 0.0) atomicAdd(&A[k], h[k]);
+    if (threadIdx.x == 0) {
+        S.nd = 0;
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) {
+            if (S.fkey[w2] < 0) break;                   // no event here nor after
+            if (S.fkey[w2] == o.key) {
+                for (int q = 0; q < 4; ++q) o.s[q] += S.fs[w2][q];
+            } else {
+                fb_close(o, &S, fb, bkey, bval, b);
+                o.key = S.fkey[w2];
+                for (int q = 0; q < 4; ++q) o.s[q] = S.fs[w2][q];
+            }
+            if (S.lkey[w2] != -2) {
+                fb_close(o, &S, fb, bkey, bval, b);
+                o.key = S.lkey[w2];
+                for (int q = 0; q < 4; ++q) o.s[q] = S.ls[w2][q];
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < S.nd) {                       // distinct cells, one thread each
+        double* f = fb + (int64_t)S.dkey[threadIdx.x] * 4;
+        for (int q = 0; q < 4; ++q) f[q] += S.ds[threadIdx.x][q];
+    }
+}
+
+// Thread 0 at the end of a block: the last run to the second boundary record (a block of
+// one run has it in the first, and the second holds the same key and zeros).
+__device__ __forceinline__ void fb_finish(FbOpen& o, double* __restrict__ fb,
+                                          int32_t* __restrict__ bkey, double* __restrict__ bval,
+                                          int64_t b) {
+    if (threadIdx.x != 0) return;
+    if (!o.first_done) {
+        fb_close(o, nullptr, fb, bkey, bval, b);
+        bkey[2 * b + 1] = o.key;
+        for (int q = 0; q < 4; ++q) bval[8 * b + 4 + q] = 0.0;
+        if (o.key < 0) bkey[2 * b] = -1;
+    } else {
+        bkey[2 * b + 1] = o.key;
+        for (int q = 0; q < 4; ++q) bval[8 * b + 4 + q] = o.s[q];
+    }
+}
+
+// The boundary records of nb blocks in block order: each first record of a run of equal
+// keys sums the run in order and adds it to fb (key -1: none).  Nothing after an overflow.
+__global__ void __launch_bounds__(kThreads)
+k_fb_bounds(int64_t nb, const int32_t* __restrict__ bkey, const double* __restrict__ bval,
+            const int64_t* __restrict__ ctrl, double* __restrict__ fb) {
+    if (ctrl[0]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * nb) return;
+    const int32_t k = bkey[i];
+    if (k < 0 || (i > 0 && bkey[i - 1] == k)) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = i; j < 2 * nb && bkey[j] == k; ++j)
+        for (int q = 0; q < 4; ++q) s[q] += bval[4 * j + q];
+    double* f = fb + (int64_t)k * 4;
+    for (int q = 0; q < 4; ++q) f[q] += s[q];
+}
+
+// The contiguous range of events of block b when `total` events are split over the
+// grid (as many blocks as there are tiles of kThreads events, at most the grid).
+__device__ __forceinline__ void ev_range(int64_t total, int64_t* lo, int64_t* hi) {
+    const int64_t tiles = (total + kThreads - 1) / kThreads;
+    const int64_t ga = tiles < (int64_t)gridDim.x ? tiles : (int64_t)gridDim.x;
+    const int64_t b = blockIdx.x;
+    if (b >= ga) { *lo = *hi = 0; return; }
+    *lo = total * b / ga;
+    *hi = total * (b + 1) / ga;
 }
 
 // ------------------------------------------------------------------ scan kernel
@@ -450,27 +648,25 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
     }
 }
 
-// Clears the used part of the privatised accumulator copies; every count
-// kernel's grid does it for the events kernel that follows it on the stream.
-__device__ __forceinline__ void clear_acc(double* __restrict__ acc, int acc_n) {
-    if (!acc) return;
-    const int64_t total = (int64_t)kCopies * acc_n;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
-         j += (int64_t)gridDim.x * blockDim.x)
-        acc[(j / acc_n) * kAccStride + j % acc_n] = 0.0;
-}
-
-// Fixed-order sum of the accumulator copies into hist[3][nbh] and stats[].
+// Column j of the nrec records (record r's column j at rec[r * rstride + j * cstride], in
+// block order): histogram column j < nh into hist[j], the others into stats[j - nh].  One
+// block per column: each thread sums its records in order, then the wavefront butterfly
+// and the wavefronts in order.
 __global__ void __launch_bounds__(kThreads)
-k_acc_reduce(const double* __restrict__ acc, int nbh, const int64_t* __restrict__ ctrl,
-             double* __restrict__ hist, double* __restrict__ stats) {
+k_acc_reduce(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int64_t cstride,
+             int nh, const int64_t* __restrict__ ctrl, double* __restrict__ hist,
+             double* __restrict__ stats) {
+    __shared__ double lds[kThreads / 64];
     if (ctrl[0]) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nh = 3 * nbh;
-    if (j >= nh + AXPIC_ST_COUNT) return;
-    const int src = j < nh ? j : 3 * nbh + (j - nh);
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int c = 0; c < kCopies; ++c) s += acc[(int64_t)c * kAccStride + src];
+    for (int64_t r = threadIdx.x; r < nrec; r += kThreads) s += rec[r * rstride + j * cstride];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    s = 0.0;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) s += lds[w2];
     if (s == 0.0) return;
     if (j < nh) { if (hist) hist[j] += s; }
     else if (stats) stats[j - nh] += s;
@@ -712,9 +908,8 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
              uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
-             double* __restrict__ acc, int acc_n, int aligned, float wt_heavy,
+             int aligned, float wt_heavy,
              const int64_t* __restrict__ off, int64_t n_sorted) {
-    clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     __shared__ int32_t s_bnd[kStageCells];
     __shared__ float4 s_pref[kStageCells];
@@ -826,69 +1021,74 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
               const uint16_t* __restrict__ code, const int64_t* __restrict__ ctrl, int64_t out_n,
               T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx,
               T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
-              uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ acc,
+              uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ rec,
               StatMap smap) {
-    extern __shared__ double hl[];                          // channel 0's bins
+    extern __shared__ double wh[];                          // per wavefront: channel 0's bins
+    __shared__ double lst[(kThreads / 64) * kStatSlots];
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
-    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
-    lds_hist_clear(hl, nbh);
+    for (int k = threadIdx.x; k < (kThreads / 64) * nbh; k += kThreads) wh[k] = 0.0;
+    __syncthreads();
+    double* myh = wh + (threadIdx.x >> 6) * nbh;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
-    bool any = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-        const uint64_t rc = aid[out_n + e];
-        aid[out_n + e] = (next_id + (uint64_t)e) | (1ull << 63);
-        if (((rc >> 40) & 0xFFu) != 0) continue;          // not the parent's first event
+    int64_t lo, hi;
+    ev_range(total, &lo, &hi);
+    for (int64_t t0 = lo; t0 < hi; t0 += kThreads) {
+        const int64_t e = t0 + threadIdx.x;
+        int bin = -1;
+        double hv = 0.0;
+        // the parent's first event writes its K products
+        const uint64_t rc = e < hi ? aid[out_n + e] : 0ull;
+        if (e < hi) aid[out_n + e] = (next_id + (uint64_t)e) | (1ull << 63);
         const int64_t i = (int64_t)(rc & kRecParentMask);
-        if (i >= n) continue;                              // never for a well-formed record
-        const uint32_t K = code[i] & 0xFFu;
-        if ((int64_t)K > total - e) continue;
-        const T wt = w[i];
-        const T* pci = pref + (int64_t)cell[i] * AXPIC_PREF_N;
-        const T l = lam_in ? lam_in[i]
-                           : (M ? lambda_primakoff_m<T>(kp, pci, wt, psq_d<T>(px, py, pz, i))
-                                : lambda_primakoff<T>(pci, wt, psq<T>(px, py, pz, i)));
-        double ws; int cp;
-        (void)cap_lambda((double)l, kp.cap, &ws, &cp);
-        double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
-        const double wpar = w_ref_g * (double)wt;
-        double dep = (double)K * wp;
-        const bool over = dep > wpar;
-        if (over) { wp = wpar / (double)K; dep = wpar; }
-        T pxv = px[i], pyv = py[i], pzv = pz[i];
-        const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
-        if (M) {                  // the axion keeps the photon's energy: |p| = sqrt(E^2 - m^2)
-            const double sc = E > kp.m_a ? sqrt((E - kp.m_a) * (E + kp.m_a)) / E : 0.0;
-            pxv = (T)((double)pxv * sc); pyv = (T)((double)pyv * sc); pzv = (T)((double)pzv * sc);
+        const uint32_t K = (e < hi && i < n) ? code[i] & 0xFFu : 0u;
+        if (e < hi && ((rc >> 40) & 0xFFu) == 0 && i < n && (int64_t)K <= total - e) {
+            const T wt = w[i];
+            const T* pci = pref + (int64_t)cell[i] * AXPIC_PREF_N;
+            const T l = lam_in ? lam_in[i]
+                               : (M ? lambda_primakoff_m<T>(kp, pci, wt, psq_d<T>(px, py, pz, i))
+                                    : lambda_primakoff<T>(pci, wt, psq<T>(px, py, pz, i)));
+            double ws; int cp;
+            (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+            double wp = kp.w_a * kp.wa_mul[0] * ws;            // physical product weight
+            const double wpar = w_ref_g * (double)wt;
+            double dep = (double)K * wp;
+            const bool over = dep > wpar;
+            if (over) { wp = wpar / (double)K; dep = wpar; }
+            T pxv = px[i], pyv = py[i], pzv = pz[i];
+            const double E = kMe * sqrt((double)pxv * pxv + (double)pyv * pyv + (double)pzv * pzv);
+            if (M) {              // the axion keeps the photon's energy: |p| = sqrt(E^2 - m^2)
+                const double sc = E > kp.m_a ? sqrt((E - kp.m_a) * (E + kp.m_a)) / E : 0.0;
+                pxv = (T)((double)pxv * sc); pyv = (T)((double)pyv * sc); pzv = (T)((double)pzv * sc);
+            }
+            const T xv0 = x0[i], xv1 = x1 ? x1[i] : (T)0, xv2 = x2 ? x2[i] : (T)0;
+            const T wrel = (T)(wp / kp.w_a);
+            const int32_t c = cell[i];
+            for (uint32_t k = 0; k < K; ++k) {
+                const int64_t slot = out_n + e + k;
+                ax0[slot] = xv0;
+                if (ax1) ax1[slot] = xv1;
+                if (ax2) ax2[slot] = xv2;
+                apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
+                aw[slot] = wrel;
+                acell[slot] = c;
+            }
+            bin = hist_bin(kp, E);
+            hv = (double)K * wp * E;
+            st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
+            st[9] += cp ? 1.0 : 0.0;
+            st[10] += over ? 1.0 : 0.0;
+            w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
         }
-        const T xv0 = x0[i], xv1 = x1 ? x1[i] : (T)0, xv2 = x2 ? x2[i] : (T)0;
-        const T wrel = (T)(wp / kp.w_a);
-        const int32_t c = cell[i];
-        const int bin = hist_bin(kp, E);
-        for (uint32_t k = 0; k < K; ++k) {
-            const int64_t slot = out_n + e + k;
-            ax0[slot] = xv0;
-            if (ax1) ax1[slot] = xv1;
-            if (ax2) ax2[slot] = xv2;
-            apx[slot] = pxv; apy[slot] = pyv; apz[slot] = pzv;
-            aw[slot] = wrel;
-            acell[slot] = c;
-        }
-        atomicAdd(&hl[bin], (double)K * wp * E);
-        st[0] += (double)K; st[3] += (double)K * wp; st[6] += (double)K * wp * E;
-        st[9] += cp ? 1.0 : 0.0;
-        st[10] += over ? 1.0 : 0.0;
-        any = true;
-        w[i] = (dep >= wpar) ? (T)0 : (T)((wpar - dep) / w_ref_g);
+        wave_hist_add(myh, bin, hv);
     }
-    lds_hist_flush(hl, nbh, A);
-    stats_flush(st, any, A, nbh, smap);
+    __syncthreads();
+    rec_write(wh, nbh, st, smap, lst, rec + (int64_t)blockIdx.x * (nbh + AXPIC_ST_COUNT));
 }
 
 // ------------------------------------------------------------------ thermal emission
@@ -955,8 +1155,7 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
               IdView id, const int32_t* __restrict__ cell,
               const T* __restrict__ lam_in, uint16_t* __restrict__ code,
               uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
-              double* __restrict__ acc, int acc_n, int aligned) {
-    clear_acc(acc, acc_n);
+              int aligned) {
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -985,67 +1184,76 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
                const int64_t* __restrict__ ctrl, int64_t out_n, T* __restrict__ ax0,
                T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx, T* __restrict__ apy,
                T* __restrict__ apz, T* __restrict__ aw, uint64_t* __restrict__ aid,
-               int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
-               StatMap smap) {
-    extern __shared__ double hl[];                          // channels 1 and 2's bins
+               int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ rec,
+               int32_t* __restrict__ bkey, double* __restrict__ bval, StatMap smap) {
+    extern __shared__ double wh[];                          // per wavefront: channels 1, 2
+    __shared__ double lst[(kThreads / 64) * kStatSlots];
+    __shared__ FbStitch fbs;
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
-    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
-    lds_hist_clear(hl, 2 * nbh);
+    const int H = 2 * nbh;
+    for (int k = threadIdx.x; k < (kThreads / 64) * H; k += kThreads) wh[k] = 0.0;
+    __syncthreads();
+    double* myh = wh + (threadIdx.x >> 6) * H;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
-    bool any = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    FbOpen open;
+    int64_t lo, hi;
+    ev_range(total, &lo, &hi);
+    for (int64_t t0 = lo; t0 < hi; t0 += kThreads) {
+        const int64_t e = t0 + threadIdx.x;
         const int64_t slot = out_n + e;
-        const uint64_t rc = aid[slot];
+        const uint64_t rc = e < hi ? aid[slot] : 0ull;
         const int64_t i = (int64_t)(rc & kRecParentMask);
         const uint32_t k = (uint32_t)((rc >> 40) & 0xFFu);
         const int ch = (int)((rc >> 48) & 0xFFu);          // 1 Compton, 2 brems
-        if (i >= n || (ch != 1 && ch != 2)) continue;      // never for a well-formed record
-        const int32_t c = cell[i];
-        const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
-        const double Tc = state[(int64_t)c * AXPIC_STATE_N + 0];
-        const T l = lam_in ? lam_in[(int64_t)(ch - 1) * n + i] : w[i] * pc[3 + ch];
-        double ws; int cp;
-        (void)cap_lambda((double)l, kp.cap, &ws, &cp);
-        const double wp = kp.w_a * kp.wa_mul[ch] * ws;
-        const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
-        const uint4 r = draw(kp, id(i), step, 1 + ch, k);
-        double E, pm;
-        thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
-        const double eu = M ? E / kMe : pm;                // energy in m_e c^2
-        const double mu = 2.0 * u24(r.y) - 1.0;
-        const double phi = 2.0 * kPi * u24(r.z);
-        const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
-        double sphi, cphi;
-        sincos(phi, &sphi, &cphi);
-        const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
-        ax0[slot] = x0[i];
-        if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
-        if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
-        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
-        aw[slot] = (T)(kp.wa_mul[ch] * ws);
-        aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
-        acell[slot] = c;
-        atomicAdd(&hl[(ch - 1) * nbh + hist_bin(kp, E)], wp * E);
-        if (fb) {
-            double* f = fb + (int64_t)c * 4;
-            atomicAdd(&f[0], -wp * eu);
-            atomicAdd(&f[1], -wp * pa[0]);
-            atomicAdd(&f[2], -wp * pa[1]);
-            atomicAdd(&f[3], -wp * pa[2]);
+        int bin = -1;
+        double hv = 0.0;
+        int32_t key = -1;                                   // the product's cell
+        double fv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (e < hi && i < n && (ch == 1 || ch == 2)) {      // always, for a well-formed record
+            const int32_t c = cell[i];
+            const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
+            const double Tc = state[(int64_t)c * AXPIC_STATE_N + 0];
+            const T l = lam_in ? lam_in[(int64_t)(ch - 1) * n + i] : w[i] * pc[3 + ch];
+            double ws; int cp;
+            (void)cap_lambda((double)l, kp.cap, &ws, &cp);
+            const double wp = kp.w_a * kp.wa_mul[ch] * ws;
+            const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
+            const uint4 r = draw(kp, id(i), step, 1 + ch, k);
+            double E, pm;
+            thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
+            const double eu = M ? E / kMe : pm;            // energy in m_e c^2
+            const double mu = 2.0 * u24(r.y) - 1.0;
+            const double phi = 2.0 * kPi * u24(r.z);
+            const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+            double sphi, cphi;
+            sincos(phi, &sphi, &cphi);
+            const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
+            ax0[slot] = x0[i];
+            if (ax1) ax1[slot] = x1 ? x1[i] : (T)0;
+            if (ax2) ax2[slot] = x2 ? x2[i] : (T)0;
+            apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
+            aw[slot] = (T)(kp.wa_mul[ch] * ws);
+            aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
+            acell[slot] = c;
+            bin = (ch - 1) * nbh + hist_bin(kp, E);
+            hv = wp * E;
+            key = c;
+            fv[0] = -wp * eu; fv[1] = -wp * pa[0]; fv[2] = -wp * pa[1]; fv[3] = -wp * pa[2];
+            st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
+            if (k == 0) st[9] += cp ? 1.0 : 0.0;
         }
-        st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
-        if (k == 0) st[9] += cp ? 1.0 : 0.0;
-        any = true;
+        wave_hist_add(myh, bin, hv);
+        if (fb) fb_tile(fbs, open, key, fv, fb, bkey, bval, blockIdx.x);
     }
-    lds_hist_flush(hl, 2 * nbh, A + nbh);
-    stats_flush(st, any, A, nbh, smap);
+    if (fb) fb_finish(open, fb, bkey, bval, blockIdx.x);
+    __syncthreads();
+    rec_write(wh, H, st, smap, lst, rec + (int64_t)blockIdx.x * (H + AXPIC_ST_COUNT));
 }
 
 // ------------------------------------------------------------------ absorption
@@ -1161,9 +1369,8 @@ k_abs_count(int64_t n, int64_t step, KParams kp, double w_ref_a, const float* __
             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
-            uint32_t* __restrict__ bact, double* __restrict__ acc, int acc_n, int aligned,
+            uint32_t* __restrict__ bact, int aligned,
             float wt_heavy, float wt_light, float prod_ratio, int64_t n_sorted) {
-    clear_acc(acc, acc_n);
     __shared__ uint32_t lds[kThreads / 64];
     __shared__ float4 s_pref[2 * kStageCells];
     const T* pref = PrefOf<T>::get(p32, p64);
@@ -1217,19 +1424,32 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gpx, T* __restrict__ gpy,
             T* __restrict__ gpz, T* __restrict__ gw, uint64_t* __restrict__ gid,
             int32_t* __restrict__ gcell, double w_ref_g, double* __restrict__ fb,
-            double* __restrict__ acc, StatMap smap) {
+            double* __restrict__ rec, int32_t* __restrict__ bkey, double* __restrict__ bval,
+            int det, StatMap smap) {
     __shared__ uint32_t lds[kThreads / 64];
-    if (ctrl[0] || bact[blockIdx.x] == 0) return;
+    __shared__ double lst[(kThreads / 64) * kStatSlots];
+    __shared__ FbStitch fbs;
+    if (ctrl[0]) return;
+    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
+    double* myrec = rec + blockIdx.x;                  // column-major: nb records
+    const bool fixed = det && fb;       // fb in fixed order: the axions are in cell order
+    if (bact[blockIdx.x] == 0) {        // nothing to apply: a zero record and boundary cells
+        for (int k = threadIdx.x; k < AXPIC_ST_COUNT; k += kThreads) myrec[k * gridDim.x] = 0.0;
+        if (fixed && threadIdx.x == 0) {
+            const int64_t last = (base + kBlockParents < n ? base + kBlockParents : n) - 1;
+            bkey[2 * blockIdx.x] = base < n ? cell[base] : -1;
+            bkey[2 * blockIdx.x + 1] = base < n ? cell[last] : -1;
+            for (int q = 0; q < 8; ++q) bval[8 * blockIdx.x + q] = 0.0;
+        }
+        return;
+    }
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
-    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
-    const int nbh = kp.nbins + 2;
-    bool any = false;
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
-    const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
+    FbOpen open;
     uint64_t run = boff[blockIdx.x];
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = base + j * kThreads + threadIdx.x;
@@ -1238,6 +1458,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
         uint32_t segtot;
         const uint32_t pre = block_excl_scan(K, lds, &segtot);
         const bool live = i < n && w[i] > (T)0;
+        double fv[4] = {0.0, 0.0, 0.0, 0.0};
         if (live && (cd != 0 || (thermal && kp.absorb_mode == 1))) {
             const T wt0 = w[i];
             T wt = wt0;
@@ -1263,16 +1484,14 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                     wt = (T)((wphys - dw) / w_ref_a);
                 }
                 if (dw > 0.0) {
-                    if (fb) {
+                    fv[0] = dw * eu; fv[1] = dw * (double)pxv;
+                    fv[2] = dw * (double)pyv; fv[3] = dw * (double)pzv;
+                    if (fb && !fixed) {
                         double* f = fb + (int64_t)c * 4;
-                        atomicAdd(&f[0], dw * eu);
-                        atomicAdd(&f[1], dw * (double)pxv);
-                        atomicAdd(&f[2], dw * (double)pyv);
-                        atomicAdd(&f[3], dw * (double)pzv);
+                        for (int q = 0; q < 4; ++q) atomicAdd(&f[q], fv[q]);
                     }
                     st[0] += dw; st[1] += dw * E;
                     if (cd & 256u) st[7] += 1.0;
-                    any = true;
                 }
                 if (cd & 256u) wt = (T)0;
                 wphys = w_ref_a * (double)wt;
@@ -1306,14 +1525,15 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                     }
                 }
                 st[2] += (double)K; st[3] += (double)K * wp; st[4] += (double)K * wp * E;
-                any = true;
                 wt = (dep >= wphys) ? (T)0 : (T)((wphys - dep) / w_ref_a);
             }
             w[i] = wt;
         }
+        if (fixed) fb_tile(fbs, open, i < n ? cell[i] : -1, fv, fb, bkey, bval, blockIdx.x);
         run += segtot;
     }
-    stats_flush(st, any, A, nbh, smap);
+    if (fixed) fb_finish(open, fb, bkey, bval, blockIdx.x);
+    rec_write(nullptr, 0, st, smap, lst, myrec, gridDim.x);
 }
 
 // ------------------------------------------------------------------ feedback
@@ -1495,8 +1715,7 @@ k_sup_count(int64_t ncell, int64_t step, KParams kp, const float* __restrict__ p
             const double* __restrict__ p64, const int64_t* __restrict__ off,
             const T* __restrict__ w, const double* __restrict__ cellw,
             uint32_t* __restrict__ counts, uint32_t* __restrict__ bsum,
-            uint32_t* __restrict__ bact, double* __restrict__ acc, int acc_n) {
-    clear_acc(acc, acc_n);
+            uint32_t* __restrict__ bact) {
     __shared__ uint32_t lds[kThreads / 64];
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
@@ -1563,93 +1782,103 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
              const int64_t* __restrict__ ctrl, int64_t out_n, T* __restrict__ ax0,
              T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx, T* __restrict__ apy,
              T* __restrict__ apz, T* __restrict__ aw, uint64_t* __restrict__ aid,
-             int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ acc,
-             StatMap smap) {
+             int32_t* __restrict__ acell, double* __restrict__ fb, double* __restrict__ rec,
+             int32_t* __restrict__ bkey, double* __restrict__ bval, StatMap smap) {
 #pragma clang fp contract(off)
-    extern __shared__ double hl[];                          // channels 1 and 2's bins
+    extern __shared__ double wh[];                          // per wavefront: channels 1, 2
+    __shared__ double lst[(kThreads / 64) * kStatSlots];
+    __shared__ FbStitch fbs;
     if (ctrl[0]) return;
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
-    double* A = acc + (int64_t)(blockIdx.x % kCopies) * kAccStride;
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
-    lds_hist_clear(hl, 2 * nbh);
+    const int H = 2 * nbh;
+    for (int k = threadIdx.x; k < (kThreads / 64) * H; k += kThreads) wh[k] = 0.0;
+    __syncthreads();
+    double* myh = wh + (threadIdx.x >> 6) * H;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
-    bool any = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    FbOpen open;
+    int64_t elo, ehi;
+    ev_range(total, &elo, &ehi);
+    for (int64_t t0 = elo; t0 < ehi; t0 += kThreads) {
+        const int64_t e = t0 + threadIdx.x;
         const int64_t slot = out_n + e;
-        const uint64_t rc = aid[slot];
+        const uint64_t rc = e < ehi ? aid[slot] : 0ull;
         const int64_t c = (int64_t)(rc & 0xFFFFFFFFull);
         const uint32_t j = (uint32_t)((rc >> 32) & 0x3FFFFFFFull);
         const int ch = (int)(rc >> 62);                     // 1 Compton, 2 brems
-        if (c >= ncell || (ch != 1 && ch != 2)) continue;   // never for a well-formed record
-        const T* pc = pref + c * AXPIC_PREF_N;
-        const double k = (double)pc[3 + ch];
-        const double W = cellw[c], wmax = cellw[ncell + c];
-        const int64_t lo = off[c], hi = off[c + 1];
-        const bool capped_cell = wmax * k > kp.cap;
-        const double L = sup_lambda<T>(k, W, wmax, kp.cap, lo, hi, w);
-        // the electron: inverse CDF of lambda_e / Lambda over the cell in index order,
-        // eight weights loaded at a time
-        uint4 r = draw(kp, (uint64_t)c, step, 6, (uint32_t)(ch - 1) * (1u << 23) + j);
-        const double target = u53(r.x, r.y) * (capped_cell ? L : W);
-        int64_t pick = -1, last = -1;
-        double a = 0.0;
-        for (int64_t e0 = lo; e0 < hi && pick < 0; e0 += 8) {
-            T v[8];
+        int bin = -1;
+        double hv = 0.0;
+        int32_t key = -1;
+        double fv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (e < ehi && c < ncell && (ch == 1 || ch == 2)) { // always, for a well-formed record
+            key = (int32_t)c;
+            const T* pc = pref + c * AXPIC_PREF_N;
+            const double k = (double)pc[3 + ch];
+            const double W = cellw[c], wmax = cellw[ncell + c];
+            const int64_t lo = off[c], hi = off[c + 1];
+            const bool capped_cell = wmax * k > kp.cap;
+            const double L = sup_lambda<T>(k, W, wmax, kp.cap, lo, hi, w);
+            // the electron: inverse CDF of lambda_e / Lambda over the cell in index order,
+            // eight weights loaded at a time
+            uint4 r = draw(kp, (uint64_t)c, step, 6, (uint32_t)(ch - 1) * (1u << 23) + j);
+            const double target = u53(r.x, r.y) * (capped_cell ? L : W);
+            int64_t pick = -1, last = -1;
+            double a = 0.0;
+            for (int64_t e0 = lo; e0 < hi && pick < 0; e0 += 8) {
+                T v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = e0 + q < hi ? w[e0 + q] : (T)0;
+                for (int q = 0; q < 8; ++q) v[q] = e0 + q < hi ? w[e0 + q] : (T)0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (pick >= 0 || !(v[q] > (T)0)) continue;
-                const double wv = (double)v[q];
-                const double le = wv * k;
-                a += capped_cell ? (le < kp.cap ? le : kp.cap) : wv;
-                last = e0 + q;
-                if (a > target) pick = e0 + q;
+                for (int q = 0; q < 8; ++q) {
+                    if (pick >= 0 || !(v[q] > (T)0)) continue;
+                    const double wv = (double)v[q];
+                    const double le = wv * k;
+                    a += capped_cell ? (le < kp.cap ? le : kp.cap) : wv;
+                    last = e0 + q;
+                    if (a > target) pick = e0 + q;
+                }
+            }
+            if (pick < 0) pick = last;
+            if (pick >= 0) {                                // none: no electron with weight (N is 0)
+                const double le = (double)w[pick] * k;
+                const double ws = le > kp.cap ? le / kp.cap : 1.0;
+                const double wp = kp.w_a * kp.wa_mul[ch] * ws;
+                const double Tc = state[c * AXPIC_STATE_N + 0];
+                const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
+                r = draw(kp, (uint64_t)c, step, 6 + ch, j);
+                double E, pm;
+                thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
+                const double eu = M ? E / kMe : pm;        // energy in m_e c^2
+                const double mu = 2.0 * u24(r.y) - 1.0;
+                const double phi = 2.0 * kPi * u24(r.z);
+                const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+                double sphi, cphi;
+                sincos(phi, &sphi, &cphi);
+                const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
+                ax0[slot] = x0[pick];
+                if (ax1) ax1[slot] = x1 ? x1[pick] : (T)0;
+                if (ax2) ax2[slot] = x2 ? x2[pick] : (T)0;
+                apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
+                aw[slot] = (T)(kp.wa_mul[ch] * ws);
+                aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
+                acell[slot] = (int32_t)c;
+                bin = (ch - 1) * nbh + hist_bin(kp, E);
+                hv = wp * E;
+                fv[0] = -wp * eu; fv[1] = -wp * pa[0]; fv[2] = -wp * pa[1]; fv[3] = -wp * pa[2];
+                st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
+                if (le > kp.cap) st[9] += 1.0;
             }
         }
-        if (pick < 0) pick = last;
-        if (pick < 0) continue;                             // no electron with weight: N is 0 then
-        const double le = (double)w[pick] * k;
-        const double ws = le > kp.cap ? le / kp.cap : 1.0;
-        const double wp = kp.w_a * kp.wa_mul[ch] * ws;
-        const double Tc = state[c * AXPIC_STATE_N + 0];
-        const double* tab = ch == 1 ? g_tab_compton : g_tab_gamma;
-        r = draw(kp, (uint64_t)c, step, 6 + ch, j);
-        double E, pm;
-        thermal_energy<M>(kp, ch, Tc, u24(r.x), tab, &E, &pm);
-        const double eu = M ? E / kMe : pm;                // energy in m_e c^2
-        const double mu = 2.0 * u24(r.y) - 1.0;
-        const double phi = 2.0 * kPi * u24(r.z);
-        const double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
-        double sphi, cphi;
-        sincos(phi, &sphi, &cphi);
-        const double pa[3] = {pm * sn * cphi, pm * sn * sphi, pm * mu};
-        ax0[slot] = x0[pick];
-        if (ax1) ax1[slot] = x1 ? x1[pick] : (T)0;
-        if (ax2) ax2[slot] = x2 ? x2[pick] : (T)0;
-        apx[slot] = (T)pa[0]; apy[slot] = (T)pa[1]; apz[slot] = (T)pa[2];
-        aw[slot] = (T)(kp.wa_mul[ch] * ws);
-        aid[slot] = (next_id + (uint64_t)e) | (1ull << 63);
-        acell[slot] = (int32_t)c;
-        atomicAdd(&hl[(ch - 1) * nbh + hist_bin(kp, E)], wp * E);
-        if (fb) {
-            double* f = fb + c * 4;
-            atomicAdd(&f[0], -wp * eu);
-            atomicAdd(&f[1], -wp * pa[0]);
-            atomicAdd(&f[2], -wp * pa[1]);
-            atomicAdd(&f[3], -wp * pa[2]);
-        }
-        st[ch] += 1.0; st[3 + ch] += wp; st[6 + ch] += wp * E;
-        if (le > kp.cap) st[9] += 1.0;
-        any = true;
+        wave_hist_add(myh, bin, hv);
+        if (fb) fb_tile(fbs, open, key, fv, fb, bkey, bval, blockIdx.x);
     }
-    lds_hist_flush(hl, 2 * nbh, A + nbh);
-    stats_flush(st, any, A, nbh, smap);
+    if (fb) fb_finish(open, fb, bkey, bval, blockIdx.x);
+    __syncthreads();
+    rec_write(wh, H, st, smap, lst, rec + (int64_t)blockIdx.x * (H + AXPIC_ST_COUNT));
 }
 
 // ------------------------------------------------------------------ compaction
@@ -2263,14 +2492,22 @@ inline float product_ratio(double wprod, double w_ref) {
     return r < 3.0e38 ? (float)r : INFINITY;
 }
 
-int acc_used(const KParams& kp) { return 3 * (kp.nbins + 2) + AXPIC_ST_COUNT; }
-
-void acc_reduce(const KParams& kp, const Workspace& W, double* hist, double* stats, hipStream_t s) {
+// The per-block records of the last accumulating kernel (nrec records of ncol columns,
+// the first nh of them histogram bins for hist; row-major, or column-major with colmajor)
+// summed into hist and stats.
+void acc_reduce(const Workspace& W, int64_t nrec, int ncol, int nh, double* hist, double* stats,
+                hipStream_t s, bool colmajor = false) {
     if (!hist && !stats) return;
-    const int nbh = kp.nbins + 2;
-    const int n = 3 * nbh + AXPIC_ST_COUNT;
-    LAUNCH("k_acc_reduce", k_acc_reduce, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-           W.acc, nbh, W.ctrl, hist, stats);
+    LAUNCH("k_acc_reduce", k_acc_reduce, dim3((unsigned)ncol), dim3(kThreads), 0, s, W.rec, nrec,
+           colmajor ? (int64_t)1 : (int64_t)ncol, colmajor ? nrec : (int64_t)1, nh, W.ctrl, hist,
+           stats);
+}
+
+// The per-cell sums the blocks of the last kernel share with their neighbours.
+void fb_bounds(const Workspace& W, int64_t nb, double* fb, hipStream_t s) {
+    if (!fb) return;
+    LAUNCH("k_fb_bounds", k_fb_bounds, dim3((unsigned)((2 * nb + kThreads - 1) / kThreads)),
+           dim3(kThreads), 0, s, nb, W.bkey, W.bval, W.ctrl, fb);
 }
 
 struct SpT {   // typed view of a species
@@ -2289,7 +2526,7 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
-                       W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       W.code, W.bsum, W.bact,
                        runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in,
                                      W.code}),
                        heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode),
@@ -2299,14 +2536,15 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
            s, n, 0, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
            runs_aligned({W.code}));
+    const int nbh = kp.nbins + 2;
     LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads),
-           sizeof(double) * (size_t)(kp.nbins + 2), s, n, step,
+           sizeof(double) * (kThreads / 64) * (size_t)nbh, s, n, step,
            next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
            TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
            TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.ctrl, ax->n, TP<T>(ax->x[0]),
            TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]),
-           TP<T>(ax->w), ax->id, ax->cell, W.acc, kEmitMap);
-    acc_reduce(kp, W, hist, stats, s);
+           TP<T>(ax->w), ax->id, ax->cell, W.rec, kEmitMap);
+    acc_reduce(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, s);
     return launched();
 }
 
@@ -2318,7 +2556,7 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact,
                        runs_aligned({el->w, el->cell, el->id, lam_in, W.code}));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
@@ -2326,14 +2564,17 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            s, n, 1, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
            runs_aligned({W.code}));
     const auto k_events = kp.massive ? k_therm_events<T, true> : k_therm_events<T, false>;
+    const int nbh = kp.nbins + 2;
     LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads),
-           sizeof(double) * 2 * (size_t)(kp.nbins + 2), s, n, step,
+           sizeof(double) * (kThreads / 64) * 2 * (size_t)nbh, s, n, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), idv(el), el->cell, TCP<T>(lam_in),
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
            TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
-                       ax->cell, fb, W.acc, kEmitMap);
-    acc_reduce(kp, W, hist, stats, s);
+                       ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
+    fb_bounds(W, kEventBlocks, fb, s);
+    acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
+               stats, s);
     return launched();
 }
 
@@ -2345,20 +2586,22 @@ axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axp
     const int64_t ncell = cells->ncell, nb = nblocks_for(std::max<int64_t>(ncell, 1));
     uint32_t* counts = (uint32_t*)W.code;
     LAUNCH("k_sup_count", k_sup_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, step, kp,
-           cells->pref32, cells->pref64, off, TCP<T>(el->w), cellw, counts, W.bsum, W.bact, W.acc,
-           acc_used(kp));
+           cells->pref32, cells->pref64, off, TCP<T>(el->w), cellw, counts, W.bsum, W.bact);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
     LAUNCH("k_sup_expand", k_sup_expand, dim3((unsigned)nb), dim3(kThreads), 0, s, ncell, counts,
            W.bact, W.boff, W.ctrl, ax->n, ax->capacity, ax->id);
     const auto k_events = kp.massive ? k_sup_events<T, true> : k_sup_events<T, false>;
+    const int nbh = kp.nbins + 2;
     LAUNCH("k_sup_events", k_events, dim3(kEventBlocks), dim3(kThreads),
-           sizeof(double) * 2 * (size_t)(kp.nbins + 2), s, ncell, step,
+           sizeof(double) * (kThreads / 64) * 2 * (size_t)nbh, s, ncell, step,
            next_id, kp, cells->pref32, cells->pref64, cells->state, off, TCP<T>(el->w),
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
            TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),
-           TP<T>(ax->p[2]), TP<T>(ax->w), ax->id, ax->cell, fb, W.acc, kEmitMap);
-    acc_reduce(kp, W, hist, stats, s);
+           TP<T>(ax->p[2]), TP<T>(ax->w), ax->id, ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
+    fb_bounds(W, kEventBlocks, fb, s);
+    acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
+               stats, s);
     return launched();
 }
 
@@ -2373,7 +2616,7 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
     LAUNCH("k_abs_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ax->w_ref, cells->pref32, cells->pref64, TCP<T>(ax->w), TCP<T>(ax->p[0]),
                        TCP<T>(ax->p[1]), TCP<T>(ax->p[2]), idv(ax), ax->cell, TCP<T>(pabs_in),
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact, W.acc, acc_used(kp),
+                       TCP<T>(lam_in), W.code, W.bsum, W.bact,
                        runs_aligned({ax->w, ax->p[0], ax->p[1], ax->p[2], ax->cell, ax->id, pabs_in,
                                      lam_in, W.code}),
                        heavy_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
@@ -2381,6 +2624,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        product_ratio(kp.w_gamma_prod, ax->w_ref),
                        ax->off ? std::min<int64_t>(ax->n_sorted, n) : (int64_t)0);
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
+    // the exchange in fixed order needs the axions in cell order (as the sort leaves them)
+    const bool det = ax->off && ax->n_sorted >= n;
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, out_n,
            out_cap, W.ctrl, status, next_id, chain, ph ? (int)AXPIC_CHAIN_PHOTONS : -1);
     LAUNCH("k_abs_apply", k_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, next_id,
@@ -2392,8 +2637,9 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        ph ? TP<T>(ph->p[0]) : nullptr, ph ? TP<T>(ph->p[1]) : nullptr,
                        ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
-                       W.acc, kAbsMap);
-    acc_reduce(kp, W, nullptr, stats, s);
+                       W.rec, W.bkey, W.bval, det ? 1 : 0, kAbsMap);
+    if (det) fb_bounds(W, nb, fb, s);
+    acc_reduce(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, s, true);
     return launched();
 }
 

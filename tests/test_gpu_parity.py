@@ -194,10 +194,13 @@ def test_light_parents_bit_exact(mode):
     np.testing.assert_allclose(gw, osp.w, rtol=2e-6, atol=0)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_thermal_emission_matches_oracle(dtype):
-    """Rate-fed Compton + brems emission from the same seeded means on both sides."""
-    wl = small_workload(dtype, channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=0.5)
+@pytest.mark.parametrize("dtype,n,ppc", [("f32", (24, 20), 37), ("f64", (24, 20), 37),
+                                          ("f32", (2, 2), 6000)])
+def test_thermal_emission_matches_oracle(dtype, n, ppc):
+    """Rate-fed Compton + brems emission from the same seeded means on both sides; with
+    four cells of 6000 electrons a cell's products span many blocks of the events kernel
+    (the exchange sums are stitched across them)."""
+    wl = small_workload(dtype, n=n, ppc=ppc, channels=6, g_ae=1e-13, w_a=4e-38, lambda_cap=0.5)
     wl.params.wa_mul = (1.0, 1.0, 0.35)
     g, o, _ = pair(wl)
     cells = o.cells()
@@ -290,21 +293,29 @@ def test_push_and_binning_bit_exact(dtype):
     np.testing.assert_array_equal(b["cell"], osp.cell)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_absorption_decisions_bit_exact(mode):
+@pytest.mark.parametrize("mode,sort,n,per_cell", [(0, False, (24, 20), 12.0),
+                                                  (1, False, (24, 20), 12.0),
+                                                  (0, True, (24, 20), 12.0),
+                                                  (1, True, (3, 2), 2500.0)])
+def test_absorption_decisions_bit_exact(mode, sort, n, per_cell):
     """Rate-fed absorption (delete or reduce) and a->gamma on a seeded axion population,
-    both sides given the same seeded probabilities and means."""
-    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10, boost=4e33,
-                        w_a=1e-36, lambda_cap=1.0, absorb_mode=mode)
+    both sides given the same seeded probabilities and means.  In cell order (sorted) the
+    exchange is summed without atomics, also over cells spanning several blocks."""
+    wl = small_workload("f32", n=n, channels=7, inverse=1, g_ae=1e-13, g_agg_GeV=1e-10,
+                        boost=4e33, w_a=1e-36, lambda_cap=1.0, absorb_mode=mode)
     g, o, pl = pair(wl)
     cells = o.cells()
-    axd = I.make_axions(wl, pl, 12.0, seed=13 + mode)
+    axd = I.make_axions(wl, pl, per_cell, seed=13 + mode)
     g.load_axions(axd)
+    osp = O.OSpecies.from_input(axd)
+    if sort:
+        g.sort_axions()
+        osp.sort_cells(g.ncell)
+        assert g.ax.off is not None and g.ax.n_sorted == g.ax.n
     n = g.ax.n
     assert n > 2000
     pab = I.means(n, seed=30, lo=1e-5, hi=0.6)
     lag = I.means(n, seed=31, lo=1e-4, hi=2.0)
-    osp = O.OSpecies.from_input(axd)
     g.fb.zero_()
     ph_n0, id0 = g.ph.n, g.next_id
     g.step_index = 3
@@ -406,26 +417,32 @@ def test_capacity_overflow_rerun_is_bit_identical():
     np.testing.assert_allclose(g1.hist_np(), g2.hist_np(), rtol=1e-12, atol=0)
 
 
-def test_determinism_two_runs_bitwise():
+@pytest.mark.parametrize("thermal,absorb_mode", [("particle", 0), ("cells", 1)])
+def test_determinism_two_runs_bitwise(thermal, absorb_mode):
+    """Two runs of the same steps (all channels forward and inverse, feedback, T evolved)
+    agree bit for bit: the FP64 sums -- the exchange fb, the histograms, the statistics --
+    take no floating-point atomics, so the remapped momenta and temperatures, and with
+    them every later decision, are reproducible."""
     wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, boost=4e33, w_a=1e-36,
-                        lambda_cap=1.0, feedback=1, T_mode=2)
+                        lambda_cap=1.0, feedback=1, T_mode=2, absorb_mode=absorb_mode)
     pl = I.make_plasma(wl, 5)
     runs = []
     for _ in range(2):
-        g = AxpicSim(pl, wl.params)
-        for _ in range(4):
+        g = AxpicSim(pl, wl.params, thermal=thermal)
+        for _ in range(5):
             g.step()
         torch.cuda.synchronize()
-        runs.append((g.ax.to_numpy(), g.el.to_numpy(), g.T.cpu().numpy(), g.hist_np()))
-    (a1, e1, T1, h1), (a2, e2, T2, h2) = runs
-    for key in ("w", "id", "cell"):
+        runs.append((g.ax.to_numpy(), g.el.to_numpy(), g.T.cpu().numpy(), g.hist_np(),
+                     g.fb.cpu().numpy(), g.stats.cpu().numpy()))
+    (a1, e1, T1, h1, f1, s1), (a2, e2, T2, h2, f2, s2) = runs
+    for key in ("w", "id", "cell", "p", "x"):
         np.testing.assert_array_equal(a1[key], a2[key])
-    # the exchange buffers are FP64 sums accumulated with atomics, so the remapped momenta
-    # and temperatures agree to rounding of the summation order
-    np.testing.assert_allclose(e1["p"], e2["p"], rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(T1, T2, rtol=1e-13)
-    # FP64 histogram atomics may sum in another order: equal to rounding
-    np.testing.assert_allclose(h1, h2, rtol=1e-12)
+    np.testing.assert_array_equal(e1["p"], e2["p"])
+    np.testing.assert_array_equal(T1, T2)
+    np.testing.assert_array_equal(h1, h2)
+    np.testing.assert_array_equal(f1, f2)
+    np.testing.assert_array_equal(s1, s2)
+    assert np.count_nonzero(f1) > 10 and h1.sum() > 0 and a1["w"].size > 100
 
 
 def test_empty_inputs_append_nothing():

@@ -82,10 +82,15 @@ def test_cell_weight_sums():
     np.testing.assert_array_equal(cw[g.ncell:], M)
 
 
-@pytest.mark.parametrize("dtype,cap", [("f32", 0.25), ("f32", float("inf")), ("f64", 0.25)])
-def test_superposed_emission_matches_oracle(dtype, cap):
+@pytest.mark.parametrize("dtype,cap,n,ppc", [("f32", 0.25, (24, 20), 37),
+                                             ("f32", float("inf"), (24, 20), 37),
+                                             ("f64", 0.25, (24, 20), 37),
+                                             ("f32", 0.25, (2, 2), 8000)])
+def test_superposed_emission_matches_oracle(dtype, cap, n, ppc):
+    """Three steps on both sides; with four cells of 8000 electrons a cell's products
+    span several blocks of the events kernel."""
     p = I.Params(channels=6, g_ae=1e-13, w_a=2e-37, wa_mul=(1.0, 1.0, 0.08), lambda_cap=cap)
-    wl = I.Workload("sup", ndim=2, n=(24, 20), ppc=37, dtype=dtype, T_keV=3.0, n_e=6e25,
+    wl = I.Workload("sup", ndim=2, n=n, ppc=ppc, dtype=dtype, T_keV=3.0, n_e=6e25,
                     n_ref=6e25, lognormal_sigma=0.5, params=p)
     pl = I.make_plasma(wl, 5)
     print(f"[superposed] workload n={wl.n} dtype={dtype} cap={cap}", flush=True)
@@ -97,8 +102,9 @@ def test_superposed_emission_matches_oracle(dtype, cap):
         k, Lam, N, prod = check_step(g, pl, cells, o.params, step)
         tot += k
     assert tot > 3000
-    if cap < 1.0:
-        # electrons at the cap were picked (their products carry lambda_e / cap > 1)
+    if cap < 1.0 and ppc < 100:
+        # electrons at the cap were picked (their products carry lambda_e / cap > 1; with
+        # thousands per cell a macro-electron's weight, and mean, is too small for the cap)
         assert (np64(g.ax.w[: g.ax.n]) > np.array(wl.params.wa_mul)[1:].max() * 1.0000001).sum() > 50
 
 

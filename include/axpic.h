@@ -19,16 +19,19 @@
  *    and the caller may grow the buffer and repeat the call with the same
  *    arguments, which gives bit-identical results (the random numbers are
  *    keyed by (seed, particle id, step), see below).
- *  - Chained calls.  The appending calls and axpic_feedback take an optional
- *    `chain`, a device int64[AXPIC_CHAIN_N] = {axion count, photon count,
- *    next id, skip flag}.  With a chain, a call takes its output offset and
- *    its first product id from the chain instead of the species' n and the
- *    next_id argument, advances both on the device, and does nothing (but
- *    report AXPIC_FLAG_SKIPPED) once the skip flag is set; a call that runs
- *    out of capacity sets the flag.  A time step can then be issued without
- *    reading any count back: the caller reads the chain once at the end, and
- *    after an overflow grows the buffer named by that call's status and
- *    repeats the calls from it on (the skipped ones modified nothing).
+ *  - Chained calls.  The appending calls, axpic_sort_cells and axpic_feedback
+ *    take an optional `chain`, a device int64[AXPIC_CHAIN_N] = {axion count,
+ *    photon count, next id, skip flag, axions at the start of the step}.  With
+ *    a chain, a call takes its output offset and its first product id from
+ *    the chain instead of the species' n and the next_id argument, advances
+ *    both on the device, and does nothing (but report AXPIC_FLAG_SKIPPED) once
+ *    the skip flag is set; a call that runs out of capacity sets the flag.
+ *    axpic_sort_cells writes the number it keeps to the axion count and the
+ *    start-of-step word; axpic_absorb acts on the first min(n, start-of-step
+ *    word) axions.  A time step can then be issued without reading any count
+ *    back: the caller reads the chain once at the end, and after an overflow
+ *    grows the buffer named by that call's status and repeats the calls from
+ *    it on (the skipped ones modified nothing).
  *  - Particle ids key the random numbers.  A buffer may declare its first
  *    n_implicit ids as id0 + i (plasma in creation order) so that the hot
  *    kernels need not read them; appended products always store theirs.
@@ -83,7 +86,8 @@ typedef enum {
 #define AXPIC_CHAIN_PHOTONS 1
 #define AXPIC_CHAIN_NEXT_ID 2
 #define AXPIC_CHAIN_SKIP 3
-#define AXPIC_CHAIN_N 4
+#define AXPIC_CHAIN_AX_START 4    /* axions present when the step's operators begin */
+#define AXPIC_CHAIN_N 5
 
 typedef enum { AXPIC_PRIMAKOFF = 1, AXPIC_COMPTON = 2, AXPIC_BREMS = 4 } axpic_channel;
 typedef enum { AXPIC_F32 = 0, AXPIC_F64 = 1 } axpic_dtype;
@@ -300,7 +304,8 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
                                      void* ws, size_t ws_bytes, int64_t* chain, void* stream);
 
 /* axpic_absorb -- Sec. II.I and the inverse of Sec. II.F.1.  On the first
- * axions->n axions: thermal absorption (delete with probability P_abs or
+ * axions->n axions (with a chain: the first min(axions->n,
+ * chain[AXPIC_CHAIN_AX_START])): thermal absorption (delete with probability P_abs or
  * reduce the weight by it; fb[cell] += (w E, w p)), then a->gamma conversion
  * of what survives (products appended to `photons` with ids as above).
  * pabs_in / lam_in optionally replace the computed P_abs / a->gamma means, both
@@ -308,7 +313,8 @@ axpic_status axpic_sample_emit_cells(const axpic_grid* g, const axpic_cells* cel
  * With weight reduction (absorb_mode 1) an axion converts with the mean of its
  * reduced weight, i.e. the start-of-step mean times (1 - P_abs) (eq. prim_prob:
  * the mean is proportional to the parent's weight), taken in FP64 whether the
- * mean is computed or handed in. */
+ * mean is computed or handed in.  The exchange is summed without atomics, in a fixed
+ * order, when the axions are in cell order (off set, n_sorted >= n). */
 axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const axpic_params* prm,
                           axpic_species* axions, const void* pabs_in, const void* lam_in,
                           int64_t step, uint64_t next_id, axpic_species* photons, double* fb,
@@ -339,6 +345,9 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
  * one per cell and block of 1024 particles, AXPIC_SORT_AUTO the second from 32
  * particles per cell on.  AXPIC_E_INVAL for another value.
  *
+ * With chain (may be NULL), the number kept also goes to chain[AXPIC_CHAIN_AXIONS] and
+ * chain[AXPIC_CHAIN_AX_START], and a set skip flag makes the call do nothing.
+ *
  * Deterministic: the placement does not depend on the order of the device's atomics.
  * ws: at least axpic_sort_ws_bytes(g, in->n) bytes; in->n < 2^32. */
 #define AXPIC_SORT_AUTO 0
@@ -347,7 +356,7 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
 size_t axpic_sort_ws_bytes(const axpic_grid* g, int64_t n);
 axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, int32_t path,
                               axpic_species* out, int64_t* off, int64_t* status, void* ws,
-                              size_t ws_bytes, void* stream);
+                              size_t ws_bytes, int64_t* chain, void* stream);
 
 /* axpic_compact -- stable removal of particles with w <= 0 from `in` into
  * `out` (distinct buffers, same dtype, out->capacity >= in->n).  status[2]

@@ -20,7 +20,8 @@ MAX_IONS, PREF_N, STATE_N, STATUS_N = 4, 8, 16, 4
 FLAG_CAPACITY = 1
 FLAG_SKIPPED = 4
 SORT_AUTO, SORT_SPARSE, SORT_DENSE = 0, 1, 2
-CHAIN_N = 4
+CHAIN_AXIONS, CHAIN_PHOTONS, CHAIN_NEXT_ID, CHAIN_SKIP, CHAIN_AX_START = 0, 1, 2, 3, 4
+CHAIN_N = 5
 ST_NAMES = ["events_P", "events_C", "events_B", "num_P", "num_C", "num_B", "en_P", "en_C", "en_B",
             "abs_num", "abs_en", "ag_events", "ag_num", "ag_en", "capped", "overdepleted",
             "cold_cells", "clamped_cells", "unapplied_E", "abs_events"]
@@ -158,7 +159,7 @@ def load(path: Optional[str] = None):
         ("axpic_mlp_batch", [_P, _P, C.c_int64, C.c_int64, C.c_uint64, C.c_int64, _P, _P, _P]),
         ("axpic_equilibrium", [_P, _P, _P, _P, C.c_double, _P, _P, C.c_size_t, _P]),
         ("axpic_diag_noalloc", [_P, C.c_double, _P, _P]),
-        ("axpic_sort_cells", [_P, _P, C.c_int32, _P, _P, _P, _P, C.c_size_t, _P]),
+        ("axpic_sort_cells", [_P, _P, C.c_int32, _P, _P, _P, _P, C.c_size_t, _P, _P]),
     ]:
         fn = getattr(L, f)
         fn.restype = C.c_int32

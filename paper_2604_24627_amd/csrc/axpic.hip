@@ -1370,9 +1370,11 @@ k_abs_count(int64_t n, int64_t step, KParams kp, double w_ref_a, const float* __
             const int32_t* __restrict__ cell, const T* __restrict__ pabs_in,
             const T* __restrict__ lam_in, uint16_t* __restrict__ code, uint32_t* __restrict__ bsum,
             uint32_t* __restrict__ bact, int aligned,
-            float wt_heavy, float wt_light, float prod_ratio, int64_t n_sorted) {
+            float wt_heavy, float wt_light, float prod_ratio, int64_t n_sorted,
+            const int64_t* __restrict__ chain) {
     __shared__ uint32_t lds[kThreads / 64];
     __shared__ float4 s_pref[2 * kStageCells];
+    if (chain) n = min(n, chain[AXPIC_CHAIN_AX_START]);   // the axions of the step's start
     const T* pref = PrefOf<T>::get(p32, p64);
     const bool thermal = kp.inverse && (kp.channels & (AXPIC_COMPTON | AXPIC_BREMS));
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -1425,11 +1427,12 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             T* __restrict__ gpz, T* __restrict__ gw, uint64_t* __restrict__ gid,
             int32_t* __restrict__ gcell, double w_ref_g, double* __restrict__ fb,
             double* __restrict__ rec, int32_t* __restrict__ bkey, double* __restrict__ bval,
-            int det, StatMap smap) {
+            int det, const int64_t* __restrict__ chain, StatMap smap) {
     __shared__ uint32_t lds[kThreads / 64];
     __shared__ double lst[(kThreads / 64) * kStatSlots];
     __shared__ FbStitch fbs;
     if (ctrl[0]) return;
+    if (chain) n = min(n, chain[AXPIC_CHAIN_AX_START]);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
     double* myrec = rec + blockIdx.x;                  // column-major: nb records
     const bool fixed = det && fb;       // fb in fixed order: the axions are in cell order
@@ -2046,10 +2049,12 @@ k_sort_blocksum(int64_t ncell, const uint32_t* __restrict__ cnt, uint32_t* __res
 }
 
 // Cell offsets off[c] = block offset + exclusive scan of the block's counts; off[ncell] =
-// the total.  Nothing when the output does not fit (ctrl[0]).
+// the total (also to the chain's axion and start-of-step words).  Nothing when the output
+// does not fit or the chain says skip (ctrl[0]).
 __global__ void __launch_bounds__(kThreads)
 k_sort_offsets(int64_t ncell, const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ boff,
-               const int64_t* __restrict__ ctrl, int64_t* __restrict__ off) {
+               const int64_t* __restrict__ ctrl, int64_t* __restrict__ off,
+               int64_t* __restrict__ chain) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0]) return;
     const int64_t c0 = (int64_t)blockIdx.x * kSortCellsPerBlock + (int64_t)kPer * threadIdx.x;
@@ -2063,7 +2068,10 @@ k_sort_offsets(int64_t ncell, const uint32_t* __restrict__ cnt, const uint64_t* 
         if (c0 + q < ncell) off[c0 + q] = (int64_t)run;
         run += v[q];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) off[ncell] = ctrl[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        off[ncell] = ctrl[1];
+        if (chain) chain[AXPIC_CHAIN_AXIONS] = chain[AXPIC_CHAIN_AX_START] = ctrl[1];
+    }
 }
 
 // Source index of every live particle into its cell's range.  The per-cell count is
@@ -2622,7 +2630,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        heavy_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
                        light_threshold(kp.w_gamma_prod, ax->w_ref, kp.light_mode),
                        product_ratio(kp.w_gamma_prod, ax->w_ref),
-                       ax->off ? std::min<int64_t>(ax->n_sorted, n) : (int64_t)0);
+                       ax->off ? std::min<int64_t>(ax->n_sorted, n) : (int64_t)0,
+                       (const int64_t*)chain);
     const int64_t out_n = ph ? ph->n : 0, out_cap = ph ? ph->capacity : 0;
     // the exchange in fixed order needs the axions in cell order (as the sort leaves them)
     const bool det = ax->off && ax->n_sorted >= n;
@@ -2637,7 +2646,7 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        ph ? TP<T>(ph->p[0]) : nullptr, ph ? TP<T>(ph->p[1]) : nullptr,
                        ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
-                       W.rec, W.bkey, W.bval, det ? 1 : 0, kAbsMap);
+                       W.rec, W.bkey, W.bval, det ? 1 : 0, (const int64_t*)chain, kAbsMap);
     if (det) fb_bounds(W, nb, fb, s);
     acc_reduce(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, s, true);
     return launched();
@@ -2718,7 +2727,7 @@ SortIO<T> sort_io(const axpic_grid* g, const axpic_species* in, axpic_species* o
 // order; otherwise one atomic per run and the gather's blocks grouped by XCD.
 template <typename T, bool DENSE>
 void sort_general(const axpic_grid* g, const axpic_species* in, axpic_species* out, int64_t* off,
-                  int64_t* status, SortWs& W, hipStream_t s) {
+                  int64_t* status, SortWs& W, int64_t* chain, hipStream_t s) {
     const int64_t ncell = ncell_of(g), n = in->n;
     const int64_t nblk = (ncell + kSortCellsPerBlock - 1) / kSortCellsPerBlock;
     const dim3 nb((unsigned)((n + kSortSlots - 1) / kSortSlots));
@@ -2732,9 +2741,9 @@ void sort_general(const axpic_grid* g, const axpic_species* in, axpic_species* o
     LAUNCH("k_sort_blocksum", k_sort_blocksum, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell,
            W.cnt, W.bsum);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nblk, (int64_t)0,
-           out->capacity, W.ctrl, status, (uint64_t)0, (int64_t*)nullptr, 0);
+           out->capacity, W.ctrl, status, (uint64_t)0, chain, -1);
     LAUNCH("k_sort_offsets", k_sort_offsets, dim3((unsigned)nblk), dim3(kThreads), 0, s, ncell,
-           W.cnt, W.boff, W.ctrl, off);
+           W.cnt, W.boff, W.ctrl, off, chain);
     if (n == 0) return;
     LAUNCH("k_sort_scatter", (k_sort_scatter<T, DENSE>), nb, dim3(kThreads), 0, s, n, ncell, w,
            in->cell, (const int64_t*)off, (const int64_t*)W.ctrl, W.cnt, W.idx);
@@ -2749,13 +2758,13 @@ constexpr int64_t kSortDense = 32;
 
 template <typename T>
 void sort_launch(const axpic_grid* g, const axpic_species* in, int32_t path, axpic_species* out,
-                 int64_t* off, int64_t* status, SortWs& W, hipStream_t s) {
+                 int64_t* off, int64_t* status, SortWs& W, int64_t* chain, hipStream_t s) {
     if (path == AXPIC_SORT_AUTO)
         path = in->n >= kSortDense * ncell_of(g) ? AXPIC_SORT_DENSE : AXPIC_SORT_SPARSE;
     if (path == AXPIC_SORT_DENSE)
-        sort_general<T, true>(g, in, out, off, status, W, s);
+        sort_general<T, true>(g, in, out, off, status, W, chain, s);
     else
-        sort_general<T, false>(g, in, out, off, status, W, s);
+        sort_general<T, false>(g, in, out, off, status, W, chain, s);
 }
 
 }  // namespace
@@ -3052,7 +3061,7 @@ size_t axpic_sort_ws_bytes(const axpic_grid* g, int64_t n) {
 
 axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, int32_t path,
                               axpic_species* out, int64_t* off, int64_t* status, void* ws,
-                              size_t ws_bytes, void* stream) {
+                              size_t ws_bytes, int64_t* chain, void* stream) {
     if (!grid_ok(g) || !species_ok(in, true) || !out || !status) return AXPIC_E_INVAL;
     if (out->dtype != in->dtype || out == in || !out->x[0] || !out->w || !out->id || !out->cell ||
         !out->p[0] || !out->p[1] || !out->p[2])
@@ -3071,9 +3080,9 @@ axpic_status axpic_sort_cells(const axpic_grid* g, const axpic_species* in, int3
     if (!off) off = W.offw;
     hipStream_t s = S(stream);
     if (in->dtype == AXPIC_F32)
-        sort_launch<float>(g, in, path, out, off, status, W, s);
+        sort_launch<float>(g, in, path, out, off, status, W, chain, s);
     else
-        sort_launch<double>(g, in, path, out, off, status, W, s);
+        sort_launch<double>(g, in, path, out, off, status, W, chain, s);
     return launched();
 }
 

@@ -381,9 +381,11 @@ class AxpicSim:
             if push:
                 self.ax.off, self.ax.n_sorted = None, 0
 
-    def sort_axions(self):
+    def sort_axions(self, chained: bool = False):
         """The axions in the canonical order (axpic_sort_cells) in the spare buffer, which
-        becomes the axion buffer; its cell offsets stay in ax_off."""
+        becomes the axion buffer; its cell offsets stay in ax_off.  Chained (inside a step)
+        the number kept goes to the device chain and is read back with it at the step's
+        end: until then ax.n is the count before the sort (an upper bound)."""
         if not self.ax.n:
             return
         ax = self.ax
@@ -403,8 +405,10 @@ class AxpicSim:
         B.check(self.lib.axpic_sort_cells(B.ref(self.grid), B.ref(ax.struct()), B.SORT_AUTO,
                                           B.ref(spare.struct()), B.ptr(self.ax_off),
                                           B.ptr(self.sort_status), B.ptr(self.sort_ws),
-                                          self.sort_ws.numel(), self.sh), "sort_cells")
-        n = int(self.sort_status.cpu()[2])
+                                          self.sort_ws.numel(),
+                                          B.ptr(self.chain) if chained else None, self.sh),
+                "sort_cells")
+        n = ax.n if chained else int(self.sort_status.cpu()[2])
         spare.n, spare.off, spare.n_sorted = n, self.ax_off, n
         self._spare[B.AXION] = ax
         self.ax = spare
@@ -477,14 +481,19 @@ class AxpicSim:
 
     # -------------------------------------------------------------- one step
     def step(self):
-        """One time step.  The appending calls are chained on the device (counts and the
-        next id stay there), so the step reads back four words once at its end; after an
-        overflow the buffer named by the failing call is grown and the calls are repeated
-        from it on (the skipped ones modified nothing)."""
+        """One time step.  The sort and the appending calls are chained on the device
+        (counts and the next id stay there), so the step reads back the chain's words once
+        at its end; after an overflow the buffer named by the failing call is grown and the
+        calls are repeated from it on (the skipped ones modified nothing)."""
         p = self.pdict
         self.bin_axions(push=True)
+        # the chain's words before the first chained call (the sort rewrites the axion
+        # count and the start-of-step word on the device)
+        self._chain_np[:] = (self.ax.n, self.ph.n, self.next_id, 0, self.ax.n)
+        self.chain.copy_(self.chain_host, non_blocking=True)
         if self.sort:
-            self.sort_axions()
+            # the surrogate's axion rates need the kept count on the host before the calls
+            self.sort_axions(chained=self.surrogate is None)
         if p["T_mode"] == 2:
             self.cell_state()
         if self.need_feedback:
@@ -523,8 +532,6 @@ class AxpicSim:
             finally:
                 self.ax.n = n_now
         n_ph0, id0 = self.ph.n, self.next_id
-        self._chain_np[:] = (self.ax.n, self.ph.n, self.next_id, 0)
-        self.chain.copy_(self.chain_host, non_blocking=True)
         st = self.status_ops
         sh, g, c, prm, ch = self.sh, B.ref(self.grid), B.ref(self.cells), B.ref(self.params), \
             B.ptr(self.chain)
@@ -588,6 +595,9 @@ class AxpicSim:
         else:
             raise B.AxpicError("chained step: capacity growth did not converge")
         self.ax.n, self.ph.n, self.next_id = int(cw[0]), int(cw[1]), int(cw[2])
+        n_ax0 = int(cw[B.CHAIN_AX_START])
+        if self.ax.off is not None:              # the sorted prefix: what the sort kept
+            self.ax.n_sorted = n_ax0
         self._last_new = (self.ax.n - n_ax0, self.ph.n - n_ph0)
         self.step_index += 1
         if self.compact_every and self.step_index % self.compact_every == 0:

@@ -36,7 +36,7 @@ def _sort_on_gpu(g, sp_in, cap=None, path=B.SORT_AUTO):
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     B.check(g.lib.axpic_sort_cells(B.ref(g.grid), B.ref(sp_in.struct()), path,
                                    B.ref(out.struct()), B.ptr(off), B.ptr(st), B.ptr(ws), need,
-                                   g.sh), "sort_cells")
+                                   None, g.sh), "sort_cells")
     torch.cuda.synchronize()
     return out, off.cpu().numpy(), st.cpu().numpy()
 

@@ -166,6 +166,6 @@ def test_sort_rejects_invalid_arguments_on_host():
     assert need > 0
     for path in (3, -1):
         assert L.axpic_sort_cells(B.ref(g), B.ref(sp), path, B.ref(out), None, st.ctypes.data,
-                                  fake, need, None) == -1
+                                  fake, need, None, None) == -1
     assert L.axpic_sort_cells(B.ref(g), B.ref(sp), 0, B.ref(out), None, st.ctypes.data, fake,
-                              need - 1, None) == -1
+                              need - 1, None, None) == -1

@@ -229,6 +229,37 @@ def timed_leg(sim, steps, warmup, name, kernel_steps=3, flops=None):
     return rec
 
 
+def train_gemm_roofline(S, batch, steps=20):
+    """The training GEMM (k_gemm_bf16, split-K sums included) over a few gradient
+    evaluations of one batch: flop of a loss-and-gradient pass over the per-launch time.
+    Per pass, with the padded widths (32 in, 128 hidden, 32 out): forward and weight
+    gradients 2 B (32*128 + 3*128*128 + 128*32) each, input gradients of layers 5..2
+    2 B (128*32 + 3*128*128)."""
+    import torch
+    from paper_2604_24627_amd import axpic as B
+    L = B.load()
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    Xb = torch.randn((batch, 32), device="cuda", generator=gen)
+    Yb = torch.randn(batch, device="cuda", generator=gen)
+    S.loss_grad(Xb, Yb)
+    torch.cuda.synchronize()
+    L.axpic_timing_enable(1)
+    for _ in range(steps):
+        S.loss_grad(Xb, Yb)
+    torch.cuda.synchronize()
+    kt = B.timing_read()
+    L.axpic_timing_enable(0)
+    flop = 2.0 * batch * (2 * (32 * 128 + 3 * 128 * 128 + 128 * 32) + (128 * 32 + 3 * 128 * 128))
+    launches, ms = kt.get("k_gemm_bf16", (0, 0.0))
+    l2, ms2 = kt.get("k_gemm_splitk_sum", (0, 0.0))
+    tf = flop * steps / ((ms + ms2) * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"bound": "mfma", "kernel": "k_gemm_bf16", "achieved": round(tf, 2),
+            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 5),
+            "flop_per_pass": flop, "batch": batch, "gemm_launches_per_pass": launches / steps,
+            "avg_gemm_us": round(ms / max(launches, 1) * 1e3, 2),
+            "splitk_sum_us_per_pass": round(ms2 / steps * 1e3, 2)}
+
+
 def stream_copy_gbps(torch, B, nbytes=1 << 30, reps=10):
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -466,7 +497,8 @@ def main():
         train = {"train_s": round(t_train, 2), "train_steps": a.train_steps,
                  "train_samples": 2_000_000, "final_loss": losses[-1][1] if losses else None,
                  "activation": "hard-swish (the network of the config asks for SiLU; see "
-                               "the design notes)"}
+                               "the design notes)",
+                 "gemm_roofline": train_gemm_roofline(S, 4096)}
         sur, Q_sur = variant("surrogate per particle", surrogate=S, surrogate_mode="particle")
         sur_tab, Q_tab = variant("surrogate tables", surrogate=S, surrogate_mode="table")
         sur.update(train)

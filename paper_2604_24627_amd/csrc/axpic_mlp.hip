@@ -38,6 +38,7 @@ namespace {
 
 // padded widths of the training layout
 constexpr int kD0 = 32, kDH = 128, kD5 = 32;
+constexpr int kSplitMax = 16;              // K splits of a training GEMM at most
 // offsets of the FP32 master parameters
 constexpr int64_t kOffW1 = 0;
 constexpr int64_t kOffB1 = kOffW1 + kD0 * kDH;
@@ -75,29 +76,73 @@ __device__ __forceinline__ float dact(float z) {
 // ------------------------------------------------------------------ training GEMM
 // C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]); A(m,k) = transA ? A[k lda + m] : A[m lda + k],
 // B(k,n) = transB ? B[n ldb + k] : B[k ldb + n].  Operands rounded to bf16, FP32 accumulation.
-// One wavefront per 16 x 16 tile of C; M, N multiples of 16, K a multiple of 32.
-__global__ void __launch_bounds__(64)
+// A workgroup of four wavefronts computes a 32 x 32 tile of C, each wavefront a 16 x 16
+// quarter: per 32-deep slice of K, op(A) and op(B) are read once from global memory in
+// 16-byte loads along their contiguous dimension, rounded to bf16 and stored k-contiguous
+// in LDS (rows padded against bank conflicts), from where each wavefront takes its MFMA
+// operands.  With gridDim.z > 1 the K range is split: slice z adds up K / gridDim.z and
+// writes its partial tile to C + z M N (no bias), summed in order by k_gemm_splitk_sum.
+// M, N multiples of 32, K a multiple of 32 gridDim.z; lda, ldb multiples of 4.
+constexpr int kGemmPad = 40;               // bf16 per LDS row: 32 + 8
+__device__ __forceinline__ void gemm_stage(const float* __restrict__ X, int64_t ld, int trans,
+                                           int64_t r0, int64_t k0, __bf16 (*S)[kGemmPad]) {
+    // 32 x 32 slice X(r0 .., k0 ..) of op(X) (op(X)(r, k) = trans ? X[k ld + r] : X[r ld + k])
+    // into S[r][k]: thread t loads four consecutive floats along X's contiguous dimension
+    const int t = threadIdx.x, u = t >> 3, v = (t & 7) * 4;
+    if (!trans) {
+        const float4 q = *(const float4*)(X + (r0 + u) * ld + k0 + v);
+        S[u][v] = (__bf16)q.x; S[u][v + 1] = (__bf16)q.y; S[u][v + 2] = (__bf16)q.z; S[u][v + 3] = (__bf16)q.w;
+    } else {
+        const float4 q = *(const float4*)(X + (k0 + u) * ld + r0 + v);
+        S[v][u] = (__bf16)q.x; S[v + 1][u] = (__bf16)q.y; S[v + 2][u] = (__bf16)q.z; S[v + 3][u] = (__bf16)q.w;
+    }
+}
+
+__global__ void __launch_bounds__(256)
 k_gemm_bf16(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_t lda, int transA,
             const float* __restrict__ B, int64_t ldb, int transB, float* __restrict__ C,
             int64_t ldc, const float* __restrict__ bias) {
-    const int l = threadIdx.x;
-    const int64_t tm = blockIdx.y, tn = blockIdx.x;
-    const int64_t m = tm * 16 + (l & 15), n = tn * 16 + (l & 15);
-    const int g = l >> 4;
+    __shared__ __bf16 As[32][kGemmPad], Bs[32][kGemmPad];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * 32, n0 = (int64_t)blockIdx.x * 32;
+    const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
+    const int64_t kz = K / gridDim.z, kb = kz * blockIdx.z;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t kc = 0; kc < K; kc += 32) {
+    for (int64_t k0 = kb; k0 < kb + kz; k0 += 32) {
+        gemm_stage(A, lda, transA, m0, k0, As);
+        gemm_stage(B, ldb, !transB, n0, k0, Bs);     // Bs[n][k] = op(B)(k, n)
+        __syncthreads();
         bf16x8 a, b;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int64_t k = kc + 8 * g + j;
-            a[j] = (__bf16)(transA ? A[k * lda + m] : A[m * lda + k]);
-            b[j] = (__bf16)(transB ? B[n * ldb + k] : B[k * ldb + n]);
+            a[j] = As[wm + (l & 15)][8 * g + j];
+            b[j] = Bs[wn + (l & 15)][8 * g + j];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        __syncthreads();
     }
-    const float bv = bias ? bias[n] : 0.0f;
+    const int64_t n = n0 + wn + (l & 15);
+    if (gridDim.z == 1) {
+        const float bv = bias ? bias[n] : 0.0f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) C[(tm * 16 + 4 * g + r) * ldc + n] = acc[r] + bv;
+        for (int r = 0; r < 4; ++r) C[(m0 + wm + 4 * g + r) * ldc + n] = acc[r] + bv;
+    } else {
+        float* P = C + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[(m0 + wm + 4 * g + r) * N + n] = acc[r];
+    }
+}
+
+// C[m][n] = sum over the split partials in order (+ bias[n]).
+__global__ void __launch_bounds__(256)
+k_gemm_splitk_sum(int64_t M, int64_t N, int nsplit, const float* __restrict__ P,
+                  float* __restrict__ C, int64_t ldc, const float* __restrict__ bias) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    const int64_t m = i / N, n = i - m * N;
+    float s = 0.0f;
+    for (int z = 0; z < nsplit; ++z) s += P[(int64_t)z * M * N + i];
+    C[m * ldc + n] = s + (bias ? bias[n] : 0.0f);
 }
 
 // The same product in FP32 throughout (the training calls' FP32-weight mode, for
@@ -345,6 +390,7 @@ k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __rest
 
 // ------------------------------------------------------------------ inference
 constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
+constexpr int kInfThreadsP = 512;           // the same, per-particle kernel
 constexpr int kNTParticles = 2;            // 16-wide column tiles per pass, per-particle kernel
 constexpr int kNTTable = 4;                // the same for the per-cell table kernel
 
@@ -506,7 +552,7 @@ __device__ __forceinline__ float log_rate(const MlpConst& mc, int ch, const floa
 
 // mode 0: photons -> lambda_P; mode 1: axions -> thermal P_abs; mode 2: axions -> a->gamma mean.
 template <typename T>
-__global__ void __launch_bounds__(kInfThreads)
+__global__ void __launch_bounds__(kInfThreadsP)
 k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P, double g2e,
             double boost,
             double lam_unit_P, double lam_unit_ag, const double* __restrict__ state,
@@ -527,34 +573,50 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
     const float* bias = (const float*)(lds + (size_t)kNFrag * kFragBytes);
     const T* pref = PrefOf<T>::get(p32, p64);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t waves_total = (int64_t)gridDim.x * (kInfThreads / 64);
+    const int64_t waves_total = (int64_t)gridDim.x * (kInfThreadsP / 64);
     const int64_t tiles = (n + 63) / 64;
     unsigned long long fb_count = 0;
-    for (int64_t t = (int64_t)blockIdx.x * (kInfThreads / 64) + wave; t < tiles; t += waves_total) {
+    for (int64_t t = (int64_t)blockIdx.x * (kInfThreadsP / 64) + wave; t < tiles; t += waves_total) {
         const int64_t i = t * 64 + lane;
         const bool live = i < n;
         const int64_t ii = live ? i : n - 1;
         const int32_t c = cell[ii];
-        const double* st = state + (int64_t)c * AXPIC_STATE_N;
-        const double Tc = st[0], ne = st[1], k2 = st[7];
-        const T p2 = psq<T>(px, py, pz, ii);
-        const double om = kMe * sqrt((double)p2);
-        const double x = om / Tc;
-        const bool in_dom = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo &&
-                            Tc <= mc.T_hi && ne >= mc.ne_lo && ne <= mc.ne_hi && x >= mc.x_lo &&
-                            x <= mc.x_hi;
+        // the network's inputs: only these stay live across the passes (the rest of the
+        // particle and cell state is read again for the rate)
         float f[8];
-        f[0] = ((float)log(x) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
-        f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
-        f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
-        f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
+        bool in_dom;
+        {
+            const double* st = state + (int64_t)c * AXPIC_STATE_N;
+            const double Tc = st[0], ne = st[1], k2 = st[7];
+            const double x = kMe * sqrt((double)psq<T>(px, py, pz, ii)) / Tc;
+            in_dom = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo && Tc <= mc.T_hi &&
+                     ne >= mc.ne_lo && ne <= mc.ne_hi && x >= mc.x_lo && x <= mc.x_hi;
+            f[0] = ((float)log(x) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
+            f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
+            f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
+            f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
+        }
+        // one network pass per channel: Primakoff (modes 0, 2) or the three thermal ones
+        float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
+        const int c0 = mode == 1 ? 1 : 0, c1 = mode == 1 ? 3 : 0;
+#pragma unroll 1
+        for (int ch = c0; ch <= c1; ++ch) {
+            f[4] = ch == 0 ? 1.0f : 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f;
+            f[6] = ch == 2 ? 1.0f : 0.0f; f[7] = ch == 3 ? 1.0f : 0.0f;
+            const float yy = mlp_wave<kNTParticles>(frag, bias, f);
+            if (ch <= 1) y0 = yy;
+            else if (ch == 2) y1 = yy;
+            else y2 = yy;
+        }
+        const float y[3] = {y0, y1, y2};
+        const double* st = state + (int64_t)c * AXPIC_STATE_N;
+        const double Tc = st[0];
         const T* pc = pref + (int64_t)c * AXPIC_PREF_N;
         const T wt = w[ii];
+        const T p2 = psq<T>(px, py, pz, ii);
         double res;
         if (mode == 0 || mode == 2) {
-            f[4] = 1.0f; f[5] = 0.0f; f[6] = 0.0f; f[7] = 0.0f;
-            const float y = mlp_wave<kNTParticles>(frag, bias, f);
-            const double GdtP = g2P * boost * exp((double)log_rate(mc, 0, f, y)) * kp.dt_phys;
+            const double GdtP = g2P * boost * exp((double)log_rate(mc, 0, f, y[0])) * kp.dt_phys;
             if (mode == 0) {
                 res = in_dom ? (double)wt * lam_unit_P * (-expm1(-GdtP))
                              : (double)lambda_primakoff<T>(pc, wt, p2);
@@ -564,16 +626,13 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
             }
         } else {
             double G = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int ch = 1; ch <= 3; ++ch) {
-                f[4] = 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f; f[6] = ch == 2 ? 1.0f : 0.0f;
-                f[7] = ch == 3 ? 1.0f : 0.0f;
                 const bool on = (ch == 1) ? (kp.channels & AXPIC_COMPTON) != 0
                                           : ((kp.channels & AXPIC_BREMS) != 0 && (ch == 2 || ee_on));
-                const float y = mlp_wave<kNTParticles>(frag, bias, f);
                 // the brems targets exclude the cell's screening-fit factor; put it back
                 const double supp = ch == 1 ? 1.0 : fmax(0.0, brems_suppression(Tc, st[5], st[6], ch == 3));
-                if (on) G += supp * exp((double)log_rate(mc, ch, f, y));
+                if (on) G += supp * exp((double)log_rate(mc, ch, f, y[ch - 1]));
             }
             res = in_dom ? -expm1(-g2e * boost * G * kp.dt_phys)
                          : (double)pabs_thermal<T>(kp, pc, energy_keV(p2));
@@ -783,8 +842,9 @@ extern "C" {
 size_t axpic_mlp_blob_bytes(void) { return kBlobBytes; }
 
 size_t axpic_mlp_train_ws_bytes(int64_t batch) {
-    // Z1..Z4, H1..H4 [B][128], Z5 [B][32], dZ [B][128], dH [B][128], grads
-    return sizeof(float) * (size_t)batch * (8 * kDH + kD5 + 2 * kDH) + sizeof(float) * kNParams;
+    // Z1..Z4, H1..H4 [B][128], Z5 [B][32], dZ [B][128], dH [B][128], grads, split-K partials
+    return sizeof(float) * (size_t)batch * (8 * kDH + kD5 + 2 * kDH) + sizeof(float) * kNParams +
+           sizeof(float) * (size_t)kSplitMax * kDH * kDH;
 }
 
 axpic_status axpic_surrogate_samples(const axpic_params* prm, int64_t n, const double* T,
@@ -922,19 +982,28 @@ axpic_status axpic_mlp_pack(const float* master, void* blob, void* stream) {
     return launched();
 }
 
+// Long K (the weight gradients, K = batch) is split so that the grid fills the chip; the
+// partial tiles go to `part` (kSplitMax M N floats) and are summed in split order.
 static void gemm(int prec, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int tA,
                  const float* B, int64_t ldb, int tB, float* C, int64_t ldc, const float* bias,
-                 hipStream_t s) {
-    if (prec == AXPIC_MLP_F32)
+                 float* part, hipStream_t s) {
+    if (prec == AXPIC_MLP_F32) {
         LAUNCH("k_gemm_f32", k_gemm_f32, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(256), 0,
                s, M, N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
-    else
-        LAUNCH("k_gemm_bf16", k_gemm_bf16, dim3((unsigned)(N / 16), (unsigned)(M / 16)), dim3(64), 0,
-               s, M, N, K, A, lda, tA, B, ldb, tB, C, ldc, bias);
+        return;
+    }
+    const int64_t tiles = (M / 32) * (N / 32);
+    int split = 1;
+    while (split < kSplitMax && tiles * split < 256 && K % (64 * split) == 0) split *= 2;
+    LAUNCH("k_gemm_bf16", k_gemm_bf16, dim3((unsigned)(N / 32), (unsigned)(M / 32), (unsigned)split),
+           dim3(256), 0, s, M, N, K, A, lda, tA, B, ldb, tB, split > 1 ? part : C, ldc, bias);
+    if (split > 1)
+        LAUNCH("k_gemm_splitk_sum", k_gemm_splitk_sum, dim3((unsigned)((M * N + 255) / 256)),
+               dim3(256), 0, s, M, N, split, (const float*)part, C, ldc, bias);
 }
 
 struct TrainWs {
-    float *Z[6], *H[5], *dZ, *dH, *grad;
+    float *Z[6], *H[5], *dZ, *dH, *grad, *part;
 };
 
 static TrainWs carve_train(void* ws, int64_t Bn) {
@@ -946,7 +1015,8 @@ static TrainWs carve_train(void* ws, int64_t Bn) {
     t.Z[5] = p; p += Bn * kD5;
     t.dZ = p; p += Bn * kDH;
     t.dH = p; p += Bn * kDH;
-    t.grad = p;
+    t.grad = p; p += kNParams;
+    t.part = p;
     return t;
 }
 
@@ -962,7 +1032,7 @@ axpic_status axpic_mlp_forward(const float* master, const float* X, int64_t batc
     const float* hin = X;
     for (int l = 1; l <= 5; ++l) {
         gemm(precision, batch, dOut(l), dIn(l), hin, dIn(l), 0, master + offW(l), dOut(l), 0, t.Z[l],
-             dOut(l), master + offB(l), s);
+             dOut(l), master + offB(l), t.part, s);
         if (l <= 4) {
             const int64_t n = batch * kDH;
             LAUNCH("k_act_fwd", k_act_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
@@ -995,14 +1065,14 @@ axpic_status axpic_mlp_loss_grad(const float* master, const float* X, const floa
         const float* hin = l == 1 ? X : t.H[l - 1];
         // weight gradient: hin^T dZ
         gemm(precision, dIn(l), dOut(l), batch, hin, dIn(l), 1, dZ, dOut(l), 0, grad + offW(l),
-             dOut(l), nullptr, s);
+             dOut(l), nullptr, t.part, s);
         LAUNCH("k_colsum", k_colsum, dim3((unsigned)dOut(l)), dim3(256), 0, s, batch,
                            (int64_t)dOut(l), dZ, grad + offB(l));
         if (l == 1) break;
         // dH_{l-1} = dZ W^T, then through the activation
         float* dst = (dZ == t.dZ) ? t.dH : t.dZ;
         gemm(precision, batch, dIn(l), dOut(l), dZ, dOut(l), 0, master + offW(l), dOut(l), 1, dst,
-             dIn(l), nullptr, s);
+             dIn(l), nullptr, t.part, s);
         const int64_t n = batch * kDH;
         LAUNCH("k_act_bwd", k_act_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                            t.Z[l - 1], dst);
@@ -1063,18 +1133,18 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
     const double lam_unit_ag = prm->w_a / kp.w_gamma_prod;
     const int ncu = compute_units();
     const int64_t tiles = (sp->n + 63) / 64;
-    constexpr int kWaves = kInfThreads / 64;
+    constexpr int kWaves = kInfThreadsP / 64;
     const int64_t wgs = std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)ncu);
     const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
     if (sp->dtype == AXPIC_F32)
-        LAUNCH("k_rates_mlp", k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+        LAUNCH("k_rates_mlp", k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreadsP), 0,
                            S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
                            lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
                            (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
                            (const float*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
                            (float*)out, n_fallback);
     else
-        LAUNCH("k_rates_mlp", k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreads), 0,
+        LAUNCH("k_rates_mlp", k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreadsP), 0,
                            S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
                            lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
                            (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],

@@ -117,6 +117,11 @@ def step_counts(sim, n_ax0, active_frac):
                        ((16.0 * el if T_all else 16.0 * fb_el) + 12.0 * fb_el + 32.0 * fb_cells)
                        / max(el, 1)),
     }
+    if sim.sort:
+        # the canonical order: cell and weight read to count, every axion read and
+        # written whole (x, p, w, id, cell) to move it
+        k["k_sort_count"] = ("axion", n_ax0, 8.0)
+        k["k_sort_gather"] = ("axion", n_ax0, 2.0 * (xb + 12 + 4 + 8 + 4))
     # products: each written whole (x, p, w, id, cell); thermal ones read the parent's x
     prod = (new_ax + new_ph) * (xb + 12 + 4 + 8 + 4) + new_ax * xb
     total = sum(n * b for _, n, b in k.values()) + prod

@@ -57,7 +57,7 @@ static __device__ __align__(256) double scratch[2 * kDiagScratchPairs];
 
 // ------------------------------------------------------------------ workspace
 struct Workspace {
-    uint16_t* code;      // [n_max]
+    uint16_t* code;      // [n_max] 16-bit codes, or (as list) 32-bit entries
     uint32_t* bsum;      // [nb] products per block
     uint32_t* bact;      // [nb] active parents per block
     uint64_t* boff;      // [nb] exclusive product offsets
@@ -65,6 +65,7 @@ struct Workspace {
     int32_t* bkey;       // [2 nbmax] boundary cells of the blocks (fixed-order fb sums)
     double* bval;        // [2 nbmax][4] their sums
     int64_t* ctrl;       // [8]: 0 skip flag, 1 total
+    uint32_t* list() const { return (uint32_t*)code; }   // [n_max] active-parent entries
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -79,7 +80,7 @@ size_t bnd_count(int64_t nb) { return 2 * (size_t)std::max<int64_t>(kEventBlocks
 
 size_t ws_bytes_for(int64_t n) {
     int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
-    return align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1)) + align256(4 * (size_t)nb) +
+    return align256(sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1)) + align256(4 * (size_t)nb) +
            align256(4 * (size_t)nb) + align256(8 * (size_t)nb) +
            align256(sizeof(double) * rec_doubles(nb)) + align256(4 * bnd_count(nb)) +
            align256(sizeof(double) * 4 * bnd_count(nb)) + 256;
@@ -89,7 +90,7 @@ bool carve(void* ws, size_t bytes, int64_t n, Workspace* w) {
     if (!ws || bytes < ws_bytes_for(n)) return false;
     int64_t nb = nblocks_for(std::max<int64_t>(n, 1));
     char* p = (char*)ws;
-    w->code = (uint16_t*)p; p += align256(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1));
+    w->code = (uint16_t*)p; p += align256(sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1));
     w->bsum = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->bact = (uint32_t*)p; p += align256(4 * (size_t)nb);
     w->boff = (uint64_t*)p; p += align256(8 * (size_t)nb);
@@ -835,16 +836,16 @@ struct CellStage {
     }
 };
 
-// Counts of the thread's run of photons; returns the run's product total, *act the
-// number of converting photons.  STAGE: the workgroup's cells are staged in LDS and the
-// photons' cell indices are not read.
+// Counts of the thread's run of photons into cd; returns the run's product total.
+// STAGE: the workgroup's cells are staged in LDS and the photons' cell indices are not
+// read.
 template <typename T, bool M, bool VEC, bool STAGE>
 __device__ __forceinline__ uint32_t prim_count_run(
     int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref, const T* __restrict__ pref,
     const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
     const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
-    const T* __restrict__ lam_in, uint16_t* __restrict__ code, float wt_heavy,
-    const CellStage& stg, int32_t t0, uint32_t* act) {
+    const T* __restrict__ lam_in, float wt_heavy, const CellStage& stg, int32_t t0,
+    uint32_t* cd) {
     T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
     int32_t cv[kPer];
     uint64_t idv[kPer];
@@ -867,7 +868,7 @@ __device__ __forceinline__ uint32_t prim_count_run(
         for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
     }
     const double wprod = kp.w_a * kp.wa_mul[0];
-    uint32_t cd[kPer], tot = 0, nact = 0;
+    uint32_t tot = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         cd[j] = 0;
@@ -894,11 +895,29 @@ __device__ __forceinline__ uint32_t prim_count_run(
         }
         cd[j] = (uint32_t)K;
         tot += K;
-        nact += K > 0;
     }
-    st_codes<VEC>(code, i0, n, cd);
-    *act = nact;
     return tot;
+}
+
+// The tile's totals and its list of active parents: entry = index in the tile (bits
+// 0-9) | counts << 10 (channel 0 or 1 in bits 10-17, brems in 18-25), in parent order at
+// list[tile start ..]; bsum / bact the tile's products and active parents.
+__device__ __forceinline__ void tile_list(int64_t b, int32_t t0, uint32_t tot, const uint32_t* cd,
+                                          uint32_t* __restrict__ list, uint32_t* __restrict__ bsum,
+                                          uint32_t* __restrict__ bact, uint32_t* lds) {
+    uint32_t na = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) na += cd[q] != 0u;
+    uint32_t ba;
+    uint32_t slot = block_excl_scan(na, lds, &ba);
+    const uint32_t bt = block_sum_u32(tot, lds);
+    if (na) {
+        uint32_t* L = list + b * kBlockParents;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (cd[q]) L[slot++] = (uint32_t)(t0 + q) | (cd[q] << 10);
+    }
+    if (threadIdx.x == 0) { bsum[b] = bt; bact[b] = ba; }
 }
 
 template <typename T, bool M>
@@ -907,7 +926,7 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
              const T* __restrict__ py, const T* __restrict__ pz, IdView id,
              const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
-             uint16_t* __restrict__ code, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
+             uint32_t* __restrict__ list, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
              int aligned, float wt_heavy,
              const int64_t* __restrict__ off, int64_t n_sorted) {
     __shared__ uint32_t lds[kThreads / 64];
@@ -936,72 +955,54 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
             stg.m = m;
         }
     }
-    uint32_t tot, act;
+    uint32_t cd[kPer], tot;
     if (stg.m > 0)
         tot = prim_count_run<T, M, true, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
-                                               lam_in, code, wt_heavy, stg, t0, &act);
+                                               lam_in, wt_heavy, stg, t0, cd);
     else if (vec)
         tot = prim_count_run<T, M, true, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
-                                                cell, lam_in, code, wt_heavy, stg, t0, &act);
+                                                cell, lam_in, wt_heavy, stg, t0, cd);
     else
         tot = prim_count_run<T, M, false, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
-                                                 cell, lam_in, code, wt_heavy, stg, t0, &act);
-    const uint32_t bt = block_sum_u32(tot, lds);
-    const uint32_t ba = block_sum_u32(act, lds);
-    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
+                                                 cell, lam_in, wt_heavy, stg, t0, cd);
+    tile_list(blockIdx.x, t0, tot, cd, list, bsum, bact, lds);
 }
 
-// Event records: the expand pass writes one record per product into the
-// product's id slot -- parent index (bits 0-39), event k (40-47), channel
-// (48-55) -- and the event kernels, one product per lane, replace it with
-// the final id after filling the product.
+// Event records: the expand pass writes one record per product into the product's id
+// slot -- parent index (bits 0-39), event k (40-47), channel (48-55: 0 Primakoff, 1
+// Compton, 2 brems), the parent's count in that channel (56-63) -- and the event kernels,
+// one product per lane, replace it with the final id after filling the product.
 constexpr uint64_t kRecParentMask = (1ull << 40) - 1;
 
-constexpr int kExpPer = 16;                              // codes per thread in k_expand
-constexpr int kExpSub = kThreads * kExpPer / kBlockParents; // count blocks per expand block
-static_assert(kExpSub * kBlockParents == kThreads * kExpPer, "expand block spans whole count blocks");
-
+// One wavefront per tile (grid-stride over the tiles): the tile's active-parent entries,
+// 64 at a time, a wavefront scan of their event counts, the records from the tile's
+// product offset on.
 __global__ void __launch_bounds__(kThreads)
-k_expand(int64_t n, int mode, const uint16_t* __restrict__ code, const uint32_t* __restrict__ bact,
-         const uint64_t* __restrict__ boff, int64_t nb, const int64_t* __restrict__ ctrl,
-         int64_t out_n, int64_t out_cap, uint64_t* __restrict__ rec, int aligned) {
-    __shared__ uint32_t lds[kThreads / 64];
-    // one expand workgroup covers kExpSub consecutive count blocks (products of a run of
-    // blocks are contiguous from the first block's offset)
-    const int64_t cb0 = (int64_t)blockIdx.x * kExpSub;
-    uint32_t live = 0;
-#pragma unroll
-    for (int q = 0; q < kExpSub; ++q) live |= (cb0 + q < nb) ? bact[cb0 + q] : 0u;
-    if (ctrl[0] || live == 0) return;
-    out_n = ctrl[2];
-    // each thread takes kExpPer consecutive parents (two 16-byte loads of their codes);
-    // one block scan keeps the records in parent order
-    const int64_t i0 = cb0 * kBlockParents + (int64_t)kExpPer * threadIdx.x;
-    uint32_t cd[kExpPer];
-    if (aligned && i0 + kExpPer <= n) {
-        const uint4 u0 = *(const uint4*)(code + i0), u1 = *(const uint4*)(code + i0 + 8);
-        const uint32_t wds[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) { cd[2 * q] = wds[q] & 0xFFFFu; cd[2 * q + 1] = wds[q] >> 16; }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kExpPer; ++q) cd[q] = i0 + q < n ? code[i0 + q] : 0u;
-    }
-    // mode 0: one channel (count in bits 0-7); mode 1: Compton bits 0-7, brems 8-15
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int q = 0; q < kExpPer; ++q) cnt += (cd[q] & 0xFFu) + (mode == 1 ? (cd[q] >> 8) : 0u);
-    uint32_t segtot;
-    const uint32_t pre = block_excl_scan(cnt, lds, &segtot);
-    if (cnt == 0) return;
-    int64_t slot = out_n + (int64_t)(boff[cb0] + pre);
-    for (int q = 0; q < kExpPer; ++q) {
-        const uint64_t i = (uint64_t)(i0 + q);
-        const uint32_t K0 = cd[q] & 0xFFu, K1 = mode == 1 ? (cd[q] >> 8) : 0u;
-        for (uint32_t k = 0; k < K0; ++k, ++slot)
-            if (slot < out_cap) rec[slot] = i | ((uint64_t)k << 40) | ((uint64_t)(mode == 1 ? 1 : 0) << 48);
-        for (uint32_t k = 0; k < K1; ++k, ++slot)
-            if (slot < out_cap) rec[slot] = i | ((uint64_t)k << 40) | (2ull << 48);
+k_expand(int64_t nb, int thermal, const uint32_t* __restrict__ list,
+         const uint32_t* __restrict__ bact, const uint64_t* __restrict__ boff,
+         const int64_t* __restrict__ ctrl, int64_t out_cap, uint64_t* __restrict__ rec) {
+    if (ctrl[0]) return;
+    const int64_t out_n = ctrl[2];
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); t < nb; t += nw) {
+        const uint32_t na = bact[t];                       // wave-uniform
+        int64_t slot0 = out_n + (int64_t)boff[t];
+        const uint32_t* L = list + t * kBlockParents;
+        for (uint32_t c = 0; c < na; c += 64) {
+            const uint32_t e = c + lane < na ? L[c + lane] : 0u;
+            const uint32_t K0 = (e >> 10) & 0xFFu, K1 = thermal ? (e >> 18) & 0xFFu : 0u;
+            const uint32_t inc = wave_incl_scan(K0 + K1, lane);
+            int64_t slot = slot0 + (int64_t)(inc - K0 - K1);
+            const uint64_t i = (uint64_t)(t * kBlockParents + (int64_t)(e & 0x3FFu));
+            const uint64_t h0 = i | ((uint64_t)(thermal ? 1 : 0) << 48) | ((uint64_t)K0 << 56);
+            for (uint32_t k = 0; k < K0; ++k, ++slot)
+                if (slot < out_cap) rec[slot] = h0 | ((uint64_t)k << 40);
+            const uint64_t h1 = i | (2ull << 48) | ((uint64_t)K1 << 56);
+            for (uint32_t k = 0; k < K1; ++k, ++slot)
+                if (slot < out_cap) rec[slot] = h1 | ((uint64_t)k << 40);
+            slot0 += (int64_t)__shfl(inc, 63, 64);
+        }
     }
 }
 
@@ -1018,7 +1019,7 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
               const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
               const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
               const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
-              const uint16_t* __restrict__ code, const int64_t* __restrict__ ctrl, int64_t out_n,
+              const int64_t* __restrict__ ctrl, int64_t out_n,
               T* __restrict__ ax0, T* __restrict__ ax1, T* __restrict__ ax2, T* __restrict__ apx,
               T* __restrict__ apy, T* __restrict__ apz, T* __restrict__ aw,
               uint64_t* __restrict__ aid, int32_t* __restrict__ acell, double* __restrict__ rec,
@@ -1046,7 +1047,7 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
         const uint64_t rc = e < hi ? aid[out_n + e] : 0ull;
         if (e < hi) aid[out_n + e] = (next_id + (uint64_t)e) | (1ull << 63);
         const int64_t i = (int64_t)(rc & kRecParentMask);
-        const uint32_t K = (e < hi && i < n) ? code[i] & 0xFFu : 0u;
+        const uint32_t K = (uint32_t)(rc >> 56);
         if (e < hi && ((rc >> 40) & 0xFFu) == 0 && i < n && (int64_t)K <= total - e) {
             const T wt = w[i];
             const T* pci = pref + (int64_t)cell[i] * AXPIC_PREF_N;
@@ -1092,13 +1093,13 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
 }
 
 // ------------------------------------------------------------------ thermal emission
-// Compton-like and brems counts of the thread's run of electrons (code: Compton in
-// bits 0-7, brems in 8-15); returns the run's product total, *act the emitting electrons.
+// Compton-like and brems counts of the thread's run of electrons into cd (Compton in
+// bits 0-7, brems in 8-15); returns the run's product total.
 template <typename T, bool VEC>
 __device__ __forceinline__ uint32_t therm_count_run(
     int64_t i0, int64_t n, int64_t step, const KParams& kp, const T* __restrict__ pref,
     const T* __restrict__ w, const IdView& id, const int32_t* __restrict__ cell,
-    const T* __restrict__ lam_in, bool lam_b_vec, uint16_t* __restrict__ code, uint32_t* act) {
+    const T* __restrict__ lam_in, bool lam_b_vec, uint32_t* cd) {
     const bool onC = kp.channels & AXPIC_COMPTON, onB = kp.channels & AXPIC_BREMS;
     T lCv[kPer], lBv[kPer];
     uint64_t idv[kPer];
@@ -1119,7 +1120,7 @@ __device__ __forceinline__ uint32_t therm_count_run(
             lBv[j] = wv[j] * pc[5];
         }
     }
-    uint32_t cd[kPer], tot = 0, nact = 0;
+    uint32_t tot = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         cd[j] = 0;
@@ -1141,10 +1142,7 @@ __device__ __forceinline__ uint32_t therm_count_run(
         }
         cd[j] = (uint32_t)(KC | (KB << 8));
         tot += KC + KB;
-        nact += (KC + KB) > 0;
     }
-    st_codes<VEC>(code, i0, n, cd);
-    *act = nact;
     return tot;
 }
 
@@ -1153,7 +1151,7 @@ __global__ void __launch_bounds__(kThreads)
 k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32,
               const double* __restrict__ p64, const T* __restrict__ w,
               IdView id, const int32_t* __restrict__ cell,
-              const T* __restrict__ lam_in, uint16_t* __restrict__ code,
+              const T* __restrict__ lam_in, uint32_t* __restrict__ list,
               uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
               int aligned) {
     __shared__ uint32_t lds[kThreads / 64];
@@ -1162,16 +1160,12 @@ k_therm_count(int64_t n, int64_t step, KParams kp, const float* __restrict__ p32
     const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
     // the brems half of lam_in starts at n: 16-byte aligned runs only if n % kPer == 0
     const bool lam_b_vec = (n % kPer) == 0;
-    uint32_t tot, act;
+    uint32_t cd[kPer], tot;
     if (aligned && base + kBlockParents <= n)
-        tot = therm_count_run<T, true>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec, code,
-                                       &act);
+        tot = therm_count_run<T, true>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec, cd);
     else
-        tot = therm_count_run<T, false>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec,
-                                        code, &act);
-    const uint32_t bt = block_sum_u32(tot, lds);
-    const uint32_t ba = block_sum_u32(act, lds);
-    if (threadIdx.x == 0) { bsum[blockIdx.x] = bt; bact[blockIdx.x] = ba; }
+        tot = therm_count_run<T, false>(i0, n, step, kp, pref, w, id, cell, lam_in, lam_b_vec, cd);
+    tile_list(blockIdx.x, kPer * (int32_t)threadIdx.x, tot, cd, list, bsum, bact, lds);
 }
 
 template <typename T, bool M>
@@ -2522,6 +2516,13 @@ struct SpT {   // typed view of a species
     void* x[3]; void* p[3]; void* w; uint64_t* id; int32_t* cell;
 };
 
+// Event records of the active-parent lists of nb tiles (after k_scan).
+void expand(const Workspace& W, int64_t nb, bool thermal, axpic_species* ax, hipStream_t s) {
+    const int64_t g = std::min<int64_t>((nb + kThreads / 64 - 1) / (kThreads / 64), 2048);
+    LAUNCH("k_expand", k_expand, dim3((unsigned)g), dim3(kThreads), 0, s, nb, thermal ? 1 : 0,
+           W.list(), W.bact, W.boff, W.ctrl, ax->capacity, ax->id);
+}
+
 template <typename T>
 axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_species* ph,
                             const void* lam_in, int64_t step, uint64_t next_id,
@@ -2534,22 +2535,19 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
                        TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
-                       W.code, W.bsum, W.bact,
-                       runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in,
-                                     W.code}),
+                       W.list(), W.bsum, W.bact,
+                       runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in}),
                        heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode),
                        ph->off, ph->off ? ph->n_sorted : (int64_t)0);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
-    LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
-           s, n, 0, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
-           runs_aligned({W.code}));
+    expand(W, nb, false, ax, s);
     const int nbh = kp.nbins + 2;
     LAUNCH("k_prim_events", k_events, dim3(kEventBlocks), dim3(kThreads),
            sizeof(double) * (kThreads / 64) * (size_t)nbh, s, n, step,
            next_id, kp, ph->w_ref, cells->pref32, cells->pref64, TP<T>(ph->w), TCP<T>(ph->x[0]),
            TCP<T>(ph->x[1]), TCP<T>(ph->x[2]), TCP<T>(ph->p[0]), TCP<T>(ph->p[1]),
-           TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.code, W.ctrl, ax->n, TP<T>(ax->x[0]),
+           TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.ctrl, ax->n, TP<T>(ax->x[0]),
            TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]),
            TP<T>(ax->w), ax->id, ax->cell, W.rec, kEmitMap);
     acc_reduce(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, s);
@@ -2564,13 +2562,11 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
     const int64_t n = el->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     LAUNCH("k_therm_count", k_therm_count<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        cells->pref32, cells->pref64, TCP<T>(el->w), idv(el), el->cell,
-                       TCP<T>(lam_in), W.code, W.bsum, W.bact,
-                       runs_aligned({el->w, el->cell, el->id, lam_in, W.code}));
+                       TCP<T>(lam_in), W.list(), W.bsum, W.bact,
+                       runs_aligned({el->w, el->cell, el->id, lam_in}));
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
            ax->capacity, W.ctrl, status, next_id, chain, (int)AXPIC_CHAIN_AXIONS);
-    LAUNCH("k_expand", k_expand, dim3((unsigned)((nb + kExpSub - 1) / kExpSub)), dim3(kThreads), 0,
-           s, n, 1, W.code, W.bact, W.boff, nb, W.ctrl, ax->n, ax->capacity, ax->id,
-           runs_aligned({W.code}));
+    expand(W, nb, true, ax, s);
     const auto k_events = kp.massive ? k_therm_events<T, true> : k_therm_events<T, false>;
     const int nbh = kp.nbins + 2;
     LAUNCH("k_therm_events", k_events, dim3(kEventBlocks), dim3(kThreads),

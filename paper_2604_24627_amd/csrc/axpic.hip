@@ -1974,6 +1974,25 @@ __device__ __forceinline__ WaveRun wave_run(int32_t key) {
     return r;
 }
 
+// The wavefront's keys sorted ascending, each tagged with its lane: (key << 6) | lane,
+// the lanes without a key (k < 0) last.  A bitonic network over the 64 lanes; runs of a
+// cell are then as long as the cell's particles in the wavefront, not only its adjacent
+// ones (the particles that moved to a neighbouring cell break no run).
+__device__ __forceinline__ uint64_t wave_sort_keys(int32_t k) {
+    const int lane = threadIdx.x & 63;
+    uint64_t key = k >= 0 ? ((uint64_t)(uint32_t)k << 6) | (uint64_t)lane : ~0ull;
+#pragma unroll
+    for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const uint64_t ok = __shfl_xor(key, j, 64);
+            const bool up = (lane & kk) == 0, lower = (lane & j) == 0;
+            if (lower == up ? ok < key : ok > key) key = ok;
+        }
+    }
+    return key;
+}
+
 // Blocks go round robin over the eight XCDs; this gives each XCD a contiguous range of
 // block indices, so that neighbouring ranges of particles share that XCD's L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
@@ -1999,35 +2018,83 @@ __device__ __forceinline__ void sort_hash_clear(int32_t* hkey, uint32_t* hval) {
     for (int h = threadIdx.x; h < kSortHash; h += kThreads) { hkey[h] = -1; hval[h] = 0u; }
 }
 
-// kSortSlots particles per block: counts per cell gathered by runs of a
-// wavefront, with TABLE further in the block's cell table (one atomic per cell and block:
-// it pays where the cells are dense), else one atomic per run.
+// The smallest and largest of the block's keys (*hi < *lo: none), in every thread.
+constexpr int kSortWin = 4096;          // cells of a block's direct-mapped LDS window
+__device__ __forceinline__ void block_key_range(const int32_t* c, int32_t* lds, int32_t* lo,
+                                                int32_t* hi) {
+    int32_t mn = INT32_MAX, mx = -1;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (c[q] >= 0) { mn = min(mn, c[q]); mx = max(mx, c[q]); }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, 64));
+        mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { lds[2 * wave] = mn; lds[2 * wave + 1] = mx; }
+    __syncthreads();
+    mn = INT32_MAX; mx = -1;
+#pragma unroll
+    for (int v = 0; v < kThreads / 64; ++v) { mn = min(mn, lds[2 * v]); mx = max(mx, lds[2 * v + 1]); }
+    *lo = mn; *hi = mx;
+}
+
+// kSortSlots particles per block: counts per cell.  With TABLE, gathered by runs of a
+// wavefront into the block's cell table (one atomic per cell and block: it pays where
+// the cells are dense); else, when the block's cells span fewer than kSortWin indices
+// (a cell-ordered input moved by a step: a block's cells and their neighbours), counted
+// in a direct-mapped LDS window and added once per cell and block, otherwise one atomic
+// per run of a wavefront's sorted cells.
 template <typename T, bool TABLE>
 __global__ void __launch_bounds__(kThreads)
 k_sort_count(int64_t n, int64_t ncell, const T* __restrict__ w,
              const int32_t* __restrict__ cell, uint32_t* __restrict__ cnt) {
     __shared__ int32_t hkey[TABLE ? kSortHash : 1];
-    __shared__ uint32_t hval[TABLE ? kSortHash : 1];
-    if (TABLE) {
-        sort_hash_clear(hkey, hval);
-        __syncthreads();
-    }
+    __shared__ uint32_t hval[TABLE ? kSortHash : kSortWin];
+    __shared__ int32_t rng[2 * (kThreads / 64)];
     const int lane = threadIdx.x & 63;
     const int64_t base = (int64_t)blockIdx.x * kSortSlots;
+    if (!TABLE) {
+        int32_t c[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            c[q] = sort_key<T>(base + q * kThreads + threadIdx.x, n, w, cell, ncell);
+        int32_t lo, hi;
+        block_key_range(c, rng, &lo, &hi);
+        if (hi < lo) return;                                    // uniform: no live particle
+        if (hi - lo < kSortWin) {
+            for (int e = threadIdx.x; e <= hi - lo; e += kThreads) hval[e] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                if (c[q] >= 0) atomicAdd(&hval[c[q] - lo], 1u);
+            __syncthreads();
+            for (int e = threadIdx.x; e <= hi - lo; e += kThreads)
+                if (hval[e]) atomicAdd(&cnt[lo + e], hval[e]);
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (!__any(c[q] >= 0)) continue;                    // wave-uniform
+            const uint64_t key = wave_sort_keys(c[q]);
+            const int32_t cs = key == ~0ull ? -1 : (int32_t)(key >> 6);
+            const WaveRun r = wave_run(cs);
+            if (cs >= 0 && r.head == lane) atomicAdd(&cnt[cs], r.len);
+        }
+        return;
+    }
+    sort_hash_clear(hkey, hval);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int32_t c = sort_key<T>(base + q * kThreads + threadIdx.x, n, w, cell, ncell);
         const WaveRun r = wave_run(c);
-        if (c >= 0 && r.head == lane) {
-            if (TABLE) atomicAdd(&hval[sort_hash_slot(c, hkey)], r.len);
-            else atomicAdd(&cnt[c], r.len);
-        }
+        if (c >= 0 && r.head == lane) atomicAdd(&hval[sort_hash_slot(c, hkey)], r.len);
     }
-    if (TABLE) {
-        __syncthreads();
-        for (int h = threadIdx.x; h < kSortHash; h += kThreads)
-            if (hkey[h] >= 0) atomicAdd(&cnt[hkey[h]], hval[h]);
-    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < kSortHash; h += kThreads)
+        if (hkey[h] >= 0) atomicAdd(&cnt[hkey[h]], hval[h]);
 }
 
 // Per block of kSortCellsPerBlock cells: the sum of their counts.
@@ -2069,25 +2136,70 @@ k_sort_offsets(int64_t ncell, const uint32_t* __restrict__ cnt, const uint64_t* 
 }
 
 // Source index of every live particle into its cell's range.  The per-cell count is
-// consumed as a countdown: one atomic
-// per run of a wavefront reserving the run's places, or with TABLE one per cell and
-// block reserving the block's share, within which each particle takes the place its run
-// and the block's table give.  The order within a cell is whatever the atomics give.
-// Nothing when the output does not fit (ctrl[0]).
+// consumed as a countdown: one atomic per cell and block reserving the block's share
+// (with TABLE through the block's cell table, else through the direct-mapped window when
+// the block's cells fit), within which each particle takes the place its run and the
+// table, or an LDS countdown, give; else one atomic per run of a wavefront's sorted
+// cells.  The order within a cell is whatever the atomics give.  Nothing when the
+// output does not fit (ctrl[0]).
 template <typename T, bool TABLE>
 __global__ void __launch_bounds__(kThreads)
 k_sort_scatter(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t* __restrict__ cell,
                const int64_t* __restrict__ off, const int64_t* __restrict__ ctrl,
                uint32_t* __restrict__ cnt, uint32_t* __restrict__ idx) {
     __shared__ int32_t hkey[TABLE ? kSortHash : 1];
-    __shared__ uint32_t hval[TABLE ? kSortHash : 1];   // a cell's count in the block, then its base
+    __shared__ uint32_t hval[TABLE ? kSortHash : kSortWin];   // a cell's count in the block
+    __shared__ uint32_t hbase[TABLE ? 1 : kSortWin];          // the block's base in the cell
+    __shared__ int32_t rng[2 * (kThreads / 64)];
     if (ctrl[0]) return;                     // uniform over the grid
-    if (TABLE) {
-        sort_hash_clear(hkey, hval);
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63;
     const int64_t base = (int64_t)blockIdx.x * kSortSlots;
+    if (!TABLE) {
+        int32_t cc[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            cc[q] = sort_key<T>(base + q * kThreads + threadIdx.x, n, w, cell, ncell);
+        int32_t lo, hi;
+        block_key_range(cc, rng, &lo, &hi);
+        if (hi < lo) return;                                // uniform: no live particle
+        if (hi - lo < kSortWin) {
+            for (int e = threadIdx.x; e <= hi - lo; e += kThreads) hval[e] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                if (cc[q] >= 0) atomicAdd(&hval[cc[q] - lo], 1u);
+            __syncthreads();
+            for (int e = threadIdx.x; e <= hi - lo; e += kThreads) {
+                const uint32_t t = hval[e];
+                if (t) hbase[e] = atomicSub(&cnt[lo + e], t) - t;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                if (cc[q] >= 0) {
+                    const int e = cc[q] - lo;
+                    const uint32_t pos = atomicSub(&hval[e], 1u) - 1u;
+                    idx[off[cc[q]] + hbase[e] + pos] = (uint32_t)(base + q * kThreads + threadIdx.x);
+                }
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t i0 = base + q * kThreads + (threadIdx.x & ~63);   // the wave's first
+            const int32_t c0 = cc[q];
+            if (!__any(c0 >= 0)) continue;                  // wave-uniform
+            const uint64_t key = wave_sort_keys(c0);
+            const int32_t c = key == ~0ull ? -1 : (int32_t)(key >> 6);
+            const WaveRun r = wave_run(c);
+            uint32_t l = 0;
+            if (c >= 0 && r.head == lane) l = atomicSub(&cnt[c], r.len) - r.len;
+            l = __shfl(l, r.head, 64) + (uint32_t)(lane - r.head);
+            if (c >= 0) idx[off[c] + l] = (uint32_t)(i0 + (int64_t)(key & 63u));
+        }
+        return;
+    }
+    sort_hash_clear(hkey, hval);
+    __syncthreads();
     int32_t cq[kPer];
     int slot[kPer];
     uint32_t loc[kPer];
@@ -2098,31 +2210,24 @@ k_sort_scatter(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t*
         int h = 0;
         uint32_t l = 0;
         if (c >= 0 && r.head == lane) {
-            if (TABLE) {
-                h = sort_hash_slot(c, hkey);
-                l = atomicAdd(&hval[h], r.len);
-            } else {
-                l = atomicSub(&cnt[c], r.len) - r.len;
-            }
+            h = sort_hash_slot(c, hkey);
+            l = atomicAdd(&hval[h], r.len);
         }
         slot[q] = __shfl(h, r.head, 64);
         loc[q] = __shfl(l, r.head, 64) + (uint32_t)(lane - r.head);
         cq[q] = c;
     }
-    if (TABLE) {
-        __syncthreads();
-        for (int h = threadIdx.x; h < kSortHash; h += kThreads)
-            if (hkey[h] >= 0) {
-                const uint32_t t = hval[h];
-                hval[h] = atomicSub(&cnt[hkey[h]], t) - t;
-            }
-        __syncthreads();
-    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < kSortHash; h += kThreads)
+        if (hkey[h] >= 0) {
+            const uint32_t t = hval[h];
+            hval[h] = atomicSub(&cnt[hkey[h]], t) - t;
+        }
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q)
         if (cq[q] >= 0)
-            idx[off[cq[q]] + (TABLE ? hval[slot[q]] : 0u) + loc[q]] =
-                (uint32_t)(base + q * kThreads + threadIdx.x);
+            idx[off[cq[q]] + hval[slot[q]] + loc[q]] = (uint32_t)(base + q * kThreads + threadIdx.x);
 }
 
 // The arrays a sort moves: particle i of `in` to slot d of `out`.

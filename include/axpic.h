@@ -326,10 +326,13 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
  * affine remap p' = S p + b (eqs. delta_def .. b_def, applied when
  * prm->feedback) and the temperature update (eqs. Te_est, Te_relax, clamp)
  * when prm->T_mode == 2.  moments: [ncell][5] FP64 output (before the remap)
- * or NULL. */
+ * or NULL.  stats (or NULL): the cold cells, the clamped cells and the energy
+ * they could not take (O10) are added in a fixed order through `ws`, which must
+ * then hold axpic_workspace_bytes(2 ncell) bytes (else NULL). */
 axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
                             axpic_species* electrons, const int64_t* off, const double* fb,
-                            double* moments, double* stats, int64_t* chain, void* stream);
+                            double* moments, double* stats, void* ws, size_t ws_bytes,
+                            int64_t* chain, void* stream);
 
 /* axpic_sort_cells -- the canonical buffer order (Sec. II.E: the operators are local to
  * a cell; the order within a buffer is this library's convention): a stable counting

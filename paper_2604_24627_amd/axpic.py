@@ -134,7 +134,7 @@ def load(path: Optional[str] = None):
                                _P, _P, _P, C.c_size_t, _P, _P]),
         ("axpic_absorb", [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P, _P, _P, _P, _P,
                           C.c_size_t, _P, _P]),
-        ("axpic_feedback", [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+        ("axpic_feedback", [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P, _P]),
         ("axpic_compact", [_P, _P, _P, _P, C.c_size_t, _P]),
         ("axpic_diag", [_P, C.c_double, _P, _P, C.c_size_t, _P]),
         ("axpic_sampler_table", [C.c_int32, C.c_double, _P]),

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -658,10 +659,19 @@ k_acc_reduce(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int6
              int nh, const int64_t* __restrict__ ctrl, double* __restrict__ hist,
              double* __restrict__ stats) {
     __shared__ double lds[kThreads / 64];
-    if (ctrl[0]) return;
+    if (ctrl && ctrl[0]) return;
     const int j = blockIdx.x;
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < nrec; r += kThreads) s += rec[r * rstride + j * cstride];
+    // eight loads in flight, added in the same order as one at a time
+    int64_t r = threadIdx.x;
+    for (; r + 7 * kThreads < nrec; r += 8 * kThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = rec[(r + u * kThreads) * rstride + j * cstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < nrec; r += kThreads) s += rec[r * rstride + j * cstride];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -1551,13 +1561,18 @@ __global__ void __launch_bounds__(kThreads)
 k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ off,
            const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
            const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
-           double* __restrict__ stats, const int64_t* __restrict__ chain) {
+           double* __restrict__ stats, double* __restrict__ ecell, int64_t* __restrict__ flag,
+           int64_t token, const int64_t* __restrict__ chain) {
     // a chained step whose appending calls were skipped after an overflow is repeated
     // whole: the feedback of its partial exchange must not be applied
     if (chain && chain[AXPIC_CHAIN_SKIP]) return;
     const int lane = threadIdx.x & 63, sub = lane & (kCellLanes - 1);
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCellLanes;
     const bool valid = c < ncell;
+    // the energy a cold or clamped cell leaves unapplied goes to its own slot (0 for every
+    // other cell) and the call's token to *flag; k_fb_unapplied then sums the slots in
+    // cell order.  The cell counts are exact in any order.
+    if (ecell && valid && sub == 0) ecell[c] = 0.0;
     const double* f = (fb && valid) ? fb + c * 4 : nullptr;
     const double dE = f ? f[0] : 0.0;
     const double f1 = f ? f[1] : 0.0, f2 = f ? f[2] : 0.0, f3 = f ? f[3] : 0.0;
@@ -1607,13 +1622,15 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
         var_new = var;
         if (sub == 0 && stats) {
             atomicAdd(&stats[AXPIC_ST_COLD_CELLS], 1.0);
-            atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], dEth);
+            ecell[c] = dEth;
+            *flag = token;
         }
     } else {
         if (var_new < 0.0) {
             if (sub == 0 && stats) {
                 atomicAdd(&stats[AXPIC_ST_CLAMPED_CELLS], 1.0);
-                atomicAdd(&stats[AXPIC_ST_UNAPPLIED_E], -var_new * 0.5);
+                ecell[c] = -var_new * 0.5;
+                *flag = token;
             }
             var_new = 0.0;
         }
@@ -1643,6 +1660,33 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
         Tn = Tn < kp.T_floor ? kp.T_floor : (Tn > kp.T_ceil ? kp.T_ceil : Tn);
         Tk[c] = Tn;
     }
+}
+
+// After k_feedback: when a cell of this call (token) left energy unapplied, the slots of
+// all cells summed in cell order (each thread a strided run, then the butterfly and the
+// wavefronts in order) into stats[AXPIC_ST_UNAPPLIED_E].  One workgroup.
+__global__ void __launch_bounds__(kThreads)
+k_fb_unapplied(int64_t ncell, const double* __restrict__ ecell, const int64_t* __restrict__ flag,
+               int64_t token, const int64_t* __restrict__ chain, double* __restrict__ stats) {
+    __shared__ double lds[kThreads / 64];
+    if ((chain && chain[AXPIC_CHAIN_SKIP]) || *flag != token) return;
+    double s = 0.0;
+    int64_t c = threadIdx.x;
+    for (; c + 7 * kThreads < ncell; c += 8 * kThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ecell[c + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < ncell; c += kThreads) s += ecell[c];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    s = 0.0;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) s += lds[w2];
+    stats[AXPIC_ST_UNAPPLIED_E] += s;
 }
 
 // ------------------------------------------------------------------ superposed thermal emission
@@ -3100,22 +3144,39 @@ axpic_status axpic_absorb(const axpic_grid* g, const axpic_cells* cells, const a
 
 axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic_params* prm,
                             axpic_species* el, const int64_t* off, const double* fb,
-                            double* moments, double* stats, int64_t* chain, void* stream) {
+                            double* moments, double* stats, void* ws, size_t ws_bytes,
+                            int64_t* chain, void* stream) {
     if (!grid_ok(g) || !params_ok(prm) || !cells || !off || !cells->T_keV) return AXPIC_E_INVAL;
     if (!species_ok(el, true) || el->kind != AXPIC_ELECTRON) return AXPIC_E_INVAL;
     if (cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
     KParams kp = make_kparams(g, prm, 0.0);
-    const int64_t threads = cells->ncell * kCellLanes;
+    const int64_t ncell = cells->ncell, threads = ncell * kCellLanes;
+    // with statistics: one FP64 slot per cell (the per-parent region of a workspace for 2
+    // ncell parents) and a flag word stamped with a token of this call
+    double* ecell = nullptr;
+    int64_t* flag = nullptr;
+    static std::atomic<int64_t> next_token{1};
+    const int64_t token = next_token.fetch_add(1) | (int64_t)1 << 62;
+    if (stats) {
+        Workspace W;
+        if (!carve(ws, ws_bytes, 2 * ncell, &W)) return AXPIC_E_INVAL;
+        ecell = (double*)W.code;
+        flag = W.ctrl + 7;
+    }
+    hipStream_t s = S(stream);
     if (el->dtype == AXPIC_F32)
-        LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, S(stream),
-                           cells->ncell, kp, el->w_ref, off, (const float*)el->w, (float*)el->p[0],
-                           (float*)el->p[1], (float*)el->p[2], fb, cells->T_keV, moments, stats,
-                           (const int64_t*)chain);
+        LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
+               el->w_ref, off, (const float*)el->w, (float*)el->p[0], (float*)el->p[1],
+               (float*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token,
+               (const int64_t*)chain);
     else
-        LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, S(stream),
-                           cells->ncell, kp, el->w_ref, off, (const double*)el->w,
-                           (double*)el->p[0], (double*)el->p[1], (double*)el->p[2], fb,
-                           cells->T_keV, moments, stats, (const int64_t*)chain);
+        LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
+               el->w_ref, off, (const double*)el->w, (double*)el->p[0], (double*)el->p[1],
+               (double*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token,
+               (const int64_t*)chain);
+    if (stats)
+        LAUNCH("k_fb_unapplied", k_fb_unapplied, dim3(1), dim3(kThreads), 0, s, ncell, ecell,
+               (const int64_t*)flag, token, (const int64_t*)chain, stats);
     return launched();
 }
 

@@ -199,7 +199,7 @@ class AxpicSim:
         self.diag_out = torch.zeros(2, dtype=f64, device=dev)
         self.ws = None
         self.ws_bytes = 0
-        self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity))
+        self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity, 2 * self.ncell))
         self.stream = stream
         s = self.sh
         B.check(self.lib.axpic_deposit(B.ref(self.grid), B.ref(self.el.struct()), B.ptr(self.el.off),
@@ -366,10 +366,11 @@ class AxpicSim:
         return k
 
     def feedback(self, moments=None, chain=None):
+        self._ensure_ws(2 * self.ncell)
         B.check(self.lib.axpic_feedback(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
                                         B.ref(self.el.struct()), B.ptr(self.el.off),
                                         B.ptr(self.fb), B.ptr(moments), B.ptr(self.stats),
-                                        B.ptr(chain), self.sh),
+                                        B.ptr(self.ws), self.ws_bytes, B.ptr(chain), self.sh),
                 "feedback")
 
     def bin_axions(self, push: bool = True):
@@ -564,7 +565,8 @@ class AxpicSim:
 
         def op_fb():
             return self.lib.axpic_feedback(g, c, prm, B.ref(self.el.struct()), B.ptr(self.el.off),
-                                           B.ptr(self.fb), None, B.ptr(self.stats), ch, sh)
+                                           B.ptr(self.fb), None, B.ptr(self.stats),
+                                           B.ptr(self.ws), self.ws_bytes, ch, sh)
         ops = []
         if p["channels"] & B.PRIMAKOFF:
             ops.append((op_prim, 0, self.ax))

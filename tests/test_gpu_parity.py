@@ -341,14 +341,21 @@ def test_absorption_decisions_bit_exact(mode, sort, n, per_cell):
     assert st["abs_num"] - st0["abs_num"] == pytest.approx(st_o[O.ST["abs_num"]], rel=1e-6)
 
 
+@pytest.mark.parametrize("scale", [80, 2000])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_feedback_matches_oracle(dtype):
+def test_feedback_matches_oracle(dtype, scale):
+    """Moments, remapped momenta and T against the oracle; at the larger exchange many
+    cells cannot give the energy asked of them (clamped, O10): their count and the energy
+    left unapplied, summed in a fixed order, are the oracle's and repeat bit for bit."""
     wl = small_workload(dtype, channels=6, g_ae=1e-13, feedback=1, T_mode=2, r_relax=0.3)
     g, o, pl = pair(wl)
     rng = np.random.default_rng(21)
-    fb = rng.normal(0, 1, (g.ncell, 4)) * np.array([3e-3, 1e-3, 1e-3, 1e-3]) * 80
+    fb = rng.normal(0, 1, (g.ncell, 4)) * np.array([3e-3, 1e-3, 1e-3, 1e-3]) * scale
     g.fb.copy_(torch.from_numpy(fb.ravel()))
     mom = torch.zeros(g.ncell * 5, dtype=torch.float64, device="cuda")
+    p_before = [g.el.p[d].clone() for d in range(3)]
+    T_before = g.T.clone()
+    g.stats.zero_()
     g.feedback(moments=mom)
     mo = np.zeros(g.ncell * 5)
     st = np.zeros(O.ST_COUNT)
@@ -359,7 +366,21 @@ def test_feedback_matches_oracle(dtype):
     tol = 2e-6 if dtype == "f32" else 1e-11
     np.testing.assert_allclose(gp, o.el.p, rtol=tol, atol=tol * np.abs(o.el.p).max())
     np.testing.assert_allclose(g.T.cpu().numpy(), o.T, rtol=1e-10)
-    assert st[O.ST["clamped_cells"]] == g.stats_dict()["clamped_cells"]
+    gst = g.stats_dict()
+    assert st[O.ST["clamped_cells"]] == gst["clamped_cells"]
+    assert st[O.ST["cold_cells"]] == gst["cold_cells"]
+    assert gst["unapplied_E"] == pytest.approx(st[O.ST["unapplied_E"]], rel=1e-9, abs=0)
+    if scale > 100:
+        assert gst["clamped_cells"] > 50
+        # the same call again from the same state: the statistics repeat bit for bit
+        first = g.stats.clone()
+        for d in range(3):
+            g.el.p[d].copy_(p_before[d])
+        g.T.copy_(T_before)
+        g.stats.zero_()
+        g.feedback()
+        torch.cuda.synchronize()
+        assert torch.equal(g.stats, first)
 
 
 def test_compaction_is_stable_and_exact():

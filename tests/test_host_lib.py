@@ -98,7 +98,7 @@ def test_invalid_arguments_rejected_on_host():
                                None) == -1
     prm = B.make_params(I.Params(r_relax=1.5))
     assert L.axpic_feedback(B.ref(g), B.ref(cells), B.ref(prm), B.ref(sp), None, None, None,
-                            None, None, None) == -1
+                            None, None, 0, None, None) == -1
     assert L.axpic_sampler_table(2, 0.0, None) == -1
 
 

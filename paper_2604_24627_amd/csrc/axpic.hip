@@ -532,12 +532,21 @@ __device__ __forceinline__ void fb_finish(FbOpen& o, double* __restrict__ fb,
     }
 }
 
+// Blocks of an events grid of nb blocks that get events when `total` events are split
+// over it: as many as there are tiles of kThreads events, at most the grid.
+__device__ __forceinline__ int64_t ev_blocks(int64_t total, int64_t nb) {
+    const int64_t tiles = (total + kThreads - 1) / kThreads;
+    return tiles < nb ? tiles : nb;
+}
+
 // The boundary records of nb blocks in block order: each first record of a run of equal
 // keys sums the run in order and adds it to fb (key -1: none).  Nothing after an overflow.
+// ev: the blocks of an events grid, of which only the first ev_blocks(ctrl[1]) wrote.
 __global__ void __launch_bounds__(kThreads)
 k_fb_bounds(int64_t nb, const int32_t* __restrict__ bkey, const double* __restrict__ bval,
-            const int64_t* __restrict__ ctrl, double* __restrict__ fb) {
+            const int64_t* __restrict__ ctrl, double* __restrict__ fb, int ev) {
     if (ctrl[0]) return;
+    if (ev) nb = ev_blocks(ctrl[1], nb);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * nb) return;
     const int32_t k = bkey[i];
@@ -549,11 +558,9 @@ k_fb_bounds(int64_t nb, const int32_t* __restrict__ bkey, const double* __restri
     for (int q = 0; q < 4; ++q) f[q] += s[q];
 }
 
-// The contiguous range of events of block b when `total` events are split over the
-// grid (as many blocks as there are tiles of kThreads events, at most the grid).
+// The contiguous range of events of block b (empty for the blocks beyond ev_blocks).
 __device__ __forceinline__ void ev_range(int64_t total, int64_t* lo, int64_t* hi) {
-    const int64_t tiles = (total + kThreads - 1) / kThreads;
-    const int64_t ga = tiles < (int64_t)gridDim.x ? tiles : (int64_t)gridDim.x;
+    const int64_t ga = ev_blocks(total, (int64_t)gridDim.x);
     const int64_t b = blockIdx.x;
     if (b >= ga) { *lo = *hi = 0; return; }
     *lo = total * b / ga;
@@ -657,9 +664,10 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
 __global__ void __launch_bounds__(kThreads)
 k_acc_reduce(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int64_t cstride,
              int nh, const int64_t* __restrict__ ctrl, double* __restrict__ hist,
-             double* __restrict__ stats) {
+             double* __restrict__ stats, int ev) {
     __shared__ double lds[kThreads / 64];
     if (ctrl && ctrl[0]) return;
+    if (ev) nrec = ev_blocks(ctrl[1], nrec);      // an events grid: its writing blocks
     const int j = blockIdx.x;
     double s = 0.0;
     // eight loads in flight, added in the same order as one at a time
@@ -1040,6 +1048,9 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
+    int64_t lo, hi;
+    ev_range(total, &lo, &hi);
+    if (lo >= hi) return;                 // no events: no record (the reduction skips it)
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
     for (int k = threadIdx.x; k < (kThreads / 64) * nbh; k += kThreads) wh[k] = 0.0;
@@ -1047,8 +1058,6 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
     double* myh = wh + (threadIdx.x >> 6) * nbh;
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
-    int64_t lo, hi;
-    ev_range(total, &lo, &hi);
     for (int64_t t0 = lo; t0 < hi; t0 += kThreads) {
         const int64_t e = t0 + threadIdx.x;
         int bin = -1;
@@ -1099,7 +1108,7 @@ k_prim_events(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_re
         wave_hist_add(myh, bin, hv);
     }
     __syncthreads();
-    rec_write(wh, nbh, st, smap, lst, rec + (int64_t)blockIdx.x * (nbh + AXPIC_ST_COUNT));
+    rec_write(wh, nbh, st, smap, lst, rec + blockIdx.x, kEventBlocks);
 }
 
 // ------------------------------------------------------------------ thermal emission
@@ -1197,6 +1206,9 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
+    int64_t lo, hi;
+    ev_range(total, &lo, &hi);
+    if (lo >= hi) return;                 // no events: no records (the reductions skip them)
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
     const int H = 2 * nbh;
@@ -1206,8 +1218,6 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     FbOpen open;
-    int64_t lo, hi;
-    ev_range(total, &lo, &hi);
     for (int64_t t0 = lo; t0 < hi; t0 += kThreads) {
         const int64_t e = t0 + threadIdx.x;
         const int64_t slot = out_n + e;
@@ -1257,7 +1267,7 @@ k_therm_events(int64_t n, int64_t step, uint64_t next_id, KParams kp,
     }
     if (fb) fb_finish(open, fb, bkey, bval, blockIdx.x);
     __syncthreads();
-    rec_write(wh, H, st, smap, lst, rec + (int64_t)blockIdx.x * (H + AXPIC_ST_COUNT));
+    rec_write(wh, H, st, smap, lst, rec + blockIdx.x, kEventBlocks);
 }
 
 // ------------------------------------------------------------------ absorption
@@ -1833,6 +1843,9 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
     out_n = ctrl[2];
     next_id = (uint64_t)ctrl[3];
     const int64_t total = ctrl[1];
+    int64_t elo, ehi;
+    ev_range(total, &elo, &ehi);
+    if (elo >= ehi) return;               // no events: no records (the reductions skip them)
     const T* pref = PrefOf<T>::get(p32, p64);
     const int nbh = kp.nbins + 2;
     const int H = 2 * nbh;
@@ -1842,8 +1855,6 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
     double st[kStatSlots];
     for (int s = 0; s < kStatSlots; ++s) st[s] = 0.0;
     FbOpen open;
-    int64_t elo, ehi;
-    ev_range(total, &elo, &ehi);
     for (int64_t t0 = elo; t0 < ehi; t0 += kThreads) {
         const int64_t e = t0 + threadIdx.x;
         const int64_t slot = out_n + e;
@@ -1919,7 +1930,7 @@ k_sup_events(int64_t ncell, int64_t step, uint64_t next_id, KParams kp,
     }
     if (fb) fb_finish(open, fb, bkey, bval, blockIdx.x);
     __syncthreads();
-    rec_write(wh, H, st, smap, lst, rec + (int64_t)blockIdx.x * (H + AXPIC_ST_COUNT));
+    rec_write(wh, H, st, smap, lst, rec + blockIdx.x, kEventBlocks);
 }
 
 // ------------------------------------------------------------------ compaction
@@ -2644,21 +2655,22 @@ inline float product_ratio(double wprod, double w_ref) {
 }
 
 // The per-block records of the last accumulating kernel (nrec records of ncol columns,
-// the first nh of them histogram bins for hist; row-major, or column-major with colmajor)
-// summed into hist and stats.
+// the first nh of them histogram bins for hist; column-major, column j at j nrec) summed
+// into hist and stats.  ev: the records of an events grid of nrec blocks, of which only
+// those that got events wrote.
 void acc_reduce(const Workspace& W, int64_t nrec, int ncol, int nh, double* hist, double* stats,
-                hipStream_t s, bool colmajor = false) {
+                hipStream_t s, bool ev) {
     if (!hist && !stats) return;
     LAUNCH("k_acc_reduce", k_acc_reduce, dim3((unsigned)ncol), dim3(kThreads), 0, s, W.rec, nrec,
-           colmajor ? (int64_t)1 : (int64_t)ncol, colmajor ? nrec : (int64_t)1, nh, W.ctrl, hist,
-           stats);
+           (int64_t)1, nrec, nh, W.ctrl, hist, stats, ev ? 1 : 0);
 }
 
-// The per-cell sums the blocks of the last kernel share with their neighbours.
-void fb_bounds(const Workspace& W, int64_t nb, double* fb, hipStream_t s) {
+// The per-cell sums the blocks of the last kernel share with their neighbours (ev: as
+// for acc_reduce).
+void fb_bounds(const Workspace& W, int64_t nb, double* fb, hipStream_t s, bool ev) {
     if (!fb) return;
     LAUNCH("k_fb_bounds", k_fb_bounds, dim3((unsigned)((2 * nb + kThreads - 1) / kThreads)),
-           dim3(kThreads), 0, s, nb, W.bkey, W.bval, W.ctrl, fb);
+           dim3(kThreads), 0, s, nb, W.bkey, W.bval, W.ctrl, fb, ev ? 1 : 0);
 }
 
 struct SpT {   // typed view of a species
@@ -2699,7 +2711,7 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
            TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.ctrl, ax->n, TP<T>(ax->x[0]),
            TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]),
            TP<T>(ax->w), ax->id, ax->cell, W.rec, kEmitMap);
-    acc_reduce(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, s);
+    acc_reduce(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, s, true);
     return launched();
 }
 
@@ -2725,9 +2737,9 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
            TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
                        ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
-    fb_bounds(W, kEventBlocks, fb, s);
+    fb_bounds(W, kEventBlocks, fb, s, true);
     acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
-               stats, s);
+               stats, s, true);
     return launched();
 }
 
@@ -2752,9 +2764,9 @@ axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axp
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
            TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),
            TP<T>(ax->p[2]), TP<T>(ax->w), ax->id, ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
-    fb_bounds(W, kEventBlocks, fb, s);
+    fb_bounds(W, kEventBlocks, fb, s, true);
     acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
-               stats, s);
+               stats, s, true);
     return launched();
 }
 
@@ -2792,8 +2804,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
                        W.rec, W.bkey, W.bval, det ? 1 : 0, (const int64_t*)chain, kAbsMap);
-    if (det) fb_bounds(W, nb, fb, s);
-    acc_reduce(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, s, true);
+    if (det) fb_bounds(W, nb, fb, s, false);
+    acc_reduce(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, s, false);
     return launched();
 }
 

@@ -1572,7 +1572,7 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
            const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
            const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
            double* __restrict__ stats, double* __restrict__ ecell, int64_t* __restrict__ flag,
-           int64_t token, const int64_t* __restrict__ chain) {
+           int64_t token, unsigned int* __restrict__ done, const int64_t* __restrict__ chain) {
     // a chained step whose appending calls were skipped after an overflow is repeated
     // whole: the feedback of its partial exchange must not be applied
     if (chain && chain[AXPIC_CHAIN_SKIP]) return;
@@ -1583,6 +1583,7 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     // other cell) and the call's token to *flag; k_fb_unapplied then sums the slots in
     // cell order.  The cell counts are exact in any order.
     if (ecell && valid && sub == 0) ecell[c] = 0.0;
+    if (ecell && blockIdx.x == 0 && threadIdx.x == 0) *done = 0u;   // for k_fb_unapplied
     const double* f = (fb && valid) ? fb + c * 4 : nullptr;
     const double dE = f ? f[0] : 0.0;
     const double f1 = f ? f[1] : 0.0, f2 = f ? f[2] : 0.0, f3 = f ? f[3] : 0.0;
@@ -1672,31 +1673,48 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     }
 }
 
+constexpr int kFbParts = 256;          // blocks of k_fb_unapplied (parts in the workspace records)
+
 // After k_feedback: when a cell of this call (token) left energy unapplied, the slots of
-// all cells summed in cell order (each thread a strided run, then the butterfly and the
-// wavefronts in order) into stats[AXPIC_ST_UNAPPLIED_E].  One workgroup.
+// all cells summed in cell order into stats[AXPIC_ST_UNAPPLIED_E]: block b sums the b-th
+// of gridDim.x equal runs of cells (each thread a strided part, then the butterfly and
+// the wavefronts in order) into part[b], and the block that finishes last adds the
+// parts in block order.  Nothing at all when no cell of the call was flagged.
 __global__ void __launch_bounds__(kThreads)
 k_fb_unapplied(int64_t ncell, const double* __restrict__ ecell, const int64_t* __restrict__ flag,
-               int64_t token, const int64_t* __restrict__ chain, double* __restrict__ stats) {
+               int64_t token, const int64_t* __restrict__ chain, double* __restrict__ part,
+               unsigned int* __restrict__ done, double* __restrict__ stats) {
     __shared__ double lds[kThreads / 64];
+    __shared__ bool last;
     if ((chain && chain[AXPIC_CHAIN_SKIP]) || *flag != token) return;
+    const int64_t per = (ncell + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < ncell ? c0 + per : ncell;
     double s = 0.0;
-    int64_t c = threadIdx.x;
-    for (; c + 7 * kThreads < ncell; c += 8 * kThreads) {
+    int64_t c = c0 + threadIdx.x;
+    for (; c + 7 * kThreads < c1; c += 8 * kThreads) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = ecell[c + u * kThreads];
 #pragma unroll
         for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; c < ncell; c += kThreads) s += ecell[c];
+    for (; c < c1; c += kThreads) s += ecell[c];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    s = 0.0;
-    for (int w2 = 0; w2 < kThreads / 64; ++w2) s += lds[w2];
-    stats[AXPIC_ST_UNAPPLIED_E] += s;
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) b += lds[w2];
+        part[blockIdx.x] = b;
+        __threadfence();                                  // the part before the count
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();                                      // every part after the count
+    double t = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[b];
+    stats[AXPIC_ST_UNAPPLIED_E] += t;
 }
 
 // ------------------------------------------------------------------ superposed thermal emission
@@ -3166,29 +3184,33 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     // with statistics: one FP64 slot per cell (the per-parent region of a workspace for 2
     // ncell parents) and a flag word stamped with a token of this call
     double* ecell = nullptr;
+    double* part = nullptr;
     int64_t* flag = nullptr;
+    unsigned int* done = nullptr;
     static std::atomic<int64_t> next_token{1};
     const int64_t token = next_token.fetch_add(1) | (int64_t)1 << 62;
     if (stats) {
         Workspace W;
         if (!carve(ws, ws_bytes, 2 * ncell, &W)) return AXPIC_E_INVAL;
         ecell = (double*)W.code;
+        part = W.rec;
         flag = W.ctrl + 7;
+        done = (unsigned int*)(W.ctrl + 6);
     }
     hipStream_t s = S(stream);
     if (el->dtype == AXPIC_F32)
         LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
                el->w_ref, off, (const float*)el->w, (float*)el->p[0], (float*)el->p[1],
-               (float*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token,
+               (float*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token, done,
                (const int64_t*)chain);
     else
         LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
                el->w_ref, off, (const double*)el->w, (double*)el->p[0], (double*)el->p[1],
-               (double*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token,
+               (double*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token, done,
                (const int64_t*)chain);
     if (stats)
-        LAUNCH("k_fb_unapplied", k_fb_unapplied, dim3(1), dim3(kThreads), 0, s, ncell, ecell,
-               (const int64_t*)flag, token, (const int64_t*)chain, stats);
+        LAUNCH("k_fb_unapplied", k_fb_unapplied, dim3(kFbParts), dim3(kThreads), 0, s, ncell,
+               ecell, (const int64_t*)flag, token, (const int64_t*)chain, part, done, stats);
     return launched();
 }
 
@@ -3409,15 +3431,23 @@ void axpic_timing_enable(int32_t on) {
 axpic_status axpic_timing_read(char* buf, size_t len) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lock(t.mu);
+    hipEvent_t prev_stop = nullptr;
     for (auto& p : t.pending) {
         // the dispatch's own events give the kernel's duration, but their start has been
         // seen to lie far too early on a queue shared with other work; the stream markers
-        // around the launch bound the duration from above, so the smaller is kept
+        // around the launch bound the duration from above, and so does the time from the
+        // previous launch's end to this one's (launches in order on one stream): the
+        // smallest is kept (the last bound fails only across an idle gap, where the
+        // dispatch's own start is right)
         float ms = 0.0f, mm = 0.0f;
         if (hipEventSynchronize(p.mb) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess ||
             hipEventElapsedTime(&mm, p.ma, p.mb) != hipSuccess)
             return AXPIC_E_DEVICE;
         ms = std::min(ms, mm);
+        float mc = 0.0f;
+        if (prev_stop && hipEventElapsedTime(&mc, prev_stop, p.b) == hipSuccess && mc > 0.0f)
+            ms = std::min(ms, mc);
+        prev_stop = p.b;
         bool found = false;
         for (auto& e : t.acc)
             if (e.first == p.name) { e.second.first += 1; e.second.second += ms; found = true; break; }

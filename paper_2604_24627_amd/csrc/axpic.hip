@@ -1554,19 +1554,21 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
 }
 
 // ------------------------------------------------------------------ feedback
-// Four cells per wavefront, 16 lanes per cell: FP64 moments by strided loads
-// and a 16-lane shuffle reduction, then the affine remap and the temperature
-// update of each cell.
+// L lanes per cell (16: four cells per wavefront; 8, eight, where the cells hold fewer
+// electrons): FP64 moments by strided loads and an L-lane shuffle reduction, then the
+// affine remap and the temperature update of each cell.
 constexpr int kCellLanes = 16;
-constexpr int kFbCache = 4;            // electrons per lane kept in registers (64 per cell)
+constexpr int kFbCache = 4;            // electrons per lane kept in registers
 
-__device__ __forceinline__ double group_sum16(double v) {
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+__device__ __forceinline__ double group_sum16(double v) { return group_sum<16>(v); }
 
-template <typename T>
+template <typename T, int L>
 __global__ void __launch_bounds__(kThreads)
 k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ off,
            const T* __restrict__ w, T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
@@ -1576,8 +1578,8 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     // a chained step whose appending calls were skipped after an overflow is repeated
     // whole: the feedback of its partial exchange must not be applied
     if (chain && chain[AXPIC_CHAIN_SKIP]) return;
-    const int lane = threadIdx.x & 63, sub = lane & (kCellLanes - 1);
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kCellLanes;
+    const int lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
     const bool valid = c < ncell;
     // the energy a cold or clamped cell leaves unapplied goes to its own slot (0 for every
     // other cell) and the call's token to *flag; k_fb_unapplied then sums the slots in
@@ -1598,7 +1600,7 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
     T cx[kFbCache], cy[kFbCache], cz[kFbCache];
 #pragma unroll
     for (int q = 0; q < kFbCache; ++q) {
-        const int64_t i = lo + sub + (int64_t)q * kCellLanes;
+        const int64_t i = lo + sub + (int64_t)q * L;
         cx[q] = cy[q] = cz[q] = (T)0;
         if (i < hi) {
             const double wi = w_ref * (double)w[i];
@@ -1608,14 +1610,14 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
             U2 += wi * (a * a + b * b + d * d);
         }
     }
-    for (int64_t i = lo + sub + (int64_t)kFbCache * kCellLanes; i < hi; i += kCellLanes) {
+    for (int64_t i = lo + sub + (int64_t)kFbCache * L; i < hi; i += L) {
         const double wi = w_ref * (double)w[i];
         const double a = px[i], b = py[i], d = pz[i];
         W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
         U2 += wi * (a * a + b * b + d * d);
     }
-    W = group_sum16(W); P0 = group_sum16(P0); P1 = group_sum16(P1); P2 = group_sum16(P2);
-    U2 = group_sum16(U2);
+    W = group_sum<L>(W); P0 = group_sum<L>(P0); P1 = group_sum<L>(P1); P2 = group_sum<L>(P2);
+    U2 = group_sum<L>(U2);
     if (!work) return;
     if (moments && sub == 0) {
         double* m = moments + c * 5;
@@ -1652,14 +1654,14 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
                      b2 = (1.0 - S) * (P2 / W) + d2;
 #pragma unroll
         for (int q = 0; q < kFbCache; ++q) {
-            const int64_t i = lo + sub + (int64_t)q * kCellLanes;
+            const int64_t i = lo + sub + (int64_t)q * L;
             if (i < hi) {
                 px[i] = (T)(S * (double)cx[q] + b0);
                 py[i] = (T)(S * (double)cy[q] + b1);
                 pz[i] = (T)(S * (double)cz[q] + b2);
             }
         }
-        for (int64_t i = lo + sub + (int64_t)kFbCache * kCellLanes; i < hi; i += kCellLanes) {
+        for (int64_t i = lo + sub + (int64_t)kFbCache * L; i < hi; i += L) {
             px[i] = (T)(S * (double)px[i] + b0);
             py[i] = (T)(S * (double)py[i] + b1);
             pz[i] = (T)(S * (double)pz[i] + b2);
@@ -3180,7 +3182,9 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     if (!species_ok(el, true) || el->kind != AXPIC_ELECTRON) return AXPIC_E_INVAL;
     if (cells->ncell != ncell_of(g)) return AXPIC_E_INVAL;
     KParams kp = make_kparams(g, prm, 0.0);
-    const int64_t ncell = cells->ncell, threads = ncell * kCellLanes;
+    // eight lanes per cell where the cells hold fewer than 48 electrons on average
+    const bool narrow = el->n < 48 * cells->ncell;
+    const int64_t ncell = cells->ncell, threads = ncell * (narrow ? 8 : kCellLanes);
     // with statistics: one FP64 slot per cell (the per-parent region of a workspace for 2
     // ncell parents) and a flag word stamped with a token of this call
     double* ecell = nullptr;
@@ -3199,12 +3203,14 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     }
     hipStream_t s = S(stream);
     if (el->dtype == AXPIC_F32)
-        LAUNCH("k_feedback", k_feedback<float>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
+        LAUNCH("k_feedback", (narrow ? k_feedback<float, 8> : k_feedback<float, 16>),
+               grid1(threads), dim3(kThreads), 0, s, ncell, kp,
                el->w_ref, off, (const float*)el->w, (float*)el->p[0], (float*)el->p[1],
                (float*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token, done,
                (const int64_t*)chain);
     else
-        LAUNCH("k_feedback", k_feedback<double>, grid1(threads), dim3(kThreads), 0, s, ncell, kp,
+        LAUNCH("k_feedback", (narrow ? k_feedback<double, 8> : k_feedback<double, 16>),
+               grid1(threads), dim3(kThreads), 0, s, ncell, kp,
                el->w_ref, off, (const double*)el->w, (double*)el->p[0], (double*)el->p[1],
                (double*)el->p[2], fb, cells->T_keV, moments, stats, ecell, flag, token, done,
                (const int64_t*)chain);

@@ -341,13 +341,16 @@ def test_absorption_decisions_bit_exact(mode, sort, n, per_cell):
     assert st["abs_num"] - st0["abs_num"] == pytest.approx(st_o[O.ST["abs_num"]], rel=1e-6)
 
 
+@pytest.mark.parametrize("ppc", [37, 64])
 @pytest.mark.parametrize("scale", [80, 2000])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_feedback_matches_oracle(dtype, scale):
-    """Moments, remapped momenta and T against the oracle; at the larger exchange many
-    cells cannot give the energy asked of them (clamped, O10): their count and the energy
-    left unapplied, summed in a fixed order, are the oracle's and repeat bit for bit."""
-    wl = small_workload(dtype, channels=6, g_ae=1e-13, feedback=1, T_mode=2, r_relax=0.3)
+def test_feedback_matches_oracle(dtype, scale, ppc):
+    """Moments, remapped momenta and T against the oracle (8 lanes per cell below 48
+    electrons per cell, 16 from there on); at the larger exchange many cells cannot give
+    the energy asked of them (clamped, O10): their count and the energy left unapplied,
+    summed in a fixed order, are the oracle's and repeat bit for bit."""
+    wl = small_workload(dtype, ppc=ppc, channels=6, g_ae=1e-13, feedback=1, T_mode=2,
+                        r_relax=0.3)
     g, o, pl = pair(wl)
     rng = np.random.default_rng(21)
     fb = rng.normal(0, 1, (g.ncell, 4)) * np.array([3e-3, 1e-3, 1e-3, 1e-3]) * scale

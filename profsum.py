@@ -13,6 +13,8 @@ Kernel names are reduced to the bare function name (k_...).
 
 Usage: python profsum.py <kernel_stats.csv> [<fetch.csv>
 <write.csv> <copy_bytes>] -- prints the table;
+python profsum.py --trace <kernel_trace.csv> <kernel> <n> -- per-kernel calls and
+mean duration from the n-th dispatch of <kernel> on (one leg of a run);
 python profsum.py --sq <counter_collection.csv> -- per-kernel
 medians over dispatches of SQ_WAVES and of the other SQ counters per wavefront; the FETCH_SIZE / WRITE_SIZE
 medians (KiB per dispatch) are scaled so that k_stream_copy of copy_bytes reads
@@ -122,9 +124,39 @@ def sq_table(path):
         print(f"{k:20s} {med[0]:8.0f} " + " ".join(f"{v:18.1f}" for v in med[1:]))
 
 
+def trace_table(path, since, nth):
+    """Per kernel of a --kernel-trace CSV: calls and mean duration over the dispatches
+    from the nth dispatch of kernel `since` on (in start order), e.g. one leg of a run."""
+    with open(path) as f:
+        rows = sorted(((short(r["Kernel_Name"]), int(r["Start_Timestamp"]),
+                        int(r["End_Timestamp"])) for r in csv.DictReader(f)),
+                      key=lambda r: r[1])
+    seen, first = 0, None
+    for i, (k, _, _) in enumerate(rows):
+        if k == since:
+            seen += 1
+            if seen == nth:
+                first = i
+                break
+    if first is None:
+        raise SystemExit(f"no dispatch {nth} of {since}")
+    acc = {}
+    for k, a, b in rows[first:]:
+        c, t = acc.get(k, (0, 0))
+        acc[k] = (c + 1, t + (b - a))
+    span = (rows[-1][2] - rows[first][1]) / 1e6
+    print(f"window: {len(rows) - first} dispatches over {span:.1f} ms")
+    print(f"{'kernel':24s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s}")
+    for k, (c, t) in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+        print(f"{k:24s} {c:6d} {t / c / 1e3:10.2f} {t / 1e6:10.3f}")
+
+
 def main(argv):
     if len(argv) > 2 and argv[1] == "--sq":
         sq_table(argv[2])
+        return
+    if len(argv) > 4 and argv[1] == "--trace":
+        trace_table(argv[2], argv[3], int(argv[4]))
         return
     stats = kernel_stats(argv[1])
     fetch = counters(argv[2], "FETCH_SIZE") if len(argv) > 2 else {}

@@ -575,8 +575,11 @@ axpic_status axpic_rates_table(const axpic_grid* g, const axpic_cells* cells, co
  * every kernel the library launches is bracketed by HIP events recorded on
  * its own stream.  axpic_timing_read waits for those events and writes one
  * line "kernel_name launches total_ms" per kernel into buf (NUL-terminated),
- * then resets the counters; AXPIC_E_CAPACITY if buf was too short. */
+ * then resets the counters; AXPIC_E_CAPACITY if buf was too short.
+ * axpic_timing_only: time only the launches of the kernel so named (NULL: all),
+ * so that the others run without events between them. */
 void axpic_timing_enable(int32_t on);
+void axpic_timing_only(const char* name);
 axpic_status axpic_timing_read(char* buf, size_t len);
 
 #ifdef __cplusplus

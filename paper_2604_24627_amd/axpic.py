@@ -76,7 +76,8 @@ class ParamsC(C.Structure):
 EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axpic_bin_cells",
            "axpic_deposit", "axpic_cell_state", "axpic_rates", "axpic_sample_emit",
            "axpic_absorb", "axpic_feedback", "axpic_compact", "axpic_diag",
-           "axpic_sampler_table", "axpic_timing_enable", "axpic_timing_read",
+           "axpic_sampler_table", "axpic_timing_enable", "axpic_timing_only",
+           "axpic_timing_read",
            "axpic_stream_copy", "axpic_mlp_blob_bytes", "axpic_mlp_train_ws_bytes",
            "axpic_mlp_pack", "axpic_mlp_forward", "axpic_mlp_loss_grad", "axpic_mlp_adam",
            "axpic_rates_mlp", "axpic_surrogate_samples", "axpic_cell_weights",
@@ -175,6 +176,8 @@ def load(path: Optional[str] = None):
     L.axpic_equilibrium_ws_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32]
     L.axpic_timing_enable.restype = None
     L.axpic_timing_enable.argtypes = [C.c_int32]
+    L.axpic_timing_only.restype = None
+    L.axpic_timing_only.argtypes = [C.c_char_p]
     _lib = L
     return L
 

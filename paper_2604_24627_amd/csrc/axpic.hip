@@ -224,6 +224,7 @@ struct PendingTime { const char* name; hipEvent_t a, b, ma, mb; };
 struct TimingState {
     std::mutex mu;
     bool on = false;
+    std::string only;                     // time only the launches of this kernel (if set)
     std::vector<hipEvent_t> pool;
     std::vector<PendingTime> pending;
     std::vector<std::pair<std::string, std::pair<long long, double>>> acc;
@@ -3413,7 +3414,7 @@ namespace axpic_timing {
 bool begin(const char* name, hipEvent_t ev[4]) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lock(t.mu);
-    if (!t.on) return false;
+    if (!t.on || (!t.only.empty() && t.only != name)) return false;
     for (int k = 0; k < 4; ++k) {
         ev[k] = pool_get(t);
         if (!ev[k]) {
@@ -3432,6 +3433,12 @@ void axpic_timing_enable(int32_t on) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lock(t.mu);
     t.on = on != 0;
+}
+
+void axpic_timing_only(const char* name) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    t.only = name ? name : "";
 }
 
 axpic_status axpic_timing_read(char* buf, size_t len) {

@@ -232,6 +232,9 @@ class AxpicSim:
         # canonical order of the axions after every push (axpic_sort_cells): stable by
         # cell, zero weights dropped, cell offsets kept for the operators
         self.sort = sort
+        # the surrogate's axion rates need the kept count on the host before the calls, so
+        # its steps sort unchained (a read-back); the plain steps chain the sort
+        self.sort_chained = surrogate is None
         self.ax_off = torch.zeros(self.ncell + 1, dtype=torch.int64, device=dev)
         self.sort_status = torch.zeros(B.STATUS_N, dtype=torch.int64, device=dev)
         self.sort_ws = None
@@ -488,13 +491,14 @@ class AxpicSim:
         calls are repeated from it on (the skipped ones modified nothing)."""
         p = self.pdict
         self.bin_axions(push=True)
-        # the chain's words before the first chained call (the sort rewrites the axion
-        # count and the start-of-step word on the device)
+        if self.sort and not self.sort_chained:
+            self.sort_axions(chained=False)          # the kept count is now ax.n
+        # the chain's words before the first chained call (a chained sort rewrites the
+        # axion count and the start-of-step word on the device)
         self._chain_np[:] = (self.ax.n, self.ph.n, self.next_id, 0, self.ax.n)
         self.chain.copy_(self.chain_host, non_blocking=True)
-        if self.sort:
-            # the surrogate's axion rates need the kept count on the host before the calls
-            self.sort_axions(chained=self.surrogate is None)
+        if self.sort and self.sort_chained:
+            self.sort_axions(chained=True)
         if p["T_mode"] == 2:
             self.cell_state()
         if self.need_feedback:

@@ -87,17 +87,24 @@ def test_sort_of_nothing_and_of_an_output_that_does_not_fit():
     assert np.all(off == -7)                    # nothing written
 
 
-def test_stepping_with_the_sort_matches_the_oracle():
+@pytest.mark.parametrize("chained", [True, False])
+def test_stepping_with_the_sort_matches_the_oracle(chained):
     """Full steps (forward and inverse channels, T evolved) on both sides, both in the
-    canonical order after every push: the axion buffers equal element for element."""
+    canonical order after every push: the axion buffers equal element for element.  Both
+    ways of sorting inside a step -- chained (the kept count stays on the device) and
+    with the count read back first (as the surrogate's steps do) -- while absorption
+    deletes axions, so that every sort drops some."""
     p = I.Params(g_agg_GeV=1e-10, g_ae=1e-13, channels=7, inverse=1, w_a=1e-36, boost=4e33,
                  lambda_cap=1.0)
     wl = I.Workload("sortstep", ndim=2, n=(12, 10), ppc=24, dtype="f64", T_keV=3.0, n_e=6e25,
                     params=p)
     pl = I.make_plasma(wl, 2)
     g = AxpicSim(pl, wl.params)
+    g.sort_chained = chained
     o = O.OracleSim(pl, wl.params, prec32=False)
+    dropped = 0
     for s in range(6):
+        n_before = g.ax.n
         g.step()
         o.step()
         a = g.ax.to_numpy()
@@ -105,7 +112,10 @@ def test_stepping_with_the_sort_matches_the_oracle():
         np.testing.assert_array_equal(a["id"], o.ax.id)
         np.testing.assert_array_equal(a["cell"], o.ax.cell)
         assert np.all(np.diff(a["cell"][: g.ax.n_sorted]) >= 0)
+        assert np.unique(a["id"]).size == g.ax.n
+        dropped += n_before - g.ax.n_sorted
     assert g.ax.n > 100
+    assert dropped > 0            # some sorts dropped absorbed axions
 
 
 @pytest.mark.parametrize("per_cell", [12.0, 0.9])

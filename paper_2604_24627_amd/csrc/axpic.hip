@@ -541,14 +541,17 @@ __device__ __forceinline__ int64_t ev_blocks(int64_t total, int64_t nb) {
 }
 
 // The boundary records of nb blocks in block order: each first record of a run of equal
-// keys sums the run in order and adds it to fb (key -1: none).  Nothing after an overflow.
-// ev: the blocks of an events grid, of which only the first ev_blocks(ctrl[1]) wrote.
-__global__ void __launch_bounds__(kThreads)
-k_fb_bounds(int64_t nb, const int32_t* __restrict__ bkey, const double* __restrict__ bval,
-            const int64_t* __restrict__ ctrl, double* __restrict__ fb, int ev) {
+// keys sums the run in order and adds it to fb (key -1: none); block b of this part takes
+// records b kThreads ...  Nothing after an overflow.  ev: the blocks of an events grid, of
+// which only the first ev_blocks(ctrl[1]) wrote.
+__device__ __forceinline__ void fb_bounds_part(int64_t b, int64_t nb,
+                                               const int32_t* __restrict__ bkey,
+                                               const double* __restrict__ bval,
+                                               const int64_t* __restrict__ ctrl,
+                                               double* __restrict__ fb, int ev) {
     if (ctrl[0]) return;
     if (ev) nb = ev_blocks(ctrl[1], nb);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = b * kThreads + threadIdx.x;
     if (i >= 2 * nb) return;
     const int32_t k = bkey[i];
     if (k < 0 || (i > 0 && bkey[i - 1] == k)) return;
@@ -662,14 +665,14 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
 // block order): histogram column j < nh into hist[j], the others into stats[j - nh].  One
 // block per column: each thread sums its records in order, then the wavefront butterfly
 // and the wavefronts in order.
-__global__ void __launch_bounds__(kThreads)
-k_acc_reduce(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int64_t cstride,
-             int nh, const int64_t* __restrict__ ctrl, double* __restrict__ hist,
-             double* __restrict__ stats, int ev) {
+__device__ __forceinline__ void acc_column(int j, const double* __restrict__ rec, int64_t nrec,
+                                           int64_t rstride, int64_t cstride, int nh,
+                                           const int64_t* __restrict__ ctrl,
+                                           double* __restrict__ hist, double* __restrict__ stats,
+                                           int ev) {
     __shared__ double lds[kThreads / 64];
     if (ctrl && ctrl[0]) return;
     if (ev) nrec = ev_blocks(ctrl[1], nrec);      // an events grid: its writing blocks
-    const int j = blockIdx.x;
     double s = 0.0;
     // eight loads in flight, added in the same order as one at a time
     int64_t r = threadIdx.x;
@@ -690,6 +693,20 @@ k_acc_reduce(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int6
     if (s == 0.0) return;
     if (j < nh) { if (hist) hist[j] += s; }
     else if (stats) stats[j - nh] += s;
+}
+
+// The end of an accumulating call in one launch: blocks 0 .. ncol-1 sum the record
+// columns (acc_column), the blocks after add the boundary records of nbb blocks to fb
+// (fb_bounds_part); either part may be empty.
+__global__ void __launch_bounds__(kThreads)
+k_finish(const double* __restrict__ rec, int64_t nrec, int64_t rstride, int64_t cstride, int nh,
+         int ncol, double* __restrict__ hist, double* __restrict__ stats, int64_t nbb,
+         const int32_t* __restrict__ bkey, const double* __restrict__ bval,
+         double* __restrict__ fb, const int64_t* __restrict__ ctrl, int ev) {
+    if ((int)blockIdx.x < ncol)
+        acc_column((int)blockIdx.x, rec, nrec, rstride, cstride, nh, ctrl, hist, stats, ev);
+    else
+        fb_bounds_part((int64_t)blockIdx.x - ncol, nbb, bkey, bval, ctrl, fb, ev);
 }
 
 // ------------------------------------------------------------------ cell state
@@ -2675,23 +2692,18 @@ inline float product_ratio(double wprod, double w_ref) {
     return r < 3.0e38 ? (float)r : INFINITY;
 }
 
-// The per-block records of the last accumulating kernel (nrec records of ncol columns,
-// the first nh of them histogram bins for hist; column-major, column j at j nrec) summed
-// into hist and stats.  ev: the records of an events grid of nrec blocks, of which only
-// those that got events wrote.
-void acc_reduce(const Workspace& W, int64_t nrec, int ncol, int nh, double* hist, double* stats,
-                hipStream_t s, bool ev) {
-    if (!hist && !stats) return;
-    LAUNCH("k_acc_reduce", k_acc_reduce, dim3((unsigned)ncol), dim3(kThreads), 0, s, W.rec, nrec,
-           (int64_t)1, nrec, nh, W.ctrl, hist, stats, ev ? 1 : 0);
-}
-
-// The per-cell sums the blocks of the last kernel share with their neighbours (ev: as
-// for acc_reduce).
-void fb_bounds(const Workspace& W, int64_t nb, double* fb, hipStream_t s, bool ev) {
-    if (!fb) return;
-    LAUNCH("k_fb_bounds", k_fb_bounds, dim3((unsigned)((2 * nb + kThreads - 1) / kThreads)),
-           dim3(kThreads), 0, s, nb, W.bkey, W.bval, W.ctrl, fb, ev ? 1 : 0);
+// The end of the last accumulating kernel: its per-block records (nrec records of ncol
+// columns, the first nh of them histogram bins for hist; column-major, column j at
+// j nrec) summed into hist and stats, and, with fb, the boundary records of its nb
+// blocks added to fb.  ev: an events grid of nrec (= nb) blocks, of which only those
+// that got events wrote.
+void finish(const Workspace& W, int64_t nrec, int ncol, int nh, double* hist, double* stats,
+            int64_t nb, double* fb, hipStream_t s, bool ev) {
+    const int cols = (hist || stats) ? ncol : 0;
+    const int64_t fbb = fb ? (2 * nb + kThreads - 1) / kThreads : 0;
+    if (cols + fbb == 0) return;
+    LAUNCH("k_finish", k_finish, dim3((unsigned)(cols + fbb)), dim3(kThreads), 0, s, W.rec, nrec,
+           (int64_t)1, nrec, nh, cols, hist, stats, nb, W.bkey, W.bval, fb, W.ctrl, ev ? 1 : 0);
 }
 
 struct SpT {   // typed view of a species
@@ -2732,7 +2744,8 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
            TCP<T>(ph->p[2]), ph->cell, TCP<T>(lam_in), W.ctrl, ax->n, TP<T>(ax->x[0]),
            TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]), TP<T>(ax->p[2]),
            TP<T>(ax->w), ax->id, ax->cell, W.rec, kEmitMap);
-    acc_reduce(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, s, true);
+    finish(W, kEventBlocks, nbh + AXPIC_ST_COUNT, nbh, hist, stats, kEventBlocks, nullptr, s,
+           true);
     return launched();
 }
 
@@ -2758,9 +2771,8 @@ axpic_status emit_thermal(const KParams& kp, const axpic_cells* cells, axpic_spe
            W.ctrl, ax->n, TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]),
            TP<T>(ax->p[1]), TP<T>(ax->p[2]), TP<T>(ax->w), ax->id,
                        ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
-    fb_bounds(W, kEventBlocks, fb, s, true);
-    acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
-               stats, s, true);
+    finish(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr, stats,
+           kEventBlocks, fb, s, true);
     return launched();
 }
 
@@ -2785,9 +2797,8 @@ axpic_status emit_thermal_cells(const KParams& kp, const axpic_cells* cells, axp
            TCP<T>(el->x[0]), TCP<T>(el->x[1]), TCP<T>(el->x[2]), cellw, W.ctrl, ax->n,
            TP<T>(ax->x[0]), TP<T>(ax->x[1]), TP<T>(ax->x[2]), TP<T>(ax->p[0]), TP<T>(ax->p[1]),
            TP<T>(ax->p[2]), TP<T>(ax->w), ax->id, ax->cell, fb, W.rec, W.bkey, W.bval, kEmitMap);
-    fb_bounds(W, kEventBlocks, fb, s, true);
-    acc_reduce(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr,
-               stats, s, true);
+    finish(W, kEventBlocks, 2 * nbh + AXPIC_ST_COUNT, 2 * nbh, hist ? hist + nbh : nullptr, stats,
+           kEventBlocks, fb, s, true);
     return launched();
 }
 
@@ -2825,8 +2836,7 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
                        W.rec, W.bkey, W.bval, det ? 1 : 0, (const int64_t*)chain, kAbsMap);
-    if (det) fb_bounds(W, nb, fb, s, false);
-    acc_reduce(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, s, false);
+    finish(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, nb, det ? fb : nullptr, s, false);
     return launched();
 }
 

@@ -584,6 +584,16 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
        uint64_t next_id, int64_t* __restrict__ chain, int chain_slot) {
     __shared__ uint64_t wsum[kScanThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // the chain's words, read before the scan so that their latency overlaps it: output
+    // offset and first id (the chain's when chained, else the host's; a call without an
+    // output species, chain_slot < 0, only honours the skip word)
+    int64_t base = n_out, id0 = (int64_t)next_id;
+    bool skip = false;
+    if (t == 0 && chain) {
+        if (chain_slot >= 0) base = chain[chain_slot];
+        id0 = chain[AXPIC_CHAIN_NEXT_ID];
+        skip = chain[AXPIC_CHAIN_SKIP] != 0;
+    }
     uint64_t carry = 0;
     for (int64_t t0 = 0; t0 < nb; t0 += kScanTile) {
         const int64_t b0 = t0 + (int64_t)t * kScanPer;
@@ -634,11 +644,6 @@ k_scan(const uint32_t* __restrict__ bsum, uint64_t* __restrict__ boff, int64_t n
         __syncthreads();
     }
     if (t == 0) {
-        // output offset and first id: the chain's when chained, else the host's (a call
-        // without an output species, chain_slot < 0, only honours the skip word)
-        const int64_t base = (chain && chain_slot >= 0) ? chain[chain_slot] : n_out;
-        const int64_t id0 = chain ? chain[AXPIC_CHAIN_NEXT_ID] : (int64_t)next_id;
-        const bool skip = chain && chain[AXPIC_CHAIN_SKIP] != 0;
         const bool full = base + (int64_t)carry > capacity;
         const bool over = skip || full;
         ctrl[0] = over ? 1 : 0;

@@ -14,7 +14,9 @@ of the step, and the feedback is applied last:
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from typing import Dict, Optional
 
 import numpy as np
@@ -282,6 +284,89 @@ class AxpicSim:
         buffers and workspaces made or enlarged (a step without any allocates nothing)."""
         sp = [self.el, self.ion, self.ph, self.ax] + list(self._spare.values())
         return self._allocs + sum(s.grows for s in sp)
+
+    # -------------------------------------------------------------- checkpoint
+    _CKPT_SPECIES = ("el", "ion", "ph", "ax")
+
+    def save(self, path: str):
+        """Write what the following steps depend on to the directory `path`: the four
+        particle buffers (their first n particles, the offsets of a cell-ordered prefix,
+        the implicit-id range), the cell temperatures, the accumulated statistics and
+        histograms, the step index and the next id.  There is no random state to keep:
+        every draw is keyed by (seed, particle id, step).  The cell state and the
+        prefactors are derived from the temperatures on load; workspaces, spare buffers
+        and the device chain are scratch.  A surrogate is not saved: the caller hands
+        the same one to the sim it loads into."""
+        from safetensors.torch import save_file
+        os.makedirs(path, exist_ok=True)
+        t = {"T": self.T, "stats": self.stats, "hist": self.hist}
+        meta = {"step_index": self.step_index, "next_id": self.next_id,
+                "last_new": list(self._last_new), "ncell": self.ncell, "species": {}}
+        for name in self._CKPT_SPECIES:
+            sp = getattr(self, name)
+            n = sp.n
+            for d in range(3):
+                if sp.x[d] is not None:
+                    t[f"{name}.x{d}"] = sp.x[d][:n]
+                if sp.p[d] is not None:
+                    t[f"{name}.p{d}"] = sp.p[d][:n]
+            t[f"{name}.w"], t[f"{name}.id"], t[f"{name}.cell"] = sp.w[:n], sp.id[:n], sp.cell[:n]
+            if sp.off is not None:
+                t[f"{name}.off"] = sp.off
+            meta["species"][name] = {"n": n, "n_sorted": sp.n_sorted, "id0": sp.id0,
+                                     "n_implicit": sp.n_implicit, "w_ref": sp.w_ref,
+                                     "dtype": sp.dtype, "has_off": sp.off is not None}
+        save_file({k: v.detach().contiguous().cpu() for k, v in t.items()},
+                  os.path.join(path, "state.safetensors"))
+        with open(os.path.join(path, "state.json"), "w") as f:
+            json.dump(meta, f)
+
+    def load(self, path: str):
+        """Continue from a checkpoint written by save() of a sim built from the same
+        plasma and parameters: the following steps then equal, bit for bit, those of the
+        sim that wrote it."""
+        from safetensors.torch import load_file
+        with open(os.path.join(path, "state.json")) as f:
+            meta = json.load(f)
+        if meta["ncell"] != self.ncell:
+            raise ValueError("checkpoint of a different grid")
+        t = load_file(os.path.join(path, "state.safetensors"), device=str(self.device))
+        for name in self._CKPT_SPECIES:
+            sp = getattr(self, name)
+            m = meta["species"][name]
+            if m["dtype"] != sp.dtype or m["w_ref"] != sp.w_ref:
+                raise ValueError(f"checkpoint {name}: dtype or reference weight differs")
+            n = int(m["n"])
+            sp.ensure(n)
+            sp.n = n
+            for d in range(3):
+                if sp.x[d] is not None:
+                    sp.x[d][:n].copy_(t[f"{name}.x{d}"])
+                if sp.p[d] is not None:
+                    sp.p[d][:n].copy_(t[f"{name}.p{d}"])
+            sp.w[:n].copy_(t[f"{name}.w"])
+            sp.id[:n].copy_(t[f"{name}.id"])
+            sp.cell[:n].copy_(t[f"{name}.cell"])
+            sp.id0, sp.n_implicit, sp.n_sorted = int(m["id0"]), int(m["n_implicit"]), int(m["n_sorted"])
+            if not m["has_off"]:
+                sp.off = None
+            elif name == "ax":
+                self.ax_off.copy_(t["ax.off"])
+                sp.off = self.ax_off
+            else:
+                sp.off = t[f"{name}.off"].clone()
+            sp._S = None
+        self.T.copy_(t["T"])
+        self.stats.copy_(t["stats"])
+        self.hist.copy_(t["hist"])
+        self.step_index, self.next_id = int(meta["step_index"]), int(meta["next_id"])
+        self._last_new = tuple(meta["last_new"])
+        self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity, 2 * self.ncell))
+        self.cell_state()
+        if self.cellw is not None:
+            B.check(self.lib.axpic_cell_weights(B.ref(self.el.struct()), B.ptr(self.el.off),
+                                                self.ncell, B.ptr(self.cellw), self.sh),
+                    "cell_weights")
 
     def cell_state(self):
         B.check(self.lib.axpic_cell_state(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),

@@ -78,7 +78,6 @@ typedef enum {
 
 /* status[1] flag bits */
 #define AXPIC_FLAG_CAPACITY 1
-#define AXPIC_FLAG_DOMAIN 2
 #define AXPIC_FLAG_SKIPPED 4      /* a chained call after an overflow: nothing done */
 
 /* chain words (see Conventions) */
@@ -130,7 +129,9 @@ typedef struct {
  * densities (slot 0 electrons, slot 1+s ion species s).  state: [ncell]
  * records of AXPIC_STATE_N doubles: T, n_e, n_e_dep, nZ, nZ2, rho, X_H,
  * kappa^2 [keV^2], G_P0, G_C, G_B [s^-1], Q_C, Q_B [erg cm^-3 s^-1],
- * <E>_C, <E>_B [keV], 0.  pref32 / pref64: [ncell] records of AXPIC_PREF_N
+ * <E>_C, <E>_B [keV], domain flag (1 when the cell's temperature or a density
+ * is negative or not finite: its prefactors are then all 0, so that no event
+ * happens there; else 0).  pref32 / pref64: [ncell] records of AXPIC_PREF_N
  * prefactors in FP32 / FP64 (filled by axpic_cell_state). */
 typedef struct {
     int64_t ncell;

@@ -724,9 +724,12 @@ k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restr
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const double Zs[4] = {Z0, Z1, Z2, Z3}, As[4] = {A0, A1, A2, A3};
+    // the model's domain: a finite, non-negative temperature and densities
+    bool dom = isfinite(Tk[c]) && Tk[c] >= 0.0 && isfinite(dens[c]) && dens[c] >= 0.0;
     double nZ = 0.0, nZ2 = 0.0, rho = 0.0, rhoH = 0.0;
     for (int s = 0; s < nion; ++s) {
         const double ni = dens[(int64_t)(1 + s) * ncell + c];
+        dom = dom && isfinite(ni) && ni >= 0.0;
         nZ += Zs[s] * ni;
         nZ2 += Zs[s] * Zs[s] * ni;
         const double m = ni * As[s] * kMu;
@@ -741,7 +744,7 @@ k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restr
     double* st = state + c * AXPIC_STATE_N;
     st[0] = T; st[1] = ne; st[2] = ne_dep; st[3] = nZ; st[4] = nZ2; st[5] = rho; st[6] = XH;
     st[7] = kappa2; st[8] = G_P0; st[9] = G_C; st[10] = G_B; st[11] = Q_C; st[12] = Q_B;
-    st[13] = meanC; st[14] = meanB; st[15] = 0.0;
+    st[13] = meanC; st[14] = meanB; st[15] = dom ? 0.0 : 1.0;
     const bool onP = prm.channels & AXPIC_PRIMAKOFF, onC = prm.channels & AXPIC_COMPTON,
                onB = prm.channels & AXPIC_BREMS;
     double pr[AXPIC_PREF_N];
@@ -766,6 +769,8 @@ k_cell_state(int64_t ncell, const double* __restrict__ Tk, const double* __restr
     const double k = prm.brems_k, th = prm.brems_theta;
     pr[7] = (prm.inverse && onB && T > 0.0)
                 ? ne_dep * G_B * twopi2hc3 * dt_phys / (exp(lgamma(k)) * pow(th, k) * T * T * T) : 0.0;
+    if (!dom)                                   // outside the domain: nothing happens there
+        for (int i = 0; i < AXPIC_PREF_N; ++i) pr[i] = 0.0;
     for (int i = 0; i < AXPIC_PREF_N; ++i) {
         p64[c * AXPIC_PREF_N + i] = pr[i];
         p32[c * AXPIC_PREF_N + i] = (float)pr[i];

@@ -368,6 +368,11 @@ class AxpicSim:
                                                 self.ncell, B.ptr(self.cellw), self.sh),
                     "cell_weights")
 
+    def domain_cells(self) -> int:
+        """Cells whose temperature or a density lies outside the model's domain (negative
+        or not finite) at the last cell-state pass; nothing is emitted or absorbed there."""
+        return int((self.state.view(-1, B.STATE_N)[:, B.STATE_N - 1] != 0.0).sum())
+
     def cell_state(self):
         B.check(self.lib.axpic_cell_state(B.ref(self.grid), B.ref(self.cells), B.ref(self.params),
                                           self.el.w_ref, self.ph.w_ref, self.sh), "cell_state")

@@ -666,3 +666,28 @@ def test_primakoff_cells_from_offsets_equal_cell_index(ppc, poisson):
             for key in ("w", "id", "cell"):
                 np.testing.assert_array_equal(x[key], y[key])
             np.testing.assert_array_equal(x["p"], y["p"])
+
+
+def test_cells_outside_the_domain_are_flagged_and_inert():
+    """A cell whose temperature is NaN or negative, or whose electron density is negative,
+    is flagged in its state record and gets zero prefactors (no event can happen there);
+    every other cell keeps its prefactors bit for bit."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13)
+    g, _, _ = pair(wl)
+    before = g.pref64.clone().view(-1, B.PREF_N)
+    assert g.domain_cells() == 0
+    bad = [3, 5, 7]
+    g.T[3] = float("nan")
+    g.T[5] = -1.0
+    g.dens[7] = -2.0
+    g.cell_state()
+    torch.cuda.synchronize()
+    after = g.pref64.view(-1, B.PREF_N)
+    assert g.domain_cells() == 3
+    assert torch.all(after[bad] == 0.0)
+    assert torch.all(g.pref32.view(-1, B.PREF_N)[bad] == 0.0)
+    keep = torch.ones(g.ncell, dtype=torch.bool, device=after.device)
+    keep[bad] = False
+    assert torch.equal(after[keep], before[keep])
+    flags = g.state.view(-1, B.STATE_N)[:, B.STATE_N - 1]
+    assert torch.equal(torch.nonzero(flags).flatten().cpu(), torch.tensor(bad))

@@ -107,7 +107,7 @@ def step_counts(sim, n_ax0, active_frac):
     fb_el = active_frac * el
     T_all = sim.pdict["T_mode"] == 2
     k = {
-        "k_prim_count": ("photon", ph, 16.0),             # p (12 B) + w (4 B) read
+        "k_prim_count": ("photon", ph, 8.0),              # |p|^2 (4 B) + w (4 B) read
         "k_therm_count": ("electron", el, 4.0),           # w read (the rate is per cell)
         "k_abs_count": ("axion", n_ax0, 32.0),            # p, w, id, cell read
         "k_bin": ("axion", n_ax0, 2.0 * xb + 12 + 4),     # x, p read; x, cell written
@@ -122,8 +122,9 @@ def step_counts(sim, n_ax0, active_frac):
         # written whole (x, p, w, id, cell) to move it
         k["k_sort_count"] = ("axion", n_ax0, 8.0)
         k["k_sort_gather"] = ("axion", n_ax0, 2.0 * (xb + 12 + 4 + 8 + 4))
-    # products: each written whole (x, p, w, id, cell); thermal ones read the parent's x
-    prod = (new_ax + new_ph) * (xb + 12 + 4 + 8 + 4) + new_ax * xb
+    # products: each written whole (x, p, w, id, cell, and a photon's |p|^2); thermal
+    # ones read the parent's x
+    prod = (new_ax + new_ph) * (xb + 12 + 4 + 8 + 4) + new_ph * 4 + new_ax * xb
     total = sum(n * b for _, n, b in k.values()) + prod
     return k, total
 

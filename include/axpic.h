@@ -123,6 +123,12 @@ typedef struct {
     int64_t n_sorted;   /* [host] order, cell c holding off[c] <= i < off[c+1] (cell[] stays
                            valid; the Primakoff count reads it only where off is NULL or the
                            cells of a 1024-particle tile are more than 256) */
+    void* p2;           /* device, `dtype` [capacity] or NULL: |p|^2 of each particle as
+                           axpic_fill_p2 evaluates it from p (a cache for buffers whose
+                           momenta do not change).  Given for photons, the massless
+                           conversion count reads it instead of p; axpic_absorb writes it
+                           for the photons it appends and axpic_compact carries it, when
+                           their output has one.  Keeping it equal to p is the caller's. */
 } axpic_species;
 
 /* Per-cell tables.  dens: [1+AXPIC_MAX_IONS][ncell] FP64 deposited physical
@@ -209,6 +215,11 @@ int32_t axpic_version(void);
 /* Bytes of workspace the calls below need for parents / axions of up to
  * n_max particles. */
 size_t axpic_workspace_bytes(int64_t n_max);
+
+/* axpic_fill_p2 -- sp->p2[i] = |p_i|^2 for from <= i < sp->n, in `dtype`, in the fixed
+ * multiply-add order every kernel uses for |p|^2 (so that a rate from the cache equals
+ * one from p bit for bit).  AXPIC_E_INVAL without p2 or p, or for from outside [0, n]. */
+axpic_status axpic_fill_p2(axpic_species* sp, int64_t from, void* stream);
 
 /* axpic_bin_cells -- Sec. II.B, II.E.  For a species of rest mass m_keV
  * (axions; 0 massless): if `push` != 0 advance x by v dt/dx with

@@ -46,7 +46,7 @@ class SpeciesC(C.Structure):
                 ("capacity", C.c_int64), ("dtype", C.c_int32), ("kind", C.c_int32),
                 ("w_ref", C.c_double), ("Z", C.c_double), ("A", C.c_double),
                 ("id0", C.c_uint64), ("n_implicit", C.c_int64), ("off", C.c_void_p),
-                ("n_sorted", C.c_int64)]
+                ("n_sorted", C.c_int64), ("p2", C.c_void_p)]
 
 
 class CellsC(C.Structure):
@@ -75,6 +75,7 @@ class ParamsC(C.Structure):
 
 EXPORTS = ["axpic_status_string", "axpic_version", "axpic_workspace_bytes", "axpic_bin_cells",
            "axpic_deposit", "axpic_cell_state", "axpic_rates", "axpic_sample_emit",
+           "axpic_fill_p2",
            "axpic_absorb", "axpic_feedback", "axpic_compact", "axpic_diag",
            "axpic_sampler_table", "axpic_timing_enable", "axpic_timing_only",
            "axpic_timing_read",
@@ -130,6 +131,7 @@ def load(path: Optional[str] = None):
         ("axpic_bin_cells", [_P, _P, C.c_int32, C.c_double, _P]),
         ("axpic_deposit", [_P, _P, _P, _P, C.c_int32, _P]),
         ("axpic_cell_state", [_P, _P, _P, C.c_double, C.c_double, _P]),
+        ("axpic_fill_p2", [_P, C.c_int64, _P]),
         ("axpic_rates", [_P, _P, _P, _P, C.c_int32, _P, _P]),
         ("axpic_sample_emit", [_P, _P, _P, _P, C.c_int32, _P, C.c_int64, C.c_uint64, _P, _P, _P,
                                _P, _P, _P, C.c_size_t, _P, _P]),

@@ -2,14 +2,18 @@
 // behind the C ABI in include/axpic.h.
 //
 // Layout of the work: every per-particle operator that creates products runs
-// as three launches over the parent stream
-//   count : rates + Philox + Poisson per parent, 16-bit event code per parent,
-//           per-block totals;
+// over the parent stream as
+//   count : rates + Philox + Poisson per parent and per-block totals; the
+//           emission counts compact each tile's converting parents into a list,
+//           the absorption count keeps a 16-bit decision code per axion;
 //   scan  : one workgroup turns the block totals into exclusive offsets and
 //           checks the capacity;
-//   apply : blocks with activity recompute their parents' rates (bitwise the
-//           same values), scan the codes in parent order and write products,
-//           depletion, histogram and feedback.
+//   expand + events (emission): one record per product from the lists, then one
+//           product per lane (recomputing its parent's rate bitwise the same);
+//   apply (absorption): blocks with activity recompute their axions' rates, scan
+//           the codes in axion order and write products;
+//   finish: the per-block histogram and statistics records and the boundary
+//           sums of the exchange, in block order.
 // Products therefore land in the canonical order (parent, channel, event) and
 // their ids come from the offset, never from an atomic slot.
 #include <hip/hip_runtime.h>
@@ -789,6 +793,15 @@ k_deposit(int64_t ncell, const T* __restrict__ w, const int64_t* __restrict__ of
     dens_slot[c] = s * scale;
 }
 
+// |p|^2 of particles from .. n-1 (the cache axpic_species.p2).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fill_p2(int64_t from, int64_t n, const T* __restrict__ px, const T* __restrict__ py,
+          const T* __restrict__ pz, T* __restrict__ p2) {
+    const int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p2[i] = p2_of<T>(px[i], py[i], pz[i]);
+}
+
 // ------------------------------------------------------------------ bin_cells
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
@@ -889,17 +902,22 @@ template <typename T, bool M, bool VEC, bool STAGE>
 __device__ __forceinline__ uint32_t prim_count_run(
     int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref, const T* __restrict__ pref,
     const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
-    const T* __restrict__ pz, const IdView& id, const int32_t* __restrict__ cell,
-    const T* __restrict__ lam_in, float wt_heavy, const CellStage& stg, int32_t t0,
-    uint32_t* cd) {
+    const T* __restrict__ pz, const T* __restrict__ p2in, const IdView& id,
+    const int32_t* __restrict__ cell, const T* __restrict__ lam_in, float wt_heavy,
+    const CellStage& stg, int32_t t0, uint32_t* cd) {
     T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
     int32_t cv[kPer];
     uint64_t idv[kPer];
+    // the cached |p|^2 (massless: 4 bytes instead of the 12 of p)
+    const bool cached = !M && p2in != nullptr;
     ld_run<VEC>(w, i0, n, wv);
     id.template run<VEC>(i0, n, idv);
     if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
-    else { ld_run<VEC>(px, i0, n, xv); ld_run<VEC>(py, i0, n, yv); ld_run<VEC>(pz, i0, n, zv);
-           if (!STAGE) ld_run<VEC>(cell, i0, n, cv); }
+    else {
+        if (cached) ld_run<VEC>(p2in, i0, n, xv);
+        else { ld_run<VEC>(px, i0, n, xv); ld_run<VEC>(py, i0, n, yv); ld_run<VEC>(pz, i0, n, zv); }
+        if (!STAGE) ld_run<VEC>(cell, i0, n, cv);
+    }
     T pcv[kPer][4];
     if constexpr (STAGE) {
         int32_t kc[kPer];
@@ -926,7 +944,7 @@ __device__ __forceinline__ uint32_t prim_count_run(
                        : (M ? lambda_primakoff_m<T>(kp, pcv[j], wt,
                                                     p2_of<double>(xv[j], yv[j], zv[j]))
                             : lambda_primakoff<T>(pcv[j], wt,
-                                                  p2_of<T>(xv[j], yv[j], zv[j])));
+                                                  cached ? xv[j] : p2_of<T>(xv[j], yv[j], zv[j])));
         int K = 0;
         if (l > (T)0) {
             const uint4 r = draw(kp, idv[j], step, 0, 0);
@@ -970,8 +988,8 @@ template <typename T, bool M>
 __global__ void __launch_bounds__(kThreads)
 k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
-             const T* __restrict__ py, const T* __restrict__ pz, IdView id,
-             const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
+             const T* __restrict__ py, const T* __restrict__ pz, const T* __restrict__ p2in,
+             IdView id, const int32_t* __restrict__ cell, const T* __restrict__ lam_in,
              uint32_t* __restrict__ list, uint32_t* __restrict__ bsum, uint32_t* __restrict__ bact,
              int aligned, float wt_heavy,
              const int64_t* __restrict__ off, int64_t n_sorted) {
@@ -1003,14 +1021,14 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
     }
     uint32_t cd[kPer], tot;
     if (stg.m > 0)
-        tot = prim_count_run<T, M, true, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id, cell,
-                                               lam_in, wt_heavy, stg, t0, cd);
+        tot = prim_count_run<T, M, true, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
+                                               id, cell, lam_in, wt_heavy, stg, t0, cd);
     else if (vec)
-        tot = prim_count_run<T, M, true, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
-                                                cell, lam_in, wt_heavy, stg, t0, cd);
+        tot = prim_count_run<T, M, true, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
+                                                id, cell, lam_in, wt_heavy, stg, t0, cd);
     else
-        tot = prim_count_run<T, M, false, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, id,
-                                                 cell, lam_in, wt_heavy, stg, t0, cd);
+        tot = prim_count_run<T, M, false, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
+                                                 id, cell, lam_in, wt_heavy, stg, t0, cd);
     tile_list(blockIdx.x, t0, tot, cd, list, bsum, bact, lds);
 }
 
@@ -1466,7 +1484,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
             const uint32_t* __restrict__ bact, const uint64_t* __restrict__ boff,
             const int64_t* __restrict__ ctrl, int64_t out_n, int64_t out_cap, T* __restrict__ gx0,
             T* __restrict__ gx1, T* __restrict__ gx2, T* __restrict__ gpx, T* __restrict__ gpy,
-            T* __restrict__ gpz, T* __restrict__ gw, uint64_t* __restrict__ gid,
+            T* __restrict__ gpz, T* __restrict__ gp2, T* __restrict__ gw, uint64_t* __restrict__ gid,
             int32_t* __restrict__ gcell, double w_ref_g, double* __restrict__ fb,
             double* __restrict__ rec, int32_t* __restrict__ bkey, double* __restrict__ bval,
             int det, const int64_t* __restrict__ chain, StatMap smap) {
@@ -1564,6 +1582,7 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
                         if (gx1) gx1[slot] = x1 ? x1[i] : (T)0;
                         if (gx2) gx2[slot] = x2 ? x2[i] : (T)0;
                         gpx[slot] = gxv; gpy[slot] = gyv; gpz[slot] = gzv;
+                        if (gp2) gp2[slot] = p2_of<T>(gxv, gyv, gzv);
                         gw[slot] = wrel;
                         gid[slot] = (next_id + rank) | (1ull << 63);
                         gcell[slot] = c;
@@ -2007,9 +2026,10 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
                 const T* __restrict__ x0, const T* __restrict__ x1, const T* __restrict__ x2,
                 const T* __restrict__ px, const T* __restrict__ py, const T* __restrict__ pz,
                 const T* __restrict__ w, IdView id,
-                const int32_t* __restrict__ cell, T* __restrict__ ox0, T* __restrict__ ox1,
-                T* __restrict__ ox2, T* __restrict__ opx, T* __restrict__ opy, T* __restrict__ opz,
-                T* __restrict__ ow, uint64_t* __restrict__ oid, int32_t* __restrict__ ocell) {
+                const int32_t* __restrict__ cell, const T* __restrict__ p2, T* __restrict__ ox0,
+                T* __restrict__ ox1, T* __restrict__ ox2, T* __restrict__ opx, T* __restrict__ opy,
+                T* __restrict__ opz, T* __restrict__ ow, uint64_t* __restrict__ oid,
+                int32_t* __restrict__ ocell, T* __restrict__ op2) {
     __shared__ uint32_t lds[kThreads / 64];
     if (ctrl[0]) return;
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -2027,6 +2047,7 @@ k_compact_apply(int64_t n, const uint16_t* __restrict__ code, const uint64_t* __
                 if (ndim > 2) ox2[s] = x2[i];
                 opx[s] = px[i]; opy[s] = py[i]; opz[s] = pz[i];
                 ow[s] = w[i]; oid[s] = id(i); ocell[s] = cell[i];
+                if (op2) op2[s] = p2 ? p2[i] : p2_of<T>(px[i], py[i], pz[i]);
             }
         }
         run += segtot;
@@ -2738,9 +2759,10 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
     const auto k_events = kp.massive ? k_prim_events<T, true> : k_prim_events<T, false>;
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),
-                       TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), idv(ph), ph->cell, TCP<T>(lam_in),
-                       W.list(), W.bsum, W.bact,
-                       runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->cell, ph->id, lam_in}),
+                       TCP<T>(ph->p[1]), TCP<T>(ph->p[2]), TCP<T>(ph->p2), idv(ph), ph->cell,
+                       TCP<T>(lam_in), W.list(), W.bsum, W.bact,
+                       runs_aligned({ph->w, ph->p[0], ph->p[1], ph->p[2], ph->p2, ph->cell, ph->id,
+                                     lam_in}),
                        heavy_threshold(kp.w_a * kp.wa_mul[0], ph->w_ref, kp.light_mode),
                        ph->off, ph->off ? ph->n_sorted : (int64_t)0);
     LAUNCH("k_scan", k_scan, dim3(1), dim3(kScanThreads), 0, s, W.bsum, W.boff, nb, ax->n,
@@ -2843,7 +2865,8 @@ axpic_status absorb_impl(const KParams& kp, const axpic_cells* cells, axpic_spec
                        W.boff, W.ctrl, out_n, out_cap, ph ? TP<T>(ph->x[0]) : nullptr,
                        ph ? TP<T>(ph->x[1]) : nullptr, ph ? TP<T>(ph->x[2]) : nullptr,
                        ph ? TP<T>(ph->p[0]) : nullptr, ph ? TP<T>(ph->p[1]) : nullptr,
-                       ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->w) : nullptr,
+                       ph ? TP<T>(ph->p[2]) : nullptr, ph ? TP<T>(ph->p2) : nullptr,
+                       ph ? TP<T>(ph->w) : nullptr,
                        ph ? ph->id : nullptr, ph ? ph->cell : nullptr, ph ? ph->w_ref : 1.0, fb,
                        W.rec, W.bkey, W.bval, det ? 1 : 0, (const int64_t*)chain, kAbsMap);
     finish(W, nb, AXPIC_ST_COUNT, 0, nullptr, stats, nb, det ? fb : nullptr, s, false);
@@ -3008,6 +3031,21 @@ axpic_status axpic_deposit(const axpic_grid* g, const axpic_species* sp, const i
     else
         LAUNCH("k_deposit", k_deposit<double>, grid1(cells->ncell), dim3(kThreads), 0, S(stream),
                            cells->ncell, (const double*)sp->w, off, scale, dst);
+    return launched();
+}
+
+axpic_status axpic_fill_p2(axpic_species* sp, int64_t from, void* stream) {
+    if (!species_ok(sp, true) || !sp->p2 || from < 0 || from > sp->n) return AXPIC_E_INVAL;
+    if (from == sp->n) return AXPIC_OK;
+    const int64_t m = sp->n - from;
+    if (sp->dtype == AXPIC_F32)
+        LAUNCH("k_fill_p2", k_fill_p2<float>, grid1(m), dim3(kThreads), 0, S(stream), from, sp->n,
+               (const float*)sp->p[0], (const float*)sp->p[1], (const float*)sp->p[2],
+               (float*)sp->p2);
+    else
+        LAUNCH("k_fill_p2", k_fill_p2<double>, grid1(m), dim3(kThreads), 0, S(stream), from,
+               sp->n, (const double*)sp->p[0], (const double*)sp->p[1], (const double*)sp->p[2],
+               (double*)sp->p2);
     return launched();
 }
 
@@ -3268,8 +3306,9 @@ axpic_status axpic_compact(const axpic_species* in, axpic_species* out, int64_t*
                        W.boff, W.ctrl, out->capacity, ndim, (const T*)in->x[0],                   \
                        (const T*)in->x[1], (const T*)in->x[2], (const T*)in->p[0],                \
                        (const T*)in->p[1], (const T*)in->p[2], (const T*)in->w, idv(in), in->cell, \
-                       (T*)out->x[0], (T*)out->x[1], (T*)out->x[2], (T*)out->p[0], (T*)out->p[1], \
-                       (T*)out->p[2], (T*)out->w, out->id, out->cell)
+                       (const T*)in->p2, (T*)out->x[0], (T*)out->x[1], (T*)out->x[2],             \
+                       (T*)out->p[0], (T*)out->p[1], (T*)out->p[2], (T*)out->w, out->id, out->cell, \
+                       (T*)out->p2)
     if (in->dtype == AXPIC_F32) { AXPIC_COMPACT(float); }
     else { AXPIC_COMPACT(double); }
 #undef AXPIC_COMPACT

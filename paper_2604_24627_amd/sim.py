@@ -33,11 +33,15 @@ class DeviceSpecies:
     """SoA macroparticle buffer on the GPU with host-side length/capacity."""
 
     def __init__(self, kind: int, dtype: int, ndim: int, capacity: int, w_ref: float,
-                 device, Z: float = 0.0, A: float = 0.0, with_p: bool = True):
+                 device, Z: float = 0.0, A: float = 0.0, with_p: bool = True,
+                 cache_p2: bool = True):
         self.kind, self.dtype, self.ndim = kind, dtype, ndim
         self.w_ref, self.Z, self.A = float(w_ref), float(Z), float(A)
         self.device = device
         self.with_p = with_p
+        # photons keep |p|^2 beside p: their conversion rate needs only that
+        self.with_p2 = with_p and kind == B.PHOTON and cache_p2
+        self.p2 = None
         self.n = 0
         self.capacity = 0
         self.x = [None, None, None]
@@ -64,6 +68,7 @@ class DeviceSpecies:
         for d in range(3):
             self.x[d] = grow(self.x[d], td) if d < self.ndim else None
             self.p[d] = grow(self.p[d], td) if self.with_p else None
+        self.p2 = grow(self.p2, td) if self.with_p2 else None
         self.w = grow(self.w, td)
         self.id = grow(self.id, torch.int64)
         self.cell = grow(self.cell, torch.int32)
@@ -132,6 +137,7 @@ class DeviceSpecies:
                 S.x[d] = B.ptr(self.x[d])
                 S.p[d] = B.ptr(self.p[d])
             S.w, S.id, S.cell = B.ptr(self.w), B.ptr(self.id), B.ptr(self.cell)
+            S.p2 = B.ptr(self.p2) if self.p2 is not None else None
             S.dtype, S.kind = self.dtype, self.kind
             S.w_ref, S.Z, S.A = self.w_ref, self.Z, self.A
             S.id0, S.n_implicit = self.id0, self.n_implicit
@@ -140,6 +146,11 @@ class DeviceSpecies:
             self._S, self._S_key = S, key
         S.n, S.capacity = self.n, self.capacity
         return S
+
+    def fill_p2(self, lib, stream, start: int = 0):
+        """|p|^2 of particles start .. n-1 from their momenta (the photons' cache)."""
+        if self.p2 is not None:
+            B.check(lib.axpic_fill_p2(B.ref(self.struct()), int(start), stream), "fill_p2")
 
     def to_numpy(self) -> Dict:
         n = self.n
@@ -204,6 +215,7 @@ class AxpicSim:
         self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity, 2 * self.ncell))
         self.stream = stream
         s = self.sh
+        self.ph.fill_p2(self.lib, s)
         B.check(self.lib.axpic_deposit(B.ref(self.grid), B.ref(self.el.struct()), B.ptr(self.el.off),
                                        B.ref(self.cells), 0, s), "deposit electrons")
         B.check(self.lib.axpic_deposit(B.ref(self.grid), B.ref(self.ion.struct()),
@@ -362,6 +374,7 @@ class AxpicSim:
         self.step_index, self.next_id = int(meta["step_index"]), int(meta["next_id"])
         self._last_new = tuple(meta["last_new"])
         self._ensure_ws(max(self.el.n, self.ph.n, self.ax.capacity, 2 * self.ncell))
+        self.ph.fill_p2(self.lib, self.sh)
         self.cell_state()
         if self.cellw is not None:
             B.check(self.lib.axpic_cell_weights(B.ref(self.el.struct()), B.ptr(self.el.off),
@@ -520,7 +533,8 @@ class AxpicSim:
         spare = self._spare.get(sp.kind)
         if spare is None or spare.capacity < sp.n or spare.w_ref != sp.w_ref:
             spare = DeviceSpecies(sp.kind, self.dtype, self.ndim, sp.capacity, sp.w_ref,
-                                  self.device, sp.Z, sp.A)
+                                  self.device, sp.Z, sp.A, with_p=sp.with_p,
+                                  cache_p2=sp.with_p2)
             self._allocs += 1
         out = spare
         out.n, out.off, out.n_sorted, out.id0, out.n_implicit = 0, None, 0, 0, 0

@@ -403,6 +403,35 @@ def test_compaction_is_stable_and_exact():
     np.testing.assert_array_equal(after["x"][:2], before["x"][:2, keep])
 
 
+def test_photon_p2_cache_changes_nothing():
+    """The photons' |p|^2 kept beside p (read by the conversion count instead of p)
+    gives the same steps, bit for bit, as p itself, through a->gamma appends and
+    photon compaction; and the cache then equals |p|^2 of every photon."""
+    wl = small_workload("f32", channels=7, inverse=1, g_ae=1e-13, boost=4e33, w_a=1e-36,
+                        lambda_cap=1.0)
+    pl = I.make_plasma(wl, 9)
+    g = AxpicSim(pl, wl.params, compact_every=2)
+    h = AxpicSim(pl, wl.params, compact_every=2)
+    h.ph.with_p2, h.ph.p2, h.ph._S = False, None, None
+    n0 = g.ph.n
+    for _ in range(5):
+        g.step()
+        h.step()
+    torch.cuda.synchronize()
+    assert h.ph.p2 is None and g.ph.p2 is not None
+    assert g.ph.n != n0 and g._spare.get(B.PHOTON) is not None
+    for key in ("w", "id", "cell", "p", "x"):
+        np.testing.assert_array_equal(g.ph.to_numpy()[key], h.ph.to_numpy()[key])
+        np.testing.assert_array_equal(g.ax.to_numpy()[key], h.ax.to_numpy()[key])
+    n = g.ph.n
+    kept = g.ph.p2[:n].clone()
+    g.ph.fill_p2(g.lib, g.sh)
+    torch.cuda.synchronize()
+    assert torch.equal(kept, g.ph.p2[:n])
+    p = [g.ph.p[d][:n].double() for d in range(3)]
+    np.testing.assert_allclose(np64(kept), np64(p[0] ** 2 + p[1] ** 2 + p[2] ** 2), rtol=1e-6)
+
+
 def test_config1_full_run_matches_oracle():
     """Config 1 (1D, 64 cells, fp64, Primakoff, 100 steps): GPU and oracle run
     independently with fused rates; every axion and the histogram agree."""

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "axpic.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(axpic_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(axpic_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -35,8 +35,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     # offsets that the C compiler would produce (natural alignment, x86-64)
     assert C.sizeof(B.Grid) == 40
-    assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2 + 8 * 2
+    assert C.sizeof(B.SpeciesC) == 8 * 9 + 8 * 2 + 4 * 2 + 8 * 3 + 8 * 2 + 8 * 2 + 8
     assert B.SpeciesC.off.offset == 136 and B.SpeciesC.n_sorted.offset == 144
+    assert B.SpeciesC.p2.offset == 152
     assert B.ParamsC.seed.offset % 8 == 0
     # sizes and offsets printed by a C compiler for include/axpic.h (x86-64)
     assert C.sizeof(B.ParamsC) == 224 and C.sizeof(B.CellsC) == 136

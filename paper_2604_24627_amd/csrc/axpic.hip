@@ -887,50 +887,61 @@ struct CellStage {
             const int mid = (lo + hi) >> 1;
             if (bnd[mid] <= t0) lo = mid + 1; else hi = mid;
         }
+        k[0] = lo;
+        // the next kPer - 1 boundaries hold every one within the run unless kPer or more
+        // fall inside it (empty cells); then the stepping loop
+        int32_t b[kPer - 1];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            while (lo < m - 1 && bnd[lo] <= t0 + q) ++lo;
-            k[q] = lo;
+        for (int q = 0; q < kPer - 1; ++q) b[q] = lo + q < m - 1 ? bnd[lo + q] : INT32_MAX;
+        if (lo + kPer - 1 < m - 1 && bnd[lo + kPer - 1] <= t0 + kPer - 1) {
+#pragma unroll
+            for (int q = 1; q < kPer; ++q) {
+                int c = k[q - 1];
+                while (c < m - 1 && bnd[c] <= t0 + q) ++c;
+                k[q] = c;
+            }
+        } else {
+#pragma unroll
+            for (int q = 1; q < kPer; ++q) {
+                int c = lo;
+#pragma unroll
+                for (int r = 0; r < kPer - 1; ++r) c += b[r] <= t0 + q;
+                k[q] = c;
+            }
         }
     }
 };
 
-// Counts of the thread's run of photons into cd; returns the run's product total.
-// STAGE: the workgroup's cells are staged in LDS and the photons' cell indices are not
-// read.
-template <typename T, bool M, bool VEC, bool STAGE>
+// What the conversion count reads besides w and id: p, the photons' |p|^2 cache
+// (massless only), or given means.
+enum PrimSrc { kSrcP = 0, kSrcP2 = 1, kSrcLam = 2 };
+
+// The photon data of a thread's run (x holds |p|^2 or the means when that is the source).
+template <typename T, int SRC>
+struct PrimRun {
+    T w[kPer], x[kPer], y[kPer], z[kPer];
+    uint64_t id[kPer];
+    template <bool VEC>
+    __device__ __forceinline__ void load(int64_t i0, int64_t n, const T* __restrict__ wp,
+                                         const T* __restrict__ px, const T* __restrict__ py,
+                                         const T* __restrict__ pz, const T* __restrict__ p2in,
+                                         const IdView& idv, const T* __restrict__ lam_in) {
+        ld_run<VEC>(wp, i0, n, w);
+        idv.template run<VEC>(i0, n, id);
+        if constexpr (SRC == kSrcLam) ld_run<VEC>(lam_in, i0, n, x);
+        else if constexpr (SRC == kSrcP2) ld_run<VEC>(p2in, i0, n, x);
+        else { ld_run<VEC>(px, i0, n, x); ld_run<VEC>(py, i0, n, y); ld_run<VEC>(pz, i0, n, z); }
+    }
+};
+
+// Counts of the thread's run of photons into cd from its data and its cells' prefactor
+// records pcv; returns the run's product total.
+template <typename T, bool M, int SRC, bool VEC>
 __device__ __forceinline__ uint32_t prim_count_run(
-    int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref, const T* __restrict__ pref,
-    const T* __restrict__ w, const T* __restrict__ px, const T* __restrict__ py,
-    const T* __restrict__ pz, const T* __restrict__ p2in, const IdView& id,
-    const int32_t* __restrict__ cell, const T* __restrict__ lam_in, float wt_heavy,
-    const CellStage& stg, int32_t t0, uint32_t* cd) {
-    T wv[kPer], xv[kPer], yv[kPer], zv[kPer], lv[kPer];
-    int32_t cv[kPer];
-    uint64_t idv[kPer];
-    // the cached |p|^2 (massless: 4 bytes instead of the 12 of p)
-    const bool cached = !M && p2in != nullptr;
-    ld_run<VEC>(w, i0, n, wv);
-    id.template run<VEC>(i0, n, idv);
-    if (lam_in) ld_run<VEC>(lam_in, i0, n, lv);
-    else {
-        if (cached) ld_run<VEC>(p2in, i0, n, xv);
-        else { ld_run<VEC>(px, i0, n, xv); ld_run<VEC>(py, i0, n, yv); ld_run<VEC>(pz, i0, n, zv); }
-        if (!STAGE) ld_run<VEC>(cell, i0, n, cv);
-    }
-    T pcv[kPer][4];
-    if constexpr (STAGE) {
-        int32_t kc[kPer];
-        stg.cells(t0, kc);
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const float4 v = stg.pref[kc[j]];
-            pcv[j][0] = v.x; pcv[j][1] = v.y; pcv[j][2] = v.z; pcv[j][3] = v.w;
-        }
-    } else if (!lam_in) {
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
-    }
+    int64_t i0, int64_t n, int64_t step, const KParams& kp, double w_ref,
+    const PrimRun<T, SRC>& d, const T (*pcv)[4], float wt_heavy, uint32_t* cd) {
+    const T* wv = d.w; const T* xv = d.x; const T* yv = d.y; const T* zv = d.z;
+    const uint64_t* idv = d.id;
     const double wprod = kp.w_a * kp.wa_mul[0];
     uint32_t tot = 0;
 #pragma unroll
@@ -939,12 +950,14 @@ __device__ __forceinline__ uint32_t prim_count_run(
         if (!VEC && i0 + j >= n) continue;
         const T wt = wv[j];
         T l = (T)0;
-        if (wt > (T)0)
-            l = lam_in ? lv[j]
-                       : (M ? lambda_primakoff_m<T>(kp, pcv[j], wt,
-                                                    p2_of<double>(xv[j], yv[j], zv[j]))
-                            : lambda_primakoff<T>(pcv[j], wt,
-                                                  cached ? xv[j] : p2_of<T>(xv[j], yv[j], zv[j])));
+        if (wt > (T)0) {
+            if constexpr (SRC == kSrcLam) l = xv[j];
+            else if constexpr (M)
+                l = lambda_primakoff_m<T>(kp, pcv[j], wt, p2_of<double>(xv[j], yv[j], zv[j]));
+            else
+                l = lambda_primakoff<T>(pcv[j], wt,
+                                        SRC == kSrcP2 ? xv[j] : p2_of<T>(xv[j], yv[j], zv[j]));
+        }
         int K = 0;
         if (l > (T)0) {
             const uint4 r = draw(kp, idv[j], step, 0, 0);
@@ -972,9 +985,13 @@ __device__ __forceinline__ void tile_list(int64_t b, int32_t t0, uint32_t tot, c
     uint32_t na = 0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) na += cd[q] != 0u;
-    uint32_t ba;
-    uint32_t slot = block_excl_scan(na, lds, &ba);
-    const uint32_t bt = block_sum_u32(tot, lds);
+    // one scan of both: active parents in bits 0-10 (at most 1024 a tile), products
+    // above (at most 2 x 255 per parent, 522240 < 2^21 a tile)
+    static_assert(kBlockParents <= 1024, "tile_list packs the active count in 11 bits");
+    uint32_t bp;
+    const uint32_t ex = block_excl_scan(na | (tot << 11), lds, &bp);
+    uint32_t slot = ex & 0x7FFu;
+    const uint32_t ba = bp & 0x7FFu, bt = bp >> 11;
     if (na) {
         uint32_t* L = list + b * kBlockParents;
 #pragma unroll
@@ -984,7 +1001,7 @@ __device__ __forceinline__ void tile_list(int64_t b, int32_t t0, uint32_t tot, c
     if (threadIdx.x == 0) { bsum[b] = bt; bact[b] = ba; }
 }
 
-template <typename T, bool M>
+template <typename T, bool M, int SRC>
 __global__ void __launch_bounds__(kThreads)
 k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __restrict__ p32,
              const double* __restrict__ p64, const T* __restrict__ w, const T* __restrict__ px,
@@ -1006,8 +1023,12 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
     // A workgroup inside the cell-ordered prefix spans the cells of its first and last
     // photon; when they are few, their prefactors and boundaries go to LDS and the
     // photons' cells come from the offsets (4 bytes less per photon)
+    // the run's own loads first: they are in flight while the cells are staged
+    PrimRun<T, SRC> d;
+    if (vec) d.template load<true>(i0, n, w, px, py, pz, p2in, id, lam_in);
+    else d.template load<false>(i0, n, w, px, py, pz, p2in, id, lam_in);
     CellStage stg{s_bnd, s_pref, 0};
-    if (sizeof(T) == 4 && !lam_in && off && vec && base + kBlockParents <= n_sorted) {
+    if (sizeof(T) == 4 && SRC != kSrcLam && off && vec && base + kBlockParents <= n_sorted) {
         const int32_t c_first = cell[base], c_last = cell[base + kBlockParents - 1];
         const int32_t m = c_last - c_first + 1;
         if (m >= 1 && m <= kStageCells) {
@@ -1019,16 +1040,25 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
             stg.m = m;
         }
     }
+    T pcv[kPer][4];
+    if (stg.m > 0) {
+        int32_t kc[kPer];
+        stg.cells(t0, kc);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const float4 v = stg.pref[kc[j]];
+            pcv[j][0] = v.x; pcv[j][1] = v.y; pcv[j][2] = v.z; pcv[j][3] = v.w;
+        }
+    } else if (SRC != kSrcLam) {
+        int32_t cv[kPer];
+        if (vec) ld_run<true>(cell, i0, n, cv);
+        else ld_run<false>(cell, i0, n, cv);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
+    }
     uint32_t cd[kPer], tot;
-    if (stg.m > 0)
-        tot = prim_count_run<T, M, true, true>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
-                                               id, cell, lam_in, wt_heavy, stg, t0, cd);
-    else if (vec)
-        tot = prim_count_run<T, M, true, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
-                                                id, cell, lam_in, wt_heavy, stg, t0, cd);
-    else
-        tot = prim_count_run<T, M, false, false>(i0, n, step, kp, w_ref, pref, w, px, py, pz, p2in,
-                                                 id, cell, lam_in, wt_heavy, stg, t0, cd);
+    if (vec) tot = prim_count_run<T, M, SRC, true>(i0, n, step, kp, w_ref, d, pcv, wt_heavy, cd);
+    else tot = prim_count_run<T, M, SRC, false>(i0, n, step, kp, w_ref, d, pcv, wt_heavy, cd);
     tile_list(blockIdx.x, t0, tot, cd, list, bsum, bact, lds);
 }
 
@@ -2755,7 +2785,10 @@ axpic_status emit_primakoff(const KParams& kp, const axpic_cells* cells, axpic_s
                             const Workspace& W, int64_t* chain, hipStream_t s) {
     const int64_t n = ph->n, nb = nblocks_for(std::max<int64_t>(n, 1));
     // massive axions take their own instantiations, so the massless kernels are unchanged
-    const auto k_count = kp.massive ? k_prim_count<T, true> : k_prim_count<T, false>;
+    const auto k_count =
+        lam_in ? (kp.massive ? k_prim_count<T, true, kSrcLam> : k_prim_count<T, false, kSrcLam>)
+        : kp.massive ? k_prim_count<T, true, kSrcP>
+        : ph->p2 ? k_prim_count<T, false, kSrcP2> : k_prim_count<T, false, kSrcP>;
     const auto k_events = kp.massive ? k_prim_events<T, true> : k_prim_events<T, false>;
     LAUNCH("k_prim_count", k_count, dim3((unsigned)nb), dim3(kThreads), 0, s, n, step, kp,
                        ph->w_ref, cells->pref32, cells->pref64, TCP<T>(ph->w), TCP<T>(ph->p[0]),

@@ -2384,7 +2384,7 @@ k_sort_scatter(int64_t n, int64_t ncell, const T* __restrict__ w, const int32_t*
             idx[off[cq[q]] + hval[slot[q]] + loc[q]] = (uint32_t)(base + q * kThreads + threadIdx.x);
 }
 
-// The arrays a sort moves: particle i of `in` to slot d of `out`.
+// The arrays a sort moves: particle i of `in` to slot d of `out` (SortVal).
 template <typename T>
 struct SortIO {
     int ndim;
@@ -2397,14 +2397,30 @@ struct SortIO {
     T* ow;
     uint64_t* oid;
     int32_t* ocell;
-    __device__ __forceinline__ void move(int64_t i, int64_t d, int32_t c) const {
-        ox[0][d] = x[0][i];
-        if (ndim > 1) ox[1][d] = x[1][i];
-        if (ndim > 2) ox[2][d] = x[2][i];
-        op[0][d] = p[0][i]; op[1][d] = p[1][i]; op[2][d] = p[2][i];
-        ow[d] = w[i];
-        oid[d] = id(i);
-        ocell[d] = c;
+};
+
+// One particle's arrays in registers (the gather loads a thread's particles first and
+// then stores them, so that their loads are in flight together).
+template <typename T>
+struct SortVal {
+    T x[3], p[3], w;
+    uint64_t id;
+    __device__ __forceinline__ void load(const SortIO<T>& io, int64_t i) {
+        x[0] = io.x[0][i];
+        x[1] = io.ndim > 1 ? io.x[1][i] : (T)0;
+        x[2] = io.ndim > 2 ? io.x[2][i] : (T)0;
+        p[0] = io.p[0][i]; p[1] = io.p[1][i]; p[2] = io.p[2][i];
+        w = io.w[i];
+        id = io.id(i);
+    }
+    __device__ __forceinline__ void store(const SortIO<T>& io, int64_t d, int32_t c) const {
+        io.ox[0][d] = x[0];
+        if (io.ndim > 1) io.ox[1][d] = x[1];
+        if (io.ndim > 2) io.ox[2][d] = x[2];
+        io.op[0][d] = p[0]; io.op[1][d] = p[1]; io.op[2][d] = p[2];
+        io.ow[d] = w;
+        io.oid[d] = id;
+        io.ocell[d] = c;
     }
 };
 
@@ -2442,20 +2458,34 @@ k_sort_gather(int64_t ncell, const int64_t* __restrict__ off, const uint32_t* __
     }
     for (int64_t m = wlo + threadIdx.x; m < whi; m += kThreads) win[m - wlo] = idx[m];
     __syncthreads();
-#pragma unroll 1
+    // the thread's kPer slots stage by stage (source, its cell, the cell's range, the
+    // particle), so each stage's loads are in flight together
+    const int64_t jt = j0 + threadIdx.x;
+    uint32_t sv[kPer];
+    int32_t cv[kPer];
+    int64_t lov[kPer], hiv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) sv[q] = jt + q * kThreads < j1 ? win[jt + q * kThreads - wlo] : 0u;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) cv[q] = jt + q * kThreads < j1 ? cell[sv[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (jt + q * kThreads < j1) { lov[q] = off[cv[q]]; hiv[q] = off[cv[q] + 1]; }
+    SortVal<T> v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (jt + q * kThreads < j1) v[q].load(io, (int64_t)sv[q]);
+#pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int64_t j = j0 + q * kThreads + threadIdx.x;
-        if (j >= j1) break;
-        const uint32_t s = win[j - wlo];
-        const int64_t i = (int64_t)s;
-        const int32_t c = cell[i];
-        const int64_t lo = off[c], hi = off[c + 1];
+        if (jt + q * kThreads >= j1) break;
+        const uint32_t s = sv[q];
+        const int64_t lo = lov[q], hi = hiv[q];
         const int a = (int)((lo > wlo ? lo : wlo) - wlo), b = (int)((hi < whi ? hi : whi) - wlo);
         uint32_t rank = 0;
         for (int m = a; m < b; ++m) rank += win[m] < s ? 1u : 0u;
         if (lo < wlo) rank += count_below(idx, lo, wlo, s);
         if (hi > whi) rank += count_below(idx, whi, hi, s);
-        io.move(i, lo + rank, c);
+        v[q].store(io, lo + rank, cv[q]);
     }
 }
 

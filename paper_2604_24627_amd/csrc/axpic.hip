@@ -1631,9 +1631,11 @@ k_abs_apply(int64_t n, int64_t step, uint64_t next_id, KParams kp, double w_ref_
 }
 
 // ------------------------------------------------------------------ feedback
-// L lanes per cell (16: four cells per wavefront; 8, eight, where the cells hold fewer
-// electrons): FP64 moments by strided loads and an L-lane shuffle reduction, then the
-// affine remap and the temperature update of each cell.
+// A wavefront takes 64 consecutive cells, finds those with work (an exchange, or every
+// cell when T evolves or the moments are requested) and works on them 64 / L at a time,
+// L lanes per cell (16, or 8 where the cells hold fewer electrons): FP64 moments by
+// strided loads and an L-lane shuffle reduction, then the affine remap and the
+// temperature update of each cell.  Cells without work cost one record read.
 constexpr int kCellLanes = 16;
 constexpr int kFbCache = 4;            // electrons per lane kept in registers
 
@@ -1652,103 +1654,125 @@ k_feedback(int64_t ncell, KParams kp, double w_ref, const int64_t* __restrict__ 
            const double* __restrict__ fb, double* __restrict__ Tk, double* __restrict__ moments,
            double* __restrict__ stats, double* __restrict__ ecell, int64_t* __restrict__ flag,
            int64_t token, unsigned int* __restrict__ done, const int64_t* __restrict__ chain) {
+    __shared__ uint8_t s_act[kThreads];            // per wavefront: its cells with work, in order
     // a chained step whose appending calls were skipped after an overflow is repeated
     // whole: the feedback of its partial exchange must not be applied
     if (chain && chain[AXPIC_CHAIN_SKIP]) return;
-    const int lane = threadIdx.x & 63, sub = lane & (L - 1);
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
-    const bool valid = c < ncell;
+    constexpr int G = 64 / L;                      // cells worked on at once
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane & (L - 1);
+    const int64_t cw = ((int64_t)blockIdx.x * (kThreads / 64) + wave) * 64;
     // the energy a cold or clamped cell leaves unapplied goes to its own slot (0 for every
     // other cell) and the call's token to *flag; k_fb_unapplied then sums the slots in
     // cell order.  The cell counts are exact in any order.
-    if (ecell && valid && sub == 0) ecell[c] = 0.0;
     if (ecell && blockIdx.x == 0 && threadIdx.x == 0) *done = 0u;   // for k_fb_unapplied
-    const double* f = (fb && valid) ? fb + c * 4 : nullptr;
-    const double dE = f ? f[0] : 0.0;
-    const double f1 = f ? f[1] : 0.0, f2 = f ? f[2] : 0.0, f3 = f ? f[3] : 0.0;
-    const bool has_fb = dE != 0.0 || f1 != 0.0 || f2 != 0.0 || f3 != 0.0;
-    // a cell without exchange is left exactly as it is (S = 1, b = 0); its moments are only
-    // needed for the temperature update or when requested
-    const bool work = valid && (moments || kp.T_mode == 2 || has_fb);
-    if (!__any(work)) return;
-    const int64_t lo = work ? off[c] : 0, hi = work ? off[c + 1] : 0;
-    double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
-    // the first kFbCache electrons of each lane stay in registers for the remap
-    T cx[kFbCache], cy[kFbCache], cz[kFbCache];
-#pragma unroll
-    for (int q = 0; q < kFbCache; ++q) {
-        const int64_t i = lo + sub + (int64_t)q * L;
-        cx[q] = cy[q] = cz[q] = (T)0;
-        if (i < hi) {
-            const double wi = w_ref * (double)w[i];
-            cx[q] = px[i]; cy[q] = py[i]; cz[q] = pz[i];
-            const double a = cx[q], b = cy[q], d = cz[q];
-            W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
-            U2 += wi * (a * a + b * b + d * d);
-        }
-    }
-    for (int64_t i = lo + sub + (int64_t)kFbCache * L; i < hi; i += L) {
-        const double wi = w_ref * (double)w[i];
-        const double a = px[i], b = py[i], d = pz[i];
-        W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
-        U2 += wi * (a * a + b * b + d * d);
-    }
-    W = group_sum<L>(W); P0 = group_sum<L>(P0); P1 = group_sum<L>(P1); P2 = group_sum<L>(P2);
-    U2 = group_sum<L>(U2);
-    if (!work) return;
-    if (moments && sub == 0) {
-        double* m = moments + c * 5;
-        m[0] = W; m[1] = P0; m[2] = P1; m[3] = P2; m[4] = U2;
-    }
-    if (!(W > 0.0)) return;
-    const double d0 = f1 / W, d1 = f2 / W, d2 = f3 / W;
-    const double var = U2 - (P0 * P0 + P1 * P1 + P2 * P2) / W;
-    const double dEbulk = (2.0 * (d0 * P0 + d1 * P1 + d2 * P2) + W * (d0 * d0 + d1 * d1 + d2 * d2)) * 0.5;
-    const double dEth = dE - dEbulk;
-    double var_new = var + 2.0 * dEth;
-    const bool cold = !(var > 1e-14 * (U2 + 1e-300));
-    double S = 1.0;
-    if (cold) {
-        var_new = var;
-        if (sub == 0 && stats) {
-            atomicAdd(&stats[AXPIC_ST_COLD_CELLS], 1.0);
-            ecell[c] = dEth;
-            *flag = token;
-        }
-    } else {
-        if (var_new < 0.0) {
-            if (sub == 0 && stats) {
-                atomicAdd(&stats[AXPIC_ST_CLAMPED_CELLS], 1.0);
-                ecell[c] = -var_new * 0.5;
-                *flag = token;
+    int nact;
+    {
+        const int64_t c = cw + lane;
+        bool work = false;
+        if (c < ncell) {
+            if (moments || kp.T_mode == 2) work = true;
+            else if (fb) {
+                const double* f = fb + c * 4;
+                work = f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0 || f[3] != 0.0;
             }
-            var_new = 0.0;
+            if (ecell && !work) ecell[c] = 0.0;
         }
-        S = sqrt(var_new / var);
+        const uint64_t m = __ballot(work);
+        nact = __popcll(m);
+        if (work) s_act[wave * 64 + __popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)lane;
     }
-    if (kp.feedback && has_fb) {
-        const double b0 = (1.0 - S) * (P0 / W) + d0, b1 = (1.0 - S) * (P1 / W) + d1,
-                     b2 = (1.0 - S) * (P2 / W) + d2;
+    __syncthreads();
+    for (int k0 = 0; k0 < nact; k0 += G) {
+        const int k = k0 + lane / L;
+        const bool work = k < nact;
+        const int64_t c = work ? cw + s_act[wave * 64 + k] : 0;
+        const double* f = (fb && work) ? fb + c * 4 : nullptr;
+        const double dE = f ? f[0] : 0.0;
+        const double f1 = f ? f[1] : 0.0, f2 = f ? f[2] : 0.0, f3 = f ? f[3] : 0.0;
+        const bool has_fb = dE != 0.0 || f1 != 0.0 || f2 != 0.0 || f3 != 0.0;
+        const int64_t lo = work ? off[c] : 0, hi = work ? off[c + 1] : 0;
+        double W = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, U2 = 0.0;
+        // the first kFbCache electrons of each lane stay in registers for the remap
+        T cx[kFbCache], cy[kFbCache], cz[kFbCache];
 #pragma unroll
         for (int q = 0; q < kFbCache; ++q) {
             const int64_t i = lo + sub + (int64_t)q * L;
+            cx[q] = cy[q] = cz[q] = (T)0;
             if (i < hi) {
-                px[i] = (T)(S * (double)cx[q] + b0);
-                py[i] = (T)(S * (double)cy[q] + b1);
-                pz[i] = (T)(S * (double)cz[q] + b2);
+                const double wi = w_ref * (double)w[i];
+                cx[q] = px[i]; cy[q] = py[i]; cz[q] = pz[i];
+                const double a = cx[q], b = cy[q], d = cz[q];
+                W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
+                U2 += wi * (a * a + b * b + d * d);
             }
         }
         for (int64_t i = lo + sub + (int64_t)kFbCache * L; i < hi; i += L) {
-            px[i] = (T)(S * (double)px[i] + b0);
-            py[i] = (T)(S * (double)py[i] + b1);
-            pz[i] = (T)(S * (double)pz[i] + b2);
+            const double wi = w_ref * (double)w[i];
+            const double a = px[i], b = py[i], d = pz[i];
+            W += wi; P0 += wi * a; P1 += wi * b; P2 += wi * d;
+            U2 += wi * (a * a + b * b + d * d);
         }
-    }
-    if (kp.T_mode == 2 && sub == 0) {
-        const double Test = kMe / 3.0 * var_new / W;
-        double Tn = (1.0 - kp.r_relax) * Tk[c] + kp.r_relax * Test;
-        Tn = Tn < kp.T_floor ? kp.T_floor : (Tn > kp.T_ceil ? kp.T_ceil : Tn);
-        Tk[c] = Tn;
+        W = group_sum<L>(W); P0 = group_sum<L>(P0); P1 = group_sum<L>(P1);
+        P2 = group_sum<L>(P2); U2 = group_sum<L>(U2);
+        if (!work) continue;
+        if (moments && sub == 0) {
+            double* mo = moments + c * 5;
+            mo[0] = W; mo[1] = P0; mo[2] = P1; mo[3] = P2; mo[4] = U2;
+        }
+        double unapplied = 0.0;
+        if (W > 0.0) {
+            const double d0 = f1 / W, d1 = f2 / W, d2 = f3 / W;
+            const double var = U2 - (P0 * P0 + P1 * P1 + P2 * P2) / W;
+            const double dEbulk =
+                (2.0 * (d0 * P0 + d1 * P1 + d2 * P2) + W * (d0 * d0 + d1 * d1 + d2 * d2)) * 0.5;
+            const double dEth = dE - dEbulk;
+            double var_new = var + 2.0 * dEth;
+            const bool cold = !(var > 1e-14 * (U2 + 1e-300));
+            double S = 1.0;
+            if (cold) {
+                var_new = var;
+                if (sub == 0 && stats) {
+                    atomicAdd(&stats[AXPIC_ST_COLD_CELLS], 1.0);
+                    unapplied = dEth;
+                    *flag = token;
+                }
+            } else {
+                if (var_new < 0.0) {
+                    if (sub == 0 && stats) {
+                        atomicAdd(&stats[AXPIC_ST_CLAMPED_CELLS], 1.0);
+                        unapplied = -var_new * 0.5;
+                        *flag = token;
+                    }
+                    var_new = 0.0;
+                }
+                S = sqrt(var_new / var);
+            }
+            if (kp.feedback && has_fb) {
+                const double b0 = (1.0 - S) * (P0 / W) + d0, b1 = (1.0 - S) * (P1 / W) + d1,
+                             b2 = (1.0 - S) * (P2 / W) + d2;
+#pragma unroll
+                for (int q = 0; q < kFbCache; ++q) {
+                    const int64_t i = lo + sub + (int64_t)q * L;
+                    if (i < hi) {
+                        px[i] = (T)(S * (double)cx[q] + b0);
+                        py[i] = (T)(S * (double)cy[q] + b1);
+                        pz[i] = (T)(S * (double)cz[q] + b2);
+                    }
+                }
+                for (int64_t i = lo + sub + (int64_t)kFbCache * L; i < hi; i += L) {
+                    px[i] = (T)(S * (double)px[i] + b0);
+                    py[i] = (T)(S * (double)py[i] + b1);
+                    pz[i] = (T)(S * (double)pz[i] + b2);
+                }
+            }
+            if (kp.T_mode == 2 && sub == 0) {
+                const double Test = kMe / 3.0 * var_new / W;
+                double Tn = (1.0 - kp.r_relax) * Tk[c] + kp.r_relax * Test;
+                Tn = Tn < kp.T_floor ? kp.T_floor : (Tn > kp.T_ceil ? kp.T_ceil : Tn);
+                Tk[c] = Tn;
+            }
+        }
+        if (ecell && sub == 0) ecell[c] = unapplied;
     }
 }
 
@@ -3306,7 +3330,7 @@ axpic_status axpic_feedback(const axpic_grid* g, axpic_cells* cells, const axpic
     KParams kp = make_kparams(g, prm, 0.0);
     // eight lanes per cell where the cells hold fewer than 48 electrons on average
     const bool narrow = el->n < 48 * cells->ncell;
-    const int64_t ncell = cells->ncell, threads = ncell * (narrow ? 8 : kCellLanes);
+    const int64_t ncell = cells->ncell, threads = ncell;   // one lane per cell to find the work
     // with statistics: one FP64 slot per cell (the per-parent region of a workspace for 2
     // ncell parents) and a flag word stamped with a token of this call
     double* ecell = nullptr;

@@ -106,8 +106,10 @@ def step_counts(sim, n_ax0, active_frac):
     fb_cells = active_frac * sim.ncell
     fb_el = active_frac * el
     T_all = sim.pdict["T_mode"] == 2
+    massless_p2 = sim.ph.p2 is not None and not sim.pdict.get("m_a_keV", 0.0)
     k = {
-        "k_prim_count": ("photon", ph, 8.0),              # |p|^2 (4 B) + w (4 B) read
+        # |p|^2 (4 B, the photons' cache) + w (4 B) read; p (12 B) for massive axions
+        "k_prim_count": ("photon", ph, 8.0 if massless_p2 else 16.0),
         "k_therm_count": ("electron", el, 4.0),           # w read (the rate is per cell)
         "k_abs_count": ("axion", n_ax0, 32.0),            # p, w, id, cell read
         "k_bin": ("axion", n_ax0, 2.0 * xb + 12 + 4),     # x, p read; x, cell written

@@ -170,3 +170,20 @@ def test_sort_rejects_invalid_arguments_on_host():
                                   fake, need, None, None) == -1
     assert L.axpic_sort_cells(B.ref(g), B.ref(sp), 0, B.ref(out), None, st.ctypes.data, fake,
                               need - 1, None, None) == -1
+
+
+def test_fill_p2_rejects_invalid_arguments_on_host():
+    """axpic_fill_p2: no cache, no momenta, or a start outside [0, n] are refused before
+    any launch; a start at n launches nothing."""
+    L = B.load()
+    fake = 1 << 20                       # never dereferenced: the call returns first
+    sp = B.SpeciesC()
+    sp.x[0] = sp.p[0] = sp.p[1] = sp.p[2] = sp.w = sp.id = sp.cell = fake
+    sp.n, sp.capacity, sp.kind = 10, 10, B.PHOTON
+    assert L.axpic_fill_p2(B.ref(sp), 0, None) == -1              # no cache
+    sp.p2 = fake + 64
+    for start in (-1, 11):
+        assert L.axpic_fill_p2(B.ref(sp), start, None) == -1
+    assert L.axpic_fill_p2(B.ref(sp), 10, None) == 0              # nothing to fill
+    sp.p[1] = None
+    assert L.axpic_fill_p2(B.ref(sp), 0, None) == -1              # no momenta

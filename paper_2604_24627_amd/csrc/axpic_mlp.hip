@@ -391,7 +391,6 @@ k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __rest
 // ------------------------------------------------------------------ inference
 constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
 constexpr int kInfThreadsP = 512;           // the same, per-particle kernel
-constexpr int kNTParticles = 2;            // 16-wide column tiles per pass, per-particle kernel
 constexpr int kNTTable = 4;                // the same for the per-cell table kernel
 
 struct MlpConst {
@@ -550,10 +549,12 @@ __device__ __forceinline__ float log_rate(const MlpConst& mc, int ch, const floa
     return fmaf(pick(mc.out_sigma, ch), y, v);
 }
 
-// mode 0: photons -> lambda_P; mode 1: axions -> thermal P_abs; mode 2: axions -> a->gamma mean.
-template <typename T>
+// MODE 0: photons -> lambda_P; 1: axions -> thermal P_abs; 2: axions -> a->gamma mean.
+// NT: 16-particle column tiles per network pass (64 particles per pass where the
+// mode's registers allow it: every weight fragment then feeds four tiles).
+template <typename T, int MODE, int NT>
 __global__ void __launch_bounds__(kInfThreadsP)
-k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P, double g2e,
+k_rates_mlp(int64_t n, int ee_on, KParams kp, MlpConst mc, double g2P, double g2e,
             double boost,
             double lam_unit_P, double lam_unit_ag, const double* __restrict__ state,
             const float* __restrict__ p32, const double* __restrict__ p64, int32_t nion, double Zion,
@@ -596,14 +597,18 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
             f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
             f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
         }
-        // one network pass per channel: Primakoff (modes 0, 2) or the three thermal ones
+        // one network pass per channel: Primakoff (modes 0, 2) or the three thermal ones.
+        // No memory access moves across a pass (the empty asm statements): what it would
+        // carry through the pass does not fit the registers at 64 particles per pass.
         float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
-        const int c0 = mode == 1 ? 1 : 0, c1 = mode == 1 ? 3 : 0;
+        constexpr int c0 = MODE == 1 ? 1 : 0, c1 = MODE == 1 ? 3 : 0;
 #pragma unroll 1
         for (int ch = c0; ch <= c1; ++ch) {
             f[4] = ch == 0 ? 1.0f : 0.0f; f[5] = ch == 1 ? 1.0f : 0.0f;
             f[6] = ch == 2 ? 1.0f : 0.0f; f[7] = ch == 3 ? 1.0f : 0.0f;
-            const float yy = mlp_wave<kNTParticles>(frag, bias, f);
+            asm volatile("" ::: "memory");
+            const float yy = mlp_wave<NT>(frag, bias, f);
+            asm volatile("" ::: "memory");
             if (ch <= 1) y0 = yy;
             else if (ch == 2) y1 = yy;
             else y2 = yy;
@@ -615,9 +620,9 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
         const T wt = w[ii];
         const T p2 = psq<T>(px, py, pz, ii);
         double res;
-        if (mode == 0 || mode == 2) {
+        if constexpr (MODE == 0 || MODE == 2) {
             const double GdtP = g2P * boost * exp((double)log_rate(mc, 0, f, y[0])) * kp.dt_phys;
-            if (mode == 0) {
+            if constexpr (MODE == 0) {
                 res = in_dom ? (double)wt * lam_unit_P * (-expm1(-GdtP))
                              : (double)lambda_primakoff<T>(pc, wt, p2);
             } else {
@@ -638,7 +643,7 @@ k_rates_mlp(int64_t n, int mode, int ee_on, KParams kp, MlpConst mc, double g2P,
                          : (double)pabs_thermal<T>(kp, pc, energy_keV(p2));
             if (!(wt > (T)0)) res = 0.0;
         }
-        if (mode != 1 && !(wt > (T)0)) res = 0.0;
+        if (MODE != 1 && !(wt > (T)0)) res = 0.0;
         if (live) {
             out[i] = (T)res;
             fb_count += in_dom ? 0 : 1;
@@ -1136,20 +1141,23 @@ axpic_status axpic_rates_mlp(const axpic_grid* g, const axpic_cells* cells, cons
     constexpr int kWaves = kInfThreadsP / 64;
     const int64_t wgs = std::min<int64_t>((tiles + kWaves - 1) / kWaves, (int64_t)ncu);
     const double Z = cells->nion == 1 ? cells->Zion[0] : 0.0;
-    if (sp->dtype == AXPIC_F32)
-        LAUNCH("k_rates_mlp", k_rates_mlp<float>, dim3((unsigned)wgs), dim3(kInfThreadsP), 0,
-                           S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
-                           lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
-                           (const float*)sp->w, (const float*)sp->p[0], (const float*)sp->p[1],
-                           (const float*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
-                           (float*)out, n_fallback);
-    else
-        LAUNCH("k_rates_mlp", k_rates_mlp<double>, dim3((unsigned)wgs), dim3(kInfThreadsP), 0,
-                           S(stream), sp->n, mode, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P,
-                           lam_unit_ag, cells->state, cells->pref32, cells->pref64, cells->nion, Z,
-                           (const double*)sp->w, (const double*)sp->p[0], (const double*)sp->p[1],
-                           (const double*)sp->p[2], sp->cell, (const unsigned char*)net->blob,
-                           (double*)out, n_fallback);
+    // 64 particles per network pass where the registers allow it (FP32), else 32
+#define AXPIC_RATES_MLP(TT, MD, NT)                                                              \
+    LAUNCH("k_rates_mlp", (k_rates_mlp<TT, MD, NT>), dim3((unsigned)wgs), dim3(kInfThreadsP), 0,   \
+           S(stream), sp->n, prm->brems_ee, kp, mc, g2P, g2e, prm->boost, lam_unit_P, lam_unit_ag, \
+           cells->state, cells->pref32, cells->pref64, cells->nion, Z, (const TT*)sp->w,           \
+           (const TT*)sp->p[0], (const TT*)sp->p[1], (const TT*)sp->p[2], sp->cell,                \
+           (const unsigned char*)net->blob, (TT*)out, n_fallback)
+    if (sp->dtype == AXPIC_F32) {
+        if (mode == 0) AXPIC_RATES_MLP(float, 0, 4);
+        else if (mode == 1) AXPIC_RATES_MLP(float, 1, 4);
+        else AXPIC_RATES_MLP(float, 2, 4);
+    } else {
+        if (mode == 0) AXPIC_RATES_MLP(double, 0, 2);
+        else if (mode == 1) AXPIC_RATES_MLP(double, 1, 2);
+        else AXPIC_RATES_MLP(double, 2, 2);
+    }
+#undef AXPIC_RATES_MLP
     return launched();
 }
 

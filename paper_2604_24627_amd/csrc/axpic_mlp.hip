@@ -592,9 +592,11 @@ k_rates_mlp(int64_t n, int ee_on, KParams kp, MlpConst mc, double g2P, double g2
             const double x = kMe * sqrt((double)psq<T>(px, py, pz, ii)) / Tc;
             in_dom = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo && Tc <= mc.T_hi &&
                      ne >= mc.ne_lo && ne <= mc.ne_hi && x >= mc.x_lo && x <= mc.x_hi;
-            f[0] = ((float)log(x) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
-            f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
-            f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
+            // the features in FP32 (they enter the network rounded to BF16): FP32 logarithms
+            // of the FP64 state, the domain test above in FP64
+            f[0] = (logf((float)x) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
+            f[1] = ((0.5f * logf((float)k2) - logf((float)Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
+            f[2] = (logf((float)ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
             f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
         }
         // one network pass per channel: Primakoff (modes 0, 2) or the three thermal ones.

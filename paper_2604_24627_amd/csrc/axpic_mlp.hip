@@ -694,9 +694,10 @@ k_mlp_table(int64_t ncell, int nodes, int slot0, int slot1, int c_on, int bz_on,
         const bool in_box = nion == 1 && (Zion == 1.0 || Zion == 2.0) && Tc >= mc.T_lo &&
                             Tc <= mc.T_hi && ne >= mc.ne_lo && ne <= mc.ne_hi;
         float f[8];
+        // FP32 logarithms of the FP64 state (the features enter the network as BF16)
         f[0] = ((float)(u0 + j * h) - mc.feat_lo[0]) * mc.feat_sc[0] - 1.0f;
-        f[1] = ((float)(0.5 * log(k2) - log(Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
-        f[2] = ((float)log(ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
+        f[1] = ((0.5f * logf((float)k2) - logf((float)Tc)) - mc.feat_lo[1]) * mc.feat_sc[1] - 1.0f;
+        f[2] = (logf((float)ne) - mc.feat_lo[2]) * mc.feat_sc[2] - 1.0f;
         f[3] = ((float)Zion - mc.feat_lo[3]) * mc.feat_sc[3] - 1.0f;
         float* out = table + c * 2 * nodes + j;
         if (slot0) {

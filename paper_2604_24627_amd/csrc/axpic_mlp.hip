@@ -411,41 +411,35 @@ __device__ __forceinline__ void act_tile(const floatx4 (&a)[NT], int mt, bf16x8 
     }
 }
 
-// Pre-activations of output tile mt of a hidden 128 -> 128 layer; the
-// accumulators start at the bias (as the first product's C operand).
-template <int NT>
-__device__ __forceinline__ void hh_tile(const bf16x8* __restrict__ frag, int fbase, int mt, int l,
-                                        const floatx4 bv, const bf16x8 (&Bin)[NT][4],
-                                        floatx4 (&a)[NT]) {
-    const bf16x8 a0 = frag[(fbase + mt * 4) * 64 + l];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) a[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, Bin[nt][0], bv, 0, 0, 0);
-#pragma unroll
-    for (int c = 1; c < 4; ++c) {
-        const bf16x8 ac = frag[(fbase + mt * 4 + c) * 64 + l];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) a[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac, Bin[nt][c], a[nt], 0, 0, 0);
-    }
-}
-
 // One hidden layer, software-pipelined over the 8 output tiles: the products of
 // tile mt are issued before the activation of tile mt - 1, so a wavefront's
-// vector work overlaps its own matrix-core chain.
+// vector work overlaps its own matrix-core chain; each weight fragment is read
+// from LDS one K-chunk ahead of its products (the scheduling barriers keep the
+// read before the previous chunk's products, so its latency hides behind them).
 template <int NT>
 __device__ __forceinline__ void hidden_layer(const bf16x8* __restrict__ frag, int fbase,
                                              const floatx4* __restrict__ b4, int l, int g,
                                              const bf16x8 (&Bin)[NT][4], bf16x8 (&Bout)[NT][4]) {
     floatx4 a0[NT], a1[NT];
-    hh_tile(frag, fbase, 0, l, b4[g], Bin, a0);
+    bf16x8 w = frag[fbase * 64 + l];
 #pragma unroll
-    for (int mt = 1; mt < 8; ++mt) {
-        if (mt & 1) {
-            hh_tile(frag, fbase, mt, l, b4[4 * mt + g], Bin, a1);
-            act_tile(a0, mt - 1, Bout);
-        } else {
-            hh_tile(frag, fbase, mt, l, b4[4 * mt + g], Bin, a0);
-            act_tile(a1, mt - 1, Bout);
+    for (int mt = 0; mt < 8; ++mt) {
+        floatx4 (&acc)[NT] = (mt & 1) ? a1 : a0;
+        const floatx4 bv = b4[4 * mt + g];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int nxt = mt * 4 + c + 1;
+            bf16x8 wn = w;
+            if (nxt < 32) wn = frag[(fbase + nxt) * 64 + l];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, Bin[nt][c],
+                                                                  c == 0 ? bv : acc[nt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            w = wn;
         }
+        if (mt > 0) act_tile((mt & 1) ? a0 : a1, mt - 1, Bout);
     }
     act_tile(a1, 7, Bout);
 }
@@ -474,10 +468,13 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
     {
         const floatx4* b4 = (const floatx4*)bias;
         floatx4 a0[NT], a1[NT];
+        bf16x8 an = frag[kFragL1 * 64 + l];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
-            const bf16x8 a = frag[(kFragL1 + mt) * 64 + l];
+            const bf16x8 a = an;                   // read one tile ahead, as in hidden_layer
+            if (mt < 7) an = frag[(kFragL1 + mt + 1) * 64 + l];
             const floatx4 bv = b4[4 * mt + g];
+            __builtin_amdgcn_sched_barrier(0);
             if (mt & 1) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B0[nt], bv, 0, 0, 0);
@@ -503,12 +500,16 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
     floatx4 o[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) o[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 an = frag[kFragL5 * 64 + l];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const bf16x8 a = frag[(kFragL5 + c) * 64 + l];
+        const bf16x8 a = an;
+        if (c < 3) an = frag[(kFragL5 + c + 1) * 64 + l];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
             o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Ba[nt][c], o[nt], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
     }
     // lane col of group 0 holds y of particle base + 16 nt + col in o[nt][0]
     const int rel = l - base;

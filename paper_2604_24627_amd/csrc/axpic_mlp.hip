@@ -392,6 +392,10 @@ k_mlp_pack(const float* __restrict__ P, __bf16* __restrict__ frag, float* __rest
 constexpr int kInfThreads = 512;            // 8 wavefronts share one copy of the weights
 constexpr int kInfThreadsP = 512;           // the same, per-particle kernel
 constexpr int kNTTable = 4;                // the same for the per-cell table kernel
+// Features that differ between the particles (or rows) of a pass: ln(omega/T), the
+// screening scale and ln n_e; the ion charge and the channel's one-hot inputs are
+// uniform over the launch or the pass.
+constexpr int kVarFeat = 3;
 
 struct MlpConst {
     float feat_lo[4], feat_sc[4];
@@ -453,13 +457,15 @@ __device__ __forceinline__ float mlp_pass(const bf16x8* __restrict__ frag,
                                           int base) {
     const int l = threadIdx.x & 63, g = l >> 4, col = l & 15;
     // layer-1 B operand: group 0 of column tile nt carries the 8 features of particle
-    // base + 16 nt + col; the other groups hold the zero padding of inputs 8..31
+    // base + 16 nt + col; the other groups hold the zero padding of inputs 8..31.  Only
+    // the first kVarFeat features differ between particles: the charge and the channel's
+    // one-hot inputs are the same in every lane and need no shuffle.
     bf16x8 B0[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float v = __shfl(f[j], base + nt * 16 + col, 64);
+            const float v = j < kVarFeat ? __shfl(f[j], base + nt * 16 + col, 64) : f[j];
             B0[nt][j] = (__bf16)(g == 0 ? v : 0.0f);
         }
     }

@@ -180,12 +180,16 @@ __device__ __forceinline__ float f_1mexp(float y) {
 __device__ __forceinline__ float screenF(float s) {
     if (!(s > 0.0f)) return 0.0f;
     if (s < 0.35f) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int n = 16; n >= 1; --n) {
-            const float c = ((n & 1) ? 1.0f : -1.0f) / (float)(n * (n + 1));
-            acc = acc * s + c;
-        }
+        // F(s)/s = sum_n (-1)^(n+1) s^(n-1) / (n (n+1)) on [0, 0.35] by a degree-6
+        // Chebyshev fit (relative error 9e-10; with FP32 Horner 5e-8, as the 16-term
+        // series it replaces)
+        float acc = 7.609401364e-03f;
+        acc = fmaf(acc, s, -1.974492148e-02f);
+        acc = fmaf(acc, s, 3.245352209e-02f);
+        acc = fmaf(acc, s, -4.989826679e-02f);
+        acc = fmaf(acc, s, 8.332762122e-02f);
+        acc = fmaf(acc, s, -1.666665375e-01f);
+        acc = fmaf(acc, s, 0.5f);
         return acc * s;
     }
     return (1.0f + frcp(s)) * flog(1.0f + s) - 1.0f;
@@ -207,9 +211,10 @@ __device__ __forceinline__ double screenF(double s) {
 // (1 - e^-x)/x, accurate for tiny (or underflowed) x.
 __device__ __forceinline__ float one_minus_exp_over(float x) {
     if (x < 0.25f) {
+        // sum_k (-x)^k / (k+1)!, k <= 6: truncation below 2e-9 relative at x = 0.25
         float a = 0.0f;
 #pragma unroll
-        for (int k = 8; k >= 0; --k) {
+        for (int k = 6; k >= 0; --k) {
             float f = 1.0f;
             for (int q = 2; q <= k + 1; ++q) f *= (float)q;
             a = a * x + ((k & 1) ? -1.0f : 1.0f) / f;

@@ -872,65 +872,29 @@ k_rates(int64_t n, KParams kp, int mode, const float* __restrict__ p32, const do
 // ------------------------------------------------------------------ Primakoff emission
 constexpr int kStageCells = 256;   // cells a workgroup of the cell-ordered prefix stages in LDS
 
-// Cells of a workgroup inside a cell-ordered prefix, staged in LDS: the first prefactor
-// record (4 entries) of cells c_first .. c_first + m - 1 and the m - 1 interior cell
-// boundaries relative to the workgroup's first parent.
-struct CellStage {
-    const int32_t* bnd;
-    const float4* pref;
-    int32_t m;
-    // relative cell of parents t0 .. t0 + kPer - 1 (t0 relative to the first parent):
-    // the number of boundaries at or below each
-    __device__ __forceinline__ void cells(int32_t t0, int32_t* k) const {
-        int lo = 0, hi = m - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (bnd[mid] <= t0) lo = mid + 1; else hi = mid;
-        }
-        k[0] = lo;
-        // the next kPer - 1 boundaries hold every one within the run unless kPer or more
-        // fall inside it (empty cells); then the stepping loop
-        int32_t b[kPer - 1];
-#pragma unroll
-        for (int q = 0; q < kPer - 1; ++q) b[q] = lo + q < m - 1 ? bnd[lo + q] : INT32_MAX;
-        if (lo + kPer - 1 < m - 1 && bnd[lo + kPer - 1] <= t0 + kPer - 1) {
-#pragma unroll
-            for (int q = 1; q < kPer; ++q) {
-                int c = k[q - 1];
-                while (c < m - 1 && bnd[c] <= t0 + q) ++c;
-                k[q] = c;
-            }
-        } else {
-#pragma unroll
-            for (int q = 1; q < kPer; ++q) {
-                int c = lo;
-#pragma unroll
-                for (int r = 0; r < kPer - 1; ++r) c += b[r] <= t0 + q;
-                k[q] = c;
-            }
-        }
-    }
-};
-
 // What the conversion count reads besides w and id: p, the photons' |p|^2 cache
 // (massless only), or given means.
 enum PrimSrc { kSrcP = 0, kSrcP2 = 1, kSrcLam = 2 };
 
-// The photon data of a thread's run (x holds |p|^2 or the means when that is the source).
+// The photon data of a thread's run (x holds |p|^2 or the means when that is the source;
+// the cells only where the rate is computed).
 template <typename T, int SRC>
 struct PrimRun {
     T w[kPer], x[kPer], y[kPer], z[kPer];
     uint64_t id[kPer];
+    int32_t c[kPer];
     template <bool VEC>
     __device__ __forceinline__ void load(int64_t i0, int64_t n, const T* __restrict__ wp,
                                          const T* __restrict__ px, const T* __restrict__ py,
                                          const T* __restrict__ pz, const T* __restrict__ p2in,
-                                         const IdView& idv, const T* __restrict__ lam_in) {
+                                         const IdView& idv, const int32_t* __restrict__ cell,
+                                         const T* __restrict__ lam_in) {
         ld_run<VEC>(wp, i0, n, w);
         idv.template run<VEC>(i0, n, id);
         if constexpr (SRC == kSrcLam) ld_run<VEC>(lam_in, i0, n, x);
         else if constexpr (SRC == kSrcP2) ld_run<VEC>(p2in, i0, n, x);
         else { ld_run<VEC>(px, i0, n, x); ld_run<VEC>(py, i0, n, y); ld_run<VEC>(pz, i0, n, z); }
+        if constexpr (SRC != kSrcLam) ld_run<VEC>(cell, i0, n, c);
     }
 };
 
@@ -1011,7 +975,6 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
              int aligned, float wt_heavy,
              const int64_t* __restrict__ off, int64_t n_sorted) {
     __shared__ uint32_t lds[kThreads / 64];
-    __shared__ int32_t s_bnd[kStageCells];
     __shared__ float4 s_pref[kStageCells];
     const T* pref = PrefOf<T>::get(p32, p64);
     const int64_t base = (int64_t)blockIdx.x * kBlockParents;
@@ -1020,41 +983,35 @@ k_prim_count(int64_t n, int64_t step, KParams kp, double w_ref, const float* __r
     const int64_t i0 = base + (int64_t)kPer * threadIdx.x;
     const int32_t t0 = kPer * (int32_t)threadIdx.x;
     const bool vec = aligned && base + kBlockParents <= n;
-    // A workgroup inside the cell-ordered prefix spans the cells of its first and last
-    // photon; when they are few, their prefactors and boundaries go to LDS and the
-    // photons' cells come from the offsets (4 bytes less per photon)
     // the run's own loads first: they are in flight while the cells are staged
     PrimRun<T, SRC> d;
-    if (vec) d.template load<true>(i0, n, w, px, py, pz, p2in, id, lam_in);
-    else d.template load<false>(i0, n, w, px, py, pz, p2in, id, lam_in);
-    CellStage stg{s_bnd, s_pref, 0};
+    if (vec) d.template load<true>(i0, n, w, px, py, pz, p2in, id, cell, lam_in);
+    else d.template load<false>(i0, n, w, px, py, pz, p2in, id, cell, lam_in);
+    // A workgroup inside the cell-ordered prefix spans the cells of its first and last
+    // photon; when they are few, their first prefactor records go to LDS, indexed by the
+    // photon's cell relative to the first (the kernel is bound by instruction issue, so
+    // the 4-byte cell read is cheaper than finding the cells from the offsets)
+    int32_t c_first = 0, m = 0;
     if (sizeof(T) == 4 && SRC != kSrcLam && off && vec && base + kBlockParents <= n_sorted) {
-        const int32_t c_first = cell[base], c_last = cell[base + kBlockParents - 1];
-        const int32_t m = c_last - c_first + 1;
-        if (m >= 1 && m <= kStageCells) {
-            for (int t = threadIdx.x; t < m; t += kThreads) {
+        c_first = cell[base];
+        const int32_t mm = cell[base + kBlockParents - 1] - c_first + 1;
+        if (mm >= 1 && mm <= kStageCells) {
+            for (int t = threadIdx.x; t < mm; t += kThreads)
                 s_pref[t] = *(const float4*)(p32 + (int64_t)(c_first + t) * AXPIC_PREF_N);
-                if (t >= 1) s_bnd[t - 1] = (int32_t)(off[c_first + t] - base);
-            }
             __syncthreads();
-            stg.m = m;
+            m = mm;
         }
     }
     T pcv[kPer][4];
-    if (stg.m > 0) {
-        int32_t kc[kPer];
-        stg.cells(t0, kc);
+    if (m > 0) {
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const float4 v = stg.pref[kc[j]];
+            const float4 v = s_pref[d.c[j] - c_first];
             pcv[j][0] = v.x; pcv[j][1] = v.y; pcv[j][2] = v.z; pcv[j][3] = v.w;
         }
     } else if (SRC != kSrcLam) {
-        int32_t cv[kPer];
-        if (vec) ld_run<true>(cell, i0, n, cv);
-        else ld_run<false>(cell, i0, n, cv);
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)cv[j] * AXPIC_PREF_N, pcv[j], 1);
+        for (int j = 0; j < kPer; ++j) load_pref(pref + (int64_t)d.c[j] * AXPIC_PREF_N, pcv[j], 1);
     }
     uint32_t cd[kPer], tot;
     if (vec) tot = prim_count_run<T, M, SRC, true>(i0, n, step, kp, w_ref, d, pcv, wt_heavy, cd);

@@ -435,7 +435,7 @@ def leg_graded(a, S=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
                           "(x-slab) decomposition is a design note, not implemented"}))
         sys.exit(2)
     import numpy as np

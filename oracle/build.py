@@ -1,7 +1,7 @@
 """Build the oracle's shared library with the host C compiler (gcc).
 
 The oracle is test infrastructure; building it is part of the build step so
-that the checker exists wherever the tests run.
+that the oracle exists wherever the tests run.
 """
 import os
 import subprocess

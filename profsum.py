@@ -19,7 +19,10 @@ python profsum.py --sq <counter_collection.csv> -- per-kernel
 medians over dispatches of SQ_WAVES and of the other SQ counters per wavefront; the FETCH_SIZE / WRITE_SIZE
 medians (KiB per dispatch) are scaled so that k_stream_copy of copy_bytes reads
 and writes copy_bytes, and a "traffic" line per kernel is printed with the
-source digest for read_traffic.
+source digest for read_traffic: the mean of its last LAST_DISPATCHES dispatches,
+which in a trace of bench.py's plain leg are the steps in which bench.py times the
+dominant kernel alone (the axion kernels' populations grow over the run, so a
+median dispatch would not match the launches the roofline divides).
 """
 from __future__ import annotations
 
@@ -28,6 +31,8 @@ import hashlib
 import os
 import re
 import statistics
+
+LAST_DISPATCHES = 3
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -176,8 +181,8 @@ def main(argv):
         print("per-dispatch HBM bytes (kernel fetch write):")
         own = step_kernels()
         for k in sorted(k for k in set(fetch) & set(write) if k in own):
-            fb = statistics.median(fetch[k]) * 1024 * scale_f
-            wb = statistics.median(write[k]) * 1024 * scale_w
+            fb = statistics.mean(fetch[k][-LAST_DISPATCHES:]) * 1024 * scale_f
+            wb = statistics.mean(write[k][-LAST_DISPATCHES:]) * 1024 * scale_w
             print(f"traffic {k} {fb:.6g} {wb:.6g}")
         print(f"source_sha256 {source_digest()}")
 
